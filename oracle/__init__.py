@@ -1,0 +1,284 @@
+"""NeuralPVS CPU oracle (numpy front end over ``npvs_oracle.c``).  TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct FP64 / exact-integer reference for every step of the forward
+path (froxelize, active sites, interleave, rulebook, submanifold convolution, de-interleave and
+threshold), the training loss and its gradient, the convolution backward, Adam and the ray-march
+labeller.  Each C function cites the passage of the paper it follows.  It shares no code with
+the HIP library and must only be used by the tests, the smoke check and the benchmark's
+CPU-baseline leg.
+
+Pinning: every function is checked by ``tests/test_oracle_*.py`` against brute force, closed
+forms, library routines (torch conv3d in float64) and the paper's stated invariants.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "npvs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C99, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "oracle_quantize_tri": (ctypes.c_int, [P, P]),
+            "oracle_tri_box_overlap": (ctypes.c_int, [P, P, P]),
+            "oracle_froxelize": (i64, [P, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]),
+            "oracle_active_sites": (i32, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]),
+            "oracle_interleave": (None, [P] + [ctypes.c_int] * 5 + [P]),
+            "oracle_deinterleave": (None, [P] + [ctypes.c_int] * 5 + [P]),
+            "oracle_gather_sites": (None, [P] + [ctypes.c_int] * 4 + [i32, P, P]),
+            "oracle_rulebook": (i64, [P, i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]),
+            "oracle_subm_conv": (None, [P, i32, ctypes.c_int, P, P, ctypes.c_int, P, P, ctypes.c_int, P]),
+            "oracle_masked_dense_conv": (None, [P, P] + [ctypes.c_int] * 4 + [P, P, ctypes.c_int, ctypes.c_int, P]),
+            "oracle_deinterleave_threshold": (None, [P, i32, P, P] + [ctypes.c_int] * 4 + [P, P]),
+            "oracle_loss": (None, [P, P, i64, f64, P, P]),
+            "oracle_subm_conv_bwd": (None, [P, i32, ctypes.c_int, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, P]),
+            "oracle_adam": (None, [P, P, P, P, i64, i64, f64, f64, f64, f64, f64]),
+            "oracle_label_raymarch": (i64, [P, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
+                                            ctypes.c_int, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------- froxelization
+def quantize_tri(tri) -> np.ndarray | None:
+    """Fixed-point (1/256 froxel, round half to even) vertices of one triangle, or None when
+    the triangle is ignored (non-finite or |coordinate| >= 2048)."""
+    t = _c(tri, np.float32).reshape(9)
+    q = np.zeros((3, 3), np.int64)
+    return q if _load().oracle_quantize_tri(_p(t), _p(q)) else None
+
+
+def tri_box_overlap(q: np.ndarray, lo, hi) -> bool:
+    """Exact SAT test of quantized triangle q against the closed fixed-point box [lo, hi]."""
+    q = _c(q, np.int64)
+    lo = _c(lo, np.int64)
+    hi = _c(hi, np.int64)
+    return bool(_load().oracle_tri_box_overlap(_p(q), _p(lo), _p(hi)))
+
+
+def froxelize(tris, dims):
+    """Packed occupancy grid uint8 [nz][ny][nx/8] and the number of ignored triangles."""
+    nx, ny, nz = dims
+    t = _c(tris, np.float32).reshape(-1, 9)
+    occ = np.zeros((nz, ny, nx // 8), np.uint8)
+    ign = _load().oracle_froxelize(_p(t), t.shape[0], nx, ny, nz, _p(occ))
+    return occ, int(ign)
+
+
+def unpack(bits: np.ndarray) -> np.ndarray:
+    """Packed [nz][ny][nx/8] -> uint8 0/1 [nz][ny][nx] (bit x & 7 of byte x >> 3)."""
+    return np.unpackbits(bits, axis=-1, bitorder="little")
+
+
+# ---------------------------------------------------------------- sites / interleave / rulebook
+def active_sites(occ, dims, d) -> np.ndarray:
+    nx, ny, nz = dims
+    occ = _c(occ, np.uint8)
+    keys = np.zeros((nx // d) * (ny // d) * (nz // d), np.int32)
+    n = _load().oracle_active_sites(_p(occ), nx, ny, nz, d, _p(keys))
+    return keys[:n].copy()
+
+
+def interleave(a: np.ndarray, d: int) -> np.ndarray:
+    """Dense g_d of a [nz][ny][nx] array of any fixed-size dtype -> [nz/d][ny/d][nx/d][d^3]."""
+    a = np.ascontiguousarray(a)
+    nz, ny, nx = a.shape
+    out = np.empty((nz // d, ny // d, nx // d, d ** 3), a.dtype)
+    _load().oracle_interleave(_p(a), nx, ny, nz, d, a.itemsize, _p(out))
+    return out
+
+
+def deinterleave(a: np.ndarray, dims, d: int) -> np.ndarray:
+    nx, ny, nz = dims
+    a = np.ascontiguousarray(a)
+    out = np.empty((nz, ny, nx), a.dtype)
+    _load().oracle_deinterleave(_p(a), nx, ny, nz, d, a.itemsize, _p(out))
+    return out
+
+
+def gather_sites(occ, dims, d, keys) -> np.ndarray:
+    nx, ny, nz = dims
+    keys = _c(keys, np.int32)
+    X = np.zeros((keys.shape[0], d ** 3), np.float64)
+    _load().oracle_gather_sites(_p(_c(occ, np.uint8)), nx, ny, nz, d, keys.shape[0], _p(keys), _p(X))
+    return X
+
+
+def rulebook(keys, bdims):
+    """CSR rulebook: rb_off int32[28], pairs int32[P][2] = (in_row, out_row)."""
+    Bx, By, Bz = bdims
+    keys = _c(keys, np.int32)
+    n = keys.shape[0]
+    rb_off = np.zeros(28, np.int32)
+    pairs = np.zeros((27 * max(n, 1), 2), np.int32)
+    P = _load().oracle_rulebook(_p(keys), n, Bx, By, Bz, _p(rb_off), _p(pairs))
+    return rb_off, pairs[:P].copy()
+
+
+def neighbor_map(rb_off, pairs, n) -> np.ndarray:
+    """nbr[27][n]: input row feeding output row r through offset k, or -1."""
+    nbr = np.full((27, n), -1, np.int32)
+    for k in range(27):
+        seg = pairs[rb_off[k]:rb_off[k + 1]]
+        nbr[k, seg[:, 1]] = seg[:, 0]
+    return nbr
+
+
+# ---------------------------------------------------------------- convolution
+def subm_conv(X, W, b, rb_off, pairs, relu: bool) -> np.ndarray:
+    X = _c(X, np.float64)
+    W = _c(W, np.float64)
+    n, cin = X.shape
+    cout = W.shape[2]
+    b = _c(b if b is not None else np.zeros(cout), np.float64)
+    Y = np.zeros((n, cout), np.float64)
+    _load().oracle_subm_conv(_p(X), n, cin, _p(W), _p(b), cout, _p(_c(rb_off, np.int32)),
+                             _p(_c(pairs, np.int32)), int(relu), _p(Y))
+    return Y
+
+
+def masked_dense_conv(dense_in, active, W, b, relu: bool) -> np.ndarray:
+    """dense_in [Bz][By][Bx][cin], active [Bz][By][Bx] -> [Bz][By][Bx][cout]."""
+    x = _c(dense_in, np.float64)
+    Bz, By, Bx, cin = x.shape
+    W = _c(W, np.float64)
+    cout = W.shape[2]
+    b = _c(b if b is not None else np.zeros(cout), np.float64)
+    out = np.zeros((Bz, By, Bx, cout), np.float64)
+    _load().oracle_masked_dense_conv(_p(x), _p(_c(active, np.uint8)), Bx, By, Bz, cin, _p(W), _p(b), cout,
+                                     int(relu), _p(out))
+    return out
+
+
+def subm_conv_bwd(X, W, rb_off, pairs, Y, dY, relu: bool, want_dx: bool = True):
+    X = _c(X, np.float64)
+    W = _c(W, np.float64)
+    n, cin = X.shape
+    cout = W.shape[2]
+    dX = np.zeros((n, cin), np.float64) if want_dx else None
+    dW = np.zeros_like(W)
+    db = np.zeros(cout, np.float64)
+    _load().oracle_subm_conv_bwd(_p(X), n, cin, _p(W), cout, _p(_c(rb_off, np.int32)), _p(_c(pairs, np.int32)),
+                                 _p(_c(Y, np.float64)), _p(_c(dY, np.float64)), int(relu), _p(dX), _p(dW), _p(db))
+    return dX, dW, db
+
+
+# ---------------------------------------------------------------- output, loss, optimizer
+def deinterleave_threshold(Y, keys, occ, dims, d, want_logits: bool = True):
+    nx, ny, nz = dims
+    Y = _c(Y, np.float64)
+    keys = _c(keys, np.int32)
+    if Y.shape != (keys.shape[0], d ** 3):
+        raise ValueError("de-interleave needs one row of d^3 logits per active site")
+    logits = np.zeros((nz, ny, nx), np.float64) if want_logits else None
+    pvs = np.zeros((nz, ny, nx // 8), np.uint8)
+    _load().oracle_deinterleave_threshold(_p(Y), keys.shape[0], _p(keys), _p(_c(occ, np.uint8)), nx, ny, nz, d,
+                                          _p(logits), _p(pvs))
+    return logits, pvs
+
+
+def loss(logits, labels, lam: float = 0.99, want_grad: bool = True):
+    l = _c(logits, np.float64).reshape(-1)
+    y = _c(labels, np.uint8).reshape(-1)
+    out = np.zeros(7, np.float64)
+    g = np.zeros_like(l) if want_grad else None
+    _load().oracle_loss(_p(l), _p(y), l.shape[0], lam, _p(out), _p(g))
+    keys = ["loss", "bce", "lrv", "tp", "fn", "fp", "gtp"]
+    res = dict(zip(keys, out.tolist()))
+    if want_grad:
+        res["grad"] = g.reshape(np.shape(logits))
+    return res
+
+
+def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=1e-10):
+    """One Adam step on FP64 copies; returns (p, m, v)."""
+    p = _c(p, np.float64).copy()
+    m = _c(m, np.float64).copy()
+    v = _c(v, np.float64).copy()
+    g = _c(g, np.float64)
+    _load().oracle_adam(_p(p), _p(g), _p(m), _p(v), p.size, t, lr, b1, b2, eps, wd)
+    return p, m, v
+
+
+def label_raymarch(tris, dims, views, s_r: int = 2) -> np.ndarray:
+    nx, ny, nz = dims
+    t = _c(tris, np.float32).reshape(-1, 9)
+    v = _c(views, np.float64).reshape(-1, 3)
+    lab = np.zeros((nz, ny, nx // 8), np.uint8)
+    _load().oracle_label_raymarch(_p(t), t.shape[0], nx, ny, nz, _p(v), v.shape[0], s_r, _p(lab))
+    return lab
+
+
+# ---------------------------------------------------------------- composition
+def forward(tris, dims, d, layers, want_logits: bool = True, occ=None):
+    """Whole path on one grid (Sec. 3: V = g_d^-1(f(g_d(G))) thresholded), FP64.
+
+    layers: list of (W [27][cin][cout], b [cout]); ReLU after every layer but the last.
+    Returns a dict of every intermediate."""
+    nx, ny, nz = dims
+    if occ is None:
+        occ, _ = froxelize(tris, dims)
+    keys = active_sites(occ, dims, d)
+    rb_off, pairs = rulebook(keys, (nx // d, ny // d, nz // d))
+    X = gather_sites(occ, dims, d, keys)
+    acts = [X]
+    for li, (W, b) in enumerate(layers):
+        acts.append(subm_conv(acts[-1], W, b, rb_off, pairs, relu=li < len(layers) - 1))
+    logits, pvs = deinterleave_threshold(acts[-1], keys, occ, dims, d, want_logits)
+    return dict(occ=occ, keys=keys, rb_off=rb_off, pairs=pairs, acts=acts, logits=logits, pvs=pvs)
+
+
+def backward(out, layers, dlogits_rows):
+    """Backward through the whole layer stack of ``forward`` (chain rule on each layer, FP64).
+
+    dlogits_rows: dL/dY of the last layer [n][d^3].  Returns [(dW, db)] per layer and dX of the
+    network input."""
+    acts, rb_off, pairs = out["acts"], out["rb_off"], out["pairs"]
+    grads = [None] * len(layers)
+    dY = dlogits_rows
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        dX, dW, db = subm_conv_bwd(acts[li], W, rb_off, pairs, acts[li + 1], dY, relu=li < len(layers) - 1)
+        grads[li] = (dW, db)
+        dY = dX
+    return grads, dY
+
+
+def site_labels(label_bits, dims, d, keys) -> np.ndarray:
+    """Labels of the froxels of the active blocks, in the interleaved [n][d^3] row layout."""
+    return gather_sites(label_bits, dims, d, keys).astype(np.uint8)
