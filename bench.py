@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Benchmark of the NeuralPVS hot path on one MI355X.
+
+Workload: the 256x256x128 froxel grid of a seeded synthetic city (50 000 triangles, about 3 %
+occupied froxels), interleave factor d = 4 (64 channels), six submanifold 3x3x3 convolutions
+64 -> 64, batch 1.  One step is one frame through the whole path: froxelize -> active sites and
+rulebook -> interleave -> 6 convolutions -> de-interleave + threshold -> BCE + repulsive
+visibility loss -> hand-written backward (checkpointed recompute of every second layer) -> Adam,
+in BF16 on MFMA with FP32 accumulation and FP32 master weights.  Each step is replayed from a
+HIP graph captured once; inputs are resident in HBM before the timed region.
+
+Also reported: forward-only and FP32 variants, the per-stage breakdown, the roofline of the
+dominant kernel (its launches timed with HIP events on the stream they run on), accuracy of the
+BF16 path against the FP32 path and the FP64 oracle, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/sec + ms/frame fwd and fwd+bwd, BF16 vs FP32, 256x256x128 froxel grid"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="run warmup + timed steps only (for rocprofv3)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(grids are independent frames; see the sharding note in the design document)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+    from paper_2509_24677_amd.train import Network, Trainer
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    cfg = synth.config("city256")
+    dims = cfg.grids
+    tris_np = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg)
+    tris = torch.from_numpy(tris_np).to(dev)
+    n_tris = [len(tris_np)]
+    total_bytes = dims[0][0] * dims[0][1] * dims[0][2] // 8
+    occ_np = None
+
+    # label subset of G for the training step (timing does not depend on label values)
+    def label_bits_for(occ):
+        mask = torch.from_numpy(synth.label_mask_bits(7, (total_bytes,))).to(dev)
+        return occ & mask
+
+    torch.cuda.synchronize()
+    occ0 = npvs.froxelize(tris, n_tris, dims)
+    labels = label_bits_for(occ0)
+    rb0 = npvs.build_rulebook(occ0, dims, cfg.d, csr=True)
+    counts = rb0.host_counts()
+    n_sites, n_pairs = counts["n_sites"], counts["n_pairs"]
+    occ_np = occ0.cpu().numpy()
+    occupied = int(np.unpackbits(occ_np).sum())
+    print(f"# workload: T={n_tris[0]} occupied={occupied} ({occupied / (8 * total_bytes):.4f}) "
+          f"sites={n_sites} pairs={n_pairs}", file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------------ step functions
+    def make(dtype):
+        net = Network(layers, cfg.d, dtype)
+        tr = Trainer(net, dims, n_tris, checkpoint=True)
+        return net, tr
+
+    def fwd_fn(net):
+        def f():
+            occ = npvs.froxelize(tris, n_tris, dims)
+            rb = npvs.build_rulebook(occ, dims, cfg.d)
+            X0 = npvs.gather_input(occ, rb, net.dtype)
+            logits, _ = net.forward(X0, rb)
+            pvs, _ = npvs.deinterleave_threshold(logits, rb, occ)
+            return pvs, logits
+        return f
+
+    def train_fn(tr):
+        return lambda: tr.step(tris, labels)
+
+    def capture(fn, warm):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warm):
+                fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out = fn()
+        torch.cuda.synchronize()
+        return g, out
+
+    def time_graph(g, steps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / steps, wall
+
+    net_b, tr_b = make(npvs.NPVS_BF16)
+    g_train_b, _ = capture(train_fn(tr_b), max(args.warmup, 2))
+    print("# captured bf16 training step", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        g_train_b.replay()
+    torch.cuda.synchronize()
+    # ------------------------------------------------------------------ timed region (primary)
+    ms_step, wall = time_graph(g_train_b, args.steps)
+    print(f"# bf16 fwd+bwd: {ms_step:.4f} ms/frame over {args.steps} steps (wall {wall:.3f} s)",
+          file=sys.stderr, flush=True)
+    if args.profile_only:
+        print(json.dumps({"profile_only": True, "ms_per_step": ms_step}))
+        return
+
+    # ------------------------------------------------------------------ variants
+    variants = {"bf16_fwd_bwd": {"ms_per_frame": ms_step, "frames_per_s": 1000.0 / ms_step}}
+    net_bf, _ = make(npvs.NPVS_BF16)
+    g_fb, (pvs_b, logits_b) = capture(fwd_fn(net_bf), 2)
+    ms, _ = time_graph(g_fb, args.steps)
+    variants["bf16_fwd"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    net_ff, _ = make(npvs.NPVS_F32)
+    g_ff, (pvs_f, logits_f) = capture(fwd_fn(net_ff), 2)
+    ms, _ = time_graph(g_ff, args.steps)
+    variants["fp32_fwd"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    net_f, tr_f = make(npvs.NPVS_F32)
+    g_train_f, _ = capture(train_fn(tr_f), 2)
+    ms, _ = time_graph(g_train_f, args.steps)
+    variants["fp32_fwd_bwd"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    # the whole forward as one library-captured graph (npvs_plan_capture / npvs_plan_replay)
+    plan = npvs.Plan(dims, n_tris, cfg.d, cfg.channels, npvs.NPVS_BF16)
+    for li, (W, b) in enumerate(layers):
+        plan.set_weights(li, torch.from_numpy(W).to(dev), torch.from_numpy(b).to(dev))
+    ps = torch.cuda.Stream()
+    with torch.cuda.stream(ps):
+        plan.capture(tris)
+        for _ in range(3):
+            plan.replay()
+        ps.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ps)
+        for _ in range(args.steps):
+            plan.replay()
+        e1.record(ps)
+        ps.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    variants["bf16_fwd_plan_graph"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    variants["bf16_fwd_speedup_vs_fp32_fwd"] = variants["fp32_fwd"]["ms_per_frame"] / variants["bf16_fwd"]["ms_per_frame"]
+    print("# variants " + json.dumps(variants), file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------------ per-launch kernel timing
+    # A GPU-side spin first lets the host enqueue the instrumented launches ahead of the GPU, so
+    # each event pair brackets exactly one kernel on the stream it runs on.
+    def timed_launches(launch, reps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda.synchronize()
+        torch.cuda._sleep(50_000_000)
+        for a, b in evs:
+            a.record()
+            launch()
+            b.record()
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]
+
+    occ = npvs.froxelize(tris, n_tris, dims)
+    rb = npvs.build_rulebook(occ, dims, cfg.d, csr=True)
+    Xb = npvs.gather_input(occ, rb, npvs.NPVS_BF16)
+    hid_b = net_b.layer(0, Xb, rb)
+    out_b = torch.empty_like(hid_b)
+    Xf = npvs.gather_input(occ, rb, npvs.NPVS_F32)
+    hid_f = net_f.layer(0, Xf, rb)
+    out_f = torch.empty_like(hid_f)
+    reps = 60
+    stage = {}
+    stage["froxelize"] = timed_launches(lambda: npvs.froxelize(tris, n_tris, dims, occ=occ), 20)
+    stage["rulebook"] = timed_launches(lambda: npvs.build_rulebook(occ, dims, cfg.d, csr=True), 20)
+    stage["gather_bf16"] = timed_launches(lambda: npvs.gather_input(occ, rb, npvs.NPVS_BF16, out=Xb), 20)
+    stage["conv_fwd_bf16"] = timed_launches(
+        lambda: npvs.sparse_conv_fwd(hid_b, net_b.Wp[1], net_b.b[1], 64, 64, rb, npvs.NPVS_BF16, True, out=out_b), reps)
+    stage["conv_fwd_fp32"] = timed_launches(
+        lambda: npvs.sparse_conv_fwd(hid_f, net_f.Wp[1], net_f.b[1], 64, 64, rb, npvs.NPVS_F32, True, out=out_f), reps)
+    dY = torch.randn((rb.cap, 64), device=dev)
+    stage["conv_bwd_bf16"] = timed_launches(
+        lambda: npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True), 20)
+    stage["deinterleave_threshold"] = timed_launches(lambda: npvs.deinterleave_threshold(logits_b, rb, occ), 20)
+    stage_ms = {k: float(np.median(v)) for k, v in stage.items()}
+    print("# stages (median ms per call) " + json.dumps(stage_ms), file=sys.stderr, flush=True)
+
+    # dominant kernel: the BF16 MFMA gather-GEMM (6 forward launches per frame + 3 recomputes)
+    conv_ms = float(np.mean(stage["conv_fwd_bf16"]))
+    flops = 2.0 * n_pairs * 64 * 64
+    achieved = flops / (conv_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                "kernel": "conv_fwd_bf16_kernel<2,4,2,3>", "avg_launch_ms": conv_ms,
+                "algorithmic_flops_per_launch": flops}
+    conv32_ms = float(np.mean(stage["conv_fwd_fp32"]))
+    roofline_fp32 = {"achieved": flops / (conv32_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "avg_launch_ms": conv32_ms}
+    roofline_fp32["frac"] = roofline_fp32["achieved"] / FP32_PEAK_TFLOPS
+
+    # ------------------------------------------------------------------ accuracy
+    torch.cuda.synchronize()
+    acc = {}
+    pb = np.unpackbits(pvs_b.cpu().numpy(), bitorder="little")
+    pf = np.unpackbits(pvs_f.cpu().numpy(), bitorder="little")
+    g = np.unpackbits(occ_np, bitorder="little")
+    lf = logits_f[:n_sites].cpu().numpy()
+    lb = logits_b[:n_sites].cpu().numpy()
+    acc["flip_rate_occupied"] = float(((pb != pf) & (g == 1)).sum() / g.sum())
+    acc["flip_rate_active_froxels"] = float((pb != pf).sum() / (n_sites * 64))
+    acc["flip_rate_all_froxels"] = float((pb != pf).sum() / g.size)
+    acc["missing_geometry_rate"] = float(((pf == 1) & (pb == 0)).sum() / max(pf.sum(), 1))
+    acc["max_abs_logit_diff_bf16_vs_fp32"] = float(np.abs(lb - lf).max())
+
+    # ------------------------------------------------------------------ CPU oracle baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        lab_np = (occ_np & synth.label_mask_bits(7, (total_bytes,))).reshape(dims[0][2], dims[0][1], -1)
+        t0 = time.perf_counter()
+        out = oracle.forward(tris_np, dims[0], cfg.d, layers)
+        site_lab = oracle.site_labels(lab_np, dims[0], cfg.d, out["keys"])
+        dl = oracle.loss(out["acts"][-1], site_lab)["grad"]
+        oracle.backward(out, layers, dl)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": 1.0 / cpu_s, "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": "one full 256x256x128 frame: froxelize, sites, rulebook, interleave, 6 conv layers, "
+                         "de-interleave + threshold, loss and backward in the FP64 C oracle (single thread), "
+                         f"{cpu_s:.2f} s"}
+        ref = out["acts"][-1]
+        acc["max_abs_logit_err_fp32_vs_fp64_oracle"] = float(np.abs(lf - ref).max())
+        acc["max_abs_logit_err_bf16_vs_fp64_oracle"] = float(np.abs(lb - ref).max())
+        acc["pvs_bits_fp32_equal_oracle_outside_1e-5_band"] = bool(
+            ((np.unpackbits(out["pvs"].reshape(-1), bitorder="little") == pf) |
+             (np.abs(np.nan_to_num(out["logits"].reshape(-1), neginf=-1e9)) <= 1e-5)).all())
+
+    line = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_step,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "city256: 256x256x128 froxel grid, 50000 triangles, d=4 (64 ch), "
+                               "6 submanifold 3^3 convs 64->64, batch 1, fwd+bwd+Adam per frame",
+                   "global_batch": 1, "grid": [256, 256, 128], "n_sites": n_sites, "n_pairs": n_pairs,
+                   "occupancy": occupied / (8 * total_bytes), "parallelism": "single GPU"},
+        "roofline": roofline,
+        "roofline_fp32_conv": roofline_fp32,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "stages_ms": stage_ms,
+        "accuracy": acc,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

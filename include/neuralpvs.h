@@ -1,0 +1,239 @@
+/*
+ * neuralpvs.h — C ABI of the MI355X (gfx950) NeuralPVS hot-path library.
+ *
+ * The library computes the forward pass of the visibility network of NeuralPVS (arXiv
+ * 2509.24677): the scene triangles are froxelized into a binary occupancy grid G (Sec. 3.2),
+ * G is interleaved by g_d (Sec. 3.3), a stack of submanifold sparse 3x3x3 convolutions runs on
+ * the interleaved sites (Sec. 2.3, 3.3), and the result is de-interleaved by g_d^-1 and
+ * thresholded into the potentially visible set V = 1[f(G) >= tau] (Sec. 3.1), so that
+ * V = g_d^-1(f(g_d(G))).  It also provides the hand-written backward, the training loss (the
+ * repulsive visibility loss of Sec. 3.3 combined with BCE) and Adam.
+ *
+ * Conventions shared by every call:
+ *  - Pointers marked (device) are HIP device pointers owned by the caller; the library never
+ *    frees them.  Pointers marked (host) are read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every call only
+ *    enqueues work on it and returns; nothing synchronizes with the host unless stated.
+ *  - Argument errors are detected on the host before anything is enqueued and return
+ *    NPVS_ERR_INVALID_ARG; launch failures return NPVS_ERR_HIP.  npvs_last_error() gives the
+ *    message of the calling thread's last failure.
+ *  - Froxels are (x, y, z), 0-based, x fastest (the paper writes the domain 1-based).  A grid
+ *    of nx*ny*nz froxels is packed as uint8 [nz][ny][nx/8], bit (x & 7) of byte (x >> 3) is
+ *    froxel x (least significant bit = lowest x), as the paper packs eight consecutive
+ *    x-froxels per byte.
+ *  - Interleave factor d: block (bx, by, bz) holds froxels [bx*d, bx*d+d) x ...; its key is
+ *    (bz*By + by)*Bx + bx with (Bx, By, Bz) = (nx/d, ny/d, nz/d); its channel vector stacks the
+ *    froxels as c = (oz*d + oy)*d + ox.
+ *  - A batch of grids is laid out back to back: grid b's packed bits start at byte
+ *    sum_{b'<b} nz*ny*nx/8 and its block keys are offset by sum_{b'<b} Bx*By*Bz ("global
+ *    keys").  Active sites (rows) are numbered in ascending global key.
+ *  - Convolution offset k = (dz+1)*9 + (dy+1)*3 + (dx+1), dz,dy,dx in {-1,0,1}; a layer is
+ *    the cross-correlation Y[p] = b + sum_k X[p + delta_k] W_k over active sites p only.
+ *  - Weights are float32 [27][cin][cout] (masters) and are packed once per layer into the
+ *    layout a convolution kernel reads (npvs_pack_weights).  Bias is always float32.
+ *  - bf16 values are raw uint16 bit patterns rounded to nearest even from float32.
+ */
+#ifndef NEURALPVS_H
+#define NEURALPVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t npvs_status;
+#define NPVS_OK 0
+#define NPVS_ERR_INVALID_ARG (-1)
+#define NPVS_ERR_CAPACITY (-2)
+#define NPVS_ERR_HIP (-3)
+#define NPVS_ERR_UNSUPPORTED (-4)
+
+/* element types */
+#define NPVS_F32 0
+#define NPVS_BF16 1
+#define NPVS_U8 2
+
+/* limits */
+#define NPVS_MAX_GRIDS 32        /* grids per batch */
+#define NPVS_MAX_DIM 1024        /* froxels per axis; triangle coordinates must satisfy |v| < 1024 */
+
+typedef struct {
+  int32_t nx, ny, nz; /* froxels; nx % 8 == 0 and every extent divisible by d */
+} npvs_dims;
+
+/* Device-side counters written by npvs_build_rulebook and read by later calls, so that no
+ * call needs the host to know the number of active sites. */
+typedef struct {
+  int32_t n_sites;        /* active sites stored (min of found and cap_sites) */
+  int32_t n_sites_needed; /* active sites found; > cap_sites means the capacity overflowed */
+  int32_t n_pairs;        /* rulebook pairs stored (when the CSR form is requested) */
+  int32_t reserved;
+} npvs_counts;
+
+const char *npvs_version(void);
+const char *npvs_last_error(void);
+
+/* Total blocks of a batch (sum of Bx*By*Bz) and total packed bytes (sum of nz*ny*nx/8). */
+npvs_status npvs_batch_sizes(int32_t n_grids, const npvs_dims *dims /*host*/, int32_t d, int64_t *total_blocks,
+                             int64_t *total_bytes);
+
+/* ---------------------------------------------------------------------------------------------
+ * Froxelization (Sec. 3.2; Fig. 2(b)): G(x) = 1 iff a triangle meets the closed froxel x.
+ * Vertices are in grid units (one froxel = 1), quantized to 1/256 froxel with round half to
+ * even, and tested exactly (integer separating-axis test).  Triangles with a non-finite
+ * coordinate or |coordinate| >= 1024 are ignored.
+ *   tris     (device) float32 [sum T_b][3][3], grid b's triangles after those of grids < b
+ *   n_tris   (host)   int64 [n_grids] triangle counts
+ *   occ_bits (device) packed grids of the batch, fully overwritten
+ *   ws       (device) workspace of npvs_froxelize_workspace_size() bytes
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_froxelize_workspace_size(int32_t n_grids, const npvs_dims *dims, const int64_t *n_tris,
+                                          size_t *bytes);
+npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, int32_t n_grids, const npvs_dims *dims,
+                           uint8_t *occ_bits, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Active sites and rulebook of the submanifold convolution (Sec. 2.3: the kernel is centred
+ * only on active sites; sparse tensors store only sites with geometry).  A block is active iff
+ * one of its d^3 froxels is occupied.
+ *   counts     (device) npvs_counts, written
+ *   site_keys  (device) int32 [cap_sites] global key of each row, ascending
+ *   block_row  (device) int32 [total_blocks] row of each block or -1 (the site lookup table)
+ *   grid_rows  (device) int32 [n_grids + 1] first row of each grid, grid_rows[n_grids] = n_sites
+ *   nbr        (device) int32 [27][cap_sites] nbr[k][r] = row at p_r + delta_k, or -1
+ *   rb_off     (device, nullable) int32 [28] CSR offsets of the per-offset pair lists
+ *   rb_pairs   (device, nullable) int32 [27*cap_sites][2] (in_row, out_row), ascending out_row
+ *              within each offset; both rb_off and rb_pairs or neither
+ *   ws         (device) workspace of npvs_rulebook_workspace_size() bytes
+ * Rows beyond cap_sites are dropped (their blocks read as inactive) and counts->n_sites_needed
+ * tells the required capacity; cap_sites = total_blocks never overflows.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_rulebook_workspace_size(int32_t n_grids, const npvs_dims *dims, int32_t d, int32_t cap_sites,
+                                         size_t *bytes);
+npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                int32_t cap_sites, npvs_counts *counts, int32_t *site_keys, int32_t *block_row,
+                                int32_t *grid_rows, int32_t *nbr, int32_t *rb_off, int32_t *rb_pairs, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Interleave g_d and its inverse (Sec. 3.3): pure index permutations of a dense grid,
+ *   out[bz][by][bx][c] = in[bz d + oz][by d + oy][bx d + ox],  c = (oz d + oy) d + ox,
+ * for any element size (1, 2, 4 or 8 bytes).  in/out (device), not aliased.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_interleave(const void *in, npvs_dims g, int32_t d, int32_t elem_bytes, void *out, void *stream);
+npvs_status npvs_deinterleave(const void *in, npvs_dims g, int32_t d, int32_t elem_bytes, void *out, void *stream);
+
+/* Sparse interleave of a packed bit grid onto the active sites:
+ *   X[r][c] = bit of froxel (bx d + ox, by d + oy, bz d + oz) of site r, as 0/1 in `dtype`
+ *   (NPVS_F32, NPVS_BF16 or NPVS_U8).  X (device) [cap_sites][d^3]; rows >= n_sites untouched.
+ * Used for the network input (bits = G) and for training labels. */
+npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                              const int32_t *site_keys, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
+                              void *X, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Weight packing.  W (device) float32 [27][cin][cout] -> Wp (device) of
+ * npvs_packed_weight_bytes() bytes in the layout of `dtype`'s convolution kernel.
+ * flip_transpose = 1 packs W'_k = (W_{26-k})^T, a [27][cout][cin] weight: the data gradient of
+ * a submanifold layer is the same convolution run with W' (the rulebook is symmetric).
+ * ------------------------------------------------------------------------------------------- */
+size_t npvs_packed_weight_bytes(int32_t cin, int32_t cout, int32_t dtype);
+npvs_status npvs_pack_weights(const float *W, int32_t cin, int32_t cout, int32_t dtype, int32_t flip_transpose,
+                              void *Wp, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Submanifold sparse 3x3x3 convolution, forward (Sec. 2.3, 3.3):
+ *   Y[r][o] = act(bias[o] + sum_k sum_c X[nbr[k][r]][c] W[k][c][o]),  act = ReLU if relu.
+ * dtype NPVS_F32: X, Y float32, vector FMA.  dtype NPVS_BF16: X bfloat16, products on MFMA
+ * with float32 accumulation, bias and ReLU in float32; Y is bfloat16, or float32 when
+ * out_f32 = 1 (the logits of the last layer).
+ *   X (device) [cap_sites][cin]; Wp packed weights; bias (device, nullable) float32 [cout];
+ *   nbr, counts from npvs_build_rulebook; Y (device) [cap_sites][cout], rows >= n_sites untouched.
+ * BF16 requires cin % 8 == 0, cin <= 512, cout % 8 == 0, cout <= 64.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                                 const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
+                                 int32_t relu, int32_t out_f32, void *Y, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Backward of one submanifold layer (chain rule on the forward definition):
+ *   dZ = dY * [Y > 0] when relu (ReLU'(0) = 0), else dY;
+ *   dX[i] = sum_k sum_{(i,r) in R_k} dZ[r] W_k^T           (nullable dX: skipped)
+ *   dW[k] = sum_{(i,r) in R_k} X[i]^T dZ[r],   db = sum_r dZ[r]   (float32, overwritten)
+ *   X (device) layer input [cap][cin] in `dtype`; Y (device, used when relu) layer output
+ *   [cap][cout] in `dtype`; dY (device) float32 [cap][cout]; Wt = npvs_pack_weights(W, ...,
+ *   flip_transpose = 1); rb_off/rb_pairs: CSR rulebook.  dX is float32 [cap][cin].
+ *   Reductions are deterministic (fixed order, compensated float32 sums).
+ *   ws (device) workspace of npvs_conv_bwd_workspace_size() bytes.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_conv_bwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
+npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
+                                 const float *dY, const int32_t *nbr, const int32_t *rb_off, const int32_t *rb_pairs,
+                                 const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
+                                 float *dW, float *db, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * De-interleave and threshold (Sec. 3.1 V = 1[f(G) >= tau] with tau = 0.5, read as logit >= 0;
+ * Sec. 3.3 g_d^-1; Sec. 3.2 the visible set lies inside the occupied set, so V is masked by G):
+ *   V(x) = [L(x) >= 0] and G(x),  L(x) = Y[row(block(x))][c(x)], -inf for inactive blocks.
+ *   Y (device) float32 [cap][d^3]; pvs_bits (device) packed like occ_bits, fully overwritten;
+ *   logits (device, nullable) float32 dense [sum nz*ny*nx], grid after grid, fully overwritten.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row, const uint8_t *occ_bits,
+                                        int32_t n_grids, const npvs_dims *dims, int32_t d, uint8_t *pvs_bits,
+                                        float *logits, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Training loss per grid over the froxels of its active blocks (Sec. 3.3: repulsive visibility
+ * loss L_rv = L_attr + L_rep with L_attr read as FN/GTP, L_rep = FP/GTP, combined with weight
+ * lambda; BCE stands in for the Dice term):
+ *   p = sigmoid(l); BCE = mean(softplus(l) - y l); TP = sum y p; FN = sum y (1-p);
+ *   FP = sum (1-y) p; GTP = sum y; L = lambda BCE + (1-lambda)(FN + FP)/max(GTP, 1).
+ * The batch loss is the mean over grids.
+ *   logits (device) float32 [cap][C]; labels (device) uint8 [cap][C] 0/1; grid_rows from the
+ *   rulebook; stats (device) float32 [n_grids + 1][8] = {L, BCE, L_rv, TP, FN, FP, GTP, m} per
+ *   grid, row n_grids = batch mean; dlogits (device, nullable) float32 [cap][C] = dL_batch/dl.
+ *   ws: npvs_loss_workspace_size() bytes.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes);
+npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                      int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, float *stats,
+                      float *dlogits, void *ws, size_t ws_bytes, void *stream);
+
+/* Adam (Kingma & Ba) step t >= 1 on float32 masters, with weight decay added to the gradient
+ * (the paper's "learning rate decay rate"); p, g, m, v (device) float32 [n]. */
+npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float beta1,
+                      float beta2, float eps, float weight_decay, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Whole forward pass V = threshold(g_d^-1(f(g_d(froxelize(tris))))) through a library-owned
+ * plan that holds the workspace, the site table, the activations and the packed weights of a
+ * fixed batch shape and network.  channels[0] must be d^3 and channels[n_layers] must be d^3;
+ * ReLU follows every layer but the last.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct npvs_plan npvs_plan;
+
+npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, const int64_t *n_tris, int32_t d,
+                             int32_t n_layers, const int32_t *channels, int32_t dtype, npvs_plan **plan);
+npvs_status npvs_plan_destroy(npvs_plan *plan);
+/* W (device) float32 [27][cin][cout], b (device, nullable) float32 [cout] of layer `layer`. */
+npvs_status npvs_plan_set_weights(npvs_plan *plan, int32_t layer, const float *W, const float *b, void *stream);
+/* tris as in npvs_froxelize.  occ_bits (nullable) receives G; logits (nullable) as in
+ * npvs_deinterleave_threshold; pvs_bits (device) receives V. */
+npvs_status npvs_pvs_forward(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits, float *logits,
+                             void *stream);
+/* Capture one npvs_pvs_forward with these buffers into a HIP graph owned by the plan, then
+ * replay it with npvs_plan_replay (one launch for the whole pass). */
+npvs_status npvs_plan_capture(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits, float *logits,
+                              void *stream);
+npvs_status npvs_plan_replay(npvs_plan *plan, void *stream);
+/* Synchronizes `stream` and copies the plan's npvs_counts to host memory; returns
+ * NPVS_ERR_CAPACITY if the site capacity overflowed (it cannot with the plan's capacity). */
+npvs_status npvs_plan_counts(npvs_plan *plan, npvs_counts *host_counts, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEURALPVS_H */

@@ -77,7 +77,7 @@ def _c(a, dtype):
 # ---------------------------------------------------------------- froxelization
 def quantize_tri(tri) -> np.ndarray | None:
     """Fixed-point (1/256 froxel, round half to even) vertices of one triangle, or None when
-    the triangle is ignored (non-finite or |coordinate| >= 2048)."""
+    the triangle is ignored (non-finite or |coordinate| >= 1024)."""
     t = _c(tri, np.float32).reshape(9)
     q = np.zeros((3, 3), np.int64)
     return q if _load().oracle_quantize_tri(_p(t), _p(q)) else None

@@ -20,7 +20,7 @@
 #include <string.h>
 
 #define FX 256 /* fixed-point scale: 1/256 froxel */
-#define COORD_LIMIT 2048.0
+#define COORD_LIMIT 1024.0
 
 static int64_t floordiv(int64_t a, int64_t b) {
   int64_t q = a / b;
@@ -37,7 +37,7 @@ static int64_t max3(int64_t a, int64_t b, int64_t c) { int64_t m = a > b ? a : b
  * quantized to 1/256 froxel with round-half-to-even.  All predicates are exact in int64.
  * ------------------------------------------------------------------------------------------ */
 
-/* Quantize one triangle.  Returns 0 when a coordinate is non-finite or |v| >= 2048 froxels
+/* Quantize one triangle.  Returns 0 when a coordinate is non-finite or |v| >= 1024 froxels
  * (such triangles are ignored by definition). */
 int oracle_quantize_tri(const float *t, int64_t q[3][3]) {
   for (int v = 0; v < 3; ++v)

@@ -1,0 +1,280 @@
+"""NeuralPVS hot path on MI355X (gfx950): Python binding of ``libneuralpvs.so``.
+
+Every function here marshals torch tensors (device memory) and the current HIP stream into one
+call of the C ABI declared in ``include/neuralpvs.h``; all computation runs in the library's
+HIP kernels.  There is no CPU fallback: calls raise if the library is not built.
+
+Stages (paper: NeuralPVS, arXiv 2509.24677):
+  froxelize (Sec. 3.2) -> build_rulebook (Sec. 2.3 submanifold sites) -> gather_input
+  (g_d of Sec. 3.3 on the active sites) -> sparse_conv_fwd x L -> deinterleave_threshold
+  (g_d^-1 and V = 1[f >= tau], Sec. 3.1).  Plan runs them all as one stream of launches.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from ._lib import NPVS_BF16, NPVS_F32, NPVS_U8, NpvsError  # noqa: F401
+
+__all__ = [
+    "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
+    "sparse_conv_fwd", "sparse_conv_bwd", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
+    "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
+]
+
+_TORCH_DT = {NPVS_F32: torch.float32, NPVS_BF16: torch.bfloat16, NPVS_U8: torch.uint8}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def version() -> str:
+    return L.get().npvs_version().decode()
+
+
+def batch_sizes(dims, d: int):
+    tb, tby = ctypes.c_int64(), ctypes.c_int64()
+    L.call("npvs_batch_sizes", len(dims), L.dims_array(dims), d, ctypes.byref(tb), ctypes.byref(tby))
+    return tb.value, tby.value
+
+
+# --------------------------------------------------------------------------------- froxelize
+def froxelize(tris: torch.Tensor, n_tris, dims, occ: torch.Tensor | None = None) -> torch.Tensor:
+    """Packed occupancy bits of a batch of grids (uint8, grids back to back).
+
+    tris: float32 device tensor [sum T][3][3] in grid units; n_tris: triangles per grid."""
+    dims = [tuple(g) for g in dims]
+    n_tris = [int(t) for t in n_tris]
+    tris = tris.contiguous()
+    if tris.dtype != torch.float32 or tris.numel() != 9 * sum(n_tris):
+        raise ValueError("tris must be float32 [sum n_tris][3][3]")
+    darr, tarr = L.dims_array(dims), L.i64_array(n_tris)
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_froxelize_workspace_size", len(dims), darr, tarr, ctypes.byref(nbytes))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=_dev())
+    _, total_bytes = batch_sizes(dims, 1)
+    if occ is None:
+        occ = torch.empty(total_bytes, dtype=torch.uint8, device=_dev())
+    elif occ.numel() != total_bytes or occ.dtype != torch.uint8:
+        raise ValueError("occ must be uint8 with one byte per 8 froxels")
+    L.call("npvs_froxelize", _p(tris) if tris.numel() else None, tarr, len(dims), darr, _p(occ), _p(ws),
+           nbytes.value, _stream())
+    return occ
+
+
+# --------------------------------------------------------------------------------- rulebook
+@dataclass
+class Rulebook:
+    dims: list
+    d: int
+    cap: int
+    counts: torch.Tensor      # int32 [4] device (npvs_counts)
+    site_keys: torch.Tensor   # int32 [cap]
+    block_row: torch.Tensor   # int32 [total_blocks]
+    grid_rows: torch.Tensor   # int32 [n_grids + 1]
+    nbr: torch.Tensor         # int32 [27][cap]
+    rb_off: torch.Tensor | None = None    # int32 [28]
+    rb_pairs: torch.Tensor | None = None  # int32 [27 cap][2]
+
+    def host_counts(self) -> dict:
+        c = self.counts.cpu().tolist()
+        return dict(n_sites=c[0], n_sites_needed=c[1], n_pairs=c[2])
+
+
+def build_rulebook(occ: torch.Tensor, dims, d: int, cap: int | None = None, csr: bool = False) -> Rulebook:
+    dims = [tuple(g) for g in dims]
+    total_blocks, _ = batch_sizes(dims, d)
+    cap = total_blocks if cap is None else int(cap)
+    darr = L.dims_array(dims)
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_rulebook_workspace_size", len(dims), darr, d, cap, ctypes.byref(nbytes))
+    dev = _dev()
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    rb = Rulebook(dims, d, cap,
+                  torch.empty(4, dtype=torch.int32, device=dev),
+                  torch.empty(cap, dtype=torch.int32, device=dev),
+                  torch.empty(total_blocks, dtype=torch.int32, device=dev),
+                  torch.empty(len(dims) + 1, dtype=torch.int32, device=dev),
+                  torch.empty((27, cap), dtype=torch.int32, device=dev))
+    if csr:
+        rb.rb_off = torch.empty(28, dtype=torch.int32, device=dev)
+        rb.rb_pairs = torch.empty((27 * cap, 2), dtype=torch.int32, device=dev)
+    L.call("npvs_build_rulebook", _p(occ), len(dims), darr, d, cap, _p(rb.counts), _p(rb.site_keys),
+           _p(rb.block_row), _p(rb.grid_rows), _p(rb.nbr), _p(rb.rb_off), _p(rb.rb_pairs), _p(ws), nbytes.value,
+           _stream())
+    return rb
+
+
+# --------------------------------------------------------------------------------- interleave
+def gather_input(bits: torch.Tensor, rb: Rulebook, dtype: int = NPVS_F32, out: torch.Tensor | None = None):
+    """Sparse g_d: [cap][d^3] 0/1 values of `bits` on the active sites (rows >= n_sites are left
+    as allocated)."""
+    C = rb.d ** 3
+    if out is None:
+        out = torch.empty((rb.cap, C), dtype=_TORCH_DT[dtype], device=_dev())
+    L.call("npvs_gather_input", _p(bits), len(rb.dims), L.dims_array(rb.dims), rb.d, _p(rb.site_keys),
+           _p(rb.counts), rb.cap, dtype, _p(out), _stream())
+    return out
+
+
+def interleave(x: torch.Tensor, d: int) -> torch.Tensor:
+    """Dense g_d of a [nz][ny][nx] tensor -> [nz/d][ny/d][nx/d][d^3]."""
+    x = x.contiguous()
+    nz, ny, nx = x.shape
+    out = torch.empty((nz // d, ny // d, nx // d, d ** 3), dtype=x.dtype, device=x.device)
+    L.call("npvs_interleave", _p(x), L.Dims(nx, ny, nz), d, x.element_size(), _p(out), _stream())
+    return out
+
+
+def deinterleave(x: torch.Tensor, dims, d: int) -> torch.Tensor:
+    x = x.contiguous()
+    nx, ny, nz = dims
+    out = torch.empty((nz, ny, nx), dtype=x.dtype, device=x.device)
+    L.call("npvs_deinterleave", _p(x), L.Dims(nx, ny, nz), d, x.element_size(), _p(out), _stream())
+    return out
+
+
+# --------------------------------------------------------------------------------- convolution
+def pack_weights(W: torch.Tensor, dtype: int, flip_transpose: bool = False) -> torch.Tensor:
+    """Kernel layout of float32 weights [27][cin][cout] (uint8 byte tensor)."""
+    W = W.contiguous()
+    if W.dtype != torch.float32 or W.dim() != 3 or W.shape[0] != 27:
+        raise ValueError("W must be float32 [27][cin][cout]")
+    cin, cout = W.shape[1], W.shape[2]
+    nbytes = L.get().npvs_packed_weight_bytes(cin, cout, dtype)
+    Wp = torch.empty(nbytes, dtype=torch.uint8, device=W.device)
+    L.call("npvs_pack_weights", _p(W), cin, cout, dtype, int(flip_transpose), _p(Wp), _stream())
+    return Wp
+
+
+def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None, cin: int, cout: int,
+                    rb: Rulebook, dtype: int, relu: bool, out_f32: bool = False,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        odt = torch.float32 if (dtype == NPVS_F32 or out_f32) else torch.bfloat16
+        out = torch.empty((rb.cap, cout), dtype=odt, device=X.device)
+    L.call("npvs_sparse_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap, dtype,
+           int(relu), int(out_f32), _p(out), _stream())
+    return out
+
+
+def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int, relu: bool, want_dx: bool = True):
+    """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout])."""
+    if rb.rb_off is None:
+        raise ValueError("the backward needs a rulebook built with csr=True")
+    dev = X.device
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_workspace_size", cin, cout, rb.cap, dtype, ctypes.byref(nbytes))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    dX = torch.empty((rb.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
+    dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
+    db = torch.empty(cout, dtype=torch.float32, device=dev)
+    L.call("npvs_sparse_conv_bwd", _p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off),
+           _p(rb.rb_pairs), _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), nbytes.value,
+           _stream())
+    return dX, dW, db
+
+
+# --------------------------------------------------------------------------------- output
+def deinterleave_threshold(Y: torch.Tensor, rb: Rulebook, occ: torch.Tensor, want_logits: bool = False):
+    """(pvs bits uint8 like occ, dense float32 logits or None)."""
+    pvs = torch.empty_like(occ)
+    logits = None
+    if want_logits:
+        n = sum(nx * ny * nz for nx, ny, nz in rb.dims)
+        logits = torch.empty(n, dtype=torch.float32, device=occ.device)
+    L.call("npvs_deinterleave_threshold", _p(Y), _p(rb.block_row), _p(occ), len(rb.dims), L.dims_array(rb.dims),
+           rb.d, _p(pvs), _p(logits), _stream())
+    return pvs, logits
+
+
+# --------------------------------------------------------------------------------- training
+def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 0.99, want_grad: bool = True):
+    """Per-grid BCE + repulsive visibility loss.  Returns (stats float32 [n_grids + 1][8] with
+    columns L, BCE, L_rv, TP, FN, FP, GTP, m and the batch mean in the last row, dL/dlogits)."""
+    G = len(rb.dims)
+    C = logits.shape[1]
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_loss_workspace_size", G, ctypes.byref(nbytes))
+    dev = logits.device
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    stats = torch.empty((G + 1, 8), dtype=torch.float32, device=dev)
+    dl = torch.zeros_like(logits) if want_grad else None
+    L.call("npvs_loss", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam),
+           _p(stats), _p(dl), _p(ws), nbytes.value, _stream())
+    return stats, dl
+
+
+def adam(p, g, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-10):
+    L.call("npvs_adam", _p(p), _p(g), _p(m), _p(v), p.numel(), int(t), float(lr), float(beta1), float(beta2),
+           float(eps), float(weight_decay), _stream())
+
+
+# --------------------------------------------------------------------------------- plan
+class Plan:
+    """Library-owned plan of the whole forward pass for a fixed batch shape and network."""
+
+    def __init__(self, dims, n_tris, d: int, channels, dtype: int = NPVS_BF16):
+        self.dims = [tuple(g) for g in dims]
+        self.n_tris = [int(t) for t in n_tris]
+        self.d = d
+        self.channels = list(channels)
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        ch = (ctypes.c_int32 * len(self.channels))(*self.channels)
+        L.call("npvs_plan_create", len(self.dims), L.dims_array(self.dims), L.i64_array(self.n_tris), d,
+               len(self.channels) - 1, ch, dtype, ctypes.byref(h))
+        self._h = h
+        self.total_blocks, self.total_bytes = batch_sizes(self.dims, d)
+
+    def set_weights(self, layer: int, W: torch.Tensor, b: torch.Tensor | None = None):
+        L.call("npvs_plan_set_weights", self._h, layer, _p(W.contiguous()), _p(b), _stream())
+
+    def _outs(self, pvs, logits, want_logits):
+        if pvs is None:
+            pvs = torch.empty(self.total_bytes, dtype=torch.uint8, device=_dev())
+        if logits is None and want_logits:
+            n = sum(nx * ny * nz for nx, ny, nz in self.dims)
+            logits = torch.empty(n, dtype=torch.float32, device=_dev())
+        return pvs, logits
+
+    def forward(self, tris, pvs=None, occ=None, logits=None, want_logits=False):
+        pvs, logits = self._outs(pvs, logits, want_logits)
+        L.call("npvs_pvs_forward", self._h, _p(tris), _p(occ), _p(pvs), _p(logits), _stream())
+        return pvs, logits
+
+    def capture(self, tris, pvs=None, occ=None, logits=None, want_logits=False):
+        pvs, logits = self._outs(pvs, logits, want_logits)
+        L.call("npvs_plan_capture", self._h, _p(tris), _p(occ), _p(pvs), _p(logits), _stream())
+        self._captured = (tris, pvs, occ, logits)  # keep the captured buffers alive
+        return pvs, logits
+
+    def replay(self):
+        L.call("npvs_plan_replay", self._h, _stream())
+
+    def counts(self) -> dict:
+        c = L.Counts()
+        L.call("npvs_plan_counts", self._h, ctypes.byref(c), _stream())
+        return dict(n_sites=c.n_sites, n_sites_needed=c.n_sites_needed, n_pairs=c.n_pairs)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and L._lib is not None:
+            L._lib.npvs_plan_destroy(h)
+            self._h = None

@@ -1,0 +1,291 @@
+// Host side of the C ABI: argument checking, error text, batch descriptors, and the plan that
+// runs the whole forward pass (froxelize -> sites/rulebook -> interleave -> convolutions ->
+// de-interleave + threshold) on one stream, optionally captured into a HIP graph.
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "npvs_common.hpp"
+
+namespace npvs {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+npvs_status fail(npvs_status code, const std::string &msg) {
+  set_error(msg);
+  return code;
+}
+
+npvs_status check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return NPVS_OK;
+  return fail(NPVS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+npvs_status make_batch(int32_t n_grids, const npvs_dims *dims, int32_t d, const int64_t *n_tris, Batch *B) {
+  if (!dims) return fail(NPVS_ERR_INVALID_ARG, "null dims");
+  if (n_grids < 1 || n_grids > NPVS_MAX_GRIDS) return fail(NPVS_ERR_INVALID_ARG, "n_grids must be in [1, 32]");
+  if (d < 1 || d > 32 || (d & (d - 1))) return fail(NPVS_ERR_INVALID_ARG, "d must be a power of two in [1, 32]");
+  std::memset(B, 0, sizeof(*B));
+  B->n = n_grids;
+  B->d = d;
+  int64_t key = 0, tile = 0, occ = 0, dense = 0, tri = 0;
+  for (int b = 0; b < n_grids; ++b) {
+    const npvs_dims &g = dims[b];
+    if (g.nx < 8 || g.ny < 1 || g.nz < 1 || g.nx > NPVS_MAX_DIM || g.ny > NPVS_MAX_DIM || g.nz > NPVS_MAX_DIM)
+      return fail(NPVS_ERR_INVALID_ARG, "grid extents must be in [1, 1024] (nx >= 8)");
+    if (g.nx % 8) return fail(NPVS_ERR_INVALID_ARG, "nx must be a multiple of 8");
+    if (g.nx % d || g.ny % d || g.nz % d) return fail(NPVS_ERR_INVALID_ARG, "grid extents must be multiples of d");
+    GridDesc &G = B->g[b];
+    G.nx = g.nx;
+    G.ny = g.ny;
+    G.nz = g.nz;
+    G.Bx = g.nx / d;
+    G.By = g.ny / d;
+    G.Bz = g.nz / d;
+    G.occ_off = occ;
+    G.dense_off = dense;
+    G.key_off = (int32_t)key;
+    G.tile_off = (int32_t)tile;
+    G.tiles_x = (g.nx + kFroxTileX - 1) / kFroxTileX;
+    G.tiles_y = (g.ny + kFroxTileY - 1) / kFroxTileY;
+    G.tiles_z = (g.nz + kFroxTileZ - 1) / kFroxTileZ;
+    G.tri_off = tri;
+    G.tri_n = 0;
+    if (n_tris) {
+      if (n_tris[b] < 0 || n_tris[b] > INT32_MAX) return fail(NPVS_ERR_INVALID_ARG, "bad triangle count");
+      G.tri_n = (int32_t)n_tris[b];
+      tri += n_tris[b];
+    }
+    key += (int64_t)G.Bx * G.By * G.Bz;
+    tile += (int64_t)G.tiles_x * G.tiles_y * G.tiles_z;
+    occ += (int64_t)g.nz * g.ny * (g.nx / 8);
+    dense += (int64_t)g.nz * g.ny * g.nx;
+    if (key > INT32_MAX / 27 || tile > INT32_MAX / kFroxTileCap)
+      return fail(NPVS_ERR_INVALID_ARG, "batch too large");
+  }
+  B->total_blocks = (int32_t)key;
+  B->total_tiles = (int32_t)tile;
+  return NPVS_OK;
+}
+
+npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                              const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
+                              int32_t out_f32, void *Y, hipStream_t s, int variant);
+
+}  // namespace npvs
+
+using namespace npvs;
+
+extern "C" const char *npvs_version(void) { return "neuralpvs-gfx950 0.1.0"; }
+
+extern "C" const char *npvs_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" npvs_status npvs_batch_sizes(int32_t n_grids, const npvs_dims *dims, int32_t d, int64_t *total_blocks,
+                                       int64_t *total_bytes) {
+  if (!total_blocks || !total_bytes) return fail(NPVS_ERR_INVALID_ARG, "npvs_batch_sizes: null pointer");
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  *total_blocks = B.total_blocks;
+  int64_t bytes = 0;
+  for (int b = 0; b < n_grids; ++b) bytes += (int64_t)dims[b].nz * dims[b].ny * (dims[b].nx / 8);
+  *total_bytes = bytes;
+  return NPVS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Plan
+// ------------------------------------------------------------------------------------------
+struct npvs_plan {
+  int n_grids = 0, d = 0, n_layers = 0, dtype = 0, cap = 0;
+  std::vector<npvs_dims> dims;
+  std::vector<int64_t> n_tris;
+  std::vector<int32_t> ch;
+  int64_t total_bytes = 0, total_dense = 0;
+  size_t frox_ws = 0, rb_ws = 0;
+  std::vector<void *> allocs;
+  void *d_frox_ws = nullptr, *d_rb_ws = nullptr, *d_X0 = nullptr, *d_act[2] = {nullptr, nullptr};
+  uint8_t *d_occ = nullptr;
+  npvs_counts *d_counts = nullptr;
+  int32_t *d_keys = nullptr, *d_block_row = nullptr, *d_grid_rows = nullptr, *d_nbr = nullptr;
+  float *d_logits = nullptr;
+  std::vector<void *> d_Wp;
+  std::vector<float *> d_bias;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static npvs_status plan_alloc(npvs_plan *p, void **ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes > 0 ? bytes : 1);
+  if (e != hipSuccess) return check_hip(e, "npvs_plan_create: hipMalloc");
+  p->allocs.push_back(*ptr);
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_plan_destroy(npvs_plan *plan) {
+  if (!plan) return NPVS_OK;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  for (void *a : plan->allocs) (void)hipFree(a);
+  delete plan;
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, const int64_t *n_tris, int32_t d,
+                                       int32_t n_layers, const int32_t *channels, int32_t dtype, npvs_plan **out) {
+  if (!out || !channels || !n_tris) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_create: null pointer");
+  *out = nullptr;
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, n_tris, &B);
+  if (st != NPVS_OK) return st;
+  if (n_layers < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_create: n_layers < 1");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_create: bad dtype");
+  const int C = d * d * d;
+  if (channels[0] != C || channels[n_layers] != C)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_create: first and last channel counts must be d^3");
+  int maxc = 0;
+  for (int l = 0; l <= n_layers; ++l) {
+    if (channels[l] < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_create: channels must be >= 1");
+    if (l > 0 && l < n_layers) maxc = channels[l] > maxc ? channels[l] : maxc;
+  }
+  npvs_plan *p = new npvs_plan();
+  p->n_grids = n_grids;
+  p->d = d;
+  p->n_layers = n_layers;
+  p->dtype = dtype;
+  p->cap = B.total_blocks;
+  p->dims.assign(dims, dims + n_grids);
+  p->n_tris.assign(n_tris, n_tris + n_grids);
+  p->ch.assign(channels, channels + n_layers + 1);
+  for (int b = 0; b < n_grids; ++b) {
+    p->total_bytes += (int64_t)dims[b].nz * dims[b].ny * (dims[b].nx / 8);
+    p->total_dense += (int64_t)dims[b].nz * dims[b].ny * dims[b].nx;
+  }
+  const size_t es = dtype == NPVS_F32 ? 4 : 2;
+  const size_t cap = (size_t)p->cap;
+#define TRY(x)                 \
+  do {                         \
+    npvs_status s_ = (x);      \
+    if (s_ != NPVS_OK) {       \
+      npvs_plan_destroy(p);    \
+      return s_;               \
+    }                          \
+  } while (0)
+  TRY(npvs_froxelize_workspace_size(n_grids, dims, n_tris, &p->frox_ws));
+  TRY(npvs_rulebook_workspace_size(n_grids, dims, d, p->cap, &p->rb_ws));
+  TRY(plan_alloc(p, &p->d_frox_ws, p->frox_ws));
+  TRY(plan_alloc(p, &p->d_rb_ws, p->rb_ws));
+  TRY(plan_alloc(p, (void **)&p->d_occ, (size_t)p->total_bytes));
+  TRY(plan_alloc(p, (void **)&p->d_counts, sizeof(npvs_counts)));
+  TRY(plan_alloc(p, (void **)&p->d_keys, sizeof(int32_t) * cap));
+  TRY(plan_alloc(p, (void **)&p->d_block_row, sizeof(int32_t) * cap));
+  TRY(plan_alloc(p, (void **)&p->d_grid_rows, sizeof(int32_t) * (n_grids + 1)));
+  TRY(plan_alloc(p, (void **)&p->d_nbr, sizeof(int32_t) * 27 * cap));
+  TRY(plan_alloc(p, &p->d_X0, es * cap * C));
+  if (n_layers > 1) {
+    TRY(plan_alloc(p, &p->d_act[0], es * cap * maxc));
+    TRY(plan_alloc(p, &p->d_act[1], es * cap * maxc));
+  }
+  TRY(plan_alloc(p, (void **)&p->d_logits, sizeof(float) * cap * C));
+  p->d_Wp.assign(n_layers, nullptr);
+  p->d_bias.assign(n_layers, nullptr);
+  for (int l = 0; l < n_layers; ++l) {
+    TRY(plan_alloc(p, &p->d_Wp[l], npvs_packed_weight_bytes(channels[l], channels[l + 1], dtype)));
+    TRY(plan_alloc(p, (void **)&p->d_bias[l], sizeof(float) * channels[l + 1]));
+    TRY(check_hip(hipMemset(p->d_bias[l], 0, sizeof(float) * channels[l + 1]), "npvs_plan_create"));
+  }
+#undef TRY
+  *out = p;
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_plan_set_weights(npvs_plan *plan, int32_t layer, const float *W, const float *b,
+                                            void *stream) {
+  if (!plan || !W) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_set_weights: null pointer");
+  if (layer < 0 || layer >= plan->n_layers) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_set_weights: bad layer");
+  const int cin = plan->ch[layer], cout = plan->ch[layer + 1];
+  npvs_status st = npvs_pack_weights(W, cin, cout, plan->dtype, 0, plan->d_Wp[layer], stream);
+  if (st != NPVS_OK) return st;
+  hipStream_t s = as_stream(stream);
+  if (b)
+    return check_hip(hipMemcpyAsync(plan->d_bias[layer], b, sizeof(float) * cout, hipMemcpyDeviceToDevice, s),
+                     "npvs_plan_set_weights");
+  return NPVS_OK;
+}
+
+static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_out, uint8_t *pvs, float *logits,
+                                hipStream_t s, int variant) {
+  uint8_t *occ = occ_out ? occ_out : p->d_occ;
+  npvs_status st = npvs_froxelize(tris, p->n_tris.data(), p->n_grids, p->dims.data(), occ, p->d_frox_ws, p->frox_ws, s);
+  if (st != NPVS_OK) return st;
+  st = npvs_build_rulebook(occ, p->n_grids, p->dims.data(), p->d, p->cap, p->d_counts, p->d_keys, p->d_block_row,
+                           p->d_grid_rows, p->d_nbr, nullptr, nullptr, p->d_rb_ws, p->rb_ws, s);
+  if (st != NPVS_OK) return st;
+  st = npvs_gather_input(occ, p->n_grids, p->dims.data(), p->d, p->d_keys, p->d_counts, p->cap, p->dtype, p->d_X0, s);
+  if (st != NPVS_OK) return st;
+  const void *in = p->d_X0;
+  for (int l = 0; l < p->n_layers; ++l) {
+    const bool last = l == p->n_layers - 1;
+    void *out = last ? (void *)p->d_logits : p->d_act[l & 1];
+    st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
+                           p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, variant);
+    if (st != NPVS_OK) return st;
+    in = out;
+  }
+  return npvs_deinterleave_threshold(p->d_logits, p->d_block_row, occ, p->n_grids, p->dims.data(), p->d, pvs, logits,
+                                     s);
+}
+
+extern "C" npvs_status npvs_pvs_forward(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits,
+                                       float *logits, void *stream) {
+  if (!plan || !pvs_bits) return fail(NPVS_ERR_INVALID_ARG, "npvs_pvs_forward: null pointer");
+  return plan_forward(plan, tris, occ_bits, pvs_bits, logits, as_stream(stream), 0);
+}
+
+extern "C" npvs_status npvs_plan_capture(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits,
+                                        float *logits, void *stream) {
+  if (!plan || !pvs_bits) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_capture: null pointer");
+  hipStream_t s = as_stream(stream);
+  if (!s) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_capture: capture needs a non-null stream");
+  if (plan->exec) {
+    (void)hipGraphExecDestroy(plan->exec);
+    plan->exec = nullptr;
+  }
+  if (plan->graph) {
+    (void)hipGraphDestroy(plan->graph);
+    plan->graph = nullptr;
+  }
+  npvs_status st = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "npvs_plan_capture: begin");
+  if (st != NPVS_OK) return st;
+  npvs_status fst = plan_forward(plan, tris, occ_bits, pvs_bits, logits, s, 0);
+  hipGraph_t g = nullptr;
+  st = check_hip(hipStreamEndCapture(s, &g), "npvs_plan_capture: end");
+  if (fst != NPVS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return fst;
+  }
+  if (st != NPVS_OK) return st;
+  plan->graph = g;
+  return check_hip(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0), "npvs_plan_capture: instantiate");
+}
+
+extern "C" npvs_status npvs_plan_replay(npvs_plan *plan, void *stream) {
+  if (!plan || !plan->exec) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_replay: no captured graph");
+  return check_hip(hipGraphLaunch(plan->exec, as_stream(stream)), "npvs_plan_replay");
+}
+
+extern "C" npvs_status npvs_plan_counts(npvs_plan *plan, npvs_counts *host_counts, void *stream) {
+  if (!plan || !host_counts) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_counts: null pointer");
+  hipStream_t s = as_stream(stream);
+  npvs_status st = check_hip(hipMemcpyAsync(host_counts, plan->d_counts, sizeof(npvs_counts), hipMemcpyDeviceToHost, s),
+                             "npvs_plan_counts");
+  if (st != NPVS_OK) return st;
+  st = check_hip(hipStreamSynchronize(s), "npvs_plan_counts");
+  if (st != NPVS_OK) return st;
+  if (host_counts->n_sites_needed > host_counts->n_sites)
+    return fail(NPVS_ERR_CAPACITY, "npvs_plan_counts: site capacity overflowed");
+  return NPVS_OK;
+}

@@ -1,0 +1,337 @@
+// Submanifold sparse 3x3x3 convolution, forward (Sec. 2.3, 3.3):
+//   Y[r][o] = act(b[o] + sum_k sum_c X[nbr[k][r]][c] W[k][c][o])
+// Output-stationary gather-GEMM: a tile of output rows loops over the 27 offsets, gathers the
+// neighbour rows of each offset and multiplies them by W_k.  Each offset really is a dense
+// [rows x Cin] x [Cin x Cout] contraction, so the BF16 path runs it on MFMA.
+#include "npvs_common.hpp"
+
+namespace npvs {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+// ------------------------------------------------------------------------------------------
+// XCD-aware tile order: workgroup i runs on XCD (i % 8); the tiles of a layer are cut into 8
+// contiguous ranges, one per XCD, so neighbouring rows (which gather overlapping inputs) share
+// that XCD's L2.  Returns the j-th tile of workgroup i, or -1.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int i, int G, int ntiles, int j) {
+  const int per = (ntiles + 7) >> 3;  // tiles per XCD
+  const int slot = (i >> 3) + j * (G >> 3);
+  if (slot >= per) return -1;
+  int t = (i & 7) * per + slot;
+  return t < ntiles ? t : -1;
+}
+
+// ------------------------------------------------------------------------------------------
+// Weight packing.  P is the conv weight a kernel reads, [27][CI][CO]:
+//   plain: P[k][c][o] = W[k][c][o]            (CI = cin,  CO = cout)
+//   flip : P[k][c][o] = W[26-k][o][c]         (CI = cout, CO = cin; the data-gradient weight)
+// F32 layout: P itself.  BF16 layout: MFMA A-operand fragments of P^T for
+// v_mfma_f32_16x16x32_bf16, Wp[k][nb][kb][lane][j] = P[k][kb*32 + 8*(lane/16) + j][nb*16 + lane%16]
+// (zero outside CI x CO), so each lane loads its 8 values with one 16-byte load.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float packed_src(const float *W, int cin, int cout, int flip, int k, int c, int o) {
+  return flip ? W[((int64_t)(26 - k) * cin + o) * cout + c] : W[((int64_t)k * cin + c) * cout + o];
+}
+
+__global__ void pack_f32_kernel(const float *__restrict__ W, int cin, int cout, int flip, float *__restrict__ P) {
+  const int CI = flip ? cout : cin, CO = flip ? cin : cout;
+  const int64_t total = 27LL * CI * CO;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int o = e % CO, c = (e / CO) % CI, k = e / ((int64_t)CO * CI);
+    P[e] = packed_src(W, cin, cout, flip, k, c, o);
+  }
+}
+
+__global__ void pack_bf16_kernel(const float *__restrict__ W, int cin, int cout, int flip, uint16_t *__restrict__ P) {
+  const int CI = flip ? cout : cin, CO = flip ? cin : cout;
+  const int KB = (CI + 31) / 32, NB = (CO + 15) / 16;
+  const int64_t total = 27LL * NB * KB * 64 * 8;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int j = e & 7, lane = (e >> 3) & 63;
+    int64_t f = e >> 9;  // fragment index (k, nb, kb)
+    int kb = f % KB, nb = (f / KB) % NB, k = f / ((int64_t)KB * NB);
+    int c = kb * 32 + 8 * (lane >> 4) + j, o = nb * 16 + (lane & 15);
+    float v = (c < CI && o < CO) ? packed_src(W, cin, cout, flip, k, c, o) : 0.0f;
+    P[e] = f32_to_bf16(v);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Plain FP32 path (vector FMA).  Workgroup of 256 = 4 waves; a tile of 32 output rows; lane =
+// output channel of a 64-channel group; each wave owns 8 rows.  For each offset the tile's 32
+// neighbour rows are staged through LDS 64 input channels at a time; every lane reads them as
+// broadcasts and its weight column with a coalesced load.
+// ------------------------------------------------------------------------------------------
+constexpr int kF32Rows = 32;
+
+__global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restrict__ X, int cin,
+                                                            const float *__restrict__ P,
+                                                            const float *__restrict__ bias, int cout,
+                                                            const int32_t *__restrict__ nbr,
+                                                            const npvs_counts *__restrict__ counts, int cap, int relu,
+                                                            float *__restrict__ Y) {
+  __shared__ float Xs[kF32Rows][64];
+  __shared__ int idx_s[kF32Rows];
+  const int32_t n = counts->n_sites;
+  const int ntiles = (n + kF32Rows - 1) / kF32Rows;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = 0;; ++j) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
+    if (tile < 0) break;
+    const int row0 = tile * kF32Rows;
+    for (int cg = 0; cg < cout; cg += 64) {
+      const int o = cg + lane;
+      float acc[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+      for (int k = 0; k < 27; ++k) {
+        __syncthreads();
+        if (tid < kF32Rows) idx_s[tid] = row0 + tid < n ? nbr[(int64_t)k * cap + row0 + tid] : -1;
+        __syncthreads();
+        if (!__syncthreads_or(idx_s[tid & (kF32Rows - 1)] >= 0)) continue;
+        for (int c0 = 0; c0 < cin; c0 += 64) {
+          for (int e = tid; e < kF32Rows * 64; e += 256) {
+            int r = e >> 6, c = e & 63;
+            int src = idx_s[r];
+            Xs[r][c] = (src >= 0 && c0 + c < cin) ? X[(int64_t)src * cin + c0 + c] : 0.0f;
+          }
+          __syncthreads();
+          const int cn = cin - c0 < 64 ? cin - c0 : 64;
+          if (o < cout) {
+            const float *wp = P + ((int64_t)k * cin + c0) * cout + o;
+            for (int c = 0; c < cn; c += 4) {
+              float w0 = wp[(int64_t)c * cout];
+              float w1 = c + 1 < cn ? wp[(int64_t)(c + 1) * cout] : 0.0f;
+              float w2 = c + 2 < cn ? wp[(int64_t)(c + 2) * cout] : 0.0f;
+              float w3 = c + 3 < cn ? wp[(int64_t)(c + 3) * cout] : 0.0f;
+#pragma unroll
+              for (int i = 0; i < 8; ++i) {
+                const float4 xv = *reinterpret_cast<const float4 *>(&Xs[wv * 8 + i][c]);
+                acc[i] = fmaf(xv.x, w0, acc[i]);
+                acc[i] = fmaf(xv.y, w1, acc[i]);
+                acc[i] = fmaf(xv.z, w2, acc[i]);
+                acc[i] = fmaf(xv.w, w3, acc[i]);
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      if (o < cout) {
+        const float bo = bias ? bias[o] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          int r = row0 + wv * 8 + i;
+          if (r < n) {
+            float v = acc[i] + bo;
+            Y[(int64_t)r * cout + o] = (relu && v < 0.0f) ? 0.0f : v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16 path on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+// The product is computed transposed, D = W^T X^T, so that a lane's accumulator holds four
+// consecutive output channels of one row (a single 8- or 16-byte store):
+//   A (16 x 32) = W^T block: lane l gives W[kb*32 + 8(l/16) + j][nb*16 + l%16]   (packed, one load)
+//   B (32 x 16) = X^T block: lane l gives X[row0 + l%16][kb*32 + 8(l/16) + j]    (gathered row, one load)
+//   D (16 x 16): lane l holds Y[row0 + l%16][nb*16 + 4(l/16) + i], i = 0..3
+// A wave owns MB x 16 rows and all NB x 16 output channels.  With KSPLIT = 3 the three waves
+// of a workgroup take the dz = -1, 0, +1 slices of the offsets of the same rows and their
+// partial sums are added in LDS in a fixed order.
+// ------------------------------------------------------------------------------------------
+template <int KB, int NB, int MB, int KSPLIT>
+__global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16_t *__restrict__ X, int cin,
+                                                                     const bf16x8_t *__restrict__ Wp,
+                                                                     const float *__restrict__ bias, int cout,
+                                                                     const int32_t *__restrict__ nbr,
+                                                                     const npvs_counts *__restrict__ counts, int cap,
+                                                                     int relu, int out_f32, void *__restrict__ Y) {
+  constexpr int ROWS = 16 * MB;
+  __shared__ f32x4_t red[KSPLIT > 1 ? (KSPLIT - 1) * MB * NB * 64 : 1];
+  const int32_t n = counts->n_sites;
+  const int ntiles = (n + ROWS - 1) / ROWS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kbeg = wv * 27 / KSPLIT, kend = (wv + 1) * 27 / KSPLIT;
+  const int csub = 8 * (lane >> 4);
+  const bf16x8_t zero8 = {};
+  for (int j = 0;; ++j) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
+    if (tile < 0) break;
+    const int row0 = tile * ROWS;
+    f32x4_t acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k = kbeg; k < kend; ++k) {
+      int idx[MB];
+      bool any = false;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int r = row0 + mb * 16 + (lane & 15);
+        idx[mb] = r < n ? nbr[(int64_t)k * cap + r] : -1;
+        any = any || idx[mb] >= 0;
+      }
+      if (!__any(any)) continue;  // no row of this wave has a neighbour at offset k
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int c = kb * 32 + csub;
+        bf16x8_t bx[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+          bx[mb] = (idx[mb] >= 0 && c < cin)
+                       ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[mb] * cin + c)
+                       : zero8;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8_t aw = Wp[(((int64_t)k * NB + nb) * KB + kb) * 64 + lane];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[mb], acc[mb][nb], 0, 0, 0);
+        }
+      }
+    }
+    if constexpr (KSPLIT > 1) {
+      __syncthreads();
+      if (wv > 0)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) red[(((wv - 1) * MB + mb) * NB + nb) * 64 + lane] = acc[mb][nb];
+      __syncthreads();
+      if (wv == 0)
+        for (int w = 1; w < KSPLIT; ++w)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] += red[(((w - 1) * MB + mb) * NB + nb) * 64 + lane];
+    }
+    if (wv == 0) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int r = row0 + mb * 16 + (lane & 15);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int o = nb * 16 + 4 * (lane >> 4);
+          if (r >= n || o >= cout) continue;
+          float v[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float t = acc[mb][nb][i] + (bias ? bias[o + i] : 0.0f);
+            v[i] = (relu && t < 0.0f) ? 0.0f : t;
+          }
+          if (out_f32) {
+            *reinterpret_cast<float4 *>(static_cast<float *>(Y) + (int64_t)r * cout + o) = make_float4(v[0], v[1], v[2], v[3]);
+          } else {
+            uint2 p;
+            p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+            p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = p;
+          }
+        }
+      }
+    }
+    if constexpr (KSPLIT > 1) __syncthreads();
+  }
+}
+
+template <int KB, int NB, int MB, int KSPLIT>
+static void launch_bf16(const void *X, int cin, const void *Wp, const float *bias, int cout, const int32_t *nbr,
+                        const npvs_counts *counts, int cap, int relu, int out_f32, void *Y, hipStream_t s) {
+  const int rows = 16 * MB;
+  int G = stride_grid(cap, rows, 2048);
+  G = (G + 7) & ~7;
+  conv_fwd_bf16_kernel<KB, NB, MB, KSPLIT><<<G, 64 * KSPLIT, 0, s>>>(
+      (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+}  // namespace npvs
+
+using namespace npvs;
+
+extern "C" size_t npvs_packed_weight_bytes(int32_t cin, int32_t cout, int32_t dtype) {
+  if (cin < 1 || cout < 1) return 0;
+  if (dtype == NPVS_F32) return sizeof(float) * 27 * (size_t)cin * cout;
+  if (dtype == NPVS_BF16) {
+    size_t a = 27 * (size_t)((cout + 15) / 16) * ((cin + 31) / 32) * 1024;
+    size_t b = 27 * (size_t)((cin + 15) / 16) * ((cout + 31) / 32) * 1024;
+    return a > b ? a : b;
+  }
+  return 0;
+}
+
+extern "C" npvs_status npvs_pack_weights(const float *W, int32_t cin, int32_t cout, int32_t dtype,
+                                        int32_t flip_transpose, void *Wp, void *stream) {
+  if (!W || !Wp) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights: null pointer");
+  if (cin < 1 || cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights: channels must be >= 1");
+  hipStream_t s = as_stream(stream);
+  if (dtype == NPVS_F32) {
+    pack_f32_kernel<<<stride_grid(27LL * cin * cout, 256, 1024), 256, 0, s>>>(W, cin, cout, flip_transpose ? 1 : 0,
+                                                                             (float *)Wp);
+  } else if (dtype == NPVS_BF16) {
+    pack_bf16_kernel<<<stride_grid(npvs_packed_weight_bytes(cin, cout, dtype) / 2, 256, 1024), 256, 0, s>>>(
+        W, cin, cout, flip_transpose ? 1 : 0, (uint16_t *)Wp);
+  } else {
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights: dtype must be NPVS_F32 or NPVS_BF16");
+  }
+  return check_hip(hipGetLastError(), "npvs_pack_weights");
+}
+
+namespace npvs {
+// Dispatch of the BF16 kernel on (ceil(cin/32), ceil(cout/16)); MB = 2 rows blocks per wave,
+// offsets split three ways.
+npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                              const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
+                              int32_t out_f32, void *Y, hipStream_t s, int variant) {
+  if (dtype == NPVS_F32) {
+    int G = stride_grid(cap, kF32Rows, 2048);
+    G = (G + 7) & ~7;
+    conv_fwd_f32_kernel<<<G, 256, 0, s>>>((const float *)X, cin, (const float *)Wp, bias, cout, nbr, counts, cap, relu,
+                                          (float *)Y);
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
+  }
+  if (cin % 8 || cout % 8 || cin > 512 || cout > 64)
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: BF16 needs cin % 8 == 0, cin <= 512, cout % 8 == 0, cout <= 64");
+  const int KB = (cin + 31) / 32, NB = (cout + 15) / 16;
+#define NPVS_BF16_CASE(kb, nb)                                                                               \
+  if (KB == kb && NB == nb) {                                                                                \
+    if (variant == 1)                                                                                        \
+      launch_bf16<kb, nb, 2, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);              \
+    else if (variant == 2)                                                                                   \
+      launch_bf16<kb, nb, 1, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);              \
+    else                                                                                                     \
+      launch_bf16<kb, nb, 2, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);              \
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");                                             \
+  }
+  NPVS_BF16_CASE(1, 1)
+  NPVS_BF16_CASE(1, 2)
+  NPVS_BF16_CASE(1, 3)
+  NPVS_BF16_CASE(1, 4)
+  NPVS_BF16_CASE(2, 1)
+  NPVS_BF16_CASE(2, 2)
+  NPVS_BF16_CASE(2, 3)
+  NPVS_BF16_CASE(2, 4)
+  NPVS_BF16_CASE(16, 4)
+#undef NPVS_BF16_CASE
+  return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: no BF16 kernel for this channel shape");
+}
+}  // namespace npvs
+
+extern "C" npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
+                                           int32_t cout, const int32_t *nbr, const npvs_counts *counts,
+                                           int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32, void *Y,
+                                           void *stream) {
+  if (!X || !Wp || !nbr || !counts || !Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: null pointer");
+  if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: bad sizes");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: dtype must be NPVS_F32 or NPVS_BF16");
+  if (X == Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: X and Y must not alias");
+  return conv_fwd_dispatch(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32, Y,
+                           as_stream(stream), 0);
+}

@@ -1,0 +1,171 @@
+// Interleave g_d, its inverse, the sparse interleave onto active sites and the fused
+// de-interleave + threshold (Sec. 3.1, Sec. 3.3).  All are pure index permutations bounded by
+// HBM bandwidth: each thread moves one contiguous run so that either the loads or the stores
+// of a wave are contiguous.
+#include "npvs_common.hpp"
+
+namespace npvs {
+
+// Dense g_d: one thread per (block, oz, oy) row of d contiguous x-elements.  The d elements
+// are contiguous on both sides (input row segment, output channel run).
+template <typename T>
+__global__ __launch_bounds__(256) void dense_interleave_kernel(const T *__restrict__ in, T *__restrict__ out, int nx,
+                                                                int ny, int nz, int d, int inverse) {
+  const int Bx = nx / d, By = ny / d, Bz = nz / d;
+  const int64_t runs = (int64_t)Bx * By * Bz * d * d;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < runs; t += (int64_t)gridDim.x * blockDim.x) {
+    // t enumerates (block key, oz, oy) with the block key outermost: output-contiguous
+    int oy = t % d, oz = (t / d) % d;
+    int64_t key = t / ((int64_t)d * d);
+    int bx = key % Bx, by = (key / Bx) % By, bz = key / ((int64_t)Bx * By);
+    int64_t src = ((int64_t)(bz * d + oz) * ny + (by * d + oy)) * nx + (int64_t)bx * d;
+    int64_t dst = key * (int64_t)d * d * d + (int64_t)(oz * d + oy) * d;
+    if (!inverse)
+      for (int ox = 0; ox < d; ++ox) out[dst + ox] = in[src + ox];
+    else
+      for (int ox = 0; ox < d; ++ox) out[src + ox] = in[dst + ox];
+  }
+}
+
+// Sparse interleave of packed bits onto active sites: one thread per (site, oz, oy) run of d
+// channels.
+template <typename T>
+__device__ __forceinline__ T one_zero(int bit);
+template <>
+__device__ __forceinline__ float one_zero<float>(int bit) { return bit ? 1.0f : 0.0f; }
+template <>
+__device__ __forceinline__ uint16_t one_zero<uint16_t>(int bit) { return bit ? (uint16_t)0x3f80 : (uint16_t)0; }
+template <>
+__device__ __forceinline__ uint8_t one_zero<uint8_t>(int bit) { return (uint8_t)bit; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t *__restrict__ bits,
+                                                           const int32_t *__restrict__ site_keys,
+                                                           const npvs_counts *__restrict__ counts, T *__restrict__ X) {
+  const int d = B.d;
+  const int32_t n = counts->n_sites;
+  const int64_t runs = (int64_t)n * d * d;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < runs; t += (int64_t)gridDim.x * blockDim.x) {
+    int oy = t % d, oz = (t / d) % d;
+    int32_t r = (int32_t)(t / ((int64_t)d * d));
+    int32_t key = site_keys[r];
+    const GridDesc &g = B.g[grid_of_key(B, key)];
+    int32_t l = key - g.key_off;
+    int bx = l % g.Bx, by = (l / g.Bx) % g.By, bz = l / (g.Bx * g.By);
+    const uint8_t *row = bits + g.occ_off + ((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * (g.nx >> 3);
+    T *dst = X + (int64_t)r * d * d * d + (oz * d + oy) * d;
+    const int x0 = bx * d;
+    for (int ox = 0; ox < d; ++ox) {
+      int x = x0 + ox;
+      dst[ox] = one_zero<T>((row[x >> 3] >> (x & 7)) & 1);
+    }
+  }
+}
+
+// De-interleave + threshold + pack: one thread per packed output byte (8 froxels along x).
+__global__ __launch_bounds__(256) void deinterleave_threshold_kernel(Batch B, int64_t total_bytes,
+                                                                      const float *__restrict__ Y,
+                                                                      const int32_t *__restrict__ block_row,
+                                                                      const uint8_t *__restrict__ occ,
+                                                                      uint8_t *__restrict__ pvs,
+                                                                      float *__restrict__ logits) {
+  const int d = B.d, C = d * d * d;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_bytes;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int b = 0;
+    while (b + 1 < B.n && t >= B.g[b + 1].occ_off) ++b;
+    const GridDesc &g = B.g[b];
+    int64_t l = t - g.occ_off;
+    const int rb = g.nx >> 3;
+    int xb = l % rb;
+    int y = (l / rb) % g.ny;
+    int z = l / ((int64_t)rb * g.ny);
+    const uint8_t gbits = occ[t];
+    uint8_t out = 0;
+    float lv[8];
+    const int key_yz = g.key_off + ((z / d) * g.By + (y / d)) * g.Bx;
+    const int cyz = ((z % d) * d + (y % d)) * d;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int x = xb * 8 + i;
+      int32_t row = block_row[key_yz + x / d];
+      float v = row >= 0 ? Y[(int64_t)row * C + cyz + (x % d)] : -__builtin_huge_valf();
+      lv[i] = v;
+      out |= (uint8_t)(((v >= 0.0f) && ((gbits >> i) & 1)) << i);
+    }
+    pvs[t] = out;
+    if (logits) {
+      float4 *dst = reinterpret_cast<float4 *>(logits + g.dense_off + (((int64_t)z * g.ny + y) * g.nx + xb * 8));
+      dst[0] = make_float4(lv[0], lv[1], lv[2], lv[3]);
+      dst[1] = make_float4(lv[4], lv[5], lv[6], lv[7]);
+    }
+  }
+}
+
+}  // namespace npvs
+
+using namespace npvs;
+
+static npvs_status dense_perm(const void *in, npvs_dims g, int32_t d, int32_t esize, void *out, void *stream,
+                              int inverse, const char *name) {
+  if (!in || !out) return fail(NPVS_ERR_INVALID_ARG, std::string(name) + ": null pointer");
+  Batch B;
+  npvs_status st = make_batch(1, &g, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  int64_t runs = (int64_t)(g.nx / d) * (g.ny / d) * (g.nz / d) * d * d;
+  int grid = stride_grid(runs, 256, 8192);
+  hipStream_t s = as_stream(stream);
+  switch (esize) {
+    case 1: dense_interleave_kernel<uint8_t><<<grid, 256, 0, s>>>((const uint8_t *)in, (uint8_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
+    case 2: dense_interleave_kernel<uint16_t><<<grid, 256, 0, s>>>((const uint16_t *)in, (uint16_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
+    case 4: dense_interleave_kernel<uint32_t><<<grid, 256, 0, s>>>((const uint32_t *)in, (uint32_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
+    case 8: dense_interleave_kernel<uint64_t><<<grid, 256, 0, s>>>((const uint64_t *)in, (uint64_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
+    default: return fail(NPVS_ERR_INVALID_ARG, std::string(name) + ": elem_bytes must be 1, 2, 4 or 8");
+  }
+  return check_hip(hipGetLastError(), name);
+}
+
+extern "C" npvs_status npvs_interleave(const void *in, npvs_dims g, int32_t d, int32_t elem_bytes, void *out,
+                                      void *stream) {
+  return dense_perm(in, g, d, elem_bytes, out, stream, 0, "npvs_interleave");
+}
+
+extern "C" npvs_status npvs_deinterleave(const void *in, npvs_dims g, int32_t d, int32_t elem_bytes, void *out,
+                                        void *stream) {
+  return dense_perm(in, g, d, elem_bytes, out, stream, 1, "npvs_deinterleave");
+}
+
+extern "C" npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                        const int32_t *site_keys, const npvs_counts *counts, int32_t cap_sites,
+                                        int32_t dtype, void *X, void *stream) {
+  if (!bits || !site_keys || !counts || !X) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: null pointer");
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: cap_sites < 1");
+  int grid = stride_grid((int64_t)cap_sites * d * d, 256, 4096);
+  hipStream_t s = as_stream(stream);
+  switch (dtype) {
+    case NPVS_F32: gather_bits_kernel<float><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (float *)X); break;
+    case NPVS_BF16: gather_bits_kernel<uint16_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint16_t *)X); break;
+    case NPVS_U8: gather_bits_kernel<uint8_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint8_t *)X); break;
+    default: return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: dtype must be NPVS_F32, NPVS_BF16 or NPVS_U8");
+  }
+  return check_hip(hipGetLastError(), "npvs_gather_input");
+}
+
+extern "C" npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row, const uint8_t *occ_bits,
+                                                   int32_t n_grids, const npvs_dims *dims, int32_t d, uint8_t *pvs_bits,
+                                                   float *logits, void *stream) {
+  if (!Y || !block_row || !occ_bits || !pvs_bits)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_deinterleave_threshold: null pointer");
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  int64_t total = 0;
+  for (int b = 0; b < n_grids; ++b) total += (int64_t)dims[b].nz * dims[b].ny * (dims[b].nx / 8);
+  int grid = stride_grid(total, 256, 8192);
+  deinterleave_threshold_kernel<<<grid, 256, 0, as_stream(stream)>>>(B, total, Y, block_row, occ_bits, pvs_bits,
+                                                                      logits);
+  return check_hip(hipGetLastError(), "npvs_deinterleave_threshold");
+}

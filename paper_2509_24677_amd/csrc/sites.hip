@@ -1,0 +1,281 @@
+// Active sites and the submanifold rulebook (Sec. 2.3: sparse tensors store only sites with
+// geometry and the submanifold kernel is centred on active sites only).
+//
+// The site lookup table is direct-indexed: block_row[global key] = row or -1.  On a GPU with
+// 288 GB of HBM a table of 4 bytes per block (512 KB for a 64 x 64 x 32 block grid) is a
+// perfect hash: one load per probe, no collisions, and it stays resident in L2.
+//
+// Rows are numbered by ascending global key through a two-pass compaction (per-workgroup
+// counts, then every workgroup adds the counts of the workgroups before it and scans its own
+// flags), so the numbering is canonical and identical run to run.
+#include "npvs_common.hpp"
+
+namespace npvs {
+
+constexpr int kSitesPerWG = 1024;  // 256 threads x 4 consecutive blocks
+
+// Exclusive scan of one int per thread over a 256-thread workgroup (4 waves of 64).
+__device__ __forceinline__ int block_exclusive_scan(int v, int *total) {
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int pre = 0;
+  for (int i = 0; i < w; ++i) pre += wsum[i];
+  *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  return pre + x - v;
+}
+
+__device__ __forceinline__ int block_sum(int v) {
+  int t;
+  block_exclusive_scan(v, &t);
+  return t;
+}
+
+// 1 iff block gb (global key) has an occupied froxel.
+__device__ __forceinline__ int block_active(const Batch &B, const uint8_t *__restrict__ occ, int32_t gb) {
+  if (gb >= B.total_blocks) return 0;
+  const GridDesc &g = B.g[grid_of_key(B, gb)];
+  const int d = B.d;
+  int32_t l = gb - g.key_off;
+  int bx = l % g.Bx, by = (l / g.Bx) % g.By, bz = l / (g.Bx * g.By);
+  const int64_t row_bytes = g.nx >> 3;
+  const int x0 = bx * d, x1 = x0 + d - 1;
+  const uint8_t *base = occ + g.occ_off;
+  for (int oz = 0; oz < d; ++oz)
+    for (int oy = 0; oy < d; ++oy) {
+      const uint8_t *row = base + ((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * row_bytes;
+      for (int xb = x0 >> 3; xb <= (x1 >> 3); ++xb) {
+        int lo = xb * 8 > x0 ? 0 : x0 - xb * 8;
+        int hi = xb * 8 + 7 < x1 ? 7 : x1 - xb * 8;
+        unsigned mask = ((2u << hi) - 1u) & ~((1u << lo) - 1u);
+        if (row[xb] & mask) return 1;
+      }
+    }
+  return 0;
+}
+
+__global__ __launch_bounds__(256) void sites_count_kernel(Batch B, const uint8_t *__restrict__ occ,
+                                                           int32_t *__restrict__ wg_counts) {
+  int32_t gb0 = blockIdx.x * kSitesPerWG + threadIdx.x * 4;
+  int c = 0;
+  for (int i = 0; i < 4; ++i) c += block_active(B, occ, gb0 + i);
+  int t = block_sum(c);
+  if (threadIdx.x == 0) wg_counts[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void sites_write_kernel(Batch B, const uint8_t *__restrict__ occ,
+                                                           const int32_t *__restrict__ wg_counts, int32_t cap,
+                                                           npvs_counts *__restrict__ counts,
+                                                           int32_t *__restrict__ site_keys,
+                                                           int32_t *__restrict__ block_row,
+                                                           int32_t *__restrict__ grid_rows) {
+  // rows before this workgroup
+  int part = 0;
+  for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) part += wg_counts[i];
+  int prefix = block_sum(part);
+  int32_t gb0 = blockIdx.x * kSitesPerWG + threadIdx.x * 4;
+  int f[4], c = 0;
+  for (int i = 0; i < 4; ++i) {
+    f[i] = block_active(B, occ, gb0 + i);
+    c += f[i];
+  }
+  int wg_total;
+  int pos = prefix + block_exclusive_scan(c, &wg_total);
+  for (int i = 0; i < 4; ++i) {
+    int32_t gb = gb0 + i;
+    if (gb >= B.total_blocks) break;
+    int b = grid_of_key(B, gb);
+    if (gb == B.g[b].key_off) grid_rows[b] = pos < cap ? pos : cap;
+    if (f[i] && pos < cap) {
+      site_keys[pos] = gb;
+      block_row[gb] = pos;
+    } else {
+      block_row[gb] = -1;
+    }
+    pos += f[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    int total = prefix + wg_total;
+    int stored = total < cap ? total : cap;
+    counts->n_sites = stored;
+    counts->n_sites_needed = total;
+    counts->n_pairs = 0;
+    counts->reserved = 0;
+    grid_rows[B.n] = stored;
+  }
+}
+
+// Neighbour of row r through offset k, or -1.
+__device__ __forceinline__ int32_t neighbor_row(const Batch &B, const int32_t *__restrict__ site_keys,
+                                                const int32_t *__restrict__ block_row, int32_t r, int k) {
+  int32_t key = site_keys[r];
+  const GridDesc &g = B.g[grid_of_key(B, key)];
+  int32_t l = key - g.key_off;
+  int bx = l % g.Bx + (k % 3 - 1);
+  int by = (l / g.Bx) % g.By + ((k / 3) % 3 - 1);
+  int bz = l / (g.Bx * g.By) + (k / 9 - 1);
+  if (bx < 0 || by < 0 || bz < 0 || bx >= g.Bx || by >= g.By || bz >= g.Bz) return -1;
+  return block_row[g.key_off + (bz * g.By + by) * g.Bx + bx];
+}
+
+constexpr int kRowsPerChunk = 1024;
+
+// grid (chunks, 27): neighbour map for offset k = blockIdx.y, and per-chunk pair counts.
+__global__ __launch_bounds__(256) void rulebook_nbr_kernel(Batch B, const int32_t *__restrict__ site_keys,
+                                                            const int32_t *__restrict__ block_row,
+                                                            const npvs_counts *__restrict__ counts, int32_t cap,
+                                                            int32_t *__restrict__ nbr,
+                                                            int32_t *__restrict__ chunk_counts, int32_t n_chunks) {
+  const int k = blockIdx.y;
+  const int32_t n = counts->n_sites;
+  const int used_chunks = (n + kRowsPerChunk - 1) / kRowsPerChunk;
+  for (int ch = blockIdx.x; ch < used_chunks; ch += gridDim.x) {
+    int c = 0;
+    for (int i = 0; i < 4; ++i) {
+      int32_t r = ch * kRowsPerChunk + i * 256 + threadIdx.x;
+      if (r < n) {
+        int32_t v = neighbor_row(B, site_keys, block_row, r, k);
+        nbr[(int64_t)k * cap + r] = v;
+        c += v >= 0;
+      }
+    }
+    if (chunk_counts) {
+      int t = block_sum(c);
+      if (threadIdx.x == 0) chunk_counts[k * n_chunks + ch] = t;
+    }
+  }
+}
+
+// One workgroup: exclusive scan of the per-(offset, chunk) counts in offset-major order.
+__global__ __launch_bounds__(256) void rulebook_scan_kernel(const npvs_counts *__restrict__ counts_in,
+                                                             npvs_counts *__restrict__ counts,
+                                                             const int32_t *__restrict__ chunk_counts,
+                                                             int32_t *__restrict__ chunk_off, int32_t n_chunks,
+                                                             int32_t *__restrict__ rb_off) {
+  const int32_t n = counts_in->n_sites;
+  const int used = (n + kRowsPerChunk - 1) / kRowsPerChunk;
+  const int total_items = 27 * used;
+  int running = 0;
+  for (int base = 0; base < total_items; base += 256) {
+    int i = base + threadIdx.x;
+    int k = used ? i / used : 0, ch = used ? i % used : 0;
+    int v = i < total_items ? chunk_counts[k * n_chunks + ch] : 0;
+    int tot;
+    int ex = block_exclusive_scan(v, &tot);
+    if (i < total_items) {
+      chunk_off[k * n_chunks + ch] = running + ex;
+      if (ch == 0) rb_off[k] = running + ex;
+    }
+    running += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (used == 0)
+      for (int k = 0; k < 27; ++k) rb_off[k] = 0;
+    rb_off[27] = running;
+    counts->n_pairs = running;
+  }
+}
+
+__global__ __launch_bounds__(256) void rulebook_pairs_kernel(const npvs_counts *__restrict__ counts, int32_t cap,
+                                                              const int32_t *__restrict__ nbr,
+                                                              const int32_t *__restrict__ chunk_off, int32_t n_chunks,
+                                                              int32_t *__restrict__ pairs) {
+  const int k = blockIdx.y;
+  const int32_t n = counts->n_sites;
+  const int used_chunks = (n + kRowsPerChunk - 1) / kRowsPerChunk;
+  for (int ch = blockIdx.x; ch < used_chunks; ch += gridDim.x) {
+    // 4 consecutive rows per thread keep the output ascending in row order
+    int32_t r0 = ch * kRowsPerChunk + threadIdx.x * 4;
+    int32_t v[4];
+    int c = 0;
+    for (int i = 0; i < 4; ++i) {
+      v[i] = r0 + i < n ? nbr[(int64_t)k * cap + r0 + i] : -1;
+      c += v[i] >= 0;
+    }
+    int tot;
+    int pos = chunk_off[k * n_chunks + ch] + block_exclusive_scan(c, &tot);
+    for (int i = 0; i < 4; ++i)
+      if (v[i] >= 0) {
+        pairs[2 * (int64_t)pos] = v[i];
+        pairs[2 * (int64_t)pos + 1] = r0 + i;
+        ++pos;
+      }
+    __syncthreads();
+  }
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static void rb_ws_layout(const Batch &B, int32_t cap, size_t *o_wg, size_t *o_cc, size_t *o_co, size_t *bytes,
+                         int *n_wg, int *n_chunks) {
+  *n_wg = (B.total_blocks + kSitesPerWG - 1) / kSitesPerWG;
+  *n_chunks = (cap + kRowsPerChunk - 1) / kRowsPerChunk;
+  size_t o = 0;
+  *o_wg = o;
+  o += align256(sizeof(int32_t) * (size_t)(*n_wg > 0 ? *n_wg : 1));
+  *o_cc = o;
+  o += align256(sizeof(int32_t) * 27 * (size_t)(*n_chunks > 0 ? *n_chunks : 1));
+  *o_co = o;
+  o += align256(sizeof(int32_t) * 27 * (size_t)(*n_chunks > 0 ? *n_chunks : 1));
+  *bytes = o;
+}
+
+}  // namespace npvs
+
+using namespace npvs;
+
+extern "C" npvs_status npvs_rulebook_workspace_size(int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                                    int32_t cap_sites, size_t *bytes) {
+  if (!bytes) return fail(NPVS_ERR_INVALID_ARG, "npvs_rulebook_workspace_size: null pointer");
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_rulebook_workspace_size: cap_sites < 1");
+  size_t a, b, c;
+  int nw, nc;
+  rb_ws_layout(B, cap_sites, &a, &b, &c, bytes, &nw, &nc);
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                           int32_t cap_sites, npvs_counts *counts, int32_t *site_keys,
+                                           int32_t *block_row, int32_t *grid_rows, int32_t *nbr, int32_t *rb_off,
+                                           int32_t *rb_pairs, void *ws, size_t ws_bytes, void *stream) {
+  if (!occ_bits || !counts || !site_keys || !block_row || !grid_rows || !nbr || !ws)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: null pointer");
+  if ((rb_off == nullptr) != (rb_pairs == nullptr))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: give both rb_off and rb_pairs or neither");
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: cap_sites < 1");
+  if ((int64_t)cap_sites * 27 > INT32_MAX) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: cap_sites too large");
+  size_t o_wg, o_cc, o_co, need;
+  int n_wg, n_chunks;
+  rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &o_co, &need, &n_wg, &n_chunks);
+  if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: workspace too small");
+  char *w = static_cast<char *>(ws);
+  int32_t *wg_counts = reinterpret_cast<int32_t *>(w + o_wg);
+  int32_t *chunk_counts = reinterpret_cast<int32_t *>(w + o_cc);
+  int32_t *chunk_off = reinterpret_cast<int32_t *>(w + o_co);
+  hipStream_t s = as_stream(stream);
+  sites_count_kernel<<<n_wg, 256, 0, s>>>(B, occ_bits, wg_counts);
+  sites_write_kernel<<<n_wg, 256, 0, s>>>(B, occ_bits, wg_counts, cap_sites, counts, site_keys, block_row, grid_rows);
+  dim3 g(stride_grid(cap_sites, kRowsPerChunk, 512), 27);
+  rulebook_nbr_kernel<<<g, 256, 0, s>>>(B, site_keys, block_row, counts, cap_sites, nbr,
+                                        rb_off ? chunk_counts : nullptr, n_chunks);
+  if (rb_off) {
+    rulebook_scan_kernel<<<1, 256, 0, s>>>(counts, counts, chunk_counts, chunk_off, n_chunks, rb_off);
+    rulebook_pairs_kernel<<<g, 256, 0, s>>>(counts, cap_sites, nbr, chunk_off, n_chunks, rb_pairs);
+  }
+  return check_hip(hipGetLastError(), "npvs_build_rulebook");
+}

@@ -1,0 +1,172 @@
+// Training loss over the froxels of each grid's active blocks and Adam.
+//   Sec. 3.3: repulsive visibility loss L_rv = L_attr + L_rep with L_rep = FP/GTP; the
+//   attraction term is read as 1 - TP/GTP = FN/GTP (printed literally it would reward missed
+//   geometry); combined as L = lambda * BCE + (1 - lambda) * L_rv with BCE in place of Dice.
+//   Soft counts use p = sigmoid(l): TP = sum y p, FN = sum y (1-p), FP = sum (1-y) p, GTP = sum y.
+// Three launches: per-(grid, slice) compensated partial sums, one workgroup that finishes the
+// sums in a fixed order and writes the statistics and gradient coefficients, and the
+// elementwise gradient dL/dl = a_b (p - y) + c_b p (1 - p)(1 - 2y).
+#include <cmath>
+
+#include "npvs_common.hpp"
+
+namespace npvs {
+
+struct Comp {
+  float s, c;
+  __device__ __forceinline__ void add(float y) {
+    float t = s + y;
+    c += (__builtin_fabsf(s) >= __builtin_fabsf(y)) ? (s - t) + y : (y - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ void merge(const Comp &o) {
+    add(o.s);
+    c += o.c;
+  }
+};
+
+constexpr int kLossSlices = 64;
+constexpr int kLossQ = 5;  // BCE sum, TP, FN, FP, GTP
+
+__device__ __forceinline__ float sigmoidf_(float l) { return 1.0f / (1.0f + expf(-l)); }
+
+// grid (kLossSlices, n_grids), 256 threads
+__global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restrict__ logits,
+                                                            const uint8_t *__restrict__ labels, int C,
+                                                            const int32_t *__restrict__ grid_rows,
+                                                            float *__restrict__ part) {
+  __shared__ Comp red[kLossQ][256];
+  const int b = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
+  const int64_t e0 = (int64_t)grid_rows[b] * C, e1 = (int64_t)grid_rows[b + 1] * C;
+  const int64_t m = e1 - e0;
+  const int64_t a0 = e0 + m * s / kLossSlices, a1 = e0 + m * (s + 1) / kLossSlices;
+  Comp q[kLossQ];
+#pragma unroll
+  for (int i = 0; i < kLossQ; ++i) q[i] = Comp{0.0f, 0.0f};
+  for (int64_t e = a0 + tid; e < a1; e += 256) {
+    const float l = logits[e];
+    const float y = labels[e] ? 1.0f : 0.0f;
+    const float p = sigmoidf_(l);
+    const float sp = fmaxf(l, 0.0f) + log1pf(expf(-__builtin_fabsf(l)));
+    q[0].add(sp - y * l);
+    q[1].add(y * p);
+    q[2].add(y * (1.0f - p));
+    q[3].add((1.0f - y) * p);
+    q[4].add(y);
+  }
+#pragma unroll
+  for (int i = 0; i < kLossQ; ++i) red[i][tid] = q[i];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {  // fixed-shape tree
+    if (tid < w)
+#pragma unroll
+      for (int i = 0; i < kLossQ; ++i) red[i][tid].merge(red[i][tid + w]);
+    __syncthreads();
+  }
+  if (tid < kLossQ) part[((int64_t)b * kLossSlices + s) * kLossQ + tid] = red[tid][0].s + red[tid][0].c;
+}
+
+// One workgroup; thread b finishes grid b.  coef[b] = {a_b, c_b}.
+__global__ void loss_final_kernel(const float *__restrict__ part, const int32_t *__restrict__ grid_rows, int n_grids,
+                                  int C, float lambda, float *__restrict__ stats, float *__restrict__ coef) {
+  __shared__ float st[NPVS_MAX_GRIDS][8];
+  const int b = threadIdx.x;
+  if (b < n_grids) {
+    Comp q[kLossQ];
+    for (int i = 0; i < kLossQ; ++i) q[i] = Comp{0.0f, 0.0f};
+    for (int s = 0; s < kLossSlices; ++s)
+      for (int i = 0; i < kLossQ; ++i) q[i].add(part[((int64_t)b * kLossSlices + s) * kLossQ + i]);
+    const float m = (float)((int64_t)(grid_rows[b + 1] - grid_rows[b]) * C);
+    const float bce_sum = q[0].s + q[0].c, tp = q[1].s + q[1].c, fn = q[2].s + q[2].c, fp = q[3].s + q[3].c,
+                gtp = q[4].s + q[4].c;
+    const float g = gtp > 1.0f ? gtp : 1.0f;
+    const float bce = m > 0.0f ? bce_sum / m : 0.0f;
+    const float lrv = fn / g + fp / g;
+    float v[8] = {lambda * bce + (1.0f - lambda) * lrv, bce, lrv, tp, fn, fp, gtp, m};
+    for (int i = 0; i < 8; ++i) {
+      st[b][i] = v[i];
+      stats[b * 8 + i] = v[i];
+    }
+    coef[2 * b] = m > 0.0f ? lambda / (m * n_grids) : 0.0f;
+    coef[2 * b + 1] = (1.0f - lambda) / (g * n_grids);
+  }
+  __syncthreads();
+  if (b < 8) {
+    float t = 0.0f;
+    for (int i = 0; i < n_grids; ++i) t += st[i][b];
+    stats[n_grids * 8 + b] = t / n_grids;
+  }
+}
+
+__global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict__ logits,
+                                                         const uint8_t *__restrict__ labels, int C,
+                                                         const int32_t *__restrict__ grid_rows, int n_grids,
+                                                         const npvs_counts *__restrict__ counts,
+                                                         const float *__restrict__ coef, float *__restrict__ dl) {
+  const int64_t total = (int64_t)counts->n_sites * C;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = (int32_t)(e / C);
+    int b = 0;
+    while (b + 1 < n_grids && r >= grid_rows[b + 1]) ++b;
+    const float l = logits[e];
+    const float y = labels[e] ? 1.0f : 0.0f;
+    const float p = sigmoidf_(l);
+    dl[e] = coef[2 * b] * (p - y) + coef[2 * b + 1] * p * (1.0f - p) * (1.0f - 2.0f * y);
+  }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ g,
+                                                    float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
+                                                    float b1, float b2, float eps, float wd, float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i] + wd * p[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+}  // namespace npvs
+
+using namespace npvs;
+
+extern "C" npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes) {
+  if (!bytes || n_grids < 1 || n_grids > NPVS_MAX_GRIDS)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_loss_workspace_size: bad arguments");
+  *bytes = sizeof(float) * ((size_t)n_grids * kLossSlices * kLossQ + 2 * (size_t)n_grids) + 256;
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                                int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
+                                float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream) {
+  if (!logits || !labels || !grid_rows || !counts || !stats || !ws)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: null pointer");
+  if (C < 1 || n_grids < 1 || n_grids > NPVS_MAX_GRIDS || cap_sites < 1)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: bad sizes");
+  size_t need;
+  npvs_loss_workspace_size(n_grids, &need);
+  if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: workspace too small");
+  float *part = static_cast<float *>(ws);
+  float *coef = part + (size_t)n_grids * kLossSlices * kLossQ;
+  hipStream_t s = as_stream(stream);
+  loss_partial_kernel<<<dim3(kLossSlices, n_grids), 256, 0, s>>>(logits, labels, C, grid_rows, part);
+  loss_final_kernel<<<1, 64, 0, s>>>(part, grid_rows, n_grids, C, lambda, stats, coef);
+  if (dlogits)
+    loss_grad_kernel<<<stride_grid((int64_t)cap_sites * C, 256, 4096), 256, 0, s>>>(logits, labels, C, grid_rows,
+                                                                                   n_grids, counts, coef, dlogits);
+  return check_hip(hipGetLastError(), "npvs_loss");
+}
+
+extern "C" npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr,
+                                float beta1, float beta2, float eps, float weight_decay, void *stream) {
+  if (!p || !g || !m || !v || n < 0 || t < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: bad arguments");
+  if (n == 0) return NPVS_OK;
+  const float c1 = 1.0f - (float)std::pow((double)beta1, (double)t);
+  const float c2 = 1.0f - (float)std::pow((double)beta2, (double)t);
+  adam_kernel<<<stride_grid(n, 256, 2048), 256, 0, as_stream(stream)>>>(p, g, m, v, n, lr, beta1, beta2, eps,
+                                                                         weight_decay, c1, c2);
+  return check_hip(hipGetLastError(), "npvs_adam");
+}

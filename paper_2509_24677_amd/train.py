@@ -1,0 +1,138 @@
+"""Forward/backward driver of the visibility network over the C ABI.
+
+* ``Network``: float32 master weights, their packed forms for the kernels (re-packed after every
+  optimizer step), the forward stack (ReLU after every layer but the last) with optional
+  activation checkpointing: only every second layer input is kept and the others are recomputed
+  in the backward.
+* ``Trainer``: one training step on a batch of grids: froxelize, rulebook, forward, de-interleave
+  + threshold, BCE + repulsive visibility loss (Sec. 3.3), hand-written backward and Adam.  Every
+  step runs entirely on one stream without host synchronization, so it can be captured in a graph.
+* ``SubMConvFn``: the same layer as a ``torch.autograd.Function`` for callers that want autograd.
+
+The loss weight lambda = 0.99, the learning rate 1e-3 and the decay 1e-10 (read as weight decay)
+follow Sec. 4.2.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam, build_rulebook, deinterleave_threshold, froxelize,
+               gather_input, loss, pack_weights, sparse_conv_bwd, sparse_conv_fwd)
+
+
+class Network:
+    def __init__(self, layers, d: int, dtype: int = NPVS_BF16, device="cuda"):
+        """layers: list of (W float32 [27][cin][cout], b float32 [cout]) as numpy or torch."""
+        self.d = d
+        self.dtype = dtype
+        self.W = [torch.as_tensor(W, dtype=torch.float32).to(device).contiguous() for W, _ in layers]
+        self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for _, b in layers]
+        self.channels = [self.W[0].shape[1]] + [w.shape[2] for w in self.W]
+        self.Wp = [None] * len(self.W)
+        self.Wt = [None] * len(self.W)
+        self.repack()
+
+    @property
+    def n_layers(self):
+        return len(self.W)
+
+    def repack(self):
+        for i, W in enumerate(self.W):
+            if self.Wp[i] is None:
+                self.Wp[i] = pack_weights(W, self.dtype)
+                self.Wt[i] = pack_weights(W, self.dtype, flip_transpose=True)
+            else:  # in place, so captured graphs keep reading the current weights
+                self.Wp[i].copy_(pack_weights(W, self.dtype))
+                self.Wt[i].copy_(pack_weights(W, self.dtype, flip_transpose=True))
+
+    def layer(self, i: int, X: torch.Tensor, rb: Rulebook) -> torch.Tensor:
+        last = i == self.n_layers - 1
+        return sparse_conv_fwd(X, self.Wp[i], self.b[i], self.channels[i], self.channels[i + 1], rb, self.dtype,
+                               relu=not last, out_f32=last)
+
+    def forward(self, X0: torch.Tensor, rb: Rulebook, checkpoint: bool = False):
+        """Returns (logits float32 [cap][d^3], saved inputs: dict layer -> input tensor)."""
+        saved = {}
+        X = X0
+        for i in range(self.n_layers):
+            if not checkpoint or i % 2 == 0:
+                saved[i] = X
+            X = self.layer(i, X, rb)
+        return X, saved
+
+    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook):
+        """Hand-written backward through the stack; recomputes the layer inputs that were not
+        saved.  Returns [(dW, db)] per layer."""
+        grads = [None] * self.n_layers
+        outputs = {self.n_layers - 1: logits}
+        dY = dlogits
+        for i in range(self.n_layers - 1, -1, -1):
+            X = saved.get(i)
+            if X is None:  # recompute this layer's input from the previous saved one
+                X = self.layer(i - 1, saved[i - 1], rb)
+            Y = outputs.get(i)
+            if Y is None:
+                Y = self.layer(i, X, rb)
+            dX, dW, db = sparse_conv_bwd(X, self.Wt[i], self.channels[i], self.channels[i + 1], Y, dY, rb,
+                                         self.dtype, relu=i < self.n_layers - 1, want_dx=i > 0)
+            grads[i] = (dW, db)
+            if i > 0:
+                outputs[i - 1] = X
+            dY = dX
+        return grads
+
+
+class Trainer:
+    """One training step per call; all state lives on the device."""
+
+    def __init__(self, net: Network, dims, n_tris, lam: float = 0.99, lr: float = 1e-3, weight_decay: float = 1e-10,
+                 checkpoint: bool = True):
+        self.net = net
+        self.dims = [tuple(g) for g in dims]
+        self.n_tris = list(n_tris)
+        self.lam, self.lr, self.wd = lam, lr, weight_decay
+        self.checkpoint = checkpoint
+        self.m = [torch.zeros_like(p) for p in net.W + net.b]
+        self.v = [torch.zeros_like(p) for p in net.W + net.b]
+        self.t = torch.zeros((), dtype=torch.int64)  # host-side step count
+        self.step_count = 0
+
+    def step(self, tris: torch.Tensor, label_bits: torch.Tensor):
+        net = self.net
+        occ = froxelize(tris, self.n_tris, self.dims)
+        rb = build_rulebook(occ, self.dims, net.d, csr=True)
+        X0 = gather_input(occ, rb, net.dtype)
+        logits, saved = net.forward(X0, rb, checkpoint=self.checkpoint)
+        pvs, _ = deinterleave_threshold(logits, rb, occ)
+        labels = gather_input(label_bits, rb, NPVS_U8)
+        stats, dl = loss(logits, labels, rb, self.lam)
+        grads = net.backward(saved, logits, dl, rb)
+        self.step_count += 1
+        params = net.W + net.b
+        flat = [g for g, _ in grads] + [b for _, b in grads]
+        for p, g, m, v in zip(params, flat, self.m, self.v):
+            adam(p, g, m, v, self.step_count, lr=self.lr, weight_decay=self.wd)
+        net.repack()
+        return stats, pvs
+
+
+class SubMConvFn(torch.autograd.Function):
+    """Y = act(b + sum_k gather_k(X) W_k) over a rulebook, differentiable in X, W and b."""
+
+    @staticmethod
+    def forward(ctx, X, W, b, rb: Rulebook, dtype: int, relu: bool, out_f32: bool):
+        Wp = pack_weights(W.detach(), dtype)
+        Y = sparse_conv_fwd(X.detach(), Wp, b.detach(), W.shape[1], W.shape[2], rb, dtype, relu, out_f32)
+        ctx.save_for_backward(X, W, Y)
+        ctx.rb, ctx.dtype, ctx.relu = rb, dtype, relu
+        return Y
+
+    @staticmethod
+    def backward(ctx, dY):
+        X, W, Y = ctx.saved_tensors
+        Wt = pack_weights(W.detach(), ctx.dtype, flip_transpose=True)
+        dX, dW, db = sparse_conv_bwd(X.detach(), Wt, W.shape[1], W.shape[2], Y, dY.float().contiguous(), ctx.rb,
+                                     ctx.dtype, ctx.relu, want_dx=ctx.needs_input_grad[0])
+        if dX is not None and X.dtype != torch.float32:
+            dX = dX.to(X.dtype)
+        return dX, dW, db, None, None, None, None

@@ -1,0 +1,74 @@
+"""The C ABI library loads on any host and exports every function include/neuralpvs.h declares;
+host-side argument checks answer without a GPU (nothing is enqueued on these paths)."""
+import ctypes
+
+import pytest
+
+from paper_2509_24677_amd import _lib as L
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.get()
+
+
+def test_exports_every_declared_function(lib):
+    names = L.header_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(L.SIGNATURES) == names  # the binding covers exactly the header
+
+
+def test_version_and_sizes(lib):
+    assert lib.npvs_version().decode().startswith("neuralpvs-gfx950")
+    tb, tby = ctypes.c_int64(), ctypes.c_int64()
+    L.call("npvs_batch_sizes", 2, L.dims_array([(256, 256, 128), (64, 64, 64)]), 4, ctypes.byref(tb), ctypes.byref(tby))
+    assert tb.value == 64 * 64 * 32 + 16 ** 3
+    assert tby.value == 128 * 256 * 32 + 64 * 64 * 8
+    assert lib.npvs_packed_weight_bytes(64, 64, L.NPVS_F32) == 27 * 64 * 64 * 4
+    assert lib.npvs_packed_weight_bytes(64, 64, L.NPVS_BF16) == 27 * 4 * 2 * 1024
+    n = ctypes.c_size_t()
+    L.call("npvs_froxelize_workspace_size", 1, L.dims_array([(256, 256, 128)]), L.i64_array([50000]), ctypes.byref(n))
+    assert n.value > 50000 * 48
+
+
+@pytest.mark.parametrize("dims,d,msg", [
+    ([(250, 256, 128)], 4, "multiple of 8"),
+    ([(256, 256, 126)], 4, "multiples of d"),
+    ([(2048, 256, 128)], 4, "1024"),
+    ([(256, 256, 128)], 3, "power of two"),
+])
+def test_bad_dims_rejected(lib, dims, d, msg):
+    tb, tby = ctypes.c_int64(), ctypes.c_int64()
+    st = lib.npvs_batch_sizes(len(dims), L.dims_array(dims), d, ctypes.byref(tb), ctypes.byref(tby))
+    assert st == L.NPVS_ERR_INVALID_ARG
+    assert msg in lib.npvs_last_error().decode()
+
+
+def test_too_many_grids_and_null_pointers(lib):
+    tb, tby = ctypes.c_int64(), ctypes.c_int64()
+    dims = L.dims_array([(64, 64, 64)] * 33)
+    assert lib.npvs_batch_sizes(33, dims, 4, ctypes.byref(tb), ctypes.byref(tby)) == L.NPVS_ERR_INVALID_ARG
+    one = L.dims_array([(64, 64, 64)])
+    st = lib.npvs_froxelize(None, L.i64_array([1]), 1, one, None, None, 0, None)
+    assert st == L.NPVS_ERR_INVALID_ARG
+    st = lib.npvs_sparse_conv_fwd(None, 64, None, None, 64, None, None, 10, 0, 1, 0, None, None)
+    assert st == L.NPVS_ERR_INVALID_ARG
+    st = lib.npvs_build_rulebook(ctypes.c_void_p(16), 1, one, 4, 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                 ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                 None, ctypes.c_void_p(16), 1 << 20, None)
+    assert st == L.NPVS_ERR_INVALID_ARG and "rb_off and rb_pairs" in lib.npvs_last_error().decode()
+
+
+def test_workspace_too_small_is_rejected(lib):
+    one = L.dims_array([(64, 64, 64)])
+    p = ctypes.c_void_p(256)
+    st = lib.npvs_froxelize(p, L.i64_array([10]), 1, one, p, p, 16, None)
+    assert st == L.NPVS_ERR_INVALID_ARG and "workspace" in lib.npvs_last_error().decode()
+
+
+def test_unsupported_bf16_shape_reported(lib):
+    p = ctypes.c_void_p(256)
+    st = lib.npvs_sparse_conv_fwd(p, 12, p, None, 64, p, p, 10, L.NPVS_BF16, 1, 0, ctypes.c_void_p(512), None)
+    assert st == L.NPVS_ERR_UNSUPPORTED

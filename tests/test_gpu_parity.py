@@ -1,0 +1,335 @@
+"""GPU parity of the forward path against the CPU oracle, through the C ABI.
+
+Integer stages (froxelize, sites, rulebook, interleave) must be bit-exact; float stages must sit
+within the float32 accumulation bound of each layer and, for the whole network, 1e-5 max-abs on
+the logits against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_24677_amd as npvs
+import synth
+from gpu_util import DEV, bf16_round, conv_tolerance, oracle_batch, to_np, upload_tris
+
+pytestmark = pytest.mark.gpu
+
+
+def _frox_and_rb(tri_list, dims, d, csr=True):
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    rb = npvs.build_rulebook(occ, dims, d, csr=csr)
+    return occ, rb
+
+
+# ------------------------------------------------------------------------------- froxelize
+@pytest.mark.parametrize("name", ["tiny32", "city256"])
+def test_froxelize_bit_exact_configs(name):
+    cfg = synth.config(name)
+    t = synth.scene_for(cfg)
+    print(f"froxelize {name} T={len(t)}", flush=True)
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    want, _ = oracle.froxelize(t, cfg.grids[0])
+    np.testing.assert_array_equal(to_np(occ), want.reshape(-1))
+
+
+def _adversarial(rng, n, dims):
+    out = []
+    hi = np.array(dims, np.float64)
+    for i in range(n):
+        kind = i % 4
+        if kind == 0:
+            v = rng.uniform(-2, hi + 2, size=(3, 3))
+        elif kind == 1:  # integer lattice: vertices/edges/faces on froxel boundaries
+            v = rng.integers(0, np.array(dims) + 1, size=(3, 3)).astype(np.float64)
+        elif kind == 2:  # small triangles near corners
+            c = rng.integers(0, np.array(dims), size=3).astype(np.float64)
+            v = c + rng.choice([-0.5, 0.0, 0.5, 1.0 / 256, -1.0 / 512], size=(3, 3))
+        else:  # long slivers across many tiles
+            a = rng.uniform(0, hi, size=3)
+            b = rng.uniform(0, hi, size=3)
+            v = np.stack([a, b, b + rng.uniform(-0.01, 0.01, 3)])
+        if i % 9 == 4:
+            v[2] = v[1]  # degenerate
+        out.append(v)
+    return np.asarray(out, np.float32)
+
+
+def test_froxelize_adversarial_and_batched():
+    rng = np.random.default_rng(21)
+    dims = [(136, 24, 40), (32, 32, 32), (64, 8, 16)]
+    tri_list = [_adversarial(rng, 700, g) for g in dims]
+    tri_list[1] = np.concatenate([tri_list[1], np.full((2, 3, 3), np.nan, np.float32),
+                                  np.full((1, 3, 3), 5000.0, np.float32)])
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    want = np.concatenate([oracle.froxelize(t, g)[0].reshape(-1) for t, g in zip(tri_list, dims)])
+    np.testing.assert_array_equal(to_np(occ), want)
+
+
+def test_froxelize_tile_overflow_falls_back_to_full_scan():
+    # more than 1024 triangles inside one 128x8x8 tile
+    rng = np.random.default_rng(3)
+    c = rng.uniform(1, 7, size=(1500, 1, 3)) * np.array([10.0, 1, 1])
+    t = (c + rng.uniform(-0.7, 0.7, size=(1500, 3, 3))).astype(np.float32)
+    dims = [(128, 16, 16)]
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, dims)
+    np.testing.assert_array_equal(to_np(occ), oracle.froxelize(t, dims[0])[0].reshape(-1))
+
+
+def test_froxelize_empty_and_all_ignored():
+    dims = [(64, 16, 16), (32, 32, 32)]
+    tri_list = [np.zeros((0, 3, 3), np.float32), np.full((3, 3, 3), np.inf, np.float32)]
+    tris, counts = upload_tris(tri_list)
+    occ = torch.full((sum(g[0] * g[1] * g[2] // 8 for g in dims),), 0xAB, dtype=torch.uint8, device=DEV)
+    npvs.froxelize(tris, counts, dims, occ=occ)
+    assert not to_np(occ).any()
+
+
+# ------------------------------------------------------------------------------- sites / rulebook
+@pytest.mark.parametrize("d", [2, 4, 8])
+def test_rulebook_bit_exact_batched(d):
+    dims = [(64, 64, 64), (32, 32, 32), (128, 64, 32)]
+    tri_list = [synth.box_scene(10 + i, g, 25, 2, 12) for i, g in enumerate(dims)]
+    occ, rb = _frox_and_rb(tri_list, dims, d)
+    ref = oracle_batch(tri_list, dims, d)
+    c = rb.host_counts()
+    assert c["n_sites"] == c["n_sites_needed"] == ref["n"]
+    assert c["n_pairs"] == len(ref["pairs"])
+    n = ref["n"]
+    np.testing.assert_array_equal(to_np(rb.site_keys)[:n], ref["keys"])
+    br = np.full(ref["total_blocks"], -1, np.int32)
+    br[ref["keys"]] = np.arange(n)
+    np.testing.assert_array_equal(to_np(rb.block_row), br)
+    np.testing.assert_array_equal(to_np(rb.grid_rows), ref["grid_rows"])
+    np.testing.assert_array_equal(to_np(rb.nbr)[:, :n], ref["nbr"])
+    np.testing.assert_array_equal(to_np(rb.rb_off), ref["rb_off"])
+    np.testing.assert_array_equal(to_np(rb.rb_pairs)[:len(ref["pairs"])], ref["pairs"])
+
+
+def test_rulebook_city_and_capacity_overflow():
+    cfg = synth.config("city256")
+    t = synth.scene_for(cfg)
+    occ, rb = _frox_and_rb([t], cfg.grids, 4)
+    ref = oracle_batch([t], cfg.grids, 4)
+    n = ref["n"]
+    assert rb.host_counts()["n_sites"] == n
+    np.testing.assert_array_equal(to_np(rb.site_keys)[:n], ref["keys"])
+    np.testing.assert_array_equal(to_np(rb.nbr)[:, :n], ref["nbr"])
+    np.testing.assert_array_equal(to_np(rb.rb_pairs)[:len(ref["pairs"])], ref["pairs"])
+    # capacity below the site count: rows are dropped, the count reports what was needed
+    small = npvs.build_rulebook(occ, cfg.grids, 4, cap=n // 2)
+    c = small.host_counts()
+    assert c["n_sites"] == n // 2 and c["n_sites_needed"] == n
+    np.testing.assert_array_equal(to_np(small.site_keys), ref["keys"][:n // 2])
+
+
+def test_empty_grid_has_no_sites():
+    dims = [(32, 32, 32)]
+    occ, rb = _frox_and_rb([np.zeros((0, 3, 3), np.float32)], dims, 2)
+    c = rb.host_counts()
+    assert c["n_sites"] == 0 and c["n_pairs"] == 0
+    assert not to_np(rb.rb_off).any()
+    assert (to_np(rb.block_row) == -1).all()
+
+
+# ------------------------------------------------------------------------------- interleave
+@pytest.mark.parametrize("d", [1, 2, 4, 8])
+@pytest.mark.parametrize("dtype", [torch.uint8, torch.float16, torch.float32, torch.float64])
+def test_dense_interleave_bit_exact(d, dtype):
+    dims = (64, 32, 16)
+    g = torch.Generator().manual_seed(d)
+    a = (torch.rand((dims[2], dims[1], dims[0]), generator=g) * 200).to(dtype)
+    out = npvs.interleave(a.to(DEV), d)
+    np.testing.assert_array_equal(to_np(out), oracle.interleave(a.numpy(), d))
+    back = npvs.deinterleave(out, dims, d)
+    np.testing.assert_array_equal(to_np(back), a.numpy())
+
+
+@pytest.mark.parametrize("dt", [npvs.NPVS_F32, npvs.NPVS_BF16, npvs.NPVS_U8])
+def test_sparse_gather_bit_exact(dt):
+    dims = [(64, 64, 64), (32, 32, 32)]
+    tri_list = [synth.box_scene(40 + i, g, 20, 2, 10) for i, g in enumerate(dims)]
+    occ, rb = _frox_and_rb(tri_list, dims, 4, csr=False)
+    X = npvs.gather_input(occ, rb, dt)
+    ref = oracle_batch(tri_list, dims, 4)
+    np.testing.assert_array_equal(to_np(X)[:ref["n"]], ref["X"])
+
+
+# ------------------------------------------------------------------------------- convolution
+def _conv_case(cin, cout, d=2, seed=0, dims=((32, 32, 32), (64, 32, 32))):
+    dims = [tuple(g) for g in dims]
+    tri_list = [synth.box_scene(seed + i, g, 25, 2, 10) for i, g in enumerate(dims)]
+    occ, rb = _frox_and_rb(tri_list, dims, d, csr=False)
+    ref = oracle_batch(tri_list, dims, d)
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(rb.cap, cin)).astype(np.float32)
+    W = (rng.normal(size=(27, cin, cout)) / np.sqrt(27 * cin)).astype(np.float32)
+    b = rng.normal(size=cout).astype(np.float32)
+    return rb, ref, X, W, b
+
+
+@pytest.mark.parametrize("cin,cout,relu", [(8, 16, True), (16, 8, False), (64, 64, True), (24, 40, False)])
+def test_conv_fwd_f32(cin, cout, relu):
+    rb, ref, X, W, b = _conv_case(cin, cout)
+    n = ref["n"]
+    Wp = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_F32)
+    Y = npvs.sparse_conv_fwd(torch.from_numpy(X).to(DEV), Wp, torch.from_numpy(b).to(DEV), cin, cout, rb,
+                             npvs.NPVS_F32, relu)
+    want = oracle.subm_conv(X[:n], W, b, ref["rb_off"], ref["pairs"], relu)
+    tol = conv_tolerance(X[:n], W, ref["rb_off"], ref["pairs"])
+    err = np.abs(to_np(Y)[:n] - want)
+    assert (err <= tol).all(), err.max()
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 16), (16, 8), (64, 64), (32, 48), (512, 64)])
+@pytest.mark.parametrize("variant_rows", [None])
+def test_conv_fwd_bf16_mfma(cin, cout, variant_rows):
+    d = 8 if cin == 512 else 2
+    rb, ref, X, W, b = _conv_case(cin, cout, d=d, dims=((64, 64, 64), (32, 32, 32)))
+    n = ref["n"]
+    Xb = torch.from_numpy(X).to(DEV).to(torch.bfloat16)
+    Wp = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_BF16)
+    Y = npvs.sparse_conv_fwd(Xb, Wp, torch.from_numpy(b).to(DEV), cin, cout, rb, npvs.NPVS_BF16, True, out_f32=True)
+    Xr, Wr = bf16_round(X[:n]), bf16_round(W)
+    want = oracle.subm_conv(Xr, Wr, b, ref["rb_off"], ref["pairs"], True)
+    tol = conv_tolerance(Xr, Wr, ref["rb_off"], ref["pairs"])
+    err = np.abs(to_np(Y)[:n] - want)
+    assert (err <= tol).all(), err.max()
+    # bf16 output: the float32 result rounded to nearest even
+    Yb = npvs.sparse_conv_fwd(Xb, Wp, torch.from_numpy(b).to(DEV), cin, cout, rb, npvs.NPVS_BF16, True)
+    np.testing.assert_array_equal(to_np(Yb)[:n], to_np(Y[:n].to(torch.bfloat16)))
+
+
+def test_conv_weight_packing_flip_transpose_is_dgrad_weight():
+    rb, ref, X, W, _ = _conv_case(16, 24)
+    n = ref["n"]
+    G = np.random.default_rng(1).normal(size=(rb.cap, 24)).astype(np.float32)
+    Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_F32, flip_transpose=True)
+    dX = npvs.sparse_conv_fwd(torch.from_numpy(G).to(DEV), Wt, None, 24, 16, rb, npvs.NPVS_F32, False)
+    want, _, _ = oracle.subm_conv_bwd(X[:n], W, ref["rb_off"], ref["pairs"], np.ones((n, 24)), G[:n], relu=False)
+    np.testing.assert_allclose(to_np(dX)[:n], want, rtol=0, atol=2e-5)
+
+
+def test_conv_rows_beyond_n_untouched_and_deterministic():
+    rb, ref, X, W, b = _conv_case(64, 64)
+    n = ref["n"]
+    Wp = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_BF16)
+    Xb = torch.from_numpy(X).to(DEV).to(torch.bfloat16)
+    Y1 = torch.full((rb.cap, 64), 7.0, device=DEV)
+    npvs.sparse_conv_fwd(Xb, Wp, None, 64, 64, rb, npvs.NPVS_BF16, False, out_f32=True, out=Y1)
+    Y2 = npvs.sparse_conv_fwd(Xb, Wp, None, 64, 64, rb, npvs.NPVS_BF16, False, out_f32=True)
+    assert (to_np(Y1)[n:] == 7.0).all()
+    np.testing.assert_array_equal(to_np(Y1)[:n], to_np(Y2)[:n])
+
+
+# ------------------------------------------------------------------------------- output
+def test_deinterleave_threshold_exact():
+    dims = [(64, 32, 32), (32, 32, 32)]
+    tri_list = [synth.box_scene(60 + i, g, 20, 2, 10) for i, g in enumerate(dims)]
+    occ, rb = _frox_and_rb(tri_list, dims, 2, csr=False)
+    ref = oracle_batch(tri_list, dims, 2)
+    n = ref["n"]
+    Y = np.random.default_rng(0).normal(size=(rb.cap, 8)).astype(np.float32)
+    Y[:n:7] = 0.0  # exact zeros are visible (tau = 0.5 <=> logit >= 0)
+    pvs, logits = npvs.deinterleave_threshold(torch.from_numpy(Y).to(DEV), rb, occ, want_logits=True)
+    wp, wl = [], []
+    for b, g in enumerate(dims):
+        r0, r1 = ref["grid_rows"][b], ref["grid_rows"][b + 1]
+        keys = ref["keys"][r0:r1] - (0 if b == 0 else (dims[0][0] // 2) * (dims[0][1] // 2) * (dims[0][2] // 2))
+        o = oracle.froxelize(tri_list[b], g)[0]
+        l, p = oracle.deinterleave_threshold(Y[r0:r1], keys, o, g, 2)
+        wp.append(p.reshape(-1))
+        wl.append(l.reshape(-1))
+    np.testing.assert_array_equal(to_np(pvs), np.concatenate(wp))
+    np.testing.assert_array_equal(to_np(logits), np.concatenate(wl).astype(np.float32))
+
+
+# ------------------------------------------------------------------------------- whole network
+def _net_fwd_gpu(occ, rb, layers, dtype):
+    X = npvs.gather_input(occ, rb, dtype)
+    for li, (W, b) in enumerate(layers):
+        last = li == len(layers) - 1
+        Wp = npvs.pack_weights(torch.from_numpy(W).to(DEV), dtype)
+        X = npvs.sparse_conv_fwd(X, Wp, torch.from_numpy(b).to(DEV), W.shape[1], W.shape[2], rb, dtype,
+                                 relu=not last, out_f32=last)
+    return X
+
+
+@pytest.mark.parametrize("name", ["tiny32", "city256"])
+def test_network_f32_logits_within_1e5_of_fp64_oracle(name):
+    cfg = synth.config(name)
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    occ, rb = _frox_and_rb([t], cfg.grids, cfg.d, csr=False)
+    Y = _net_fwd_gpu(occ, rb, layers, npvs.NPVS_F32)
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers)
+    n = len(out["keys"])
+    err = np.abs(to_np(Y)[:n] - out["acts"][-1]).max()
+    print(f"{name}: n_sites={n} max|logit err|={err:.3e}", flush=True)
+    assert err <= 1e-5
+    pvs, _ = npvs.deinterleave_threshold(Y, rb, occ)
+    # bits agree wherever the oracle's logit is farther than the error bound from the threshold
+    got = oracle.unpack(to_np(pvs).reshape(out["pvs"].shape))
+    want = oracle.unpack(out["pvs"])
+    near = np.abs(np.nan_to_num(out["logits"], neginf=-1e9)) <= 1e-5
+    assert ((got == want) | near).all()
+
+
+def test_network_bf16_close_to_fp64_oracle_c2():
+    cfg = synth.config("city256")
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg)
+    occ, rb = _frox_and_rb([t], cfg.grids, cfg.d, csr=False)
+    Yb = _net_fwd_gpu(occ, rb, layers, npvs.NPVS_BF16)
+    Yf = _net_fwd_gpu(occ, rb, layers, npvs.NPVS_F32)
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers)
+    n = len(out["keys"])
+    ref = out["acts"][-1]
+    err_b = np.abs(to_np(Yb)[:n] - ref)
+    print(f"bf16 max|err|={err_b.max():.3e} mean={err_b.mean():.3e} max|logit|={np.abs(ref).max():.3f}", flush=True)
+    # bf16 keeps 8 significant bits: each of the 6 layers adds a relative rounding of at most
+    # 2^-9 to its inputs; with logits of magnitude <= 2.5 a 0.1 max-abs bound leaves a wide margin
+    assert err_b.max() < 0.1
+    pb, _ = npvs.deinterleave_threshold(Yb, rb, occ)
+    pf, _ = npvs.deinterleave_threshold(Yf, rb, occ)
+    vb, vf = oracle.unpack(to_np(pb)), oracle.unpack(to_np(pf))
+    g = oracle.unpack(to_np(occ))
+    flips = ((vb != vf) & (g == 1)).sum() / g.sum()
+    missing = ((vf == 1) & (vb == 0)).sum() / max(vf.sum(), 1)
+    print(f"bf16 vs fp32: flip rate over occupied froxels {flips:.5f}, missing-geometry rate {missing:.5f}", flush=True)
+    assert flips < 0.05
+
+
+# ------------------------------------------------------------------------------- plan / graph
+def test_plan_forward_matches_staged_calls_and_graph_replays():
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    for dtype in (npvs.NPVS_F32, npvs.NPVS_BF16):
+        tris, counts = upload_tris([t])
+        plan = npvs.Plan(cfg.grids, counts, cfg.d, cfg.channels, dtype)
+        for li, (W, b) in enumerate(layers):
+            plan.set_weights(li, torch.from_numpy(W).to(DEV), torch.from_numpy(b).to(DEV))
+        pvs, logits = plan.forward(tris, want_logits=True)
+        occ, rb = _frox_and_rb([t], cfg.grids, cfg.d, csr=False)
+        Y = _net_fwd_gpu(occ, rb, layers, dtype)
+        p2, l2 = npvs.deinterleave_threshold(Y, rb, occ, want_logits=True)
+        np.testing.assert_array_equal(to_np(pvs), to_np(p2))
+        np.testing.assert_array_equal(to_np(logits), to_np(l2))
+        assert plan.counts()["n_sites"] == rb.host_counts()["n_sites"]
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            gp, gl = plan.capture(tris, want_logits=True)
+            for rep in range(3):
+                gp.fill_(0xFF)
+                gl.fill_(123.0)
+                plan.replay()
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(to_np(gp), to_np(pvs))
+                np.testing.assert_array_equal(to_np(gl), to_np(logits))
+                _ = _net_fwd_gpu(occ, rb, layers[:1], dtype)  # eager work between replays
+        torch.cuda.synchronize()

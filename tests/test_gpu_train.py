@@ -1,0 +1,167 @@
+"""GPU parity of the training path (loss, backward, Adam) against the oracle, through the C ABI,
+and the backward against FP64 finite differences of the oracle's forward."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_24677_amd as npvs
+import synth
+from gpu_util import DEV, oracle_batch, to_np, upload_tris
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name="tiny32", layers=None, label_seed=5):
+    cfg = synth.config(name)
+    t = synth.scene_for(cfg)
+    layers = layers or synth.net_layers(cfg, bias_std=0.05)
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
+    lab_bits = torch.from_numpy(to_np(occ) & synth.label_mask_bits(label_seed, (to_np(occ).size,))).to(DEV)
+    return cfg, t, layers, occ, rb, lab_bits
+
+
+def _gpu_forward(occ, rb, layers, dtype):
+    acts = [npvs.gather_input(occ, rb, dtype)]
+    for li, (W, b) in enumerate(layers):
+        last = li == len(layers) - 1
+        Wp = npvs.pack_weights(torch.from_numpy(W).to(DEV), dtype)
+        acts.append(npvs.sparse_conv_fwd(acts[-1], Wp, torch.from_numpy(b).to(DEV), W.shape[1], W.shape[2], rb, dtype,
+                                         relu=not last, out_f32=last))
+    return acts
+
+
+def _gpu_backward(acts, rb, layers, dtype, dlogits):
+    grads = [None] * len(layers)
+    dY = dlogits
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), dtype, flip_transpose=True)
+        dX, dW, db = npvs.sparse_conv_bwd(acts[li], Wt, W.shape[1], W.shape[2], acts[li + 1], dY, rb, dtype,
+                                          relu=li < len(layers) - 1, want_dx=li > 0)
+        grads[li] = (to_np(dW), to_np(db))
+        dY = dX
+    return grads
+
+
+def test_loss_matches_oracle():
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    stats, dl = npvs.loss(acts[-1], labels, rb, lam=0.99)
+    n = rb.host_counts()["n_sites"]
+    l64 = to_np(acts[-1])[:n].astype(np.float64)
+    ref = oracle.loss(l64, to_np(labels)[:n], lam=0.99)
+    s = to_np(stats)[0]
+    for i, key in enumerate(["loss", "bce", "lrv", "tp", "fn", "fp", "gtp"]):
+        assert abs(s[i] - ref[key]) <= 2e-6 * max(1.0, abs(ref[key])), (key, s[i], ref[key])
+    assert s[7] == n * cfg.d ** 3
+    g = to_np(dl)[:n]
+    assert np.abs(g - ref["grad"]).max() <= 1e-6 * np.abs(ref["grad"]).max()
+
+
+def test_loss_batched_mean_over_grids():
+    dims = [(32, 32, 32), (64, 32, 32), (32, 32, 64)]
+    tri_list = [synth.box_scene(70 + i, g, 20, 2, 8) for i, g in enumerate(dims)]
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    rb = npvs.build_rulebook(occ, dims, 2)
+    ref = oracle_batch(tri_list, dims, 2)
+    n = ref["n"]
+    rng = np.random.default_rng(2)
+    L = rng.normal(size=(rb.cap, 8)).astype(np.float32)
+    Y = (rng.random((rb.cap, 8)) < 0.3).astype(np.uint8)
+    stats, dl = npvs.loss(torch.from_numpy(L).to(DEV), torch.from_numpy(Y).to(DEV), rb)
+    s = to_np(stats)
+    gr = ref["grid_rows"]
+    per = [oracle.loss(L[gr[b]:gr[b + 1]].astype(np.float64), Y[gr[b]:gr[b + 1]]) for b in range(3)]
+    for b in range(3):
+        assert abs(s[b, 0] - per[b]["loss"]) <= 2e-6 * abs(per[b]["loss"])
+    assert abs(s[3, 0] - np.mean([p["loss"] for p in per])) <= 2e-6
+    want = np.concatenate([p["grad"] / 3 for p in per])
+    assert np.abs(to_np(dl)[:n] - want).max() <= 1e-6 * np.abs(want).max()
+
+
+def test_backward_f32_matches_oracle_gradient():
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    _, dl = npvs.loss(acts[-1], labels, rb)
+    grads = _gpu_backward(acts, rb, layers, npvs.NPVS_F32, dl)
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
+    n = len(out["keys"])
+    lab = to_np(labels)[:n]
+    ref_dl = oracle.loss(out["acts"][-1], lab)["grad"]
+    ref, _ = oracle.backward(out, layers, ref_dl)
+    for li in range(len(layers)):
+        for a, b, nm in ((grads[li][0], ref[li][0], "dW"), (grads[li][1], ref[li][1], "db")):
+            scale = np.abs(b).max()
+            err = np.abs(a - b).max()
+            print(f"layer {li} {nm}: max|err|={err:.3e} max|g|={scale:.3e}", flush=True)
+            assert err <= 1e-4 * scale + 1e-9
+
+
+def test_backward_matches_fp64_finite_differences():
+    cfg, t, layers, occ, rb, lab_bits = _setup(layers=synth.he_weights(7, [8, 4, 8], 0.1))
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    _, dl = npvs.loss(acts[-1], labels, rb)
+    grads = _gpu_backward(acts, rb, layers, npvs.NPVS_F32, dl)
+    n = rb.host_counts()["n_sites"]
+    lab = to_np(labels)[:n]
+    occ_np = to_np(occ).reshape(cfg.grids[0][2], cfg.grids[0][1], -1)
+    rng = np.random.default_rng(0)
+    h = 1e-5
+    checked = 0
+    for li, (W, b) in enumerate(layers):
+        for _ in range(12):
+            k, c, o = rng.integers(27), rng.integers(W.shape[1]), rng.integers(W.shape[2])
+            f, masks = [], []
+            for s in (+1, -1):
+                L2 = [(w.astype(np.float64).copy(), bb.astype(np.float64).copy()) for w, bb in layers]
+                L2[li][0][k, c, o] += s * h
+                o2 = oracle.forward(t, cfg.grids[0], cfg.d, L2, want_logits=False, occ=occ_np)
+                f.append(oracle.loss(o2["acts"][-1], lab, want_grad=False)["loss"])
+                masks.append([a > 0 for a in o2["acts"][1:-1]])
+            if any((m1 != m2).any() for m1, m2 in zip(*masks)):
+                continue
+            fd = (f[0] - f[1]) / (2 * h)
+            g = grads[li][0][k, c, o]
+            # float32 gradients against FP64 finite differences
+            assert abs(g - fd) <= 1e-4 * abs(fd) + 1e-7, (li, k, c, o, g, fd)
+            checked += 1
+    assert checked >= 15
+
+
+def test_backward_bf16_close_to_oracle_and_deterministic():
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_BF16)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    _, dl = npvs.loss(acts[-1], labels, rb)
+    g1 = _gpu_backward(acts, rb, layers, npvs.NPVS_BF16, dl)
+    g2 = _gpu_backward(acts, rb, layers, npvs.NPVS_BF16, dl)
+    for a, b in zip(g1, g2):
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
+    n = len(out["keys"])
+    ref_dl = oracle.loss(out["acts"][-1], to_np(labels)[:n])["grad"]
+    ref, _ = oracle.backward(out, layers, ref_dl)
+    for li in range(len(layers)):
+        rel = np.abs(g1[li][0] - ref[li][0]).max() / np.abs(ref[li][0]).max()
+        print(f"bf16 layer {li}: max rel dW err {rel:.3e}", flush=True)
+        assert rel < 0.1
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(8)
+    p = rng.normal(size=5000).astype(np.float32)
+    gs = [rng.normal(size=5000).astype(np.float32) for _ in range(3)]
+    tp, tm, tv = (torch.from_numpy(x).to(DEV) for x in (p, np.zeros_like(p), np.zeros_like(p)))
+    rp, rm, rv = p.astype(np.float64), np.zeros(5000), np.zeros(5000)
+    for t, g in enumerate(gs, start=1):
+        npvs.adam(tp, torch.from_numpy(g).to(DEV), tm, tv, t)
+        rp, rm, rv = oracle.adam(rp, g, rm, rv, t)
+    assert np.abs(to_np(tp) - rp).max() <= 1e-6
