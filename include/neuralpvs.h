@@ -156,6 +156,14 @@ npvs_status npvs_pack_weights(const float *W, int32_t cin, int32_t cout, int32_t
 npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                  const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                  int32_t relu, int32_t out_f32, void *Y, void *stream);
+/* Same, with an explicit BF16 tile shape `variant` in [0, NPVS_CONV_VARIANTS): (rows per wave,
+ * waves sharing the 27 offsets of a tile) = 0 (16, 9), 1 (32, 1), 2 (16, 3), 3 (32, 3),
+ * 4 (16, 1), 5 (32, 9).  All variants give results within float32 rounding of each other; each
+ * one is deterministic.  Ignored by the FP32 path. */
+#define NPVS_CONV_VARIANTS 6
+npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                                    const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
+                                    int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Backward of one submanifold layer (chain rule on the forward definition):
@@ -229,6 +237,11 @@ npvs_status npvs_pvs_forward(npvs_plan *plan, const float *tris, uint8_t *occ_bi
 npvs_status npvs_plan_capture(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits, float *logits,
                               void *stream);
 npvs_status npvs_plan_replay(npvs_plan *plan, void *stream);
+/* Autotuner: runs the pass once on `tris`, then times every BF16 tile shape (`reps` launches
+ * each, HIP events on `stream`) for each distinct layer shape on the real rulebook and keeps the
+ * fastest for later passes and captures.  Synchronizes `stream`.  variants (host, nullable)
+ * receives the chosen variant of each layer. */
+npvs_status npvs_plan_autotune(npvs_plan *plan, const float *tris, int32_t reps, int32_t *variants, void *stream);
 /* Synchronizes `stream` and copies the plan's npvs_counts to host memory; returns
  * NPVS_ERR_CAPACITY if the site capacity overflowed (it cannot with the plan's capacity). */
 npvs_status npvs_plan_counts(npvs_plan *plan, npvs_counts *host_counts, void *stream);

@@ -165,12 +165,17 @@ def pack_weights(W: torch.Tensor, dtype: int, flip_transpose: bool = False) -> t
 
 def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None, cin: int, cout: int,
                     rb: Rulebook, dtype: int, relu: bool, out_f32: bool = False,
-                    out: torch.Tensor | None = None) -> torch.Tensor:
+                    out: torch.Tensor | None = None, variant: int | None = None) -> torch.Tensor:
+    """One submanifold layer; `variant` selects the BF16 tile shape (None = library default)."""
     if out is None:
         odt = torch.float32 if (dtype == NPVS_F32 or out_f32) else torch.bfloat16
         out = torch.empty((rb.cap, cout), dtype=odt, device=X.device)
-    L.call("npvs_sparse_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap, dtype,
-           int(relu), int(out_f32), _p(out), _stream())
+    if variant is None:
+        L.call("npvs_sparse_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap, dtype,
+               int(relu), int(out_f32), _p(out), _stream())
+    else:
+        L.call("npvs_sparse_conv_fwd_ex", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap,
+               dtype, int(relu), int(out_f32), int(variant), _p(out), _stream())
     return out
 
 
@@ -267,6 +272,13 @@ class Plan:
 
     def replay(self):
         L.call("npvs_plan_replay", self._h, _stream())
+
+    def autotune(self, tris, reps: int = 20) -> list:
+        """Times every BF16 tile shape per distinct layer shape on the real rulebook of `tris` and
+        keeps the fastest (synchronizes)."""
+        v = (ctypes.c_int32 * (len(self.channels) - 1))()
+        L.call("npvs_plan_autotune", self._h, _p(tris), int(reps), v, _stream())
+        return list(v)
 
     def counts(self) -> dict:
         c = L.Counts()

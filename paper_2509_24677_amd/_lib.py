@@ -19,6 +19,7 @@ NPVS_ERR_HIP = -3
 NPVS_ERR_UNSUPPORTED = -4
 NPVS_F32, NPVS_BF16, NPVS_U8 = 0, 1, 2
 NPVS_MAX_GRIDS = 32
+NPVS_CONV_VARIANTS = 6
 
 
 class NpvsError(RuntimeError):
@@ -55,6 +56,7 @@ SIGNATURES = {
     "npvs_packed_weight_bytes": (sz, [i32, i32, i32]),
     "npvs_pack_weights": (i32, [P, i32, i32, i32, i32, P, P]),
     "npvs_sparse_conv_fwd": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, P, P]),
+    "npvs_sparse_conv_fwd_ex": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P]),
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),
@@ -68,6 +70,7 @@ SIGNATURES = {
     "npvs_plan_capture": (i32, [P, P, P, P, P, P]),
     "npvs_plan_replay": (i32, [P, P]),
     "npvs_plan_counts": (i32, [P, ctypes.POINTER(Counts), P]),
+    "npvs_plan_autotune": (i32, [P, P, i32, P, P]),
 }
 
 _lib = None

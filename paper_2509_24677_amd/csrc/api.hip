@@ -114,6 +114,8 @@ struct npvs_plan {
   float *d_logits = nullptr;
   std::vector<void *> d_Wp;
   std::vector<float *> d_bias;
+  std::vector<int> variant;  // BF16 tile shape per layer
+  uint8_t *d_pvs_scratch = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -190,6 +192,8 @@ extern "C" npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, 
     TRY(plan_alloc(p, &p->d_act[1], es * cap * maxc));
   }
   TRY(plan_alloc(p, (void **)&p->d_logits, sizeof(float) * cap * C));
+  TRY(plan_alloc(p, (void **)&p->d_pvs_scratch, (size_t)p->total_bytes));
+  p->variant.assign(n_layers, kDefaultConvVariant);
   p->d_Wp.assign(n_layers, nullptr);
   p->d_bias.assign(n_layers, nullptr);
   for (int l = 0; l < n_layers; ++l) {
@@ -217,7 +221,7 @@ extern "C" npvs_status npvs_plan_set_weights(npvs_plan *plan, int32_t layer, con
 }
 
 static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_out, uint8_t *pvs, float *logits,
-                                hipStream_t s, int variant) {
+                                hipStream_t s) {
   uint8_t *occ = occ_out ? occ_out : p->d_occ;
   npvs_status st = npvs_froxelize(tris, p->n_tris.data(), p->n_grids, p->dims.data(), occ, p->d_frox_ws, p->frox_ws, s);
   if (st != NPVS_OK) return st;
@@ -231,7 +235,7 @@ static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_ou
     const bool last = l == p->n_layers - 1;
     void *out = last ? (void *)p->d_logits : p->d_act[l & 1];
     st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
-                           p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, variant);
+                           p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, p->variant[l]);
     if (st != NPVS_OK) return st;
     in = out;
   }
@@ -242,7 +246,7 @@ static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_ou
 extern "C" npvs_status npvs_pvs_forward(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits,
                                        float *logits, void *stream) {
   if (!plan || !pvs_bits) return fail(NPVS_ERR_INVALID_ARG, "npvs_pvs_forward: null pointer");
-  return plan_forward(plan, tris, occ_bits, pvs_bits, logits, as_stream(stream), 0);
+  return plan_forward(plan, tris, occ_bits, pvs_bits, logits, as_stream(stream));
 }
 
 extern "C" npvs_status npvs_plan_capture(npvs_plan *plan, const float *tris, uint8_t *occ_bits, uint8_t *pvs_bits,
@@ -260,7 +264,7 @@ extern "C" npvs_status npvs_plan_capture(npvs_plan *plan, const float *tris, uin
   }
   npvs_status st = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "npvs_plan_capture: begin");
   if (st != NPVS_OK) return st;
-  npvs_status fst = plan_forward(plan, tris, occ_bits, pvs_bits, logits, s, 0);
+  npvs_status fst = plan_forward(plan, tris, occ_bits, pvs_bits, logits, s);
   hipGraph_t g = nullptr;
   st = check_hip(hipStreamEndCapture(s, &g), "npvs_plan_capture: end");
   if (fst != NPVS_OK) {
@@ -288,4 +292,62 @@ extern "C" npvs_status npvs_plan_counts(npvs_plan *plan, npvs_counts *host_count
   if (host_counts->n_sites_needed > host_counts->n_sites)
     return fail(NPVS_ERR_CAPACITY, "npvs_plan_counts: site capacity overflowed");
   return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_plan_autotune(npvs_plan *plan, const float *tris, int32_t reps, int32_t *variants,
+                                         void *stream) {
+  if (!plan) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_autotune: null plan");
+  if (reps < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_plan_autotune: reps < 1");
+  hipStream_t s = as_stream(stream);
+  npvs_plan *p = plan;
+  npvs_status st = plan_forward(p, tris, nullptr, p->d_pvs_scratch, nullptr, s);
+  if (st != NPVS_OK) return st;
+  if (p->dtype == NPVS_BF16) {
+    hipEvent_t e0, e1;
+    st = check_hip(hipEventCreate(&e0), "npvs_plan_autotune");
+    if (st != NPVS_OK) return st;
+    st = check_hip(hipEventCreate(&e1), "npvs_plan_autotune");
+    if (st != NPVS_OK) {
+      (void)hipEventDestroy(e0);
+      return st;
+    }
+    for (int l = 0; l < p->n_layers && st == NPVS_OK; ++l) {
+      const bool last = l == p->n_layers - 1;
+      int same = -1;  // an earlier layer of the same shape
+      for (int m = 0; m < l; ++m)
+        if (p->ch[m] == p->ch[l] && p->ch[m + 1] == p->ch[l + 1] && (m == p->n_layers - 1) == last) same = m;
+      if (same >= 0) {
+        p->variant[l] = p->variant[same];
+        continue;
+      }
+      const void *in = l == 0 ? p->d_X0 : p->d_act[(l - 1) & 1];
+      void *out = last ? (void *)p->d_logits : p->d_act[l & 1];
+      float best = 3.4e38f;
+      for (int v = 0; v < NPVS_CONV_VARIANTS && st == NPVS_OK; ++v) {
+        // rerunning layer l on its own input rewrites the same output values
+        st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
+                               p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v);
+        if (st != NPVS_OK) break;
+        st = check_hip(hipEventRecord(e0, s), "npvs_plan_autotune");
+        for (int r = 0; r < reps && st == NPVS_OK; ++r)
+          st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
+                                 p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v);
+        if (st != NPVS_OK) break;
+        st = check_hip(hipEventRecord(e1, s), "npvs_plan_autotune");
+        if (st == NPVS_OK) st = check_hip(hipEventSynchronize(e1), "npvs_plan_autotune");
+        float ms = 0.0f;
+        if (st == NPVS_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "npvs_plan_autotune");
+        if (st == NPVS_OK && ms < best) {
+          best = ms;
+          p->variant[l] = v;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != NPVS_OK) return st;
+  }
+  if (variants)
+    for (int l = 0; l < p->n_layers; ++l) variants[l] = p->variant[l];
+  return check_hip(hipStreamSynchronize(s), "npvs_plan_autotune");
 }

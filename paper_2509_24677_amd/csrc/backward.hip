@@ -3,13 +3,16 @@
 //   dX = conv(dZ, W'), W'_k = (W_{26-k})^T: the rulebook is symmetric (R_{26-k} is R_k with the
 //        roles of input and output swapped), so the data gradient is a forward convolution;
 //   dW_k = sum_{(i,r) in R_k} X[i]^T dZ[r]: per-offset reduced outer products over the CSR
-//        pair list, cut into a fixed number of slices per offset, reduced in a fixed order;
-//   db = sum_r dZ[r].
+//        pair list, cut into a fixed number of slices per offset and reduced in a fixed order;
+//   db = sum_r dZ[r], accumulated by the slices of the centre offset (whose pairs are (r, r)).
 // Every float32 reduction adds short plain partial sums into a Neumaier-compensated total, and
 // all reduction orders are fixed, so gradients are bit-identical run to run.
 #include "npvs_common.hpp"
 
 namespace npvs {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
 npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                               const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
@@ -28,7 +31,7 @@ struct Comp {  // Neumaier-compensated float sum
 __device__ __forceinline__ float load_as_f32(const float *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float load_as_f32(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
 
-// dZ in float32 (for wgrad/db) and, for the BF16 path, a bfloat16 copy (dgrad input).
+// dZ in float32 (for wgrad/db) and, for the BF16 path, a bfloat16 copy (MFMA operand).
 template <typename T>
 __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y, const float *__restrict__ dY,
                                                          const npvs_counts *__restrict__ counts, int C, int relu,
@@ -43,23 +46,37 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
 }
 
 constexpr int kWgSlices = 16;  // slices of each offset's pair list
-constexpr int kWgPairs = 32;   // pairs staged per step
-constexpr int kWgEPT = 16;     // dW entries per thread per pass
+constexpr int kWgPairs = 32;   // pairs staged per step (vector path)
+constexpr int kWgEPT = 16;     // dW entries per thread per pass (vector path)
 
-// grid (kWgSlices, 27), 256 threads.  Partial dW of offset k over slice s of its pairs.
+// Centre offset: db partial of this slice, db[o] += sum over the slice's rows of dZ[r][o].
+__device__ __forceinline__ void db_slice(const float *__restrict__ dZ, int cout, const int32_t *__restrict__ pairs,
+                                         int64_t p0, int64_t p1, float *__restrict__ dbpart, int s) {
+  for (int o = threadIdx.x; o < cout; o += blockDim.x) {
+    Comp a{0.0f, 0.0f};
+    for (int64_t p = p0; p < p1; p += 32) {
+      const int64_t pe = p + 32 < p1 ? p + 32 : p1;
+      float t = 0.0f;
+      for (int64_t q = p; q < pe; ++q) t += dZ[(int64_t)pairs[2 * q + 1] * cout + o];
+      a.add(t);
+    }
+    dbpart[s * cout + o] = a.value();
+  }
+}
+
+// Vector FP32 path: grid (kWgSlices, 27), 256 threads.  Partial dW of offset k over slice s.
 template <typename T>
 __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict__ X, int cin,
                                                              const float *__restrict__ dZ, int cout,
                                                              const int32_t *__restrict__ rb_off,
                                                              const int32_t *__restrict__ pairs,
-                                                             float *__restrict__ part) {
+                                                             float *__restrict__ part, float *__restrict__ dbpart) {
   __shared__ float Xs[kWgPairs][65];
   __shared__ float Gs[kWgPairs][64];
   __shared__ int in_s[kWgPairs], out_s[kWgPairs];
   const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
   const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
-  const int E = cin * cout;
   const int cw = (256 * kWgEPT) / cout < 64 ? (256 * kWgEPT) / cout : 64;  // channels of X per pass
   for (int cbase = 0; cbase < cin; cbase += cw) {
     const int cn = cin - cbase < cw ? cin - cbase : cw;
@@ -101,27 +118,115 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
       }
     }
   }
-  (void)E;
+  if (k == 13) db_slice(dZ, cout, pairs, p0, p1, dbpart, s);
 }
 
-constexpr int kDbSlices = 64;
+// BF16 path on MFMA.  grid (kWgSlices, 27), 256 threads = 4 waves; cin, cout <= 64.
+// dW_k[c][o] = sum_p X[in_p][c] dZ[out_p][o] is a [cin x P] x [P x cout] product with the pair
+// index as the contraction.  64 pairs at a time are staged into LDS transposed (channel-major,
+// XT[c][p], GT[o][p]) so that both MFMA operands of v_mfma_f32_16x16x32_bf16 are one 16-byte
+// LDS read per lane:
+//   A (16 x 32): lane l gives XT[mb*16 + l%16][kk + 8(l/16) + j]
+//   B (32 x 16): lane l gives GT[nb*16 + l%16][kk + 8(l/16) + j]
+//   D: lane l holds dW[mb*16 + 4(l/16) + i][nb*16 + l%16]
+// Each chunk's product starts from zero and is added into a compensated total.
+constexpr int kWgChunk = 64;
+constexpr int kWgPitch = kWgChunk + 8;  // bf16 elements per LDS row (padding spreads banks)
 
-// grid kDbSlices: column sums of dZ over a slice of rows.
-__global__ __launch_bounds__(256) void db_partial_kernel(const float *__restrict__ dZ, int cout,
-                                                          const npvs_counts *__restrict__ counts,
-                                                          float *__restrict__ part) {
-  const int64_t n = counts->n_sites;
-  const int64_t r0 = n * blockIdx.x / kDbSlices, r1 = n * (blockIdx.x + 1) / kDbSlices;
-  for (int o = threadIdx.x; o < cout; o += blockDim.x) {
-    Comp a{0.0f, 0.0f};
-    for (int64_t r = r0; r < r1; r += 32) {
-      float t = 0.0f;
-      int64_t re = r + 32 < r1 ? r + 32 : r1;
-      for (int64_t q = r; q < re; ++q) t += dZ[q * cout + o];
-      a.add(t);
-    }
-    part[blockIdx.x * cout + o] = a.value();
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restrict__ X, int cin,
+                                                          const uint16_t *__restrict__ dZ16,
+                                                          const float *__restrict__ dZ32, int cout,
+                                                          const int32_t *__restrict__ rb_off,
+                                                          const int32_t *__restrict__ pairs,
+                                                          float *__restrict__ part, float *__restrict__ dbpart) {
+  __shared__ __attribute__((aligned(16))) uint16_t XT[64 * kWgPitch];
+  __shared__ __attribute__((aligned(16))) uint16_t GT[64 * kWgPitch];
+  __shared__ int in_s[kWgChunk], out_s[kWgChunk];
+  const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
+  const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
+  const int CB = (cin + 15) / 16, OB = (cout + 15) / 16, nblk = CB * OB;
+  const int cin8 = (cin + 7) / 8, cout8 = (cout + 7) / 8;
+  // channel rows past cin / cout stay zero
+  for (int e = tid; e < 64 * kWgPitch; e += 256) {
+    XT[e] = 0;
+    GT[e] = 0;
   }
+  f32x4_t acc[4];
+  Comp tot[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[j][i] = Comp{0.0f, 0.0f};
+  for (int64_t pb = p0; pb < p1; pb += kWgChunk) {
+    const int m = p1 - pb < kWgChunk ? (int)(p1 - pb) : kWgChunk;
+    __syncthreads();
+    if (tid < kWgChunk) {
+      in_s[tid] = tid < m ? pairs[2 * (pb + tid)] : -1;
+      out_s[tid] = tid < m ? pairs[2 * (pb + tid) + 1] : -1;
+    }
+    __syncthreads();
+    // task = 4 consecutive pairs x 8 channels; 16 pair-quads per chunk
+    for (int task = tid; task < 16 * (cin8 + cout8); task += 256) {
+      const int pq = task & 15;
+      int cc = task >> 4;
+      const bool isx = cc < cin8;
+      if (!isx) cc -= cin8;
+      const uint16_t *src = isx ? X : dZ16;
+      const int C = isx ? cin : cout;
+      uint16_t *dst = isx ? XT : GT;
+      uint4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = isx ? in_s[4 * pq + i] : out_s[4 * pq + i];
+        v[i] = r >= 0 ? *reinterpret_cast<const uint4 *>(src + (int64_t)r * C + 8 * cc) : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int sh = (j & 1) * 16;
+        uint32_t w0 = (((j >> 1) == 0 ? v[0].x : (j >> 1) == 1 ? v[0].y : (j >> 1) == 2 ? v[0].z : v[0].w) >> sh) & 0xffffu;
+        uint32_t w1 = (((j >> 1) == 0 ? v[1].x : (j >> 1) == 1 ? v[1].y : (j >> 1) == 2 ? v[1].z : v[1].w) >> sh) & 0xffffu;
+        uint32_t w2 = (((j >> 1) == 0 ? v[2].x : (j >> 1) == 1 ? v[2].y : (j >> 1) == 2 ? v[2].z : v[2].w) >> sh) & 0xffffu;
+        uint32_t w3 = (((j >> 1) == 0 ? v[3].x : (j >> 1) == 1 ? v[3].y : (j >> 1) == 2 ? v[3].z : v[3].w) >> sh) & 0xffffu;
+        uint2 pk2 = make_uint2(w0 | (w1 << 16), w2 | (w3 << 16));
+        *reinterpret_cast<uint2 *>(dst + (8 * cc + j) * kWgPitch + 4 * pq) = pk2;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < kWgChunk; kk += 32) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int blk = wv + 4 * j;
+        if (blk < nblk) {
+          const int mb = blk / OB, nb = blk % OB;
+          const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(XT + (mb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
+          const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(GT + (nb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tot[j][i].add(acc[j][i]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int blk = wv + 4 * j;
+    if (blk < nblk) {
+      const int mb = blk / OB, nb = blk % OB;
+      const int o = nb * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = mb * 16 + 4 * (lane >> 4) + i;
+        if (c < cin && o < cout) part[((int64_t)(k * kWgSlices + s) * cin + c) * cout + o] = tot[j][i].value();
+      }
+    }
+  }
+  if (k == 13) db_slice(dZ32, cout, pairs, p0, p1, dbpart, s);
 }
 
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
@@ -137,7 +242,7 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
       dW[e] = a.value();
     } else {
       int o = (int)(e - 27 * E);
-      for (int s = 0; s < kDbSlices; ++s) a.add(dbpart[s * cout + o]);
+      for (int s = 0; s < kWgSlices; ++s) a.add(dbpart[s * cout + o]);
       db[o] = a.value();
     }
   }
@@ -155,7 +260,7 @@ static void bwd_ws_layout(int32_t cin, int32_t cout, int32_t cap, int32_t dtype,
   *o_wp = o;
   o += align256(sizeof(float) * 27 * kWgSlices * (size_t)cin * cout);
   *o_dbp = o;
-  o += align256(sizeof(float) * kDbSlices * (size_t)cout);
+  o += align256(sizeof(float) * kWgSlices * (size_t)cout);
   *bytes = o;
 }
 
@@ -183,6 +288,8 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   if (cout > 64) return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd: cout > 64");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: dtype must be NPVS_F32 or NPVS_BF16");
+  if (dtype == NPVS_BF16 && (cin % 8 || cout % 8))
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd: BF16 needs cin % 8 == 0 and cout % 8 == 0");
   size_t o32, o16, owp, odb, need;
   bwd_ws_layout(cin, cout, cap_sites, dtype, &o32, &o16, &owp, &odb, &need);
   if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: workspace too small");
@@ -206,10 +313,12 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   }
   dim3 gw(kWgSlices, 27);
   if (dtype == NPVS_F32)
-    wgrad_partial_kernel<float><<<gw, 256, 0, s>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
+    wgrad_partial_kernel<float><<<gw, 256, 0, s>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart, dbpart);
+  else if (cin <= 64)
+    wgrad_bf16_kernel<<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ16, dZ32, cout, rb_off, rb_pairs, wpart, dbpart);
   else
-    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
-  db_partial_kernel<<<kDbSlices, 256, 0, s>>>(dZ32, cout, counts, dbpart);
+    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart,
+                                                      dbpart);
   grad_reduce_kernel<<<stride_grid(27LL * cin * cout + cout, 256, 2048), 256, 0, s>>>(wpart, dbpart, cin, cout, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
 }

@@ -141,10 +141,33 @@ __global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restri
 //   A (16 x 32) = W^T block: lane l gives W[kb*32 + 8(l/16) + j][nb*16 + l%16]   (packed, one load)
 //   B (32 x 16) = X^T block: lane l gives X[row0 + l%16][kb*32 + 8(l/16) + j]    (gathered row, one load)
 //   D (16 x 16): lane l holds Y[row0 + l%16][nb*16 + 4(l/16) + i], i = 0..3
-// A wave owns MB x 16 rows and all NB x 16 output channels.  With KSPLIT = 3 the three waves
-// of a workgroup take the dz = -1, 0, +1 slices of the offsets of the same rows and their
-// partial sums are added in LDS in a fixed order.
+// A wave owns MB x 16 rows and all NB x 16 output channels.  The KSPLIT waves of a workgroup
+// take consecutive slices of 27 / KSPLIT offsets of the same rows.  A wave loads the neighbour
+// indices of all its offsets at once, then loads the row and weight fragments of offset q + 1
+// while the MFMAs of offset q run; offsets where none of its rows has a neighbour are skipped.
+// The partial sums of the waves are added in LDS in wave order (deterministic) and every wave
+// finishes some of the 16 x 16 output blocks (bias, ReLU, rounding, store).
 // ------------------------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void conv_bf16_epilogue(const f32x4_t &acc, int r, int n, int o, int cout,
+                                                   const float *__restrict__ bias, int relu, int out_f32, void *Y) {
+  if (r >= n || o >= cout) return;
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float t = acc[i] + (bias ? bias[o + i] : 0.0f);
+    v[i] = (relu && t < 0.0f) ? 0.0f : t;
+  }
+  if (out_f32) {
+    *reinterpret_cast<float4 *>(static_cast<float *>(Y) + (int64_t)r * cout + o) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    uint2 p;
+    p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+    p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+    *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = p;
+  }
+}
+
 template <int KB, int NB, int MB, int KSPLIT>
 __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16_t *__restrict__ X, int cin,
                                                                      const bf16x8_t *__restrict__ Wp,
@@ -153,102 +176,128 @@ __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16
                                                                      const npvs_counts *__restrict__ counts, int cap,
                                                                      int relu, int out_f32, void *__restrict__ Y) {
   constexpr int ROWS = 16 * MB;
-  __shared__ f32x4_t red[KSPLIT > 1 ? (KSPLIT - 1) * MB * NB * 64 : 1];
+  constexpr int KPER = 27 / KSPLIT;
+  constexpr int NBLK = MB * NB;
+  constexpr int S = KPER * KB;  // stages: (offset, 32-channel chunk)
+  constexpr int PD = S < 4 ? S : 4;  // stages in flight
+  static_assert(KPER * KSPLIT == 27, "KSPLIT must divide 27");
+  __shared__ f32x4_t red[KSPLIT > 1 ? KSPLIT * NBLK * 64 : 1];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int kbeg = wv * 27 / KSPLIT, kend = (wv + 1) * 27 / KSPLIT;
+  const int kbeg = wv * KPER;
   const int csub = 8 * (lane >> 4);
   const bf16x8_t zero8 = {};
   for (int j = 0;; ++j) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
     if (tile < 0) break;
     const int row0 = tile * ROWS;
+    int idx[KPER][MB];
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int r = row0 + mb * 16 + (lane & 15);
+        idx[q][mb] = r < n ? nbr[(int64_t)(kbeg + q) * cap + r] : -1;
+      }
+    bool act[KPER];
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) {
+      bool a = false;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) a = a || idx[q][mb] >= 0;
+      act[q] = __any(a);
+    }
     f32x4_t acc[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k = kbeg; k < kend; ++k) {
-      int idx[MB];
-      bool any = false;
+    bf16x8_t bx[PD][MB], aw[PD][NB];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int r = row0 + mb * 16 + (lane & 15);
-        idx[mb] = r < n ? nbr[(int64_t)k * cap + r] : -1;
-        any = any || idx[mb] >= 0;
-      }
-      if (!__any(any)) continue;  // no row of this wave has a neighbour at offset k
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        const int c = kb * 32 + csub;
-        bf16x8_t bx[MB];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-          bx[mb] = (idx[mb] >= 0 && c < cin)
-                       ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[mb] * cin + c)
-                       : zero8;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const bf16x8_t aw = Wp[(((int64_t)k * NB + nb) * KB + kb) * 64 + lane];
+    for (int st = -(PD - 1); st < S; ++st) {
+      const int ld = st + PD - 1;  // stage whose loads are issued now
+      if (ld < S) {
+        const int q = ld / KB, kb = ld % KB, slot = ld % PD;
+        if (act[q]) {
+          const int c = kb * 32 + csub;
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[mb], acc[mb][nb], 0, 0, 0);
+            bx[slot][mb] = (idx[q][mb] >= 0 && c < cin)
+                               ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[q][mb] * cin + c)
+                               : zero8;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) aw[slot][nb] = Wp[(((int64_t)(kbeg + q) * NB + nb) * KB + kb) * 64 + lane];
         }
       }
-    }
-    if constexpr (KSPLIT > 1) {
-      __syncthreads();
-      if (wv > 0)
+      if (st >= 0 && act[st / KB]) {
+        const int slot = st % PD;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) red[(((wv - 1) * MB + mb) * NB + nb) * 64 + lane] = acc[mb][nb];
-      __syncthreads();
-      if (wv == 0)
-        for (int w = 1; w < KSPLIT; ++w)
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] += red[(((w - 1) * MB + mb) * NB + nb) * 64 + lane];
-    }
-    if (wv == 0) {
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int r = row0 + mb * 16 + (lane & 15);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int o = nb * 16 + 4 * (lane >> 4);
-          if (r >= n || o >= cout) continue;
-          float v[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            float t = acc[mb][nb][i] + (bias ? bias[o + i] : 0.0f);
-            v[i] = (relu && t < 0.0f) ? 0.0f : t;
-          }
-          if (out_f32) {
-            *reinterpret_cast<float4 *>(static_cast<float *>(Y) + (int64_t)r * cout + o) = make_float4(v[0], v[1], v[2], v[3]);
-          } else {
-            uint2 p;
-            p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-            p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-            *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = p;
-          }
-        }
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[slot][nb], bx[slot][mb], acc[mb][nb], 0, 0, 0);
       }
     }
-    if constexpr (KSPLIT > 1) __syncthreads();
+    if constexpr (KSPLIT == 1) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          conv_bf16_epilogue<NB>(acc[mb][nb], row0 + mb * 16 + (lane & 15), n, nb * 16 + 4 * (lane >> 4), cout, bias,
+                                 relu, out_f32, Y);
+    } else {
+      __syncthreads();  // the previous tile's readers are done with red
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) red[(wv * NBLK + mb * NB + nb) * 64 + lane] = acc[mb][nb];
+      __syncthreads();
+      for (int blk = wv; blk < NBLK; blk += KSPLIT) {
+        f32x4_t sum = red[blk * 64 + lane];
+        for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
+        const int mb = blk / NB, nb = blk % NB;
+        conv_bf16_epilogue<NB>(sum, row0 + mb * 16 + (lane & 15), n, nb * 16 + 4 * (lane >> 4), cout, bias, relu,
+                               out_f32, Y);
+      }
+    }
   }
 }
+
+// Tile shapes (MB, KSPLIT) = (rows per wave / 16, waves sharing the 27 offsets of a tile):
+// variant 0 (1, 9), 1 (2, 1), 2 (1, 3), 3 (2, 3), 4 (1, 1), 5 (2, 9).  Inputs wider than 64
+// channels use only the 9-way split (a long unrolled offset loop would not fit the registers).
+// kDefaultConvVariant is used by npvs_sparse_conv_fwd; the autotuner can pick another per layer.
 
 template <int KB, int NB, int MB, int KSPLIT>
 static void launch_bf16(const void *X, int cin, const void *Wp, const float *bias, int cout, const int32_t *nbr,
                         const npvs_counts *counts, int cap, int relu, int out_f32, void *Y, hipStream_t s) {
   const int rows = 16 * MB;
-  int G = stride_grid(cap, rows, 2048);
+  int G = stride_grid(cap, rows, 4096);
   G = (G + 7) & ~7;
   conv_fwd_bf16_kernel<KB, NB, MB, KSPLIT><<<G, 64 * KSPLIT, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+template <int KB, int NB>
+static void launch_bf16_variant(int v, const void *X, int cin, const void *Wp, const float *bias, int cout,
+                                const int32_t *nbr, const npvs_counts *counts, int cap, int relu, int out_f32, void *Y,
+                                hipStream_t s) {
+  if constexpr (KB > 2) {
+    if (v == 5)
+      launch_bf16<KB, NB, 2, 9>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    else
+      launch_bf16<KB, NB, 1, 9>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+  } else {
+    switch (v) {
+      case 0: launch_bf16<KB, NB, 1, 9>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 1: launch_bf16<KB, NB, 2, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 2: launch_bf16<KB, NB, 1, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 3: launch_bf16<KB, NB, 2, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 4: launch_bf16<KB, NB, 1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      default: launch_bf16<KB, NB, 2, 9>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+    }
+  }
 }
 
 }  // namespace npvs
@@ -299,15 +348,10 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
   if (cin % 8 || cout % 8 || cin > 512 || cout > 64)
     return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: BF16 needs cin % 8 == 0, cin <= 512, cout % 8 == 0, cout <= 64");
   const int KB = (cin + 31) / 32, NB = (cout + 15) / 16;
-#define NPVS_BF16_CASE(kb, nb)                                                                               \
-  if (KB == kb && NB == nb) {                                                                                \
-    if (variant == 1)                                                                                        \
-      launch_bf16<kb, nb, 2, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);              \
-    else if (variant == 2)                                                                                   \
-      launch_bf16<kb, nb, 1, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);              \
-    else                                                                                                     \
-      launch_bf16<kb, nb, 2, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);              \
-    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");                                             \
+#define NPVS_BF16_CASE(kb, nb)                                                                           \
+  if (KB == kb && NB == nb) {                                                                            \
+    launch_bf16_variant<kb, nb>(variant, X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); \
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");                                         \
   }
   NPVS_BF16_CASE(1, 1)
   NPVS_BF16_CASE(1, 2)
@@ -323,15 +367,25 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
 }
 }  // namespace npvs
 
-extern "C" npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
-                                           int32_t cout, const int32_t *nbr, const npvs_counts *counts,
-                                           int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32, void *Y,
-                                           void *stream) {
+extern "C" npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias,
+                                              int32_t cout, const int32_t *nbr, const npvs_counts *counts,
+                                              int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32,
+                                              int32_t variant, void *Y, void *stream) {
   if (!X || !Wp || !nbr || !counts || !Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: null pointer");
   if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: bad sizes");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: dtype must be NPVS_F32 or NPVS_BF16");
   if (X == Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: X and Y must not alias");
+  if (variant < 0 || variant >= NPVS_CONV_VARIANTS)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: variant out of range");
   return conv_fwd_dispatch(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32, Y,
-                           as_stream(stream), 0);
+                           as_stream(stream), variant);
+}
+
+extern "C" npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
+                                           int32_t cout, const int32_t *nbr, const npvs_counts *counts,
+                                           int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32, void *Y,
+                                           void *stream) {
+  return npvs_sparse_conv_fwd_ex(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32,
+                                 kDefaultConvVariant, Y, stream);
 }

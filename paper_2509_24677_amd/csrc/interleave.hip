@@ -62,7 +62,9 @@ __global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t
   }
 }
 
-// De-interleave + threshold + pack: one thread per packed output byte (8 froxels along x).
+// De-interleave + threshold + pack: one thread per packed output byte (8 froxels along x).  The
+// byte's froxels lie in 8/d consecutive blocks (d <= 8) or in one block (d >= 8); each block's
+// row is looked up once and its logits of this (y, z) line are contiguous in Y.
 __global__ __launch_bounds__(256) void deinterleave_threshold_kernel(Batch B, int64_t total_bytes,
                                                                       const float *__restrict__ Y,
                                                                       const int32_t *__restrict__ block_row,
@@ -70,29 +72,46 @@ __global__ __launch_bounds__(256) void deinterleave_threshold_kernel(Batch B, in
                                                                       uint8_t *__restrict__ pvs,
                                                                       float *__restrict__ logits) {
   const int d = B.d, C = d * d * d;
+  const float ninf = -__builtin_huge_valf();
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_bytes;
        t += (int64_t)gridDim.x * blockDim.x) {
     int b = 0;
     while (b + 1 < B.n && t >= B.g[b + 1].occ_off) ++b;
     const GridDesc &g = B.g[b];
-    int64_t l = t - g.occ_off;
+    const int64_t l = t - g.occ_off;
     const int rb = g.nx >> 3;
-    int xb = l % rb;
-    int y = (l / rb) % g.ny;
-    int z = l / ((int64_t)rb * g.ny);
+    const int xb = l % rb;
+    const int y = (l / rb) % g.ny;
+    const int z = l / ((int64_t)rb * g.ny);
     const uint8_t gbits = occ[t];
-    uint8_t out = 0;
-    float lv[8];
     const int key_yz = g.key_off + ((z / d) * g.By + (y / d)) * g.Bx;
     const int cyz = ((z % d) * d + (y % d)) * d;
+    float lv[8];
+    if (d == 4) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int x = xb * 8 + i;
-      int32_t row = block_row[key_yz + x / d];
-      float v = row >= 0 ? Y[(int64_t)row * C + cyz + (x % d)] : -__builtin_huge_valf();
-      lv[i] = v;
-      out |= (uint8_t)(((v >= 0.0f) && ((gbits >> i) & 1)) << i);
+      for (int j = 0; j < 2; ++j) {
+        const int32_t row = block_row[key_yz + xb * 2 + j];
+        float4 v = row >= 0 ? *reinterpret_cast<const float4 *>(Y + (int64_t)row * C + cyz)
+                            : make_float4(ninf, ninf, ninf, ninf);
+        lv[4 * j] = v.x;
+        lv[4 * j + 1] = v.y;
+        lv[4 * j + 2] = v.z;
+        lv[4 * j + 3] = v.w;
+      }
+    } else if (d < 8) {
+      for (int j = 0; j < 8 / d; ++j) {
+        const int32_t row = block_row[key_yz + (xb * 8) / d + j];
+        for (int ox = 0; ox < d; ++ox) lv[j * d + ox] = row >= 0 ? Y[(int64_t)row * C + cyz + ox] : ninf;
+      }
+    } else {
+      const int32_t row = block_row[key_yz + (xb * 8) / d];
+      const int off = (xb * 8) % d;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) lv[i] = row >= 0 ? Y[(int64_t)row * C + cyz + off + i] : ninf;
     }
+    uint8_t out = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out |= (uint8_t)(((lv[i] >= 0.0f) && ((gbits >> i) & 1)) << i);
     pvs[t] = out;
     if (logits) {
       float4 *dst = reinterpret_cast<float4 *>(logits + g.dense_off + (((int64_t)z * g.ny + y) * g.nx + xb * 8));

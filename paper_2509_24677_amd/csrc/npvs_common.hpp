@@ -78,6 +78,9 @@ inline int stride_grid(int64_t max_items, int per_block, int cap = 4096) {
 constexpr int kFroxTileX = 128;  // froxels per tile along x (four 32-froxel words)
 constexpr int kFroxTileY = 8;
 constexpr int kFroxTileZ = 8;
-constexpr int kFroxTileCap = 1024;  // triangle slots per tile before the tile falls back to a full scan
+constexpr int kFroxTileCap = 2048;  // triangle slots per tile before the tile falls back to a full scan
+
+// Tile shape of the BF16 convolution used when no autotuned choice is given (see conv.hip).
+constexpr int kDefaultConvVariant = 3;
 
 }  // namespace npvs

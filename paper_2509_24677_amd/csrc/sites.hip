@@ -12,8 +12,6 @@
 
 namespace npvs {
 
-constexpr int kSitesPerWG = 1024;  // 256 threads x 4 consecutive blocks
-
 // Exclusive scan of one int per thread over a 256-thread workgroup (4 waves of 64).
 __device__ __forceinline__ int block_exclusive_scan(int v, int *total) {
   __shared__ int wsum[4];
@@ -39,7 +37,10 @@ __device__ __forceinline__ int block_sum(int v) {
   return t;
 }
 
-// 1 iff block gb (global key) has an occupied froxel.
+// Each thread tests BPT consecutive blocks (global keys).  When every grid has nx % 32 == 0 the
+// BPT = 32 / d blocks of a thread share one 32-froxel span of their rows, so the thread ORs d*d
+// dword loads and splits the word into block flags; otherwise BPT = 4 and each block is tested
+// byte by byte.
 __device__ __forceinline__ int block_active(const Batch &B, const uint8_t *__restrict__ occ, int32_t gb) {
   if (gb >= B.total_blocks) return 0;
   const GridDesc &g = B.g[grid_of_key(B, gb)];
@@ -49,6 +50,7 @@ __device__ __forceinline__ int block_active(const Batch &B, const uint8_t *__res
   const int64_t row_bytes = g.nx >> 3;
   const int x0 = bx * d, x1 = x0 + d - 1;
   const uint8_t *base = occ + g.occ_off;
+  int any = 0;
   for (int oz = 0; oz < d; ++oz)
     for (int oy = 0; oy < d; ++oy) {
       const uint8_t *row = base + ((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * row_bytes;
@@ -56,22 +58,45 @@ __device__ __forceinline__ int block_active(const Batch &B, const uint8_t *__res
         int lo = xb * 8 > x0 ? 0 : x0 - xb * 8;
         int hi = xb * 8 + 7 < x1 ? 7 : x1 - xb * 8;
         unsigned mask = ((2u << hi) - 1u) & ~((1u << lo) - 1u);
-        if (row[xb] & mask) return 1;
+        any |= row[xb] & mask;
       }
     }
-  return 0;
+  return any != 0;
 }
 
-__global__ __launch_bounds__(256) void sites_count_kernel(Batch B, const uint8_t *__restrict__ occ,
+// Bit i of the result = activity of block gb0 + i, i < bpt.
+__device__ __forceinline__ uint32_t thread_flags(const Batch &B, const uint8_t *__restrict__ occ, int32_t gb0,
+                                                 int bpt, int fast) {
+  if (gb0 >= B.total_blocks) return 0u;
+  if (!fast) {
+    uint32_t f = 0;
+    for (int i = 0; i < bpt; ++i) f |= (uint32_t)block_active(B, occ, gb0 + i) << i;
+    return f;
+  }
+  const GridDesc &g = B.g[grid_of_key(B, gb0)];
+  const int d = B.d;
+  const int32_t l = gb0 - g.key_off;
+  const int bx = l % g.Bx, by = (l / g.Bx) % g.By, bz = l / (g.Bx * g.By);
+  const int64_t row_words = g.nx >> 5;
+  const uint32_t *base = reinterpret_cast<const uint32_t *>(occ + g.occ_off) + (bx * d >> 5);
+  uint32_t w = 0;
+  for (int oz = 0; oz < d; ++oz)
+    for (int oy = 0; oy < d; ++oy) w |= base[((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * row_words];
+  if (d == 32) return w != 0u;
+  const uint32_t m = (1u << d) - 1u;
+  uint32_t f = 0;
+  for (int i = 0; i < bpt; ++i) f |= (uint32_t)(((w >> (i * d)) & m) != 0u) << i;
+  return f;
+}
+
+__global__ __launch_bounds__(256) void sites_count_kernel(Batch B, const uint8_t *__restrict__ occ, int bpt, int fast,
                                                            int32_t *__restrict__ wg_counts) {
-  int32_t gb0 = blockIdx.x * kSitesPerWG + threadIdx.x * 4;
-  int c = 0;
-  for (int i = 0; i < 4; ++i) c += block_active(B, occ, gb0 + i);
-  int t = block_sum(c);
+  const int32_t gb0 = (blockIdx.x * 256 + threadIdx.x) * bpt;
+  int t = block_sum(__popc(thread_flags(B, occ, gb0, bpt, fast)));
   if (threadIdx.x == 0) wg_counts[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void sites_write_kernel(Batch B, const uint8_t *__restrict__ occ,
+__global__ __launch_bounds__(256) void sites_write_kernel(Batch B, const uint8_t *__restrict__ occ, int bpt, int fast,
                                                            const int32_t *__restrict__ wg_counts, int32_t cap,
                                                            npvs_counts *__restrict__ counts,
                                                            int32_t *__restrict__ site_keys,
@@ -80,31 +105,28 @@ __global__ __launch_bounds__(256) void sites_write_kernel(Batch B, const uint8_t
   // rows before this workgroup
   int part = 0;
   for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) part += wg_counts[i];
-  int prefix = block_sum(part);
-  int32_t gb0 = blockIdx.x * kSitesPerWG + threadIdx.x * 4;
-  int f[4], c = 0;
-  for (int i = 0; i < 4; ++i) {
-    f[i] = block_active(B, occ, gb0 + i);
-    c += f[i];
-  }
+  const int prefix = block_sum(part);
+  const int32_t gb0 = (blockIdx.x * 256 + threadIdx.x) * bpt;
+  const uint32_t f = thread_flags(B, occ, gb0, bpt, fast);
   int wg_total;
-  int pos = prefix + block_exclusive_scan(c, &wg_total);
-  for (int i = 0; i < 4; ++i) {
-    int32_t gb = gb0 + i;
+  int pos = prefix + block_exclusive_scan(__popc(f), &wg_total);
+  for (int i = 0; i < bpt; ++i) {
+    const int32_t gb = gb0 + i;
     if (gb >= B.total_blocks) break;
-    int b = grid_of_key(B, gb);
+    const int b = grid_of_key(B, gb);
     if (gb == B.g[b].key_off) grid_rows[b] = pos < cap ? pos : cap;
-    if (f[i] && pos < cap) {
+    const int fi = (f >> i) & 1;
+    if (fi && pos < cap) {
       site_keys[pos] = gb;
       block_row[gb] = pos;
     } else {
       block_row[gb] = -1;
     }
-    pos += f[i];
+    pos += fi;
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    int total = prefix + wg_total;
-    int stored = total < cap ? total : cap;
+    const int total = prefix + wg_total;
+    const int stored = total < cap ? total : cap;
     counts->n_sites = stored;
     counts->n_sites_needed = total;
     counts->n_pairs = 0;
@@ -215,9 +237,19 @@ __global__ __launch_bounds__(256) void rulebook_pairs_kernel(const npvs_counts *
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Blocks per thread of the site kernels and whether the 32-froxel span path applies.
+static void sites_shape(const Batch &B, int *bpt, int *fast) {
+  bool all32 = B.d <= 32;
+  for (int b = 0; b < B.n; ++b) all32 = all32 && (B.g[b].nx % 32 == 0);
+  *fast = all32 ? 1 : 0;
+  *bpt = all32 ? 32 / B.d : 4;
+}
+
 static void rb_ws_layout(const Batch &B, int32_t cap, size_t *o_wg, size_t *o_cc, size_t *o_co, size_t *bytes,
                          int *n_wg, int *n_chunks) {
-  *n_wg = (B.total_blocks + kSitesPerWG - 1) / kSitesPerWG;
+  int bpt, fast;
+  sites_shape(B, &bpt, &fast);
+  *n_wg = (B.total_blocks + 256 * bpt - 1) / (256 * bpt);
   *n_chunks = (cap + kRowsPerChunk - 1) / kRowsPerChunk;
   size_t o = 0;
   *o_wg = o;
@@ -268,8 +300,11 @@ extern "C" npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_gr
   int32_t *chunk_counts = reinterpret_cast<int32_t *>(w + o_cc);
   int32_t *chunk_off = reinterpret_cast<int32_t *>(w + o_co);
   hipStream_t s = as_stream(stream);
-  sites_count_kernel<<<n_wg, 256, 0, s>>>(B, occ_bits, wg_counts);
-  sites_write_kernel<<<n_wg, 256, 0, s>>>(B, occ_bits, wg_counts, cap_sites, counts, site_keys, block_row, grid_rows);
+  int bpt, fast;
+  sites_shape(B, &bpt, &fast);
+  sites_count_kernel<<<n_wg, 256, 0, s>>>(B, occ_bits, bpt, fast, wg_counts);
+  sites_write_kernel<<<n_wg, 256, 0, s>>>(B, occ_bits, bpt, fast, wg_counts, cap_sites, counts, site_keys, block_row,
+                                          grid_rows);
   dim3 g(stride_grid(cap_sites, kRowsPerChunk, 512), 27);
   rulebook_nbr_kernel<<<g, 256, 0, s>>>(B, site_keys, block_row, counts, cap_sites, nbr,
                                         rb_off ? chunk_counts : nullptr, n_chunks);

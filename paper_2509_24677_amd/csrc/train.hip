@@ -25,7 +25,7 @@ struct Comp {
   }
 };
 
-constexpr int kLossSlices = 64;
+constexpr int kLossSlices = 256;
 constexpr int kLossQ = 5;  // BCE sum, TP, FN, FP, GTP
 
 __device__ __forceinline__ float sigmoidf_(float l) { return 1.0f / (1.0f + expf(-l)); }

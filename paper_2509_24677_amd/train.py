@@ -30,6 +30,7 @@ class Network:
         self.channels = [self.W[0].shape[1]] + [w.shape[2] for w in self.W]
         self.Wp = [None] * len(self.W)
         self.Wt = [None] * len(self.W)
+        self.variant = [None] * len(self.W)  # BF16 tile shape per layer (None = library default)
         self.repack()
 
     @property
@@ -48,7 +49,40 @@ class Network:
     def layer(self, i: int, X: torch.Tensor, rb: Rulebook) -> torch.Tensor:
         last = i == self.n_layers - 1
         return sparse_conv_fwd(X, self.Wp[i], self.b[i], self.channels[i], self.channels[i + 1], rb, self.dtype,
-                               relu=not last, out_f32=last)
+                               relu=not last, out_f32=last, variant=self.variant[i])
+
+    def autotune(self, X0: torch.Tensor, rb: Rulebook, reps: int = 20):
+        """Times every BF16 tile shape of each distinct layer shape on the rulebook `rb` (HIP events
+        on the current stream) and keeps the fastest.  Synchronizes."""
+        if self.dtype != NPVS_BF16:
+            return self.variant
+        from ._lib import NPVS_CONV_VARIANTS
+        chosen = {}
+        X = X0
+        for i in range(self.n_layers):
+            last = i == self.n_layers - 1
+            key = (self.channels[i], self.channels[i + 1], last)
+            if key not in chosen:
+                out = self.layer(i, X, rb)
+                best = None
+                for v in range(NPVS_CONV_VARIANTS):
+                    self.variant[i] = v
+                    self.layer(i, X, rb)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        sparse_conv_fwd(X, self.Wp[i], self.b[i], self.channels[i], self.channels[i + 1], rb,
+                                        self.dtype, relu=not last, out_f32=last, out=out, variant=v)
+                    e1.record()
+                    e1.synchronize()
+                    t = e0.elapsed_time(e1)
+                    if best is None or t < best[0]:
+                        best = (t, v)
+                chosen[key] = best[1]
+            self.variant[i] = chosen[key]
+            X = self.layer(i, X, rb)
+        torch.cuda.synchronize()
+        return list(self.variant)
 
     def forward(self, X0: torch.Tensor, rb: Rulebook, checkpoint: bool = False):
         """Returns (logits float32 [cap][d^3], saved inputs: dict layer -> input tensor)."""

@@ -70,14 +70,26 @@ def test_froxelize_adversarial_and_batched():
 
 
 def test_froxelize_tile_overflow_falls_back_to_full_scan():
-    # more than 1024 triangles inside one 128x8x8 tile
+    # more than 2048 triangles inside one 128x8x8 tile
     rng = np.random.default_rng(3)
-    c = rng.uniform(1, 7, size=(1500, 1, 3)) * np.array([10.0, 1, 1])
-    t = (c + rng.uniform(-0.7, 0.7, size=(1500, 3, 3))).astype(np.float32)
+    c = rng.uniform(1, 7, size=(2600, 1, 3)) * np.array([10.0, 1, 1])
+    t = (c + rng.uniform(-0.7, 0.7, size=(2600, 3, 3))).astype(np.float32)
     dims = [(128, 16, 16)]
     tris, counts = upload_tris([t])
     occ = npvs.froxelize(tris, counts, dims)
     np.testing.assert_array_equal(to_np(occ), oracle.froxelize(t, dims[0])[0].reshape(-1))
+
+
+def test_froxelize_parts_of_one_tile():
+    # 300 to 2000 triangles in one tile are split over several 256-triangle parts
+    rng = np.random.default_rng(4)
+    for n in (300, 1100, 2000):
+        c = rng.uniform(1, 7, size=(n, 1, 3)) * np.array([16.0, 1, 1])
+        t = (c + rng.uniform(-0.9, 0.9, size=(n, 3, 3))).astype(np.float32)
+        dims = [(256, 16, 8)]
+        tris, counts = upload_tris([t])
+        occ = npvs.froxelize(tris, counts, dims)
+        np.testing.assert_array_equal(to_np(occ), oracle.froxelize(t, dims[0])[0].reshape(-1))
 
 
 def test_froxelize_empty_and_all_ignored():
@@ -202,6 +214,44 @@ def test_conv_fwd_bf16_mfma(cin, cout, variant_rows):
     # bf16 output: the float32 result rounded to nearest even
     Yb = npvs.sparse_conv_fwd(Xb, Wp, torch.from_numpy(b).to(DEV), cin, cout, rb, npvs.NPVS_BF16, True)
     np.testing.assert_array_equal(to_np(Yb)[:n], to_np(Y[:n].to(torch.bfloat16)))
+
+
+@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("cin,cout,d", [(64, 64, 2), (16, 8, 2), (512, 64, 8)])
+def test_conv_fwd_bf16_every_tile_shape(variant, cin, cout, d):
+    rb, ref, X, W, b = _conv_case(cin, cout, d=d, dims=((64, 64, 64), (32, 32, 32)))
+    n = ref["n"]
+    Xb = torch.from_numpy(X).to(DEV).to(torch.bfloat16)
+    Wp = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_BF16)
+    Y = npvs.sparse_conv_fwd(Xb, Wp, torch.from_numpy(b).to(DEV), cin, cout, rb, npvs.NPVS_BF16, True, out_f32=True,
+                             variant=variant)
+    Xr, Wr = bf16_round(X[:n]), bf16_round(W)
+    want = oracle.subm_conv(Xr, Wr, b, ref["rb_off"], ref["pairs"], True)
+    tol = conv_tolerance(Xr, Wr, ref["rb_off"], ref["pairs"])
+    err = np.abs(to_np(Y)[:n] - want)
+    assert (err <= tol).all(), err.max()
+    # deterministic run to run
+    Y2 = npvs.sparse_conv_fwd(Xb, Wp, torch.from_numpy(b).to(DEV), cin, cout, rb, npvs.NPVS_BF16, True, out_f32=True,
+                              variant=variant)
+    np.testing.assert_array_equal(to_np(Y)[:n], to_np(Y2)[:n])
+
+
+def test_plan_autotune_picks_valid_shapes_and_keeps_results():
+    cfg = synth.config("city256")
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg)
+    tris, counts = upload_tris([t])
+    plan = npvs.Plan(cfg.grids, counts, cfg.d, cfg.channels, npvs.NPVS_BF16)
+    for li, (W, b) in enumerate(layers):
+        plan.set_weights(li, torch.from_numpy(W).to(DEV), torch.from_numpy(b).to(DEV))
+    v = plan.autotune(tris, reps=3)
+    print("autotuned variants", v, flush=True)
+    assert len(v) == 6 and all(0 <= x < 6 for x in v) and len(set(v[:5])) == 1
+    pvs, logits = plan.forward(tris, want_logits=True)
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers)
+    got = to_np(logits).reshape(out["logits"].shape)
+    act = np.isfinite(out["logits"])
+    assert np.abs(got[act] - out["logits"][act]).max() < 0.1
 
 
 def test_conv_weight_packing_flip_transpose_is_dgrad_weight():
