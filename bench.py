@@ -224,10 +224,11 @@ def main():
     conv_ms = float(np.mean(stage["conv_fwd_bf16"]))
     flops = 2.0 * n_pairs * 64 * 64
     achieved = flops / (conv_ms * 1e-3) / 1e12
-    mb_ks = {0: (1, 9), 1: (2, 1), 2: (1, 3), 3: (2, 3), 4: (1, 1), 5: (2, 9)}[net_b.variant[1]]
+    shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
+              6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>"}
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
-                "kernel": f"conv_fwd_bf16_kernel<2,4,{mb_ks[0]},{mb_ks[1]}>", "avg_launch_ms": conv_ms,
+                "kernel": "conv_fwd_bf16" + shapes[net_b.variant[1]], "avg_launch_ms": conv_ms,
                 "algorithmic_flops_per_launch": flops, "autotuned_variants": net_b.variant}
     conv32_ms = float(np.mean(stage["conv_fwd_fp32"]))
     roofline_fp32 = {"achieved": flops / (conv32_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -156,11 +156,13 @@ npvs_status npvs_pack_weights(const float *W, int32_t cin, int32_t cout, int32_t
 npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                  const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                  int32_t relu, int32_t out_f32, void *Y, void *stream);
-/* Same, with an explicit BF16 tile shape `variant` in [0, NPVS_CONV_VARIANTS): (rows per wave,
- * waves sharing the 27 offsets of a tile) = 0 (16, 9), 1 (32, 1), 2 (16, 3), 3 (32, 3),
- * 4 (16, 1), 5 (32, 9).  All variants give results within float32 rounding of each other; each
- * one is deterministic.  Ignored by the FP32 path. */
-#define NPVS_CONV_VARIANTS 6
+/* Same, with an explicit BF16 tile shape `variant` in [0, NPVS_CONV_VARIANTS).  Variants 0-5
+ * split a tile's 27 offsets over several waves, (rows per wave, waves) = 0 (16, 9), 1 (32, 1),
+ * 2 (16, 3), 3 (32, 3), 4 (16, 1), 5 (32, 9); variants 6-9 give each wave its own rows and all
+ * offsets and share each offset's weights through LDS, (rows per wave, waves) = 6 (16, 4),
+ * 7 (16, 2), 8 (32, 2), 9 (16, 8).  All variants give results within float32 rounding of each
+ * other; each one is deterministic.  Ignored by the FP32 path. */
+#define NPVS_CONV_VARIANTS 10
 npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                     const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                     int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);

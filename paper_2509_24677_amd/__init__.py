@@ -179,8 +179,10 @@ def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None
     return out
 
 
-def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int, relu: bool, want_dx: bool = True):
-    """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout])."""
+def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int, relu: bool, want_dx: bool = True,
+                    dW: torch.Tensor | None = None, db: torch.Tensor | None = None):
+    """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout]).
+    dW / db may be given (contiguous float32 device tensors) to receive the gradients in place."""
     if rb.rb_off is None:
         raise ValueError("the backward needs a rulebook built with csr=True")
     dev = X.device
@@ -188,8 +190,12 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
     L.call("npvs_conv_bwd_workspace_size", cin, cout, rb.cap, dtype, ctypes.byref(nbytes))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     dX = torch.empty((rb.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
-    dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
-    db = torch.empty(cout, dtype=torch.float32, device=dev)
+    if dW is None:
+        dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
+    if db is None:
+        db = torch.empty(cout, dtype=torch.float32, device=dev)
+    if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
+        raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
     L.call("npvs_sparse_conv_bwd", _p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off),
            _p(rb.rb_pairs), _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), nbytes.value,
            _stream())

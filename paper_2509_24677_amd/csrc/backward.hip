@@ -4,7 +4,7 @@
 //        roles of input and output swapped), so the data gradient is a forward convolution;
 //   dW_k = sum_{(i,r) in R_k} X[i]^T dZ[r]: per-offset reduced outer products over the CSR
 //        pair list, cut into a fixed number of slices per offset and reduced in a fixed order;
-//   db = sum_r dZ[r], accumulated by the slices of the centre offset (whose pairs are (r, r)).
+//   db = sum_r dZ[r], from per-row-block partial sums written while dZ is formed.
 // Every float32 reduction adds short plain partial sums into a Neumaier-compensated total, and
 // all reduction orders are fixed, so gradients are bit-identical run to run.
 #include "npvs_common.hpp"
@@ -31,17 +31,37 @@ struct Comp {  // Neumaier-compensated float sum
 __device__ __forceinline__ float load_as_f32(const float *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float load_as_f32(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
 
-// dZ in float32 (for wgrad/db) and, for the BF16 path, a bfloat16 copy (MFMA operand).
+constexpr int kDbBlocks = 32;  // row blocks of the bias-gradient partial sums
+
+// dZ in float32 (for wgrad) and, for the BF16 path, a bfloat16 copy (MFMA operand), plus the
+// bias-gradient partial of this block's rows: grid kDbBlocks, 256 threads, C <= 64.  Thread t
+// owns column t % C of the rows r = r0 + t / C (mod 256 / C); the row groups are combined in LDS
+// in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y, const float *__restrict__ dY,
                                                          const npvs_counts *__restrict__ counts, int C, int relu,
-                                                         float *__restrict__ dZ32, uint16_t *__restrict__ dZ16) {
-  const int64_t total = (int64_t)counts->n_sites * C;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    float g = dY[e];
-    if (relu && !(load_as_f32(Y, e) > 0.0f)) g = 0.0f;
-    dZ32[e] = g;
-    if (dZ16) dZ16[e] = f32_to_bf16(g);
+                                                         float *__restrict__ dZ32, uint16_t *__restrict__ dZ16,
+                                                         float *__restrict__ dbpart) {
+  __shared__ float red[256];
+  const int64_t n = counts->n_sites;
+  const int64_t r0 = n * blockIdx.x / kDbBlocks, r1 = n * (blockIdx.x + 1) / kDbBlocks;
+  const int c = threadIdx.x % C, rg = threadIdx.x / C, RG = 256 / C;
+  Comp a{0.0f, 0.0f};
+  if (rg < RG)
+    for (int64_t r = r0 + rg; r < r1; r += RG) {
+      const int64_t e = r * C + c;
+      float g = dY[e];
+      if (relu && !(load_as_f32(Y, e) > 0.0f)) g = 0.0f;
+      dZ32[e] = g;
+      if (dZ16) dZ16[e] = f32_to_bf16(g);
+      a.add(g);
+    }
+  red[threadIdx.x] = a.value();
+  __syncthreads();
+  if (threadIdx.x < C) {
+    Comp t{0.0f, 0.0f};
+    for (int g = 0; g < RG; ++g) t.add(red[g * C + threadIdx.x]);
+    dbpart[blockIdx.x * C + threadIdx.x] = t.value();
   }
 }
 
@@ -49,28 +69,13 @@ constexpr int kWgSlices = 16;  // slices of each offset's pair list
 constexpr int kWgPairs = 32;   // pairs staged per step (vector path)
 constexpr int kWgEPT = 16;     // dW entries per thread per pass (vector path)
 
-// Centre offset: db partial of this slice, db[o] += sum over the slice's rows of dZ[r][o].
-__device__ __forceinline__ void db_slice(const float *__restrict__ dZ, int cout, const int32_t *__restrict__ pairs,
-                                         int64_t p0, int64_t p1, float *__restrict__ dbpart, int s) {
-  for (int o = threadIdx.x; o < cout; o += blockDim.x) {
-    Comp a{0.0f, 0.0f};
-    for (int64_t p = p0; p < p1; p += 32) {
-      const int64_t pe = p + 32 < p1 ? p + 32 : p1;
-      float t = 0.0f;
-      for (int64_t q = p; q < pe; ++q) t += dZ[(int64_t)pairs[2 * q + 1] * cout + o];
-      a.add(t);
-    }
-    dbpart[s * cout + o] = a.value();
-  }
-}
-
 // Vector FP32 path: grid (kWgSlices, 27), 256 threads.  Partial dW of offset k over slice s.
 template <typename T>
 __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict__ X, int cin,
                                                              const float *__restrict__ dZ, int cout,
                                                              const int32_t *__restrict__ rb_off,
                                                              const int32_t *__restrict__ pairs,
-                                                             float *__restrict__ part, float *__restrict__ dbpart) {
+                                                             float *__restrict__ part) {
   __shared__ float Xs[kWgPairs][65];
   __shared__ float Gs[kWgPairs][64];
   __shared__ int in_s[kWgPairs], out_s[kWgPairs];
@@ -118,7 +123,6 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
       }
     }
   }
-  if (k == 13) db_slice(dZ, cout, pairs, p0, p1, dbpart, s);
 }
 
 // BF16 path on MFMA.  grid (kWgSlices, 27), 256 threads = 4 waves; cin, cout <= 64.
@@ -135,10 +139,9 @@ constexpr int kWgPitch = kWgChunk + 8;  // bf16 elements per LDS row (padding sp
 
 __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restrict__ X, int cin,
                                                           const uint16_t *__restrict__ dZ16,
-                                                          const float *__restrict__ dZ32, int cout,
-                                                          const int32_t *__restrict__ rb_off,
+                                                          int cout, const int32_t *__restrict__ rb_off,
                                                           const int32_t *__restrict__ pairs,
-                                                          float *__restrict__ part, float *__restrict__ dbpart) {
+                                                          float *__restrict__ part) {
   __shared__ __attribute__((aligned(16))) uint16_t XT[64 * kWgPitch];
   __shared__ __attribute__((aligned(16))) uint16_t GT[64 * kWgPitch];
   __shared__ int in_s[kWgChunk], out_s[kWgChunk];
@@ -226,7 +229,6 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
       }
     }
   }
-  if (k == 13) db_slice(dZ32, cout, pairs, p0, p1, dbpart, s);
 }
 
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
       dW[e] = a.value();
     } else {
       int o = (int)(e - 27 * E);
-      for (int s = 0; s < kWgSlices; ++s) a.add(dbpart[s * cout + o]);
+      for (int s = 0; s < kDbBlocks; ++s) a.add(dbpart[s * cout + o]);
       db[o] = a.value();
     }
   }
@@ -260,7 +262,7 @@ static void bwd_ws_layout(int32_t cin, int32_t cout, int32_t cap, int32_t dtype,
   *o_wp = o;
   o += align256(sizeof(float) * 27 * kWgSlices * (size_t)cin * cout);
   *o_dbp = o;
-  o += align256(sizeof(float) * kWgSlices * (size_t)cout);
+  o += align256(sizeof(float) * kDbBlocks * (size_t)cout);
   *bytes = o;
 }
 
@@ -299,11 +301,11 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   float *wpart = reinterpret_cast<float *>(w + owp);
   float *dbpart = reinterpret_cast<float *>(w + odb);
   hipStream_t s = as_stream(stream);
-  const int g_el = stride_grid((int64_t)cap_sites * cout, 256, 4096);
   if (dtype == NPVS_F32)
-    relu_grad_kernel<float><<<g_el, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, dZ32, nullptr);
+    relu_grad_kernel<float><<<kDbBlocks, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, dZ32, nullptr, dbpart);
   else
-    relu_grad_kernel<uint16_t><<<g_el, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, dZ32, dZ16);
+    relu_grad_kernel<uint16_t><<<kDbBlocks, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, dZ32, dZ16,
+                                                          dbpart);
   npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
   if (st != NPVS_OK) return st;
   if (dX) {
@@ -313,12 +315,11 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   }
   dim3 gw(kWgSlices, 27);
   if (dtype == NPVS_F32)
-    wgrad_partial_kernel<float><<<gw, 256, 0, s>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart, dbpart);
+    wgrad_partial_kernel<float><<<gw, 256, 0, s>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
   else if (cin <= 64)
-    wgrad_bf16_kernel<<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ16, dZ32, cout, rb_off, rb_pairs, wpart, dbpart);
+    wgrad_bf16_kernel<<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
   else
-    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart,
-                                                      dbpart);
+    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
   grad_reduce_kernel<<<stride_grid(27LL * cin * cout + cout, 256, 2048), 256, 0, s>>>(wpart, dbpart, cin, cout, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
 }

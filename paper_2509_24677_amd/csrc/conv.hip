@@ -264,9 +264,120 @@ __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16
   }
 }
 
-// Tile shapes (MB, KSPLIT) = (rows per wave / 16, waves sharing the 27 offsets of a tile):
-// variant 0 (1, 9), 1 (2, 1), 2 (1, 3), 3 (2, 3), 4 (1, 1), 5 (2, 9).  Inputs wider than 64
-// channels use only the 9-way split (a long unrolled offset loop would not fit the registers).
+// Shared-weight variant: the RG waves of a workgroup own different rows (16 MB each) and all 27
+// offsets; each offset's packed weights are staged once per workgroup into a double-buffered LDS
+// slot (loaded into registers one offset ahead, stored after the current offset's MFMAs), so the
+// L2 reads of weights drop by a factor of RG.  The neighbour rows are gathered straight from
+// global memory one offset ahead as in the split kernel.
+template <int KB, int NB, int MB, int RG>
+__global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16_t *__restrict__ X, int cin,
+                                                                     const bf16x8_t *__restrict__ Wp,
+                                                                     const float *__restrict__ bias, int cout,
+                                                                     const int32_t *__restrict__ nbr,
+                                                                     const npvs_counts *__restrict__ counts, int cap,
+                                                                     int relu, int out_f32, void *__restrict__ Y) {
+  constexpr int ROWS = 16 * MB * RG;
+  constexpr int FR = NB * KB;                 // weight fragments of one offset (64 lanes x 16 bytes each)
+  constexpr int WPT = (FR + RG - 1) / RG;     // fragments each thread stages per offset (some idle)
+  __shared__ bf16x8_t Ws[2][FR * 64];
+  const int32_t n = counts->n_sites;
+  const int ntiles = (n + ROWS - 1) / ROWS;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int csub = 8 * (lane >> 4);
+  const bf16x8_t zero8 = {};
+  for (int j = 0;; ++j) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
+    if (tile < 0) break;
+    const int row0 = tile * ROWS + wv * 16 * MB;
+    int idx[27][MB];
+#pragma unroll
+    for (int q = 0; q < 27; ++q)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int r = row0 + mb * 16 + (lane & 15);
+        idx[q][mb] = r < n ? nbr[(int64_t)q * cap + r] : -1;
+      }
+    f32x4_t acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8_t wreg[WPT], bx[2][MB][KB];
+    // prologue: offset 0's weights into LDS slot 0, its rows into registers
+#pragma unroll
+    for (int i = 0; i < WPT; ++i)
+      if (tid + i * 64 * RG < FR * 64) Ws[0][tid + i * 64 * RG] = Wp[tid + i * 64 * RG];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int c = kb * 32 + csub;
+        bx[0][mb][kb] = (idx[0][mb] >= 0 && c < cin)
+                            ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[0][mb] * cin + c)
+                            : zero8;
+      }
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const int cur = k & 1, nxt = (k + 1) & 1;
+      if (k + 1 < 27) {  // loads of offset k + 1
+#pragma unroll
+        for (int i = 0; i < WPT; ++i)
+          if (tid + i * 64 * RG < FR * 64) wreg[i] = Wp[(int64_t)(k + 1) * FR * 64 + tid + i * 64 * RG];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const int c = kb * 32 + csub;
+            bx[nxt][mb][kb] = (idx[k + 1][mb] >= 0 && c < cin)
+                                  ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[k + 1][mb] * cin + c)
+                                  : zero8;
+          }
+      }
+      __syncthreads();  // slot cur holds offset k's weights; slot nxt is no longer read
+      bool a = false;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) a = a || idx[k][mb] >= 0;
+      if (__any(a)) {
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const bf16x8_t aw = Ws[cur][(nb * KB + kb) * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[cur][mb][kb], acc[mb][nb], 0, 0, 0);
+          }
+      }
+      if (k + 1 < 27) {
+#pragma unroll
+        for (int i = 0; i < WPT; ++i)
+          if (tid + i * 64 * RG < FR * 64) Ws[nxt][tid + i * 64 * RG] = wreg[i];
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        conv_bf16_epilogue<NB>(acc[mb][nb], row0 + mb * 16 + (lane & 15), n, nb * 16 + 4 * (lane >> 4), cout, bias,
+                               relu, out_f32, Y);
+    __syncthreads();  // the next tile's prologue rewrites slot 0
+  }
+}
+
+template <int KB, int NB, int MB, int RG>
+static void launch_bf16_lds(const void *X, int cin, const void *Wp, const float *bias, int cout, const int32_t *nbr,
+                            const npvs_counts *counts, int cap, int relu, int out_f32, void *Y, hipStream_t s) {
+  int G = stride_grid(cap, 16 * MB * RG, 4096);
+  G = (G + 7) & ~7;
+  conv_fwd_bf16_lds_kernel<KB, NB, MB, RG><<<G, 64 * RG, 0, s>>>(
+      (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+// Tile shapes.  Split kernel (MB, KSPLIT) = (rows per wave / 16, waves sharing the 27 offsets of a
+// tile): variant 0 (1, 9), 1 (2, 1), 2 (1, 3), 3 (2, 3), 4 (1, 1), 5 (2, 9).  Shared-weight kernel
+// (MB, RG) = (rows per wave / 16, waves per workgroup): 6 (1, 4), 7 (1, 2), 8 (2, 2), 9 (1, 8).
+// Inputs wider than 64 channels use only the 9-way split (a long unrolled offset loop would not
+// fit the registers, nor a double-buffered offset of weights the LDS).
 // kDefaultConvVariant is used by npvs_sparse_conv_fwd; the autotuner can pick another per layer.
 
 template <int KB, int NB, int MB, int KSPLIT>
@@ -295,7 +406,11 @@ static void launch_bf16_variant(int v, const void *X, int cin, const void *Wp, c
       case 2: launch_bf16<KB, NB, 1, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
       case 3: launch_bf16<KB, NB, 2, 3>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
       case 4: launch_bf16<KB, NB, 1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
-      default: launch_bf16<KB, NB, 2, 9>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 5: launch_bf16<KB, NB, 2, 9>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 6: launch_bf16_lds<KB, NB, 1, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 7: launch_bf16_lds<KB, NB, 1, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 8: launch_bf16_lds<KB, NB, 2, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      default: launch_bf16_lds<KB, NB, 1, 8>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
     }
   }
 }

@@ -4,35 +4,44 @@
 // (round half to even) and overlap is decided by the separating-axis theorem in exact integer
 // arithmetic, so the result does not depend on triangle order or on the schedule.
 //
-// Four launches:
-//   1. zero the per-tile triangle counters;
-//   2. bin: one thread per triangle quantizes it, clips its froxel range and appends it to the
-//      list of every tile (128 x 8 x 8 froxels) the range meets; lanes of a wave that append to
-//      the same tile share one counter update;
-//   3. part: the bin kernel opens a part for every 256 triangles appended to a tile; workgroups
-//      take parts from that list, one thread per triangle; each thread tests the froxels of its
-//      triangle's range inside the tile and ORs the hits into the tile's 64 x 128-bit mask in
-//      LDS; the part's mask is stored once;
-//   4. merge: one thread per 32-froxel word ORs the parts of its tile and writes the word.
+// Five launches:
+//   1. zero the per-tile triangle counters and the part counter;
+//   2. bin: one thread per triangle quantizes it, clips its froxel range, computes the constants
+//      of its separating-axis test once, and appends it to the list of every tile (32 x 8 x 8
+//      froxels) the range meets; lanes of a wave that append to the same tile share one counter
+//      update;
+//   3. plan: one workgroup scans the tiles' counts into a list of parts (256 listed triangles each);
+//   4. part: workgroups take parts from the list, one thread per triangle; each thread tests the
+//      froxels of its triangle's range inside the tile and ORs the hits into the tile's 64-word
+//      mask in LDS; the part's mask is stored once;
+//   5. merge: one thread per 32-froxel word ORs the parts of its tile and writes the word.
 // The output is written once per word, with no global atomics.  A tile whose list overflowed
 // (more than 2048 triangles) is covered by 16 parts that together scan all triangles of its grid.
 #include "npvs_common.hpp"
 
 namespace npvs {
 
-struct TriRec {
-  int32_t q[9];     // fixed-point vertices v0, v1, v2 (x, y, z)
-  int16_t lo[3];    // clipped froxel range; lo > hi when empty or ignored
-  int16_t hi[3];
+// Constants of one triangle's overlap test.  For an axis a the closed froxel I = (i, j, k) meets
+// the triangle along a iff L <= a . I <= H.  The axes are the triangle normal n and the nine
+// cross products of the edges e_i with the box axes (e x x = (0, e_z, -e_y), e x y = (-e_z, 0, e_x),
+// e x z = (e_y, -e_x, 0)); the box normals are the clipped froxel range.  With |v| < 1024 the
+// edge-axis bounds and projections fit int32.
+struct TriSetup {
+  int64_t n[3];          // normal (fixed-point cross product of two edges)
+  int64_t nL, nH;        // normal-axis bounds
+  int32_t e[3][3];       // edges e_i = v_{i+1} - v_i
+  int32_t L[3][3];       // [edge][box axis]
+  int32_t H[3][3];
+  int16_t lo[3], hi[3];  // clipped froxel range; lo > hi when empty or ignored
 };
-static_assert(sizeof(TriRec) == 48, "record layout");
+static_assert(sizeof(TriSetup) % 16 == 0, "setup record is loaded as 16-byte words");
 
 constexpr int kPartTris = 256;                          // triangles of a listed part
 constexpr int kListedParts = kFroxTileCap / kPartTris;  // parts of a tile whose list did not overflow
 constexpr int kMaxParts = 16;                           // parts of a tile that scans its whole grid
 static_assert(kListedParts <= kMaxParts, "part indices");
-constexpr int kTileWords = (kFroxTileX / 32) * kFroxTileY * kFroxTileZ;  // 256
-static_assert(kTileWords == 256, "one merge thread per tile word");
+constexpr int kTileWords = (kFroxTileX / 32) * kFroxTileY * kFroxTileZ;  // 64
+static_assert(kFroxTileX == 32 && kTileWords == 64, "one 32-froxel word per tile row");
 
 __global__ void frox_zero_kernel(int32_t *p, int n, int32_t *n_parts) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
@@ -45,105 +54,9 @@ __device__ __forceinline__ int tri_grid(const Batch &B, int64_t t) {
   return b;
 }
 
-__global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__ tris, Batch B, int64_t total,
-                                                        TriRec *__restrict__ recs, int32_t *__restrict__ tile_count,
-                                                        int32_t *__restrict__ tile_list, int32_t *__restrict__ part_list,
-                                                        int32_t *__restrict__ n_parts) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool valid_t = t < total;
-  int ntl = 0, tx0 = 0, ty0 = 0, tz0 = 0, ntx = 1, nty = 1, toff = 0, tys = 1, txs = 1;
-  if (valid_t) {
-    const GridDesc &g = B.g[tri_grid(B, t)];
-    TriRec r;
-    bool ok = true;
-    int32_t mn[3], mx[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = 0x7fffffff;
-      mx[a] = -0x7fffffff;
-    }
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float x = tris[t * 9 + v * 3 + a];
-        ok = ok && (__builtin_fabsf(x) < (float)NPVS_MAX_DIM);  // finite and |x| < 1024 (NaN fails)
-        int32_t q = ok ? (int32_t)__builtin_rintf(x * 256.0f) : 0;  // exact scaling, round half to even
-        r.q[v * 3 + a] = q;
-        mn[a] = q < mn[a] ? q : mn[a];
-        mx[a] = q > mx[a] ? q : mx[a];
-      }
-    int32_t dims[3] = {g.nx, g.ny, g.nz};
-    int32_t lo[3], hi[3];
-    bool empty = !ok;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      // closed cells [256 i, 256 i + 256] meeting [mn, mx]: i in [floor((mn-1)/256), floor(mx/256)]
-      lo[a] = (mn[a] - 1) >> 8;
-      hi[a] = mx[a] >> 8;
-      lo[a] = lo[a] < 0 ? 0 : lo[a];
-      hi[a] = hi[a] > dims[a] - 1 ? dims[a] - 1 : hi[a];
-      empty = empty || lo[a] > hi[a];
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      r.lo[a] = (int16_t)(empty ? 1 : lo[a]);
-      r.hi[a] = (int16_t)(empty ? 0 : hi[a]);
-    }
-    recs[t] = r;
-    if (!empty) {
-      tx0 = lo[0] / kFroxTileX;
-      ty0 = lo[1] / kFroxTileY;
-      tz0 = lo[2] / kFroxTileZ;
-      ntx = hi[0] / kFroxTileX - tx0 + 1;
-      nty = hi[1] / kFroxTileY - ty0 + 1;
-      int ntz = hi[2] / kFroxTileZ - tz0 + 1;
-      ntl = ntx * nty * ntz;
-      toff = g.tile_off;
-      txs = g.tiles_x;
-      tys = g.tiles_y;
-    }
-  }
-  // Append to each covered tile; lanes targeting the same tile in a round share one atomic.
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int j = 0;; ++j) {
-    const bool active = j < ntl;
-    if (__ballot(active) == 0ull) break;
-    int tile = -1;
-    if (active) {
-      int ix = j % ntx, iy = (j / ntx) % nty, iz = j / (ntx * nty);
-      tile = toff + ((tz0 + iz) * tys + (ty0 + iy)) * txs + (tx0 + ix);
-    }
-    uint64_t pending = __ballot(active);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int lt = __shfl(tile, leader, 64);
-      const uint64_t same = __ballot(active && tile == lt);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&tile_count[lt], __popcll(same));
-      base = __shfl(base, leader, 64);
-      if (active && tile == lt) {
-        const int slot = base + __popcll(same & below);
-        if (slot < kFroxTileCap) {
-          tile_list[(int64_t)lt * kFroxTileCap + slot] = (int32_t)t;
-          if (slot % kPartTris == 0)  // this append opens a new part of the tile
-            part_list[atomicAdd(n_parts, 1)] = lt * kMaxParts + slot / kPartTris;
-        } else if (slot == kFroxTileCap) {  // the list overflowed: add the remaining scan parts
-          const int p0 = atomicAdd(n_parts, kMaxParts - kListedParts);
-          for (int i = 0; i < kMaxParts - kListedParts; ++i) part_list[p0 + i] = lt * kMaxParts + kListedParts + i;
-        }
-      }
-      pending &= ~same;
-    }
-  }
-}
-
-// Axis bounds of the exact overlap test.  For an axis a, the closed froxel I = (i, j, k) meets
-// the triangle along a iff L <= a . I <= H, with
-//   L = ceil((min_v a.q_v - 256 sum_c max(0, a_c)) / 256),  H = floor((max_v a.q_v - 256 sum_c min(0, a_c)) / 256)
-// since the box [256 I, 256 I + 256] projects onto [256 a.I + R-, 256 a.I + R+].  A zero axis
-// gives L = H = 0 = a . I and never separates.
+// L = ceil((min_v a.q_v - 256 sum_c max(0, a_c)) / 256), H = floor((max_v a.q_v - 256 sum_c min(0, a_c)) / 256):
+// the box [256 I, 256 I + 256] projects onto [256 a.I + R-, 256 a.I + R+].  A zero axis gives
+// L = H = 0 = a . I and never separates.
 __device__ __forceinline__ void axis_bounds(int64_t a0, int64_t a1, int64_t a2, const int32_t *q, int64_t &L,
                                             int64_t &H) {
   int64_t p0 = a0 * q[0] + a1 * q[1] + a2 * q[2];
@@ -158,76 +71,157 @@ __device__ __forceinline__ void axis_bounds(int64_t a0, int64_t a1, int64_t a2, 
   H = (pmax - rm) >> 8;
 }
 
-// ORs the froxels of triangle r inside the tile with origin (X0, Y0, Z0) into the LDS mask
-// (word (z - Z0) * 32 + (y - Y0) * 4 + (x - X0) / 32, bit (x - X0) % 32).
-__device__ __forceinline__ void frox_triangle(const TriRec &r, int X0, int Y0, int Z0, uint32_t *mask) {
-  const int xa = r.lo[0] > X0 ? r.lo[0] : X0, xb = r.hi[0] < X0 + kFroxTileX - 1 ? r.hi[0] : X0 + kFroxTileX - 1;
-  const int ya = r.lo[1] > Y0 ? r.lo[1] : Y0, yb = r.hi[1] < Y0 + kFroxTileY - 1 ? r.hi[1] : Y0 + kFroxTileY - 1;
-  const int za = r.lo[2] > Z0 ? r.lo[2] : Z0, zb = r.hi[2] < Z0 + kFroxTileZ - 1 ? r.hi[2] : Z0 + kFroxTileZ - 1;
-  if (xa > xb || ya > yb || za > zb) return;
-  const int32_t *q = r.q;
+__device__ __forceinline__ void make_setup(const int32_t *q, TriSetup &S) {
   int32_t e[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) e[i][c] = q[((i + 1) % 3) * 3 + c] - q[i * 3 + c];
-  const int64_t n0 = (int64_t)e[0][1] * e[1][2] - (int64_t)e[0][2] * e[1][1];
-  const int64_t n1 = (int64_t)e[0][2] * e[1][0] - (int64_t)e[0][0] * e[1][2];
-  const int64_t n2 = (int64_t)e[0][0] * e[1][1] - (int64_t)e[0][1] * e[1][0];
-  int64_t nL, nH, L, H;
-  axis_bounds(n0, n1, n2, q, nL, nH);
-  int32_t Lx[3], Hx[3], Ly[3], Hy[3], Lz[3], Hz[3];
+    for (int c = 0; c < 3; ++c) {
+      e[i][c] = q[((i + 1) % 3) * 3 + c] - q[i * 3 + c];
+      S.e[i][c] = e[i][c];
+    }
+  S.n[0] = (int64_t)e[0][1] * e[1][2] - (int64_t)e[0][2] * e[1][1];
+  S.n[1] = (int64_t)e[0][2] * e[1][0] - (int64_t)e[0][0] * e[1][2];
+  S.n[2] = (int64_t)e[0][0] * e[1][1] - (int64_t)e[0][1] * e[1][0];
+  axis_bounds(S.n[0], S.n[1], S.n[2], q, S.nL, S.nH);
+  int64_t L, H;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    // e x x = (0, e_z, -e_y), e x y = (-e_z, 0, e_x), e x z = (e_y, -e_x, 0); with |v| < 1024 the
-    // bounds and the per-froxel projections fit int32
     axis_bounds(0, e[i][2], -e[i][1], q, L, H);
-    Lx[i] = (int32_t)L;
-    Hx[i] = (int32_t)H;
+    S.L[i][0] = (int32_t)L;
+    S.H[i][0] = (int32_t)H;
     axis_bounds(-e[i][2], 0, e[i][0], q, L, H);
-    Ly[i] = (int32_t)L;
-    Hy[i] = (int32_t)H;
+    S.L[i][1] = (int32_t)L;
+    S.H[i][1] = (int32_t)H;
     axis_bounds(e[i][1], -e[i][0], 0, q, L, H);
-    Lz[i] = (int32_t)L;
-    Hz[i] = (int32_t)H;
+    S.L[i][2] = (int32_t)L;
+    S.H[i][2] = (int32_t)H;
   }
+}
+
+__global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__ tris, Batch B, int64_t total,
+                                                        TriSetup *__restrict__ recs, int32_t *__restrict__ tile_count,
+                                                        int32_t *__restrict__ tile_list) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int ntl = 0, tx0 = 0, ty0 = 0, tz0 = 0, ntx = 1, nty = 1, toff = 0, tys = 1, txs = 1;
+  if (t < total) {
+    const GridDesc &g = B.g[tri_grid(B, t)];
+    TriSetup S = {};
+    int32_t q[9];
+    bool ok = true;
+    int32_t mn[3], mx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = 0x7fffffff;
+      mx[a] = -0x7fffffff;
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float x = tris[t * 9 + v * 3 + a];
+        ok = ok && (__builtin_fabsf(x) < (float)NPVS_MAX_DIM);  // finite and |x| < 1024 (NaN fails)
+        int32_t qq = ok ? (int32_t)__builtin_rintf(x * 256.0f) : 0;  // exact scaling, round half to even
+        q[v * 3 + a] = qq;
+        mn[a] = qq < mn[a] ? qq : mn[a];
+        mx[a] = qq > mx[a] ? qq : mx[a];
+      }
+    int32_t dims[3] = {g.nx, g.ny, g.nz};
+    int32_t lo[3], hi[3];
+    bool empty = !ok;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      // closed cells [256 i, 256 i + 256] meeting [mn, mx]: i in [floor((mn-1)/256), floor(mx/256)]
+      lo[a] = (mn[a] - 1) >> 8;
+      hi[a] = mx[a] >> 8;
+      lo[a] = lo[a] < 0 ? 0 : lo[a];
+      hi[a] = hi[a] > dims[a] - 1 ? dims[a] - 1 : hi[a];
+      empty = empty || lo[a] > hi[a];
+    }
+    if (!empty) make_setup(q, S);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      S.lo[a] = (int16_t)(empty ? 1 : lo[a]);
+      S.hi[a] = (int16_t)(empty ? 0 : hi[a]);
+    }
+    recs[t] = S;
+    if (!empty) {
+      tx0 = lo[0] / kFroxTileX;
+      ty0 = lo[1] / kFroxTileY;
+      tz0 = lo[2] / kFroxTileZ;
+      ntx = hi[0] / kFroxTileX - tx0 + 1;
+      nty = hi[1] / kFroxTileY - ty0 + 1;
+      const int ntz = hi[2] / kFroxTileZ - tz0 + 1;
+      ntl = ntx * nty * ntz;
+      toff = g.tile_off;
+      txs = g.tiles_x;
+      tys = g.tiles_y;
+    }
+  }
+  // Append to each covered tile; in each round the lanes that target the same tile share one
+  // counter update.
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int j = 0;; ++j) {
+    const bool active = j < ntl;
+    if (__ballot(active) == 0ull) break;
+    int tile = -1;
+    if (active) {
+      const int ix = j % ntx, iy = (j / ntx) % nty, iz = j / (ntx * nty);
+      tile = toff + ((tz0 + iz) * tys + (ty0 + iy)) * txs + (tx0 + ix);
+    }
+    int slot = -1;
+    uint64_t pending = __ballot(active);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int lt = __shfl(tile, leader, 64);
+      const uint64_t same = __ballot(active && tile == lt);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&tile_count[lt], __popcll(same));
+      base = __shfl(base, leader, 64);
+      if (active && tile == lt) slot = base + __popcll(same & below);
+      pending &= ~same;
+    }
+    if (active && slot < kFroxTileCap) tile_list[(int64_t)tile * kFroxTileCap + slot] = (int32_t)t;
+  }
+}
+
+// ORs the froxels of the triangle inside the tile with origin (X0, Y0, Z0) into the LDS mask
+// (word (z - Z0) * 8 + (y - Y0), bit x - X0).
+__device__ __forceinline__ void frox_triangle(const TriSetup &S, int X0, int Y0, int Z0, uint32_t *mask) {
+  const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+  const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
+  const int za = S.lo[2] > Z0 ? S.lo[2] : Z0, zb = S.hi[2] < Z0 + 7 ? S.hi[2] : Z0 + 7;
+  if (xa > xb || ya > yb || za > zb) return;
   for (int z = za; z <= zb; ++z)
     for (int y = ya; y <= yb; ++y) {
       bool row_ok = true;  // the edge x x-axis tests do not depend on x
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const int32_t s = e[i][2] * y - e[i][1] * z;
-        row_ok = row_ok && s >= Lx[i] && s <= Hx[i];
+        const int32_t s = S.e[i][2] * y - S.e[i][1] * z;
+        row_ok = row_ok && s >= S.L[i][0] && s <= S.H[i][0];
       }
       if (!row_ok) continue;
       int32_t sy[3], sz[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        sy[i] = -e[i][2] * xa + e[i][0] * z;
-        sz[i] = e[i][1] * xa - e[i][0] * y;
+        sy[i] = -S.e[i][2] * xa + S.e[i][0] * z;
+        sz[i] = S.e[i][1] * xa - S.e[i][0] * y;
       }
-      int64_t sn = n0 * xa + n1 * y + n2 * z;
-      uint32_t *row = mask + (z - Z0) * 32 + (y - Y0) * 4;
-      int w = (xa - X0) >> 5;
+      int64_t sn = S.n[0] * xa + S.n[1] * y + S.n[2] * z;
       uint32_t m = 0;
       for (int x = xa; x <= xb; ++x) {
-        const int wx = (x - X0) >> 5;
-        if (wx != w) {
-          if (m) atomicOr(row + w, m);
-          m = 0;
-          w = wx;
-        }
-        bool hit = sn >= nL && sn <= nH;
+        bool hit = sn >= S.nL && sn <= S.nH;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          hit = hit && sy[i] >= Ly[i] && sy[i] <= Hy[i] && sz[i] >= Lz[i] && sz[i] <= Hz[i];
-          sy[i] -= e[i][2];
-          sz[i] += e[i][1];
+          hit = hit && sy[i] >= S.L[i][1] && sy[i] <= S.H[i][1] && sz[i] >= S.L[i][2] && sz[i] <= S.H[i][2];
+          sy[i] -= S.e[i][2];
+          sz[i] += S.e[i][1];
         }
-        sn += n0;
-        m |= (uint32_t)hit << ((x - X0) & 31);
+        sn += S.n[0];
+        m |= (uint32_t)hit << (x - X0);
       }
-      if (m) atomicOr(row + w, m);
+      if (m) atomicOr(mask + (z - Z0) * 8 + (y - Y0), m);
     }
 }
 
@@ -246,8 +240,51 @@ __device__ __forceinline__ void tile_parts(const GridDesc &g, int cnt, int &item
   nparts = listed ? (cnt + kPartTris - 1) / kPartTris : kMaxParts;
 }
 
-// Grid-stride over the parts the bin kernel opened; 256 threads, one triangle per thread.
-__global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriRec *__restrict__ recs,
+__device__ __forceinline__ void tile_origin(const GridDesc &g, int tile, int &X0, int &Y0, int &Z0) {
+  const int lt = tile - g.tile_off;
+  X0 = (lt % g.tiles_x) * kFroxTileX;
+  Y0 = ((lt / g.tiles_x) % g.tiles_y) * kFroxTileY;
+  Z0 = (lt / (g.tiles_x * g.tiles_y)) * kFroxTileZ;
+}
+
+// One workgroup of 1024 threads: the part list, in tile order, from the tiles' counts
+// (exclusive scan of the number of parts of every tile).
+__global__ __launch_bounds__(1024) void frox_plan_kernel(Batch B, const int32_t *__restrict__ tile_count,
+                                                         int32_t *__restrict__ part_list, int32_t *__restrict__ n_parts) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int running = 0;
+  for (int base = 0; base < B.total_tiles; base += 1024) {
+    const int tile = base + tid;
+    int np = 0;
+    if (tile < B.total_tiles) {
+      int items, per;
+      bool listed;
+      tile_parts(tile_grid(B, tile), tile_count[tile], items, per, np, listed);
+    }
+    int x = np;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int i = 0; i < 16; ++i) {
+      pre += i < w ? wsum[i] : 0;
+      tot += wsum[i];
+    }
+    const int p0 = running + pre + x - np;
+    for (int i = 0; i < np; ++i) part_list[p0 + i] = tile * kMaxParts + i;
+    running += tot;
+  }
+  if (tid == 0) *n_parts = running;
+}
+
+// Grid-stride over the part list; 256 threads, one triangle per thread.
+__global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriSetup *__restrict__ recs,
                                                          const int32_t *__restrict__ tile_count,
                                                          const int32_t *__restrict__ tile_list,
                                                          const int32_t *__restrict__ part_list,
@@ -257,45 +294,43 @@ __global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriRec *_
   const int tid = threadIdx.x;
   const int np = *n_parts;
   for (int pi = blockIdx.x; pi < np; pi += gridDim.x) {
-  const int code = part_list[pi];
-  const int tile = code / kMaxParts, part = code % kMaxParts;
-  const GridDesc &g = tile_grid(B, tile);
-  int items, per, nparts;
-  bool listed;
-  tile_parts(g, tile_count[tile], items, per, nparts, listed);
-  const int lt = tile - g.tile_off;
-  const int X0 = (lt % g.tiles_x) * kFroxTileX;
-  const int Y0 = ((lt / g.tiles_x) % g.tiles_y) * kFroxTileY;
-  const int Z0 = (lt / (g.tiles_x * g.tiles_y)) * kFroxTileZ;
-  mask[tid] = 0;
-  __syncthreads();
-  const int i1 = (part + 1) * per < items ? (part + 1) * per : items;
-  for (int i = part * per + tid; i < i1; i += 256) {
-    const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + i] : g.tri_off + i;
-    frox_triangle(recs[t], X0, Y0, Z0, mask);
-  }
-  __syncthreads();
-  partial[((int64_t)tile * kMaxParts + part) * kTileWords + tid] = mask[tid];
-  __syncthreads();  // mask is cleared for the next part only after every thread has stored
+    const int code = part_list[pi];
+    const int tile = code / kMaxParts, part = code % kMaxParts;
+    const GridDesc &g = tile_grid(B, tile);
+    int items, per, nparts;
+    bool listed;
+    tile_parts(g, tile_count[tile], items, per, nparts, listed);
+    int X0, Y0, Z0;
+    tile_origin(g, tile, X0, Y0, Z0);
+    if (tid < kTileWords) mask[tid] = 0;
+    __syncthreads();
+    const int i1 = (part + 1) * per < items ? (part + 1) * per : items;
+    for (int i = part * per + tid; i < i1; i += 256) {
+      const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + i] : g.tri_off + i;
+      frox_triangle(recs[t], X0, Y0, Z0, mask);
+    }
+    __syncthreads();
+    if (tid < kTileWords) partial[((int64_t)tile * kMaxParts + part) * kTileWords + tid] = mask[tid];
+    __syncthreads();  // the mask is cleared for the next part only after it has been stored
   }
 }
 
-// one workgroup per tile, one thread per word: OR the parts, write the word once
+// 256 threads = 4 tiles x 64 words: OR the parts of the word's tile, write the word once.
 __global__ __launch_bounds__(256) void frox_merge_kernel(Batch B, const int32_t *__restrict__ tile_count,
                                                           const uint32_t *__restrict__ partial,
                                                           uint8_t *__restrict__ occ) {
-  const int tile = blockIdx.x, tid = threadIdx.x;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), w = threadIdx.x & 63;
+  if (tile >= B.total_tiles) return;
   const GridDesc &g = tile_grid(B, tile);
   int items, per, nparts;
   bool listed;
   tile_parts(g, tile_count[tile], items, per, nparts, listed);
   uint32_t word = 0;
-  for (int p = 0; p < nparts; ++p) word |= partial[((int64_t)tile * kMaxParts + p) * kTileWords + tid];
-  const int lt = tile - g.tile_off;
-  const int x0 = (lt % g.tiles_x) * kFroxTileX + (tid & 3) * 32;
-  const int y = ((lt / g.tiles_x) % g.tiles_y) * kFroxTileY + ((tid >> 2) & 7);
-  const int z = (lt / (g.tiles_x * g.tiles_y)) * kFroxTileZ + (tid >> 5);
-  if (x0 >= g.nx || y >= g.ny || z >= g.nz) return;
+  for (int p = 0; p < nparts; ++p) word |= partial[((int64_t)tile * kMaxParts + p) * kTileWords + w];
+  int X0, Y0, Z0;
+  tile_origin(g, tile, X0, Y0, Z0);
+  const int x0 = X0, y = Y0 + (w & 7), z = Z0 + (w >> 3);
+  if (y >= g.ny || z >= g.nz) return;
   const int64_t row_bytes = g.nx / 8;
   uint8_t *dst = occ + g.occ_off + ((int64_t)z * g.ny + y) * row_bytes + x0 / 8;
   if (x0 + 32 <= g.nx && (row_bytes & 3) == 0 && (g.occ_off & 3) == 0) {
@@ -315,7 +350,7 @@ static void frox_ws_layout(const Batch &B, int64_t total_tris, size_t *off_count
   *off_list = o;
   o += align256(sizeof(int32_t) * (size_t)B.total_tiles * kFroxTileCap);
   *off_recs = o;
-  o += align256(sizeof(TriRec) * (size_t)(total_tris > 0 ? total_tris : 1));
+  o += align256(sizeof(TriSetup) * (size_t)(total_tris > 0 ? total_tris : 1));
   *off_part = o;
   o += align256(sizeof(uint32_t) * (size_t)B.total_tiles * kMaxParts * kTileWords);
   *bytes = o;
@@ -356,16 +391,16 @@ extern "C" npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, 
   int32_t *n_parts = cnt + B.total_tiles;
   int32_t *part_list = n_parts + 1;
   int32_t *lst = reinterpret_cast<int32_t *>(w + ol);
-  TriRec *recs = reinterpret_cast<TriRec *>(w + orr);
+  TriSetup *recs = reinterpret_cast<TriSetup *>(w + orr);
   uint32_t *part = reinterpret_cast<uint32_t *>(w + op);
   hipStream_t s = as_stream(stream);
   frox_zero_kernel<<<stride_grid(B.total_tiles, 256, 1024), 256, 0, s>>>(cnt, B.total_tiles, n_parts);
   if (total > 0) {
-    frox_bin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(tris, B, total, recs, cnt, lst, part_list,
-                                                                    n_parts);
+    frox_bin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(tris, B, total, recs, cnt, lst);
+    frox_plan_kernel<<<1, 1024, 0, s>>>(B, cnt, part_list, n_parts);
     frox_part_kernel<<<stride_grid((int64_t)B.total_tiles * kMaxParts, 1, 2048), 256, 0, s>>>(
         B, recs, cnt, lst, part_list, n_parts, part);
   }
-  frox_merge_kernel<<<B.total_tiles, 256, 0, s>>>(B, cnt, part, occ_bits);
+  frox_merge_kernel<<<(B.total_tiles + 3) / 4, 256, 0, s>>>(B, cnt, part, occ_bits);
   return check_hip(hipGetLastError(), "npvs_froxelize");
 }

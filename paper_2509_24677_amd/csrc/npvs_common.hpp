@@ -75,7 +75,7 @@ inline int stride_grid(int64_t max_items, int per_block, int cap = 4096) {
   return (int)b;
 }
 
-constexpr int kFroxTileX = 128;  // froxels per tile along x (four 32-froxel words)
+constexpr int kFroxTileX = 32;  // froxels per tile along x (one 32-froxel word)
 constexpr int kFroxTileY = 8;
 constexpr int kFroxTileZ = 8;
 constexpr int kFroxTileCap = 2048;  // triangle slots per tile before the tile falls back to a full scan

@@ -66,35 +66,44 @@ __global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restri
   if (tid < kLossQ) part[((int64_t)b * kLossSlices + s) * kLossQ + tid] = red[tid][0].s + red[tid][0].c;
 }
 
-// One workgroup; thread b finishes grid b.  coef[b] = {a_b, c_b}.
-__global__ void loss_final_kernel(const float *__restrict__ part, const int32_t *__restrict__ grid_rows, int n_grids,
-                                  int C, float lambda, float *__restrict__ stats, float *__restrict__ coef) {
-  __shared__ float st[NPVS_MAX_GRIDS][8];
-  const int b = threadIdx.x;
-  if (b < n_grids) {
-    Comp q[kLossQ];
-    for (int i = 0; i < kLossQ; ++i) q[i] = Comp{0.0f, 0.0f};
-    for (int s = 0; s < kLossSlices; ++s)
-      for (int i = 0; i < kLossQ; ++i) q[i].add(part[((int64_t)b * kLossSlices + s) * kLossQ + i]);
+// One workgroup per grid: thread s takes slice s's partial sums, a fixed-shape tree adds them,
+// thread 0 writes the grid's statistics and gradient coefficients coef[b] = {a_b, c_b}.
+__global__ __launch_bounds__(kLossSlices) void loss_final_kernel(const float *__restrict__ part,
+                                                                 const int32_t *__restrict__ grid_rows, int n_grids,
+                                                                 int C, float lambda, float *__restrict__ stats,
+                                                                 float *__restrict__ coef) {
+  __shared__ Comp red[kLossQ][kLossSlices];
+  const int b = blockIdx.x, s = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kLossQ; ++i) red[i][s] = Comp{part[((int64_t)b * kLossSlices + s) * kLossQ + i], 0.0f};
+  __syncthreads();
+  for (int w = kLossSlices / 2; w > 0; w >>= 1) {
+    if (s < w)
+#pragma unroll
+      for (int i = 0; i < kLossQ; ++i) red[i][s].merge(red[i][s + w]);
+    __syncthreads();
+  }
+  if (s == 0) {
     const float m = (float)((int64_t)(grid_rows[b + 1] - grid_rows[b]) * C);
-    const float bce_sum = q[0].s + q[0].c, tp = q[1].s + q[1].c, fn = q[2].s + q[2].c, fp = q[3].s + q[3].c,
-                gtp = q[4].s + q[4].c;
+    const float bce_sum = red[0][0].s + red[0][0].c, tp = red[1][0].s + red[1][0].c, fn = red[2][0].s + red[2][0].c,
+                fp = red[3][0].s + red[3][0].c, gtp = red[4][0].s + red[4][0].c;
     const float g = gtp > 1.0f ? gtp : 1.0f;
     const float bce = m > 0.0f ? bce_sum / m : 0.0f;
     const float lrv = fn / g + fp / g;
-    float v[8] = {lambda * bce + (1.0f - lambda) * lrv, bce, lrv, tp, fn, fp, gtp, m};
-    for (int i = 0; i < 8; ++i) {
-      st[b][i] = v[i];
-      stats[b * 8 + i] = v[i];
-    }
+    const float v[8] = {lambda * bce + (1.0f - lambda) * lrv, bce, lrv, tp, fn, fp, gtp, m};
+    for (int i = 0; i < 8; ++i) stats[b * 8 + i] = v[i];
     coef[2 * b] = m > 0.0f ? lambda / (m * n_grids) : 0.0f;
     coef[2 * b + 1] = (1.0f - lambda) / (g * n_grids);
   }
-  __syncthreads();
-  if (b < 8) {
+}
+
+// Batch row of the statistics: the mean over grids, in grid order.
+__global__ void loss_mean_kernel(float *__restrict__ stats, int n_grids) {
+  const int i = threadIdx.x;
+  if (i < 8) {
     float t = 0.0f;
-    for (int i = 0; i < n_grids; ++i) t += st[i][b];
-    stats[n_grids * 8 + b] = t / n_grids;
+    for (int b = 0; b < n_grids; ++b) t += stats[b * 8 + i];
+    stats[n_grids * 8 + i] = t / n_grids;
   }
 }
 
@@ -153,7 +162,8 @@ extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int
   float *coef = part + (size_t)n_grids * kLossSlices * kLossQ;
   hipStream_t s = as_stream(stream);
   loss_partial_kernel<<<dim3(kLossSlices, n_grids), 256, 0, s>>>(logits, labels, C, grid_rows, part);
-  loss_final_kernel<<<1, 64, 0, s>>>(part, grid_rows, n_grids, C, lambda, stats, coef);
+  loss_final_kernel<<<n_grids, kLossSlices, 0, s>>>(part, grid_rows, n_grids, C, lambda, stats, coef);
+  loss_mean_kernel<<<1, 64, 0, s>>>(stats, n_grids);
   if (dlogits)
     loss_grad_kernel<<<stride_grid((int64_t)cap_sites * C, 256, 4096), 256, 0, s>>>(logits, labels, C, grid_rows,
                                                                                    n_grids, counts, coef, dlogits);

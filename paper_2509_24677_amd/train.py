@@ -25,8 +25,22 @@ class Network:
         """layers: list of (W float32 [27][cin][cout], b float32 [cout]) as numpy or torch."""
         self.d = d
         self.dtype = dtype
-        self.W = [torch.as_tensor(W, dtype=torch.float32).to(device).contiguous() for W, _ in layers]
-        self.b = [torch.as_tensor(b, dtype=torch.float32).to(device).contiguous() for _, b in layers]
+        Ws = [torch.as_tensor(W, dtype=torch.float32) for W, _ in layers]
+        bs = [torch.as_tensor(b, dtype=torch.float32) for _, b in layers]
+        # all parameters (and their gradients) live in one flat buffer, so one optimizer launch
+        # updates every layer; W[i], b[i], gW[i], gb[i] are views into it
+        sizes = [w.numel() for w in Ws] + [b.numel() for b in bs]
+        self.flat = torch.empty(sum(sizes), dtype=torch.float32, device=device)
+        self.gflat = torch.zeros_like(self.flat)
+        views, gviews, off = [], [], 0
+        for t, n in zip(Ws + bs, sizes):
+            views.append(self.flat[off:off + n].view(t.shape))
+            gviews.append(self.gflat[off:off + n].view(t.shape))
+            views[-1].copy_(t)
+            off += n
+        L = len(Ws)
+        self.W, self.b = views[:L], views[L:]
+        self.gW, self.gb = gviews[:L], gviews[L:]
         self.channels = [self.W[0].shape[1]] + [w.shape[2] for w in self.W]
         self.Wp = [None] * len(self.W)
         self.Wt = [None] * len(self.W)
@@ -108,7 +122,8 @@ class Network:
             if Y is None:
                 Y = self.layer(i, X, rb)
             dX, dW, db = sparse_conv_bwd(X, self.Wt[i], self.channels[i], self.channels[i + 1], Y, dY, rb,
-                                         self.dtype, relu=i < self.n_layers - 1, want_dx=i > 0)
+                                         self.dtype, relu=i < self.n_layers - 1, want_dx=i > 0,
+                                         dW=self.gW[i], db=self.gb[i])
             grads[i] = (dW, db)
             if i > 0:
                 outputs[i - 1] = X
@@ -126,9 +141,8 @@ class Trainer:
         self.n_tris = list(n_tris)
         self.lam, self.lr, self.wd = lam, lr, weight_decay
         self.checkpoint = checkpoint
-        self.m = [torch.zeros_like(p) for p in net.W + net.b]
-        self.v = [torch.zeros_like(p) for p in net.W + net.b]
-        self.t = torch.zeros((), dtype=torch.int64)  # host-side step count
+        self.m = torch.zeros_like(net.flat)
+        self.v = torch.zeros_like(net.flat)
         self.step_count = 0
 
     def step(self, tris: torch.Tensor, label_bits: torch.Tensor):
@@ -140,12 +154,9 @@ class Trainer:
         pvs, _ = deinterleave_threshold(logits, rb, occ)
         labels = gather_input(label_bits, rb, NPVS_U8)
         stats, dl = loss(logits, labels, rb, self.lam)
-        grads = net.backward(saved, logits, dl, rb)
+        net.backward(saved, logits, dl, rb)  # gradients land in net.gflat
         self.step_count += 1
-        params = net.W + net.b
-        flat = [g for g, _ in grads] + [b for _, b in grads]
-        for p, g, m, v in zip(params, flat, self.m, self.v):
-            adam(p, g, m, v, self.step_count, lr=self.lr, weight_decay=self.wd)
+        adam(net.flat, net.gflat, self.m, self.v, self.step_count, lr=self.lr, weight_decay=self.wd)
         net.repack()
         return stats, pvs
 

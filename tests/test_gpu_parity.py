@@ -216,7 +216,7 @@ def test_conv_fwd_bf16_mfma(cin, cout, variant_rows):
     np.testing.assert_array_equal(to_np(Yb)[:n], to_np(Y[:n].to(torch.bfloat16)))
 
 
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(10))
 @pytest.mark.parametrize("cin,cout,d", [(64, 64, 2), (16, 8, 2), (512, 64, 8)])
 def test_conv_fwd_bf16_every_tile_shape(variant, cin, cout, d):
     rb, ref, X, W, b = _conv_case(cin, cout, d=d, dims=((64, 64, 64), (32, 32, 32)))
@@ -246,7 +246,7 @@ def test_plan_autotune_picks_valid_shapes_and_keeps_results():
         plan.set_weights(li, torch.from_numpy(W).to(DEV), torch.from_numpy(b).to(DEV))
     v = plan.autotune(tris, reps=3)
     print("autotuned variants", v, flush=True)
-    assert len(v) == 6 and all(0 <= x < 6 for x in v) and len(set(v[:5])) == 1
+    assert len(v) == 6 and all(0 <= x < 10 for x in v) and len(set(v[:5])) == 1
     pvs, logits = plan.forward(tris, want_logits=True)
     out = oracle.forward(t, cfg.grids[0], cfg.d, layers)
     got = to_np(logits).reshape(out["logits"].shape)
