@@ -37,7 +37,87 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + timed steps only (for rocprofv3)")
+    ap.add_argument("--counters", action="store_true",
+                    help="for rocprofv3 --pmc: a plain 256 MiB copy (counter calibration), then --steps eager "
+                         "(not graph-replayed) BF16 training steps; prints one JSON line and exits")
     return ap.parse_args()
+
+
+def bench_batch16(args, dev, timed_launches):
+    """16 viewcell grids of uneven size (64^3 .. 256x256x128) and occupancy (1-10 %) through the
+    BF16 forward as one plan (one concatenated site table and rulebook, autotuned tile shapes, one
+    captured graph), against the same 16 grids as 16 single-grid plans replayed one after another.
+    Also times one hidden conv launch on the batched rulebook (MFMA roofline at this size)."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+
+    cfg = synth.config("batch16")
+    tri_list = [synth.scene_for(cfg, i) for i in range(len(cfg.grids))]
+    layers = synth.net_layers(cfg)
+    flat = np.concatenate([t.reshape(-1) for t in tri_list]).astype(np.float32)
+    tris = torch.from_numpy(flat).to(dev)
+    counts = [len(t) for t in tri_list]
+
+    def plan_for(dims, cnts, tr):
+        p = npvs.Plan(dims, cnts, cfg.d, cfg.channels, npvs.NPVS_BF16)
+        for li, (W, b) in enumerate(layers):
+            p.set_weights(li, torch.from_numpy(W).to(dev), torch.from_numpy(b).to(dev))
+        return p, p.autotune(tr, reps=5)
+
+    def time_replays(plans, steps):
+        for p in plans:
+            p.replay()
+        torch.cuda.current_stream().synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            for p in plans:
+                p.replay()
+        e1.record()
+        torch.cuda.current_stream().synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan, tuned = plan_for(cfg.grids, counts, tris)
+        plan.capture(tris)
+        ms_batched = time_replays([plan], args.steps)
+        singles, off = [], 0
+        for g, t in zip(cfg.grids, tri_list):
+            tr = tris[off:off + t.size]
+            off += t.size
+            p, _ = plan_for([g], [len(t)], tr)
+            p.capture(tr)
+            singles.append(p)
+        ms_separate = time_replays(singles, args.steps)
+    torch.cuda.synchronize()
+    c = plan.counts()
+    # one hidden layer on the batched rulebook, launch by launch
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
+    X0 = npvs.gather_input(occ, rb, npvs.NPVS_BF16)
+    W1 = npvs.pack_weights(torch.from_numpy(layers[1][0]).to(dev), npvs.NPVS_BF16)
+    b1 = torch.from_numpy(layers[1][1]).to(dev)
+    W0 = npvs.pack_weights(torch.from_numpy(layers[0][0]).to(dev), npvs.NPVS_BF16)
+    H = npvs.sparse_conv_fwd(X0, W0, torch.from_numpy(layers[0][1]).to(dev), 64, 64, rb, npvs.NPVS_BF16, True)
+    out = torch.empty_like(H)
+    var = tuned[1]
+    ts = timed_launches(lambda: npvs.sparse_conv_fwd(H, W1, b1, 64, 64, rb, npvs.NPVS_BF16, True, out=out,
+                                                     variant=var), 40)
+    conv_ms = float(np.mean(ts))
+    n_pairs = rb.host_counts()["n_pairs"]
+    flops = 2.0 * n_pairs * 64 * 64
+    n = len(cfg.grids)
+    return {"grids": n, "n_sites": c["n_sites"], "n_pairs": n_pairs, "tile_variants": tuned,
+            "batched_ms": ms_batched, "batched_frames_per_s": 1000.0 * n / ms_batched,
+            "separate_ms": ms_separate, "separate_frames_per_s": 1000.0 * n / ms_separate,
+            "speedup": ms_separate / ms_batched,
+            "conv_fwd_bf16_avg_launch_ms": conv_ms,
+            "conv_fwd_bf16_tflops": flops / (conv_ms * 1e-3) / 1e12,
+            "conv_fwd_bf16_frac_of_peak": flops / (conv_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
 
 
 def main():
@@ -133,6 +213,19 @@ def main():
         return e0.elapsed_time(e1) / steps, wall
 
     net_b, tr_b = make(npvs.NPVS_BF16)
+    if args.counters:
+        # calibration: an elementwise kernel that reads and writes exactly 256 MiB each
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        step = train_fn(tr_b)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        print(json.dumps({"counters": True, "steps": args.steps, "calibration_bytes_each_way": a.numel() * 4}))
+        return
     g_train_b, _ = capture(train_fn(tr_b), max(args.warmup, 2))
     print("# captured bf16 training step", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -235,6 +328,10 @@ def main():
                      "avg_launch_ms": conv32_ms}
     roofline_fp32["frac"] = roofline_fp32["achieved"] / FP32_PEAK_TFLOPS
 
+    # ------------------------------------------------------------------ batching (16 uneven grids)
+    batch16 = bench_batch16(args, dev, timed_launches)
+    print("# batch16 " + json.dumps(batch16), file=sys.stderr, flush=True)
+
     # ------------------------------------------------------------------ accuracy
     torch.cuda.synchronize()
     acc = {}
@@ -294,6 +391,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "stages_ms": stage_ms,
+        "batch16": batch16,
         "accuracy": acc,
     }
     print(json.dumps(line))

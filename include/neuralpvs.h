@@ -138,10 +138,24 @@ npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_d
  * npvs_packed_weight_bytes() bytes in the layout of `dtype`'s convolution kernel.
  * flip_transpose = 1 packs W'_k = (W_{26-k})^T, a [27][cout][cin] weight: the data gradient of
  * a submanifold layer is the same convolution run with W' (the rulebook is symmetric).
+ * The size serves both orientations (for BF16 the larger one); the whole buffer is written,
+ * entries past the orientation's own layout as zero.
  * ------------------------------------------------------------------------------------------- */
 size_t npvs_packed_weight_bytes(int32_t cin, int32_t cout, int32_t dtype);
 npvs_status npvs_pack_weights(const float *W, int32_t cin, int32_t cout, int32_t dtype, int32_t flip_transpose,
                               void *Wp, void *stream);
+
+/* Several packings in one launch (a training step re-packs every layer, in both orientations,
+ * after each optimizer update).  descs (host) [n]: each entry is one npvs_pack_weights call with
+ * the same meaning of its fields; all entries use `dtype`.  At most NPVS_MAX_PACK entries; the
+ * outputs must not overlap each other or any W. */
+#define NPVS_MAX_PACK 64
+typedef struct {
+  const float *W;  /* (device) float32 [27][cin][cout] */
+  void *Wp;        /* (device) npvs_packed_weight_bytes(cin, cout, dtype) bytes */
+  int32_t cin, cout, flip_transpose, reserved;
+} npvs_pack_desc;
+npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int32_t dtype, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Submanifold sparse 3x3x3 convolution, forward (Sec. 2.3, 3.3):
@@ -184,6 +198,18 @@ npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int
                                  const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
                                  float *dW, float *db, void *ws, size_t ws_bytes, void *stream);
 
+/* The same backward with the weight and bias gradients on a second stream, so that they overlap
+ * the data-gradient chain of the layers below.  dZ and the bias partials are formed on `stream`,
+ * then `wgrad_stream` waits for them and computes dW and db while dX is computed on `stream`.
+ * Until the caller makes `stream` wait for `wgrad_stream`, dW, db, X and ws are in use by
+ * `wgrad_stream` (do not read dW / db or reuse ws or X before that).  wgrad_stream == stream is
+ * npvs_sparse_conv_bwd.  Both streams may be under capture (the wait is a graph dependency). */
+npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
+                                       const float *dY, const int32_t *nbr, const int32_t *rb_off,
+                                       const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
+                                       int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
+                                       size_t ws_bytes, void *stream, void *wgrad_stream);
+
 /* ---------------------------------------------------------------------------------------------
  * De-interleave and threshold (Sec. 3.1 V = 1[f(G) >= tau] with tau = 0.5, read as logit >= 0;
  * Sec. 3.3 g_d^-1; Sec. 3.2 the visible set lies inside the occupied set, so V is masked by G):
@@ -216,6 +242,17 @@ npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, con
  * (the paper's "learning rate decay rate"); p, g, m, v (device) float32 [n]. */
 npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float beta1,
                       float beta2, float eps, float weight_decay, void *stream);
+
+/* The same update with the step counter on the device, so that a captured training step replays
+ * with the right bias correction: `step` (device) is advanced on the stream first (t += 1,
+ * c1 = 1 - beta1^t, c2 = 1 - beta2^t, each rounded from double to float), then the update uses
+ * its c1, c2.  Start from t = 0. */
+typedef struct {
+  int64_t t;
+  float c1, c2;
+} npvs_adam_step;
+npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step, float lr,
+                          float beta1, float beta2, float eps, float weight_decay, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Whole forward pass V = threshold(g_d^-1(f(g_d(froxelize(tris))))) through a library-owned

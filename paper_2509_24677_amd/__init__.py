@@ -163,6 +163,23 @@ def pack_weights(W: torch.Tensor, dtype: int, flip_transpose: bool = False) -> t
     return Wp
 
 
+def pack_weights_batch(items, dtype: int):
+    """Packs several weights in one launch: items = [(W float32 [27][cin][cout], Wp uint8 output,
+    flip_transpose)], every Wp of npvs_packed_weight_bytes(cin, cout, dtype) bytes, written in place."""
+    n = len(items)
+    if n > L.NPVS_MAX_PACK:
+        raise ValueError(f"at most {L.NPVS_MAX_PACK} packings per call")
+    descs = (L.PackDesc * max(n, 1))()
+    for i, (W, Wp, flip) in enumerate(items):
+        if W.dtype != torch.float32 or W.dim() != 3 or W.shape[0] != 27 or not W.is_contiguous():
+            raise ValueError("W must be contiguous float32 [27][cin][cout]")
+        cin, cout = W.shape[1], W.shape[2]
+        if Wp.numel() * Wp.element_size() != L.get().npvs_packed_weight_bytes(cin, cout, dtype):
+            raise ValueError("Wp has the wrong size")
+        descs[i] = L.PackDesc(_p(W), _p(Wp), cin, cout, int(flip), 0)
+    L.call("npvs_pack_weights_batch", n, ctypes.cast(descs, ctypes.c_void_p), dtype, _stream())
+
+
 def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None, cin: int, cout: int,
                     rb: Rulebook, dtype: int, relu: bool, out_f32: bool = False,
                     out: torch.Tensor | None = None, variant: int | None = None) -> torch.Tensor:
@@ -179,16 +196,24 @@ def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None
     return out
 
 
+def conv_bwd_workspace(cin: int, cout: int, rb: Rulebook, dtype: int) -> torch.Tensor:
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_workspace_size", cin, cout, rb.cap, dtype, ctypes.byref(nbytes))
+    return torch.empty(nbytes.value, dtype=torch.uint8, device=rb.nbr.device)
+
+
 def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int, relu: bool, want_dx: bool = True,
-                    dW: torch.Tensor | None = None, db: torch.Tensor | None = None):
+                    dW: torch.Tensor | None = None, db: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    wgrad_stream: torch.cuda.Stream | None = None):
     """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout]).
-    dW / db may be given (contiguous float32 device tensors) to receive the gradients in place."""
+    dW / db may be given (contiguous float32 device tensors) to receive the gradients in place.
+    With `wgrad_stream`, dW and db are computed on that stream (npvs_sparse_conv_bwd_split): the
+    caller keeps X and ws alive and joins the stream before reading dW / db."""
     if rb.rb_off is None:
         raise ValueError("the backward needs a rulebook built with csr=True")
     dev = X.device
-    nbytes = ctypes.c_size_t()
-    L.call("npvs_conv_bwd_workspace_size", cin, cout, rb.cap, dtype, ctypes.byref(nbytes))
-    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    if ws is None:
+        ws = conv_bwd_workspace(cin, cout, rb, dtype)
     dX = torch.empty((rb.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
     if dW is None:
         dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
@@ -196,9 +221,12 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
         db = torch.empty(cout, dtype=torch.float32, device=dev)
     if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
         raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
-    L.call("npvs_sparse_conv_bwd", _p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off),
-           _p(rb.rb_pairs), _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), nbytes.value,
-           _stream())
+    args = (_p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off), _p(rb.rb_pairs),
+            _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), ws.numel(), _stream())
+    if wgrad_stream is None:
+        L.call("npvs_sparse_conv_bwd", *args)
+    else:
+        L.call("npvs_sparse_conv_bwd_split", *args, ctypes.c_void_p(wgrad_stream.cuda_stream))
     return dX, dW, db
 
 
@@ -234,6 +262,15 @@ def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 
 
 def adam(p, g, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-10):
     L.call("npvs_adam", _p(p), _p(g), _p(m), _p(v), p.numel(), int(t), float(lr), float(beta1), float(beta2),
+           float(eps), float(weight_decay), _stream())
+
+
+def adam_dev(p, g, m, v, step: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-10):
+    """Adam with the step counter on the device: `step` is a 16-byte npvs_adam_step (uint8
+    tensor, zero to start), advanced by the call (so graph replays keep counting)."""
+    if step.numel() * step.element_size() != 16:
+        raise ValueError("step must hold 16 bytes (npvs_adam_step)")
+    L.call("npvs_adam_dev", _p(p), _p(g), _p(m), _p(v), p.numel(), _p(step), float(lr), float(beta1), float(beta2),
            float(eps), float(weight_decay), _stream())
 
 

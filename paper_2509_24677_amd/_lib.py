@@ -20,6 +20,7 @@ NPVS_ERR_UNSUPPORTED = -4
 NPVS_F32, NPVS_BF16, NPVS_U8 = 0, 1, 2
 NPVS_MAX_GRIDS = 32
 NPVS_CONV_VARIANTS = 10
+NPVS_MAX_PACK = 64
 
 
 class NpvsError(RuntimeError):
@@ -35,6 +36,11 @@ class Dims(ctypes.Structure):
 class Counts(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("n_sites_needed", ctypes.c_int32),
                 ("n_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PackDesc(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_void_p), ("Wp", ctypes.c_void_p), ("cin", ctypes.c_int32), ("cout", ctypes.c_int32),
+                ("flip_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 P = ctypes.c_void_p
@@ -55,14 +61,17 @@ SIGNATURES = {
     "npvs_gather_input": (i32, [P, i32, P, i32, P, P, i32, i32, P, P]),
     "npvs_packed_weight_bytes": (sz, [i32, i32, i32]),
     "npvs_pack_weights": (i32, [P, i32, i32, i32, i32, P, P]),
+    "npvs_pack_weights_batch": (i32, [i32, P, i32, P]),
     "npvs_sparse_conv_fwd": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, P, P]),
     "npvs_sparse_conv_fwd_ex": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P]),
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
+    "npvs_sparse_conv_bwd_split": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),
     "npvs_loss_workspace_size": (i32, [i32, PS]),
     "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, P, P, P, sz, P]),
     "npvs_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, f32, P]),
+    "npvs_adam_dev": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, P]),
     "npvs_plan_create": (i32, [i32, P, P, i32, i32, P, i32, ctypes.POINTER(P)]),
     "npvs_plan_destroy": (i32, [P]),
     "npvs_plan_set_weights": (i32, [P, i32, P, P, P]),

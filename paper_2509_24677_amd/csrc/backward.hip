@@ -31,37 +31,78 @@ struct Comp {  // Neumaier-compensated float sum
 __device__ __forceinline__ float load_as_f32(const float *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float load_as_f32(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
 
-constexpr int kDbBlocks = 32;  // row blocks of the bias-gradient partial sums
+constexpr int kDbBlocks = 256;  // row blocks of the bias-gradient partial sums
 
 // dZ in float32 (for wgrad) and, for the BF16 path, a bfloat16 copy (MFMA operand), plus the
-// bias-gradient partial of this block's rows: grid kDbBlocks, 256 threads, C <= 64.  Thread t
-// owns column t % C of the rows r = r0 + t / C (mod 256 / C); the row groups are combined in LDS
+// bias-gradient partial of this block's rows: grid kDbBlocks, 256 threads, C <= 64.  With vec
+// (C % 4 == 0 and 16-byte aligned rows) a thread owns 4 adjacent columns, else one; the threads of
+// a row group cover one row, the row groups stride over the block's rows and are combined in LDS
 // in a fixed order.
+__device__ __forceinline__ void load4(const float *p, int64_t e, float *v) {
+  const f32x4_t x = *reinterpret_cast<const f32x4_t *>(p + e);
+  v[0] = x[0], v[1] = x[1], v[2] = x[2], v[3] = x[3];
+}
+__device__ __forceinline__ void load4(const uint16_t *p, int64_t e, float *v) {
+  const uint2 x = *reinterpret_cast<const uint2 *>(p + e);
+  v[0] = bf16_to_f32((uint16_t)x.x), v[1] = bf16_to_f32((uint16_t)(x.x >> 16));
+  v[2] = bf16_to_f32((uint16_t)x.y), v[3] = bf16_to_f32((uint16_t)(x.y >> 16));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y, const float *__restrict__ dY,
                                                          const npvs_counts *__restrict__ counts, int C, int relu,
-                                                         float *__restrict__ dZ32, uint16_t *__restrict__ dZ16,
+                                                         int vec, float *__restrict__ dZ32, uint16_t *__restrict__ dZ16,
                                                          float *__restrict__ dbpart) {
-  __shared__ float red[256];
+  __shared__ float red[256 * 4];
   const int64_t n = counts->n_sites;
   const int64_t r0 = n * blockIdx.x / kDbBlocks, r1 = n * (blockIdx.x + 1) / kDbBlocks;
-  const int c = threadIdx.x % C, rg = threadIdx.x / C, RG = 256 / C;
-  Comp a{0.0f, 0.0f};
-  if (rg < RG)
-    for (int64_t r = r0 + rg; r < r1; r += RG) {
-      const int64_t e = r * C + c;
-      float g = dY[e];
-      if (relu && !(load_as_f32(Y, e) > 0.0f)) g = 0.0f;
-      dZ32[e] = g;
-      if (dZ16) dZ16[e] = f32_to_bf16(g);
-      a.add(g);
+  const int V = vec ? 4 : 1, TPR = C / V, RG = 256 / TPR;
+  const int cg = threadIdx.x % TPR, rg = threadIdx.x / TPR;
+  Comp a[4] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+  if (rg < RG) {
+    if (vec) {
+      for (int64_t r = r0 + rg; r < r1; r += RG) {
+        const int64_t e = r * C + 4 * cg;
+        float g[4], y[4];
+        load4(dY, e, g);
+        if (relu) {
+          load4(Y, e, y);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g[i] = y[i] > 0.0f ? g[i] : 0.0f;
+        }
+        f32x4_t o;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          o[i] = g[i];
+          a[i].add(g[i]);
+        }
+        *reinterpret_cast<f32x4_t *>(dZ32 + e) = o;
+        if (dZ16) {
+          uint2 h;
+          h.x = (uint32_t)f32_to_bf16(g[0]) | ((uint32_t)f32_to_bf16(g[1]) << 16);
+          h.y = (uint32_t)f32_to_bf16(g[2]) | ((uint32_t)f32_to_bf16(g[3]) << 16);
+          *reinterpret_cast<uint2 *>(dZ16 + e) = h;
+        }
+      }
+    } else {
+      for (int64_t r = r0 + rg; r < r1; r += RG) {
+        const int64_t e = r * C + cg;
+        float g = dY[e];
+        if (relu && !(load_as_f32(Y, e) > 0.0f)) g = 0.0f;
+        dZ32[e] = g;
+        if (dZ16) dZ16[e] = f32_to_bf16(g);
+        a[0].add(g);
+      }
     }
-  red[threadIdx.x] = a.value();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[threadIdx.x * 4 + i] = a[i].value();
   __syncthreads();
   if (threadIdx.x < C) {
+    const int c = threadIdx.x, g0 = c / V, comp = c % V;
     Comp t{0.0f, 0.0f};
-    for (int g = 0; g < RG; ++g) t.add(red[g * C + threadIdx.x]);
-    dbpart[blockIdx.x * C + threadIdx.x] = t.value();
+    for (int g = 0; g < RG; ++g) t.add(red[(g * TPR + g0) * 4 + comp]);
+    dbpart[blockIdx.x * C + c] = t.value();
   }
 }
 
@@ -127,15 +168,64 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
 
 // BF16 path on MFMA.  grid (kWgSlices, 27), 256 threads = 4 waves; cin, cout <= 64.
 // dW_k[c][o] = sum_p X[in_p][c] dZ[out_p][o] is a [cin x P] x [P x cout] product with the pair
-// index as the contraction.  64 pairs at a time are staged into LDS transposed (channel-major,
+// index as the contraction.  128 pairs at a time are staged into LDS transposed (channel-major,
 // XT[c][p], GT[o][p]) so that both MFMA operands of v_mfma_f32_16x16x32_bf16 are one 16-byte
 // LDS read per lane:
 //   A (16 x 32): lane l gives XT[mb*16 + l%16][kk + 8(l/16) + j]
 //   B (32 x 16): lane l gives GT[nb*16 + l%16][kk + 8(l/16) + j]
 //   D: lane l holds dW[mb*16 + 4(l/16) + i][nb*16 + l%16]
-// Each chunk's product starts from zero and is added into a compensated total.
-constexpr int kWgChunk = 64;
+// A staging task is 4 consecutive pairs x 8 channels of X or dZ (at most 2 per thread).  The pair
+// indices are fetched two chunks ahead and the rows one chunk ahead, so the gathers overlap the
+// products.  Each chunk's product starts from zero and is added into a compensated total.
+constexpr int kWgChunk = 128;
 constexpr int kWgPitch = kWgChunk + 8;  // bf16 elements per LDS row (padding spreads banks)
+constexpr int kWgQuads = kWgChunk / 4;
+
+struct WgTask {
+  int pq, cc;  // pair quad, 8-channel group within X (isx) or dZ
+  bool isx, valid;
+};
+
+// Loads are unconditional (a missing pair reads pair pb, a missing row reads row 0; both exist
+// whenever the chunk does) so that the wait before a chunk's use only covers that chunk's loads.
+__device__ __forceinline__ void wg_indices(const int32_t *__restrict__ pairs, int64_t pb, int m, const WgTask &t,
+                                           int *r) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int p = 4 * t.pq + i;
+    const bool ok = t.valid && p < m;
+    const int v = pairs[2 * (pb + (ok ? p : 0)) + (t.isx ? 0 : 1)];
+    r[i] = ok ? v : -1;
+  }
+}
+
+__device__ __forceinline__ void wg_gather(const uint16_t *__restrict__ X, int cin, const uint16_t *__restrict__ G,
+                                          int cout, const WgTask &t, const int *r, uint4 *v) {
+  const uint16_t *src = t.isx ? X : G;
+  const int C = t.isx ? cin : cout;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool ok = r[i] >= 0;
+    const uint4 x = *reinterpret_cast<const uint4 *>(src + (ok ? (int64_t)r[i] * C + 8 * t.cc : 0));
+    v[i] = ok ? x : make_uint4(0, 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ uint32_t bf16_lane(const uint4 &v, int j) {
+  const uint32_t w = (j >> 1) == 0 ? v.x : (j >> 1) == 1 ? v.y : (j >> 1) == 2 ? v.z : v.w;
+  return (w >> ((j & 1) * 16)) & 0xffffu;
+}
+
+__device__ __forceinline__ void wg_store(uint16_t *XT, uint16_t *GT, const WgTask &t, const uint4 *v) {
+  if (!t.valid) return;
+  uint16_t *dst = t.isx ? XT : GT;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint2 pk2 = make_uint2(bf16_lane(v[0], j) | (bf16_lane(v[1], j) << 16),
+                                 bf16_lane(v[2], j) | (bf16_lane(v[3], j) << 16));
+    *reinterpret_cast<uint2 *>(dst + (8 * t.cc + j) * kWgPitch + 4 * t.pq) = pk2;
+  }
+}
 
 __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restrict__ X, int cin,
                                                           const uint16_t *__restrict__ dZ16,
@@ -144,58 +234,59 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
                                                           float *__restrict__ part) {
   __shared__ __attribute__((aligned(16))) uint16_t XT[64 * kWgPitch];
   __shared__ __attribute__((aligned(16))) uint16_t GT[64 * kWgPitch];
-  __shared__ int in_s[kWgChunk], out_s[kWgChunk];
   const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
   const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
   const int CB = (cin + 15) / 16, OB = (cout + 15) / 16, nblk = CB * OB;
   const int cin8 = (cin + 7) / 8, cout8 = (cout + 7) / 8;
+  WgTask task[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = tid + 256 * u;
+    int cc = t / kWgQuads;
+    task[u].pq = t % kWgQuads;
+    task[u].valid = cc < cin8 + cout8;
+    task[u].isx = cc < cin8;
+    task[u].cc = task[u].isx ? cc : cc - cin8;
+  }
   // channel rows past cin / cout stay zero
   for (int e = tid; e < 64 * kWgPitch; e += 256) {
     XT[e] = 0;
     GT[e] = 0;
   }
-  f32x4_t acc[4];
   Comp tot[4][4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int i = 0; i < 4; ++i) tot[j][i] = Comp{0.0f, 0.0f};
-  for (int64_t pb = p0; pb < p1; pb += kWgChunk) {
-    const int m = p1 - pb < kWgChunk ? (int)(p1 - pb) : kWgChunk;
-    __syncthreads();
-    if (tid < kWgChunk) {
-      in_s[tid] = tid < m ? pairs[2 * (pb + tid)] : -1;
-      out_s[tid] = tid < m ? pairs[2 * (pb + tid) + 1] : -1;
-    }
-    __syncthreads();
-    // task = 4 consecutive pairs x 8 channels; 16 pair-quads per chunk
-    for (int task = tid; task < 16 * (cin8 + cout8); task += 256) {
-      const int pq = task & 15;
-      int cc = task >> 4;
-      const bool isx = cc < cin8;
-      if (!isx) cc -= cin8;
-      const uint16_t *src = isx ? X : dZ16;
-      const int C = isx ? cin : cout;
-      uint16_t *dst = isx ? XT : GT;
-      uint4 v[4];
+  const int nch = (int)((p1 - p0 + kWgChunk - 1) / kWgChunk);
+  auto chunk_m = [&](int ch) {
+    const int64_t left = p1 - (p0 + (int64_t)ch * kWgChunk);
+    return left < kWgChunk ? (int)left : kWgChunk;
+  };
+  int rn[2][4];
+  uint4 v[2][4];
+  if (nch > 0) {  // an empty slice loads nothing (p0 may be the end of the pair list)
+    // the prefetches past the last chunk re-read the last chunk (no branch around a load)
+    const int c1 = nch > 1 ? 1 : 0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = isx ? in_s[4 * pq + i] : out_s[4 * pq + i];
-        v[i] = r >= 0 ? *reinterpret_cast<const uint4 *>(src + (int64_t)r * C + 8 * cc) : make_uint4(0, 0, 0, 0);
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int sh = (j & 1) * 16;
-        uint32_t w0 = (((j >> 1) == 0 ? v[0].x : (j >> 1) == 1 ? v[0].y : (j >> 1) == 2 ? v[0].z : v[0].w) >> sh) & 0xffffu;
-        uint32_t w1 = (((j >> 1) == 0 ? v[1].x : (j >> 1) == 1 ? v[1].y : (j >> 1) == 2 ? v[1].z : v[1].w) >> sh) & 0xffffu;
-        uint32_t w2 = (((j >> 1) == 0 ? v[2].x : (j >> 1) == 1 ? v[2].y : (j >> 1) == 2 ? v[2].z : v[2].w) >> sh) & 0xffffu;
-        uint32_t w3 = (((j >> 1) == 0 ? v[3].x : (j >> 1) == 1 ? v[3].y : (j >> 1) == 2 ? v[3].z : v[3].w) >> sh) & 0xffffu;
-        uint2 pk2 = make_uint2(w0 | (w1 << 16), w2 | (w3 << 16));
-        *reinterpret_cast<uint2 *>(dst + (8 * cc + j) * kWgPitch + 4 * pq) = pk2;
-      }
+    for (int u = 0; u < 2; ++u) {
+      wg_indices(pairs, p0, chunk_m(0), task[u], rn[u]);
+      wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);
+      wg_indices(pairs, p0 + (int64_t)c1 * kWgChunk, chunk_m(c1), task[u], rn[u]);
     }
+  }
+  for (int ch = 0; ch < nch; ++ch) {
+    __syncthreads();  // the previous chunk's operand reads are done
+#pragma unroll
+    for (int u = 0; u < 2; ++u) wg_store(XT, GT, task[u], v[u]);
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);
+    const int c2 = ch + 2 < nch ? ch + 2 : nch - 1;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) wg_indices(pairs, p0 + (int64_t)c2 * kWgChunk, chunk_m(c2), task[u], rn[u]);
+    f32x4_t acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -231,23 +322,30 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
   }
 }
 
+// Blocks [0, nbw) reduce dW over the slices (grid-stride, one entry per thread); each block
+// after them reduces db for 4 channels, one wave per channel: lane l adds partials l, l + 64, ...,
+// then a fixed butterfly adds the 64 lane totals; lane 0 writes.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
                                                            const float *__restrict__ dbpart, int cin, int cout,
-                                                           float *__restrict__ dW, float *__restrict__ db) {
-  const int64_t E = (int64_t)cin * cout;
-  const int64_t total = 27 * E + cout;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    Comp a{0.0f, 0.0f};
-    if (e < 27 * E) {
-      int64_t k = e / E, ce = e % E;
+                                                           int nbw, float *__restrict__ dW, float *__restrict__ db) {
+  if ((int)blockIdx.x < nbw) {
+    const int64_t E = (int64_t)cin * cout;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 27 * E; e += (int64_t)nbw * blockDim.x) {
+      Comp a{0.0f, 0.0f};
+      const int64_t k = e / E, ce = e % E;
       for (int s = 0; s < kWgSlices; ++s) a.add(wpart[(k * kWgSlices + s) * E + ce]);
       dW[e] = a.value();
-    } else {
-      int o = (int)(e - 27 * E);
-      for (int s = 0; s < kDbBlocks; ++s) a.add(dbpart[s * cout + o]);
-      db[o] = a.value();
     }
+    return;
   }
+  const int o = ((int)blockIdx.x - nbw) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (o >= cout) return;  // whole waves leave together
+  Comp a{0.0f, 0.0f};
+  for (int s = lane; s < kDbBlocks; s += 64) a.add(dbpart[s * cout + o]);
+  float t = a.value();
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) db[o] = t;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -279,11 +377,29 @@ extern "C" npvs_status npvs_conv_bwd_workspace_size(int32_t cin, int32_t cout, i
   return NPVS_OK;
 }
 
-extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
-                                           const float *dY, const int32_t *nbr, const int32_t *rb_off,
-                                           const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
-                                           int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
-                                           size_t ws_bytes, void *stream) {
+// One event per thread and device orders a second stream after the first.  Re-recording it is
+// safe: a wait takes the state the event had when the wait was enqueued.
+static npvs_status fork_event(hipEvent_t *ev) {
+  constexpr int kMaxDevices = 64;
+  thread_local hipEvent_t events[kMaxDevices] = {};
+  int dev = 0;
+  npvs_status st = check_hip(hipGetDevice(&dev), "npvs_sparse_conv_bwd_split");
+  if (st != NPVS_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd_split: device index");
+  if (!events[dev]) {
+    st = check_hip(hipEventCreateWithFlags(&events[dev], hipEventDisableTiming), "npvs_sparse_conv_bwd_split");
+    if (st != NPVS_OK) return st;
+  }
+  *ev = events[dev];
+  return NPVS_OK;
+}
+
+// dZ and the bias partials on s; the data gradient on s; the weight gradient and the reductions
+// on s2 (s2 == s: one stream; otherwise s2 first waits for the dZ of s).
+static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y, const float *dY,
+                            const int32_t *nbr, const int32_t *rb_off, const int32_t *rb_pairs,
+                            const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
+                            float *dW, float *db, void *ws, size_t ws_bytes, hipStream_t s, hipStream_t s2) {
   if (!X || !dY || !nbr || !rb_off || !rb_pairs || !counts || !dW || !db || !ws || (relu && !Y) || (dX && !Wt))
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: null pointer");
   if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: bad sizes");
@@ -300,14 +416,23 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   uint16_t *dZ16 = dtype == NPVS_BF16 ? reinterpret_cast<uint16_t *>(w + o16) : nullptr;
   float *wpart = reinterpret_cast<float *>(w + owp);
   float *dbpart = reinterpret_cast<float *>(w + odb);
-  hipStream_t s = as_stream(stream);
+  const int vec = cout % 4 == 0 && (reinterpret_cast<uintptr_t>(dY) & 15) == 0 &&
+                  (!relu || (reinterpret_cast<uintptr_t>(Y) & (dtype == NPVS_F32 ? 15 : 7)) == 0);
   if (dtype == NPVS_F32)
-    relu_grad_kernel<float><<<kDbBlocks, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, dZ32, nullptr, dbpart);
+    relu_grad_kernel<float><<<kDbBlocks, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, vec, dZ32, nullptr,
+                                                       dbpart);
   else
-    relu_grad_kernel<uint16_t><<<kDbBlocks, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, dZ32, dZ16,
-                                                          dbpart);
+    relu_grad_kernel<uint16_t><<<kDbBlocks, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, vec, dZ32,
+                                                          dZ16, dbpart);
   npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
   if (st != NPVS_OK) return st;
+  if (s2 != s) {
+    hipEvent_t ev;
+    st = fork_event(&ev);
+    if (st == NPVS_OK) st = check_hip(hipEventRecord(ev, s), "npvs_sparse_conv_bwd_split");
+    if (st == NPVS_OK) st = check_hip(hipStreamWaitEvent(s2, ev, 0), "npvs_sparse_conv_bwd_split");
+    if (st != NPVS_OK) return st;
+  }
   if (dX) {
     st = conv_fwd_dispatch(dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, Wt, nullptr, cin, nbr,
                            counts, cap_sites, dtype, 0, 1, dX, s, 0);
@@ -315,11 +440,31 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   }
   dim3 gw(kWgSlices, 27);
   if (dtype == NPVS_F32)
-    wgrad_partial_kernel<float><<<gw, 256, 0, s>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
+    wgrad_partial_kernel<float><<<gw, 256, 0, s2>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
   else if (cin <= 64)
-    wgrad_bf16_kernel<<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
+    wgrad_bf16_kernel<<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
   else
-    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
-  grad_reduce_kernel<<<stride_grid(27LL * cin * cout + cout, 256, 2048), 256, 0, s>>>(wpart, dbpart, cin, cout, dW, db);
+    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
+  const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbpart, cin, cout, nbw, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
+}
+
+extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
+                                           const float *dY, const int32_t *nbr, const int32_t *rb_off,
+                                           const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
+                                           int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
+                                           size_t ws_bytes, void *stream) {
+  return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
+                  ws_bytes, as_stream(stream), as_stream(stream));
+}
+
+extern "C" npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *Wt, int32_t cout,
+                                                 const void *Y, const float *dY, const int32_t *nbr,
+                                                 const int32_t *rb_off, const int32_t *rb_pairs,
+                                                 const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
+                                                 int32_t relu, float *dX, float *dW, float *db, void *ws,
+                                                 size_t ws_bytes, void *stream, void *wgrad_stream) {
+  return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
+                  ws_bytes, as_stream(stream), as_stream(wgrad_stream));
 }

@@ -44,17 +44,51 @@ __global__ void pack_f32_kernel(const float *__restrict__ W, int cin, int cout, 
   }
 }
 
-__global__ void pack_bf16_kernel(const float *__restrict__ W, int cin, int cout, int flip, uint16_t *__restrict__ P) {
+__device__ __forceinline__ void pack_bf16_entry(const float *__restrict__ W, int cin, int cout, int flip,
+                                                uint16_t *__restrict__ P, int64_t e) {
   const int CI = flip ? cout : cin, CO = flip ? cin : cout;
   const int KB = (CI + 31) / 32, NB = (CO + 15) / 16;
-  const int64_t total = 27LL * NB * KB * 64 * 8;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    int j = e & 7, lane = (e >> 3) & 63;
-    int64_t f = e >> 9;  // fragment index (k, nb, kb)
-    int kb = f % KB, nb = (f / KB) % NB, k = f / ((int64_t)KB * NB);
-    int c = kb * 32 + 8 * (lane >> 4) + j, o = nb * 16 + (lane & 15);
-    float v = (c < CI && o < CO) ? packed_src(W, cin, cout, flip, k, c, o) : 0.0f;
-    P[e] = f32_to_bf16(v);
+  int j = e & 7, lane = (e >> 3) & 63;
+  int64_t f = e >> 9;  // fragment index (k, nb, kb)
+  int kb = f % KB, nb = (f / KB) % NB, k = f / ((int64_t)KB * NB);
+  int c = kb * 32 + 8 * (lane >> 4) + j, o = nb * 16 + (lane & 15);
+  float v = (c < CI && o < CO) ? packed_src(W, cin, cout, flip, k, c, o) : 0.0f;
+  P[e] = f32_to_bf16(v);
+}
+
+// The buffer holds npvs_packed_weight_bytes() bytes, sized for the larger orientation; entries
+// past this orientation's fragments are zero, so the whole buffer is defined.
+__global__ void pack_bf16_kernel(const float *__restrict__ W, int cin, int cout, int flip, int64_t buf_elems,
+                                 uint16_t *__restrict__ P) {
+  const int CI = flip ? cout : cin, CO = flip ? cin : cout;
+  const int64_t total = 27LL * ((CO + 15) / 16) * ((CI + 31) / 32) * 64 * 8;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < buf_elems; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < total) pack_bf16_entry(W, cin, cout, flip, P, e);
+    else P[e] = 0;
+  }
+}
+
+// Batched packing: blockIdx.y selects the entry; each entry is grid-strided over blockIdx.x.
+struct PackBatch {
+  npvs_pack_desc d[NPVS_MAX_PACK];
+  int64_t elems[NPVS_MAX_PACK];  // buffer entries (npvs_packed_weight_bytes / element size)
+};
+
+__global__ void pack_batch_kernel(PackBatch PB, int dtype) {
+  const npvs_pack_desc &D = PB.d[blockIdx.y];
+  const int flip = D.flip_transpose ? 1 : 0;
+  const int CI = flip ? D.cout : D.cin, CO = flip ? D.cin : D.cout;
+  const int64_t total = dtype == NPVS_F32 ? 27LL * CI * CO : 27LL * ((CO + 15) / 16) * ((CI + 31) / 32) * 64 * 8;
+  const int64_t buf = PB.elems[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < buf; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e >= total) {
+      static_cast<uint16_t *>(D.Wp)[e] = 0;  // only the BF16 layout has a tail
+    } else if (dtype == NPVS_F32) {
+      const int o = e % CO, c = (e / CO) % CI, k = e / ((int64_t)CO * CI);
+      static_cast<float *>(D.Wp)[e] = packed_src(D.W, D.cin, D.cout, flip, k, c, o);
+    } else {
+      pack_bf16_entry(D.W, D.cin, D.cout, flip, static_cast<uint16_t *>(D.Wp), e);
+    }
   }
 }
 
@@ -148,6 +182,33 @@ __global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restri
 // The partial sums of the waves are added in LDS in wave order (deterministic) and every wave
 // finishes some of the 16 x 16 output blocks (bias, ReLU, rounding, store).
 // ------------------------------------------------------------------------------------------
+// 8 channels [c, c + 8) of row i of X, or zero when i < 0 or c >= cin.  The load itself is
+// unconditional (a missing row reads row 0, which exists whenever a tile does, and the value is
+// discarded), so the loads of a stage are the same on every path and the wait before the MFMAs
+// of a stage only covers that stage's loads, not the ones prefetched after it.
+__device__ __forceinline__ bf16x8_t gather8(const uint16_t *__restrict__ X, int cin, int i, int c) {
+  const bool ok = i >= 0 && c < cin;
+  const bf16x8_t v = *reinterpret_cast<const bf16x8_t *>(X + (ok ? (int64_t)i * cin + c : 0));
+  return ok ? v : bf16x8_t{};
+}
+
+// Zero as a value the compiler cannot see through, taken once per tile and added to the weight
+// index: the weight loads then stay inside the tile loop instead of being hoisted out of it into
+// registers for all tiles (which would cost the occupancy the gather latency needs), and the
+// pointer keeps its global address space.  The empty asm emits no instruction.
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
+// Neighbour index of row r for offset k, or -1 past the last site (unconditional load of a row
+// that exists: r is clamped to n - 1).
+__device__ __forceinline__ int nbr_index(const int32_t *__restrict__ nbr, int cap, int k, int r, int n) {
+  const int v = nbr[(int64_t)k * cap + (r < n ? r : n - 1)];
+  return r < n ? v : -1;
+}
+
 template <int NB>
 __device__ __forceinline__ void conv_bf16_epilogue(const f32x4_t &acc, int r, int n, int o, int cout,
                                                    const float *__restrict__ bias, int relu, int out_f32, void *Y) {
@@ -187,19 +248,16 @@ __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int kbeg = wv * KPER;
   const int csub = 8 * (lane >> 4);
-  const bf16x8_t zero8 = {};
   for (int j = 0;; ++j) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
     if (tile < 0) break;
     const int row0 = tile * ROWS;
+    const bf16x8_t *W = Wp + opaque_zero();
     int idx[KPER][MB];
 #pragma unroll
     for (int q = 0; q < KPER; ++q)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int r = row0 + mb * 16 + (lane & 15);
-        idx[q][mb] = r < n ? nbr[(int64_t)(kbeg + q) * cap + r] : -1;
-      }
+      for (int mb = 0; mb < MB; ++mb) idx[q][mb] = nbr_index(nbr, cap, kbeg + q, row0 + mb * 16 + (lane & 15), n);
     bool act[KPER];
 #pragma unroll
     for (int q = 0; q < KPER; ++q) {
@@ -217,18 +275,12 @@ __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16
 #pragma unroll
     for (int st = -(PD - 1); st < S; ++st) {
       const int ld = st + PD - 1;  // stage whose loads are issued now
-      if (ld < S) {
+      if (ld < S) {  // compile-time after unrolling; loads are issued even for skipped offsets
         const int q = ld / KB, kb = ld % KB, slot = ld % PD;
-        if (act[q]) {
-          const int c = kb * 32 + csub;
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            bx[slot][mb] = (idx[q][mb] >= 0 && c < cin)
-                               ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[q][mb] * cin + c)
-                               : zero8;
+        for (int mb = 0; mb < MB; ++mb) bx[slot][mb] = gather8(X, cin, idx[q][mb], kb * 32 + csub);
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) aw[slot][nb] = Wp[(((int64_t)(kbeg + q) * NB + nb) * KB + kb) * 64 + lane];
-        }
+        for (int nb = 0; nb < NB; ++nb) aw[slot][nb] = W[(((int64_t)(kbeg + q) * NB + nb) * KB + kb) * 64 + lane];
       }
       if (st >= 0 && act[st / KB]) {
         const int slot = st % PD;
@@ -284,19 +336,16 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
   const int ntiles = (n + ROWS - 1) / ROWS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int csub = 8 * (lane >> 4);
-  const bf16x8_t zero8 = {};
   for (int j = 0;; ++j) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
     if (tile < 0) break;
     const int row0 = tile * ROWS + wv * 16 * MB;
+    const bf16x8_t *W = Wp + opaque_zero();
     int idx[27][MB];
 #pragma unroll
     for (int q = 0; q < 27; ++q)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int r = row0 + mb * 16 + (lane & 15);
-        idx[q][mb] = r < n ? nbr[(int64_t)q * cap + r] : -1;
-      }
+      for (int mb = 0; mb < MB; ++mb) idx[q][mb] = nbr_index(nbr, cap, q, row0 + mb * 16 + (lane & 15), n);
     f32x4_t acc[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -306,32 +355,23 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
     // prologue: offset 0's weights into LDS slot 0, its rows into registers
 #pragma unroll
     for (int i = 0; i < WPT; ++i)
-      if (tid + i * 64 * RG < FR * 64) Ws[0][tid + i * 64 * RG] = Wp[tid + i * 64 * RG];
+      if (FR % RG == 0 || tid + i * 64 * RG < FR * 64) Ws[0][tid + i * 64 * RG] = W[tid + i * 64 * RG];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int c = kb * 32 + csub;
-        bx[0][mb][kb] = (idx[0][mb] >= 0 && c < cin)
-                            ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[0][mb] * cin + c)
-                            : zero8;
-      }
+      for (int mb = 0; mb < MB; ++mb) bx[0][mb][kb] = gather8(X, cin, idx[0][mb], kb * 32 + csub);
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
       const int cur = k & 1, nxt = (k + 1) & 1;
       if (k + 1 < 27) {  // loads of offset k + 1
 #pragma unroll
         for (int i = 0; i < WPT; ++i)
-          if (tid + i * 64 * RG < FR * 64) wreg[i] = Wp[(int64_t)(k + 1) * FR * 64 + tid + i * 64 * RG];
+          if (FR % RG == 0 || tid + i * 64 * RG < FR * 64)
+            wreg[i] = W[(int64_t)(k + 1) * FR * 64 + tid + i * 64 * RG];
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb) {
-            const int c = kb * 32 + csub;
-            bx[nxt][mb][kb] = (idx[k + 1][mb] >= 0 && c < cin)
-                                  ? *reinterpret_cast<const bf16x8_t *>(X + (int64_t)idx[k + 1][mb] * cin + c)
-                                  : zero8;
-          }
+          for (int mb = 0; mb < MB; ++mb) bx[nxt][mb][kb] = gather8(X, cin, idx[k + 1][mb], kb * 32 + csub);
       }
       __syncthreads();  // slot cur holds offset k's weights; slot nxt is no longer read
       bool a = false;
@@ -351,7 +391,7 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
       if (k + 1 < 27) {
 #pragma unroll
         for (int i = 0; i < WPT; ++i)
-          if (tid + i * 64 * RG < FR * 64) Ws[nxt][tid + i * 64 * RG] = wreg[i];
+          if (FR % RG == 0 || tid + i * 64 * RG < FR * 64) Ws[nxt][tid + i * 64 * RG] = wreg[i];
       }
     }
 #pragma unroll
@@ -439,12 +479,35 @@ extern "C" npvs_status npvs_pack_weights(const float *W, int32_t cin, int32_t co
     pack_f32_kernel<<<stride_grid(27LL * cin * cout, 256, 1024), 256, 0, s>>>(W, cin, cout, flip_transpose ? 1 : 0,
                                                                              (float *)Wp);
   } else if (dtype == NPVS_BF16) {
-    pack_bf16_kernel<<<stride_grid(npvs_packed_weight_bytes(cin, cout, dtype) / 2, 256, 1024), 256, 0, s>>>(
-        W, cin, cout, flip_transpose ? 1 : 0, (uint16_t *)Wp);
+    const int64_t buf = (int64_t)npvs_packed_weight_bytes(cin, cout, dtype) / 2;
+    pack_bf16_kernel<<<stride_grid(buf, 256, 1024), 256, 0, s>>>(W, cin, cout, flip_transpose ? 1 : 0, buf,
+                                                                  (uint16_t *)Wp);
   } else {
     return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights: dtype must be NPVS_F32 or NPVS_BF16");
   }
   return check_hip(hipGetLastError(), "npvs_pack_weights");
+}
+
+extern "C" npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int32_t dtype, void *stream) {
+  if (n < 0 || n > NPVS_MAX_PACK) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_batch: n out of range");
+  if (n == 0) return NPVS_OK;
+  if (!descs) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_batch: null descriptors");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_batch: dtype must be NPVS_F32 or NPVS_BF16");
+  PackBatch PB = {};
+  size_t most = 0;
+  for (int i = 0; i < n; ++i) {
+    const npvs_pack_desc &D = descs[i];
+    if (!D.W || !D.Wp) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_batch: null pointer");
+    if (D.cin < 1 || D.cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_batch: channels must be >= 1");
+    PB.d[i] = D;
+    const size_t e = npvs_packed_weight_bytes(D.cin, D.cout, dtype) / (dtype == NPVS_F32 ? 4 : 2);
+    PB.elems[i] = (int64_t)e;
+    most = e > most ? e : most;
+  }
+  dim3 grid(stride_grid((int64_t)most, 256, 256), n);
+  pack_batch_kernel<<<grid, 256, 0, as_stream(stream)>>>(PB, dtype);
+  return check_hip(hipGetLastError(), "npvs_pack_weights_batch");
 }
 
 namespace npvs {

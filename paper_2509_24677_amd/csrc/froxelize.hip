@@ -103,7 +103,6 @@ __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__
                                                         TriSetup *__restrict__ recs, int32_t *__restrict__ tile_count,
                                                         int32_t *__restrict__ tile_list) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
   int ntl = 0, tx0 = 0, ty0 = 0, tz0 = 0, ntx = 1, nty = 1, toff = 0, tys = 1, txs = 1;
   if (t < total) {
     const GridDesc &g = B.g[tri_grid(B, t)];
@@ -159,9 +158,11 @@ __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__
       tys = g.tiles_y;
     }
   }
-  // Append to each covered tile; in each round the lanes that target the same tile share one
-  // counter update.
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // Append to each covered tile.  Triangles of one object tend to be consecutive and to share
+  // tiles, so in each round a run of consecutive lanes that target the same tile shares one
+  // counter update (made by the run's first lane); lanes of unrelated triangles update their own
+  // counters in parallel.
+  const int lane = threadIdx.x & 63;
   for (int j = 0;; ++j) {
     const bool active = j < ntl;
     if (__ballot(active) == 0ull) break;
@@ -170,59 +171,53 @@ __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__
       const int ix = j % ntx, iy = (j / ntx) % nty, iz = j / (ntx * nty);
       tile = toff + ((tz0 + iz) * tys + (ty0 + iy)) * txs + (tx0 + ix);
     }
-    int slot = -1;
-    uint64_t pending = __ballot(active);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int lt = __shfl(tile, leader, 64);
-      const uint64_t same = __ballot(active && tile == lt);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&tile_count[lt], __popcll(same));
-      base = __shfl(base, leader, 64);
-      if (active && tile == lt) slot = base + __popcll(same & below);
-      pending &= ~same;
+    // runs: maximal groups of consecutive lanes with the same tile (inactive lanes have tile -1,
+    // so they form runs of their own and never make an update)
+    const int prev = __shfl_up(tile, 1, 64);
+    const uint64_t starts = __ballot(lane == 0 || prev != tile);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
+    const int first = 63 - __clzll((long long)(starts & upto));    // start of this lane's run
+    int base = 0;
+    if (active && first == lane) {
+      const uint64_t later = starts & ~upto;
+      const int next = later ? __ffsll((long long)later) - 1 : 64;  // the run is [lane, next)
+      base = atomicAdd(&tile_count[tile], next - lane);
     }
-    if (active && slot < kFroxTileCap) tile_list[(int64_t)tile * kFroxTileCap + slot] = (int32_t)t;
+    base = __shfl(base, first, 64);
+    if (active) {
+      const int slot = base + (lane - first);
+      if (slot < kFroxTileCap) tile_list[(int64_t)tile * kFroxTileCap + slot] = (int32_t)t;
+    }
   }
 }
 
-// ORs the froxels of the triangle inside the tile with origin (X0, Y0, Z0) into the LDS mask
-// (word (z - Z0) * 8 + (y - Y0), bit x - X0).
-__device__ __forceinline__ void frox_triangle(const TriSetup &S, int X0, int Y0, int Z0, uint32_t *mask) {
-  const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
-  const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
-  const int za = S.lo[2] > Z0 ? S.lo[2] : Z0, zb = S.hi[2] < Z0 + 7 ? S.hi[2] : Z0 + 7;
-  if (xa > xb || ya > yb || za > zb) return;
-  for (int z = za; z <= zb; ++z)
-    for (int y = ya; y <= yb; ++y) {
-      bool row_ok = true;  // the edge x x-axis tests do not depend on x
+// Froxels x in [xa, xb] of row (y, z) that the triangle meets, as bits x - X0 of a 32-bit word.
+__device__ __forceinline__ uint32_t frox_row(const TriSetup &S, int xa, int xb, int y, int z, int X0) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int32_t s = S.e[i][2] * y - S.e[i][1] * z;
-        row_ok = row_ok && s >= S.L[i][0] && s <= S.H[i][0];
-      }
-      if (!row_ok) continue;
-      int32_t sy[3], sz[3];
+  for (int i = 0; i < 3; ++i) {  // the edge x x-axis tests do not depend on x
+    const int32_t s = S.e[i][2] * y - S.e[i][1] * z;
+    if (s < S.L[i][0] || s > S.H[i][0]) return 0u;
+  }
+  int32_t sy[3], sz[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        sy[i] = -S.e[i][2] * xa + S.e[i][0] * z;
-        sz[i] = S.e[i][1] * xa - S.e[i][0] * y;
-      }
-      int64_t sn = S.n[0] * xa + S.n[1] * y + S.n[2] * z;
-      uint32_t m = 0;
-      for (int x = xa; x <= xb; ++x) {
-        bool hit = sn >= S.nL && sn <= S.nH;
+  for (int i = 0; i < 3; ++i) {
+    sy[i] = -S.e[i][2] * xa + S.e[i][0] * z;
+    sz[i] = S.e[i][1] * xa - S.e[i][0] * y;
+  }
+  int64_t sn = S.n[0] * xa + S.n[1] * y + S.n[2] * z;
+  uint32_t m = 0;
+  for (int x = xa; x <= xb; ++x) {
+    bool hit = sn >= S.nL && sn <= S.nH;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          hit = hit && sy[i] >= S.L[i][1] && sy[i] <= S.H[i][1] && sz[i] >= S.L[i][2] && sz[i] <= S.H[i][2];
-          sy[i] -= S.e[i][2];
-          sz[i] += S.e[i][1];
-        }
-        sn += S.n[0];
-        m |= (uint32_t)hit << (x - X0);
-      }
-      if (m) atomicOr(mask + (z - Z0) * 8 + (y - Y0), m);
+    for (int i = 0; i < 3; ++i) {
+      hit = hit && sy[i] >= S.L[i][1] && sy[i] <= S.H[i][1] && sz[i] >= S.L[i][2] && sz[i] <= S.H[i][2];
+      sy[i] -= S.e[i][2];
+      sz[i] += S.e[i][1];
     }
+    sn += S.n[0];
+    m |= (uint32_t)hit << (x - X0);
+  }
+  return m;
 }
 
 __device__ __forceinline__ const GridDesc &tile_grid(const Batch &B, int tile) {
@@ -283,15 +278,22 @@ __global__ __launch_bounds__(1024) void frox_plan_kernel(Batch B, const int32_t 
   if (tid == 0) *n_parts = running;
 }
 
-// Grid-stride over the part list; 256 threads, one triangle per thread.
+// Grid-stride over the part list; 256 threads.  The part's triangles are taken 256 at a time:
+// their setup records go to LDS, a scan of the number of tile rows (y, z) each one covers gives
+// a flat list of (triangle, row) items, and each thread tests the froxels of one row at a time,
+// so a triangle that covers the whole tile costs 64 short rows spread over the workgroup rather
+// than one long loop on one lane.
 __global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriSetup *__restrict__ recs,
                                                          const int32_t *__restrict__ tile_count,
                                                          const int32_t *__restrict__ tile_list,
                                                          const int32_t *__restrict__ part_list,
                                                          const int32_t *__restrict__ n_parts,
                                                          uint32_t *__restrict__ partial) {
+  __shared__ TriSetup srec[256];
+  __shared__ int row0[257];  // exclusive scan of the rows of the staged triangles
+  __shared__ int wsum[4];
   __shared__ uint32_t mask[kTileWords];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int np = *n_parts;
   for (int pi = blockIdx.x; pi < np; pi += gridDim.x) {
     const int code = part_list[pi];
@@ -303,11 +305,51 @@ __global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriSetup 
     int X0, Y0, Z0;
     tile_origin(g, tile, X0, Y0, Z0);
     if (tid < kTileWords) mask[tid] = 0;
-    __syncthreads();
     const int i1 = (part + 1) * per < items ? (part + 1) * per : items;
-    for (int i = part * per + tid; i < i1; i += 256) {
-      const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + i] : g.tri_off + i;
-      frox_triangle(recs[t], X0, Y0, Z0, mask);
+    for (int c0 = part * per; c0 < i1; c0 += 256) {
+      const int i = c0 + tid;
+      int rows = 0;
+      if (i < i1) {
+        const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + i] : g.tri_off + i;
+        const TriSetup S = recs[t];
+        srec[tid] = S;
+        const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+        const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
+        const int za = S.lo[2] > Z0 ? S.lo[2] : Z0, zb = S.hi[2] < Z0 + 7 ? S.hi[2] : Z0 + 7;
+        if (xa <= xb && ya <= yb && za <= zb) rows = (yb - ya + 1) * (zb - za + 1);
+      }
+      int x = rows;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (lane == 63) wsum[w] = x;
+      __syncthreads();  // also orders the previous chunk's reads of srec / row0 before these writes
+      int pre = 0;
+      for (int k = 0; k < w; ++k) pre += wsum[k];
+      row0[tid] = pre + x - rows;
+      if (tid == 255) row0[256] = pre + x;
+      __syncthreads();
+      const int R = row0[256];
+      const int n = i1 - c0 < 256 ? i1 - c0 : 256;
+      for (int r = tid; r < R; r += 256) {
+        int lo = 0, hi = n - 1;  // last staged triangle whose rows start at or before r
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (row0[mid] <= r) lo = mid;
+          else hi = mid - 1;
+        }
+        const TriSetup &S = srec[lo];
+        const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+        const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
+        const int za = S.lo[2] > Z0 ? S.lo[2] : Z0;
+        const int rr = r - row0[lo], ny = yb - ya + 1;
+        const int y = ya + rr % ny, z = za + rr / ny;
+        const uint32_t m = frox_row(S, xa, xb, y, z, X0);
+        if (m) atomicOr(mask + (z - Z0) * 8 + (y - Y0), m);
+      }
+      __syncthreads();  // srec and row0 are rewritten by the next chunk
     }
     __syncthreads();
     if (tid < kTileWords) partial[((int64_t)tile * kMaxParts + part) * kTileWords + tid] = mask[tid];

@@ -124,9 +124,15 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict_
   }
 }
 
+// c1, c2 come from `coef` (the device step state) when it is given.
 __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ g,
                                                     float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
-                                                    float b1, float b2, float eps, float wd, float c1, float c2) {
+                                                    float b1, float b2, float eps, float wd, float c1, float c2,
+                                                    const npvs_adam_step *__restrict__ coef) {
+  if (coef) {
+    c1 = coef->c1;
+    c2 = coef->c2;
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i] + wd * p[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
@@ -135,6 +141,13 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const 
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   }
+}
+
+__global__ void adam_step_kernel(npvs_adam_step *st, float b1, float b2) {
+  const int64_t t = st->t + 1;
+  st->t = t;
+  st->c1 = 1.0f - (float)pow((double)b1, (double)t);
+  st->c2 = 1.0f - (float)pow((double)b2, (double)t);
 }
 
 }  // namespace npvs
@@ -177,6 +190,17 @@ extern "C" npvs_status npvs_adam(float *p, const float *g, float *m, float *v, i
   const float c1 = 1.0f - (float)std::pow((double)beta1, (double)t);
   const float c2 = 1.0f - (float)std::pow((double)beta2, (double)t);
   adam_kernel<<<stride_grid(n, 256, 2048), 256, 0, as_stream(stream)>>>(p, g, m, v, n, lr, beta1, beta2, eps,
-                                                                         weight_decay, c1, c2);
+                                                                         weight_decay, c1, c2, nullptr);
   return check_hip(hipGetLastError(), "npvs_adam");
+}
+
+extern "C" npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
+                                    float lr, float beta1, float beta2, float eps, float weight_decay, void *stream) {
+  if (!p || !g || !m || !v || !step || n < 0) return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev: bad arguments");
+  hipStream_t s = as_stream(stream);
+  adam_step_kernel<<<1, 1, 0, s>>>(step, beta1, beta2);
+  if (n > 0)
+    adam_kernel<<<stride_grid(n, 256, 2048), 256, 0, s>>>(p, g, m, v, n, lr, beta1, beta2, eps, weight_decay, 0.0f,
+                                                          0.0f, step);
+  return check_hip(hipGetLastError(), "npvs_adam_dev");
 }

@@ -16,8 +16,10 @@ from __future__ import annotations
 
 import torch
 
-from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam, build_rulebook, deinterleave_threshold, froxelize,
-               gather_input, loss, pack_weights, sparse_conv_bwd, sparse_conv_fwd)
+from . import _lib as L
+from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam_dev, build_rulebook, deinterleave_threshold, froxelize,
+               conv_bwd_workspace, gather_input, loss, pack_weights, pack_weights_batch, sparse_conv_bwd,
+               sparse_conv_fwd)
 
 
 class Network:
@@ -52,13 +54,17 @@ class Network:
         return len(self.W)
 
     def repack(self):
+        """Packs every layer for the forward and the data-gradient convolutions in one launch,
+        in place, so captured graphs keep reading the current weights."""
         for i, W in enumerate(self.W):
             if self.Wp[i] is None:
-                self.Wp[i] = pack_weights(W, self.dtype)
-                self.Wt[i] = pack_weights(W, self.dtype, flip_transpose=True)
-            else:  # in place, so captured graphs keep reading the current weights
-                self.Wp[i].copy_(pack_weights(W, self.dtype))
-                self.Wt[i].copy_(pack_weights(W, self.dtype, flip_transpose=True))
+                nbytes = L.get().npvs_packed_weight_bytes(W.shape[1], W.shape[2], self.dtype)
+                self.Wp[i] = torch.empty(nbytes, dtype=torch.uint8, device=W.device)
+                self.Wt[i] = torch.empty(nbytes, dtype=torch.uint8, device=W.device)
+        items = [(W, self.Wp[i], False) for i, W in enumerate(self.W)]
+        items += [(W, self.Wt[i], True) for i, W in enumerate(self.W)]
+        for j in range(0, len(items), L.NPVS_MAX_PACK):
+            pack_weights_batch(items[j:j + L.NPVS_MAX_PACK], self.dtype)
 
     def layer(self, i: int, X: torch.Tensor, rb: Rulebook) -> torch.Tensor:
         last = i == self.n_layers - 1
@@ -108,11 +114,20 @@ class Network:
             X = self.layer(i, X, rb)
         return X, saved
 
-    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook):
+    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True):
         """Hand-written backward through the stack; recomputes the layer inputs that were not
-        saved.  Returns [(dW, db)] per layer."""
+        saved.  With `overlap`, each layer's weight gradient runs on a side stream while the data
+        gradient continues down the stack; the side stream is joined before returning.  The
+        gradients land in the flat gradient buffer; returns [(dW, db)] per layer (views of it)."""
         grads = [None] * self.n_layers
         outputs = {self.n_layers - 1: logits}
+        main = torch.cuda.current_stream()
+        side = None
+        if overlap:
+            if getattr(self, "_side", None) is None:
+                self._side = torch.cuda.Stream()
+            side = self._side
+        in_use = []  # tensors the side stream reads: alive until it is joined
         dY = dlogits
         for i in range(self.n_layers - 1, -1, -1):
             X = saved.get(i)
@@ -121,13 +136,18 @@ class Network:
             Y = outputs.get(i)
             if Y is None:
                 Y = self.layer(i, X, rb)
+            ws = conv_bwd_workspace(self.channels[i], self.channels[i + 1], rb, self.dtype)
             dX, dW, db = sparse_conv_bwd(X, self.Wt[i], self.channels[i], self.channels[i + 1], Y, dY, rb,
                                          self.dtype, relu=i < self.n_layers - 1, want_dx=i > 0,
-                                         dW=self.gW[i], db=self.gb[i])
+                                         dW=self.gW[i], db=self.gb[i], ws=ws, wgrad_stream=side)
+            in_use += [X, ws]
             grads[i] = (dW, db)
             if i > 0:
                 outputs[i - 1] = X
             dY = dX
+        if side is not None:
+            main.wait_stream(side)
+        del in_use
         return grads
 
 
@@ -143,7 +163,8 @@ class Trainer:
         self.checkpoint = checkpoint
         self.m = torch.zeros_like(net.flat)
         self.v = torch.zeros_like(net.flat)
-        self.step_count = 0
+        self.adam_step = torch.zeros(16, dtype=torch.uint8, device=net.flat.device)  # npvs_adam_step, t = 0
+        self.step_count = 0  # host mirror of the device counter (eager calls only)
 
     def step(self, tris: torch.Tensor, label_bits: torch.Tensor):
         net = self.net
@@ -156,7 +177,7 @@ class Trainer:
         stats, dl = loss(logits, labels, rb, self.lam)
         net.backward(saved, logits, dl, rb)  # gradients land in net.gflat
         self.step_count += 1
-        adam(net.flat, net.gflat, self.m, self.v, self.step_count, lr=self.lr, weight_decay=self.wd)
+        adam_dev(net.flat, net.gflat, self.m, self.v, self.adam_step, lr=self.lr, weight_decay=self.wd)
         net.repack()
         return stats, pvs
 

@@ -33,6 +33,22 @@ def test_version_and_sizes(lib):
     assert n.value > 50000 * 48
 
 
+def test_header_constants_match_binding():
+    text = open(L.HEADER).read()
+    for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK"):
+        assert f"#define {name} {getattr(L, name)}" in text, name
+    assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16
+    assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes
+
+
+def test_batched_packing_argument_checks(lib):
+    assert lib.npvs_pack_weights_batch(0, None, L.NPVS_BF16, None) == L.NPVS_OK
+    assert lib.npvs_pack_weights_batch(L.NPVS_MAX_PACK + 1, None, L.NPVS_BF16, None) == L.NPVS_ERR_INVALID_ARG
+    d = (L.PackDesc * 1)(L.PackDesc(None, None, 8, 8, 0, 0))
+    assert lib.npvs_pack_weights_batch(1, ctypes.cast(d, ctypes.c_void_p), L.NPVS_BF16, None) == L.NPVS_ERR_INVALID_ARG
+    assert b"null pointer" in lib.npvs_last_error()
+
+
 @pytest.mark.parametrize("dims,d,msg", [
     ([(250, 256, 128)], 4, "multiple of 8"),
     ([(256, 256, 126)], 4, "multiples of d"),

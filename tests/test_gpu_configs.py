@@ -32,14 +32,14 @@ def _train_setup():
     return cfg, tri_list, labels
 
 
-def _grads(net, tris, counts, dims, lab_bits, checkpoint):
+def _grads(net, tris, counts, dims, lab_bits, checkpoint, overlap=True):
     occ = npvs.froxelize(tris, counts, dims)
     rb = npvs.build_rulebook(occ, dims, net.d, csr=True)
     X0 = npvs.gather_input(occ, rb, net.dtype)
     logits, saved = net.forward(X0, rb, checkpoint=checkpoint)
     labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
     stats, dl = npvs.loss(logits, labels, rb)
-    grads = net.backward(saved, logits, dl, rb)
+    grads = net.backward(saved, logits, dl, rb, overlap=overlap)
     # the gradients are views of the network's flat gradient buffer: keep copies
     return stats, [(a.clone(), b.clone()) for a, b in grads], rb
 
@@ -84,6 +84,52 @@ def test_checkpointed_recompute_gives_identical_gradients(dtype):
     for (a, b), (c, d) in zip(g1, g2):
         np.testing.assert_array_equal(to_np(a), to_np(c))
         np.testing.assert_array_equal(to_np(b), to_np(d))
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_weight_gradient_on_side_stream_gives_identical_gradients(dtype):
+    cfg, tri_list, labels = _train_setup()
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    tris, counts = upload_tris(tri_list)
+    lab_bits = torch.from_numpy(np.concatenate([l.reshape(-1) for l in labels])).to(DEV)
+    net = Network(layers, cfg.d, dtype)
+    _, g1, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, overlap=True)
+    _, g2, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, overlap=False)
+    for (a, b), (c, d) in zip(g1, g2):
+        np.testing.assert_array_equal(to_np(a), to_np(c))
+        np.testing.assert_array_equal(to_np(b), to_np(d))
+
+
+def test_captured_training_step_replays_equal_eager_steps():
+    """A training step captured in a graph (two streams, device-side Adam counter) and replayed
+    three times ends in the same weights and moments as three eager steps."""
+    cfg, tri_list, labels = _train_setup()
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    tris, counts = upload_tris(tri_list)
+    lab_bits = torch.from_numpy(np.concatenate([l.reshape(-1) for l in labels])).to(DEV)
+    trainers = []
+    for _ in range(2):
+        net = Network(layers, cfg.d, npvs.NPVS_BF16)
+        trainers.append(Trainer(net, cfg.grids, counts))
+    eager, graphed = trainers
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        eager.step(tris, lab_bits)  # warm-up step on both (allocator and library state)
+        graphed.step(tris, lab_bits)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        stats_g, _ = graphed.step(tris, lab_bits)
+    for _ in range(3):
+        stats_e, _ = eager.step(tris, lab_bits)
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(stats_g), to_np(stats_e))
+    for a, b in ((eager.net.flat, graphed.net.flat), (eager.m, graphed.m), (eager.v, graphed.v)):
+        np.testing.assert_array_equal(to_np(a), to_np(b))
+    assert int(graphed.adam_step[:8].view(torch.int64).item()) == 4
 
 
 def test_trainer_step_applies_adam_to_the_gradient():

@@ -264,6 +264,22 @@ def test_conv_weight_packing_flip_transpose_is_dgrad_weight():
     np.testing.assert_allclose(to_np(dX)[:n], want, rtol=0, atol=2e-5)
 
 
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_batched_packing_equals_single_packings(dtype):
+    rng = np.random.default_rng(7)
+    shapes = [(8, 16), (64, 64), (24, 40), (512, 64), (64, 8)]
+    Ws = [torch.from_numpy(rng.normal(size=(27, ci, co)).astype(np.float32)).to(DEV) for ci, co in shapes]
+    items, want = [], []
+    for W in Ws:
+        for flip in (False, True):
+            ref = npvs.pack_weights(W, dtype, flip_transpose=flip)
+            items.append((W, torch.full_like(ref, 0xAB), flip))
+            want.append(ref)
+    npvs.pack_weights_batch(items, dtype)
+    for (_, got, _), ref in zip(items, want):
+        np.testing.assert_array_equal(to_np(got), to_np(ref))
+
+
 def test_conv_rows_beyond_n_untouched_and_deterministic():
     rb, ref, X, W, b = _conv_case(64, 64)
     n = ref["n"]

@@ -165,3 +165,18 @@ def test_adam_matches_oracle():
         npvs.adam(tp, torch.from_numpy(g).to(DEV), tm, tv, t)
         rp, rm, rv = oracle.adam(rp, g, rm, rv, t)
     assert np.abs(to_np(tp) - rp).max() <= 1e-6
+
+
+def test_adam_with_device_step_equals_host_step():
+    rng = np.random.default_rng(9)
+    p = rng.normal(size=3000).astype(np.float32)
+    gs = [torch.from_numpy(rng.normal(size=3000).astype(np.float32)).to(DEV) for _ in range(4)]
+    a = [torch.from_numpy(x).to(DEV) for x in (p, np.zeros_like(p), np.zeros_like(p))]
+    b = [x.clone() for x in a]
+    step = torch.zeros(16, dtype=torch.uint8, device=DEV)
+    for t, g in enumerate(gs, start=1):
+        npvs.adam(a[0], g, a[1], a[2], t)
+        npvs.adam_dev(b[0], g, b[1], b[2], step)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(to_np(x), to_np(y))
+    assert int(step[:8].view(torch.int64).item()) == 4
