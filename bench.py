@@ -43,6 +43,30 @@ def parse():
     return ap.parse_args()
 
 
+def conv_traffic(variant):
+    """HBM bytes per launch of the timed hidden-layer conv in tile shape `variant`, from the counter
+    summary under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size);
+    None when that summary is missing or was taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "conv_fwd_bf16_city256_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    for src in ("conv.hip", "npvs_common.hpp"):
+        h = hashlib.sha256(open(os.path.join(ROOT, "paper_2509_24677_amd", "csrc", src), "rb").read()).hexdigest()
+        if f"{src} {h}" not in text:
+            return None
+    shapes = {0: (1, 9), 1: (2, 1), 2: (1, 3), 3: (2, 3), 4: (1, 1), 5: (2, 9)}
+    lds = {6: (1, 4), 7: (1, 2), 8: (2, 2), 9: (1, 8)}
+    name = (f"conv_fwd_bf16_kernel<2, 4, {shapes[variant][0]}, {shapes[variant][1]}>" if variant in shapes
+            else f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>")
+    for line in text.splitlines():
+        parts = line.rsplit(None, 3)
+        if len(parts) == 4 and parts[0] == name:
+            return int(parts[3])
+    return None
+
+
 def bench_batch16(args, dev, timed_launches):
     """16 viewcell grids of uneven size (64^3 .. 256x256x128) and occupancy (1-10 %) through the
     BF16 forward as one plan (one concatenated site table and rulebook, autotuned tile shapes, one
@@ -223,6 +247,14 @@ def main():
         step = train_fn(tr_b)
         for _ in range(args.steps):
             step()
+        # last: 10 launches of the timed hidden layer in each tile shape (the kernel whose roofline
+        # the benchmark line reports is one of them)
+        rbc = npvs.build_rulebook(occ0, dims, cfg.d, csr=True)
+        hid = net_b.layer(0, npvs.gather_input(occ0, rbc, npvs.NPVS_BF16), rbc)
+        out = torch.empty_like(hid)
+        for v in range(npvs.NPVS_CONV_VARIANTS):
+            for _ in range(10):
+                npvs.sparse_conv_fwd(hid, net_b.Wp[1], net_b.b[1], 64, 64, rbc, npvs.NPVS_BF16, True, out=out, variant=v)
         torch.cuda.synchronize()
         print(json.dumps({"counters": True, "steps": args.steps, "calibration_bytes_each_way": a.numel() * 4}))
         return
@@ -319,8 +351,10 @@ def main():
     achieved = flops / (conv_ms * 1e-3) / 1e12
     shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
               6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>"}
+    alg_bytes = n_sites * 64 * 2 * 2 + 27 * n_sites * 4 + 27 * 64 * 64 * 2  # X in, Y out, neighbour map, weights
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / BF16_PEAK_TFLOPS, "traffic": conv_traffic(net_b.variant[1]),
+                "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel": "conv_fwd_bf16" + shapes[net_b.variant[1]], "avg_launch_ms": conv_ms,
                 "algorithmic_flops_per_launch": flops, "autotuned_variants": net_b.variant}
     conv32_ms = float(np.mean(stage["conv_fwd_fp32"]))

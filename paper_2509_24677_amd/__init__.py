@@ -17,7 +17,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib as L
-from ._lib import NPVS_BF16, NPVS_F32, NPVS_U8, NpvsError  # noqa: F401
+from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  # noqa: F401
 
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",

@@ -175,8 +175,9 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
 //   B (32 x 16): lane l gives GT[nb*16 + l%16][kk + 8(l/16) + j]
 //   D: lane l holds dW[mb*16 + 4(l/16) + i][nb*16 + l%16]
 // A staging task is 4 consecutive pairs x 8 channels of X or dZ (at most 2 per thread).  The pair
-// indices are fetched two chunks ahead and the rows one chunk ahead, so the gathers overlap the
-// products.  Each chunk's product starts from zero and is added into a compensated total.
+// indices are fetched two chunks ahead and the rows of the next chunk are loaded while the
+// current chunk's products run, then stored into the other LDS buffer.  Each chunk's product
+// starts from zero and is added into a compensated total.
 constexpr int kWgChunk = 128;
 constexpr int kWgPitch = kWgChunk + 8;  // bf16 elements per LDS row (padding spreads banks)
 constexpr int kWgQuads = kWgChunk / 4;
@@ -207,22 +208,26 @@ __device__ __forceinline__ void wg_gather(const uint16_t *__restrict__ X, int ci
   for (int i = 0; i < 4; ++i) {
     const bool ok = r[i] >= 0;
     const uint4 x = *reinterpret_cast<const uint4 *>(src + (ok ? (int64_t)r[i] * C + 8 * t.cc : 0));
-    v[i] = ok ? x : make_uint4(0, 0, 0, 0);
+    const uint32_t m = ok ? ~0u : 0u;  // a mask, not a select of the loaded value: no branch around the load
+    v[i] = make_uint4(x.x & m, x.y & m, x.z & m, x.w & m);
   }
 }
 
-__device__ __forceinline__ uint32_t bf16_lane(const uint4 &v, int j) {
-  const uint32_t w = (j >> 1) == 0 ? v.x : (j >> 1) == 1 ? v.y : (j >> 1) == 2 ? v.z : v.w;
-  return (w >> ((j & 1) * 16)) & 0xffffu;
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int w) {
+  return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
 }
 
+// Channel j of the 4 staged rows as two packed dwords (rows 0,1 and rows 2,3): one byte permute
+// per dword picks the same 16-bit half of two source words (0x05040100: low halves, 0x07060302:
+// high halves).
 __device__ __forceinline__ void wg_store(uint16_t *XT, uint16_t *GT, const WgTask &t, const uint4 *v) {
   if (!t.valid) return;
   uint16_t *dst = t.isx ? XT : GT;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const uint2 pk2 = make_uint2(bf16_lane(v[0], j) | (bf16_lane(v[1], j) << 16),
-                                 bf16_lane(v[2], j) | (bf16_lane(v[3], j) << 16));
+    const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+    const uint2 pk2 = make_uint2(__builtin_amdgcn_perm(word_of(v[1], j >> 1), word_of(v[0], j >> 1), sel),
+                                 __builtin_amdgcn_perm(word_of(v[3], j >> 1), word_of(v[2], j >> 1), sel));
     *reinterpret_cast<uint2 *>(dst + (8 * t.cc + j) * kWgPitch + 4 * t.pq) = pk2;
   }
 }
@@ -232,9 +237,12 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
                                                           int cout, const int32_t *__restrict__ rb_off,
                                                           const int32_t *__restrict__ pairs,
                                                           float *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) uint16_t XT[64 * kWgPitch];
-  __shared__ __attribute__((aligned(16))) uint16_t GT[64 * kWgPitch];
-  const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // two staging buffers: chunk ch is read from buffer ch & 1 while chunk ch + 1 is written to the
+  // other one, so one barrier per chunk orders both
+  __shared__ __attribute__((aligned(16))) uint16_t XT[2][64 * kWgPitch];
+  __shared__ __attribute__((aligned(16))) uint16_t GT[2][64 * kWgPitch];
+  const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
   const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
   const int CB = (cin + 15) / 16, OB = (cout + 15) / 16, nblk = CB * OB;
@@ -249,10 +257,15 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
     task[u].isx = cc < cin8;
     task[u].cc = task[u].isx ? cc : cc - cin8;
   }
-  // channel rows past cin / cout stay zero
-  for (int e = tid; e < 64 * kWgPitch; e += 256) {
-    XT[e] = 0;
-    GT[e] = 0;
+  // channel rows past cin / cout (up to the 16-row MFMA block) stay zero; the others are written
+  // by every chunk
+  for (int e = cin * kWgPitch / 2 + tid; e < CB * 16 * kWgPitch / 2; e += 256) {
+    reinterpret_cast<uint32_t *>(XT[0])[e] = 0;
+    reinterpret_cast<uint32_t *>(XT[1])[e] = 0;
+  }
+  for (int e = cout * kWgPitch / 2 + tid; e < OB * 16 * kWgPitch / 2; e += 256) {
+    reinterpret_cast<uint32_t *>(GT[0])[e] = 0;
+    reinterpret_cast<uint32_t *>(GT[1])[e] = 0;
   }
   Comp tot[4][4];
 #pragma unroll
@@ -265,24 +278,27 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
     return left < kWgChunk ? (int)left : kWgChunk;
   };
   int rn[2][4];
-  uint4 v[2][4];
   if (nch > 0) {  // an empty slice loads nothing (p0 may be the end of the pair list)
-    // the prefetches past the last chunk re-read the last chunk (no branch around a load)
-    const int c1 = nch > 1 ? 1 : 0;
+    uint4 v[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       wg_indices(pairs, p0, chunk_m(0), task[u], rn[u]);
       wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);
+    }
+    // the prefetches past the last chunk re-read the last chunk (no branch around a load)
+    const int c1 = nch > 1 ? 1 : 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
       wg_indices(pairs, p0 + (int64_t)c1 * kWgChunk, chunk_m(c1), task[u], rn[u]);
+      wg_store(XT[0], GT[0], task[u], v[u]);
     }
   }
+  __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
-    __syncthreads();  // the previous chunk's operand reads are done
+    const int cur = ch & 1;
+    uint4 v[2][4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) wg_store(XT, GT, task[u], v[u]);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 2; ++u) wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);
+    for (int u = 0; u < 2; ++u) wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);  // chunk ch + 1
     const int c2 = ch + 2 < nch ? ch + 2 : nch - 1;
 #pragma unroll
     for (int u = 0; u < 2; ++u) wg_indices(pairs, p0 + (int64_t)c2 * kWgChunk, chunk_m(c2), task[u], rn[u]);
@@ -293,19 +309,25 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
     for (int kk = 0; kk < kWgChunk; kk += 32) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
+        // blocks past nblk compute on in-range rows and are discarded at the store, so the
+        // products need no branch (a branch would make the compiler copy the accumulators)
         const int blk = wv + 4 * j;
-        if (blk < nblk) {
-          const int mb = blk / OB, nb = blk % OB;
-          const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(XT + (mb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
-          const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(GT + (nb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-        }
+        const int mb = blk / OB < 3 ? blk / OB : 3, nb = blk % OB;
+        const bf16x8_t a =
+            *reinterpret_cast<const bf16x8_t *>(XT[cur] + (mb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
+        const bf16x8_t b =
+            *reinterpret_cast<const bf16x8_t *>(GT[cur] + (nb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int i = 0; i < 4; ++i) tot[j][i].add(acc[j][i]);
+    // the other buffer was last read in chunk ch - 1, before the barrier that ended it
+#pragma unroll
+    for (int u = 0; u < 2; ++u) wg_store(XT[cur ^ 1], GT[cur ^ 1], task[u], v[u]);
+    __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {

@@ -110,7 +110,8 @@ __global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restri
   __shared__ int idx_s[kF32Rows];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + kF32Rows - 1) / kF32Rows;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
   for (int j = 0;; ++j) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
     if (tile < 0) break;
@@ -188,8 +189,9 @@ __global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restri
 // of a stage only covers that stage's loads, not the ones prefetched after it.
 __device__ __forceinline__ bf16x8_t gather8(const uint16_t *__restrict__ X, int cin, int i, int c) {
   const bool ok = i >= 0 && c < cin;
-  const bf16x8_t v = *reinterpret_cast<const bf16x8_t *>(X + (ok ? (int64_t)i * cin + c : 0));
-  return ok ? v : bf16x8_t{};
+  const uint4 v = *reinterpret_cast<const uint4 *>(X + (ok ? (int64_t)i * cin + c : 0));
+  const uint32_t m = ok ? ~0u : 0u;  // a mask, not a select of the loaded value: no branch around the load
+  return __builtin_bit_cast(bf16x8_t, make_uint4(v.x & m, v.y & m, v.z & m, v.w & m));
 }
 
 // Zero as a value the compiler cannot see through, taken once per tile and added to the weight
@@ -245,7 +247,8 @@ __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16
   __shared__ f32x4_t red[KSPLIT > 1 ? KSPLIT * NBLK * 64 : 1];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index, uniform (scalar)
   const int kbeg = wv * KPER;
   const int csub = 8 * (lane >> 4);
   for (int j = 0;; ++j) {
@@ -334,7 +337,8 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
   __shared__ bf16x8_t Ws[2][FR * 64];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
   const int csub = 8 * (lane >> 4);
   for (int j = 0;; ++j) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
