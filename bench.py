@@ -5,11 +5,12 @@ Workload: the 256x256x128 froxel grid of a seeded synthetic city (50 000 triangl
 occupied froxels), interleave factor d = 4 (64 channels), six submanifold 3x3x3 convolutions
 64 -> 64, batch 1.  One step is one frame through the whole path: froxelize -> active sites and
 rulebook -> interleave -> 6 convolutions -> de-interleave + threshold -> BCE + repulsive
-visibility loss -> hand-written backward (checkpointed recompute of every second layer) -> Adam,
+visibility loss -> hand-written backward (weight gradients on a second stream) -> Adam,
 in BF16 on MFMA with FP32 accumulation and FP32 master weights.  Each step is replayed from a
 HIP graph captured once; inputs are resident in HBM before the timed region.
 
-Also reported: forward-only and FP32 variants, the per-stage breakdown, the roofline of the
+Also reported: forward-only and FP32 variants, the step with activation checkpointing, the
+per-stage breakdown, the roofline of the
 dominant kernel (its launches timed with HIP events on the stream they run on), accuracy of the
 BF16 path against the FP32 path and the FP64 oracle, and the CPU oracle timed on a bounded sample.
 
@@ -57,7 +58,7 @@ def conv_traffic(variant):
         if f"{src} {h}" not in text:
             return None
     shapes = {0: (1, 9), 1: (2, 1), 2: (1, 3), 3: (2, 3), 4: (1, 1), 5: (2, 9)}
-    lds = {6: (1, 4), 7: (1, 2), 8: (2, 2), 9: (1, 8)}
+    lds = {6: (1, 4), 7: (1, 2), 8: (2, 2), 9: (1, 8), 10: (2, 4), 11: (2, 8)}
     name = (f"conv_fwd_bf16_kernel<2, 4, {shapes[variant][0]}, {shapes[variant][1]}>" if variant in shapes
             else f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>")
     for line in text.splitlines():
@@ -188,18 +189,29 @@ def main():
     X0_b = npvs.gather_input(occ0, rb0, npvs.NPVS_BF16)
     tuned = {}
 
-    def make(dtype):
+    def make(dtype, checkpoint=False):
         net = Network(layers, cfg.d, dtype)
         if dtype == npvs.NPVS_BF16:  # autotuned tile shapes, chosen once on the real rulebook
             if "v" not in tuned:
                 tuned["v"] = net.autotune(X0_b, rb0)
             net.variant = list(tuned["v"])
-        tr = Trainer(net, dims, n_tris, checkpoint=True)
+        tr = Trainer(net, dims, n_tris, checkpoint=checkpoint)
         return net, tr
 
     def fwd_fn(net):
         def f():
             occ = npvs.froxelize(tris, n_tris, dims)
+            rb = npvs.build_rulebook(occ, dims, cfg.d)
+            X0 = npvs.gather_input(occ, rb, net.dtype)
+            logits, _ = net.forward(X0, rb)
+            pvs, _ = npvs.deinterleave_threshold(logits, rb, occ)
+            return pvs, logits
+        return f
+
+    def infer_fn(net, occ):
+        """Inference from a froxelized grid: sites and rulebook, interleave, convolutions,
+        de-interleave + threshold (everything after froxelization)."""
+        def f():
             rb = npvs.build_rulebook(occ, dims, cfg.d)
             X0 = npvs.gather_input(occ, rb, net.dtype)
             logits, _ = net.forward(X0, rb)
@@ -224,7 +236,10 @@ def main():
         torch.cuda.synchronize()
         return g, out
 
-    def time_graph(g, steps):
+    def time_graph(g, steps, per_step=None):
+        """Mean ms per replay over `steps` back-to-back replays (one event pair around all of
+        them); with `per_step` (a dict), also the median / p10 / p90 of per-replay event pairs
+        from a second run of the same length."""
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
@@ -234,6 +249,16 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        if per_step is not None:
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            evs[0].record()
+            for i in range(steps):
+                g.replay()
+                evs[i + 1].record()
+            torch.cuda.synchronize()
+            d = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+            per_step.update(median_ms=float(np.median(d)), p10_ms=float(np.percentile(d, 10)),
+                            p90_ms=float(np.percentile(d, 90)))
         return e0.elapsed_time(e1) / steps, wall
 
     net_b, tr_b = make(npvs.NPVS_BF16)
@@ -264,7 +289,8 @@ def main():
         g_train_b.replay()
     torch.cuda.synchronize()
     # ------------------------------------------------------------------ timed region (primary)
-    ms_step, wall = time_graph(g_train_b, args.steps)
+    step_dist = {}
+    ms_step, wall = time_graph(g_train_b, args.steps, step_dist)
     print(f"# bf16 fwd+bwd: {ms_step:.4f} ms/frame over {args.steps} steps (wall {wall:.3f} s)",
           file=sys.stderr, flush=True)
     if args.profile_only:
@@ -272,19 +298,31 @@ def main():
         return
 
     # ------------------------------------------------------------------ variants
-    variants = {"bf16_fwd_bwd": {"ms_per_frame": ms_step, "frames_per_s": 1000.0 / ms_step}}
+    variants = {"bf16_fwd_bwd": {"ms_per_frame": ms_step, "frames_per_s": 1000.0 / ms_step, **step_dist}}
+
+    def variant(name, g):
+        dist = {}
+        ms, _ = time_graph(g, args.steps, dist)
+        variants[name] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms, **dist}
+
+    # end to end (froxelize -> PVS) and inference only (after froxelization), BF16 and FP32
     net_bf, _ = make(npvs.NPVS_BF16)
     g_fb, (pvs_b, logits_b) = capture(fwd_fn(net_bf), 2)
-    ms, _ = time_graph(g_fb, args.steps)
-    variants["bf16_fwd"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    variant("bf16_fwd", g_fb)
+    g_ib, _ = capture(infer_fn(net_bf, occ0), 2)
+    variant("bf16_infer", g_ib)
     net_ff, _ = make(npvs.NPVS_F32)
     g_ff, (pvs_f, logits_f) = capture(fwd_fn(net_ff), 2)
-    ms, _ = time_graph(g_ff, args.steps)
-    variants["fp32_fwd"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    variant("fp32_fwd", g_ff)
+    g_if, _ = capture(infer_fn(net_ff, occ0), 2)
+    variant("fp32_infer", g_if)
     net_f, tr_f = make(npvs.NPVS_F32)
     g_train_f, _ = capture(train_fn(tr_f), 2)
-    ms, _ = time_graph(g_train_f, args.steps)
-    variants["fp32_fwd_bwd"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
+    variant("fp32_fwd_bwd", g_train_f)
+    # the same BF16 step with activation checkpointing (every second layer input recomputed)
+    _, tr_c = make(npvs.NPVS_BF16, checkpoint=True)
+    g_train_c, _ = capture(train_fn(tr_c), 2)
+    variant("bf16_fwd_bwd_checkpointed", g_train_c)
     # the whole forward as one library-captured graph (npvs_plan_capture / npvs_plan_replay)
     plan = npvs.Plan(dims, n_tris, cfg.d, cfg.channels, npvs.NPVS_BF16)
     for li, (W, b) in enumerate(layers):
@@ -304,6 +342,8 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     variants["bf16_fwd_plan_graph"] = {"ms_per_frame": ms, "frames_per_s": 1000.0 / ms}
     variants["bf16_fwd_speedup_vs_fp32_fwd"] = variants["fp32_fwd"]["ms_per_frame"] / variants["bf16_fwd"]["ms_per_frame"]
+    variants["bf16_infer_speedup_vs_fp32_infer"] = (variants["fp32_infer"]["ms_per_frame"] /
+                                                   variants["bf16_infer"]["ms_per_frame"])
     print("# variants " + json.dumps(variants), file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------------ per-launch kernel timing
@@ -343,6 +383,18 @@ def main():
         lambda: npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True), 20)
     stage["deinterleave_threshold"] = timed_launches(lambda: npvs.deinterleave_threshold(logits_b, rb, occ), 20)
     stage_ms = {k: float(np.median(v)) for k, v in stage.items()}
+    # algorithmic bytes of the memory-bound stages and the HBM rate they reach (peak 8 TB/s)
+    N = dims[0][0] * dims[0][1] * dims[0][2]
+    nblocks = N // cfg.d ** 3
+    stage_bytes = {
+        "froxelize": 36 * n_tris[0] + N // 8,                        # triangles in, bits out
+        "rulebook": N // 8 + 4 * nblocks + 4 * n_sites + 27 * 4 * n_sites + 8 * n_pairs,
+        "gather_bf16": N // 8 + n_sites * 64 * 2,                  # bits in, rows out
+        "deinterleave_threshold": n_sites * 64 * 4 + 2 * (N // 8),  # logits and G in, PVS out
+    }
+    stage_gbs = {k: {"bytes": b, "GB_per_s": b / (stage_ms[k] * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": b / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                 for k, b in stage_bytes.items()}
     print("# stages (median ms per call) " + json.dumps(stage_ms), file=sys.stderr, flush=True)
 
     # dominant kernel: the BF16 MFMA gather-GEMM (6 forward launches per frame + 3 recomputes)
@@ -350,7 +402,8 @@ def main():
     flops = 2.0 * n_pairs * 64 * 64
     achieved = flops / (conv_ms * 1e-3) / 1e12
     shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
-              6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>"}
+              6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>",
+              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>"}
     alg_bytes = n_sites * 64 * 2 * 2 + 27 * n_sites * 4 + 27 * 64 * 64 * 2  # X in, Y out, neighbour map, weights
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / BF16_PEAK_TFLOPS, "traffic": conv_traffic(net_b.variant[1]),
@@ -425,6 +478,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "stages_ms": stage_ms,
+        "stages_hbm": stage_gbs,
         "batch16": batch16,
         "accuracy": acc,
     }

@@ -174,9 +174,9 @@ npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, con
  * split a tile's 27 offsets over several waves, (rows per wave, waves) = 0 (16, 9), 1 (32, 1),
  * 2 (16, 3), 3 (32, 3), 4 (16, 1), 5 (32, 9); variants 6-9 give each wave its own rows and all
  * offsets and share each offset's weights through LDS, (rows per wave, waves) = 6 (16, 4),
- * 7 (16, 2), 8 (32, 2), 9 (16, 8).  All variants give results within float32 rounding of each
- * other; each one is deterministic.  Ignored by the FP32 path. */
-#define NPVS_CONV_VARIANTS 10
+ * 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8).  All variants give results within
+ * float32 rounding of each other; each one is deterministic.  Ignored by the FP32 path. */
+#define NPVS_CONV_VARIANTS 12
 npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                     const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                     int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);
@@ -230,7 +230,8 @@ npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row
  * The batch loss is the mean over grids.
  *   logits (device) float32 [cap][C]; labels (device) uint8 [cap][C] 0/1; grid_rows from the
  *   rulebook; stats (device) float32 [n_grids + 1][8] = {L, BCE, L_rv, TP, FN, FP, GTP, m} per
- *   grid, row n_grids = batch mean; dlogits (device, nullable) float32 [cap][C] = dL_batch/dl.
+ *   grid, row n_grids = batch mean; dlogits (device, nullable) float32 [cap][C] = dL_batch/dl,
+ *   rows >= n_sites untouched.
  *   ws: npvs_loss_workspace_size() bytes.
  * ------------------------------------------------------------------------------------------- */
 npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes);

@@ -254,7 +254,7 @@ def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 
     dev = logits.device
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     stats = torch.empty((G + 1, 8), dtype=torch.float32, device=dev)
-    dl = torch.zeros_like(logits) if want_grad else None
+    dl = torch.empty_like(logits) if want_grad else None  # rows past the active sites are never read
     L.call("npvs_loss", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam),
            _p(stats), _p(dl), _p(ws), nbytes.value, _stream())
     return stats, dl

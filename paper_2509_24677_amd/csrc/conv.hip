@@ -419,7 +419,9 @@ static void launch_bf16_lds(const void *X, int cin, const void *Wp, const float 
 
 // Tile shapes.  Split kernel (MB, KSPLIT) = (rows per wave / 16, waves sharing the 27 offsets of a
 // tile): variant 0 (1, 9), 1 (2, 1), 2 (1, 3), 3 (2, 3), 4 (1, 1), 5 (2, 9).  Shared-weight kernel
-// (MB, RG) = (rows per wave / 16, waves per workgroup): 6 (1, 4), 7 (1, 2), 8 (2, 2), 9 (1, 8).
+// (MB, RG) = (rows per wave / 16, waves per workgroup): 6 (1, 4), 7 (1, 2), 8 (2, 2), 9 (1, 8),
+// 10 (2, 4), 11 (2, 8).  Larger row blocks read each staged weight fragment for more rows (less
+// weight traffic per row) and suit large batches; small ones keep more waves busy on one frame.
 // Inputs wider than 64 channels use only the 9-way split (a long unrolled offset loop would not
 // fit the registers, nor a double-buffered offset of weights the LDS).
 // kDefaultConvVariant is used by npvs_sparse_conv_fwd; the autotuner can pick another per layer.
@@ -454,7 +456,9 @@ static void launch_bf16_variant(int v, const void *X, int cin, const void *Wp, c
       case 6: launch_bf16_lds<KB, NB, 1, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
       case 7: launch_bf16_lds<KB, NB, 1, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
       case 8: launch_bf16_lds<KB, NB, 2, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
-      default: launch_bf16_lds<KB, NB, 1, 8>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 9: launch_bf16_lds<KB, NB, 1, 8>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      case 10: launch_bf16_lds<KB, NB, 2, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
+      default: launch_bf16_lds<KB, NB, 2, 8>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); break;
     }
   }
 }

@@ -34,9 +34,10 @@ __device__ __forceinline__ float sigmoidf_(float l) { return 1.0f / (1.0f + expf
 __global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restrict__ logits,
                                                             const uint8_t *__restrict__ labels, int C,
                                                             const int32_t *__restrict__ grid_rows,
-                                                            float *__restrict__ part) {
+                                                            float *__restrict__ part, uint32_t *__restrict__ ticket) {
   __shared__ Comp red[kLossQ][256];
   const int b = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
+  if (b == 0 && s == 0 && tid == 0) *ticket = 0u;  // for the finishing kernel that follows
   const int64_t e0 = (int64_t)grid_rows[b] * C, e1 = (int64_t)grid_rows[b + 1] * C;
   const int64_t m = e1 - e0;
   const int64_t a0 = e0 + m * s / kLossSlices, a1 = e0 + m * (s + 1) / kLossSlices;
@@ -68,11 +69,14 @@ __global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restri
 
 // One workgroup per grid: thread s takes slice s's partial sums, a fixed-shape tree adds them,
 // thread 0 writes the grid's statistics and gradient coefficients coef[b] = {a_b, c_b}.
+// One block per grid finishes that grid's sums (fixed tree); the last block to finish, found with
+// a ticket taken after a device-scope fence, writes the batch mean (grids in order).
 __global__ __launch_bounds__(kLossSlices) void loss_final_kernel(const float *__restrict__ part,
                                                                  const int32_t *__restrict__ grid_rows, int n_grids,
                                                                  int C, float lambda, float *__restrict__ stats,
-                                                                 float *__restrict__ coef) {
+                                                                 float *__restrict__ coef, uint32_t *__restrict__ ticket) {
   __shared__ Comp red[kLossQ][kLossSlices];
+  __shared__ bool last;
   const int b = blockIdx.x, s = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < kLossQ; ++i) red[i][s] = Comp{part[((int64_t)b * kLossSlices + s) * kLossQ + i], 0.0f};
@@ -94,16 +98,15 @@ __global__ __launch_bounds__(kLossSlices) void loss_final_kernel(const float *__
     for (int i = 0; i < 8; ++i) stats[b * 8 + i] = v[i];
     coef[2 * b] = m > 0.0f ? lambda / (m * n_grids) : 0.0f;
     coef[2 * b + 1] = (1.0f - lambda) / (g * n_grids);
+    __threadfence();  // this grid's stats are visible before its ticket
+    last = atomicAdd(ticket, 1u) == (uint32_t)(n_grids - 1);
   }
-}
-
-// Batch row of the statistics: the mean over grids, in grid order.
-__global__ void loss_mean_kernel(float *__restrict__ stats, int n_grids) {
-  const int i = threadIdx.x;
-  if (i < 8) {
+  __syncthreads();
+  if (last && s < 8) {
+    __threadfence();  // every grid's stats are visible to the last block
     float t = 0.0f;
-    for (int b = 0; b < n_grids; ++b) t += stats[b * 8 + i];
-    stats[n_grids * 8 + i] = t / n_grids;
+    for (int gb = 0; gb < n_grids; ++gb) t += __builtin_nontemporal_load(stats + gb * 8 + s);
+    stats[n_grids * 8 + s] = t / n_grids;
   }
 }
 
@@ -173,10 +176,10 @@ extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int
   if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: workspace too small");
   float *part = static_cast<float *>(ws);
   float *coef = part + (size_t)n_grids * kLossSlices * kLossQ;
+  uint32_t *ticket = reinterpret_cast<uint32_t *>(coef + 2 * (size_t)n_grids);
   hipStream_t s = as_stream(stream);
-  loss_partial_kernel<<<dim3(kLossSlices, n_grids), 256, 0, s>>>(logits, labels, C, grid_rows, part);
-  loss_final_kernel<<<n_grids, kLossSlices, 0, s>>>(part, grid_rows, n_grids, C, lambda, stats, coef);
-  loss_mean_kernel<<<1, 64, 0, s>>>(stats, n_grids);
+  loss_partial_kernel<<<dim3(kLossSlices, n_grids), 256, 0, s>>>(logits, labels, C, grid_rows, part, ticket);
+  loss_final_kernel<<<n_grids, kLossSlices, 0, s>>>(part, grid_rows, n_grids, C, lambda, stats, coef, ticket);
   if (dlogits)
     loss_grad_kernel<<<stride_grid((int64_t)cap_sites * C, 256, 4096), 256, 0, s>>>(logits, labels, C, grid_rows,
                                                                                    n_grids, counts, coef, dlogits);

@@ -216,7 +216,7 @@ def test_conv_fwd_bf16_mfma(cin, cout, variant_rows):
     np.testing.assert_array_equal(to_np(Yb)[:n], to_np(Y[:n].to(torch.bfloat16)))
 
 
-@pytest.mark.parametrize("variant", range(10))
+@pytest.mark.parametrize("variant", range(npvs.NPVS_CONV_VARIANTS))
 @pytest.mark.parametrize("cin,cout,d", [(64, 64, 2), (16, 8, 2), (512, 64, 8)])
 def test_conv_fwd_bf16_every_tile_shape(variant, cin, cout, d):
     rb, ref, X, W, b = _conv_case(cin, cout, d=d, dims=((64, 64, 64), (32, 32, 32)))
