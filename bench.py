@@ -59,8 +59,12 @@ def conv_traffic(variant):
             return None
     shapes = {0: (1, 9), 1: (2, 1), 2: (1, 3), 3: (2, 3), 4: (1, 1), 5: (2, 9)}
     lds = {6: (1, 4), 7: (1, 2), 8: (2, 2), 9: (1, 8), 10: (2, 4), 11: (2, 8)}
-    name = (f"conv_fwd_bf16_kernel<2, 4, {shapes[variant][0]}, {shapes[variant][1]}>" if variant in shapes
-            else f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>")
+    if variant in shapes:
+        name = f"conv_fwd_bf16_kernel<2, 4, {shapes[variant][0]}, {shapes[variant][1]}>"
+    elif variant in lds:
+        name = f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>"
+    else:
+        name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}>"
     for line in text.splitlines():
         parts = line.rsplit(None, 3)
         if len(parts) == 4 and parts[0] == name:
@@ -143,6 +147,67 @@ def bench_batch16(args, dev, timed_launches):
             "conv_fwd_bf16_avg_launch_ms": conv_ms,
             "conv_fwd_bf16_tflops": flops / (conv_ms * 1e-3) / 1e12,
             "conv_fwd_bf16_frac_of_peak": flops / (conv_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
+
+
+def bench_wide(args, dev, timed_launches):
+    """The city frame at the paper's interleave factors d = 8 and 16: forward (froxelize -> PVS) as a
+    library-captured graph in BF16 and FP32, and the wide first and last layers (Cin or Cout =
+    d^3 = 512 / 4096) timed launch by launch against the BF16 MFMA peak."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+
+    res = {}
+    for name in ("city256_d8", "city256_d16"):
+        cfg = synth.config(name)
+        t = synth.scene_for(cfg)
+        layers = synth.net_layers(cfg)
+        tris = torch.from_numpy(t).to(dev)
+        nt = [len(t)]
+        r = {"d": cfg.d, "channels": cfg.channels}
+        for dtype, tag in ((npvs.NPVS_BF16, "bf16"), (npvs.NPVS_F32, "fp32")):
+            plan = npvs.Plan(cfg.grids, nt, cfg.d, cfg.channels, dtype)
+            for li, (W, b) in enumerate(layers):
+                plan.set_weights(li, torch.from_numpy(W).to(dev), torch.from_numpy(b).to(dev))
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                plan.capture(tris)
+                for _ in range(3):
+                    plan.replay()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                for _ in range(args.steps):
+                    plan.replay()
+                e1.record(s)
+                s.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            r[f"{tag}_fwd_ms"] = ms
+            r[f"{tag}_fwd_frames_per_s"] = 1000.0 / ms
+        r["bf16_fwd_speedup_vs_fp32"] = r["fp32_fwd_ms"] / r["bf16_fwd_ms"]
+        occ = npvs.froxelize(tris, nt, cfg.grids)
+        rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
+        c = rb.host_counts()
+        r["n_sites"], r["n_pairs"] = c["n_sites"], c["n_pairs"]
+        C, H = cfg.channels[0], cfg.channels[1]
+        X0 = npvs.gather_input(occ, rb, npvs.NPVS_BF16)
+        Wf = npvs.pack_weights(torch.from_numpy(layers[0][0]).to(dev), npvs.NPVS_BF16)
+        bf = torch.from_numpy(layers[0][1]).to(dev)
+        Hd = npvs.sparse_conv_fwd(X0, Wf, bf, C, H, rb, npvs.NPVS_BF16, True)
+        Wl = npvs.pack_weights(torch.from_numpy(layers[-1][0]).to(dev), npvs.NPVS_BF16)
+        bl = torch.from_numpy(layers[-1][1]).to(dev)
+        Lo = torch.empty((rb.cap, C), dtype=torch.float32, device=dev)
+        flops = 2.0 * c["n_pairs"] * C * H
+        for key, launch in (("first_layer", lambda: npvs.sparse_conv_fwd(X0, Wf, bf, C, H, rb, npvs.NPVS_BF16, True,
+                                                                          out=Hd)),
+                            ("last_layer", lambda: npvs.sparse_conv_fwd(Hd, Wl, bl, H, C, rb, npvs.NPVS_BF16, False,
+                                                                         out_f32=True, out=Lo))):
+            ms = float(np.mean(timed_launches(launch, 20)))
+            r[key] = {"shape": [C, H] if key == "first_layer" else [H, C], "ms": ms,
+                      "tflops": flops / (ms * 1e-3) / 1e12, "frac_of_bf16_peak": flops / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
+        res[name] = r
+    return res
 
 
 def main():
@@ -403,7 +468,7 @@ def main():
     achieved = flops / (conv_ms * 1e-3) / 1e12
     shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
               6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>",
-              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>"}
+              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>", 12: "_wsta<2,1>", 13: "_wsta<2,2>"}
     alg_bytes = n_sites * 64 * 2 * 2 + 27 * n_sites * 4 + 27 * 64 * 64 * 2  # X in, Y out, neighbour map, weights
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / BF16_PEAK_TFLOPS, "traffic": conv_traffic(net_b.variant[1]),
@@ -418,6 +483,8 @@ def main():
     # ------------------------------------------------------------------ batching (16 uneven grids)
     batch16 = bench_batch16(args, dev, timed_launches)
     print("# batch16 " + json.dumps(batch16), file=sys.stderr, flush=True)
+    wide = bench_wide(args, dev, timed_launches)
+    print("# interleave factors 8 and 16 " + json.dumps(wide), file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------------ accuracy
     torch.cuda.synchronize()
@@ -480,6 +547,7 @@ def main():
         "stages_ms": stage_ms,
         "stages_hbm": stage_gbs,
         "batch16": batch16,
+        "interleave_8_16": wide,
         "accuracy": acc,
     }
     print(json.dumps(line))

@@ -174,12 +174,28 @@ npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, con
  * split a tile's 27 offsets over several waves, (rows per wave, waves) = 0 (16, 9), 1 (32, 1),
  * 2 (16, 3), 3 (32, 3), 4 (16, 1), 5 (32, 9); variants 6-9 give each wave its own rows and all
  * offsets and share each offset's weights through LDS, (rows per wave, waves) = 6 (16, 4),
- * 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8).  All variants give results within
- * float32 rounding of each other; each one is deterministic.  Ignored by the FP32 path. */
-#define NPVS_CONV_VARIANTS 12
+ * 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8); variants 12 and 13 (inputs of at
+ * most 64 channels) keep each wave's weights in registers while a workgroup walks several row
+ * tiles of 16 or 32 rows.  Channel counts no tuned shape covers use a general kernel (variants
+ * 5 and 13 select its 32-row tiles).  All variants give results within float32 rounding of each
+ * other; each one is deterministic.  Ignored by the FP32 path. */
+#define NPVS_CONV_VARIANTS 14
+#define NPVS_DEFAULT_CONV_VARIANT 3 /* the tile shape npvs_sparse_conv_fwd uses */
 npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                     const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                     int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);
+
+/* Same, with a workspace: BF16 layers with 1024 or more input channels (the first layer of
+ * interleave factor 16, Cin = 4096) then split their input channels over several workgroups and
+ * add the partial sums in a fixed order (results within float32 rounding of the unsplit kernel,
+ * deterministic).  npvs_conv_fwd_workspace_size() gives the bytes (0: no workspace needed, ws
+ * may be NULL); a smaller non-zero ws_bytes is an argument error.  ws (device) is scratch,
+ * overwritten by the call. */
+npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
+npvs_status npvs_sparse_conv_fwd_ws(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                                    const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
+                                    int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *ws,
+                                    size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Backward of one submanifold layer (chain rule on the forward definition):

@@ -187,7 +187,14 @@ def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None
     if out is None:
         odt = torch.float32 if (dtype == NPVS_F32 or out_f32) else torch.bfloat16
         out = torch.empty((rb.cap, cout), dtype=odt, device=X.device)
-    if variant is None:
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_conv_fwd_workspace_size", cin, cout, rb.cap, dtype, ctypes.byref(nbytes))
+    if nbytes.value:  # wide inputs: channel-split partial sums
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
+        L.call("npvs_sparse_conv_fwd_ws", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap,
+               dtype, int(relu), int(out_f32), int(variant if variant is not None else L.NPVS_DEFAULT_CONV_VARIANT), _p(out),
+               _p(ws), nbytes.value, _stream())
+    elif variant is None:
         L.call("npvs_sparse_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap, dtype,
                int(relu), int(out_f32), _p(out), _stream())
     else:

@@ -19,7 +19,8 @@ NPVS_ERR_HIP = -3
 NPVS_ERR_UNSUPPORTED = -4
 NPVS_F32, NPVS_BF16, NPVS_U8 = 0, 1, 2
 NPVS_MAX_GRIDS = 32
-NPVS_CONV_VARIANTS = 12
+NPVS_CONV_VARIANTS = 14
+NPVS_DEFAULT_CONV_VARIANT = 3
 NPVS_MAX_PACK = 64
 
 
@@ -64,6 +65,8 @@ SIGNATURES = {
     "npvs_pack_weights_batch": (i32, [i32, P, i32, P]),
     "npvs_sparse_conv_fwd": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, P, P]),
     "npvs_sparse_conv_fwd_ex": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P]),
+    "npvs_conv_fwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
+    "npvs_sparse_conv_fwd_ws": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P, sz, P]),
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
     "npvs_sparse_conv_bwd_split": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P]),

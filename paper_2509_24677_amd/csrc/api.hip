@@ -71,9 +71,6 @@ npvs_status make_batch(int32_t n_grids, const npvs_dims *dims, int32_t d, const 
   return NPVS_OK;
 }
 
-npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
-                              const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
-                              int32_t out_f32, void *Y, hipStream_t s, int variant);
 
 }  // namespace npvs
 
@@ -116,6 +113,8 @@ struct npvs_plan {
   std::vector<float *> d_bias;
   std::vector<int> variant;  // BF16 tile shape per layer
   uint8_t *d_pvs_scratch = nullptr;
+  void *d_conv_ws = nullptr;  // channel-split partial sums of the widest layer (or null)
+  size_t conv_ws = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -193,6 +192,11 @@ extern "C" npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, 
   }
   TRY(plan_alloc(p, (void **)&p->d_logits, sizeof(float) * cap * C));
   TRY(plan_alloc(p, (void **)&p->d_pvs_scratch, (size_t)p->total_bytes));
+  for (int l = 0; l < n_layers; ++l) {
+    const size_t b = conv_fwd_ws_bytes(channels[l], channels[l + 1], cap, dtype);
+    p->conv_ws = b > p->conv_ws ? b : p->conv_ws;
+  }
+  if (p->conv_ws) TRY(plan_alloc(p, &p->d_conv_ws, p->conv_ws));
   p->variant.assign(n_layers, kDefaultConvVariant);
   p->d_Wp.assign(n_layers, nullptr);
   p->d_bias.assign(n_layers, nullptr);
@@ -235,7 +239,7 @@ static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_ou
     const bool last = l == p->n_layers - 1;
     void *out = last ? (void *)p->d_logits : p->d_act[l & 1];
     st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
-                           p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, p->variant[l]);
+                           p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, p->variant[l], p->d_conv_ws, p->conv_ws);
     if (st != NPVS_OK) return st;
     in = out;
   }
@@ -326,12 +330,12 @@ extern "C" npvs_status npvs_plan_autotune(npvs_plan *plan, const float *tris, in
       for (int v = 0; v < NPVS_CONV_VARIANTS && st == NPVS_OK; ++v) {
         // rerunning layer l on its own input rewrites the same output values
         st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
-                               p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v);
+                               p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v, p->d_conv_ws, p->conv_ws);
         if (st != NPVS_OK) break;
         st = check_hip(hipEventRecord(e0, s), "npvs_plan_autotune");
         for (int r = 0; r < reps && st == NPVS_OK; ++r)
           st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
-                                 p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v);
+                                 p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v, p->d_conv_ws, p->conv_ws);
         if (st != NPVS_OK) break;
         st = check_hip(hipEventRecord(e1, s), "npvs_plan_autotune");
         if (st == NPVS_OK) st = check_hip(hipEventSynchronize(e1), "npvs_plan_autotune");

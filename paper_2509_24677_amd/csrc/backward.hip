@@ -14,9 +14,6 @@ namespace npvs {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
-npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
-                              const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
-                              int32_t out_f32, void *Y, hipStream_t s, int variant);
 
 struct Comp {  // Neumaier-compensated float sum
   float s, c;
@@ -457,7 +454,7 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
   }
   if (dX) {
     st = conv_fwd_dispatch(dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, Wt, nullptr, cin, nbr,
-                           counts, cap_sites, dtype, 0, 1, dX, s, 0);
+                           counts, cap_sites, dtype, 0, 1, dX, s, 0, nullptr, 0);
     if (st != NPVS_OK) return st;
   }
   dim3 gw(kWgSlices, 27);

@@ -324,6 +324,217 @@ __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16
 // slot (loaded into registers one offset ahead, stored after the current offset's MFMAs), so the
 // L2 reads of weights drop by a factor of RG.  The neighbour rows are gathered straight from
 // global memory one offset ahead as in the split kernel.
+// ------------------------------------------------------------------------------------------
+// BF16 path for any channel counts (cin % 8 == 0, cout % 8 == 0), used for the shapes the tuned
+// kernels above do not cover, e.g. the wide first and last layers of interleave factors 8 and 16
+// (Cin or Cout = d^3 = 512 or 4096).  Workgroup = 9 waves over the same MB x 16 rows, wave w owning
+// offsets 3w .. 3w + 2; blockIdx.y selects 64 output channels (4 MFMA output blocks).  The
+// (offset, 32-channel chunk) stages are walked with a runtime chunk count and 4 stages in flight;
+// loads past the last stage re-read it and are masked to zero, and offsets with no neighbour
+// gather zeros, so every MFMA is unconditional (no branch around an accumulator).  The 9 partial
+// sums are added in LDS in wave order, as in the split kernel.
+// ------------------------------------------------------------------------------------------
+template <int MB>
+__global__ __launch_bounds__(576) void conv_fwd_bf16_wide_kernel(const uint16_t *__restrict__ X, int cin,
+                                                                  const bf16x8_t *__restrict__ Wp,
+                                                                  const float *__restrict__ bias, int cout,
+                                                                  const int32_t *__restrict__ nbr,
+                                                                  const npvs_counts *__restrict__ counts, int cap,
+                                                                  int relu, int out_f32, void *__restrict__ Y,
+                                                                  float *__restrict__ part) {
+  constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBLK = MB * 4, PD = 4;
+  __shared__ f32x4_t red[KSPLIT * NBLK * 64];
+  const int32_t n = counts->n_sites;
+  const int ntiles = (n + ROWS - 1) / ROWS;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index, uniform (scalar)
+  const int kbeg = wv * KPER, csub = 8 * (lane >> 4);
+  const int KB = (cin + 31) / 32, NBT = (cout + 15) / 16, nb0 = 4 * blockIdx.y;
+  // input-channel split (gridDim.z > 1 only with `part`): this workgroup's 32-channel chunks
+  const int KBZ = (KB + gridDim.z - 1) / gridDim.z, kb_lo = blockIdx.z * KBZ;
+  const int nkb = KB - kb_lo < KBZ ? KB - kb_lo : KBZ;
+  const int S = KPER * nkb;  // stages of this wave
+  for (int j = 0;; ++j) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
+    if (tile < 0) break;
+    const int row0 = tile * ROWS;
+    const bf16x8_t *W = Wp + opaque_zero();
+    int idx[KPER][MB];
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) idx[q][mb] = nbr_index(nbr, cap, kbeg + q, row0 + mb * 16 + (lane & 15), n);
+    f32x4_t acc[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8_t bx[PD][MB], aw[PD][4];
+    // operands of stage st (clamped to the last one; zero rows past the end)
+    auto load = [&](int st, int slot) {
+      const bool live = st < S;
+      st = live ? st : S - 1;
+      const int q = st / nkb, kb = kb_lo + st - q * nkb;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int i = q == 0 ? idx[0][mb] : q == 1 ? idx[1][mb] : idx[2][mb];
+        bx[slot][mb] = gather8(X, cin, live ? i : -1, kb * 32 + csub);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int g = nb0 + nb < NBT ? nb0 + nb : NBT - 1;  // blocks past cout: any valid fragment
+        aw[slot][nb] = W[(((int64_t)(kbeg + q) * NBT + g) * KB + kb) * 64 + lane];
+      }
+    };
+#pragma unroll
+    for (int p = 0; p < PD; ++p) load(p, p);
+    for (int g = 0; g < S; g += PD) {
+#pragma unroll
+      for (int p = 0; p < PD; ++p) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[p][nb], bx[p][mb], acc[mb][nb], 0, 0, 0);
+        load(g + p + PD, p);
+      }
+    }
+    __syncthreads();  // the previous tile's readers are done with red
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) red[(wv * NBLK + mb * 4 + nb) * 64 + lane] = acc[mb][nb];
+    __syncthreads();
+    for (int blk = wv; blk < NBLK; blk += KSPLIT) {
+      f32x4_t sum = red[blk * 64 + lane];
+      for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
+      const int mb = blk / 4, nb = blk % 4;
+      const int r = row0 + mb * 16 + (lane & 15), o = (nb0 + nb) * 16 + 4 * (lane >> 4);
+      if (part) {  // raw partial sum of this channel range; the finishing kernel adds the ranges
+        if (r < n && o < cout) *reinterpret_cast<f32x4_t *>(part + ((int64_t)blockIdx.z * cap + r) * cout + o) = sum;
+      } else {
+        conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
+      }
+    }
+  }
+}
+
+// Sum of the channel-range partials in range order, then bias, ReLU and rounding: one thread per
+// 4 outputs of an active row.
+__global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__restrict__ part, int KZ, int cap,
+                                                                  const float *__restrict__ bias, int cout,
+                                                                  const npvs_counts *__restrict__ counts, int relu,
+                                                                  int out_f32, void *__restrict__ Y) {
+  const int64_t q = cout / 4, total = (int64_t)counts->n_sites * q;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / q), o = (int)(e % q) * 4;
+    f32x4_t sum = *reinterpret_cast<const f32x4_t *>(part + (int64_t)r * cout + o);
+    for (int z = 1; z < KZ; ++z) sum += *reinterpret_cast<const f32x4_t *>(part + ((int64_t)z * cap + r) * cout + o);
+    conv_bf16_epilogue<4>(sum, r, r + 1, o, cout, bias, relu, out_f32, Y);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16 path, weight-stationary, for inputs of at most 64 channels and any number of outputs.
+// Workgroup = 9 waves over the same MB x 16 rows, wave w owning offsets 3w .. 3w + 2;
+// blockIdx.y selects 32 output channels (2 MFMA output blocks).  A wave loads the weight
+// fragments of its 3 offsets x KB chunks x 2 output blocks once (at most 12 fragments) and keeps
+// them in registers while the workgroup walks its row tiles; the next tile's rows and the
+// neighbour indices of the tile after it are loaded during the current tile's products.  The 9
+// partial sums are added in LDS in wave order.
+// ------------------------------------------------------------------------------------------
+template <int KB, int MB>
+__global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
+                                                                  const bf16x8_t *__restrict__ Wp,
+                                                                  const float *__restrict__ bias, int cout,
+                                                                  const int32_t *__restrict__ nbr,
+                                                                  const npvs_counts *__restrict__ counts, int cap,
+                                                                  int relu, int out_f32, void *__restrict__ Y) {
+  constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBW = 2, NBLK = MB * NBW;
+  __shared__ f32x4_t red[KSPLIT * NBLK * 64];
+  const int32_t n = counts->n_sites;
+  const int ntiles = (n + ROWS - 1) / ROWS;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index, uniform (scalar)
+  const int kbeg = wv * KPER, csub = 8 * (lane >> 4);
+  const int NBT = (cout + 15) / 16, nb0 = NBW * blockIdx.y;
+  bf16x8_t aw[KPER][KB][NBW];
+#pragma unroll
+  for (int q = 0; q < KPER; ++q)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        const int g = nb0 + nb < NBT ? nb0 + nb : NBT - 1;  // blocks past cout: any valid fragment
+        aw[q][kb][nb] = Wp[(((int64_t)(kbeg + q) * NBT + g) * KB + kb) * 64 + lane];
+      }
+  int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
+  if (tile < 0) return;  // whole workgroup: tile depends on blockIdx only
+  // indices of a tile (clamped: a missing tile re-reads the last valid one)
+  auto indices = [&](int t, int (&ix)[KPER][MB]) {
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) ix[q][mb] = nbr_index(nbr, cap, kbeg + q, t * ROWS + mb * 16 + (lane & 15), n);
+  };
+  auto rows = [&](const int (&ix)[KPER][MB], bf16x8_t (&b)[KPER][KB][MB]) {
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) b[q][kb][mb] = gather8(X, cin, ix[q][mb], kb * 32 + csub);
+  };
+  int ix[KPER][MB];
+  bf16x8_t bx[KPER][KB][MB];
+  indices(tile, ix);
+  rows(ix, bx);
+  int t1 = xcd_tile(blockIdx.x, gridDim.x, ntiles, 1);
+  indices(t1 >= 0 ? t1 : tile, ix);
+  for (int j = 0; tile >= 0; ++j) {
+    const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
+    bf16x8_t bn[KPER][KB][MB];
+    rows(ix, bn);                                        // tile j + 1 (or a repeat)
+    indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
+    f32x4_t acc[MB][NBW];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], bx[q][kb][mb], acc[mb][nb], 0, 0, 0);
+    __syncthreads();  // the previous tile's readers are done with red
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) red[(wv * NBLK + mb * NBW + nb) * 64 + lane] = acc[mb][nb];
+    __syncthreads();
+    const int row0 = tile * ROWS;
+    for (int blk = wv; blk < NBLK; blk += KSPLIT) {
+      f32x4_t sum = red[blk * 64 + lane];
+      for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
+      const int mb = blk / NBW, nb = blk % NBW;
+      conv_bf16_epilogue<4>(sum, row0 + mb * 16 + (lane & 15), n, (nb0 + nb) * 16 + 4 * (lane >> 4), cout, bias,
+                            relu, out_f32, Y);
+    }
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) bx[q][kb][mb] = bn[q][kb][mb];
+    tile = t1;
+    t1 = t2;
+  }
+}
+
 template <int KB, int NB, int MB, int RG>
 __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16_t *__restrict__ X, int cin,
                                                                      const bf16x8_t *__restrict__ Wp,
@@ -422,6 +633,7 @@ static void launch_bf16_lds(const void *X, int cin, const void *Wp, const float 
 // (MB, RG) = (rows per wave / 16, waves per workgroup): 6 (1, 4), 7 (1, 2), 8 (2, 2), 9 (1, 8),
 // 10 (2, 4), 11 (2, 8).  Larger row blocks read each staged weight fragment for more rows (less
 // weight traffic per row) and suit large batches; small ones keep more waves busy on one frame.
+// Weight-stationary kernel (inputs of at most 64 channels): 12 (16-row tiles), 13 (32-row tiles).
 // Inputs wider than 64 channels use only the 9-way split (a long unrolled offset loop would not
 // fit the registers, nor a double-buffered offset of weights the LDS).
 // kDefaultConvVariant is used by npvs_sparse_conv_fwd; the autotuner can pick another per layer.
@@ -434,6 +646,36 @@ static void launch_bf16(const void *X, int cin, const void *Wp, const float *bia
   G = (G + 7) & ~7;
   conv_fwd_bf16_kernel<KB, NB, MB, KSPLIT><<<G, 64 * KSPLIT, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+template <int KB, int MB>
+static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float *bias, int cout, const int32_t *nbr,
+                             const npvs_counts *counts, int cap, int relu, int out_f32, void *Y, hipStream_t s) {
+  // as many workgroups as fit on the chip at once (9-wave workgroups: two per compute unit with
+  // one input chunk, one with two chunks or 32-row tiles), spread over the output groups; each
+  // walks several row tiles
+  const int groups = (cout + 31) / 32;
+  int G = (KB == 1 && MB == 1 ? 512 : 256) / groups;
+  G = G < 8 ? 8 : G;
+  const int most = stride_grid(cap, 16 * MB, 4096);
+  G = G > most ? most : G;
+  G = (G + 7) & ~7;
+  conv_fwd_bf16_wsta_kernel<KB, MB><<<dim3(G, groups), 576, 0, s>>>(
+      (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+template <int MB>
+static void launch_bf16_wide(const void *X, int cin, const void *Wp, const float *bias, int cout, const int32_t *nbr,
+                             const npvs_counts *counts, int cap, int relu, int out_f32, void *Y, hipStream_t s,
+                             int KZ, float *part) {
+  int G = stride_grid(cap, 16 * MB, 4096);
+  G = (G + 7) & ~7;
+  const dim3 grid(G, (cout + 63) / 64, part ? KZ : 1);
+  conv_fwd_bf16_wide_kernel<MB><<<grid, 576, 0, s>>>((const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr,
+                                                      counts, cap, relu, out_f32, Y, part);
+  if (part)
+    conv_splitk_finish_kernel<<<stride_grid((int64_t)cap * (cout / 4), 256, 4096), 256, 0, s>>>(
+        part, KZ, cap, bias, cout, counts, relu, out_f32, Y);
 }
 
 template <int KB, int NB>
@@ -521,9 +763,23 @@ extern "C" npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *
 namespace npvs {
 // Dispatch of the BF16 kernel on (ceil(cin/32), ceil(cout/16)); MB = 2 rows blocks per wave,
 // offsets split three ways.
+// Input-channel split of the general BF16 kernel: 1, or a divisor-friendly count for 1024+ input
+// channels (8 chunks of 32 channels per split at least, at most 16 splits).
+int splitk_factor(int32_t cin, int32_t cout, int32_t dtype) {
+  const int KB = (cin + 31) / 32;
+  if (dtype != NPVS_BF16 || KB < 32 || cin % 8 || cout % 8) return 1;
+  const int kz = KB / 8;
+  return kz > 16 ? 16 : kz;
+}
+
+size_t conv_fwd_ws_bytes(int32_t cin, int32_t cout, int32_t cap, int32_t dtype) {
+  const int kz = splitk_factor(cin, cout, dtype);
+  return kz > 1 ? sizeof(float) * (size_t)kz * cap * cout : 0;
+}
+
 npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                               const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
-                              int32_t out_f32, void *Y, hipStream_t s, int variant) {
+                              int32_t out_f32, void *Y, hipStream_t s, int variant, void *ws, size_t ws_bytes) {
   if (dtype == NPVS_F32) {
     int G = stride_grid(cap, kF32Rows, 2048);
     G = (G + 7) & ~7;
@@ -531,9 +787,19 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
                                           (float *)Y);
     return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
   }
-  if (cin % 8 || cout % 8 || cin > 512 || cout > 64)
-    return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: BF16 needs cin % 8 == 0, cin <= 512, cout % 8 == 0, cout <= 64");
+  if (cin % 8 || cout % 8)
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: BF16 needs cin % 8 == 0 and cout % 8 == 0");
   const int KB = (cin + 31) / 32, NB = (cout + 15) / 16;
+  if ((variant == 12 || variant == 13) && KB <= 2) {  // weight-stationary tiles
+    if (KB == 1) {
+      if (variant == 12) launch_bf16_wsta<1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+      else launch_bf16_wsta<1, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    } else {
+      if (variant == 12) launch_bf16_wsta<2, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+      else launch_bf16_wsta<2, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    }
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
+  }
 #define NPVS_BF16_CASE(kb, nb)                                                                           \
   if (KB == kb && NB == nb) {                                                                            \
     launch_bf16_variant<kb, nb>(variant, X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s); \
@@ -549,9 +815,55 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
   NPVS_BF16_CASE(2, 4)
   NPVS_BF16_CASE(16, 4)
 #undef NPVS_BF16_CASE
-  return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: no BF16 kernel for this channel shape");
+  // any other shape: up to 64 input channels (e.g. the wide last layer of d = 8 or 16) the
+  // weight-stationary kernel, else the general one (variants 5 and 13 pick 32-row tiles)
+  if (KB <= 2) {
+    const bool wide_rows = variant == 5 || variant == 13;
+    if (KB == 1) {
+      if (wide_rows) launch_bf16_wsta<1, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+      else launch_bf16_wsta<1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    } else {
+      if (wide_rows) launch_bf16_wsta<2, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+      else launch_bf16_wsta<2, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    }
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
+  }
+  // wide inputs: split the channel chunks over workgroups when the caller gave a workspace
+  const int KZ = splitk_factor(cin, cout, dtype);
+  float *part = (KZ > 1 && ws && ws_bytes >= conv_fwd_ws_bytes(cin, cout, cap, dtype)) ? (float *)ws : nullptr;
+  if (variant == 5 || variant == 13)
+    launch_bf16_wide<2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s, KZ, part);
+  else
+    launch_bf16_wide<1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s, KZ, part);
+  return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
 }
 }  // namespace npvs
+
+extern "C" npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype,
+                                                    size_t *bytes) {
+  if (!bytes || cin < 1 || cout < 1 || cap_sites < 1)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_fwd_workspace_size: bad arguments");
+  *bytes = conv_fwd_ws_bytes(cin, cout, cap_sites, dtype);
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_sparse_conv_fwd_ws(const void *X, int32_t cin, const void *Wp, const float *bias,
+                                              int32_t cout, const int32_t *nbr, const npvs_counts *counts,
+                                              int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32,
+                                              int32_t variant, void *Y, void *ws, size_t ws_bytes, void *stream) {
+  if (!X || !Wp || !nbr || !counts || !Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: null pointer");
+  if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: bad sizes");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: dtype must be NPVS_F32 or NPVS_BF16");
+  if (X == Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: X and Y must not alias");
+  if (variant < 0 || variant >= NPVS_CONV_VARIANTS)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: variant out of range");
+  const size_t need = conv_fwd_ws_bytes(cin, cout, cap_sites, dtype);
+  if (need && (!ws || ws_bytes < need))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd_ws: workspace missing or too small");
+  return conv_fwd_dispatch(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32, Y,
+                           as_stream(stream), variant, ws, ws_bytes);
+}
 
 extern "C" npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias,
                                               int32_t cout, const int32_t *nbr, const npvs_counts *counts,
@@ -565,7 +877,7 @@ extern "C" npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const
   if (variant < 0 || variant >= NPVS_CONV_VARIANTS)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: variant out of range");
   return conv_fwd_dispatch(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32, Y,
-                           as_stream(stream), variant);
+                           as_stream(stream), variant, nullptr, 0);
 }
 
 extern "C" npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,

@@ -81,6 +81,13 @@ constexpr int kFroxTileZ = 8;
 constexpr int kFroxTileCap = 2048;  // triangle slots per tile before the tile falls back to a full scan
 
 // Tile shape of the BF16 convolution used when no autotuned choice is given (see conv.hip).
-constexpr int kDefaultConvVariant = 3;
+constexpr int kDefaultConvVariant = NPVS_DEFAULT_CONV_VARIANT;
+
+// One convolution layer on `s` (conv.hip).  ws (nullable): workspace of conv_fwd_ws_bytes() bytes
+// that lets wide BF16 inputs split their channels over several workgroups.
+npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                              const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
+                              int32_t out_f32, void *Y, hipStream_t s, int variant, void *ws, size_t ws_bytes);
+size_t conv_fwd_ws_bytes(int32_t cin, int32_t cout, int32_t cap, int32_t dtype);
 
 }  // namespace npvs

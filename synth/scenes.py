@@ -212,6 +212,15 @@ CONFIGS = {
 }
 _g, _a = _c4_grids()
 CONFIGS["batch16"] = Config("batch16", _g, 4, [64] * 7, "boxes", list(range(40, 56)), 101, _a)
+# the paper's interleave factors: first and last layers d^3 = 512 or 4096 channels wide
+CONFIGS["city256_d8"] = Config("city256_d8", [(256, 256, 128)], 8, [512] + [64] * 5 + [512], "city", [1], 108,
+                               [dict()])
+CONFIGS["city256_d16"] = Config("city256_d16", [(256, 256, 128)], 16, [4096] + [64] * 5 + [4096], "city", [1],
+                                116, [dict()])
+CONFIGS["boxes64_d8"] = Config("boxes64_d8", [(64, 64, 64)], 8, [512, 32, 512], "boxes", [5], 208,
+                               [dict(n_boxes=12, side_lo=4, side_hi=16)])
+CONFIGS["boxes64_d16"] = Config("boxes64_d16", [(64, 64, 64)], 16, [4096, 32, 4096], "boxes", [6], 216,
+                                [dict(n_boxes=12, side_lo=4, side_hi=16)])
 
 
 def config(name: str) -> Config:

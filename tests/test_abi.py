@@ -35,10 +35,23 @@ def test_version_and_sizes(lib):
 
 def test_header_constants_match_binding():
     text = open(L.HEADER).read()
-    for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK"):
+    for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT"):
         assert f"#define {name} {getattr(L, name)}" in text, name
     assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16
     assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes
+
+
+def test_conv_workspace_sizes_and_checks(lib):
+    n = ctypes.c_size_t()
+    L.call("npvs_conv_fwd_workspace_size", 4096, 64, 1000, L.NPVS_BF16, ctypes.byref(n))
+    assert n.value == 16 * 1000 * 64 * 4  # 128 chunks of 32 channels split 16 ways, float32 partials
+    for cin, cout, dt in ((64, 64, L.NPVS_BF16), (512, 64, L.NPVS_BF16), (4096, 64, L.NPVS_F32)):
+        L.call("npvs_conv_fwd_workspace_size", cin, cout, 1000, dt, ctypes.byref(n))
+        assert n.value == 0
+    fake = ctypes.c_void_p(16)  # never dereferenced: the argument check answers first
+    st = lib.npvs_sparse_conv_fwd_ws(fake, 4096, fake, None, 64, fake, fake, 1000, L.NPVS_BF16, 1, 0, 0,
+                                     ctypes.c_void_p(32), None, 0, None)
+    assert st == L.NPVS_ERR_INVALID_ARG and b"workspace" in lib.npvs_last_error()
 
 
 def test_batched_packing_argument_checks(lib):

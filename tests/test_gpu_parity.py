@@ -102,7 +102,7 @@ def test_froxelize_empty_and_all_ignored():
 
 
 # ------------------------------------------------------------------------------- sites / rulebook
-@pytest.mark.parametrize("d", [2, 4, 8])
+@pytest.mark.parametrize("d", [2, 4, 8, 16, 32])
 def test_rulebook_bit_exact_batched(d):
     dims = [(64, 64, 64), (32, 32, 32), (128, 64, 32)]
     tri_list = [synth.box_scene(10 + i, g, 25, 2, 12) for i, g in enumerate(dims)]
@@ -246,7 +246,7 @@ def test_plan_autotune_picks_valid_shapes_and_keeps_results():
         plan.set_weights(li, torch.from_numpy(W).to(DEV), torch.from_numpy(b).to(DEV))
     v = plan.autotune(tris, reps=3)
     print("autotuned variants", v, flush=True)
-    assert len(v) == 6 and all(0 <= x < 10 for x in v) and len(set(v[:5])) == 1
+    assert len(v) == 6 and all(0 <= x < npvs.NPVS_CONV_VARIANTS for x in v) and len(set(v[:5])) == 1
     pvs, logits = plan.forward(tris, want_logits=True)
     out = oracle.forward(t, cfg.grids[0], cfg.d, layers)
     got = to_np(logits).reshape(out["logits"].shape)
