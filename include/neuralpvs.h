@@ -180,7 +180,7 @@ npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, con
  * 5 and 13 select its 32-row tiles).  All variants give results within float32 rounding of each
  * other; each one is deterministic.  Ignored by the FP32 path. */
 #define NPVS_CONV_VARIANTS 14
-#define NPVS_DEFAULT_CONV_VARIANT 3 /* the tile shape npvs_sparse_conv_fwd uses */
+#define NPVS_DEFAULT_CONV_VARIANT 12 /* the tile shape npvs_sparse_conv_fwd and the data gradient use */
 npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                     const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                     int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);

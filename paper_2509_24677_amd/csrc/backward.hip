@@ -454,7 +454,7 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
   }
   if (dX) {
     st = conv_fwd_dispatch(dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, Wt, nullptr, cin, nbr,
-                           counts, cap_sites, dtype, 0, 1, dX, s, 0, nullptr, 0);
+                           counts, cap_sites, dtype, 0, 1, dX, s, kDefaultConvVariant, nullptr, 0);
     if (st != NPVS_OK) return st;
   }
   dim3 gw(kWgSlices, 27);

@@ -543,9 +543,14 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
                                                                      const npvs_counts *__restrict__ counts, int cap,
                                                                      int relu, int out_f32, void *__restrict__ Y) {
   constexpr int ROWS = 16 * MB * RG;
-  constexpr int FR = NB * KB;                 // weight fragments of one offset (64 lanes x 16 bytes each)
-  constexpr int WPT = (FR + RG - 1) / RG;     // fragments each thread stages per offset (some idle)
-  __shared__ bf16x8_t Ws[2][FR * 64];
+  constexpr int FR = NB * KB;              // weight fragments of one offset (64 lanes x 16 bytes each)
+  constexpr int WPT = (FR + RG - 1) / RG;  // fragments each thread stages per offset (some idle)
+  constexpr int NS = 4;                    // LDS weight slots: offset o lives in slot o % NS
+  // Offset o's weights are loaded into registers at step o - 4, stored to LDS at step o - 2 and
+  // read at step o; its rows are gathered at step o - 3.  One barrier ends every step, which
+  // orders each slot's store after the last read of the offset it held (step o - 4) and before
+  // its first read.
+  __shared__ bf16x8_t Ws[NS][FR * 64];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -566,48 +571,53 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8_t wreg[WPT], bx[2][MB][KB];
-    // prologue: offset 0's weights into LDS slot 0, its rows into registers
+    bf16x8_t wreg[2][WPT], bx[4][MB][KB];
+    auto wload = [&](int o, bf16x8_t (&w)[WPT]) {
 #pragma unroll
-    for (int i = 0; i < WPT; ++i)
-      if (FR % RG == 0 || tid + i * 64 * RG < FR * 64) Ws[0][tid + i * 64 * RG] = W[tid + i * 64 * RG];
+      for (int i = 0; i < WPT; ++i)
+        if (FR % RG == 0 || tid + i * 64 * RG < FR * 64) w[i] = W[(int64_t)o * FR * 64 + tid + i * 64 * RG];
+    };
+    auto wstore = [&](int slot, const bf16x8_t (&w)[WPT]) {
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
+      for (int i = 0; i < WPT; ++i)
+        if (FR % RG == 0 || tid + i * 64 * RG < FR * 64) Ws[slot][tid + i * 64 * RG] = w[i];
+    };
+    auto gather = [&](int o, bf16x8_t (&b)[MB][KB]) {
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) bx[0][mb][kb] = gather8(X, cin, idx[0][mb], kb * 32 + csub);
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) b[mb][kb] = gather8(X, cin, idx[o][mb], kb * 32 + csub);
+    };
+    // prologue: offsets 0 and 1 in LDS, 2 and 3 in registers, rows of offsets 0-2
+    {
+      bf16x8_t w0[WPT], w1[WPT];
+      wload(0, w0);
+      wload(1, w1);
+      wload(2, wreg[0]);
+      wload(3, wreg[1]);
+      gather(0, bx[0]);
+      gather(1, bx[1]);
+      gather(2, bx[2]);
+      wstore(0, w0);
+      wstore(1, w1);
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
-      const int cur = k & 1, nxt = (k + 1) & 1;
-      if (k + 1 < 27) {  // loads of offset k + 1
+      if (k + 2 < 27) wstore((k + 2) % NS, wreg[k % 2]);  // offset k + 2 (loaded at step k - 2)
+      if (k + 4 < 27) wload(k + 4, wreg[k % 2]);
+      if (k + 3 < 27) gather(k + 3, bx[(k + 3) % 4]);
+      // offsets without any neighbour in this wave gather zeros: no branch around the products
 #pragma unroll
-        for (int i = 0; i < WPT; ++i)
-          if (FR % RG == 0 || tid + i * 64 * RG < FR * 64)
-            wreg[i] = W[(int64_t)(k + 1) * FR * 64 + tid + i * 64 * RG];
+      for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8_t aw = Ws[k % NS][(nb * KB + kb) * 64 + lane];
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb) bx[nxt][mb][kb] = gather8(X, cin, idx[k + 1][mb], kb * 32 + csub);
-      }
-      __syncthreads();  // slot cur holds offset k's weights; slot nxt is no longer read
-      bool a = false;
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) a = a || idx[k][mb] >= 0;
-      if (__any(a)) {
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const bf16x8_t aw = Ws[cur][(nb * KB + kb) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[cur][mb][kb], acc[mb][nb], 0, 0, 0);
-          }
-      }
-      if (k + 1 < 27) {
-#pragma unroll
-        for (int i = 0; i < WPT; ++i)
-          if (FR % RG == 0 || tid + i * 64 * RG < FR * 64) Ws[nxt][tid + i * 64 * RG] = wreg[i];
-      }
+          for (int mb = 0; mb < MB; ++mb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[k % 4][mb][kb], acc[mb][nb], 0, 0, 0);
+        }
+      __syncthreads();
     }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -615,7 +625,6 @@ __global__ __launch_bounds__(64 * RG) void conv_fwd_bf16_lds_kernel(const uint16
       for (int nb = 0; nb < NB; ++nb)
         conv_bf16_epilogue<NB>(acc[mb][nb], row0 + mb * 16 + (lane & 15), n, nb * 16 + 4 * (lane >> 4), cout, bias,
                                relu, out_f32, Y);
-    __syncthreads();  // the next tile's prologue rewrites slot 0
   }
 }
 
