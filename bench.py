@@ -210,6 +210,32 @@ def bench_wide(args, dev, timed_launches):
     return res
 
 
+def bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs):
+    """Culling against the city's BF16 PVS: every scene triangle (npvs_visible_triangles), and 2048
+    box-shaped temporal bounding volumes of 10 triangles each as objects (npvs_visible_objects)."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+
+    vis = npvs.visible_triangles(tris, n_tris, dims, pvs)
+    ms_t = float(np.median(timed_launches(lambda: npvs.visible_triangles(tris, n_tris, dims, pvs), 20)))
+    boxes = synth.box_scene(77, dims[0], 2048, 4, 24)
+    tb = torch.from_numpy(boxes).to(dev)
+    off = torch.arange(0, len(boxes) + 1, 10, dtype=torch.int64, device=dev)
+
+    def tbv():
+        v = npvs.visible_triangles(tb, [len(boxes)], dims, pvs)
+        return npvs.visible_objects(v, off)
+    kept = tbv()
+    ms_o = float(np.median(timed_launches(lambda: (tbv(),), 20)))  # two launches per call
+    return {"scene_triangles": int(sum(n_tris)), "kept_triangles": int(vis.sum().item()),
+            "triangles_ms": ms_t, "triangles_per_s": sum(n_tris) / (ms_t * 1e-3),
+            "tbv_objects": 2048, "kept_objects": int(kept.sum().item()), "tbv_ms": ms_o,
+            "objects_per_s": 2048 / (ms_o * 1e-3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -498,6 +524,8 @@ def main():
     print("# batch16 " + json.dumps(batch16), file=sys.stderr, flush=True)
     wide = bench_wide(args, dev, timed_launches)
     print("# interleave factors 8 and 16 " + json.dumps(wide), file=sys.stderr, flush=True)
+    cull = bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs_b)
+    print("# culling " + json.dumps(cull), file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------------ accuracy
     torch.cuda.synchronize()
@@ -561,6 +589,7 @@ def main():
         "stages_hbm": stage_gbs,
         "batch16": batch16,
         "interleave_8_16": wide,
+        "culling": cull,
         "accuracy": acc,
     }
     print(json.dumps(line))

@@ -238,6 +238,22 @@ npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row
                                         float *logits, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Culling against the PVS (the pipeline discards primitives whose froxels are all invisible,
+ * Fig. 2; dynamic objects: the froxelized temporal bounding volume of a moving object is tested
+ * against the froxelized PVS and the object is pruned when none of its froxels is visible).
+ *   visible[t] = 1 iff some froxel that triangle t overlaps (the exact test of npvs_froxelize:
+ *   closed froxels, 1/256 fixed point) has its bit set in pvs_bits, else 0; ignored triangles
+ *   (|coordinate| >= 1024 or not finite) are 0.  tris, n_tris, n_grids, dims as for
+ *   npvs_froxelize; pvs_bits (device) packed like occ_bits; visible (device) uint8 [total].
+ * npvs_visible_objects: visible[i] = OR of vis_tris[obj_off[i] .. obj_off[i + 1] - 1];
+ *   obj_off (device) int64 [n_objects + 1], non-decreasing, within vis_tris.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_visible_triangles(const float *tris, const int64_t *n_tris, int32_t n_grids, const npvs_dims *dims,
+                                   const uint8_t *pvs_bits, uint8_t *visible, void *stream);
+npvs_status npvs_visible_objects(const uint8_t *vis_tris, const int64_t *obj_off, int64_t n_objects,
+                                 uint8_t *visible, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Training loss per grid over the froxels of its active blocks (Sec. 3.3: repulsive visibility
  * loss L_rv = L_attr + L_rep with L_attr read as FN/GTP, L_rep = FP/GTP, combined with weight
  * lambda; BCE stands in for the Dice term):

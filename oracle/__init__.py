@@ -100,6 +100,28 @@ def froxelize(tris, dims):
     return occ, int(ign)
 
 
+def visible_triangles(tris, dims, pvs) -> np.ndarray:
+    """Culling against a PVS (the pipeline of Fig. 2 discards primitives whose froxels are all
+    invisible; Sec. 6, dynamic objects, tests a froxelized temporal bounding volume the same way):
+    uint8 [T], 1 iff some froxel the triangle overlaps (the froxelization of that triangle alone)
+    has its PVS bit set."""
+    t = np.asarray(tris, np.float32).reshape(-1, 9)
+    pvs = np.asarray(pvs, np.uint8).reshape(dims[2], dims[1], dims[0] // 8)
+    out = np.zeros(t.shape[0], np.uint8)
+    for i in range(t.shape[0]):
+        occ, _ = froxelize(t[i:i + 1], dims)
+        out[i] = 1 if (occ & pvs).any() else 0
+    return out
+
+
+def visible_objects(vis_tris, obj_off) -> np.ndarray:
+    """An object (e.g. the triangles of a temporal bounding volume) is kept iff any of its
+    triangles is visible: uint8 [n_objects], triangles obj_off[i] .. obj_off[i+1] - 1."""
+    v = np.asarray(vis_tris, np.uint8)
+    off = np.asarray(obj_off, np.int64)
+    return np.array([1 if v[off[i]:off[i + 1]].any() else 0 for i in range(len(off) - 1)], np.uint8)
+
+
 def unpack(bits: np.ndarray) -> np.ndarray:
     """Packed [nz][ny][nx/8] -> uint8 0/1 [nz][ny][nx] (bit x & 7 of byte x >> 3)."""
     return np.unpackbits(bits, axis=-1, bitorder="little")

@@ -250,6 +250,25 @@ def deinterleave_threshold(Y: torch.Tensor, rb: Rulebook, occ: torch.Tensor, wan
     return pvs, logits
 
 
+# --------------------------------------------------------------------------------- culling
+def visible_triangles(tris: torch.Tensor, n_tris, dims, pvs: torch.Tensor) -> torch.Tensor:
+    """uint8 [total triangles]: 1 iff the triangle overlaps a froxel whose PVS bit is set."""
+    dims = [tuple(g) for g in dims]
+    total = int(sum(n_tris))
+    vis = torch.empty(total, dtype=torch.uint8, device=pvs.device)
+    L.call("npvs_visible_triangles", _p(tris), L.i64_array(list(n_tris)), len(dims), L.dims_array(dims), _p(pvs),
+           _p(vis), _stream())
+    return vis
+
+
+def visible_objects(vis_tris: torch.Tensor, obj_off: torch.Tensor) -> torch.Tensor:
+    """uint8 [n_objects]: OR of each object's triangle flags (obj_off int64 [n_objects + 1])."""
+    n = obj_off.numel() - 1
+    out = torch.empty(max(n, 0), dtype=torch.uint8, device=vis_tris.device)
+    L.call("npvs_visible_objects", _p(vis_tris), _p(obj_off), n, _p(out), _stream())
+    return out
+
+
 # --------------------------------------------------------------------------------- training
 def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 0.99, want_grad: bool = True):
     """Per-grid BCE + repulsive visibility loss.  Returns (stats float32 [n_grids + 1][8] with

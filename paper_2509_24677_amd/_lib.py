@@ -70,6 +70,8 @@ SIGNATURES = {
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
     "npvs_sparse_conv_bwd_split": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P]),
+    "npvs_visible_triangles": (i32, [P, PI64, i32, P, P, P, P]),
+    "npvs_visible_objects": (i32, [P, P, i64, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),
     "npvs_loss_workspace_size": (i32, [i32, PS]),
     "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, P, P, P, sz, P]),

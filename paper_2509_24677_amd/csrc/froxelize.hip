@@ -99,6 +99,43 @@ __device__ __forceinline__ void make_setup(const int32_t *q, TriSetup &S) {
   }
 }
 
+// Fixed-point vertices (rint(256 v), round half to even) and the clipped closed-froxel range of
+// triangle t; true when the triangle is ignored (a coordinate not finite or |v| >= 1024) or its
+// range misses the grid.
+__device__ __forceinline__ bool quantize_tri(const float *__restrict__ tris, int64_t t, const GridDesc &g,
+                                             int32_t *q, int32_t *lo, int32_t *hi) {
+  bool ok = true;
+  int32_t mn[3], mx[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = 0x7fffffff;
+    mx[a] = -0x7fffffff;
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float x = tris[t * 9 + v * 3 + a];
+      ok = ok && (__builtin_fabsf(x) < (float)NPVS_MAX_DIM);  // finite and |x| < 1024 (NaN fails)
+      int32_t qq = ok ? (int32_t)__builtin_rintf(x * 256.0f) : 0;  // exact scaling, round half to even
+      q[v * 3 + a] = qq;
+      mn[a] = qq < mn[a] ? qq : mn[a];
+      mx[a] = qq > mx[a] ? qq : mx[a];
+    }
+  const int32_t dims[3] = {g.nx, g.ny, g.nz};
+  bool empty = !ok;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // closed cells [256 i, 256 i + 256] meeting [mn, mx]: i in [floor((mn-1)/256), floor(mx/256)]
+    lo[a] = (mn[a] - 1) >> 8;
+    hi[a] = mx[a] >> 8;
+    lo[a] = lo[a] < 0 ? 0 : lo[a];
+    hi[a] = hi[a] > dims[a] - 1 ? dims[a] - 1 : hi[a];
+    empty = empty || lo[a] > hi[a];
+  }
+  return empty;
+}
+
 __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__ tris, Batch B, int64_t total,
                                                         TriSetup *__restrict__ recs, int32_t *__restrict__ tile_count,
                                                         int32_t *__restrict__ tile_list) {
@@ -107,37 +144,8 @@ __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__
   if (t < total) {
     const GridDesc &g = B.g[tri_grid(B, t)];
     TriSetup S = {};
-    int32_t q[9];
-    bool ok = true;
-    int32_t mn[3], mx[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = 0x7fffffff;
-      mx[a] = -0x7fffffff;
-    }
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float x = tris[t * 9 + v * 3 + a];
-        ok = ok && (__builtin_fabsf(x) < (float)NPVS_MAX_DIM);  // finite and |x| < 1024 (NaN fails)
-        int32_t qq = ok ? (int32_t)__builtin_rintf(x * 256.0f) : 0;  // exact scaling, round half to even
-        q[v * 3 + a] = qq;
-        mn[a] = qq < mn[a] ? qq : mn[a];
-        mx[a] = qq > mx[a] ? qq : mx[a];
-      }
-    int32_t dims[3] = {g.nx, g.ny, g.nz};
-    int32_t lo[3], hi[3];
-    bool empty = !ok;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      // closed cells [256 i, 256 i + 256] meeting [mn, mx]: i in [floor((mn-1)/256), floor(mx/256)]
-      lo[a] = (mn[a] - 1) >> 8;
-      hi[a] = mx[a] >> 8;
-      lo[a] = lo[a] < 0 ? 0 : lo[a];
-      hi[a] = hi[a] > dims[a] - 1 ? dims[a] - 1 : hi[a];
-      empty = empty || lo[a] > hi[a];
-    }
+    int32_t q[9], lo[3], hi[3];
+    const bool empty = quantize_tri(tris, t, g, q, lo, hi);
     if (!empty) make_setup(q, S);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -218,6 +226,97 @@ __device__ __forceinline__ uint32_t frox_row(const TriSetup &S, int xa, int xb, 
     m |= (uint32_t)hit << (x - X0);
   }
   return m;
+}
+
+// Culling against a PVS.  A workgroup takes 256 triangles: each thread quantizes one and stages
+// its overlap constants in LDS, a scan of the rows (y, z) each range covers gives a flat list of
+// (triangle, row) items, and each thread tests one row at a time: the PVS word(s) of the row
+// first, the exact overlap test only where a visible froxel lies in the range.  A hit sets the
+// triangle's flag in LDS (a plain store of 1), and rows of flagged triangles are skipped.
+__global__ __launch_bounds__(256) void visible_tris_kernel(const float *__restrict__ tris, Batch B, int64_t total,
+                                                            const uint8_t *__restrict__ pvs,
+                                                            uint8_t *__restrict__ visible) {
+  __shared__ TriSetup srec[256];
+  __shared__ int row0[257];
+  __shared__ int wsum[4];
+  __shared__ int gidx[256];
+  __shared__ uint32_t flag[256];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
+    const int64_t t = base + tid;
+    int rows = 0;
+    flag[tid] = 0;
+    if (t < total) {
+      const int b = tri_grid(B, t);
+      int32_t q[9], lo[3], hi[3];
+      TriSetup S = {};
+      const bool empty = quantize_tri(tris, t, B.g[b], q, lo, hi);
+      if (!empty) make_setup(q, S);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        S.lo[a] = (int16_t)(empty ? 1 : lo[a]);
+        S.hi[a] = (int16_t)(empty ? 0 : hi[a]);
+      }
+      srec[tid] = S;
+      gidx[tid] = b;
+      if (!empty) rows = (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+    }
+    int x = rows;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();  // also orders the previous chunk's reads before these writes
+    int pre = 0;
+    for (int k = 0; k < w; ++k) pre += wsum[k];
+    row0[tid] = pre + x - rows;
+    if (tid == 255) row0[256] = pre + x;
+    __syncthreads();
+    const int R = row0[256];
+    const int n = total - base < 256 ? (int)(total - base) : 256;
+    for (int r = tid; r < R; r += 256) {
+      int lo = 0, hi = n - 1;  // last staged triangle whose rows start at or before r
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row0[mid] <= r) lo = mid;
+        else hi = mid - 1;
+      }
+      if (flag[lo]) continue;  // already visible
+      const TriSetup &S = srec[lo];
+      const GridDesc &g = B.g[gidx[lo]];
+      const int rr = r - row0[lo], ny = S.hi[1] - S.lo[1] + 1;
+      const int y = S.lo[1] + rr % ny, z = S.lo[2] + rr / ny;
+      const uint8_t *row = pvs + g.occ_off + ((int64_t)z * g.ny + y) * (g.nx >> 3);
+      for (int X0 = S.lo[0] & ~31; X0 <= S.hi[0]; X0 += 32) {
+        const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+        uint32_t m = 0;  // PVS bits of froxels X0 .. X0 + 31 (bytes past the row read as 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (X0 + 8 * k < g.nx) m |= (uint32_t)row[(X0 >> 3) + k] << (8 * k);
+        m &= (xb - X0 == 31 ? ~0u : ((2u << (xb - X0)) - 1u)) & ~((1u << (xa - X0)) - 1u);
+        if (m && (frox_row(S, xa, xb, y, z, X0) & m)) {
+          flag[lo] = 1u;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (t < total) visible[t] = flag[tid] ? 1 : 0;
+    __syncthreads();  // flags and staging are rewritten by the next chunk
+  }
+}
+
+// One thread per object: OR of its triangles' flags.
+__global__ __launch_bounds__(256) void visible_objects_kernel(const uint8_t *__restrict__ vis_tris,
+                                                               const int64_t *__restrict__ obj_off, int64_t n_obj,
+                                                               uint8_t *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_obj; i += (int64_t)gridDim.x * blockDim.x) {
+    uint8_t v = 0;
+    for (int64_t t = obj_off[i]; t < obj_off[i + 1] && !v; ++t) v = vis_tris[t];
+    out[i] = v;
+  }
 }
 
 __device__ __forceinline__ const GridDesc &tile_grid(const Batch &B, int tile) {
@@ -445,4 +544,30 @@ extern "C" npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, 
   }
   frox_merge_kernel<<<(B.total_tiles + 3) / 4, 256, 0, s>>>(B, cnt, part, occ_bits);
   return check_hip(hipGetLastError(), "npvs_froxelize");
+}
+
+extern "C" npvs_status npvs_visible_triangles(const float *tris, const int64_t *n_tris, int32_t n_grids,
+                                              const npvs_dims *dims, const uint8_t *pvs_bits, uint8_t *visible,
+                                              void *stream) {
+  if (!n_tris || !pvs_bits) return fail(NPVS_ERR_INVALID_ARG, "npvs_visible_triangles: null pointer");
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, 1, n_tris, &B);
+  if (st != NPVS_OK) return st;
+  int64_t total = 0;
+  for (int b = 0; b < n_grids; ++b) total += n_tris[b];
+  if (total == 0) return NPVS_OK;
+  if (!tris || !visible) return fail(NPVS_ERR_INVALID_ARG, "npvs_visible_triangles: null triangles or output");
+  visible_tris_kernel<<<stride_grid(total, 256, 4096), 256, 0, as_stream(stream)>>>(tris, B, total, pvs_bits,
+                                                                                      visible);
+  return check_hip(hipGetLastError(), "npvs_visible_triangles");
+}
+
+extern "C" npvs_status npvs_visible_objects(const uint8_t *vis_tris, const int64_t *obj_off, int64_t n_objects,
+                                            uint8_t *visible, void *stream) {
+  if (n_objects < 0) return fail(NPVS_ERR_INVALID_ARG, "npvs_visible_objects: n_objects < 0");
+  if (n_objects == 0) return NPVS_OK;
+  if (!vis_tris || !obj_off || !visible) return fail(NPVS_ERR_INVALID_ARG, "npvs_visible_objects: null pointer");
+  visible_objects_kernel<<<stride_grid(n_objects, 256, 4096), 256, 0, as_stream(stream)>>>(vis_tris, obj_off,
+                                                                                           n_objects, visible);
+  return check_hip(hipGetLastError(), "npvs_visible_objects");
 }
