@@ -239,7 +239,7 @@ npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row
 
 /* ---------------------------------------------------------------------------------------------
  * Culling against the PVS (the pipeline discards primitives whose froxels are all invisible,
- * Fig. 2; dynamic objects: the froxelized temporal bounding volume of a moving object is tested
+ * Fig. 3; Sec. 5.6: the froxelized temporal bounding volume of a moving object is tested
  * against the froxelized PVS and the object is pruned when none of its froxels is visible).
  *   visible[t] = 1 iff some froxel that triangle t overlaps (the exact test of npvs_froxelize:
  *   closed froxels, 1/256 fixed point) has its bit set in pvs_bits, else 0; ignored triangles

@@ -101,8 +101,8 @@ def froxelize(tris, dims):
 
 
 def visible_triangles(tris, dims, pvs) -> np.ndarray:
-    """Culling against a PVS (the pipeline of Fig. 2 discards primitives whose froxels are all
-    invisible; Sec. 6, dynamic objects, tests a froxelized temporal bounding volume the same way):
+    """Culling against a PVS (the pipeline of Fig. 3 discards primitives whose froxels are all
+    invisible; Sec. 5.6, dynamic scenes, tests a froxelized temporal bounding volume the same way):
     uint8 [T], 1 iff some froxel the triangle overlaps (the froxelization of that triangle alone)
     has its PVS bit set."""
     t = np.asarray(tris, np.float32).reshape(-1, 9)
