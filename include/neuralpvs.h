@@ -272,7 +272,7 @@ npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, con
                       float *dlogits, void *ws, size_t ws_bytes, void *stream);
 
 /* Adam (Kingma & Ba) step t >= 1 on float32 masters, with weight decay added to the gradient
- * (the paper's "learning rate decay rate"); p, g, m, v (device) float32 [n]. */
+ * (read from the decay rate the paper lists with the learning rate); p, g, m, v (device) float32 [n]. */
 npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float beta1,
                       float beta2, float eps, float weight_decay, void *stream);
 

@@ -31,7 +31,7 @@ static int64_t min3(int64_t a, int64_t b, int64_t c) { int64_t m = a < b ? a : b
 static int64_t max3(int64_t a, int64_t b, int64_t c) { int64_t m = a > b ? a : b; return m > c ? m : c; }
 
 /* ------------------------------------------------------------------------------------------
- * Froxelization (Sec. 3.2 "Pre-processing"; Fig. 2(b)): G(x) = 1 iff some triangle overlaps
+ * Froxelization (Sec. 3.2, pre-processing; Fig. 2(b)): G(x) = 1 iff some triangle overlaps
  * froxel x.  The paper rasterizes "conservatively"; the exact reading used here is
  * closed-box / triangle intersection, decided by the separating-axis theorem on vertices
  * quantized to 1/256 froxel with round-half-to-even.  All predicates are exact in int64.
@@ -132,8 +132,8 @@ static int get_bit(const uint8_t *g, int nx, int ny, int x, int y, int z) {
 }
 
 /* ------------------------------------------------------------------------------------------
- * Active sites (Sec. 2.3: sparse tensors store only sites that contain geometry; Sec. 5.3:
- * "only the positions where geometry exists" are recorded).  A block is active iff one of its
+ * Active sites (Sec. 2.3: sparse tensors store only sites that contain geometry; Sec. 5.2: an
+ * empty region costs no memory).  A block is active iff one of its
  * d^3 froxels is occupied; rows are numbered in ascending key order.
  * ------------------------------------------------------------------------------------------ */
 int32_t oracle_active_sites(const uint8_t *occ, int nx, int ny, int nz, int d, int32_t *keys) {
@@ -372,7 +372,7 @@ void oracle_subm_conv_bwd(const double *X, int32_t n, int cin, const double *W, 
 
 /* ------------------------------------------------------------------------------------------
  * Adam (Kingma & Ba), one step t >= 1, on FP64 copies; weight decay is added to the gradient
- * (the paper's "learning rate decay rate 1e-10" read as weight decay).
+ * (the decay rate of 1e-10 that the paper lists with the learning rate, read as weight decay).
  * ------------------------------------------------------------------------------------------ */
 void oracle_adam(double *p, const double *g, double *m, double *v, int64_t count, int64_t t, double lr,
                  double b1, double b2, double eps, double wd) {

@@ -1,4 +1,4 @@
-"""Pins of the oracle's froxelization (Sec. 3.2 "Pre-processing", Fig. 2(b)).
+"""Pins of the oracle's froxelization (Sec. 3.2, pre-processing; Fig. 2(b)).
 
 The oracle decides triangle / closed-froxel overlap with an integer separating-axis test.  These
 tests pin it to things other than itself: an exact rational polygon-clipping test over every
