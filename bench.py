@@ -239,7 +239,7 @@ def bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(grids are independent frames; see the sharding note in the design document)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
