@@ -226,6 +226,37 @@ npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *W
                                        int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
                                        size_t ws_bytes, void *stream, void *wgrad_stream);
 
+/* The backward of a stack of BF16 layers as a chain, one call per layer from the top, with each
+ * layer's ReLU' fused into the data gradient of the layer above it (the same chain rule as above;
+ * the gradients are in a different float32 summation order for db only: dZ and dW are
+ * bit-identical to npvs_sparse_conv_bwd).  A layer's dZ travels as bfloat16 [cap][cout] (the
+ * MFMA operand; rows >= n_sites undefined) with a bias partial table dbp, float32
+ * [NPVS_BWD_DB_PARTS][cout], whose column sums in a fixed order give db.
+ *
+ * npvs_conv_bwd_begin: dZ = bf16(dY * [Y > 0]) (relu) or bf16(dY), and its dbp, for the top
+ *   layer.  dY (device) float32 [cap][cout], Y (device, used when relu) bfloat16 [cap][cout];
+ *   cout <= 64, cout % 4 == 0, dY and Y 16-byte aligned.
+ * npvs_sparse_conv_bwd_chain: given this layer's dZ / dbp (as begin or the chain call of the
+ *   layer above wrote them), computes dW [27][cin][cout] and db [cout] (float32, overwritten) on
+ *   wgrad_stream (after a wait for `stream`), and, when dZ_below is non-null, on `stream`
+ *   dZ_below[r][c] = bf16(dX[r][c] * [X[r][c] > 0]) (relu_below; else without the mask) for
+ *   r < n_sites with its dbp_below (float32 [NPVS_BWD_DB_PARTS][cin]): the dZ / dbp of the layer
+ *   below, whose output X is.  X (device) bfloat16 layer input [cap][cin]; Wt as for
+ *   npvs_sparse_conv_bwd; cin, cout <= 64 and multiples of 8; ws (device) of
+ *   npvs_conv_bwd_chain_workspace_size() bytes, scratch.  Until the caller makes `stream` wait
+ *   for wgrad_stream, dZ, dbp, X, dW, db and ws are in use by wgrad_stream (one ws serves
+ *   calls whose wgrad_stream is the same stream); dZ_below / dbp_below must not alias them.
+ *   wgrad_stream may equal stream; both may be under capture. */
+#define NPVS_BWD_DB_PARTS 512
+npvs_status npvs_conv_bwd_begin(const float *dY, const void *Y, int32_t cout, const npvs_counts *counts,
+                                int32_t cap_sites, int32_t relu, void *dZ, float *dbp, void *stream);
+npvs_status npvs_conv_bwd_chain_workspace_size(int32_t cin, int32_t cout, size_t *bytes);
+npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *dZ,
+                                       const float *dbp, const int32_t *nbr, const int32_t *rb_off,
+                                       const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
+                                       int32_t relu_below, void *dZ_below, float *dbp_below, float *dW, float *db,
+                                       void *ws, size_t ws_bytes, void *stream, void *wgrad_stream);
+
 /* ---------------------------------------------------------------------------------------------
  * De-interleave and threshold (Sec. 3.1 V = 1[f(G) >= tau] with tau = 0.5, read as logit >= 0;
  * Sec. 3.3 g_d^-1; Sec. 3.2 the visible set lies inside the occupied set, so V is masked by G):

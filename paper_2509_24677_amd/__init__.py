@@ -21,7 +21,7 @@ from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  #
 
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
-    "sparse_conv_fwd", "sparse_conv_bwd", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
+    "sparse_conv_fwd", "sparse_conv_bwd", "conv_bwd_begin", "sparse_conv_bwd_chain", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
     "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
 ]
 
@@ -221,6 +221,8 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
     dev = X.device
     if ws is None:
         ws = conv_bwd_workspace(cin, cout, rb, dtype)
+        if wgrad_stream is not None:  # freed here, still read by the side stream
+            ws.record_stream(wgrad_stream)
     dX = torch.empty((rb.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
     if dW is None:
         dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
@@ -235,6 +237,53 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
     else:
         L.call("npvs_sparse_conv_bwd_split", *args, ctypes.c_void_p(wgrad_stream.cuda_stream))
     return dX, dW, db
+
+
+def conv_bwd_begin(dY: torch.Tensor, rb: Rulebook, Y: torch.Tensor | None = None, relu: bool = False):
+    """Top of a BF16 backward chain: (dZ bfloat16 [cap][C], dbp float32 [NPVS_BWD_DB_PARTS][C]) from
+    dY float32 [cap][C] (masked by Y > 0 when relu)."""
+    C = dY.shape[1]
+    dY = dY.contiguous()
+    dZ = torch.empty((rb.cap, C), dtype=torch.bfloat16, device=dY.device)
+    dbp = torch.empty((L.NPVS_BWD_DB_PARTS, C), dtype=torch.float32, device=dY.device)
+    L.call("npvs_conv_bwd_begin", _p(dY), _p(Y) if relu else None, C, _p(rb.counts), rb.cap, int(relu), _p(dZ),
+           _p(dbp), _stream())
+    return dZ, dbp
+
+
+def conv_bwd_chain_workspace(cin: int, cout: int, device) -> torch.Tensor:
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_chain_workspace_size", cin, cout, ctypes.byref(nbytes))
+    return torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+
+
+def sparse_conv_bwd_chain(X, Wt, cin: int, cout: int, dZ, dbp, rb: Rulebook, relu_below: bool = True,
+                          want_below: bool = True, dW: torch.Tensor | None = None, db: torch.Tensor | None = None,
+                          ws: torch.Tensor | None = None, wgrad_stream: torch.cuda.Stream | None = None):
+    """One layer of the BF16 backward chain (npvs_sparse_conv_bwd_chain).  Returns (dZ_below, dbp_below,
+    dW, db); dZ_below / dbp_below are None without want_below.  With `wgrad_stream`, dW and db are
+    computed there: the caller keeps X, dZ, dbp and ws alive and joins it before reading them."""
+    if rb.rb_off is None:
+        raise ValueError("the backward needs a rulebook built with csr=True")
+    dev = X.device
+    if ws is None:
+        ws = conv_bwd_chain_workspace(cin, cout, dev)
+        if wgrad_stream is not None:  # freed here, still read by the side stream
+            ws.record_stream(wgrad_stream)
+    dZb = torch.empty((rb.cap, cin), dtype=torch.bfloat16, device=dev) if want_below else None
+    dbpb = torch.empty((L.NPVS_BWD_DB_PARTS, cin), dtype=torch.float32, device=dev) if want_below else None
+    if dW is None:
+        dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
+    if db is None:
+        db = torch.empty(cout, dtype=torch.float32, device=dev)
+    if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
+        raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
+    s = _stream()
+    s2 = ctypes.c_void_p(wgrad_stream.cuda_stream) if wgrad_stream is not None else s
+    L.call("npvs_sparse_conv_bwd_chain", _p(X), cin, _p(Wt), cout, _p(dZ), _p(dbp), _p(rb.nbr), _p(rb.rb_off),
+           _p(rb.rb_pairs), _p(rb.counts), rb.cap, int(relu_below), _p(dZb), _p(dbpb), _p(dW), _p(db), _p(ws),
+           ws.numel(), s, s2)
+    return dZb, dbpb, dW, db
 
 
 # --------------------------------------------------------------------------------- output

@@ -22,6 +22,7 @@ NPVS_MAX_GRIDS = 32
 NPVS_CONV_VARIANTS = 14
 NPVS_DEFAULT_CONV_VARIANT = 12
 NPVS_MAX_PACK = 64
+NPVS_BWD_DB_PARTS = 512
 
 
 class NpvsError(RuntimeError):
@@ -70,6 +71,9 @@ SIGNATURES = {
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
     "npvs_sparse_conv_bwd_split": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P]),
+    "npvs_conv_bwd_begin": (i32, [P, P, i32, P, i32, i32, P, P, P]),
+    "npvs_conv_bwd_chain_workspace_size": (i32, [i32, i32, PS]),
+    "npvs_sparse_conv_bwd_chain": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, P, P, P, P, P, sz, P, P]),
     "npvs_visible_triangles": (i32, [P, PI64, i32, P, P, P, P]),
     "npvs_visible_objects": (i32, [P, P, i64, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),

@@ -28,10 +28,11 @@ struct Comp {  // Neumaier-compensated float sum
 __device__ __forceinline__ float load_as_f32(const float *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float load_as_f32(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
 
-constexpr int kDbBlocks = 256;  // row blocks of the bias-gradient partial sums
+constexpr int kDbBlocks = 256;  // row blocks of the bias-gradient partial sums (one layer)
 
-// dZ in float32 (for wgrad) and, for the BF16 path, a bfloat16 copy (MFMA operand), plus the
-// bias-gradient partial of this block's rows: grid kDbBlocks, 256 threads, C <= 64.  With vec
+// dZ in float32 (for wgrad; nullable) and, for the BF16 path, a bfloat16 copy (MFMA operand),
+// plus the bias-gradient partial of this block's rows: one block per partial row, 256 threads,
+// C <= 64.  With vec
 // (C % 4 == 0 and 16-byte aligned rows) a thread owns 4 adjacent columns, else one; the threads of
 // a row group cover one row, the row groups stride over the block's rows and are combined in LDS
 // in a fixed order.
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
                                                          float *__restrict__ dbpart) {
   __shared__ float red[256 * 4];
   const int64_t n = counts->n_sites;
-  const int64_t r0 = n * blockIdx.x / kDbBlocks, r1 = n * (blockIdx.x + 1) / kDbBlocks;
+  const int64_t r0 = n * blockIdx.x / gridDim.x, r1 = n * (blockIdx.x + 1) / gridDim.x;
   const int V = vec ? 4 : 1, TPR = C / V, RG = 256 / TPR;
   const int cg = threadIdx.x % TPR, rg = threadIdx.x / TPR;
   Comp a[4] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
           o[i] = g[i];
           a[i].add(g[i]);
         }
-        *reinterpret_cast<f32x4_t *>(dZ32 + e) = o;
+        if (dZ32) *reinterpret_cast<f32x4_t *>(dZ32 + e) = o;
         if (dZ16) {
           uint2 h;
           h.x = (uint32_t)f32_to_bf16(g[0]) | ((uint32_t)f32_to_bf16(g[1]) << 16);
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
         const int64_t e = r * C + cg;
         float g = dY[e];
         if (relu && !(load_as_f32(Y, e) > 0.0f)) g = 0.0f;
-        dZ32[e] = g;
+        if (dZ32) dZ32[e] = g;
         if (dZ16) dZ16[e] = f32_to_bf16(g);
         a[0].add(g);
       }
@@ -342,11 +343,12 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
 }
 
 // Blocks [0, nbw) reduce dW over the slices (grid-stride, one entry per thread); each block
-// after them reduces db for 4 channels, one wave per channel: lane l adds partials l, l + 64, ...,
-// then a fixed butterfly adds the 64 lane totals; lane 0 writes.
+// after them reduces db over the nparts partial rows for 4 channels, one wave per channel: lane l
+// adds partials l, l + 64, ..., then a fixed butterfly adds the 64 lane totals; lane 0 writes.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
-                                                           const float *__restrict__ dbpart, int cin, int cout,
-                                                           int nbw, float *__restrict__ dW, float *__restrict__ db) {
+                                                           const float *__restrict__ dbpart, int nparts, int cin,
+                                                           int cout, int nbw, float *__restrict__ dW,
+                                                           float *__restrict__ db) {
   if ((int)blockIdx.x < nbw) {
     const int64_t E = (int64_t)cin * cout;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 27 * E; e += (int64_t)nbw * blockDim.x) {
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
   const int o = ((int)blockIdx.x - nbw) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (o >= cout) return;  // whole waves leave together
   Comp a{0.0f, 0.0f};
-  for (int s = lane; s < kDbBlocks; s += 64) a.add(dbpart[s * cout + o]);
+  for (int s = lane; s < nparts; s += 64) a.add(dbpart[s * cout + o]);
   float t = a.value();
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
@@ -402,15 +404,25 @@ static npvs_status fork_event(hipEvent_t *ev) {
   constexpr int kMaxDevices = 64;
   thread_local hipEvent_t events[kMaxDevices] = {};
   int dev = 0;
-  npvs_status st = check_hip(hipGetDevice(&dev), "npvs_sparse_conv_bwd_split");
+  npvs_status st = check_hip(hipGetDevice(&dev), "backward stream join");
   if (st != NPVS_OK) return st;
-  if (dev < 0 || dev >= kMaxDevices) return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd_split: device index");
+  if (dev < 0 || dev >= kMaxDevices) return fail(NPVS_ERR_UNSUPPORTED, "backward stream join: device index");
   if (!events[dev]) {
-    st = check_hip(hipEventCreateWithFlags(&events[dev], hipEventDisableTiming), "npvs_sparse_conv_bwd_split");
+    st = check_hip(hipEventCreateWithFlags(&events[dev], hipEventDisableTiming), "backward stream join");
     if (st != NPVS_OK) return st;
   }
   *ev = events[dev];
   return NPVS_OK;
+}
+
+// s2 waits for the work enqueued so far on s (no-op when they are the same stream).
+static npvs_status join_after(hipStream_t s, hipStream_t s2) {
+  if (s2 == s) return NPVS_OK;
+  hipEvent_t ev;
+  npvs_status st = fork_event(&ev);
+  if (st == NPVS_OK) st = check_hip(hipEventRecord(ev, s), "backward stream join");
+  if (st == NPVS_OK) st = check_hip(hipStreamWaitEvent(s2, ev, 0), "backward stream join");
+  return st;
 }
 
 // dZ and the bias partials on s; the data gradient on s; the weight gradient and the reductions
@@ -445,13 +457,8 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
                                                           dZ16, dbpart);
   npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
   if (st != NPVS_OK) return st;
-  if (s2 != s) {
-    hipEvent_t ev;
-    st = fork_event(&ev);
-    if (st == NPVS_OK) st = check_hip(hipEventRecord(ev, s), "npvs_sparse_conv_bwd_split");
-    if (st == NPVS_OK) st = check_hip(hipStreamWaitEvent(s2, ev, 0), "npvs_sparse_conv_bwd_split");
-    if (st != NPVS_OK) return st;
-  }
+  st = join_after(s, s2);
+  if (st != NPVS_OK) return st;
   if (dX) {
     st = conv_fwd_dispatch(dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, Wt, nullptr, cin, nbr,
                            counts, cap_sites, dtype, 0, 1, dX, s, kDefaultConvVariant, nullptr, 0);
@@ -465,9 +472,10 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
   else
     wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
   const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbpart, cin, cout, nbw, dW, db);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbpart, kDbBlocks, cin, cout, nbw, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
 }
+
 
 extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
                                            const float *dY, const int32_t *nbr, const int32_t *rb_off,
@@ -486,4 +494,55 @@ extern "C" npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, co
                                                  size_t ws_bytes, void *stream, void *wgrad_stream) {
   return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
                   ws_bytes, as_stream(stream), as_stream(wgrad_stream));
+}
+
+extern "C" npvs_status npvs_conv_bwd_begin(const float *dY, const void *Y, int32_t cout, const npvs_counts *counts,
+                                          int32_t cap_sites, int32_t relu, void *dZ, float *dbp, void *stream) {
+  if (!dY || !counts || !dZ || !dbp || (relu && !Y)) return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_begin: null pointer");
+  if (cout < 1 || cout > 64 || cout % 4 || cap_sites < 1)
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_conv_bwd_begin: needs 4 <= cout <= 64, cout % 4 == 0");
+  if ((reinterpret_cast<uintptr_t>(dY) & 15) || (relu && (reinterpret_cast<uintptr_t>(Y) & 15)))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_begin: dY and Y must be 16-byte aligned");
+  relu_grad_kernel<uint16_t><<<NPVS_BWD_DB_PARTS, 256, 0, as_stream(stream)>>>(
+      (const uint16_t *)Y, dY, counts, cout, relu, 1, nullptr, static_cast<uint16_t *>(dZ), dbp);
+  return check_hip(hipGetLastError(), "npvs_conv_bwd_begin");
+}
+
+// Chain workspace: the float32 slice partials of dW.
+static size_t chain_ws_bytes(int32_t cin, int32_t cout) { return sizeof(float) * 27 * kWgSlices * (size_t)cin * cout; }
+
+extern "C" npvs_status npvs_conv_bwd_chain_workspace_size(int32_t cin, int32_t cout, size_t *bytes) {
+  if (!bytes || cin < 1 || cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_chain_workspace_size: bad arguments");
+  *bytes = chain_ws_bytes(cin, cout);
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, const void *Wt, int32_t cout,
+                                                 const void *dZ, const float *dbp, const int32_t *nbr,
+                                                 const int32_t *rb_off, const int32_t *rb_pairs,
+                                                 const npvs_counts *counts, int32_t cap_sites, int32_t relu_below,
+                                                 void *dZ_below, float *dbp_below, float *dW, float *db, void *ws,
+                                                 size_t ws_bytes, void *stream, void *wgrad_stream) {
+  if (!X || !dZ || !dbp || !nbr || !rb_off || !rb_pairs || !counts || !dW || !db || !ws ||
+      (dZ_below && (!Wt || !dbp_below)))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd_chain: null pointer");
+  if (cap_sites < 1 || cin < 8 || cout < 8 || cin > 64 || cout > 64 || cin % 8 || cout % 8)
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd_chain: needs cin, cout in [8, 64], multiples of 8");
+  if (ws_bytes < chain_ws_bytes(cin, cout))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd_chain: workspace too small");
+  const hipStream_t s = as_stream(stream), s2 = as_stream(wgrad_stream);
+  // the side stream joins before the data gradient is enqueued: it waits for dZ only
+  npvs_status st = join_after(s, s2);
+  if (st != NPVS_OK) return st;
+  if (dZ_below) {
+    st = dgrad_relu_fused((const uint16_t *)dZ, cout, Wt, cin, nbr, counts, cap_sites,
+                          relu_below ? (const uint16_t *)X : nullptr, static_cast<uint16_t *>(dZ_below), dbp_below, s);
+    if (st != NPVS_OK) return st;
+  }
+  float *wpart = static_cast<float *>(ws);
+  wgrad_bf16_kernel<<<dim3(kWgSlices, 27), 256, 0, s2>>>((const uint16_t *)X, cin, (const uint16_t *)dZ, cout,
+                                                         rb_off, rb_pairs, wpart);
+  const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbp, NPVS_BWD_DB_PARTS, cin, cout, nbw, dW, db);
+  return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd_chain");
 }

@@ -443,14 +443,23 @@ __global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__
 // neighbour indices of the tile after it are loaded during the current tile's products.  The 9
 // partial sums are added in LDS in wave order.
 // ------------------------------------------------------------------------------------------
-template <int KB, int MB>
+// With FUSE (the data gradient of a layer, feeding the backward of the layer below): the result
+// is masked by M > 0 (ReLU' of the layer below, whose output M is; no mask when M is null),
+// rounded to bf16 into Y, and each epilogue wave keeps per-lane running sums of its masked values
+// over all the tiles its workgroup walks.  At the end a fixed butterfly adds the 16 rows of each
+// column and the workgroup writes its row of dbp[NPVS_BWD_DB_PARTS][cout] (rows past the grid are
+// written as zeros), so the bias gradient of the layer below is a fixed-order sum over that table.
+template <int KB, int MB, bool FUSE = false>
 __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
                                                                   const bf16x8_t *__restrict__ Wp,
                                                                   const float *__restrict__ bias, int cout,
                                                                   const int32_t *__restrict__ nbr,
                                                                   const npvs_counts *__restrict__ counts, int cap,
-                                                                  int relu, int out_f32, void *__restrict__ Y) {
+                                                                  int relu, int out_f32, void *__restrict__ Y,
+                                                                  const uint16_t *__restrict__ M = nullptr,
+                                                                  float *__restrict__ dbp = nullptr) {
   constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBW = 2, NBLK = MB * NBW;
+  static_assert(!FUSE || MB == 1, "the fused data gradient keeps one column block per epilogue wave");
   __shared__ f32x4_t red[KSPLIT * NBLK * 64];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
@@ -468,8 +477,24 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         const int g = nb0 + nb < NBT ? nb0 + nb : NBT - 1;  // blocks past cout: any valid fragment
         aw[q][kb][nb] = Wp[(((int64_t)(kbeg + q) * NBT + g) * KB + kb) * 64 + lane];
       }
+  float da[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // FUSE: this lane's running column sums
+  auto write_db_parts = [&]() {
+    if (wv >= NBLK) return;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) da[i] += __shfl_xor(da[i], off, 64);
+    const int o = (nb0 + wv) * 16 + 4 * (lane >> 4);
+    if ((lane & 15) == 0 && o < cout)
+      for (int row = blockIdx.x; row < NPVS_BWD_DB_PARTS; row += gridDim.x)
+        *reinterpret_cast<f32x4_t *>(dbp + (int64_t)row * cout + o) =
+            row == (int)blockIdx.x ? f32x4_t{da[0], da[1], da[2], da[3]} : f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  };
   int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
-  if (tile < 0) return;  // whole workgroup: tile depends on blockIdx only
+  if (tile < 0) {  // whole workgroup: tile depends on blockIdx only
+    if constexpr (FUSE) write_db_parts();
+    return;
+  }
   // indices of a tile (clamped: a missing tile re-reads the last valid one)
   auto indices = [&](int t, int (&ix)[KPER][MB]) {
 #pragma unroll
@@ -493,6 +518,12 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   indices(t1 >= 0 ? t1 : tile, ix);
   for (int j = 0; tile >= 0; ++j) {
     const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
+    // FUSE: the epilogue waves fetch this tile's mask now, so its latency hides under the products
+    uint2 mk = {0u, 0u};
+    if constexpr (FUSE) {
+      const int r = tile * ROWS + (lane & 15), o = (nb0 + wv) * 16 + 4 * (lane >> 4);
+      if (M && wv < NBLK && r < n && o < cout) mk = *reinterpret_cast<const uint2 *>(M + (int64_t)r * cout + o);
+    }
     bf16x8_t bn[KPER][KB][MB];
     rows(ix, bn);                                        // tile j + 1 (or a repeat)
     indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
@@ -521,8 +552,25 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
       f32x4_t sum = red[blk * 64 + lane];
       for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
       const int mb = blk / NBW, nb = blk % NBW;
-      conv_bf16_epilogue<4>(sum, row0 + mb * 16 + (lane & 15), n, (nb0 + nb) * 16 + 4 * (lane >> 4), cout, bias,
-                            relu, out_f32, Y);
+      const int r = row0 + mb * 16 + (lane & 15), o = (nb0 + nb) * 16 + 4 * (lane >> 4);
+      if constexpr (FUSE) {
+        if (r < n && o < cout) {
+          float g[4] = {sum[0], sum[1], sum[2], sum[3]};
+          if (M) {
+            const uint16_t mv[4] = {(uint16_t)mk.x, (uint16_t)(mk.x >> 16), (uint16_t)mk.y, (uint16_t)(mk.y >> 16)};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g[i] = bf16_to_f32(mv[i]) > 0.0f ? g[i] : 0.0f;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) da[i] += g[i];
+          uint2 h;
+          h.x = (uint32_t)f32_to_bf16(g[0]) | ((uint32_t)f32_to_bf16(g[1]) << 16);
+          h.y = (uint32_t)f32_to_bf16(g[2]) | ((uint32_t)f32_to_bf16(g[3]) << 16);
+          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = h;
+        }
+      } else {
+        conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
+      }
     }
 #pragma unroll
     for (int q = 0; q < KPER; ++q)
@@ -533,6 +581,7 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
     tile = t1;
     t1 = t2;
   }
+  if constexpr (FUSE) write_db_parts();
 }
 
 template <int KB, int NB, int MB, int RG>
@@ -671,6 +720,29 @@ static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float
   G = (G + 7) & ~7;
   conv_fwd_bf16_wsta_kernel<KB, MB><<<dim3(G, groups), 576, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+// The data gradient of a BF16 layer with the ReLU' mask of the layer below fused in (see the
+// weight-stationary kernel): dZ_below[r][o] = bf16(conv(dZ, Wt)[r][o] if M[r][o] > 0 else 0) for
+// r < n_sites, and the bias partial table dbp.  Requires cin (of the data gradient) <= 64 and
+// cout % 4 == 0.
+npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int cout, const int32_t *nbr,
+                             const npvs_counts *counts, int cap, const uint16_t *M, uint16_t *dZ_below, float *dbp,
+                             hipStream_t s) {
+  if (cin > 64 || cout % 4) return fail(NPVS_ERR_UNSUPPORTED, "dgrad with fused ReLU': unsupported channel counts");
+  const int groups = (cout + 31) / 32;
+  int G = (cin <= 32 ? 512 : 256) / groups;
+  G = G < 8 ? 8 : G;
+  const int most = stride_grid(cap, 16, 4096);
+  G = G > most ? most : G;
+  G = (G + 7) & ~7;
+  if (cin <= 32)
+    conv_fwd_bf16_wsta_kernel<1, 1, true><<<dim3(G, groups), 576, 0, s>>>(
+        dZ, cin, (const bf16x8_t *)Wt, nullptr, cout, nbr, counts, cap, 0, 0, dZ_below, M, dbp);
+  else
+    conv_fwd_bf16_wsta_kernel<2, 1, true><<<dim3(G, groups), 576, 0, s>>>(
+        dZ, cin, (const bf16x8_t *)Wt, nullptr, cout, nbr, counts, cap, 0, 0, dZ_below, M, dbp);
+  return check_hip(hipGetLastError(), "dgrad with fused ReLU'");
 }
 
 template <int MB>

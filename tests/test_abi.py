@@ -35,7 +35,8 @@ def test_version_and_sizes(lib):
 
 def test_header_constants_match_binding():
     text = open(L.HEADER).read()
-    for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT"):
+    for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT",
+                 "NPVS_BWD_DB_PARTS"):
         assert f"#define {name} {getattr(L, name)}" in text, name
     assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16
     assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes
@@ -60,6 +61,28 @@ def test_batched_packing_argument_checks(lib):
     d = (L.PackDesc * 1)(L.PackDesc(None, None, 8, 8, 0, 0))
     assert lib.npvs_pack_weights_batch(1, ctypes.cast(d, ctypes.c_void_p), L.NPVS_BF16, None) == L.NPVS_ERR_INVALID_ARG
     assert b"null pointer" in lib.npvs_last_error()
+
+
+def test_backward_chain_argument_checks(lib):
+    n = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_chain_workspace_size", 32, 64, ctypes.byref(n))
+    assert n.value == 27 * 16 * 32 * 64 * 4  # float32 weight-gradient slices of every offset
+    fake = ctypes.c_void_p(256)  # never dereferenced: the argument checks answer first
+    args = [fake, 32, fake, 64, fake, fake, fake, fake, fake, fake, 1000, 1, fake, fake, fake, fake, fake, n.value,
+            None, None]
+    bad = list(args)
+    bad[1] = 96  # cin > 64
+    assert lib.npvs_sparse_conv_bwd_chain(*bad) == L.NPVS_ERR_UNSUPPORTED
+    bad = list(args)
+    bad[17] = n.value - 1
+    assert lib.npvs_sparse_conv_bwd_chain(*bad) == L.NPVS_ERR_INVALID_ARG and b"workspace" in lib.npvs_last_error()
+    bad = list(args)
+    bad[13] = None  # dZ_below given without dbp_below
+    assert lib.npvs_sparse_conv_bwd_chain(*bad) == L.NPVS_ERR_INVALID_ARG
+    assert lib.npvs_conv_bwd_begin(fake, None, 64, fake, 1000, 1, fake, fake, None) == L.NPVS_ERR_INVALID_ARG
+    assert lib.npvs_conv_bwd_begin(fake, fake, 66, fake, 1000, 0, fake, fake, None) == L.NPVS_ERR_UNSUPPORTED
+    assert lib.npvs_conv_bwd_begin(ctypes.c_void_p(260), None, 64, fake, 1000, 0, fake, fake, None) == \
+        L.NPVS_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("dims,d,msg", [

@@ -399,3 +399,39 @@ def test_plan_forward_matches_staged_calls_and_graph_replays():
                 np.testing.assert_array_equal(to_np(gl), to_np(logits))
                 _ = _net_fwd_gpu(occ, rb, layers[:1], dtype)  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_maximum_grid_extent_bit_exact():
+    """Grids 1024 froxels long (the largest extent) with triangles spanning the whole x range:
+    froxelize, the rulebook at d = 8 and culling against a random PVS, bit for bit."""
+    rng = np.random.default_rng(77)
+    dims = [(1024, 16, 8), (8, 1024, 8)]
+    tri_list = []
+    for g in dims:
+        hi = np.array(g, np.float64)
+        t = []
+        for i in range(120):
+            if i % 2 == 0:  # long slivers across the long axis
+                a = rng.uniform(0, hi, size=3)
+                b = rng.uniform(0, hi, size=3)
+                ax = int(np.argmax(hi))
+                a[ax], b[ax] = rng.uniform(0, 4), rng.uniform(hi[ax] - 4, hi[ax])
+                t.append(np.stack([a, b, b + rng.uniform(-0.5, 0.5, 3)]))
+            else:
+                t.append(rng.uniform(-1, hi + 1, size=(3, 3)))
+        tri_list.append(np.asarray(t, np.float32))
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    want = [oracle.froxelize(t, g)[0] for t, g in zip(tri_list, dims)]
+    np.testing.assert_array_equal(to_np(occ), np.concatenate([w.reshape(-1) for w in want]))
+    rb = npvs.build_rulebook(occ, dims, 8, csr=True)
+    ref = oracle_batch(tri_list, dims, 8)
+    n = ref["n"]
+    assert rb.host_counts()["n_sites"] == n
+    np.testing.assert_array_equal(to_np(rb.site_keys)[:n], ref["keys"])
+    np.testing.assert_array_equal(to_np(rb.rb_pairs)[:len(ref["pairs"])], ref["pairs"])
+    pvs = [np.packbits((rng.random((g[2], g[1], g[0] // 8, 8)) < 0.01).astype(np.uint8), axis=-1,
+                       bitorder="little").reshape(g[2], g[1], g[0] // 8) for g in dims]
+    vis = npvs.visible_triangles(tris, counts, dims, torch.from_numpy(np.concatenate([p.reshape(-1) for p in pvs])).to(DEV))
+    np.testing.assert_array_equal(to_np(vis), np.concatenate([oracle.visible_triangles(t, g, p)
+                                                              for t, g, p in zip(tri_list, dims, pvs)]))
