@@ -172,12 +172,13 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
 //   A (16 x 32): lane l gives XT[mb*16 + l%16][kk + 8(l/16) + j]
 //   B (32 x 16): lane l gives GT[nb*16 + l%16][kk + 8(l/16) + j]
 //   D: lane l holds dW[mb*16 + 4(l/16) + i][nb*16 + l%16]
-// A staging task is 4 consecutive pairs x 8 channels of X or dZ (at most 2 per thread).  The pair
+// A staging task is 4 consecutive pairs x 8 channels of X or dZ (at most 2 per thread; the 8
+// tasks of one pair quad sit in adjacent lanes).  The pair
 // indices are fetched two chunks ahead and the rows of the next chunk are loaded while the
 // current chunk's products run, then stored into the other LDS buffer.  Each chunk's product
 // starts from zero and is added into a compensated total.
 constexpr int kWgChunk = 128;
-constexpr int kWgPitch = kWgChunk + 8;  // bf16 elements per LDS row (padding spreads banks)
+constexpr int kWgPitch = kWgChunk + 16;  // bf16 elements per LDS row (padding spreads banks)
 constexpr int kWgQuads = kWgChunk / 4;
 
 struct WgTask {
@@ -245,15 +246,17 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
   const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
   const int CB = (cin + 15) / 16, OB = (cout + 15) / 16, nblk = CB * OB;
   const int cin8 = (cin + 7) / 8, cout8 = (cout + 7) / 8;
+  // tasks of X first, then of dZ; the channel group runs fastest, so the lanes of one load
+  // instruction cover whole 128-byte rows (8 lanes per row) instead of 16 bytes of 64 rows
   WgTask task[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const int t = tid + 256 * u;
-    int cc = t / kWgQuads;
-    task[u].pq = t % kWgQuads;
-    task[u].valid = cc < cin8 + cout8;
-    task[u].isx = cc < cin8;
-    task[u].cc = task[u].isx ? cc : cc - cin8;
+    const int t = tid + 256 * u, nx = cin8 * kWgQuads;
+    task[u].isx = t < nx;
+    const int tt = task[u].isx ? t : t - nx, c8 = task[u].isx ? cin8 : cout8;
+    task[u].cc = tt % c8;
+    task[u].pq = tt / c8;
+    task[u].valid = t < (cin8 + cout8) * kWgQuads;
   }
   // channel rows past cin / cout (up to the 16-row MFMA block) stay zero; the others are written
   // by every chunk
