@@ -2,8 +2,9 @@
 
 Plain, slow, obviously correct FP64 / exact-integer reference for every step of the forward
 path (froxelize, active sites, interleave, rulebook, submanifold convolution, de-interleave and
-threshold), the training loss and its gradient, the convolution backward, Adam and the ray-march
-labeller.  Each C function cites the passage of the paper it follows.  It shares no code with
+threshold), the training loss and its gradient, the convolution backward, Adam, the ray-march
+labeller, culling against the PVS, and the two-level U-Net (level relation, strided and inverse
+convolutions, the whole encoder/decoder forward).  Each C function cites the passage of the paper it follows.  It shares no code with
 the HIP library and must only be used by the tests, the smoke check and the benchmark's
 CPU-baseline leg.
 
@@ -304,3 +305,92 @@ def backward(out, layers, dlogits_rows):
 def site_labels(label_bits, dims, d, keys) -> np.ndarray:
     """Labels of the froxels of the active blocks, in the interleaved [n][d^3] row layout."""
     return gather_sites(label_bits, dims, d, keys).astype(np.uint8)
+
+
+# ---------------------------------------------------------------- two-level sparse U-Net
+# The backbone of Sec. 3.3 is an encoder/decoder (Suppl. A.2: embedding 64 channels, encoder
+# channels 64, down ratio 2, decoder channels 96, encoder depths 2 and 3, decoder depth 2).  Its
+# coarse level holds the blocks of the grid at interleave factor 2d, i.e. the 2x2x2 groups of
+# level-0 blocks; a coarse block is active iff one of its eight children is.
+def level_maps(keys0, keys1, bdims0):
+    """Child / parent relation between the active blocks of level 0 (block grid bdims0 =
+    (Bx, By, Bz)) and of level 1 (the grid halved along each axis).  Child index
+    k = ((bz & 1) * 2 + (by & 1)) * 2 + (bx & 1).  Returns children int32 [8][n1] (level-0 row
+    or -1), parent int32 [n0] (level-1 row) and kid int32 [n0] (child index)."""
+    Bx, By, Bz = bdims0
+    Cx, Cy = Bx // 2, By // 2
+    row1 = {int(key): r for r, key in enumerate(keys1)}
+    children = np.full((8, len(keys1)), -1, np.int32)
+    parent = np.zeros(len(keys0), np.int32)
+    kid = np.zeros(len(keys0), np.int32)
+    for f, key in enumerate(keys0):
+        key = int(key)
+        bx, by, bz = key % Bx, (key // Bx) % By, key // (Bx * By)
+        c = row1[((bz >> 1) * Cy + (by >> 1)) * Cx + (bx >> 1)]
+        k = ((bz & 1) * 2 + (by & 1)) * 2 + (bx & 1)
+        children[k, c] = f
+        parent[f] = c
+        kid[f] = k
+    return children, parent, kid
+
+
+def strided_down(X0, children, W, b, relu: bool) -> np.ndarray:
+    """Sparse convolution with kernel 2 and stride 2 (down ratio 2): coarse row c gets
+    b + sum_k X0[child k of c] W[k] over its active children; W [8][cin][cout]."""
+    X0 = np.asarray(X0, np.float64)
+    W = np.asarray(W, np.float64)
+    Y = np.zeros((children.shape[1], W.shape[2])) + np.asarray(b, np.float64)
+    for k in range(8):
+        has = children[k] >= 0
+        Y[has] += X0[children[k, has]] @ W[k]
+    return np.maximum(Y, 0.0) if relu else Y
+
+
+def inverse_up(X1, parent, kid, W, b, relu: bool) -> np.ndarray:
+    """The inverse (transposed) convolution of strided_down on the same blocks: level-0 row f
+    gets b + X1[parent f] W[kid f]; W [8][cin][cout]."""
+    X1 = np.asarray(X1, np.float64)
+    W = np.asarray(W, np.float64)
+    Y = np.zeros((len(parent), W.shape[2])) + np.asarray(b, np.float64)
+    for k in range(8):
+        sel = kid == k
+        Y[sel] += X1[parent[sel]] @ W[k]
+    return np.maximum(Y, 0.0) if relu else Y
+
+
+def unet_forward(tris, dims, d, params, want_logits: bool = True, occ=None):
+    """Whole path with the two-level U-Net in place of the plain stack, FP64.  params: dict of
+    lists of (W, b): stem [1] (d^3 -> E), enc0, down [1] (W [8][E][E]), enc1, up [1]
+    (W [8][E][D]), dec0 (first one takes D + E channels: the up output, then the level-0 skip),
+    head [1] (-> d^3, no ReLU).  ReLU after every other layer."""
+    nx, ny, nz = dims
+    if occ is None:
+        occ, _ = froxelize(tris, dims)
+    b0 = (nx // d, ny // d, nz // d)
+    keys0 = active_sites(occ, dims, d)
+    keys1 = active_sites(occ, dims, 2 * d)
+    rb0 = rulebook(keys0, b0)
+    rb1 = rulebook(keys1, (b0[0] // 2, b0[1] // 2, b0[2] // 2))
+    children, parent, kid = level_maps(keys0, keys1, b0)
+    acts = {"X": gather_sites(occ, dims, d, keys0)}
+    h = acts["X"]
+    for W, b in params["stem"] + params["enc0"]:
+        h = subm_conv(h, W, b, *rb0, relu=True)
+    acts["skip"] = h
+    (W, b), = params["down"]
+    h1 = strided_down(h, children, W, b, relu=True)
+    for W, b in params["enc1"]:
+        h1 = subm_conv(h1, W, b, *rb1, relu=True)
+    acts["coarse"] = h1
+    (W, b), = params["up"]
+    u = inverse_up(h1, parent, kid, W, b, relu=True)
+    acts["up"] = u
+    h = np.concatenate([u, acts["skip"]], axis=1)
+    for W, b in params["dec0"]:
+        h = subm_conv(h, W, b, *rb0, relu=True)
+    (W, b), = params["head"]
+    Y = subm_conv(h, W, b, *rb0, relu=False)
+    acts["Y"] = Y
+    logits, pvs = deinterleave_threshold(Y, keys0, occ, dims, d, want_logits)
+    return dict(occ=occ, keys0=keys0, keys1=keys1, children=children, parent=parent, kid=kid, acts=acts,
+                logits=logits, pvs=pvs)
