@@ -258,6 +258,44 @@ npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, const void *W
                                        void *ws, size_t ws_bytes, void *stream, void *wgrad_stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Two-level sparse U-Net pieces (Sec. 3.3 adopts an encoder/decoder backbone; the supplement's
+ * network settings give a down ratio of 2 and 64 / 96 channels).  Level 0 is the rulebook of
+ * interleave factor d, level 1 that of factor 2d (npvs_build_rulebook with 2d): its blocks are
+ * the 2x2x2 groups of level-0 blocks that contain an active one.
+ *
+ * npvs_level_maps: children (device) int32 [8][cap1]: children[k][c] = level-0 row of child k
+ *   = ((bz&1)*2 + (by&1))*2 + (bx&1) of level-1 row c, or -1; parent (device) int32 [cap0]:
+ *   8 * (level-1 row) + k for level-0 row f.  Entries past the counts are -1.  The level-0 and
+ *   level-1 site_keys / block_row / counts are those written by npvs_build_rulebook at d and 2d
+ *   for the same grids (extents multiples of 2d, d <= 16).
+ * npvs_packed_weight_bytes_k / npvs_pack_weights_k: float32 [K][cin][cout] weights of K offsets
+ *   packed like npvs_pack_weights (no flip); the strided layers use K = 8.
+ * npvs_strided_conv_fwd: up = 0, the convolution with kernel 2 and stride 2 (level 0 -> 1):
+ *     Y[c] = act(b + sum_k X[children[k][c]] W_k), map = children, counts_out / cap_out of level 1;
+ *   up = 1, its transposed convolution on the same blocks (level 1 -> 0):
+ *     Y[f] = act(b + X[parent[f] / 8] W_{parent[f] % 8}), map = parent, counts_out / cap_out of
+ *     level 0.
+ *   X [cap_in][cin] and Y [cap_out][cout] in `dtype` (with BF16, Y is float32 when out_f32;
+ *   cin, cout multiples of 8); Wp from npvs_pack_weights_k(K = 8); bias nullable; rows past the
+ *   output count untouched.
+ * npvs_concat_channels: Y[r] = [A[r] | B[r]] for r < n_sites, A [cap][ca], B [cap][cb],
+ *   Y [cap][ca + cb], elements of elem_bytes (2 or 4) bytes, rows of A and B multiples of 16
+ *   bytes; rows past n_sites untouched.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_level_maps(int32_t n_grids, const npvs_dims *dims, int32_t d, const npvs_counts *counts0,
+                            const int32_t *site_keys0, const int32_t *block_row0, int32_t cap0,
+                            const npvs_counts *counts1, const int32_t *site_keys1, const int32_t *block_row1,
+                            int32_t cap1, int32_t *children, int32_t *parent, void *stream);
+size_t npvs_packed_weight_bytes_k(int32_t K, int32_t cin, int32_t cout, int32_t dtype);
+npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t dtype, void *Wp,
+                                void *stream);
+npvs_status npvs_strided_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
+                                  const int32_t *map, int32_t up, const npvs_counts *counts_out, int32_t cap_out,
+                                  int32_t dtype, int32_t relu, int32_t out_f32, void *Y, void *stream);
+npvs_status npvs_concat_channels(const void *A, int32_t ca, const void *B, int32_t cb, int32_t elem_bytes,
+                                 const npvs_counts *counts, int32_t cap, void *Y, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * De-interleave and threshold (Sec. 3.1 V = 1[f(G) >= tau] with tau = 0.5, read as logit >= 0;
  * Sec. 3.3 g_d^-1; Sec. 3.2 the visible set lies inside the occupied set, so V is masked by G):
  *   V(x) = [L(x) >= 0] and G(x),  L(x) = Y[row(block(x))][c(x)], -inf for inactive blocks.

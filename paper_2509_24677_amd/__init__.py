@@ -21,7 +21,8 @@ from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  #
 
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
-    "sparse_conv_fwd", "sparse_conv_bwd", "conv_bwd_begin", "sparse_conv_bwd_chain", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
+    "sparse_conv_fwd", "sparse_conv_bwd", "conv_bwd_begin", "sparse_conv_bwd_chain", "Levels", "build_levels",
+    "pack_weights_k", "strided_conv_fwd", "concat_channels", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
     "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
 ]
 
@@ -284,6 +285,65 @@ def sparse_conv_bwd_chain(X, Wt, cin: int, cout: int, dZ, dbp, rb: Rulebook, rel
            _p(rb.rb_pairs), _p(rb.counts), rb.cap, int(relu_below), _p(dZb), _p(dbpb), _p(dW), _p(db), _p(ws),
            ws.numel(), s, s2)
     return dZb, dbpb, dW, db
+
+
+# --------------------------------------------------------------------------------- U-Net levels
+@dataclass
+class Levels:
+    """Two levels of a sparse U-Net: rb0 at interleave factor d, rb1 at 2d, and the maps between
+    them (children int32 [8][rb1.cap], parent int32 [rb0.cap] = 8 * level-1 row + child index)."""
+    rb0: Rulebook
+    rb1: Rulebook
+    children: torch.Tensor
+    parent: torch.Tensor
+
+
+def build_levels(occ: torch.Tensor, dims, d: int, csr: bool = False) -> Levels:
+    dims = [tuple(g) for g in dims]
+    rb0 = build_rulebook(occ, dims, d, csr=csr)
+    rb1 = build_rulebook(occ, dims, 2 * d, csr=csr)
+    dev = occ.device
+    children = torch.empty((8, rb1.cap), dtype=torch.int32, device=dev)
+    parent = torch.empty(rb0.cap, dtype=torch.int32, device=dev)
+    L.call("npvs_level_maps", len(dims), L.dims_array(dims), d, _p(rb0.counts), _p(rb0.site_keys), _p(rb0.block_row),
+           rb0.cap, _p(rb1.counts), _p(rb1.site_keys), _p(rb1.block_row), rb1.cap, _p(children), _p(parent),
+           _stream())
+    return Levels(rb0, rb1, children, parent)
+
+
+def pack_weights_k(W: torch.Tensor, dtype: int) -> torch.Tensor:
+    """Kernel layout of float32 weights [K][cin][cout] of K offsets (uint8 byte tensor)."""
+    W = W.contiguous()
+    if W.dtype != torch.float32 or W.dim() != 3:
+        raise ValueError("W must be float32 [K][cin][cout]")
+    K, cin, cout = W.shape
+    nbytes = L.get().npvs_packed_weight_bytes_k(K, cin, cout, dtype)
+    Wp = torch.empty(nbytes, dtype=torch.uint8, device=W.device)
+    L.call("npvs_pack_weights_k", _p(W), K, cin, cout, dtype, _p(Wp), _stream())
+    return Wp
+
+
+def strided_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None, cin: int, cout: int, lv: Levels,
+                     up: bool, dtype: int, relu: bool = True, out_f32: bool = False,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """Kernel-2 stride-2 convolution level 0 -> 1 (up=False) or its inverse level 1 -> 0 (up=True);
+    Wp from pack_weights_k of a [8][cin][cout] weight."""
+    rb = lv.rb0 if up else lv.rb1
+    tdt = torch.float32 if (dtype == NPVS_F32 or out_f32) else _TORCH_DT[dtype]
+    Y = torch.empty((rb.cap, cout), dtype=tdt, device=X.device) if out is None else out
+    L.call("npvs_strided_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(lv.parent if up else lv.children),
+           int(up), _p(rb.counts), rb.cap, dtype, int(relu), int(out_f32), _p(Y), _stream())
+    return Y
+
+
+def concat_channels(A: torch.Tensor, B: torch.Tensor, rb: Rulebook) -> torch.Tensor:
+    """[A | B] row by row over the active sites (rows past the count left uninitialized)."""
+    if A.dtype != B.dtype or A.shape[0] != B.shape[0]:
+        raise ValueError("A and B must have the same dtype and row count")
+    Y = torch.empty((A.shape[0], A.shape[1] + B.shape[1]), dtype=A.dtype, device=A.device)
+    L.call("npvs_concat_channels", _p(A.contiguous()), A.shape[1], _p(B.contiguous()), B.shape[1], A.element_size(),
+           _p(rb.counts), rb.cap, _p(Y), _stream())
+    return Y
 
 
 # --------------------------------------------------------------------------------- output

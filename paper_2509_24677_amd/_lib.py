@@ -74,6 +74,11 @@ SIGNATURES = {
     "npvs_conv_bwd_begin": (i32, [P, P, i32, P, i32, i32, P, P, P]),
     "npvs_conv_bwd_chain_workspace_size": (i32, [i32, i32, PS]),
     "npvs_sparse_conv_bwd_chain": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, P, P, P, P, P, sz, P, P]),
+    "npvs_level_maps": (i32, [i32, P, i32, P, P, P, i32, P, P, P, i32, P, P, P]),
+    "npvs_packed_weight_bytes_k": (sz, [i32, i32, i32, i32]),
+    "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, P, P]),
+    "npvs_strided_conv_fwd": (i32, [P, i32, P, P, i32, P, i32, P, i32, i32, i32, i32, P, P]),
+    "npvs_concat_channels": (i32, [P, i32, P, i32, i32, P, i32, P, P]),
     "npvs_visible_triangles": (i32, [P, PI64, i32, P, P, P, P]),
     "npvs_visible_objects": (i32, [P, P, i64, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),

@@ -6,5 +6,5 @@ so the oracle and the HIP path can both consume its output without sharing code.
 """
 from .scenes import (  # noqa: F401
     box_scene, city_scene, he_weights, label_mask_bits, viewpoints, CONFIGS, config,
-    net_layers, scene_for,
+    net_layers, scene_for, unet_params,
 )

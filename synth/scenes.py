@@ -155,6 +155,22 @@ def he_weights(seed: int, channels, bias_std: float = 0.0):
     return out
 
 
+def unet_params(seed: int, d: int, E: int = 64, Dc: int = 96, bias_std: float = 0.05) -> dict:
+    """He-normal weights of the two-level U-Net, stage by stage: stem [27][d^3][E], enc0 2 x
+    [27][E][E], down [8][E][E], enc1 3 x [27][E][E], up [8][E][Dc], dec0 [27][Dc+E][Dc] and
+    [27][Dc][Dc], head [27][Dc][d^3]; biases N(0, bias_std)."""
+    rng = _rng(seed)
+
+    def conv(k, cin, cout):
+        w = rng.normal(0.0, math.sqrt(2.0 / (k * cin)), size=(k, cin, cout)).astype(np.float32)
+        return w, rng.normal(0.0, bias_std, size=cout).astype(np.float32)
+
+    C = d ** 3
+    return dict(stem=[conv(27, C, E)], enc0=[conv(27, E, E) for _ in range(2)], down=[conv(8, E, E)],
+                enc1=[conv(27, E, E) for _ in range(3)], up=[conv(8, E, Dc)],
+                dec0=[conv(27, Dc + E, Dc), conv(27, Dc, Dc)], head=[conv(27, Dc, C)])
+
+
 def label_mask_bits(seed: int, shape_bytes, p: float = 0.35) -> np.ndarray:
     """Random packed bit mask (uint8, same shape as a packed froxel grid) with each bit set with
     probability p.  ANDed with an occupancy grid it gives a fixed label subset of G, used where

@@ -1,0 +1,139 @@
+"""GPU parity of the two-level U-Net pieces (level maps, strided and inverse convolutions, the
+whole encoder/decoder forward) against the oracle, through the C ABI."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_24677_amd as npvs
+import synth
+from gpu_util import DEV, bf16_round, to_np, upload_tris
+from paper_2509_24677_amd.unet import UNet, unet_pvs
+
+pytestmark = pytest.mark.gpu
+
+
+def _grids(dims, seeds):
+    tri_list = [synth.box_scene(s, g, 20, 2, 8) for s, g in zip(seeds, dims)]
+    tris, counts = upload_tris(tri_list)
+    return tri_list, npvs.froxelize(tris, counts, dims)
+
+
+def _oracle_levels(tri_list, dims, d):
+    """Per-grid oracle level maps in the batch's row numbering: children [8][n1], parent [n0]
+    (8 * level-1 row + child index), n0, n1."""
+    ch, par, n0, n1 = [], [], 0, 0
+    for t, g in zip(tri_list, dims):
+        occ, _ = oracle.froxelize(t, g)
+        k0, k1 = oracle.active_sites(occ, g, d), oracle.active_sites(occ, g, 2 * d)
+        c, p, kid = oracle.level_maps(k0, k1, (g[0] // d, g[1] // d, g[2] // d))
+        ch.append(np.where(c >= 0, c + n0, -1))
+        par.append((p + n1) * 8 + kid)
+        n0 += len(k0)
+        n1 += len(k1)
+    return np.concatenate(ch, axis=1), np.concatenate(par), n0, n1
+
+
+@pytest.mark.parametrize("d", [2, 4])
+def test_level_maps_bit_exact(d):
+    dims = [(64, 32, 32), (32, 32, 16), (128, 64, 32)]
+    tri_list, occ = _grids(dims, [5, 6, 7])
+    lv = npvs.build_levels(occ, dims, d)
+    ch, par, n0, n1 = _oracle_levels(tri_list, dims, d)
+    assert lv.rb0.host_counts()["n_sites"] == n0 and lv.rb1.host_counts()["n_sites"] == n1
+    assert 0 < n1 < n0
+    got_c, got_p = to_np(lv.children), to_np(lv.parent)
+    np.testing.assert_array_equal(got_c[:, :n1], ch)
+    assert (got_c[:, n1:] == -1).all()
+    np.testing.assert_array_equal(got_p[:n0], par)
+    assert (got_p[n0:] == -1).all()
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+@pytest.mark.parametrize("up", [False, True])
+@pytest.mark.parametrize("cin,cout", [(64, 64), (64, 96), (8, 24), (160, 16)])
+def test_strided_conv_matches_oracle(dtype, up, cin, cout):
+    dims, d = [(64, 32, 32), (32, 32, 16)], 4
+    tri_list, occ = _grids(dims, [3, 4])
+    lv = npvs.build_levels(occ, dims, d)
+    ch, par, n0, n1 = _oracle_levels(tri_list, dims, d)
+    rng = np.random.default_rng(cin * 1000 + cout + 7 * up)
+    cap_in = lv.rb1.cap if up else lv.rb0.cap
+    X = rng.normal(size=(cap_in, cin)).astype(np.float32)
+    W = (rng.normal(size=(8, cin, cout)) / np.sqrt(8 * cin)).astype(np.float32)
+    b = rng.normal(0, 0.1, size=cout).astype(np.float32)
+    Xt = torch.from_numpy(X).to(DEV)
+    if dtype == npvs.NPVS_BF16:
+        Xt, Xr, Wr = Xt.to(torch.bfloat16), bf16_round(X), bf16_round(W)
+    else:
+        Xr, Wr = X.astype(np.float64), W.astype(np.float64)
+    Wp = npvs.pack_weights_k(torch.from_numpy(W).to(DEV), dtype)
+    bt = torch.from_numpy(b).to(DEV)
+    Y = npvs.strided_conv_fwd(Xt, Wp, bt, cin, cout, lv, up, dtype, relu=True, out_f32=True)
+    if up:
+        want = oracle.inverse_up(Xr[:n1], par // 8, par % 8, Wr, b, True)
+        mag = oracle.inverse_up(np.abs(Xr[:n1]), par // 8, par % 8, np.abs(Wr), np.zeros(cout), False)
+        n_out = n0
+    else:
+        want = oracle.strided_down(Xr[:n0], ch, Wr, b, True)
+        mag = oracle.strided_down(np.abs(Xr[:n0]), ch, np.abs(Wr), np.zeros(cout), False)
+        n_out = n1
+    tol = 2 * 8 * cin * 2.0 ** -24 * (mag + np.abs(b)) + 1e-30  # float32 accumulation bound
+    err = np.abs(to_np(Y)[:n_out] - want)
+    assert (err <= tol).all(), (err.max(), tol.max())
+    if dtype == npvs.NPVS_BF16:  # bf16 output: the float32 result rounded to nearest even
+        Yb = npvs.strided_conv_fwd(Xt, Wp, bt, cin, cout, lv, up, dtype, relu=True)
+        np.testing.assert_array_equal(to_np(Yb)[:n_out], to_np(Y[:n_out].to(torch.bfloat16)))
+
+
+def test_concat_channels_bit_exact():
+    dims = [(32, 32, 32)]
+    _, occ = _grids(dims, [9])
+    rb = npvs.build_rulebook(occ, dims, 2)
+    n = rb.host_counts()["n_sites"]
+    A = torch.randn((rb.cap, 24), device=DEV).to(torch.bfloat16)
+    B = torch.randn((rb.cap, 16), device=DEV).to(torch.bfloat16)
+    Y = npvs.concat_channels(A, B, rb)
+    np.testing.assert_array_equal(to_np(Y)[:n], np.concatenate([to_np(A)[:n], to_np(B)[:n]], axis=1))
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_unet(name, seed, E, Dc):
+    cfg = synth.config(name)
+    t = synth.scene_for(cfg)
+    params = synth.unet_params(seed, cfg.d, E=E, Dc=Dc)
+    return cfg, t, params, oracle.unet_forward(t, cfg.grids[0], cfg.d, params)
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+@pytest.mark.parametrize("name,E,Dc", [("tiny32", 16, 24), ("city256", 64, 96)])
+def test_unet_forward_matches_oracle(name, E, Dc, dtype):
+    cfg, t, params, out = _oracle_unet(name, 11, E, Dc)
+    net = UNet(params, cfg.d, dtype)
+    tris, counts = upload_tris([t])
+    pvs, logits, lv, occ = unet_pvs(net, tris, counts, cfg.grids)
+    n = len(out["keys0"])
+    assert lv.rb0.host_counts()["n_sites"] == n and lv.rb1.host_counts()["n_sites"] == len(out["keys1"])
+    np.testing.assert_array_equal(to_np(occ).reshape(-1), out["occ"].reshape(-1))
+    ref = out["acts"]["Y"]
+    err = np.abs(to_np(logits)[:n] - ref).max()
+    tol = 1e-4 if dtype == npvs.NPVS_F32 else 0.1
+    print(f"{name} dtype {dtype}: n0 {n} n1 {len(out['keys1'])} max |logit err| {err:.3e}", flush=True)
+    assert err <= tol, err
+    # the PVS bits agree wherever the oracle's logit is clear of the threshold by the tolerance
+    lg = out["logits"].reshape(-1)
+    safe = np.abs(lg) > tol
+    pv = np.unpackbits(to_np(pvs).reshape(-1), bitorder="little")
+    pw = np.unpackbits(out["pvs"].reshape(-1), bitorder="little")
+    np.testing.assert_array_equal(pv[safe], pw[safe])
+
+
+def test_unet_forward_on_an_empty_grid():
+    cfg = synth.config("tiny32")
+    net = UNet(synth.unet_params(11, cfg.d, E=16, Dc=24), cfg.d, npvs.NPVS_BF16)
+    tris, counts = upload_tris([np.zeros((0, 3, 3), np.float32)])
+    pvs, logits, lv, occ = unet_pvs(net, tris, counts, cfg.grids)
+    assert lv.rb0.host_counts()["n_sites"] == 0 and lv.rb1.host_counts()["n_sites"] == 0
+    assert not to_np(pvs).any()

@@ -73,22 +73,12 @@ def test_coarse_sites_are_the_sites_of_interleave_factor_2d():
     np.testing.assert_array_equal(np.unique(((bz // 2) * C + by // 2) * C + bx // 2), keys1)
 
 
-def unet_params(seed, d, E=16, Dc=24):
-    """Small random U-Net parameters (the layer shapes of the two-level network)."""
-    rng = np.random.default_rng(seed)
-    def conv(k, cin, cout):
-        return (rng.normal(0, np.sqrt(2.0 / (k * cin)), size=(k, cin, cout)), rng.normal(0, 0.05, size=cout))
-    C = d ** 3
-    return dict(stem=[conv(27, C, E)], enc0=[conv(27, E, E), conv(27, E, E)], down=[conv(8, E, E)],
-                enc1=[conv(27, E, E) for _ in range(3)], up=[conv(8, E, Dc)],
-                dec0=[conv(27, Dc + E, Dc), conv(27, Dc, Dc)], head=[conv(27, Dc, C)])
-
-
 def test_unet_forward_matches_masked_dense_torch():
     cfg = synth.config("tiny32")
     tris = synth.scene_for(cfg)
     g, d = cfg.grids[0], 2
-    params = unet_params(4, d)
+    params = {k: [(W.astype(np.float64), b.astype(np.float64)) for W, b in v]
+              for k, v in synth.unet_params(4, d, E=16, Dc=24).items()}
     out = oracle.unet_forward(tris, g, d, params, want_logits=False)
     keys0, keys1 = out["keys0"], out["keys1"]
     b0 = (g[0] // d, g[1] // d, g[2] // d)
