@@ -212,6 +212,74 @@ def bench_wide(args, dev, timed_launches):
     return res
 
 
+def bench_unet(args, dev, timed_launches):
+    """The city frame through the two-level U-Net (d = 4; embedding / encoder 64 and decoder 96
+    channels): the whole path froxelize -> PVS captured as one graph in BF16 and FP32, and the
+    strided down and inverse up convolutions timed launch by launch."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+    from paper_2509_24677_amd.unet import UNet, unet_pvs
+
+    cfg = synth.config("city256")
+    t = synth.scene_for(cfg)
+    params = synth.unet_params(11, cfg.d)
+    tris = torch.from_numpy(t).to(dev)
+    nt = [len(t)]
+    r = {"d": cfg.d, "channels": {"embed": 64, "encoder": 64, "decoder": 96}}
+    for dtype, tag in ((npvs.NPVS_BF16, "bf16"), (npvs.NPVS_F32, "fp32")):
+        net = UNet(params, cfg.d, dtype)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(3):
+                unet_pvs(net, tris, nt, cfg.grids)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            unet_pvs(net, tris, nt, cfg.grids)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        r[f"{tag}_fwd_ms"] = ms
+        r[f"{tag}_fwd_frames_per_s"] = 1000.0 / ms
+        del g
+    r["bf16_fwd_speedup_vs_fp32"] = r["fp32_fwd_ms"] / r["bf16_fwd_ms"]
+    occ = npvs.froxelize(tris, nt, cfg.grids)
+    lv = npvs.build_levels(occ, cfg.grids, cfg.d, csr=True)
+    c0, c1 = lv.rb0.host_counts(), lv.rb1.host_counts()
+    r.update(n_sites_level0=c0["n_sites"], n_sites_level1=c1["n_sites"], n_pairs_level0=c0["n_pairs"],
+             n_pairs_level1=c1["n_pairs"])
+    n0 = c0["n_sites"]
+    X0 = torch.randn((lv.rb0.cap, 64), device=dev).to(torch.bfloat16)
+    (Wd, bd), = params["down"]
+    (Wu, bu), = params["up"]
+    Wdp = npvs.pack_weights_k(torch.from_numpy(Wd).to(dev), npvs.NPVS_BF16)
+    Wup = npvs.pack_weights_k(torch.from_numpy(Wu).to(dev), npvs.NPVS_BF16)
+    bdt, but = torch.from_numpy(bd).to(dev), torch.from_numpy(bu).to(dev)
+    H1 = npvs.strided_conv_fwd(X0, Wdp, bdt, 64, 64, lv, False, npvs.NPVS_BF16)
+    U = npvs.strided_conv_fwd(H1, Wup, but, 64, 96, lv, True, npvs.NPVS_BF16)
+    for key, cin, cout, launch in (
+            ("down_layer", 64, 64, lambda: npvs.strided_conv_fwd(X0, Wdp, bdt, 64, 64, lv, False, npvs.NPVS_BF16, out=H1)),
+            ("up_layer", 64, 96, lambda: npvs.strided_conv_fwd(H1, Wup, but, 64, 96, lv, True, npvs.NPVS_BF16, out=U))):
+        ms = float(np.mean(timed_launches(launch, 20)))
+        flops = 2.0 * n0 * cin * cout  # every level-0 site enters exactly one product
+        r[key] = {"shape": [cin, cout], "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                  "frac_of_bf16_peak": flops / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
+    return r
+
+
 def bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs):
     """Culling against the city's BF16 PVS: every scene triangle (npvs_visible_triangles), and 2048
     box-shaped temporal bounding volumes of 10 triangles each as objects (npvs_visible_objects)."""
@@ -528,6 +596,8 @@ def main():
     print("# interleave factors 8 and 16 " + json.dumps(wide), file=sys.stderr, flush=True)
     cull = bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs_b)
     print("# culling " + json.dumps(cull), file=sys.stderr, flush=True)
+    unet = bench_unet(args, dev, timed_launches)
+    print("# two-level U-Net " + json.dumps(unet), file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------------ accuracy
     torch.cuda.synchronize()
@@ -592,6 +662,7 @@ def main():
         "batch16": batch16,
         "interleave_8_16": wide,
         "culling": cull,
+        "unet": unet,
         "accuracy": acc,
     }
     print(json.dumps(line))
