@@ -54,6 +54,7 @@ def _load():
             "oracle_masked_dense_conv": (None, [P, P] + [ctypes.c_int] * 4 + [P, P, ctypes.c_int, ctypes.c_int, P]),
             "oracle_deinterleave_threshold": (None, [P, i32, P, P] + [ctypes.c_int] * 4 + [P, P]),
             "oracle_loss": (None, [P, P, i64, f64, P, P]),
+            "oracle_loss_dice": (None, [P, P, i64, f64, f64, P, P]),
             "oracle_subm_conv_bwd": (None, [P, i32, ctypes.c_int, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, P]),
             "oracle_adam": (None, [P, P, P, P, i64, i64, f64, f64, f64, f64, f64]),
             "oracle_label_raymarch": (i64, [P, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
@@ -243,6 +244,20 @@ def loss(logits, labels, lam: float = 0.99, want_grad: bool = True):
     _load().oracle_loss(_p(l), _p(y), l.shape[0], lam, _p(out), _p(g))
     keys = ["loss", "bce", "lrv", "tp", "fn", "fp", "gtp"]
     res = dict(zip(keys, out.tolist()))
+    if want_grad:
+        res["grad"] = g.reshape(np.shape(logits))
+    return res
+
+
+def loss_dice(logits, labels, lam: float = 0.99, alpha: float = 0.9, want_grad: bool = True):
+    """The paper's combined loss lambda * L_dice + (1 - lambda) * L_rv (Sec. 3.3), weighted Dice
+    with alpha on the missed ground-truth froxels.  Keys: loss, dice, lrv, tp, fn, fp, gtp[, grad]."""
+    l = _c(logits, np.float64).reshape(-1)
+    y = _c(labels, np.uint8).reshape(-1)
+    out = np.zeros(7, np.float64)
+    g = np.zeros_like(l) if want_grad else None
+    _load().oracle_loss_dice(_p(l), _p(y), l.shape[0], lam, alpha, _p(out), _p(g))
+    res = dict(zip(["loss", "dice", "lrv", "tp", "fn", "fp", "gtp"], out.tolist()))
     if want_grad:
         res["grad"] = g.reshape(np.shape(logits))
     return res

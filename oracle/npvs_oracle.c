@@ -342,6 +342,49 @@ void oracle_loss(const double *l, const uint8_t *y, int64_t m, double lambda, do
 }
 
 /* ------------------------------------------------------------------------------------------
+ * The paper's combined loss with its weighted Dice term (Sec. 3.3):
+ *   L = lambda * L_dice + (1 - lambda) * L_rv,
+ *   L_dice = 1 - 2 TP / (2 TP + alpha * A + (1 - alpha) * B),
+ * where A and B are the terms the printed formulas call FP and FN: A = sum y (1-p) (ground-truth
+ * froxels the prediction misses) and B = sum (1-y) p, so that alpha weighs the missed froxels,
+ * as the text says.  L_rv as in oracle_loss (FN = A, FP = B in the words' sense).  Soft counts
+ * with p = sigmoid(l).  out: L, L_dice, L_rv, TP, FN, FP, GTP; grad = dL/dl (nullable).
+ * ------------------------------------------------------------------------------------------ */
+void oracle_loss_dice(const double *l, const uint8_t *y, int64_t m, double lambda, double alpha, double *out,
+                      double *grad) {
+  double tp = 0, fn = 0, fp = 0, gtp = 0;
+  for (int64_t t = 0; t < m; ++t) {
+    double p = 1.0 / (1.0 + exp(-l[t]));
+    tp += y[t] * p;
+    fn += y[t] * (1.0 - p);
+    fp += (1 - y[t]) * p;
+    gtp += y[t];
+  }
+  double g = gtp > 1.0 ? gtp : 1.0;
+  double den = 2.0 * tp + alpha * fn + (1.0 - alpha) * fp;
+  double dice = den > 0.0 ? 1.0 - 2.0 * tp / den : 0.0;
+  double lrv = fn / g + fp / g;
+  out[0] = lambda * dice + (1.0 - lambda) * lrv;
+  out[1] = dice;
+  out[2] = lrv;
+  out[3] = tp;
+  out[4] = fn;
+  out[5] = fp;
+  out[6] = gtp;
+  if (grad)
+    for (int64_t t = 0; t < m; ++t) {
+      double p = 1.0 / (1.0 + exp(-l[t]));
+      double yt = y[t];
+      /* quotient rule: d(2TP)/dp = 2y, d(den)/dp = 2y - alpha y + (1 - alpha)(1 - y) */
+      double ddice = den > 0.0 ? -(2.0 * yt * den - 2.0 * tp * (2.0 * yt - alpha * yt + (1.0 - alpha) * (1.0 - yt))) /
+                                     (den * den)
+                               : 0.0;
+      double drv = (1.0 - 2.0 * yt) / g;
+      grad[t] = (lambda * ddice + (1.0 - lambda) * drv) * p * (1.0 - p);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------
  * Backward of one submanifold layer, FP64, by the chain rule on the forward definition:
  *   dZ = dY * [Y > 0] (ReLU'(0) = 0) when relu, else dY;
  *   dX[i] += sum_k sum_{(i,r) in R_k} dZ[r] W_k^T;  dW_k = sum_{(i,r)} X[i]^T dZ[r];  db = sum_r dZ[r].

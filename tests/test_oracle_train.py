@@ -68,6 +68,49 @@ def test_no_positive_labels_guard():
     assert r["gtp"] == 0 and r["lrv"] == pytest.approx(p.sum(), abs=1e-15)
 
 
+def test_dice_loss_three_froxel_hand_example():
+    # l = (ln 3, ln 3, -ln 3), y = (1, 0, 1): p = (3/4, 3/4, 1/4); TP = 1, missed A = 1, B = 3/4,
+    # GTP = 2; alpha = 0.8: den = 2 + 0.8 + 0.15 = 59/20, L_dice = 1 - 40/59 = 19/59; L_rv = 7/8
+    r = oracle.loss_dice(np.array([math.log(3.0), math.log(3.0), -math.log(3.0)]), np.array([1, 0, 1]), lam=0.99,
+                         alpha=0.8)
+    assert (r["tp"], r["fn"], r["fp"], r["gtp"]) == pytest.approx((1.0, 1.0, 0.75, 2.0), abs=1e-15)
+    assert r["dice"] == pytest.approx(19.0 / 59.0, abs=1e-15)
+    assert r["lrv"] == pytest.approx(0.875, abs=1e-15)
+    assert r["loss"] == pytest.approx(0.99 * 19.0 / 59.0 + 0.01 * 0.875, abs=1e-15)
+
+
+def test_dice_loss_gradient_finite_differences_and_autograd():
+    rng = np.random.default_rng(1)
+    l = rng.normal(0, 2, size=40)
+    y = (rng.random(40) < 0.3).astype(np.uint8)
+    for alpha in (0.9, 0.5, 0.0):
+        g = oracle.loss_dice(l, y, alpha=alpha)["grad"]
+        h = 1e-6
+        for t in range(40):
+            lp, lm = l.copy(), l.copy()
+            lp[t] += h
+            lm[t] -= h
+            fd = (oracle.loss_dice(lp, y, alpha=alpha, want_grad=False)["loss"]
+                  - oracle.loss_dice(lm, y, alpha=alpha, want_grad=False)["loss"]) / (2 * h)
+            assert abs(fd - g[t]) <= 1e-7 * max(1.0, abs(g[t]))
+        # torch autograd of the soft counts (float64)
+        lt = torch.tensor(l, requires_grad=True)
+        yt = torch.tensor(y, dtype=torch.float64)
+        p = torch.sigmoid(lt)
+        tp, a, b = (yt * p).sum(), (yt * (1 - p)).sum(), ((1 - yt) * p).sum()
+        val = 0.99 * (1 - 2 * tp / (2 * tp + alpha * a + (1 - alpha) * b)) + 0.01 * (a + b) / max(float(y.sum()), 1.0)
+        val.backward()
+        np.testing.assert_allclose(g, lt.grad.numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_dice_loss_limits():
+    y = np.array([1, 0, 1, 1, 0, 0], np.uint8)
+    r = oracle.loss_dice(np.where(y == 1, 60.0, -60.0), y)  # perfect prediction
+    assert r["dice"] < 1e-20 and r["lrv"] < 1e-20
+    r = oracle.loss_dice(np.array([0.3, -1.0]), np.array([0, 0]))  # no ground truth: TP = 0
+    assert r["dice"] == pytest.approx(1.0, abs=1e-15)
+
+
 # ------------------------------------------------------------------ backward
 def _small_net():
     dims = (32, 32, 32)
