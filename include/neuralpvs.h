@@ -340,6 +340,17 @@ npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, con
                       int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, float *stats,
                       float *dlogits, void *ws, size_t ws_bytes, void *stream);
 
+/* The same with the paper's weighted Dice term in place of BCE (term = NPVS_LOSS_DICE):
+ *   L = lambda L_dice + (1-lambda) L_rv,  L_dice = 1 - 2 TP / (2 TP + alpha FN + (1-alpha) FP)
+ * (alpha weighs the missed ground-truth froxels, as the text of Sec. 3.3 says; the printed
+ * formulas name that term FP); stats column 1 then holds L_dice.  term = NPVS_LOSS_BCE is
+ * npvs_loss (alpha unused). */
+#define NPVS_LOSS_BCE 0
+#define NPVS_LOSS_DICE 1
+npvs_status npvs_loss_ex(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                         int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, int32_t term,
+                         float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream);
+
 /* Adam (Kingma & Ba) step t >= 1 on float32 masters, with weight decay added to the gradient
  * (read from the decay rate the paper lists with the learning rate); p, g, m, v (device) float32 [n]. */
 npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float beta1,

@@ -379,9 +379,11 @@ def visible_objects(vis_tris: torch.Tensor, obj_off: torch.Tensor) -> torch.Tens
 
 
 # --------------------------------------------------------------------------------- training
-def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 0.99, want_grad: bool = True):
-    """Per-grid BCE + repulsive visibility loss.  Returns (stats float32 [n_grids + 1][8] with
-    columns L, BCE, L_rv, TP, FN, FP, GTP, m and the batch mean in the last row, dL/dlogits)."""
+def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 0.99, want_grad: bool = True,
+         dice_alpha: float | None = None):
+    """Per-grid BCE (or, with dice_alpha, the weighted Dice term) + repulsive visibility loss.
+    Returns (stats float32 [n_grids + 1][8] with columns L, BCE or Dice, L_rv, TP, FN, FP, GTP, m
+    and the batch mean in the last row, dL/dlogits)."""
     G = len(rb.dims)
     C = logits.shape[1]
     nbytes = ctypes.c_size_t()
@@ -390,8 +392,9 @@ def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     stats = torch.empty((G + 1, 8), dtype=torch.float32, device=dev)
     dl = torch.empty_like(logits) if want_grad else None  # rows past the active sites are never read
-    L.call("npvs_loss", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam),
-           _p(stats), _p(dl), _p(ws), nbytes.value, _stream())
+    term = L.NPVS_LOSS_BCE if dice_alpha is None else L.NPVS_LOSS_DICE
+    L.call("npvs_loss_ex", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam), term,
+           float(dice_alpha or 0.0), _p(stats), _p(dl), _p(ws), nbytes.value, _stream())
     return stats, dl
 
 

@@ -23,6 +23,8 @@ NPVS_CONV_VARIANTS = 14
 NPVS_DEFAULT_CONV_VARIANT = 12
 NPVS_MAX_PACK = 64
 NPVS_BWD_DB_PARTS = 512
+NPVS_LOSS_BCE = 0
+NPVS_LOSS_DICE = 1
 
 
 class NpvsError(RuntimeError):
@@ -84,6 +86,7 @@ SIGNATURES = {
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),
     "npvs_loss_workspace_size": (i32, [i32, PS]),
     "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, P, P, P, sz, P]),
+    "npvs_loss_ex": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, P]),
     "npvs_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, f32, P]),
     "npvs_adam_dev": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, P]),
     "npvs_plan_create": (i32, [i32, P, P, i32, i32, P, i32, ctypes.POINTER(P)]),

@@ -1,11 +1,13 @@
 // Training loss over the froxels of each grid's active blocks and Adam.
 //   Sec. 3.3: repulsive visibility loss L_rv = L_attr + L_rep with L_rep = FP/GTP; the
 //   attraction term is read as 1 - TP/GTP = FN/GTP (printed literally it would reward missed
-//   geometry); combined as L = lambda * BCE + (1 - lambda) * L_rv with BCE in place of Dice.
+//   geometry); combined as L = lambda * T + (1 - lambda) * L_rv, with T = BCE in place of Dice
+//   (the weight alpha of the Dice term is unstated) or T = the weighted Dice term
+//   1 - 2 TP / (2 TP + alpha FN + (1 - alpha) FP), alpha on the missed ground truth.
 //   Soft counts use p = sigmoid(l): TP = sum y p, FN = sum y (1-p), FP = sum (1-y) p, GTP = sum y.
 // Three launches: per-(grid, slice) compensated partial sums, one workgroup that finishes the
 // sums in a fixed order and writes the statistics and gradient coefficients, and the
-// elementwise gradient dL/dl = a_b (p - y) + c_b p (1 - p)(1 - 2y).
+// elementwise gradient dL/dl = c0_b (p - y) + p (1 - p) (y ? cy_b : cn_b).
 #include <cmath>
 
 #include "npvs_common.hpp"
@@ -68,13 +70,14 @@ __global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restri
 }
 
 // One workgroup per grid: thread s takes slice s's partial sums, a fixed-shape tree adds them,
-// thread 0 writes the grid's statistics and gradient coefficients coef[b] = {a_b, c_b}.
+// thread 0 writes the grid's statistics and gradient coefficients coef[b] = {c0_b, cy_b, cn_b}.
 // One block per grid finishes that grid's sums (fixed tree); the last block to finish, found with
 // a ticket taken after a device-scope fence, writes the batch mean (grids in order).
 __global__ __launch_bounds__(kLossSlices) void loss_final_kernel(const float *__restrict__ part,
                                                                  const int32_t *__restrict__ grid_rows, int n_grids,
-                                                                 int C, float lambda, float *__restrict__ stats,
-                                                                 float *__restrict__ coef, uint32_t *__restrict__ ticket) {
+                                                                 int C, float lambda, int term, float alpha,
+                                                                 float *__restrict__ stats, float *__restrict__ coef,
+                                                                 uint32_t *__restrict__ ticket) {
   __shared__ Comp red[kLossQ][kLossSlices];
   __shared__ bool last;
   const int b = blockIdx.x, s = threadIdx.x;
@@ -92,12 +95,28 @@ __global__ __launch_bounds__(kLossSlices) void loss_final_kernel(const float *__
     const float bce_sum = red[0][0].s + red[0][0].c, tp = red[1][0].s + red[1][0].c, fn = red[2][0].s + red[2][0].c,
                 fp = red[3][0].s + red[3][0].c, gtp = red[4][0].s + red[4][0].c;
     const float g = gtp > 1.0f ? gtp : 1.0f;
-    const float bce = m > 0.0f ? bce_sum / m : 0.0f;
     const float lrv = fn / g + fp / g;
-    const float v[8] = {lambda * bce + (1.0f - lambda) * lrv, bce, lrv, tp, fn, fp, gtp, m};
+    const float crv = (1.0f - lambda) / (g * n_grids);  // L_rv: d/dp = (1 - 2y) / GTP
+    float first, c0, cy, cn;
+    if (term == NPVS_LOSS_DICE) {
+      // quotient rule on 1 - 2TP/den: d(2TP)/dp = 2y, d(den)/dp = 2y - alpha y + (1 - alpha)(1 - y)
+      const float den = 2.0f * tp + alpha * fn + (1.0f - alpha) * fp;
+      const float kd = lambda / n_grids;
+      first = den > 0.0f ? 1.0f - 2.0f * tp / den : 0.0f;
+      c0 = 0.0f;
+      cy = (den > 0.0f ? kd * (-2.0f / den + 2.0f * tp * (2.0f - alpha) / (den * den)) : 0.0f) - crv;
+      cn = (den > 0.0f ? kd * (2.0f * tp * (1.0f - alpha) / (den * den)) : 0.0f) + crv;
+    } else {
+      first = m > 0.0f ? bce_sum / m : 0.0f;
+      c0 = m > 0.0f ? lambda / (m * n_grids) : 0.0f;
+      cy = -crv;
+      cn = crv;
+    }
+    const float v[8] = {lambda * first + (1.0f - lambda) * lrv, first, lrv, tp, fn, fp, gtp, m};
     for (int i = 0; i < 8; ++i) stats[b * 8 + i] = v[i];
-    coef[2 * b] = m > 0.0f ? lambda / (m * n_grids) : 0.0f;
-    coef[2 * b + 1] = (1.0f - lambda) / (g * n_grids);
+    coef[3 * b] = c0;
+    coef[3 * b + 1] = cy;
+    coef[3 * b + 2] = cn;
     __threadfence();  // this grid's stats are visible before its ticket
     last = atomicAdd(ticket, 1u) == (uint32_t)(n_grids - 1);
   }
@@ -123,7 +142,7 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict_
     const float l = logits[e];
     const float y = labels[e] ? 1.0f : 0.0f;
     const float p = sigmoidf_(l);
-    dl[e] = coef[2 * b] * (p - y) + coef[2 * b + 1] * p * (1.0f - p) * (1.0f - 2.0f * y);
+    dl[e] = coef[3 * b] * (p - y) + p * (1.0f - p) * (labels[e] ? coef[3 * b + 1] : coef[3 * b + 2]);
   }
 }
 
@@ -160,13 +179,14 @@ using namespace npvs;
 extern "C" npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes) {
   if (!bytes || n_grids < 1 || n_grids > NPVS_MAX_GRIDS)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_loss_workspace_size: bad arguments");
-  *bytes = sizeof(float) * ((size_t)n_grids * kLossSlices * kLossQ + 2 * (size_t)n_grids) + 256;
+  *bytes = sizeof(float) * ((size_t)n_grids * kLossSlices * kLossQ + 3 * (size_t)n_grids) + 256;
   return NPVS_OK;
 }
 
-extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
-                                int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
-                                float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream) {
+extern "C" npvs_status npvs_loss_ex(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                                   int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
+                                   int32_t term, float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes,
+                                   void *stream) {
   if (!logits || !labels || !grid_rows || !counts || !stats || !ws)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: null pointer");
   if (C < 1 || n_grids < 1 || n_grids > NPVS_MAX_GRIDS || cap_sites < 1)
@@ -175,15 +195,25 @@ extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int
   npvs_loss_workspace_size(n_grids, &need);
   if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: workspace too small");
   float *part = static_cast<float *>(ws);
+  if (term != NPVS_LOSS_BCE && term != NPVS_LOSS_DICE)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: term must be NPVS_LOSS_BCE or NPVS_LOSS_DICE");
   float *coef = part + (size_t)n_grids * kLossSlices * kLossQ;
-  uint32_t *ticket = reinterpret_cast<uint32_t *>(coef + 2 * (size_t)n_grids);
+  uint32_t *ticket = reinterpret_cast<uint32_t *>(coef + 3 * (size_t)n_grids);
   hipStream_t s = as_stream(stream);
   loss_partial_kernel<<<dim3(kLossSlices, n_grids), 256, 0, s>>>(logits, labels, C, grid_rows, part, ticket);
-  loss_final_kernel<<<n_grids, kLossSlices, 0, s>>>(part, grid_rows, n_grids, C, lambda, stats, coef, ticket);
+  loss_final_kernel<<<n_grids, kLossSlices, 0, s>>>(part, grid_rows, n_grids, C, lambda, term, alpha, stats, coef,
+                                                    ticket);
   if (dlogits)
     loss_grad_kernel<<<stride_grid((int64_t)cap_sites * C, 256, 4096), 256, 0, s>>>(logits, labels, C, grid_rows,
                                                                                    n_grids, counts, coef, dlogits);
   return check_hip(hipGetLastError(), "npvs_loss");
+}
+
+extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                                int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
+                                float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream) {
+  return npvs_loss_ex(logits, labels, C, grid_rows, n_grids, counts, cap_sites, lambda, NPVS_LOSS_BCE, 0.0f, stats,
+                      dlogits, ws, ws_bytes, stream);
 }
 
 extern "C" npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr,

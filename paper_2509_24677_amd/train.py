@@ -202,8 +202,10 @@ class Trainer:
     """One training step per call; all state lives on the device."""
 
     def __init__(self, net: Network, dims, n_tris, lam: float = 0.99, lr: float = 1e-3, weight_decay: float = 1e-10,
-                 checkpoint: bool = True):
+                 checkpoint: bool = True, dice_alpha: float | None = None):
+        """dice_alpha: train on the paper's weighted Dice term (with that alpha) instead of BCE."""
         self.net = net
+        self.dice_alpha = dice_alpha
         self.dims = [tuple(g) for g in dims]
         self.n_tris = list(n_tris)
         self.lam, self.lr, self.wd = lam, lr, weight_decay
@@ -221,7 +223,7 @@ class Trainer:
         logits, saved = net.forward(X0, rb, checkpoint=self.checkpoint)
         pvs, _ = deinterleave_threshold(logits, rb, occ)
         labels = gather_input(label_bits, rb, NPVS_U8)
-        stats, dl = loss(logits, labels, rb, self.lam)
+        stats, dl = loss(logits, labels, rb, self.lam, dice_alpha=self.dice_alpha)
         net.backward(saved, logits, dl, rb)  # gradients land in net.gflat
         self.step_count += 1
         adam_dev(net.flat, net.gflat, self.m, self.v, self.adam_step, lr=self.lr, weight_decay=self.wd)

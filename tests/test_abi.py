@@ -36,7 +36,7 @@ def test_version_and_sizes(lib):
 def test_header_constants_match_binding():
     text = open(L.HEADER).read()
     for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT",
-                 "NPVS_BWD_DB_PARTS"):
+                 "NPVS_BWD_DB_PARTS", "NPVS_LOSS_BCE", "NPVS_LOSS_DICE"):
         assert f"#define {name} {getattr(L, name)}" in text, name
     assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16
     assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes

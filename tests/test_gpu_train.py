@@ -111,6 +111,43 @@ def test_loss_batched_mean_over_grids():
     assert np.abs(to_np(dl)[:n] - want).max() <= 1e-6 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("alpha", [0.9, 0.5])
+def test_dice_loss_matches_oracle(alpha):
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    stats, dl = npvs.loss(acts[-1], labels, rb, lam=0.99, dice_alpha=alpha)
+    n = rb.host_counts()["n_sites"]
+    ref = oracle.loss_dice(to_np(acts[-1])[:n].astype(np.float64), to_np(labels)[:n], lam=0.99, alpha=alpha)
+    s = to_np(stats)[0]
+    for i, key in enumerate(["loss", "dice", "lrv", "tp", "fn", "fp", "gtp"]):
+        assert abs(s[i] - ref[key]) <= 2e-6 * max(1.0, abs(ref[key])), (key, s[i], ref[key])
+    g = to_np(dl)[:n]
+    assert np.abs(g - ref["grad"]).max() <= 1e-5 * np.abs(ref["grad"]).max()
+
+
+def test_dice_loss_batched_mean_over_grids():
+    dims = [(32, 32, 32), (64, 32, 32), (32, 32, 64)]
+    tri_list = [synth.box_scene(70 + i, g, 20, 2, 8) for i, g in enumerate(dims)]
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    rb = npvs.build_rulebook(occ, dims, 2)
+    ref = oracle_batch(tri_list, dims, 2)
+    n = ref["n"]
+    rng = np.random.default_rng(3)
+    L = rng.normal(size=(rb.cap, 8)).astype(np.float32)
+    Y = (rng.random((rb.cap, 8)) < 0.3).astype(np.uint8)
+    stats, dl = npvs.loss(torch.from_numpy(L).to(DEV), torch.from_numpy(Y).to(DEV), rb, dice_alpha=0.8)
+    s = to_np(stats)
+    gr = ref["grid_rows"]
+    per = [oracle.loss_dice(L[gr[b]:gr[b + 1]].astype(np.float64), Y[gr[b]:gr[b + 1]], alpha=0.8) for b in range(3)]
+    for b in range(3):
+        assert abs(s[b, 0] - per[b]["loss"]) <= 2e-6 * abs(per[b]["loss"])
+    assert abs(s[3, 0] - np.mean([p["loss"] for p in per])) <= 2e-6
+    want = np.concatenate([p["grad"] / 3 for p in per])
+    assert np.abs(to_np(dl)[:n] - want).max() <= 1e-5 * np.abs(want).max()
+
+
 def test_backward_f32_matches_oracle_gradient():
     cfg, t, layers, occ, rb, lab_bits = _setup()
     acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
