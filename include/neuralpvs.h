@@ -226,6 +226,17 @@ npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *W
                                        int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
                                        size_t ws_bytes, void *stream, void *wgrad_stream);
 
+/* The same with the final reductions (dW over the weight-gradient slices, db over the row blocks)
+ * on a third stream: reduce_stream waits for the weight gradient of wgrad_stream, so the next
+ * layer's weight gradient does not wait for this layer's reductions (they are small and run
+ * beside it).  Until the caller makes `stream` wait for reduce_stream (and wgrad_stream), dW,
+ * db, X and ws are in use; reduce_stream may equal wgrad_stream (npvs_sparse_conv_bwd_split). */
+npvs_status npvs_sparse_conv_bwd_split2(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
+                                        const float *dY, const int32_t *nbr, const int32_t *rb_off,
+                                        const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
+                                        int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
+                                        size_t ws_bytes, void *stream, void *wgrad_stream, void *reduce_stream);
+
 /* The backward of a stack of BF16 layers as a chain, one call per layer from the top, with each
  * layer's ReLU' fused into the data gradient of the layer above it (the same chain rule as above;
  * the gradients are in a different float32 summation order for db only: dZ and dW are

@@ -212,18 +212,20 @@ def conv_bwd_workspace(cin: int, cout: int, rb: Rulebook, dtype: int) -> torch.T
 
 def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int, relu: bool, want_dx: bool = True,
                     dW: torch.Tensor | None = None, db: torch.Tensor | None = None, ws: torch.Tensor | None = None,
-                    wgrad_stream: torch.cuda.Stream | None = None):
+                    wgrad_stream: torch.cuda.Stream | None = None, reduce_stream: torch.cuda.Stream | None = None):
     """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout]).
     dW / db may be given (contiguous float32 device tensors) to receive the gradients in place.
-    With `wgrad_stream`, dW and db are computed on that stream (npvs_sparse_conv_bwd_split): the
-    caller keeps X and ws alive and joins the stream before reading dW / db."""
+    With `wgrad_stream`, dW and db are computed on that stream (npvs_sparse_conv_bwd_split), and
+    with `reduce_stream` too their final reductions on that one (npvs_sparse_conv_bwd_split2):
+    the caller keeps X and ws alive and joins the streams before reading dW / db."""
     if rb.rb_off is None:
         raise ValueError("the backward needs a rulebook built with csr=True")
     dev = X.device
     if ws is None:
         ws = conv_bwd_workspace(cin, cout, rb, dtype)
-        if wgrad_stream is not None:  # freed here, still read by the side stream
-            ws.record_stream(wgrad_stream)
+        for side in (wgrad_stream, reduce_stream):  # freed here, still read by the side streams
+            if side is not None:
+                ws.record_stream(side)
     dX = torch.empty((rb.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
     if dW is None:
         dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
@@ -235,8 +237,11 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
             _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), ws.numel(), _stream())
     if wgrad_stream is None:
         L.call("npvs_sparse_conv_bwd", *args)
-    else:
+    elif reduce_stream is None:
         L.call("npvs_sparse_conv_bwd_split", *args, ctypes.c_void_p(wgrad_stream.cuda_stream))
+    else:
+        L.call("npvs_sparse_conv_bwd_split2", *args, ctypes.c_void_p(wgrad_stream.cuda_stream),
+               ctypes.c_void_p(reduce_stream.cuda_stream))
     return dX, dW, db
 
 

@@ -73,6 +73,7 @@ SIGNATURES = {
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
     "npvs_sparse_conv_bwd_split": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P]),
+    "npvs_sparse_conv_bwd_split2": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P, P]),
     "npvs_conv_bwd_begin": (i32, [P, P, i32, P, i32, i32, P, P, P]),
     "npvs_conv_bwd_chain_workspace_size": (i32, [i32, i32, PS]),
     "npvs_sparse_conv_bwd_chain": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, P, P, P, P, P, sz, P, P]),

@@ -428,12 +428,14 @@ static npvs_status join_after(hipStream_t s, hipStream_t s2) {
   return st;
 }
 
-// dZ and the bias partials on s; the data gradient on s; the weight gradient and the reductions
-// on s2 (s2 == s: one stream; otherwise s2 first waits for the dZ of s).
+// dZ and the bias partials on s; the data gradient on s; the weight gradient on s2 and the
+// reductions on s3 (s2 first waits for the dZ of s, s3 for the weight gradient of s2; equal
+// streams need no wait).
 static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y, const float *dY,
                             const int32_t *nbr, const int32_t *rb_off, const int32_t *rb_pairs,
                             const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
-                            float *dW, float *db, void *ws, size_t ws_bytes, hipStream_t s, hipStream_t s2) {
+                            float *dW, float *db, void *ws, size_t ws_bytes, hipStream_t s, hipStream_t s2,
+                            hipStream_t s3) {
   if (!X || !dY || !nbr || !rb_off || !rb_pairs || !counts || !dW || !db || !ws || (relu && !Y) || (dX && !Wt))
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: null pointer");
   if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: bad sizes");
@@ -474,8 +476,11 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
     wgrad_bf16_kernel<<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
   else
     wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
+  st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
+  if (st == NPVS_OK) st = join_after(s2, s3);
+  if (st != NPVS_OK) return st;
   const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbpart, kDbBlocks, cin, cout, nbw, dW, db);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s3>>>(wpart, dbpart, kDbBlocks, cin, cout, nbw, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
 }
 
@@ -486,7 +491,7 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
                                            int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
                                            size_t ws_bytes, void *stream) {
   return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
-                  ws_bytes, as_stream(stream), as_stream(stream));
+                  ws_bytes, as_stream(stream), as_stream(stream), as_stream(stream));
 }
 
 extern "C" npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *Wt, int32_t cout,
@@ -496,7 +501,18 @@ extern "C" npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, co
                                                  int32_t relu, float *dX, float *dW, float *db, void *ws,
                                                  size_t ws_bytes, void *stream, void *wgrad_stream) {
   return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
-                  ws_bytes, as_stream(stream), as_stream(wgrad_stream));
+                  ws_bytes, as_stream(stream), as_stream(wgrad_stream), as_stream(wgrad_stream));
+}
+
+extern "C" npvs_status npvs_sparse_conv_bwd_split2(const void *X, int32_t cin, const void *Wt, int32_t cout,
+                                                  const void *Y, const float *dY, const int32_t *nbr,
+                                                  const int32_t *rb_off, const int32_t *rb_pairs,
+                                                  const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
+                                                  int32_t relu, float *dX, float *dW, float *db, void *ws,
+                                                  size_t ws_bytes, void *stream, void *wgrad_stream,
+                                                  void *reduce_stream) {
+  return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
+                  ws_bytes, as_stream(stream), as_stream(wgrad_stream), as_stream(reduce_stream));
 }
 
 extern "C" npvs_status npvs_conv_bwd_begin(const float *dY, const void *Y, int32_t cout, const npvs_counts *counts,

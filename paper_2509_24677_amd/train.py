@@ -123,7 +123,8 @@ class Network:
                  fused: bool | None = None):
         """Hand-written backward through the stack; recomputes the layer inputs that were not
         saved.  With `overlap`, each layer's weight gradient runs on a side stream while the data
-        gradient continues down the stack; the side stream is joined before returning.  The
+        gradient continues down the stack (their final reductions on a third stream, beside the
+        next weight gradient); the side streams are joined before returning.  The
         gradients land in the flat gradient buffer; returns [(dW, db)] per layer (views of it).
         With `fused` (and a chainable stack) the layers are chained through bfloat16 dZ with the
         ReLU' fused into the data gradients; otherwise each layer forms its own dZ in a small
@@ -134,11 +135,11 @@ class Network:
         if fused is None:
             fused = not overlap
         main = torch.cuda.current_stream()
-        side = None
+        side = side2 = None
         if overlap:
             if getattr(self, "_side", None) is None:
-                self._side = torch.cuda.Stream()
-            side = self._side
+                self._side, self._side2 = torch.cuda.Stream(), torch.cuda.Stream()
+            side, side2 = self._side, self._side2
         if fused and self.chainable():
             return self._backward_chain(saved, dlogits, rb, main, side)
         grads = [None] * self.n_layers
@@ -155,7 +156,8 @@ class Network:
             ws = conv_bwd_workspace(self.channels[i], self.channels[i + 1], rb, self.dtype)
             dX, dW, db = sparse_conv_bwd(X, self.Wt[i], self.channels[i], self.channels[i + 1], Y, dY, rb,
                                          self.dtype, relu=i < self.n_layers - 1, want_dx=i > 0,
-                                         dW=self.gW[i], db=self.gb[i], ws=ws, wgrad_stream=side)
+                                         dW=self.gW[i], db=self.gb[i], ws=ws, wgrad_stream=side,
+                                         reduce_stream=side2)
             in_use += [X, ws]
             grads[i] = (dW, db)
             if i > 0:
@@ -163,6 +165,7 @@ class Network:
             dY = dX
         if side is not None:
             main.wait_stream(side)
+            main.wait_stream(side2)
         del in_use
         return grads
 
