@@ -55,6 +55,8 @@ def _load():
             "oracle_deinterleave_threshold": (None, [P, i32, P, P] + [ctypes.c_int] * 4 + [P, P]),
             "oracle_loss": (None, [P, P, i64, f64, P, P]),
             "oracle_loss_dice": (None, [P, P, i64, f64, f64, P, P]),
+            "oracle_froxelize_view": (i64, [P, i64, P, P, P, P, f64, f64, f64, f64, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, f64, P]),
             "oracle_subm_conv_bwd": (None, [P, i32, ctypes.c_int, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, P]),
             "oracle_adam": (None, [P, P, P, P, i64, i64, f64, f64, f64, f64, f64]),
             "oracle_label_raymarch": (i64, [P, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
@@ -409,3 +411,33 @@ def unet_forward(tris, dims, d, params, want_logits: bool = True, occ=None):
     logits, pvs = deinterleave_threshold(Y, keys0, occ, dims, d, want_logits)
     return dict(occ=occ, keys0=keys0, keys1=keys1, children=children, parent=parent, kid=kid, acts=acts,
                 logits=logits, pvs=pvs)
+
+
+# ---------------------------------------------------------------- world-space front end
+def viewcell_view(c, forward, up, fov_y, aspect, r, beta, z_near, z_far):
+    """The frustum F of a viewcell (Sec. 3.2): a camera at c looking along `forward` with
+    vertical field of view fov_y (radians) may move laterally by up to r and turn by up to beta;
+    F has its apex at c' = c - r / tan(fov_y / 2) * forward and the field of view fov_y + 2 beta
+    (horizontal: aspect times its tangent).  Returns a dict: eye, right, up, fwd (orthonormal;
+    right = up x forward), tx, ty (half-angle tangents), zn, zf (linear depth range)."""
+    f = np.asarray(forward, np.float64)
+    f = f / np.linalg.norm(f)
+    rt = np.cross(np.asarray(up, np.float64), f)
+    rt = rt / np.linalg.norm(rt)
+    u = np.cross(f, rt)
+    eye = np.asarray(c, np.float64) - r / np.tan(fov_y / 2.0) * f
+    ty = np.tan((fov_y + 2.0 * beta) / 2.0)
+    return dict(eye=eye, right=rt, up=u, fwd=f, tx=aspect * ty, ty=ty, zn=float(z_near), zf=float(z_far))
+
+
+def froxelize_view(tris_world, view, dims, margin: float = 0.0):
+    """Packed occupancy [nz][ny][nx/8] of world-space triangles in the froxels of `view` (linear
+    depth slices); `margin` widens (> 0) or shrinks (< 0) every froxel by that fraction of its
+    extent per axis in (x/z, y/z, 1/z).  Returns (occ, number of marked froxels)."""
+    nx, ny, nz = dims
+    t = _c(tris_world, np.float32).reshape(-1, 3, 3)
+    occ = np.zeros((nz, ny, nx // 8), np.uint8)
+    v = {k: _c(view[k], np.float64) for k in ("eye", "right", "up", "fwd")}
+    n = _load().oracle_froxelize_view(_p(t), t.shape[0], _p(v["eye"]), _p(v["right"]), _p(v["up"]), _p(v["fwd"]),
+                                      view["tx"], view["ty"], view["zn"], view["zf"], nx, ny, nz, margin, _p(occ))
+    return occ, n

@@ -587,3 +587,105 @@ int64_t oracle_label_raymarch(const float *tris, int64_t T, int nx, int ny, int 
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * World-space froxelization of the viewcell frustum (Sec. 3.2; linear depth slices, Suppl. A.1).
+ * Camera: apex e, orthonormal right / up / forward (r, u, f); eye coordinates
+ * (x, y, z) = ((p-e).r, (p-e).u, (p-e).f).  Froxel (i, j, k) of an Nx x Ny x Nz grid is the set of
+ * points with z in [zn + k s, zn + (k+1) s] (s = (zf - zn) / Nz), x / z in
+ * [tx (2i/Nx - 1), tx (2(i+1)/Nx - 1)] and y / z likewise with ty.  G(i, j, k) = 1 iff a
+ * triangle meets that closed set.  Under (X, Y, Q) = (x/z, y/z, 1/z), a projective map on z > 0,
+ * triangles stay triangles and each froxel becomes an axis-aligned box, so the test is: clip the
+ * triangle at the near plane z = zn, map the pieces, and clip each against the six planes of the
+ * box (non-empty result = overlap).  `margin` moves every box plane outward by margin times the
+ * box's extent along that axis (negative: inward), for tests that need the robustly inside and
+ * robustly outside sets.  occ is packed like the grid-space froxelization.
+ * ------------------------------------------------------------------------------------------ */
+static int clip_poly(double (*in)[3], int n, int axis, double bound, int keep_above, double (*out)[3]) {
+  int m = 0;
+  for (int a = 0; a < n; ++a) {
+    const double *P = in[a], *R = in[(a + 1) % n];
+    double dp = keep_above ? P[axis] - bound : bound - P[axis];
+    double dr = keep_above ? R[axis] - bound : bound - R[axis];
+    if (dp >= 0) {
+      out[m][0] = P[0], out[m][1] = P[1], out[m][2] = P[2];
+      ++m;
+    }
+    if ((dp >= 0) != (dr >= 0)) {
+      double t = dp / (dp - dr);
+      for (int c = 0; c < 3; ++c) out[m][c] = P[c] + t * (R[c] - P[c]);
+      ++m;
+    }
+  }
+  return m;
+}
+
+int64_t oracle_froxelize_view(const float *tris, int64_t T, const double *eye, const double *right, const double *up,
+                              const double *fwd, double tx, double ty, double zn, double zf, int nx, int ny, int nz,
+                              double margin, uint8_t *occ) {
+  memset(occ, 0, (size_t)nz * ny * (nx / 8));
+  const double s = (zf - zn) / nz;
+  int64_t marked = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    double poly[16][3], tmp[16][3];
+    for (int v = 0; v < 3; ++v) {
+      double d[3];
+      for (int c = 0; c < 3; ++c) d[c] = (double)tris[(t * 3 + v) * 3 + c] - eye[c];
+      poly[v][0] = d[0] * right[0] + d[1] * right[1] + d[2] * right[2];
+      poly[v][1] = d[0] * up[0] + d[1] * up[1] + d[2] * up[2];
+      poly[v][2] = d[0] * fwd[0] + d[1] * fwd[1] + d[2] * fwd[2];
+    }
+    int finite = 1;
+    for (int v = 0; v < 3; ++v)
+      for (int c = 0; c < 3; ++c) finite &= isfinite(poly[v][c]) != 0;
+    if (!finite) continue;
+    int n = clip_poly(poly, 3, 2, zn, 1, tmp); /* keep z >= zn */
+    if (n < 3) continue;
+    double P[16][3];
+    for (int a = 0; a < n; ++a) {
+      P[a][0] = tmp[a][0] / tmp[a][2];
+      P[a][1] = tmp[a][1] / tmp[a][2];
+      P[a][2] = 1.0 / tmp[a][2];
+    }
+    /* froxels outside the index range of the mapped polygon (one froxel of slack) cannot meet it */
+    double mn[3] = {P[0][0], P[0][1], P[0][2]}, mx[3] = {P[0][0], P[0][1], P[0][2]};
+    for (int a = 1; a < n; ++a)
+      for (int c = 0; c < 3; ++c) {
+        mn[c] = P[a][c] < mn[c] ? P[a][c] : mn[c];
+        mx[c] = P[a][c] > mx[c] ? P[a][c] : mx[c];
+      }
+#define CLAMPI(v, hi) ((int)((v) < 0.0 ? 0.0 : ((v) > (double)(hi) ? (double)(hi) : (v))))
+    const int i0 = CLAMPI(floor((mn[0] / tx + 1.0) * 0.5 * nx) - 1.0, nx - 1);
+    const int i1 = CLAMPI(floor((mx[0] / tx + 1.0) * 0.5 * nx) + 1.0, nx - 1);
+    const int j0 = CLAMPI(floor((mn[1] / ty + 1.0) * 0.5 * ny) - 1.0, ny - 1);
+    const int j1 = CLAMPI(floor((mx[1] / ty + 1.0) * 0.5 * ny) + 1.0, ny - 1);
+    const int k0 = CLAMPI(floor((1.0 / mx[2] - zn) / s) - 1.0, nz - 1);
+    const int k1 = CLAMPI(floor((1.0 / mn[2] - zn) / s) + 1.0, nz - 1);
+#undef CLAMPI
+    for (int k = k0; k <= k1; ++k) {
+      const double qlo = 1.0 / (zn + (k + 1) * s), qhi = 1.0 / (zn + k * s);
+      for (int j = j0; j <= j1; ++j) {
+        const double ylo = ty * (2.0 * j / ny - 1.0), yhi = ty * (2.0 * (j + 1) / ny - 1.0);
+        for (int i = i0; i <= i1; ++i) {
+          const double xlo = tx * (2.0 * i / nx - 1.0), xhi = tx * (2.0 * (i + 1) / nx - 1.0);
+          const double lo[3] = {xlo - margin * (xhi - xlo), ylo - margin * (yhi - ylo), qlo - margin * (qhi - qlo)};
+          const double hi[3] = {xhi + margin * (xhi - xlo), yhi + margin * (yhi - ylo), qhi + margin * (qhi - qlo)};
+          double A[16][3], B[16][3];
+          int m = n;
+          for (int a = 0; a < n; ++a) A[a][0] = P[a][0], A[a][1] = P[a][1], A[a][2] = P[a][2];
+          for (int ax = 0; ax < 3 && m > 0; ++ax) {
+            m = clip_poly(A, m, ax, lo[ax], 1, B);
+            if (m == 0) break;
+            m = clip_poly(B, m, ax, hi[ax], 0, A);
+          }
+          if (m > 0) {
+            uint8_t *w = occ + ((size_t)k * ny + j) * (nx / 8) + (i >> 3);
+            if (!(*w & (1u << (i & 7)))) ++marked;
+            *w |= (uint8_t)(1u << (i & 7));
+          }
+        }
+      }
+    }
+  }
+  return marked;
+}
