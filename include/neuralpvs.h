@@ -125,6 +125,36 @@ npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const 
 npvs_status npvs_interleave(const void *in, npvs_dims g, int32_t d, int32_t elem_bytes, void *out, void *stream);
 npvs_status npvs_deinterleave(const void *in, npvs_dims g, int32_t d, int32_t elem_bytes, void *out, void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * World-space front end (Sec. 3.2): the frustum F of a viewcell and the froxelization of
+ * world-space triangles into F's froxels with linear depth slices.
+ *
+ * npvs_viewcell_frustum (host): a camera at c looking along `forward` (up hint `up`, not parallel
+ *   to it) with vertical field of view fov_y radians and aspect ratio `aspect` may move
+ *   laterally by up to r and turn by up to beta; F has its apex r / tan(fov_y / 2) behind c on the
+ *   view axis and the field of view fov_y + 2 beta.  Writes the apex, the orthonormal basis
+ *   (right = up x forward, up, forward), the half-angle tangents and the depth range.
+ * npvs_froxelize_view: eye coordinates (x, y, z) = ((p - eye).right, (p - eye).up,
+ *   (p - eye).forward); froxel (i, j, k) of grid g is the closed set with z in
+ *   [z_near + k s, z_near + (k+1) s] (s = (z_far - z_near) / nz), x / z in
+ *   [tx (2i/nx - 1), tx (2(i+1)/nx - 1)], y / z likewise with ty; G = 1 iff a triangle meets it
+ *   (decided in float64: triangles clipped at z = z_near, mapped to (x/z, y/z, 1/z) where froxels
+ *   are boxes, separating-axis test).  tris (device) float32 [T][3][3] in world units; view
+ *   (host); occ_bits (device, 4-byte aligned) packed as the grid-space froxelization, fully
+ *   overwritten; nx a multiple of 32; triangles with a non-finite coordinate are ignored.
+ *   ws: npvs_froxelize_view_workspace_size(T) bytes.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+  double eye[3], right[3], up[3], forward[3];
+  double tan_half_x, tan_half_y;
+  double z_near, z_far;
+} npvs_view;
+npvs_status npvs_viewcell_frustum(const double *c, const double *forward, const double *up, double fov_y,
+                                  double aspect, double r, double beta, double z_near, double z_far, npvs_view *out);
+npvs_status npvs_froxelize_view_workspace_size(int64_t n_tris, size_t *bytes);
+npvs_status npvs_froxelize_view(const float *tris, int64_t n_tris, const npvs_view *view, npvs_dims g,
+                                uint8_t *occ_bits, void *ws, size_t ws_bytes, void *stream);
+
 /* Sparse interleave of a packed bit grid onto the active sites:
  *   X[r][c] = bit of froxel (bx d + ox, by d + oy, bz d + oz) of site r, as 0/1 in `dtype`
  *   (NPVS_F32, NPVS_BF16 or NPVS_U8).  X (device) [cap_sites][d^3]; rows >= n_sites untouched.

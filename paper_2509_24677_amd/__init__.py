@@ -22,7 +22,7 @@ from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  #
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
     "sparse_conv_fwd", "sparse_conv_bwd", "conv_bwd_begin", "sparse_conv_bwd_chain", "Levels", "build_levels",
-    "pack_weights_k", "strided_conv_fwd", "concat_channels", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
+    "pack_weights_k", "strided_conv_fwd", "concat_channels", "viewcell_frustum", "froxelize_view", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
     "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
 ]
 
@@ -362,6 +362,33 @@ def deinterleave_threshold(Y: torch.Tensor, rb: Rulebook, occ: torch.Tensor, wan
     L.call("npvs_deinterleave_threshold", _p(Y), _p(rb.block_row), _p(occ), len(rb.dims), L.dims_array(rb.dims),
            rb.d, _p(pvs), _p(logits), _stream())
     return pvs, logits
+
+
+# --------------------------------------------------------------------------------- world space
+def viewcell_frustum(c, forward, up, fov_y: float, aspect: float, r: float, beta: float, z_near: float,
+                     z_far: float) -> L.View:
+    """The frustum of a viewcell (npvs_viewcell_frustum): apex, basis, half-angle tangents, depth range."""
+    arr = lambda v: (ctypes.c_double * 3)(*[float(x) for x in v])
+    out = L.View()
+    L.call("npvs_viewcell_frustum", ctypes.cast(arr(c), ctypes.c_void_p), ctypes.cast(arr(forward), ctypes.c_void_p),
+           ctypes.cast(arr(up), ctypes.c_void_p), float(fov_y), float(aspect), float(r), float(beta), float(z_near),
+           float(z_far), ctypes.byref(out))
+    return out
+
+
+def froxelize_view(tris: torch.Tensor, view: L.View, dims) -> torch.Tensor:
+    """Packed occupancy uint8 [nz][ny][nx/8] of world-space triangles float32 [T][3][3] in the
+    froxels of `view` (linear depth slices)."""
+    nx, ny, nz = dims
+    T = tris.shape[0] if tris.numel() else 0
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_froxelize_view_workspace_size", T, ctypes.byref(nbytes))
+    dev = tris.device
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    occ = torch.empty(nz * ny * nx // 8, dtype=torch.uint8, device=dev)
+    L.call("npvs_froxelize_view", _p(tris.contiguous()) if T else None, T, ctypes.byref(view), L.Dims(nx, ny, nz),
+           _p(occ), _p(ws), nbytes.value, _stream())
+    return occ
 
 
 # --------------------------------------------------------------------------------- culling

@@ -47,8 +47,15 @@ class PackDesc(ctypes.Structure):
                 ("flip_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class View(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("right", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
+                ("forward", ctypes.c_double * 3), ("tan_half_x", ctypes.c_double), ("tan_half_y", ctypes.c_double),
+                ("z_near", ctypes.c_double), ("z_far", ctypes.c_double)]
+
+
 P = ctypes.c_void_p
 i32, i64, f32, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+f64 = ctypes.c_double
 PS = ctypes.POINTER(ctypes.c_size_t)
 PI64 = ctypes.POINTER(ctypes.c_int64)
 
@@ -82,6 +89,9 @@ SIGNATURES = {
     "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, P, P]),
     "npvs_strided_conv_fwd": (i32, [P, i32, P, P, i32, P, i32, P, i32, i32, i32, i32, P, P]),
     "npvs_concat_channels": (i32, [P, i32, P, i32, i32, P, i32, P, P]),
+    "npvs_viewcell_frustum": (i32, [P, P, P, f64, f64, f64, f64, f64, f64, P]),
+    "npvs_froxelize_view_workspace_size": (i32, [i64, PS]),
+    "npvs_froxelize_view": (i32, [P, i64, P, Dims, P, P, sz, P]),
     "npvs_visible_triangles": (i32, [P, PI64, i32, P, P, P, P]),
     "npvs_visible_objects": (i32, [P, P, i64, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),

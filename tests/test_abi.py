@@ -124,3 +124,31 @@ def test_unsupported_bf16_shape_reported(lib):
     p = ctypes.c_void_p(256)
     st = lib.npvs_sparse_conv_fwd(p, 12, p, None, 64, p, p, 10, L.NPVS_BF16, 1, 0, ctypes.c_void_p(512), None)
     assert st == L.NPVS_ERR_UNSUPPORTED
+
+
+def test_viewcell_frustum_matches_oracle_and_rejects_bad_cameras(lib):
+    import math
+
+    import numpy as np
+
+    import oracle
+    import paper_2509_24677_amd as npvs
+
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        c, f, u = rng.normal(size=3) * 10, rng.normal(size=3), rng.normal(size=3)
+        fov, asp, r, beta = rng.uniform(0.3, 1.5), rng.uniform(0.5, 2), rng.uniform(0, 1), rng.uniform(0, 0.4)
+        v = npvs.viewcell_frustum(c, f, u, fov, asp, r, beta, 0.3, 1000.0)
+        w = oracle.viewcell_view(c, f, u, fov, asp, r, beta, 0.3, 1000.0)
+        for key, wk in (("eye", "eye"), ("right", "right"), ("up", "up"), ("forward", "fwd")):
+            np.testing.assert_allclose(list(getattr(v, key)), w[wk], rtol=0, atol=1e-12)
+        assert v.tan_half_x == pytest.approx(w["tx"], rel=1e-14) and v.tan_half_y == pytest.approx(w["ty"], rel=1e-14)
+    arr = lambda x: (ctypes.c_double * 3)(*x)
+    out = L.View()
+    p = lambda x: ctypes.cast(arr(x), ctypes.c_void_p)
+    st = lib.npvs_viewcell_frustum(p([0, 0, 0]), p([0, 0, 1]), p([0, 0, 2]), math.pi / 3, 1.0, 0.6, 0.2, 0.3, 100.0,
+                                   ctypes.byref(out))
+    assert st == L.NPVS_ERR_INVALID_ARG and b"parallel" in lib.npvs_last_error()
+    st = lib.npvs_viewcell_frustum(p([0, 0, 0]), p([0, 0, 1]), p([0, 1, 0]), math.pi / 3, 1.0, 0.6, 0.2, 100.0, 50.0,
+                                   ctypes.byref(out))
+    assert st == L.NPVS_ERR_INVALID_ARG
