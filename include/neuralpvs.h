@@ -139,9 +139,11 @@ npvs_status npvs_deinterleave(const void *in, npvs_dims g, int32_t d, int32_t el
  *   [z_near + k s, z_near + (k+1) s] (s = (z_far - z_near) / nz), x / z in
  *   [tx (2i/nx - 1), tx (2(i+1)/nx - 1)], y / z likewise with ty; G = 1 iff a triangle meets it
  *   (decided in float64: triangles clipped at z = z_near, mapped to (x/z, y/z, 1/z) where froxels
- *   are boxes, separating-axis test).  tris (device) float32 [T][3][3] in world units; view
- *   (host); occ_bits (device, 4-byte aligned) packed as the grid-space froxelization, fully
- *   overwritten; nx a multiple of 32; triangles with a non-finite coordinate are ignored.
+ *   are boxes; each row (j, k) of froxels is the slab y/z in its Y interval, 1/z in its Q
+ *   interval, and the triangle's polygon clipped to that slab marks the froxels its X extent
+ *   meets).  tris (device) float32 [T][3][3] in world units; view (host); occ_bits (device,
+ *   4-byte aligned) packed as the grid-space froxelization, fully overwritten; nx a multiple of
+ *   32; triangles with a non-finite coordinate are ignored.
  *   ws: npvs_froxelize_view_workspace_size(T) bytes.
  * ------------------------------------------------------------------------------------------- */
 typedef struct {

@@ -6,14 +6,15 @@
 // (i, j, k) of an nx x ny x nz grid is the closed set with z in [zn + k s, zn + (k+1) s]
 // (s = (zf - zn) / nz), x / z in [tx (2i/nx - 1), tx (2(i+1)/nx - 1)] and y / z likewise with ty.
 // The map (X, Y, Q) = (x/z, y/z, 1/z) is projective on z > 0: a triangle clipped to z >= zn maps
-// to a convex polygon and every froxel to an axis-aligned box, so G(i, j, k) = 1 iff a fan
-// triangle of that polygon and the box pass the separating-axis test (box normals, triangle
-// normal, and the nine products of triangle edges with the box axes; touching counts).  All
-// geometry is in float64 on the device.
+// to a convex polygon and every froxel to an axis-aligned box.  The froxels of row (j, k) form
+// the slab Y in [Y_j, Y_j+1], Q in [Q_k+1, Q_k] cut at the X boundaries, so the froxels the
+// polygon meets in that row are exactly those whose closed X interval meets the X extent of the
+// polygon clipped to the slab.  All geometry is in float64 on the device.
 //
 // Three launches: one thread per triangle (transform, near clip, map, froxel index box, number
-// of (j, k) rows), one 1024-thread workgroup that scans the row counts, and one thread per
-// (triangle, row) that tests the row's froxels and ORs whole 32-froxel words into the grid.
+// of (j, k) rows, and each workgroup's total), a scan of the row counts (each workgroup adds the
+// totals before it), and one thread per (triangle, row) that clips the polygon to its slab and
+// ORs the covered 32-froxel words.
 #include <cmath>
 
 #include "npvs_common.hpp"
@@ -36,10 +37,14 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) { retur
 
 __device__ __forceinline__ int clampi(double v, int hi) { return (int)(v < 0.0 ? 0.0 : (v > (double)hi ? (double)hi : v)); }
 
+// One thread per triangle (grid ceil(T / 256)); each workgroup also writes its rows' total.
 __global__ __launch_bounds__(256) void world_setup_kernel(const float *__restrict__ tris, int64_t T, ViewK V, int nx,
                                                           int ny, int nz, WorldTri *__restrict__ rec,
-                                                          int32_t *__restrict__ rows) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (int64_t)gridDim.x * blockDim.x) {
+                                                          int32_t *__restrict__ rows, int64_t *__restrict__ wg_rows) {
+  __shared__ int64_t red[256];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t my_rows = 0;
+  if (t < T) {
     double e[3][3];
     bool finite = true;
     for (int v = 0; v < 3; ++v) {
@@ -79,11 +84,12 @@ __global__ __launch_bounds__(256) void world_setup_kernel(const float *__restric
             mx[c] = fmax(mx[c], R.P[a][c]);
           }
         }
-        // froxel index box with one froxel of slack; boxes wholly outside the grid are dropped
+        // froxel index box: froxel n spans [n, n + 1] in grid units and meets [a, b] iff
+        // ceil(a) - 1 <= n <= floor(b) (closed); boxes wholly outside the grid are dropped
         const double s = (V.zf - V.zn) / nz;
-        const double fi0 = floor((mn[0] / V.tx + 1.0) * 0.5 * nx) - 1.0, fi1 = floor((mx[0] / V.tx + 1.0) * 0.5 * nx) + 1.0;
-        const double fj0 = floor((mn[1] / V.ty + 1.0) * 0.5 * ny) - 1.0, fj1 = floor((mx[1] / V.ty + 1.0) * 0.5 * ny) + 1.0;
-        const double fk0 = floor((1.0 / mx[2] - V.zn) / s) - 1.0, fk1 = floor((1.0 / mn[2] - V.zn) / s) + 1.0;
+        const double fi0 = ceil((mn[0] / V.tx + 1.0) * 0.5 * nx) - 1.0, fi1 = floor((mx[0] / V.tx + 1.0) * 0.5 * nx);
+        const double fj0 = ceil((mn[1] / V.ty + 1.0) * 0.5 * ny) - 1.0, fj1 = floor((mx[1] / V.ty + 1.0) * 0.5 * ny);
+        const double fk0 = ceil((1.0 / mx[2] - V.zn) / s) - 1.0, fk1 = floor((1.0 / mn[2] - V.zn) / s);
         if (fi1 >= 0.0 && fi0 <= nx - 1 && fj1 >= 0.0 && fj0 <= ny - 1 && fk1 >= 0.0 && fk0 <= nz - 1) {
           R.n = n;
           R.i0 = clampi(fi0, nx - 1), R.i1 = clampi(fi1, nx - 1);
@@ -93,61 +99,113 @@ __global__ __launch_bounds__(256) void world_setup_kernel(const float *__restric
       }
     }
     rec[t] = R;
-    rows[t] = R.n ? (R.j1 - R.j0 + 1) * (R.k1 - R.k0 + 1) : 0;
+    my_rows = R.n ? (int64_t)(R.j1 - R.j0 + 1) * (R.k1 - R.k0 + 1) : 0;
+    rows[t] = (int32_t)my_rows;
   }
-}
-
-// Exclusive scan of rows[0, T) into off[0, T]; off[T] = total.  One workgroup of 1024 threads,
-// each owning a contiguous run.
-__global__ __launch_bounds__(1024) void world_scan_kernel(const int32_t *__restrict__ rows, int64_t T,
-                                                          int64_t *__restrict__ off) {
-  __shared__ int64_t part[1024];
-  const int tid = threadIdx.x;
-  const int64_t per = (T + 1023) / 1024, a = tid * per, b = a + per < T ? a + per : T;
-  int64_t sum = 0;
-  for (int64_t t = a; t < b; ++t) sum += rows[t];
-  part[tid] = sum;
+  red[threadIdx.x] = my_rows;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
-    const int64_t v = tid >= d ? part[tid - d] : 0;
-    __syncthreads();
-    part[tid] += v;
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  int64_t run = part[tid] - sum;
-  for (int64_t t = a; t < b; ++t) {
-    off[t] = run;
-    run += rows[t];
-  }
-  if (tid == 1023) off[T] = part[1023];
+  if (threadIdx.x == 0) wg_rows[blockIdx.x] = red[0];
 }
 
-// Closed triangle (vertices relative to the box centre) against the box of half sizes h.
-__device__ bool tri_box_sat(const double (&v)[3][3], const double (&h)[3]) {
-  for (int a = 0; a < 3; ++a) {
-    const double lo = fmin(v[0][a], fmin(v[1][a], v[2][a])), hi = fmax(v[0][a], fmax(v[1][a], v[2][a]));
-    if (lo > h[a] || hi < -h[a]) return false;
+// Exclusive scan of rows[0, T) into off[0, T] (off[T] = total), one workgroup per 256 triangles:
+// the workgroup adds the totals of the workgroups before it, then scans its own counts.
+__global__ __launch_bounds__(256) void world_scan_kernel(const int32_t *__restrict__ rows,
+                                                         const int64_t *__restrict__ wg_rows, int64_t T,
+                                                         int64_t *__restrict__ off) {
+  __shared__ int64_t sh[256];
+  const int tid = threadIdx.x;
+  int64_t carry = 0;
+  for (int i = tid; i < (int)blockIdx.x; i += 256) carry += wg_rows[i];
+  sh[tid] = carry;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
   }
-  double ed[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) ed[a][c] = v[(a + 1) % 3][c] - v[a][c];
-  const double nrm[3] = {ed[0][1] * ed[1][2] - ed[0][2] * ed[1][1], ed[0][2] * ed[1][0] - ed[0][0] * ed[1][2],
-                         ed[0][0] * ed[1][1] - ed[0][1] * ed[1][0]};
-  const double dn = dot3(nrm, v[0]);
-  if (fabs(dn) > h[0] * fabs(nrm[0]) + h[1] * fabs(nrm[1]) + h[2] * fabs(nrm[2])) return false;
-  for (int a = 0; a < 3; ++a)
-    for (int u = 0; u < 3; ++u) {
-      // axis = edge a x unit u
-      double ax[3] = {0.0, 0.0, 0.0};
-      const int u1 = (u + 1) % 3, u2 = (u + 2) % 3;
-      ax[u1] = ed[a][u2];
-      ax[u2] = -ed[a][u1];
-      const double p0 = dot3(ax, v[0]), p1 = dot3(ax, v[1]), p2 = dot3(ax, v[2]);
-      const double r = h[0] * fabs(ax[0]) + h[1] * fabs(ax[1]) + h[2] * fabs(ax[2]);
-      if (fmin(p0, fmin(p1, p2)) > r || fmax(p0, fmax(p1, p2)) < -r) return false;
-    }
-  return true;
+  carry = sh[0];
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t v = t < T ? rows[t] : 0;
+  sh[tid] = v;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int64_t u = tid >= d ? sh[tid - d] : 0;
+    __syncthreads();
+    sh[tid] += u;
+    __syncthreads();
+  }
+  if (t < T) off[t] = carry + sh[tid] - v;
+  if (t == T - 1) off[T] = carry + sh[tid];
 }
+
+// Streaming Sutherland-Hodgman clip of a convex polygon by four planes (the row's slab), each
+// stage keeping only its first and previous vertex and passing what it emits to the next stage;
+// the last stage records the X extent.  No vertex arrays, so everything stays in registers.
+struct V3 {
+  double x, y, z;
+};
+
+struct ClipStage {
+  V3 f, p;
+  bool has;
+};
+
+struct SlabClip {  // stages 0, 1 cut Y at b0 (keep above) and b1 (keep below); 2, 3 cut Q likewise
+  ClipStage s0, s1, s2, s3;
+  double b0, b1, b2, b3;
+  double xmin, xmax;
+
+  template <int S>
+  __device__ __forceinline__ ClipStage &stage() {
+    if constexpr (S == 0) return s0;
+    else if constexpr (S == 1) return s1;
+    else if constexpr (S == 2) return s2;
+    else return s3;
+  }
+  template <int S>
+  __device__ __forceinline__ double side(V3 v) const {
+    if constexpr (S == 0) return v.y - b0;
+    else if constexpr (S == 1) return b1 - v.y;
+    else if constexpr (S == 2) return v.z - b2;
+    else return b3 - v.z;
+  }
+  template <int S>
+  __device__ __forceinline__ void edge(V3 P, V3 Q) {  // stage S edge P -> Q
+    const double dp = side<S>(P), dq = side<S>(Q);
+    if ((dp >= 0.0) != (dq >= 0.0)) {
+      const double u = dp / (dp - dq);
+      push<S + 1>(V3{P.x + u * (Q.x - P.x), P.y + u * (Q.y - P.y), P.z + u * (Q.z - P.z)});
+    }
+    if (dq >= 0.0) push<S + 1>(Q);
+  }
+  template <int S>
+  __device__ __forceinline__ void push(V3 v) {
+    if constexpr (S == 4) {
+      xmin = fmin(xmin, v.x);
+      xmax = fmax(xmax, v.x);
+    } else {
+      ClipStage &c = stage<S>();
+      if (!c.has) {
+        c.has = true;
+        c.f = v;
+      } else {
+        edge<S>(c.p, v);
+      }
+      c.p = v;
+    }
+  }
+  template <int S>
+  __device__ __forceinline__ void finish() {  // close stage S's polygon, then the next stage's
+    if constexpr (S < 4) {
+      if (stage<S>().has) edge<S>(stage<S>().p, stage<S>().f);
+      finish<S + 1>();
+    }
+  }
+};
 
 __global__ __launch_bounds__(256) void world_rows_kernel(const WorldTri *__restrict__ rec, const int64_t *__restrict__ off,
                                                          int64_t T, ViewK V, int nx, int ny, int nz,
@@ -165,33 +223,32 @@ __global__ __launch_bounds__(256) void world_rows_kernel(const WorldTri *__restr
     const int64_t r = it - off[lo];
     const int nj = R.j1 - R.j0 + 1;
     const int j = R.j0 + (int)(r % nj), k = R.k0 + (int)(r / nj);
-    const double y0 = V.ty * (2.0 * j / ny - 1.0), y1 = V.ty * (2.0 * (j + 1) / ny - 1.0);
-    const double q0 = 1.0 / (V.zn + (k + 1) * s), q1 = 1.0 / (V.zn + k * s);
-    uint32_t word = 0;
-    int wcur = R.i0 >> 5;
+    SlabClip C;
+    C.s0.has = C.s1.has = C.s2.has = C.s3.has = false;
+    C.b0 = V.ty * (2.0 * j / ny - 1.0);
+    C.b1 = V.ty * (2.0 * (j + 1) / ny - 1.0);
+    C.b2 = 1.0 / (V.zn + (k + 1) * s);
+    C.b3 = 1.0 / (V.zn + k * s);
+    C.xmin = 1e300, C.xmax = -1e300;
+    C.push<0>(V3{R.P[0][0], R.P[0][1], R.P[0][2]});
+    C.push<0>(V3{R.P[1][0], R.P[1][1], R.P[1][2]});
+    C.push<0>(V3{R.P[2][0], R.P[2][1], R.P[2][2]});
+    if (R.n > 3) C.push<0>(V3{R.P[3][0], R.P[3][1], R.P[3][2]});
+    C.finish<0>();
+    if (C.xmin > C.xmax) continue;  // nothing of the polygon in this row's slab
+    const double xmin = C.xmin, xmax = C.xmax;
+    // froxel i spans [i, i + 1] in u = (X / tx + 1) nx / 2 and meets [umin, umax] iff
+    // ceil(umin) - 1 <= i <= floor(umax)
+    const double umin = (xmin / V.tx + 1.0) * 0.5 * nx, umax = (xmax / V.tx + 1.0) * 0.5 * nx;
+    const double fa = ceil(umin) - 1.0, fb = floor(umax);
+    if (fb < 0.0 || fa > nx - 1) continue;
+    const int ia = fa < 0.0 ? 0 : (int)fa, ib = fb > nx - 1 ? nx - 1 : (int)fb;
     uint32_t *row = occ_words + ((int64_t)k * ny + j) * (nx >> 5);
-    for (int i = R.i0; i <= R.i1; ++i) {
-      if ((i >> 5) != wcur) {
-        if (word) atomicOr(row + wcur, word);
-        word = 0;
-        wcur = i >> 5;
-      }
-      const double x0 = V.tx * (2.0 * i / nx - 1.0), x1 = V.tx * (2.0 * (i + 1) / nx - 1.0);
-      const double c[3] = {0.5 * (x0 + x1), 0.5 * (y0 + y1), 0.5 * (q0 + q1)};
-      const double h[3] = {0.5 * (x1 - x0), 0.5 * (y1 - y0), 0.5 * (q1 - q0)};
-      bool hit = false;
-      for (int f = 1; f + 1 < R.n && !hit; ++f) {
-        double v[3][3];
-        for (int cc = 0; cc < 3; ++cc) {
-          v[0][cc] = R.P[0][cc] - c[cc];
-          v[1][cc] = R.P[f][cc] - c[cc];
-          v[2][cc] = R.P[f + 1][cc] - c[cc];
-        }
-        hit = tri_box_sat(v, h);
-      }
-      if (hit) word |= 1u << (i & 31);
+    for (int w = ia >> 5; w <= (ib >> 5); ++w) {
+      const int b0 = ia > 32 * w ? ia - 32 * w : 0, b1 = ib < 32 * w + 31 ? ib - 32 * w : 31;
+      const uint32_t mask = (b1 == 31 ? ~0u : ((1u << (b1 + 1)) - 1u)) & ~((1u << b0) - 1u);
+      atomicOr(row + w, mask);
     }
-    if (word) atomicOr(row + wcur, word);
   }
 }
 
@@ -201,7 +258,7 @@ __global__ void world_zero_kernel(uint32_t *__restrict__ w, int64_t n) {
 
 static size_t align256w(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static void world_ws_layout(int64_t T, size_t *o_rec, size_t *o_rows, size_t *o_off, size_t *bytes) {
+static void world_ws_layout(int64_t T, size_t *o_rec, size_t *o_rows, size_t *o_off, size_t *o_wg, size_t *bytes) {
   size_t o = 0;
   *o_rec = o;
   o += align256w(sizeof(WorldTri) * (size_t)(T > 0 ? T : 1));
@@ -209,6 +266,8 @@ static void world_ws_layout(int64_t T, size_t *o_rec, size_t *o_rows, size_t *o_
   o += align256w(sizeof(int32_t) * (size_t)(T > 0 ? T : 1));
   *o_off = o;
   o += align256w(sizeof(int64_t) * (size_t)(T + 1));
+  *o_wg = o;
+  o += align256w(sizeof(int64_t) * (size_t)((T + 255) / 256 + 1));
   *bytes = o;
 }
 
@@ -250,8 +309,8 @@ extern "C" npvs_status npvs_viewcell_frustum(const double *c, const double *forw
 
 extern "C" npvs_status npvs_froxelize_view_workspace_size(int64_t n_tris, size_t *bytes) {
   if (!bytes || n_tris < 0) return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize_view_workspace_size: bad arguments");
-  size_t a, b, c;
-  world_ws_layout(n_tris, &a, &b, &c, bytes);
+  size_t a, b, c, d;
+  world_ws_layout(n_tris, &a, &b, &c, &d, bytes);
   return NPVS_OK;
 }
 
@@ -265,13 +324,14 @@ extern "C" npvs_status npvs_froxelize_view(const float *tris, int64_t n_tris, co
     return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize_view: occ_bits must be 4-byte aligned");
   if (!(view->z_near > 0.0) || !(view->z_far > view->z_near) || !(view->tan_half_x > 0.0) || !(view->tan_half_y > 0.0))
     return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize_view: bad view");
-  size_t o_rec, o_rows, o_off, need;
-  world_ws_layout(n_tris, &o_rec, &o_rows, &o_off, &need);
+  size_t o_rec, o_rows, o_off, o_wg, need;
+  world_ws_layout(n_tris, &o_rec, &o_rows, &o_off, &o_wg, &need);
   if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize_view: workspace too small");
   char *w = static_cast<char *>(ws);
   WorldTri *rec = reinterpret_cast<WorldTri *>(w + o_rec);
   int32_t *rows = reinterpret_cast<int32_t *>(w + o_rows);
   int64_t *off = reinterpret_cast<int64_t *>(w + o_off);
+  int64_t *wg_rows = reinterpret_cast<int64_t *>(w + o_wg);
   ViewK V;
   for (int i = 0; i < 3; ++i) {
     V.eye[i] = view->eye[i];
@@ -284,8 +344,9 @@ extern "C" npvs_status npvs_froxelize_view(const float *tris, int64_t n_tris, co
   const int64_t words = (int64_t)g.nz * g.ny * (g.nx / 32);
   world_zero_kernel<<<stride_grid(words, 256, 4096), 256, 0, s>>>(reinterpret_cast<uint32_t *>(occ_bits), words);
   if (n_tris > 0) {
-    world_setup_kernel<<<stride_grid(n_tris, 256, 4096), 256, 0, s>>>(tris, n_tris, V, g.nx, g.ny, g.nz, rec, rows);
-    world_scan_kernel<<<1, 1024, 0, s>>>(rows, n_tris, off);
+    const int nwg = (int)((n_tris + 255) / 256);
+    world_setup_kernel<<<nwg, 256, 0, s>>>(tris, n_tris, V, g.nx, g.ny, g.nz, rec, rows, wg_rows);
+    world_scan_kernel<<<nwg, 256, 0, s>>>(rows, wg_rows, n_tris, off);
     world_rows_kernel<<<4096, 256, 0, s>>>(rec, off, n_tris, V, g.nx, g.ny, g.nz,
                                           reinterpret_cast<uint32_t *>(occ_bits));
   }

@@ -1,8 +1,9 @@
 """GPU parity of the world-space front end (viewcell frustum, froxelization into linear depth
 slices) against the oracle, through the C ABI.  Both sides decide in float64 but do different
-arithmetic (the oracle clips polygons, the kernels use the separating-axis test), so the GPU grid
-must contain every froxel the oracle marks with the froxels shrunk by 1e-9 of their size, and no
-froxel the oracle rejects with them grown by 1e-9; in practice it equals the oracle's grid."""
+arithmetic (the oracle clips the polygon against every froxel, the kernels clip it once per row
+of froxels and read the covered run off its X extent), so the GPU grid must contain every froxel
+the oracle marks with the froxels shrunk by 1e-9 of their size, and no froxel the oracle rejects
+with them grown by 1e-9; in practice it equals the oracle's grid."""
 import math
 
 import numpy as np
