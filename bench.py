@@ -280,6 +280,64 @@ def bench_unet(args, dev, timed_launches):
     return r
 
 
+def bench_world(args, dev, timed_launches):
+    """The city frame in world space: froxelization into the viewcell frustum of the paper's camera
+    (60 degree field of view widened by 2 x 15 degrees, near 0.3, far 1000, 256^3 froxels, linear
+    depth slices), timed launch by launch, and the whole pass world triangles -> PVS through the
+    BF16 network of the benchmark (d = 4, six 64-channel layers) captured as one graph."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+    from paper_2509_24677_amd.train import Network
+
+    cfg = synth.config("city256")
+    t = synth.scene_for(cfg)
+    tris = torch.from_numpy(t).to(dev)
+    view = npvs.viewcell_frustum([128.0, 40.0, -20.0], [0.0, 0.0, 1.0], [0.0, 1.0, 0.0], math.pi / 3, 1.0, 0.6,
+                                 math.pi / 12, 0.3, 1000.0)
+    dims = (256, 256, 256)
+    occ = npvs.froxelize_view(tris, view, dims)
+    r = {"grid": list(dims), "scene_triangles": len(t),
+         "occupied": int(np.unpackbits(occ.cpu().numpy()).sum())}
+    r["froxelize_ms"] = float(np.median(timed_launches(lambda: npvs.froxelize_view(tris, view, dims), 20)))
+    net = Network(synth.net_layers(cfg), cfg.d, npvs.NPVS_BF16)
+
+    def frame():
+        o = npvs.froxelize_view(tris, view, dims)
+        rb = npvs.build_rulebook(o, [dims], cfg.d)
+        logits, _ = net.forward(npvs.gather_input(o, rb, npvs.NPVS_BF16), rb)
+        return npvs.deinterleave_threshold(logits, rb, o)[0]
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            frame()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        frame()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    rb = npvs.build_rulebook(occ, [dims], cfg.d)
+    r.update(bf16_fwd_ms=ms, bf16_fwd_frames_per_s=1000.0 / ms, n_sites=rb.host_counts()["n_sites"])
+    return r
+
+
 def bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs):
     """Culling against the city's BF16 PVS: every scene triangle (npvs_visible_triangles), and 2048
     box-shaped temporal bounding volumes of 10 triangles each as objects (npvs_visible_objects)."""
@@ -598,6 +656,8 @@ def main():
     print("# culling " + json.dumps(cull), file=sys.stderr, flush=True)
     unet = bench_unet(args, dev, timed_launches)
     print("# two-level U-Net " + json.dumps(unet), file=sys.stderr, flush=True)
+    world = bench_world(args, dev, timed_launches)
+    print("# world space " + json.dumps(world), file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------------ accuracy
     torch.cuda.synchronize()
@@ -663,6 +723,7 @@ def main():
         "interleave_8_16": wide,
         "culling": cull,
         "unet": unet,
+        "world_space": world,
         "accuracy": acc,
     }
     print(json.dumps(line))
