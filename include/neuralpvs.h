@@ -197,7 +197,7 @@ npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int3
  * out_f32 = 1 (the logits of the last layer).
  *   X (device) [cap_sites][cin]; Wp packed weights; bias (device, nullable) float32 [cout];
  *   nbr, counts from npvs_build_rulebook; Y (device) [cap_sites][cout], rows >= n_sites untouched.
- * BF16 requires cin % 8 == 0, cin <= 512, cout % 8 == 0, cout <= 64.
+ * BF16 requires cin % 8 == 0 and cout % 8 == 0 (NPVS_ERR_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------------------------- */
 npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                  const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
@@ -239,6 +239,10 @@ npvs_status npvs_sparse_conv_fwd_ws(const void *X, int32_t cin, const void *Wp, 
  *   flip_transpose = 1); rb_off/rb_pairs: CSR rulebook.  dX is float32 [cap][cin].
  *   Reductions are deterministic (fixed order, compensated float32 sums).
  *   ws (device) workspace of npvs_conv_bwd_workspace_size() bytes.
+ *   Any channel counts (BF16: multiples of 8, NPVS_ERR_UNSUPPORTED otherwise), e.g. the 512- and
+ *   4096-channel first and last layers of interleave factors 8 and 16: dW is computed in windows
+ *   of 64 x 64 channels, and the data gradient of a BF16 layer with 1024+ outputs splits its input
+ *   channels over several workgroups (the workspace size covers it).
  * ------------------------------------------------------------------------------------------- */
 npvs_status npvs_conv_bwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
 npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,

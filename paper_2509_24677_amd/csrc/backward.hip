@@ -31,11 +31,11 @@ __device__ __forceinline__ float load_as_f32(const uint16_t *p, int64_t i) { ret
 constexpr int kDbBlocks = 256;  // row blocks of the bias-gradient partial sums (one layer)
 
 // dZ in float32 (for wgrad; nullable) and, for the BF16 path, a bfloat16 copy (MFMA operand),
-// plus the bias-gradient partial of this block's rows: one block per partial row, 256 threads,
-// C <= 64.  With vec
-// (C % 4 == 0 and 16-byte aligned rows) a thread owns 4 adjacent columns, else one; the threads of
-// a row group cover one row, the row groups stride over the block's rows and are combined in LDS
-// in a fixed order.
+// plus the bias-gradient partial of this block's rows: blockIdx.x = partial row, blockIdx.y = a
+// window of 64 columns (one window when C <= 64), 256 threads.  With vec (C % 4 == 0 and 16-byte
+// aligned rows) a thread owns 4 adjacent columns, else one; the threads of a row group cover the
+// window of one row, the row groups stride over the block's rows and are combined in LDS in a
+// fixed order.
 __device__ __forceinline__ void load4(const float *p, int64_t e, float *v) {
   const f32x4_t x = *reinterpret_cast<const f32x4_t *>(p + e);
   v[0] = x[0], v[1] = x[1], v[2] = x[2], v[3] = x[3];
@@ -54,13 +54,14 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
   __shared__ float red[256 * 4];
   const int64_t n = counts->n_sites;
   const int64_t r0 = n * blockIdx.x / gridDim.x, r1 = n * (blockIdx.x + 1) / gridDim.x;
-  const int V = vec ? 4 : 1, TPR = C / V, RG = 256 / TPR;
+  const int c0 = 64 * blockIdx.y, Cw = C - c0 < 64 ? C - c0 : 64;
+  const int V = vec ? 4 : 1, TPR = Cw / V, RG = 256 / TPR;
   const int cg = threadIdx.x % TPR, rg = threadIdx.x / TPR;
   Comp a[4] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
   if (rg < RG) {
     if (vec) {
       for (int64_t r = r0 + rg; r < r1; r += RG) {
-        const int64_t e = r * C + 4 * cg;
+        const int64_t e = r * C + c0 + 4 * cg;
         float g[4], y[4];
         load4(dY, e, g);
         if (relu) {
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
       }
     } else {
       for (int64_t r = r0 + rg; r < r1; r += RG) {
-        const int64_t e = r * C + cg;
+        const int64_t e = r * C + c0 + cg;
         float g = dY[e];
         if (relu && !(load_as_f32(Y, e) > 0.0f)) g = 0.0f;
         if (dZ32) dZ32[e] = g;
@@ -96,19 +97,29 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[threadIdx.x * 4 + i] = a[i].value();
   __syncthreads();
-  if (threadIdx.x < C) {
+  if (threadIdx.x < Cw) {
     const int c = threadIdx.x, g0 = c / V, comp = c % V;
     Comp t{0.0f, 0.0f};
     for (int g = 0; g < RG; ++g) t.add(red[(g * TPR + g0) * 4 + comp]);
-    dbpart[blockIdx.x * C + c] = t.value();
+    dbpart[(int64_t)blockIdx.x * C + c0 + c] = t.value();
   }
 }
 
-constexpr int kWgSlices = 16;  // slices of each offset's pair list
+constexpr int kWgSlices = 16;  // slices of each offset's pair list (at most; fewer for wide layers)
+constexpr size_t kWgPartBudget = size_t(8) << 20;  // bytes of float32 slice partials aimed at
+
+// Slices per offset: 16 while the float32 partials of every slice stay within the budget (every
+// layer of at most 64 x 64 channels), fewer for wider layers, at least one.
+static int wg_slices(int cin, int cout) {
+  const size_t per = sizeof(float) * 27 * (size_t)cin * cout;
+  const size_t s = kWgPartBudget / per;
+  return s < 1 ? 1 : s > (size_t)kWgSlices ? kWgSlices : (int)s;
+}
 constexpr int kWgPairs = 32;   // pairs staged per step (vector path)
 constexpr int kWgEPT = 16;     // dW entries per thread per pass (vector path)
 
-// Vector FP32 path: grid (kWgSlices, 27), 256 threads.  Partial dW of offset k over slice s.
+// Vector FP32 path: grid (S slices, 27, output windows of 64 channels), 256 threads.  Partial dW
+// of offset k over slice s for the outputs o0 .. o0 + 63.
 template <typename T>
 __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict__ X, int cin,
                                                              const float *__restrict__ dZ, int cout,
@@ -118,13 +129,14 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
   __shared__ float Xs[kWgPairs][65];
   __shared__ float Gs[kWgPairs][64];
   __shared__ int in_s[kWgPairs], out_s[kWgPairs];
-  const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x;
+  const int k = blockIdx.y, s = blockIdx.x, S = gridDim.x, tid = threadIdx.x;
+  const int o0 = 64 * blockIdx.z, ow = cout - o0 < 64 ? cout - o0 : 64;
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
-  const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
-  const int cw = (256 * kWgEPT) / cout < 64 ? (256 * kWgEPT) / cout : 64;  // channels of X per pass
+  const int64_t p0 = pk0 + pk * s / S, p1 = pk0 + pk * (s + 1) / S;
+  const int cw = (256 * kWgEPT) / ow < 64 ? (256 * kWgEPT) / ow : 64;  // channels of X per pass
   for (int cbase = 0; cbase < cin; cbase += cw) {
     const int cn = cin - cbase < cw ? cin - cbase : cw;
-    const int e_pass = cn * cout;
+    const int e_pass = cn * ow;
     Comp acc[kWgEPT];
 #pragma unroll
     for (int j = 0; j < kWgEPT; ++j) acc[j] = Comp{0.0f, 0.0f};
@@ -139,14 +151,14 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
       for (int e = tid; e < kWgPairs * 64; e += 256) {
         int p = e >> 6, c = e & 63;
         Xs[p][c] = (p < m && c < cn) ? load_as_f32(X, (int64_t)in_s[p] * cin + cbase + c) : 0.0f;
-        Gs[p][c] = (p < m && c < cout) ? dZ[(int64_t)out_s[p] * cout + c] : 0.0f;
+        Gs[p][c] = (p < m && c < ow) ? dZ[(int64_t)out_s[p] * cout + o0 + c] : 0.0f;
       }
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < kWgEPT; ++j) {
         const int e = tid + 256 * j;
         if (e < e_pass) {
-          const int c = e / cout, o = e % cout;
+          const int c = e / ow, o = e % ow;
           float t = 0.0f;
           for (int p = 0; p < m; ++p) t = fmaf(Xs[p][c], Gs[p][o], t);
           acc[j].add(t);
@@ -157,14 +169,16 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
     for (int j = 0; j < kWgEPT; ++j) {
       const int e = tid + 256 * j;
       if (e < e_pass) {
-        const int c = e / cout, o = e % cout;
-        part[((int64_t)(k * kWgSlices + s) * cin + cbase + c) * cout + o] = acc[j].value();
+        const int c = e / ow, o = e % ow;
+        part[((int64_t)(k * S + s) * cin + cbase + c) * cout + o0 + o] = acc[j].value();
       }
     }
   }
 }
 
-// BF16 path on MFMA.  grid (kWgSlices, 27), 256 threads = 4 waves; cin, cout <= 64.
+// BF16 path on MFMA.  grid (S slices, 27, windows), 256 threads = 4 waves; a workgroup computes
+// the window of at most 64 x 64 entries (input channels c0 .., outputs o0 ..) that blockIdx.z
+// selects (one window when cin, cout <= 64).
 // dW_k[c][o] = sum_p X[in_p][c] dZ[out_p][o] is a [cin x P] x [P x cout] product with the pair
 // index as the contraction.  128 pairs at a time are staged into LDS transposed (channel-major,
 // XT[c][p], GT[o][p]) so that both MFMA operands of v_mfma_f32_16x16x32_bf16 are one 16-byte
@@ -240,12 +254,17 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
   // other one, so one barrier per chunk orders both
   __shared__ __attribute__((aligned(16))) uint16_t XT[2][64 * kWgPitch];
   __shared__ __attribute__((aligned(16))) uint16_t GT[2][64 * kWgPitch];
-  const int k = blockIdx.y, s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int k = blockIdx.y, s = blockIdx.x, S = gridDim.x, tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
+  const int otiles = (cout + 63) / 64;
+  const int c0 = 64 * (blockIdx.z / otiles), o0 = 64 * (blockIdx.z % otiles);
+  const int cw = cin - c0 < 64 ? cin - c0 : 64, ow = cout - o0 < 64 ? cout - o0 : 64;  // window size
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
-  const int64_t p0 = pk0 + pk * s / kWgSlices, p1 = pk0 + pk * (s + 1) / kWgSlices;
-  const int CB = (cin + 15) / 16, OB = (cout + 15) / 16, nblk = CB * OB;
-  const int cin8 = (cin + 7) / 8, cout8 = (cout + 7) / 8;
+  const int64_t p0 = pk0 + pk * s / S, p1 = pk0 + pk * (s + 1) / S;
+  const int CB = (cw + 15) / 16, OB = (ow + 15) / 16, nblk = CB * OB;
+  const int cin8 = (cw + 7) / 8, cout8 = (ow + 7) / 8;
+  // rows are read from the window's first channel on; the row pitch stays cin / cout
+  const uint16_t *Xw = X + c0, *Gw = dZ16 + o0;
   // tasks of X first, then of dZ; the channel group runs fastest, so the lanes of one load
   // instruction cover whole 128-byte rows (8 lanes per row) instead of 16 bytes of 64 rows
   WgTask task[2];
@@ -260,11 +279,11 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
   }
   // channel rows past cin / cout (up to the 16-row MFMA block) stay zero; the others are written
   // by every chunk
-  for (int e = cin * kWgPitch / 2 + tid; e < CB * 16 * kWgPitch / 2; e += 256) {
+  for (int e = cw * kWgPitch / 2 + tid; e < CB * 16 * kWgPitch / 2; e += 256) {
     reinterpret_cast<uint32_t *>(XT[0])[e] = 0;
     reinterpret_cast<uint32_t *>(XT[1])[e] = 0;
   }
-  for (int e = cout * kWgPitch / 2 + tid; e < OB * 16 * kWgPitch / 2; e += 256) {
+  for (int e = ow * kWgPitch / 2 + tid; e < OB * 16 * kWgPitch / 2; e += 256) {
     reinterpret_cast<uint32_t *>(GT[0])[e] = 0;
     reinterpret_cast<uint32_t *>(GT[1])[e] = 0;
   }
@@ -284,7 +303,7 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       wg_indices(pairs, p0, chunk_m(0), task[u], rn[u]);
-      wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);
+      wg_gather(Xw, cin, Gw, cout, task[u], rn[u], v[u]);
     }
     // the prefetches past the last chunk re-read the last chunk (no branch around a load)
     const int c1 = nch > 1 ? 1 : 0;
@@ -299,7 +318,7 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
     const int cur = ch & 1;
     uint4 v[2][4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) wg_gather(X, cin, dZ16, cout, task[u], rn[u], v[u]);  // chunk ch + 1
+    for (int u = 0; u < 2; ++u) wg_gather(Xw, cin, Gw, cout, task[u], rn[u], v[u]);  // chunk ch + 1
     const int c2 = ch + 2 < nch ? ch + 2 : nch - 1;
 #pragma unroll
     for (int u = 0; u < 2; ++u) wg_indices(pairs, p0 + (int64_t)c2 * kWgChunk, chunk_m(c2), task[u], rn[u]);
@@ -339,7 +358,7 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int c = mb * 16 + 4 * (lane >> 4) + i;
-        if (c < cin && o < cout) part[((int64_t)(k * kWgSlices + s) * cin + c) * cout + o] = tot[j][i].value();
+        if (c < cw && o < ow) part[((int64_t)(k * S + s) * cin + c0 + c) * cout + o0 + o] = tot[j][i].value();
       }
     }
   }
@@ -350,14 +369,14 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
 // adds partials l, l + 64, ..., then a fixed butterfly adds the 64 lane totals; lane 0 writes.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
                                                            const float *__restrict__ dbpart, int nparts, int cin,
-                                                           int cout, int nbw, float *__restrict__ dW,
+                                                           int cout, int nbw, int S, float *__restrict__ dW,
                                                            float *__restrict__ db) {
   if ((int)blockIdx.x < nbw) {
     const int64_t E = (int64_t)cin * cout;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 27 * E; e += (int64_t)nbw * blockDim.x) {
       Comp a{0.0f, 0.0f};
       const int64_t k = e / E, ce = e % E;
-      for (int s = 0; s < kWgSlices; ++s) a.add(wpart[(k * kWgSlices + s) * E + ce]);
+      for (int s = 0; s < S; ++s) a.add(wpart[(k * S + s) * E + ce]);
       dW[e] = a.value();
     }
     return;
@@ -374,17 +393,23 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workspace: float32 dZ (FP32 path), bfloat16 dZ (BF16 path), the slice partials of dW, the bias
+// partials, and the split-input partials of the data gradient (BF16 layers with 1024+ outputs,
+// whose data gradient reads that many channels).
 static void bwd_ws_layout(int32_t cin, int32_t cout, int32_t cap, int32_t dtype, size_t *o_dz32, size_t *o_dz16,
-                          size_t *o_wp, size_t *o_dbp, size_t *bytes) {
+                          size_t *o_wp, size_t *o_dbp, size_t *o_dx, size_t *dx_bytes, size_t *bytes) {
   size_t o = 0;
   *o_dz32 = o;
-  o += align256(sizeof(float) * (size_t)cap * cout);
+  if (dtype == NPVS_F32) o += align256(sizeof(float) * (size_t)cap * cout);
   *o_dz16 = o;
   if (dtype == NPVS_BF16) o += align256(sizeof(uint16_t) * (size_t)cap * cout);
   *o_wp = o;
-  o += align256(sizeof(float) * 27 * kWgSlices * (size_t)cin * cout);
+  o += align256(sizeof(float) * 27 * wg_slices(cin, cout) * (size_t)cin * cout);
   *o_dbp = o;
   o += align256(sizeof(float) * kDbBlocks * (size_t)cout);
+  *o_dx = o;
+  *dx_bytes = conv_fwd_ws_bytes(cout, cin, cap, dtype);
+  o += align256(*dx_bytes);
   *bytes = o;
 }
 
@@ -396,8 +421,8 @@ extern "C" npvs_status npvs_conv_bwd_workspace_size(int32_t cin, int32_t cout, i
                                                     size_t *bytes) {
   if (!bytes || cin < 1 || cout < 1 || cap_sites < 1)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_workspace_size: bad arguments");
-  size_t a, b, c, d;
-  bwd_ws_layout(cin, cout, cap_sites, dtype, &a, &b, &c, &d, bytes);
+  size_t a, b, c, d, e, f;
+  bwd_ws_layout(cin, cout, cap_sites, dtype, &a, &b, &c, &d, &e, &f, bytes);
   return NPVS_OK;
 }
 
@@ -439,48 +464,49 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
   if (!X || !dY || !nbr || !rb_off || !rb_pairs || !counts || !dW || !db || !ws || (relu && !Y) || (dX && !Wt))
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: null pointer");
   if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: bad sizes");
-  if (cout > 64) return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd: cout > 64");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: dtype must be NPVS_F32 or NPVS_BF16");
   if (dtype == NPVS_BF16 && (cin % 8 || cout % 8))
     return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd: BF16 needs cin % 8 == 0 and cout % 8 == 0");
-  size_t o32, o16, owp, odb, need;
-  bwd_ws_layout(cin, cout, cap_sites, dtype, &o32, &o16, &owp, &odb, &need);
+  size_t o32, o16, owp, odb, odx, dx_bytes, need;
+  bwd_ws_layout(cin, cout, cap_sites, dtype, &o32, &o16, &owp, &odb, &odx, &dx_bytes, &need);
   if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: workspace too small");
   char *w = static_cast<char *>(ws);
-  float *dZ32 = reinterpret_cast<float *>(w + o32);
+  // the FP32 path keeps dZ in float32, the BF16 path in bfloat16 only (both of its products read it)
+  float *dZ32 = dtype == NPVS_F32 ? reinterpret_cast<float *>(w + o32) : nullptr;
   uint16_t *dZ16 = dtype == NPVS_BF16 ? reinterpret_cast<uint16_t *>(w + o16) : nullptr;
   float *wpart = reinterpret_cast<float *>(w + owp);
   float *dbpart = reinterpret_cast<float *>(w + odb);
   const int vec = cout % 4 == 0 && (reinterpret_cast<uintptr_t>(dY) & 15) == 0 &&
                   (!relu || (reinterpret_cast<uintptr_t>(Y) & (dtype == NPVS_F32 ? 15 : 7)) == 0);
+  const dim3 gz(kDbBlocks, (cout + 63) / 64);
   if (dtype == NPVS_F32)
-    relu_grad_kernel<float><<<kDbBlocks, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, vec, dZ32, nullptr,
-                                                       dbpart);
+    relu_grad_kernel<float><<<gz, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, vec, dZ32, nullptr, dbpart);
   else
-    relu_grad_kernel<uint16_t><<<kDbBlocks, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, vec, dZ32,
-                                                          dZ16, dbpart);
+    relu_grad_kernel<uint16_t><<<gz, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, vec, nullptr, dZ16,
+                                                   dbpart);
   npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
   if (st != NPVS_OK) return st;
   st = join_after(s, s2);
   if (st != NPVS_OK) return st;
   if (dX) {
     st = conv_fwd_dispatch(dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, Wt, nullptr, cin, nbr,
-                           counts, cap_sites, dtype, 0, 1, dX, s, kDefaultConvVariant, nullptr, 0);
+                           counts, cap_sites, dtype, 0, 1, dX, s, kDefaultConvVariant, dx_bytes ? w + odx : nullptr,
+                           dx_bytes);
     if (st != NPVS_OK) return st;
   }
-  dim3 gw(kWgSlices, 27);
+  const int S = wg_slices(cin, cout);
   if (dtype == NPVS_F32)
-    wgrad_partial_kernel<float><<<gw, 256, 0, s2>>>((const float *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
-  else if (cin <= 64)
-    wgrad_bf16_kernel<<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
+    wgrad_partial_kernel<float><<<dim3(S, 27, (cout + 63) / 64), 256, 0, s2>>>((const float *)X, cin, dZ32, cout,
+                                                                              rb_off, rb_pairs, wpart);
   else
-    wgrad_partial_kernel<uint16_t><<<gw, 256, 0, s2>>>((const uint16_t *)X, cin, dZ32, cout, rb_off, rb_pairs, wpart);
+    wgrad_bf16_kernel<<<dim3(S, 27, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s2>>>(
+        (const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
   st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
   if (st == NPVS_OK) st = join_after(s2, s3);
   if (st != NPVS_OK) return st;
   const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s3>>>(wpart, dbpart, kDbBlocks, cin, cout, nbw, dW, db);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s3>>>(wpart, dbpart, kDbBlocks, cin, cout, nbw, S, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
 }
 
@@ -562,6 +588,7 @@ extern "C" npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, co
   wgrad_bf16_kernel<<<dim3(kWgSlices, 27), 256, 0, s2>>>((const uint16_t *)X, cin, (const uint16_t *)dZ, cout,
                                                          rb_off, rb_pairs, wpart);
   const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbp, NPVS_BWD_DB_PARTS, cin, cout, nbw, dW, db);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbp, NPVS_BWD_DB_PARTS, cin, cout, nbw, kWgSlices,
+                                                            dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd_chain");
 }

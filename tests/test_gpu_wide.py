@@ -1,6 +1,6 @@
 """GPU parity of the general BF16 convolution (channel counts the tuned tile shapes do not cover)
 and of whole networks at the paper's interleave factors d = 8 and 16, whose first and last layers
-are d^3 = 512 or 4096 channels wide, against the oracle, through the C ABI."""
+are d^3 = 512 or 4096 channels wide, forward and backward, against the oracle, through the C ABI."""
 import numpy as np
 import pytest
 import torch
@@ -9,6 +9,7 @@ import oracle
 import paper_2509_24677_amd as npvs
 import synth
 from gpu_util import DEV, bf16_round, conv_tolerance, oracle_batch, to_np, upload_tris
+from paper_2509_24677_amd.train import Network
 
 pytestmark = pytest.mark.gpu
 
@@ -74,3 +75,89 @@ def test_network_at_paper_interleave_factors(name, dtype):
         pw = np.unpackbits(out["pvs"].reshape(-1), bitorder="little")
         safe = np.abs(np.nan_to_num(ref, neginf=-1e9)) > 1e-5
         np.testing.assert_array_equal(pv[safe], pw[safe])
+
+
+def _bwd_case(cin, cout, d, seed=11):
+    """Two grids (64^3 and 32^3) with a CSR rulebook, and bfloat16-representable layer input X,
+    output Y (about half negative: the ReLU mask), weights W, plus a float32 dY."""
+    dims = [(64, 64, 64), (32, 32, 32)]
+    tri_list = [synth.box_scene(seed + i, g, 25, 2, 10) for i, g in enumerate(dims)]
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    rb = npvs.build_rulebook(occ, dims, d, csr=True)
+    ref = oracle_batch(tri_list, dims, d)
+    rng = np.random.default_rng(seed)
+    X = bf16_round(rng.normal(size=(rb.cap, cin))).astype(np.float32)
+    Y = bf16_round(rng.normal(size=(rb.cap, cout))).astype(np.float32)
+    dY = rng.normal(size=(rb.cap, cout)).astype(np.float32)
+    W = bf16_round(rng.normal(size=(27, cin, cout)) / np.sqrt(27 * cin)).astype(np.float32)
+    return rb, ref, X, Y, dY, W
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+@pytest.mark.parametrize("cin,cout,d", [(512, 64, 8), (64, 512, 8), (4096, 64, 16), (64, 4096, 16), (136, 72, 4),
+                                        (72, 200, 4)])
+def test_conv_bwd_wide_layers_match_oracle(cin, cout, d, dtype):
+    """dX, dW and db of one ReLU layer with more than 64 input or output channels (64 x 64 windows
+    of the weight gradient, ragged last windows, the split data gradient of 4096 inputs) against
+    the FP64 oracle on the same operands: the BF16 path's products take dZ rounded to bfloat16,
+    its bias gradient the float32 dZ."""
+    rb, ref, X, Y, dY, W = _bwd_case(cin, cout, d)
+    n, rb_off, pairs = ref["n"], ref["rb_off"], ref["pairs"]
+    assert n == rb.host_counts()["n_sites"] and n > 8
+    tdt = torch.float32 if dtype == npvs.NPVS_F32 else torch.bfloat16
+    Xd, Yd = torch.from_numpy(X).to(DEV).to(tdt), torch.from_numpy(Y).to(DEV).to(tdt)
+    Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), dtype, flip_transpose=True)
+    dX, dW, db = npvs.sparse_conv_bwd(Xd, Wt, cin, cout, Yd, torch.from_numpy(dY).to(DEV), rb, dtype, relu=True)
+    dX, dW, db = to_np(dX)[:n], to_np(dW), to_np(db)
+    dZ = np.where(Y[:n] > 0, dY[:n], np.float32(0)).astype(np.float64)
+    dZm = dZ if dtype == npvs.NPVS_F32 else bf16_round(dZ)  # the operand of the products
+    u = 2.0 ** -24
+    # data and weight gradients: the oracle on the same operands; float32 accumulation bounds
+    rX, rW, _ = oracle.subm_conv_bwd(X[:n], W, rb_off, pairs, Y[:n], dZm, relu=False)
+    aX, aW, _ = oracle.subm_conv_bwd(np.abs(X[:n]), np.abs(W), rb_off, pairs, Y[:n], np.abs(dZm), relu=False)
+    errW = np.abs(dW - rW)
+    assert (errW <= 2e-5 * aW + 1e-30).all(), (errW.max(), aW.max())
+    errX = np.abs(dX - rX)
+    assert (errX <= 2 * 27 * cout * u * aX + 1e-30).all(), (errX.max(), aX.max())
+    # bias gradient: the float32 dZ summed over the rows
+    _, _, rb_ = oracle.subm_conv_bwd(X[:n], W, rb_off, pairs, Y[:n], dY[:n], relu=True, want_dx=False)
+    assert (np.abs(db - rb_) <= 1e-5 * np.abs(dZ).sum(0) + 1e-30).all()
+    # deterministic
+    dX2, dW2, db2 = npvs.sparse_conv_bwd(Xd, Wt, cin, cout, Yd, torch.from_numpy(dY).to(DEV), rb, dtype, relu=True)
+    np.testing.assert_array_equal(to_np(dW2), dW)
+    np.testing.assert_array_equal(to_np(db2), db)
+    np.testing.assert_array_equal(to_np(dX2)[:n], dX)
+
+
+@pytest.mark.parametrize("name", ["boxes64_d8", "boxes64_d16"])
+def test_network_backward_at_paper_interleave_factors(name):
+    """Gradients of BCE + repulsive visibility loss through the whole network at d = 8 and 16
+    (first and last layers d^3 wide) against the oracle's FP64 backward: FP32 within float32
+    rounding, BF16 within its operand rounding."""
+    cfg = synth.config(name)
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
+    lab_bits = torch.from_numpy(to_np(occ) & synth.label_mask_bits(5, (to_np(occ).size,))).to(DEV)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
+    n = len(out["keys"])
+    ref_dl = oracle.loss(out["acts"][-1], to_np(labels)[:n])["grad"]
+    ref, _ = oracle.backward(out, layers, ref_dl)
+    for dtype in (npvs.NPVS_F32, npvs.NPVS_BF16):
+        net = Network(layers, cfg.d, dtype)
+        X0 = npvs.gather_input(occ, rb, dtype)
+        logits, saved = net.forward(X0, rb)
+        _, dl = npvs.loss(logits, labels, rb)
+        grads = net.backward(saved, logits, dl, rb)
+        torch.cuda.synchronize()
+        for li in range(len(layers)):
+            for a, b, nm in ((to_np(grads[li][0]), ref[li][0], "dW"), (to_np(grads[li][1]), ref[li][1], "db")):
+                scale = np.abs(b).max()
+                rel = np.abs(a - b).max() / scale
+                print(f"{name} dtype {dtype} layer {li} {nm}: max rel err {rel:.3e} (max|g| {scale:.3e})", flush=True)
+                assert scale > 0
+                assert rel <= (1e-4 if dtype == npvs.NPVS_F32 else 0.1)
