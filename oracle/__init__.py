@@ -390,27 +390,118 @@ def unet_forward(tris, dims, d, params, want_logits: bool = True, occ=None):
     rb1 = rulebook(keys1, (b0[0] // 2, b0[1] // 2, b0[2] // 2))
     children, parent, kid = level_maps(keys0, keys1, b0)
     acts = {"X": gather_sites(occ, dims, d, keys0)}
+    inputs = {st: [] for st in params}  # the input of every layer, kept for the backward
     h = acts["X"]
-    for W, b in params["stem"] + params["enc0"]:
-        h = subm_conv(h, W, b, *rb0, relu=True)
+    for st in ("stem", "enc0"):
+        for W, b in params[st]:
+            inputs[st].append(h)
+            h = subm_conv(h, W, b, *rb0, relu=True)
     acts["skip"] = h
     (W, b), = params["down"]
+    inputs["down"].append(h)
     h1 = strided_down(h, children, W, b, relu=True)
     for W, b in params["enc1"]:
+        inputs["enc1"].append(h1)
         h1 = subm_conv(h1, W, b, *rb1, relu=True)
     acts["coarse"] = h1
     (W, b), = params["up"]
+    inputs["up"].append(h1)
     u = inverse_up(h1, parent, kid, W, b, relu=True)
     acts["up"] = u
     h = np.concatenate([u, acts["skip"]], axis=1)
     for W, b in params["dec0"]:
+        inputs["dec0"].append(h)
         h = subm_conv(h, W, b, *rb0, relu=True)
     (W, b), = params["head"]
+    inputs["head"].append(h)
     Y = subm_conv(h, W, b, *rb0, relu=False)
     acts["Y"] = Y
+    acts["inputs"] = inputs
     logits, pvs = deinterleave_threshold(Y, keys0, occ, dims, d, want_logits)
     return dict(occ=occ, keys0=keys0, keys1=keys1, children=children, parent=parent, kid=kid, acts=acts,
-                logits=logits, pvs=pvs)
+                rb0=rb0, rb1=rb1, logits=logits, pvs=pvs)
+
+
+def strided_down_bwd(X0, children, W, Y, dY, relu: bool, want_dx: bool = True):
+    """Chain rule on strided_down: dZ = dY [Y > 0] (ReLU'(0) = 0) or dY; every level-0 row is the
+    child k of exactly one coarse row c, so dX0[child k of c] = dZ[c] W[k]^T; dW[k] = sum over
+    coarse rows c of X0[child k of c]^T dZ[c]; db = sum_c dZ[c].  FP64."""
+    X0 = np.asarray(X0, np.float64)
+    W = np.asarray(W, np.float64)
+    dZ = np.asarray(dY, np.float64) * (np.asarray(Y) > 0) if relu else np.asarray(dY, np.float64)
+    dX0 = np.zeros_like(X0) if want_dx else None
+    dW = np.zeros_like(W)
+    for k in range(8):
+        has = children[k] >= 0
+        rows = children[k, has]
+        if want_dx:
+            dX0[rows] = dZ[has] @ W[k].T
+        dW[k] = X0[rows].T @ dZ[has]
+    return dX0, dW, dZ.sum(0)
+
+
+def inverse_up_bwd(X1, parent, kid, W, Y, dY, relu: bool, want_dx: bool = True):
+    """Chain rule on inverse_up: dZ as in strided_down_bwd; coarse row c collects the products of
+    its children, dX1[c] = sum over children f of c of dZ[f] W[kid f]^T; dW[k] = sum over level-0
+    rows f with kid k of X1[parent f]^T dZ[f]; db = sum_f dZ[f].  FP64."""
+    X1 = np.asarray(X1, np.float64)
+    W = np.asarray(W, np.float64)
+    dZ = np.asarray(dY, np.float64) * (np.asarray(Y) > 0) if relu else np.asarray(dY, np.float64)
+    dX1 = np.zeros_like(X1) if want_dx else None
+    dW = np.zeros_like(W)
+    for k in range(8):
+        sel = kid == k
+        if want_dx:
+            np.add.at(dX1, parent[sel], dZ[sel] @ W[k].T)
+        dW[k] = X1[parent[sel]].T @ dZ[sel]
+    return dX1, dW, dZ.sum(0)
+
+
+def unet_backward(out, params, dY_rows):
+    """Backward through the U-Net of ``unet_forward`` (chain rule stage by stage, FP64), from dL/dY
+    of the head [n0][d^3].  The gradient of the concatenation splits into its up and skip parts;
+    the skip's gradient adds the one arriving through the strided convolution.  Returns
+    {stage: [(dW, db), ...]} and dX of the network input."""
+    acts = out["acts"]
+    inp = acts["inputs"]
+    rb0, rb1 = out["rb0"], out["rb1"]
+    grads = {st: [None] * len(v) for st, v in params.items()}
+
+    def subm_chain(st, dY, rb, relu_top=True):
+        # layers of stage st in reverse; a layer's output is the next layer's input (or the
+        # stage's given output for the last one)
+        ins = inp[st]
+        for i in range(len(ins) - 1, -1, -1):
+            W, _ = params[st][i]
+            Y = outs[st][i]
+            relu = relu_top or i < len(ins) - 1
+            dX, dW, db = subm_conv_bwd(ins[i], W, *rb, Y, dY, relu=relu)
+            grads[st][i] = (dW, db)
+            dY = dX
+        return dY
+
+    def stage_outputs(st, last):
+        return inp[st][1:] + [last]
+
+    u = acts["up"]
+    outs = {"stem": stage_outputs("stem", inp["enc0"][0]), "enc0": stage_outputs("enc0", acts["skip"]),
+            "enc1": stage_outputs("enc1", acts["coarse"]), "dec0": stage_outputs("dec0", inp["head"][0]),
+            "head": [acts["Y"]]}
+    dH = subm_chain("head", dY_rows, rb0, relu_top=False)
+    dH = subm_chain("dec0", dH, rb0)
+    Dc = u.shape[1]
+    dU, dS = dH[:, :Dc], dH[:, Dc:]
+    (W, _), = params["up"]
+    dC, dW, db = inverse_up_bwd(inp["up"][0], out["parent"], out["kid"], W, u, dU, relu=True)
+    grads["up"][0] = (dW, db)
+    dC = subm_chain("enc1", dC, rb1)
+    (W, _), = params["down"]
+    dX0, dW, db = strided_down_bwd(inp["down"][0], out["children"], W, inp["enc1"][0], dC, relu=True)
+    grads["down"][0] = (dW, db)
+    dS = dS + dX0
+    dS = subm_chain("enc0", dS, rb0)
+    dX = subm_chain("stem", dS, rb0)
+    return grads, dX
 
 
 # ---------------------------------------------------------------- world-space front end

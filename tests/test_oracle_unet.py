@@ -111,3 +111,106 @@ def test_unet_forward_matches_masked_dense_torch():
     y = subm(x, params["head"][0], m0, relu=False)
     np.testing.assert_allclose(out["acts"]["Y"], _at(y, keys0), rtol=1e-9, atol=1e-9)
     assert len(keys1) < len(keys0)
+
+
+def _leaf(a):
+    return torch.tensor(np.asarray(a, np.float64), requires_grad=True)
+
+
+@pytest.mark.parametrize("relu", [False, True])
+def test_strided_backward_matches_torch_autograd(relu):
+    """The backward of the strided convolution and of its inverse against torch autograd through
+    dense stride-2 conv3d / conv_transpose3d (float64): dX, dW, db."""
+    rng = np.random.default_rng(5)
+    b0, b1 = (8, 6, 4), (4, 3, 2)
+    keys0 = _random_blocks(rng, b0, 0.4)
+    bx, by, bz = keys0 % 8, (keys0 // 8) % 6, keys0 // 48
+    keys1 = np.unique(((bz // 2) * 3 + by // 2) * 4 + bx // 2).astype(np.int32)
+    children, parent, kid = oracle.level_maps(keys0, keys1, b0)
+    cin, cout = 5, 7
+    for up in (False, True):
+        n_in, n_out = (len(keys1), len(keys0)) if up else (len(keys0), len(keys1))
+        X = rng.normal(size=(n_in, cin))
+        W = rng.normal(size=(8, cin, cout))
+        b = rng.normal(size=cout)
+        G = rng.normal(size=(n_out, cout))
+        x, w, bb = _leaf(_dense(X, keys1 if up else keys0, b1 if up else b0).numpy()), _leaf(W), _leaf(b)
+        w5 = w.reshape(2, 2, 2, cin, cout)
+        if up:
+            y = F.conv_transpose3d(x[None], w5.permute(3, 4, 0, 1, 2), bb, stride=2)[0]
+            keys_out = keys0
+        else:
+            y = F.conv3d(x[None], w5.permute(4, 3, 0, 1, 2), bb, stride=2)[0]
+            keys_out = keys1
+        if relu:
+            y = torch.relu(y)
+        yr = y.reshape(cout, -1)[:, torch.from_numpy(keys_out.astype(np.int64))].T
+        (yr * torch.from_numpy(G)).sum().backward()
+        Yo = yr.detach().numpy()
+        if up:
+            dX, dW, db = oracle.inverse_up_bwd(X, parent, kid, W, Yo, G, relu)
+            gx = x.grad.reshape(cin, -1)[:, torch.from_numpy(keys1.astype(np.int64))].T.numpy()
+        else:
+            dX, dW, db = oracle.strided_down_bwd(X, children, W, Yo, G, relu)
+            gx = x.grad.reshape(cin, -1)[:, torch.from_numpy(keys0.astype(np.int64))].T.numpy()
+        np.testing.assert_allclose(dX, gx, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(dW, w.grad.numpy(), rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(db, bb.grad.numpy(), rtol=1e-10, atol=1e-10)
+
+
+def test_unet_backward_matches_torch_autograd_on_masked_dense():
+    """The oracle's U-Net backward against torch autograd through the masked dense evaluation of
+    the same network (float64), for the loss sum(Y * G) with a random G: the gradient of every
+    weight and bias of every stage and of the network input."""
+    cfg = synth.config("tiny32")
+    tris = synth.scene_for(cfg)
+    g, d = cfg.grids[0], 2
+    params = {k: [(W.astype(np.float64), b.astype(np.float64)) for W, b in v]
+              for k, v in synth.unet_params(6, d, E=8, Dc=12).items()}
+    out = oracle.unet_forward(tris, g, d, params, want_logits=False)
+    keys0, keys1 = out["keys0"], out["keys1"]
+    b0 = (g[0] // d, g[1] // d, g[2] // d)
+    b1 = (b0[0] // 2, b0[1] // 2, b0[2] // 2)
+    m0 = np.zeros(b0[0] * b0[1] * b0[2]); m0[keys0] = 1
+    m1 = np.zeros(b1[0] * b1[1] * b1[2]); m1[keys1] = 1
+    m0 = torch.from_numpy(m0.reshape(b0[2], b0[1], b0[0]))
+    m1 = torch.from_numpy(m1.reshape(b1[2], b1[1], b1[0]))
+    leaves = {st: [(_leaf(W), _leaf(b)) for W, b in v] for st, v in params.items()}
+
+    def subm(x, wb, mask, relu=True):
+        w, b = wb
+        cin, cout = w.shape[1], w.shape[2]
+        y = F.conv3d(x[None], w.reshape(3, 3, 3, cin, cout).permute(4, 3, 0, 1, 2), b, padding=1)[0] * mask
+        return torch.relu(y) if relu else y
+
+    x = _leaf(_dense(oracle.gather_sites(out["occ"], g, d, keys0), keys0, b0).numpy())
+    h = x
+    for wb in leaves["stem"] + leaves["enc0"]:
+        h = subm(h, wb, m0)
+    skip = h
+    (w, b), = leaves["down"]
+    E = w.shape[1]
+    h1 = torch.relu(F.conv3d(h[None], w.reshape(2, 2, 2, E, E).permute(4, 3, 0, 1, 2), b, stride=2)[0]) * m1
+    for wb in leaves["enc1"]:
+        h1 = subm(h1, wb, m1)
+    (w, b), = leaves["up"]
+    Dc = w.shape[2]
+    u = torch.relu(F.conv_transpose3d(h1[None], w.reshape(2, 2, 2, E, Dc).permute(3, 4, 0, 1, 2), b, stride=2)[0]) * m0
+    h = torch.cat([u, skip], 0)
+    for wb in leaves["dec0"]:
+        h = subm(h, wb, m0)
+    y = subm(h, leaves["head"][0], m0, relu=False)
+    G = np.random.default_rng(9).normal(size=out["acts"]["Y"].shape)
+    yr = y.reshape(y.shape[0], -1)[:, torch.from_numpy(keys0.astype(np.int64))].T
+    (yr * torch.from_numpy(G)).sum().backward()
+    grads, dX = oracle.unet_backward(out, params, G)
+    checked = 0
+    for st, layer_grads in grads.items():
+        for (dW, db), (w, b) in zip(layer_grads, leaves[st]):
+            np.testing.assert_allclose(dW, w.grad.numpy(), rtol=1e-9, atol=1e-9, err_msg=st)
+            np.testing.assert_allclose(db, b.grad.numpy(), rtol=1e-9, atol=1e-9, err_msg=st)
+            assert np.abs(dW).max() > 0, st
+            checked += 1
+    assert checked == 11
+    gx = x.grad.reshape(x.shape[0], -1)[:, torch.from_numpy(keys0.astype(np.int64))].T.numpy()
+    np.testing.assert_allclose(dX, gx, rtol=1e-9, atol=1e-9)
