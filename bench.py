@@ -153,13 +153,40 @@ def bench_batch16(args, dev, timed_launches):
 
 def bench_wide(args, dev, timed_launches):
     """The city frame at the paper's interleave factors d = 8 and 16: forward (froxelize -> PVS) as a
-    library-captured graph in BF16 and FP32, and the wide first and last layers (Cin or Cout =
-    d^3 = 512 / 4096) timed launch by launch against the BF16 MFMA peak."""
+    library-captured graph in BF16 and FP32, the training step (forward, loss, backward, Adam) as
+    a captured graph in BF16 (and FP32 at d = 8), and the wide first and last layers (Cin or Cout
+    = d^3 = 512 / 4096) timed launch by launch against the BF16 MFMA peak."""
     import numpy as np
     import torch
 
     import paper_2509_24677_amd as npvs
     import synth
+    from paper_2509_24677_amd.train import Network, Trainer
+
+    def train_ms(cfg, layers, tris, nt, dtype, steps):
+        net = Network(layers, cfg.d, dtype)
+        tr = Trainer(net, cfg.grids, nt, checkpoint=False)
+        occ = npvs.froxelize(tris, nt, cfg.grids)
+        lab = occ & torch.from_numpy(synth.label_mask_bits(7, (occ.numel(),))).to(dev)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                tr.step(tris, lab)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            tr.step(tris, lab)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
 
     res = {}
     for name in ("city256_d8", "city256_d16"):
@@ -188,6 +215,12 @@ def bench_wide(args, dev, timed_launches):
             r[f"{tag}_fwd_ms"] = ms
             r[f"{tag}_fwd_frames_per_s"] = 1000.0 / ms
         r["bf16_fwd_speedup_vs_fp32"] = r["fp32_fwd_ms"] / r["bf16_fwd_ms"]
+        ms = train_ms(cfg, layers, tris, nt, npvs.NPVS_BF16, args.steps)
+        r["bf16_fwd_bwd_ms"], r["bf16_fwd_bwd_frames_per_s"] = ms, 1000.0 / ms
+        if cfg.d == 8:  # the FP32 step at d = 16 takes about 0.1 s: left out to keep the run short
+            ms = train_ms(cfg, layers, tris, nt, npvs.NPVS_F32, 5)
+            r["fp32_fwd_bwd_ms"], r["fp32_fwd_bwd_frames_per_s"] = ms, 1000.0 / ms
+            r["bf16_fwd_bwd_speedup_vs_fp32"] = r["fp32_fwd_bwd_ms"] / r["bf16_fwd_bwd_ms"]
         occ = npvs.froxelize(tris, nt, cfg.grids)
         rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
         c = rb.host_counts()
@@ -214,8 +247,9 @@ def bench_wide(args, dev, timed_launches):
 
 def bench_unet(args, dev, timed_launches):
     """The city frame through the two-level U-Net (d = 4; embedding / encoder 64 and decoder 96
-    channels): the whole path froxelize -> PVS captured as one graph in BF16 and FP32, and the
-    strided down and inverse up convolutions timed launch by launch."""
+    channels): the whole path froxelize -> PVS captured as one graph in BF16 and FP32, the
+    training pass (froxelize -> loss -> backward of every stage) as one graph in BF16 and FP32,
+    and the strided down and inverse up convolutions timed launch by launch."""
     import numpy as np
     import torch
 
@@ -256,6 +290,43 @@ def bench_unet(args, dev, timed_launches):
         r[f"{tag}_fwd_frames_per_s"] = 1000.0 / ms
         del g
     r["bf16_fwd_speedup_vs_fp32"] = r["fp32_fwd_ms"] / r["bf16_fwd_ms"]
+    # forward + loss + backward (every stage's weight and bias gradient), captured as one graph;
+    # labels: a fixed subset of the occupied froxels (timing does not depend on their values)
+    lab = npvs.froxelize(tris, nt, cfg.grids)
+    lab &= torch.from_numpy(synth.label_mask_bits(7, (lab.numel(),))).to(dev)
+    for dtype, tag, steps in ((npvs.NPVS_BF16, "bf16", args.steps), (npvs.NPVS_F32, "fp32", 5)):
+        net = UNet(params, cfg.d, dtype)
+
+        def train_pass():
+            occ_ = npvs.froxelize(tris, nt, cfg.grids)
+            lv_ = npvs.build_levels(occ_, cfg.grids, cfg.d, csr=True)
+            saved = {}
+            logits = net.forward(npvs.gather_input(occ_, lv_.rb0, dtype), lv_, saved=saved)
+            _, dl = npvs.loss(logits, npvs.gather_input(lab, lv_.rb0, npvs.NPVS_U8), lv_.rb0)
+            return net.backward(saved, logits, dl, lv_)
+
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                train_pass()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            train_pass()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r[f"{tag}_fwd_bwd_ms"], r[f"{tag}_fwd_bwd_frames_per_s"] = ms, 1000.0 / ms
+        del g
+    r["bf16_fwd_bwd_speedup_vs_fp32"] = r["fp32_fwd_bwd_ms"] / r["bf16_fwd_bwd_ms"]
     occ = npvs.froxelize(tris, nt, cfg.grids)
     lv = npvs.build_levels(occ, cfg.grids, cfg.d, csr=True)
     c0, c1 = lv.rb0.host_counts(), lv.rb1.host_counts()

@@ -343,6 +343,40 @@ npvs_status npvs_concat_channels(const void *A, int32_t ca, const void *B, int32
                                  const npvs_counts *counts, int32_t cap, void *Y, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Backward of the U-Net's strided layers and skip concatenation (chain rule on the forward
+ * definitions above; the paper trains its encoder/decoder backbone, Sec. 3.3, 4.2):
+ * npvs_pack_weights_k_ex: npvs_pack_weights_k, or with transpose = 1 the packing of the
+ *   per-offset transposes W_k^T ([K][cout][cin], npvs_packed_weight_bytes_k(K, cout, cin, dtype)
+ *   bytes): the weight of the data gradient.
+ * npvs_strided_conv_bwd: dZ = dY [Y > 0] when relu (ReLU'(0) = 0), else dY; for the strided
+ *   convolution (up = 0: X level 0, Y level 1) dX0[child k of c] = dZ[c] W_k^T and
+ *   dW_k = sum_c X0[child k of c]^T dZ[c]; for its inverse (up = 1: X level 1, Y level 0)
+ *   dX1[c] = sum over the children f of c of dZ[f] W_{k(f)}^T and dW_k = sum over the level-0
+ *   rows f with child index k of X1[parent f]^T dZ[f]; db = sum of dZ over the output rows.
+ *   X (device) [cap_in][cin] and Y [cap_out][cout] in `dtype`; dY float32 [cap_out][cout];
+ *   children / parent from npvs_level_maps; counts_in / counts_out the input and output level's
+ *   counts; Wt = npvs_pack_weights_k_ex(W, 8, cin, cout, transpose = 1) (nullable when dX is);
+ *   dX (nullable) float32 [cap_in][cin], dW float32 [8][cin][cout], db float32 [cout], all
+ *   overwritten (rows of dX past the input count untouched).  ws (device) scratch of
+ *   npvs_strided_bwd_workspace_size() bytes.  Deterministic (fixed reduction orders).  BF16:
+ *   products on MFMA from bfloat16 dZ, cin and cout multiples of 8.
+ * npvs_concat_channels_bwd: for r < n_sites, dA[r] = dY[r][0, ca) and dB[r] = dY[r][ca, ca + cb)
+ *   (+ add_b[r] when add_b is given: the gradient the second part receives from elsewhere);
+ *   float32, dA or dB nullable (not both), ca and cb multiples of 4, 16-byte aligned buffers.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_pack_weights_k_ex(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t transpose,
+                                   int32_t dtype, void *Wp, void *stream);
+npvs_status npvs_strided_bwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_in, int32_t cap_out, int32_t up,
+                                            int32_t dtype, size_t *bytes);
+npvs_status npvs_strided_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
+                                  const float *dY, const int32_t *children, const int32_t *parent, int32_t up,
+                                  const npvs_counts *counts_in, int32_t cap_in, const npvs_counts *counts_out,
+                                  int32_t cap_out, int32_t dtype, int32_t relu, float *dX, float *dW, float *db,
+                                  void *ws, size_t ws_bytes, void *stream);
+npvs_status npvs_concat_channels_bwd(const float *dY, int32_t ca, int32_t cb, const float *add_b,
+                                     const npvs_counts *counts, int32_t cap, float *dA, float *dB, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * De-interleave and threshold (Sec. 3.1 V = 1[f(G) >= tau] with tau = 0.5, read as logit >= 0;
  * Sec. 3.3 g_d^-1; Sec. 3.2 the visible set lies inside the occupied set, so V is masked by G):
  *   V(x) = [L(x) >= 0] and G(x),  L(x) = Y[row(block(x))][c(x)], -inf for inactive blocks.

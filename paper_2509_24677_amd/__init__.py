@@ -316,15 +316,16 @@ def build_levels(occ: torch.Tensor, dims, d: int, csr: bool = False) -> Levels:
     return Levels(rb0, rb1, children, parent)
 
 
-def pack_weights_k(W: torch.Tensor, dtype: int) -> torch.Tensor:
-    """Kernel layout of float32 weights [K][cin][cout] of K offsets (uint8 byte tensor)."""
+def pack_weights_k(W: torch.Tensor, dtype: int, transpose: bool = False) -> torch.Tensor:
+    """Kernel layout of float32 weights [K][cin][cout] of K offsets (uint8 byte tensor); with
+    `transpose` that of the per-offset transposes W_k^T (the strided layers' data gradient)."""
     W = W.contiguous()
     if W.dtype != torch.float32 or W.dim() != 3:
         raise ValueError("W must be float32 [K][cin][cout]")
     K, cin, cout = W.shape
-    nbytes = L.get().npvs_packed_weight_bytes_k(K, cin, cout, dtype)
+    nbytes = L.get().npvs_packed_weight_bytes_k(K, cout if transpose else cin, cin if transpose else cout, dtype)
     Wp = torch.empty(nbytes, dtype=torch.uint8, device=W.device)
-    L.call("npvs_pack_weights_k", _p(W), K, cin, cout, dtype, _p(Wp), _stream())
+    L.call("npvs_pack_weights_k_ex", _p(W), K, cin, cout, int(transpose), dtype, _p(Wp), _stream())
     return Wp
 
 
@@ -339,6 +340,41 @@ def strided_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | Non
     L.call("npvs_strided_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(lv.parent if up else lv.children),
            int(up), _p(rb.counts), rb.cap, dtype, int(relu), int(out_f32), _p(Y), _stream())
     return Y
+
+
+def strided_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, lv: Levels, up: bool, dtype: int, relu: bool = True,
+                     want_dx: bool = True, dW: torch.Tensor | None = None, db: torch.Tensor | None = None):
+    """Backward of strided_conv_fwd (npvs_strided_conv_bwd).  Wt = pack_weights_k(W, dtype,
+    transpose=True).  Returns (dX float32 [input cap][cin] or None, dW float32 [8][cin][cout],
+    db float32 [cout])."""
+    rb_in, rb_out = (lv.rb1, lv.rb0) if up else (lv.rb0, lv.rb1)
+    dev = X.device
+    nbytes = ctypes.c_size_t()
+    L.call("npvs_strided_bwd_workspace_size", cin, cout, rb_in.cap, rb_out.cap, int(up), dtype, ctypes.byref(nbytes))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    dX = torch.empty((rb_in.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
+    if dW is None:
+        dW = torch.empty((8, cin, cout), dtype=torch.float32, device=dev)
+    if db is None:
+        db = torch.empty(cout, dtype=torch.float32, device=dev)
+    if dW.numel() != 8 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
+        raise ValueError("dW / db must be contiguous float32 [8][cin][cout] / [cout]")
+    L.call("npvs_strided_conv_bwd", _p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(lv.children),
+           _p(lv.parent), int(up), _p(rb_in.counts), rb_in.cap, _p(rb_out.counts), rb_out.cap, dtype, int(relu),
+           _p(dX), _p(dW), _p(db), _p(ws), ws.numel(), _stream())
+    return dX, dW, db
+
+
+def concat_channels_bwd(dY: torch.Tensor, ca: int, cb: int, rb: Rulebook, add_b: torch.Tensor | None = None,
+                        want_a: bool = True, want_b: bool = True):
+    """Gradient of concat_channels (float32): (dA [cap][ca] or None, dB [cap][cb] or None), with
+    add_b (float32 [cap][cb]) added to dB."""
+    dev = dY.device
+    dA = torch.empty((dY.shape[0], ca), dtype=torch.float32, device=dev) if want_a else None
+    dB = torch.empty((dY.shape[0], cb), dtype=torch.float32, device=dev) if want_b else None
+    L.call("npvs_concat_channels_bwd", _p(dY.contiguous()), ca, cb, _p(add_b), _p(rb.counts), rb.cap, _p(dA), _p(dB),
+           _stream())
+    return dA, dB
 
 
 def concat_channels(A: torch.Tensor, B: torch.Tensor, rb: Rulebook) -> torch.Tensor:

@@ -89,6 +89,10 @@ SIGNATURES = {
     "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, P, P]),
     "npvs_strided_conv_fwd": (i32, [P, i32, P, P, i32, P, i32, P, i32, i32, i32, i32, P, P]),
     "npvs_concat_channels": (i32, [P, i32, P, i32, i32, P, i32, P, P]),
+    "npvs_pack_weights_k_ex": (i32, [P, i32, i32, i32, i32, i32, P, P]),
+    "npvs_strided_bwd_workspace_size": (i32, [i32, i32, i32, i32, i32, i32, PS]),
+    "npvs_strided_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, i32, P, i32, P, i32, i32, i32, P, P, P, P, sz, P]),
+    "npvs_concat_channels_bwd": (i32, [P, i32, i32, P, P, i32, P, P, P]),
     "npvs_viewcell_frustum": (i32, [P, P, P, f64, f64, f64, f64, f64, f64, P]),
     "npvs_froxelize_view_workspace_size": (i32, [i64, PS]),
     "npvs_froxelize_view": (i32, [P, i64, P, Dims, P, P, sz, P]),

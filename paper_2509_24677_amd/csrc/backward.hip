@@ -28,7 +28,7 @@ struct Comp {  // Neumaier-compensated float sum
 __device__ __forceinline__ float load_as_f32(const float *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float load_as_f32(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
 
-constexpr int kDbBlocks = 256;  // row blocks of the bias-gradient partial sums (one layer)
+constexpr int kDbBlocks = kBwdDbBlocks;  // row blocks of the bias-gradient partial sums (one layer)
 
 // dZ in float32 (for wgrad; nullable) and, for the BF16 path, a bfloat16 copy (MFMA operand),
 // plus the bias-gradient partial of this block's rows: blockIdx.x = partial row, blockIdx.y = a
@@ -110,7 +110,7 @@ constexpr size_t kWgPartBudget = size_t(8) << 20;  // bytes of float32 slice par
 
 // Slices per offset: 16 while the float32 partials of every slice stay within the budget (every
 // layer of at most 64 x 64 channels), fewer for wider layers, at least one.
-static int wg_slices(int cin, int cout) {
+int wg_slices(int cin, int cout) {
   const size_t per = sizeof(float) * 27 * (size_t)cin * cout;
   const size_t s = kWgPartBudget / per;
   return s < 1 ? 1 : s > (size_t)kWgSlices ? kWgSlices : (int)s;
@@ -118,8 +118,9 @@ static int wg_slices(int cin, int cout) {
 constexpr int kWgPairs = 32;   // pairs staged per step (vector path)
 constexpr int kWgEPT = 16;     // dW entries per thread per pass (vector path)
 
-// Vector FP32 path: grid (S slices, 27, output windows of 64 channels), 256 threads.  Partial dW
-// of offset k over slice s for the outputs o0 .. o0 + 63.
+// Vector FP32 path: grid (S slices, K offsets, output windows of 64 channels), 256 threads.
+// Partial dW of offset k over slice s for the outputs o0 .. o0 + 63.  A pair member of -1 (the
+// pair lists of the strided layers) reads as a zero row.
 template <typename T>
 __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict__ X, int cin,
                                                              const float *__restrict__ dZ, int cout,
@@ -150,8 +151,8 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
       __syncthreads();
       for (int e = tid; e < kWgPairs * 64; e += 256) {
         int p = e >> 6, c = e & 63;
-        Xs[p][c] = (p < m && c < cn) ? load_as_f32(X, (int64_t)in_s[p] * cin + cbase + c) : 0.0f;
-        Gs[p][c] = (p < m && c < ow) ? dZ[(int64_t)out_s[p] * cout + o0 + c] : 0.0f;
+        Xs[p][c] = (p < m && c < cn && in_s[p] >= 0) ? load_as_f32(X, (int64_t)in_s[p] * cin + cbase + c) : 0.0f;
+        Gs[p][c] = (p < m && c < ow && out_s[p] >= 0) ? dZ[(int64_t)out_s[p] * cout + o0 + c] : 0.0f;
       }
       __syncthreads();
 #pragma unroll
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
   }
 }
 
-// BF16 path on MFMA.  grid (S slices, 27, windows), 256 threads = 4 waves; a workgroup computes
+// BF16 path on MFMA.  grid (S slices, K offsets, windows), 256 threads = 4 waves; a workgroup computes
 // the window of at most 64 x 64 entries (input channels c0 .., outputs o0 ..) that blockIdx.z
 // selects (one window when cin, cout <= 64).
 // dW_k[c][o] = sum_p X[in_p][c] dZ[out_p][o] is a [cin x P] x [P x cout] product with the pair
@@ -364,19 +365,24 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
   }
 }
 
-// Blocks [0, nbw) reduce dW over the slices (grid-stride, one entry per thread); each block
+// Blocks [0, nbw) reduce dW (K offsets) over the slices (grid-stride, one entry per thread); each block
 // after them reduces db over the nparts partial rows for 4 channels, one wave per channel: lane l
 // adds partials l, l + 64, ..., then a fixed butterfly adds the 64 lane totals; lane 0 writes.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
                                                            const float *__restrict__ dbpart, int nparts, int cin,
-                                                           int cout, int nbw, int S, float *__restrict__ dW,
+                                                           int cout, int nbw, int K, int S, float *__restrict__ dW,
                                                            float *__restrict__ db) {
   if ((int)blockIdx.x < nbw) {
     const int64_t E = (int64_t)cin * cout;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 27 * E; e += (int64_t)nbw * blockDim.x) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K * E; e += (int64_t)nbw * blockDim.x) {
       Comp a{0.0f, 0.0f};
       const int64_t k = e / E, ce = e % E;
-      for (int s = 0; s < S; ++s) a.add(wpart[(k * S + s) * E + ce]);
+      if (S == kWgSlices) {  // the usual count, unrolled so that the loads are issued together
+#pragma unroll
+        for (int s = 0; s < kWgSlices; ++s) a.add(wpart[(k * kWgSlices + s) * E + ce]);
+      } else {
+        for (int s = 0; s < S; ++s) a.add(wpart[(k * S + s) * E + ce]);
+      }
       dW[e] = a.value();
     }
     return;
@@ -389,6 +395,37 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
   if (lane == 0) db[o] = t;
+}
+
+npvs_status bwd_form_dz(int32_t dtype, const void *Y, const float *dY, const npvs_counts *counts, int32_t C,
+                        int32_t relu, float *dZ32, uint16_t *dZ16, float *dbpart, hipStream_t s) {
+  const int vec = C % 4 == 0 && (reinterpret_cast<uintptr_t>(dY) & 15) == 0 &&
+                  (!relu || (reinterpret_cast<uintptr_t>(Y) & (dtype == NPVS_F32 ? 15 : 7)) == 0);
+  const dim3 gz(kDbBlocks, (C + 63) / 64);
+  if (dtype == NPVS_F32)
+    relu_grad_kernel<float><<<gz, 256, 0, s>>>((const float *)Y, dY, counts, C, relu, vec, dZ32, nullptr, dbpart);
+  else
+    relu_grad_kernel<uint16_t><<<gz, 256, 0, s>>>((const uint16_t *)Y, dY, counts, C, relu, vec, nullptr, dZ16,
+                                                   dbpart);
+  return check_hip(hipGetLastError(), "backward: dZ");
+}
+
+npvs_status bwd_wgrad(int32_t dtype, const void *X, int32_t cin, const void *dZ, int32_t cout, int32_t K,
+                      const int32_t *rb_off, const int32_t *pairs, int S, float *wpart, hipStream_t s) {
+  if (dtype == NPVS_F32)
+    wgrad_partial_kernel<float><<<dim3(S, K, (cout + 63) / 64), 256, 0, s>>>(
+        (const float *)X, cin, (const float *)dZ, cout, rb_off, pairs, wpart);
+  else
+    wgrad_bf16_kernel<<<dim3(S, K, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s>>>(
+        (const uint16_t *)X, cin, (const uint16_t *)dZ, cout, rb_off, pairs, wpart);
+  return check_hip(hipGetLastError(), "backward: weight gradient");
+}
+
+npvs_status bwd_reduce(const float *wpart, const float *dbpart, int nparts, int32_t K, int S, int32_t cin,
+                       int32_t cout, float *dW, float *db, hipStream_t s) {
+  const int nbw = stride_grid((int64_t)K * cin * cout, 256, 2048);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s>>>(wpart, dbpart, nparts, cin, cout, nbw, K, S, dW, db);
+  return check_hip(hipGetLastError(), "backward: reductions");
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -477,15 +514,7 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
   uint16_t *dZ16 = dtype == NPVS_BF16 ? reinterpret_cast<uint16_t *>(w + o16) : nullptr;
   float *wpart = reinterpret_cast<float *>(w + owp);
   float *dbpart = reinterpret_cast<float *>(w + odb);
-  const int vec = cout % 4 == 0 && (reinterpret_cast<uintptr_t>(dY) & 15) == 0 &&
-                  (!relu || (reinterpret_cast<uintptr_t>(Y) & (dtype == NPVS_F32 ? 15 : 7)) == 0);
-  const dim3 gz(kDbBlocks, (cout + 63) / 64);
-  if (dtype == NPVS_F32)
-    relu_grad_kernel<float><<<gz, 256, 0, s>>>((const float *)Y, dY, counts, cout, relu, vec, dZ32, nullptr, dbpart);
-  else
-    relu_grad_kernel<uint16_t><<<gz, 256, 0, s>>>((const uint16_t *)Y, dY, counts, cout, relu, vec, nullptr, dZ16,
-                                                   dbpart);
-  npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
+  npvs_status st = bwd_form_dz(dtype, Y, dY, counts, cout, relu, dZ32, dZ16, dbpart, s);
   if (st != NPVS_OK) return st;
   st = join_after(s, s2);
   if (st != NPVS_OK) return st;
@@ -496,18 +525,11 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
     if (st != NPVS_OK) return st;
   }
   const int S = wg_slices(cin, cout);
-  if (dtype == NPVS_F32)
-    wgrad_partial_kernel<float><<<dim3(S, 27, (cout + 63) / 64), 256, 0, s2>>>((const float *)X, cin, dZ32, cout,
-                                                                              rb_off, rb_pairs, wpart);
-  else
-    wgrad_bf16_kernel<<<dim3(S, 27, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s2>>>(
-        (const uint16_t *)X, cin, dZ16, cout, rb_off, rb_pairs, wpart);
-  st = check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
+  st = bwd_wgrad(dtype, X, cin, dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, 27, rb_off,
+                 rb_pairs, S, wpart, s2);
   if (st == NPVS_OK) st = join_after(s2, s3);
   if (st != NPVS_OK) return st;
-  const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s3>>>(wpart, dbpart, kDbBlocks, cin, cout, nbw, S, dW, db);
-  return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd");
+  return bwd_reduce(wpart, dbpart, kDbBlocks, 27, S, cin, cout, dW, db, s3);
 }
 
 
@@ -588,7 +610,7 @@ extern "C" npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, co
   wgrad_bf16_kernel<<<dim3(kWgSlices, 27), 256, 0, s2>>>((const uint16_t *)X, cin, (const uint16_t *)dZ, cout,
                                                          rb_off, rb_pairs, wpart);
   const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbp, NPVS_BWD_DB_PARTS, cin, cout, nbw, kWgSlices,
-                                                            dW, db);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbp, NPVS_BWD_DB_PARTS, cin, cout, nbw, 27,
+                                                            kWgSlices, dW, db);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd_chain");
 }

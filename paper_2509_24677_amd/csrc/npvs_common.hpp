@@ -94,4 +94,20 @@ npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int co
                              hipStream_t s);
 size_t conv_fwd_ws_bytes(int32_t cin, int32_t cout, int32_t cap, int32_t dtype);
 
+// Backward building blocks shared by the submanifold and the strided layers (backward.hip), all
+// enqueued on `s`:
+//   bwd_form_dz: dZ = dY [Y > 0] (or dY) for the rows counts->n_sites, as float32 (dZ32, FP32
+//     path) or bfloat16 (dZ16, BF16 path), plus the bias partials dbpart[kBwdDbBlocks][C];
+//   bwd_wgrad: slice partials wpart[K][S][cin][cout] of dW_k = sum over the pairs (i, r) of
+//     offset k (CSR rb_off[K + 1], pairs[][2]; a member of -1 reads as a zero row) of X[i]^T dZ[r];
+//   bwd_reduce: dW = the slice partials summed in a fixed order, db = the bias partials summed.
+constexpr int kBwdDbBlocks = 256;
+int wg_slices(int cin, int cout);  // slices per offset of the weight-gradient partials
+npvs_status bwd_form_dz(int32_t dtype, const void *Y, const float *dY, const npvs_counts *counts, int32_t C,
+                        int32_t relu, float *dZ32, uint16_t *dZ16, float *dbpart, hipStream_t s);
+npvs_status bwd_wgrad(int32_t dtype, const void *X, int32_t cin, const void *dZ, int32_t cout, int32_t K,
+                      const int32_t *rb_off, const int32_t *pairs, int S, float *wpart, hipStream_t s);
+npvs_status bwd_reduce(const float *wpart, const float *dbpart, int nparts, int32_t K, int S, int32_t cin,
+                       int32_t cout, float *dW, float *db, hipStream_t s);
+
 }  // namespace npvs

@@ -80,19 +80,27 @@ __global__ __launch_bounds__(256) void level_maps_kernel(LevelDesc L, const npvs
 // layout is that of the submanifold kernels, Wp[k][nb][kb][lane][j] = W[k][kb*32 + 8(lane/16) + j]
 // [nb*16 + lane%16] (zero outside cin x cout).
 // ------------------------------------------------------------------------------------------
-__global__ void pack_k_kernel(const float *__restrict__ W, int K, int cin, int cout, int dtype, void *__restrict__ P) {
-  const int KB = (cin + 31) / 32, NB = (cout + 15) / 16;
-  const int64_t total = dtype == NPVS_F32 ? (int64_t)K * cin * cout : (int64_t)K * NB * KB * 512;
+// With transpose the packed weight is P_k = W_k^T ([K][cout][cin]: the data gradient of the
+// strided layers), else P = W.
+__global__ void pack_k_kernel(const float *__restrict__ W, int K, int cin, int cout, int transpose, int dtype,
+                              void *__restrict__ P) {
+  const int CI = transpose ? cout : cin, CO = transpose ? cin : cout;
+  const int KB = (CI + 31) / 32, NB = (CO + 15) / 16;
+  const int64_t total = dtype == NPVS_F32 ? (int64_t)K * CI * CO : (int64_t)K * NB * KB * 512;
+  auto src = [&](int k, int c, int o) {  // P[k][c][o]
+    return transpose ? W[((int64_t)k * cin + o) * cout + c] : W[((int64_t)k * cin + c) * cout + o];
+  };
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     if (dtype == NPVS_F32) {
-      static_cast<float *>(P)[e] = W[e];
+      const int o = (int)(e % CO), c = (int)((e / CO) % CI), k = (int)(e / ((int64_t)CO * CI));
+      static_cast<float *>(P)[e] = src(k, c, o);
       continue;
     }
     const int j = e & 7, lane = (e >> 3) & 63;
     const int64_t frag = e >> 9;
     const int kb = frag % KB, nb = (frag / KB) % NB, k = (int)(frag / ((int64_t)KB * NB));
     const int c = kb * 32 + 8 * (lane >> 4) + j, o = nb * 16 + (lane & 15);
-    const float v = (c < cin && o < cout) ? W[((int64_t)k * cin + c) * cout + o] : 0.0f;
+    const float v = (c < CI && o < CO) ? src(k, c, o) : 0.0f;
     static_cast<uint16_t *>(P)[e] = f32_to_bf16(v);
   }
 }
@@ -235,6 +243,64 @@ __global__ __launch_bounds__(256) void concat_kernel(const uint4 *__restrict__ A
   }
 }
 
+// Pair lists of the strided layers' weight gradients, one CSR segment per child index k over the
+// coarse rows c < n1: (children[k][c], c) for the strided convolution (input level 0, output level
+// 1), (c, children[k][c]) for its inverse.  A missing child (-1) stays in the list and reads as a
+// zero row.  rb_off[k] = k n1.
+__global__ __launch_bounds__(256) void strided_pairs_kernel(const int32_t *__restrict__ children,
+                                                            const npvs_counts *__restrict__ counts1, int cap1, int up,
+                                                            int32_t *__restrict__ rb_off,
+                                                            int32_t *__restrict__ pairs) {
+  const int n1 = counts1->n_sites;
+  if (blockIdx.x == 0 && threadIdx.x <= 8) rb_off[threadIdx.x] = (int32_t)threadIdx.x * n1;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 8LL * n1; e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / n1), c = (int)(e % n1);
+    const int32_t m = children[(int64_t)k * cap1 + c];
+    pairs[2 * e] = up ? c : m;
+    pairs[2 * e + 1] = up ? m : c;
+  }
+}
+
+// Gradient of the channel concatenation Y = [A | B]: dA[r] = dY[r][0, ca), dB[r] = dY[r][ca,
+// ca + cb) + add[r] (add nullable: the skip's gradient from its other consumer), float32, four
+// channels per thread step.
+__global__ __launch_bounds__(256) void concat_bwd_kernel(const f32x4_t *__restrict__ dY, int qa, int qb,
+                                                         const f32x4_t *__restrict__ add,
+                                                         const npvs_counts *__restrict__ counts,
+                                                         f32x4_t *__restrict__ dA, f32x4_t *__restrict__ dB) {
+  const int q = qa + qb;
+  const int64_t total = (int64_t)counts->n_sites * q;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / q;
+    const int j = (int)(e % q);
+    if (j < qa) {
+      if (dA) dA[r * qa + j] = dY[e];
+    } else if (dB) {
+      const int64_t i = r * qb + (j - qa);
+      dB[i] = add ? dY[e] + add[i] : dY[e];
+    }
+  }
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of the strided backward: dZ [cap_out][cout] (float32 or bfloat16), the pair list
+// [8 cap1][2], rb_off [9], the weight-gradient slice partials and the bias partials.
+static void strided_bwd_layout(int32_t cin, int32_t cout, int32_t cap_in, int32_t cap_out, int32_t up, int32_t dtype,
+                               size_t *o_pairs, size_t *o_off, size_t *o_wp, size_t *o_dbp, size_t *bytes) {
+  const size_t cap1 = up ? cap_in : cap_out;
+  size_t o = al256((dtype == NPVS_F32 ? 4 : 2) * (size_t)cap_out * cout);
+  *o_pairs = o;
+  o += al256(sizeof(int32_t) * 2 * 8 * cap1);
+  *o_off = o;
+  o += al256(sizeof(int32_t) * 9);
+  *o_wp = o;
+  o += al256(sizeof(float) * 8 * wg_slices(cin, cout) * (size_t)cin * cout);
+  *o_dbp = o;
+  o += al256(sizeof(float) * kBwdDbBlocks * (size_t)cout);
+  *bytes = o;
+}
+
 }  // namespace npvs
 
 using namespace npvs;
@@ -273,15 +339,22 @@ extern "C" size_t npvs_packed_weight_bytes_k(int32_t K, int32_t cin, int32_t cou
   return 0;
 }
 
-extern "C" npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t dtype,
-                                          void *Wp, void *stream) {
+extern "C" npvs_status npvs_pack_weights_k_ex(const float *W, int32_t K, int32_t cin, int32_t cout,
+                                             int32_t transpose, int32_t dtype, void *Wp, void *stream) {
   if (!W || !Wp) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_k: null pointer");
   if (K < 1 || cin < 1 || cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_k: bad sizes");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_k: dtype must be NPVS_F32 or NPVS_BF16");
-  const int64_t elems = (int64_t)npvs_packed_weight_bytes_k(K, cin, cout, dtype) / (dtype == NPVS_F32 ? 4 : 2);
-  pack_k_kernel<<<stride_grid(elems, 256, 1024), 256, 0, as_stream(stream)>>>(W, K, cin, cout, dtype, Wp);
+  const int64_t elems = (int64_t)npvs_packed_weight_bytes_k(K, transpose ? cout : cin, transpose ? cin : cout, dtype) /
+                        (dtype == NPVS_F32 ? 4 : 2);
+  pack_k_kernel<<<stride_grid(elems, 256, 1024), 256, 0, as_stream(stream)>>>(W, K, cin, cout, transpose ? 1 : 0,
+                                                                              dtype, Wp);
   return check_hip(hipGetLastError(), "npvs_pack_weights_k");
+}
+
+extern "C" npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t dtype,
+                                          void *Wp, void *stream) {
+  return npvs_pack_weights_k_ex(W, K, cin, cout, 0, dtype, Wp, stream);
 }
 
 extern "C" npvs_status npvs_strided_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
@@ -327,4 +400,70 @@ extern "C" npvs_status npvs_concat_channels(const void *A, int32_t ca, const voi
   concat_kernel<<<stride_grid((int64_t)cap * (qa + qb), 256, 4096), 256, 0, as_stream(stream)>>>(
       (const uint4 *)A, qa, (const uint4 *)B, qb, counts, (uint4 *)Y);
   return check_hip(hipGetLastError(), "npvs_concat_channels");
+}
+
+extern "C" npvs_status npvs_concat_channels_bwd(const float *dY, int32_t ca, int32_t cb, const float *add_b,
+                                               const npvs_counts *counts, int32_t cap, float *dA, float *dB,
+                                               void *stream) {
+  if (!dY || !counts || (!dA && !dB)) return fail(NPVS_ERR_INVALID_ARG, "npvs_concat_channels_bwd: null pointer");
+  if (ca < 1 || cb < 1 || cap < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_concat_channels_bwd: bad sizes");
+  if (ca % 4 || cb % 4) return fail(NPVS_ERR_UNSUPPORTED, "npvs_concat_channels_bwd: ca and cb must be multiples of 4");
+  const uintptr_t any = reinterpret_cast<uintptr_t>(dY) | reinterpret_cast<uintptr_t>(add_b) |
+                        reinterpret_cast<uintptr_t>(dA) | reinterpret_cast<uintptr_t>(dB);
+  if (any & 15) return fail(NPVS_ERR_INVALID_ARG, "npvs_concat_channels_bwd: buffers must be 16-byte aligned");
+  const int qa = ca / 4, qb = cb / 4;
+  concat_bwd_kernel<<<stride_grid((int64_t)cap * (qa + qb), 256, 4096), 256, 0, as_stream(stream)>>>(
+      (const f32x4_t *)dY, qa, qb, (const f32x4_t *)add_b, counts, (f32x4_t *)dA, (f32x4_t *)dB);
+  return check_hip(hipGetLastError(), "npvs_concat_channels_bwd");
+}
+
+extern "C" npvs_status npvs_strided_bwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_in, int32_t cap_out,
+                                                      int32_t up, int32_t dtype, size_t *bytes) {
+  if (!bytes || cin < 1 || cout < 1 || cap_in < 1 || cap_out < 1)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_strided_bwd_workspace_size: bad arguments");
+  size_t a, b, c, d;
+  strided_bwd_layout(cin, cout, cap_in, cap_out, up, dtype, &a, &b, &c, &d, bytes);
+  return NPVS_OK;
+}
+
+extern "C" npvs_status npvs_strided_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
+                                            const float *dY, const int32_t *children, const int32_t *parent,
+                                            int32_t up, const npvs_counts *counts_in, int32_t cap_in,
+                                            const npvs_counts *counts_out, int32_t cap_out, int32_t dtype,
+                                            int32_t relu, float *dX, float *dW, float *db, void *ws, size_t ws_bytes,
+                                            void *stream) {
+  if (!X || !dY || !children || !parent || !counts_in || !counts_out || !dW || !db || !ws || (relu && !Y) ||
+      (dX && !Wt))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_strided_conv_bwd: null pointer");
+  if (cin < 1 || cout < 1 || cap_in < 1 || cap_out < 1)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_strided_conv_bwd: bad sizes");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_strided_conv_bwd: dtype must be NPVS_F32 or NPVS_BF16");
+  if (dtype == NPVS_BF16 && (cin % 8 || cout % 8))
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_strided_conv_bwd: BF16 needs cin % 8 == 0 and cout % 8 == 0");
+  size_t o_pairs, o_off, o_wp, o_dbp, need;
+  strided_bwd_layout(cin, cout, cap_in, cap_out, up, dtype, &o_pairs, &o_off, &o_wp, &o_dbp, &need);
+  if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_strided_conv_bwd: workspace too small");
+  char *w = static_cast<char *>(ws);
+  void *dZ = w;
+  int32_t *pairs = reinterpret_cast<int32_t *>(w + o_pairs), *rb_off = reinterpret_cast<int32_t *>(w + o_off);
+  float *wpart = reinterpret_cast<float *>(w + o_wp), *dbpart = reinterpret_cast<float *>(w + o_dbp);
+  const hipStream_t s = as_stream(stream);
+  npvs_status st = bwd_form_dz(dtype, Y, dY, counts_out, cout, relu, dtype == NPVS_F32 ? (float *)dZ : nullptr,
+                               dtype == NPVS_BF16 ? (uint16_t *)dZ : nullptr, dbpart, s);
+  if (st != NPVS_OK) return st;
+  if (dX) {  // the data gradient is the opposite strided layer with the transposed weights
+    st = npvs_strided_conv_fwd(dZ, cout, Wt, nullptr, cin, up ? children : parent, up ? 0 : 1, counts_in, cap_in,
+                               dtype, 0, 1, dX, stream);
+    if (st != NPVS_OK) return st;
+  }
+  const int cap1 = up ? cap_in : cap_out;
+  strided_pairs_kernel<<<stride_grid(8LL * cap1, 256, 1024), 256, 0, s>>>(children, up ? counts_in : counts_out, cap1,
+                                                                         up ? 1 : 0, rb_off, pairs);
+  st = check_hip(hipGetLastError(), "npvs_strided_conv_bwd");
+  if (st != NPVS_OK) return st;
+  const int S = wg_slices(cin, cout);
+  st = bwd_wgrad(dtype, X, cin, dZ, cout, 8, rb_off, pairs, S, wpart, s);
+  if (st != NPVS_OK) return st;
+  return bwd_reduce(wpart, dbpart, kBwdDbBlocks, 8, S, cin, cout, dW, db, s);
 }

@@ -137,3 +137,104 @@ def test_unet_forward_on_an_empty_grid():
     pvs, logits, lv, occ = unet_pvs(net, tris, counts, cfg.grids)
     assert lv.rb0.host_counts()["n_sites"] == 0 and lv.rb1.host_counts()["n_sites"] == 0
     assert not to_np(pvs).any()
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+@pytest.mark.parametrize("up", [False, True])
+@pytest.mark.parametrize("cin,cout", [(64, 96), (24, 16), (136, 72)])
+def test_strided_conv_bwd_matches_oracle(dtype, up, cin, cout):
+    """dX, dW and db of the strided convolution and of its inverse (ReLU) against the oracle on the
+    same operands (bfloat16-representable X, Y, W; the BF16 products take dZ rounded to bfloat16,
+    the bias gradient the float32 dZ); also deterministic."""
+    dims, d = [(64, 32, 32), (32, 32, 16)], 4
+    tri_list, occ = _grids(dims, [3, 4])
+    lv = npvs.build_levels(occ, dims, d)
+    ch, par, n0, n1 = _oracle_levels(tri_list, dims, d)
+    rng = np.random.default_rng(cin * 1000 + cout + 7 * up)
+    cap_in, cap_out = (lv.rb1.cap, lv.rb0.cap) if up else (lv.rb0.cap, lv.rb1.cap)
+    n_in, n_out = (n1, n0) if up else (n0, n1)
+    X = bf16_round(rng.normal(size=(cap_in, cin))).astype(np.float32)
+    Y = bf16_round(rng.normal(size=(cap_out, cout))).astype(np.float32)
+    dY = rng.normal(size=(cap_out, cout)).astype(np.float32)
+    W = bf16_round(rng.normal(size=(8, cin, cout)) / np.sqrt(8 * cin)).astype(np.float32)
+    tdt = torch.float32 if dtype == npvs.NPVS_F32 else torch.bfloat16
+    Wt = npvs.pack_weights_k(torch.from_numpy(W).to(DEV), dtype, transpose=True)
+    args = (torch.from_numpy(X).to(DEV).to(tdt), Wt, cin, cout, torch.from_numpy(Y).to(DEV).to(tdt),
+            torch.from_numpy(dY).to(DEV), lv, up, dtype)
+    dX, dW, db = npvs.strided_conv_bwd(*args)
+    dX, dW, db = to_np(dX)[:n_in], to_np(dW), to_np(db)
+    dZ = np.where(Y[:n_out] > 0, dY[:n_out], np.float32(0)).astype(np.float64)
+    dZm = dZ if dtype == npvs.NPVS_F32 else bf16_round(dZ)
+    if up:
+        bwd = lambda x, w, g: oracle.inverse_up_bwd(x, par // 8, par % 8, w, Y[:n_out], g, relu=False)
+    else:
+        bwd = lambda x, w, g: oracle.strided_down_bwd(x, ch, w, Y[:n_out], g, relu=False)
+    rX, rW, rb_ = bwd(X[:n_in], W, dZm)
+    aX, aW, _ = bwd(np.abs(X[:n_in]), np.abs(W), np.abs(dZm))
+    u = 2.0 ** -24
+    assert (np.abs(dW - rW) <= 2e-5 * aW + 1e-30).all(), np.abs(dW - rW).max()
+    assert (np.abs(dX - rX) <= 2 * 8 * cout * u * aX + 1e-30).all(), np.abs(dX - rX).max()
+    _, _, rdb = bwd(X[:n_in], W, dZ)
+    assert (np.abs(db - rdb) <= 1e-5 * np.abs(dZ).sum(0) + 1e-30).all()
+    dX2, dW2, db2 = npvs.strided_conv_bwd(*args)
+    np.testing.assert_array_equal(to_np(dW2), dW)
+    np.testing.assert_array_equal(to_np(db2), db)
+    np.testing.assert_array_equal(to_np(dX2)[:n_in], dX)
+
+
+def test_concat_channels_bwd_splits_and_adds():
+    dims, d = [(64, 32, 32)], 4
+    _, occ = _grids(dims, [8])
+    rb = npvs.build_rulebook(occ, dims, d)
+    n = rb.host_counts()["n_sites"]
+    g = torch.Generator(device=DEV).manual_seed(1)
+    dY = torch.randn((rb.cap, 40), device=DEV, generator=g)
+    add = torch.randn((rb.cap, 16), device=DEV, generator=g)
+    dA, dB = npvs.concat_channels_bwd(dY, 24, 16, rb, add_b=add)
+    np.testing.assert_array_equal(to_np(dA)[:n], to_np(dY)[:n, :24])
+    np.testing.assert_array_equal(to_np(dB)[:n], to_np(dY)[:n, 24:] + to_np(add)[:n])
+    _, dB = npvs.concat_channels_bwd(dY, 24, 16, rb, want_a=False)
+    np.testing.assert_array_equal(to_np(dB)[:n], to_np(dY)[:n, 24:])
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_unet_backward_matches_oracle(dtype):
+    """Gradients of BCE + repulsive visibility loss through the whole two-level U-Net against the
+    oracle's FP64 backward.  FP32: max error 1e-4 of the largest gradient.  BF16: every layer
+    rounds its activation (forward) and its dZ (backward) to bfloat16, relative error 2^-9 each,
+    and the gradient of a layer passes at most through the 2 L = 22 roundings of the L = 11
+    layers, so its relative error in norm is bounded at first order by 22 2^-9 = 0.043; the
+    test allows twice that (ReLU masks that flip between the two evaluations add to it)."""
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    g, d = cfg.grids[0], 2
+    params = synth.unet_params(6, d, E=16, Dc=24)
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    lv = npvs.build_levels(occ, cfg.grids, d, csr=True)
+    lab_bits = torch.from_numpy(to_np(occ) & synth.label_mask_bits(5, (to_np(occ).size,))).to(DEV)
+    labels = npvs.gather_input(lab_bits, lv.rb0, npvs.NPVS_U8)
+    net = UNet(params, d, dtype)
+    saved = {}
+    logits = net.forward(npvs.gather_input(occ, lv.rb0, dtype), lv, saved=saved)
+    _, dl = npvs.loss(logits, labels, lv.rb0)
+    grads = net.backward(saved, logits, dl, lv)
+    torch.cuda.synchronize()
+    p64 = {k: [(W.astype(np.float64), b.astype(np.float64)) for W, b in v] for k, v in params.items()}
+    out = oracle.unet_forward(t, g, d, p64, want_logits=False)
+    n = len(out["keys0"])
+    ref_dl = oracle.loss(out["acts"]["Y"], to_np(labels)[:n])["grad"]
+    ref, _ = oracle.unet_backward(out, p64, ref_dl)
+    for st in ref:
+        for i, ((dW, db), (rW, rdb)) in enumerate(zip(grads[st], ref[st])):
+            for a, b, nm in ((to_np(dW), rW, "dW"), (to_np(db), rdb, "db")):
+                scale = np.abs(b).max()
+                rel = np.abs(a - b).max() / scale
+                nrel = np.linalg.norm(a - b) / np.linalg.norm(b)
+                print(f"dtype {dtype} {st}[{i}] {nm}: max rel err {rel:.3e}, norm rel err {nrel:.3e} "
+                      f"(max|g| {scale:.3e})", flush=True)
+                assert scale > 0
+                if dtype == npvs.NPVS_F32:
+                    assert rel <= 1e-4, (st, i, nm)
+                else:
+                    assert nrel <= 2 * 22 * 2.0 ** -9, (st, i, nm)
