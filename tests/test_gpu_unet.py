@@ -290,3 +290,23 @@ def test_unet_backward_matches_oracle(dtype):
                     print(msg + f"; vs same operands norm rel err {nrel:.3e}", flush=True)
                     assert nrel <= 1e-3, (st, i, nm)
                     assert cos >= 0.99, (st, i, nm)
+
+
+def test_unet_backward_on_an_empty_grid_is_zero():
+    """No triangles: no active sites on either level; every gradient is zero (the strided layers'
+    pair lists are empty, every slice partial is zero)."""
+    cfg = synth.config("tiny32")
+    d = 2
+    params = synth.unet_params(6, d, E=16, Dc=24)
+    tris, counts = upload_tris([np.zeros((0, 3, 3), np.float32)])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    lv = npvs.build_levels(occ, cfg.grids, d, csr=True)
+    assert lv.rb0.host_counts()["n_sites"] == 0 and lv.rb1.host_counts()["n_sites"] == 0
+    net = UNet(params, d, npvs.NPVS_BF16)
+    saved = {}
+    logits = net.forward(npvs.gather_input(occ, lv.rb0, npvs.NPVS_BF16), lv, saved=saved)
+    dl = torch.zeros_like(logits)
+    grads = net.backward(saved, logits, dl, lv)
+    for st, layer_grads in grads.items():
+        for dW, db in layer_grads:
+            assert not to_np(dW).any() and not to_np(db).any(), st

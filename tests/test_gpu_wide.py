@@ -161,3 +161,20 @@ def test_network_backward_at_paper_interleave_factors(name):
                 print(f"{name} dtype {dtype} layer {li} {nm}: max rel err {rel:.3e} (max|g| {scale:.3e})", flush=True)
                 assert scale > 0
                 assert rel <= (1e-4 if dtype == npvs.NPVS_F32 else 0.1)
+
+
+@pytest.mark.parametrize("cin,cout", [(512, 64), (64, 4096)])
+def test_conv_bwd_wide_layers_on_an_empty_grid_are_zero(cin, cout):
+    dims = [(64, 64, 64)]
+    tris, counts = upload_tris([np.zeros((0, 3, 3), np.float32)])
+    occ = npvs.froxelize(tris, counts, dims)
+    d = 8 if max(cin, cout) <= 512 else 16
+    rb = npvs.build_rulebook(occ, dims, d, csr=True)
+    assert rb.host_counts()["n_sites"] == 0
+    X = torch.zeros((rb.cap, cin), dtype=torch.bfloat16, device=DEV)
+    Y = torch.zeros((rb.cap, cout), dtype=torch.bfloat16, device=DEV)
+    dY = torch.ones((rb.cap, cout), dtype=torch.float32, device=DEV)
+    W = torch.ones((27, cin, cout), dtype=torch.float32, device=DEV)
+    Wt = npvs.pack_weights(W, npvs.NPVS_BF16, flip_transpose=True)
+    _, dW, db = npvs.sparse_conv_bwd(X, Wt, cin, cout, Y, dY, rb, npvs.NPVS_BF16, relu=True, want_dx=False)
+    assert not to_np(dW).any() and not to_np(db).any()
