@@ -663,6 +663,20 @@ def main():
         torch.cuda.synchronize()
         return [a.elapsed_time(b) for a, b in evs]
 
+    def streamed_launches(launch, reps):
+        """Mean ms per launch of `reps` launches back to back between one pair of events on the
+        launching stream: the GPU runs them one after another, with no event inside the region."""
+        for _ in range(3):
+            launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            launch()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     occ = npvs.froxelize(tris, n_tris, dims)
     rb = npvs.build_rulebook(occ, dims, cfg.d, csr=True)
     Xb = npvs.gather_input(occ, rb, npvs.NPVS_BF16)
@@ -700,8 +714,12 @@ def main():
                  for k, b in stage_bytes.items()}
     print("# stages (median ms per call) " + json.dumps(stage_ms), file=sys.stderr, flush=True)
 
-    # dominant kernel: the BF16 MFMA gather-GEMM (6 forward launches per frame + 3 recomputes)
-    conv_ms = float(np.mean(stage["conv_fwd_bf16"]))
+    # dominant kernel: the BF16 MFMA gather-GEMM (6 forward and 5 data-gradient launches per
+    # frame); its average launch duration from 200 launches back to back (the isolated,
+    # event-bracketed launch of the stage table also counts the events' own overhead)
+    conv_bf16 = lambda: npvs.sparse_conv_fwd(hid_b, net_b.Wp[1], net_b.b[1], 64, 64, rb, npvs.NPVS_BF16, True,
+                                            out=out_b, variant=net_b.variant[1])
+    conv_ms = streamed_launches(conv_bf16, 200)
     flops = 2.0 * n_pairs * 64 * 64
     achieved = flops / (conv_ms * 1e-3) / 1e12
     shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
@@ -712,8 +730,10 @@ def main():
                 "frac": achieved / BF16_PEAK_TFLOPS, "traffic": conv_traffic(net_b.variant[1]),
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel": "conv_fwd_bf16" + shapes[net_b.variant[1]], "avg_launch_ms": conv_ms,
+                "isolated_launch_ms": float(np.mean(stage["conv_fwd_bf16"])),
                 "algorithmic_flops_per_launch": flops, "autotuned_variants": net_b.variant}
-    conv32_ms = float(np.mean(stage["conv_fwd_fp32"]))
+    conv32_ms = streamed_launches(
+        lambda: npvs.sparse_conv_fwd(hid_f, net_f.Wp[1], net_f.b[1], 64, 64, rb, npvs.NPVS_F32, True, out=out_f), 50)
     roofline_fp32 = {"achieved": flops / (conv32_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "avg_launch_ms": conv32_ms}
     roofline_fp32["frac"] = roofline_fp32["achieved"] / FP32_PEAK_TFLOPS

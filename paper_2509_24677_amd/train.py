@@ -71,9 +71,11 @@ class Network:
         return sparse_conv_fwd(X, self.Wp[i], self.b[i], self.channels[i], self.channels[i + 1], rb, self.dtype,
                                relu=not last, out_f32=last, variant=self.variant[i])
 
-    def autotune(self, X0: torch.Tensor, rb: Rulebook, reps: int = 20):
+    def autotune(self, X0: torch.Tensor, rb: Rulebook, reps: int = 20, margin: float = 0.03):
         """Times every BF16 tile shape of each distinct layer shape on the rulebook `rb` (HIP events
-        on the current stream) and keeps the fastest.  Synchronizes."""
+        on the current stream) and keeps the fastest; the library's default shape is kept unless
+        another one is faster by more than `margin` (so that timing noise does not flip the choice
+        between shapes of equal speed from run to run).  Synchronizes."""
         if self.dtype != NPVS_BF16:
             return self.variant
         from ._lib import NPVS_CONV_VARIANTS
@@ -96,9 +98,11 @@ class Network:
                     e1.record()
                     e1.synchronize()
                     t = e0.elapsed_time(e1)
+                    if v == L.NPVS_DEFAULT_CONV_VARIANT:
+                        t_default = t
                     if best is None or t < best[0]:
                         best = (t, v)
-                chosen[key] = best[1]
+                chosen[key] = best[1] if best[0] < (1.0 - margin) * t_default else L.NPVS_DEFAULT_CONV_VARIANT
             self.variant[i] = chosen[key]
             X = self.layer(i, X, rb)
         torch.cuda.synchronize()
