@@ -196,6 +196,16 @@ constexpr int kWgChunk = 128;
 constexpr int kWgPitch = kWgChunk + 16;  // bf16 elements per LDS row (padding spreads banks)
 constexpr int kWgQuads = kWgChunk / 4;
 
+// LDS position of pair p of staged row `row` (a channel): the 16-byte blocks of 8 pairs are
+// permuted within the row by XOR with (row / 8) % 8.  A staging store writes 4 pairs of rows
+// 8 cc + j for 8 channel groups cc at once; the row pitch (72 dwords) puts those 8 rows on the
+// same bank group, and the swizzle moves them onto 8 different ones, while the 16 rows x 4 blocks
+// of an MFMA operand read still cover every bank group equally.  A block stays 16 bytes and
+// aligned, so an operand is one 16-byte read.
+__device__ __forceinline__ int wg_lds_pos(int row, int p) {
+  return row * kWgPitch + ((((p >> 3) ^ (row >> 3)) & 15) << 3) + (p & 7);
+}
+
 struct WgTask {
   int pq, cc;  // pair quad, 8-channel group within X (isx) or dZ
   bool isx, valid;
@@ -242,7 +252,7 @@ __device__ __forceinline__ void wg_store(uint16_t *XT, uint16_t *GT, const WgTas
     const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
     const uint2 pk2 = make_uint2(__builtin_amdgcn_perm(word_of(v[1], j >> 1), word_of(v[0], j >> 1), sel),
                                  __builtin_amdgcn_perm(word_of(v[3], j >> 1), word_of(v[2], j >> 1), sel));
-    *reinterpret_cast<uint2 *>(dst + (8 * t.cc + j) * kWgPitch + 4 * t.pq) = pk2;
+    *reinterpret_cast<uint2 *>(dst + wg_lds_pos(8 * t.cc + j, 4 * t.pq)) = pk2;
   }
 }
 
@@ -335,9 +345,9 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
         const int blk = wv + 4 * j;
         const int mb = blk / OB < 3 ? blk / OB : 3, nb = blk % OB;
         const bf16x8_t a =
-            *reinterpret_cast<const bf16x8_t *>(XT[cur] + (mb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
+            *reinterpret_cast<const bf16x8_t *>(XT[cur] + wg_lds_pos(mb * 16 + (lane & 15), kk + 8 * (lane >> 4)));
         const bf16x8_t b =
-            *reinterpret_cast<const bf16x8_t *>(GT[cur] + (nb * 16 + (lane & 15)) * kWgPitch + kk + 8 * (lane >> 4));
+            *reinterpret_cast<const bf16x8_t *>(GT[cur] + wg_lds_pos(nb * 16 + (lane & 15), kk + 8 * (lane >> 4)));
         acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
       }
     }
