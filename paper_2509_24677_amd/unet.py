@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import torch
 
-from . import (NPVS_BF16, NPVS_F32, Levels, build_levels, concat_channels, concat_channels_bwd,
+from . import (NPVS_BF16, NPVS_F32, Levels, build_levels, concat_channels, concat_channels_bwd, conv_bwd_workspace,
                deinterleave_threshold, froxelize, gather_input, pack_weights, pack_weights_k, sparse_conv_bwd,
                sparse_conv_fwd, strided_conv_bwd, strided_conv_fwd)
 
@@ -99,12 +99,23 @@ class UNet:
                                 pack_weights(W, self.dtype, flip_transpose=True))
         return self.Wt[(st, i)]
 
-    def backward(self, saved: dict, logits: torch.Tensor, dlogits: torch.Tensor, lv: Levels) -> dict:
+    def backward(self, saved: dict, logits: torch.Tensor, dlogits: torch.Tensor, lv: Levels,
+                 overlap: bool = True) -> dict:
         """Gradients {stage: [(dW, db), ...]} (float32) of the loss whose gradient with respect to
         the logits rows is `dlogits` (float32 [rb0.cap][d^3]), through the activations kept by
-        forward(saved=...).  The levels must carry CSR rulebooks (build_levels(csr=True))."""
+        forward(saved=...).  The levels must carry CSR rulebooks (build_levels(csr=True)).  With
+        `overlap`, the weight gradients of the 3^3 layers run on a side stream (their final
+        reductions on a third) while the data gradients continue; both are joined before
+        returning."""
         dt = self.dtype
         rb0, rb1 = lv.rb0, lv.rb1
+        main = torch.cuda.current_stream()
+        side = side2 = None
+        if overlap:
+            if getattr(self, "_side", None) is None:
+                self._side, self._side2 = torch.cuda.Stream(), torch.cuda.Stream()
+            side, side2 = self._side, self._side2
+        in_use = []  # tensors the side streams read: alive until they are joined
         outs = {"stem": saved["stem"][1:] + [saved["enc0"][0]], "enc0": saved["enc0"][1:] + [saved["down"][0]],
                 "enc1": saved["enc1"][1:] + [saved["up"][0]], "dec0": saved["dec0"][1:] + [saved["head"][0]],
                 "head": [logits]}
@@ -113,8 +124,11 @@ class UNet:
         def subm_chain(st, dY, rb, last_is_head=False, want_dx=True):
             for i in range(len(self.layers[st]) - 1, -1, -1):
                 _, _, cin, cout = self.layers[st][i]
+                ws = conv_bwd_workspace(cin, cout, rb, dt)
                 dX, dW, db = sparse_conv_bwd(saved[st][i], self._wt(st, i), cin, cout, outs[st][i], dY, rb, dt,
-                                             relu=not last_is_head, want_dx=want_dx or i > 0)
+                                             relu=not last_is_head, want_dx=want_dx or i > 0, ws=ws,
+                                             wgrad_stream=side, reduce_stream=side2)
+                in_use.extend((ws, saved[st][i]))
                 grads[st][i] = (dW, db)
                 dY = dX
             return dY
@@ -133,6 +147,10 @@ class UNet:
         _, dS = concat_channels_bwd(dH, Dc, E, rb0, add_b=dX0, want_a=False)
         dS = subm_chain("enc0", dS, rb0)
         subm_chain("stem", dS, rb0, want_dx=False)
+        if side is not None:
+            main.wait_stream(side)
+            main.wait_stream(side2)
+        del in_use
         return grads
 
 
