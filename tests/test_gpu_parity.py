@@ -339,7 +339,7 @@ def test_network_f32_logits_within_1e5_of_fp64_oracle(name):
     assert err <= 1e-5
     pvs, _ = npvs.deinterleave_threshold(Y, rb, occ)
     # bits agree wherever the oracle's logit is farther than the error bound from the threshold
-    got = oracle.unpack(to_np(pvs).reshape(out["pvs"].shape))
+    got = np.unpackbits(to_np(pvs).reshape(out["pvs"].shape), axis=-1, bitorder="little")
     want = oracle.unpack(out["pvs"])
     near = np.abs(np.nan_to_num(out["logits"], neginf=-1e9)) <= 1e-5
     assert ((got == want) | near).all()
@@ -362,8 +362,7 @@ def test_network_bf16_close_to_fp64_oracle_c2():
     assert err_b.max() < 0.1
     pb, _ = npvs.deinterleave_threshold(Yb, rb, occ)
     pf, _ = npvs.deinterleave_threshold(Yf, rb, occ)
-    vb, vf = oracle.unpack(to_np(pb)), oracle.unpack(to_np(pf))
-    g = oracle.unpack(to_np(occ))
+    vb, vf, g = (np.unpackbits(to_np(x), bitorder="little") for x in (pb, pf, occ))
     flips = ((vb != vf) & (g == 1)).sum() / g.sum()
     missing = ((vf == 1) & (vb == 0)).sum() / max(vf.sum(), 1)
     print(f"bf16 vs fp32: flip rate over occupied froxels {flips:.5f}, missing-geometry rate {missing:.5f}", flush=True)

@@ -8,8 +8,16 @@ import oracle
 import paper_2509_24677_amd as npvs
 import synth
 from gpu_util import DEV, oracle_batch, to_np, upload_tris
+from paper_2509_24677_amd.train import Network
 
 pytestmark = pytest.mark.gpu
+
+
+def _oracle_labels(out, dims, d, label_seed=5):
+    """The oracle's labels: the same seeded mask over the oracle's own occupancy, interleaved by
+    the oracle (no GPU output enters the reference)."""
+    occ = out["occ"].reshape(-1)
+    return oracle.site_labels(occ & synth.label_mask_bits(label_seed, (occ.size,)), dims, d, out["keys"])
 
 
 def _setup(name="tiny32", layers=None, label_seed=5):
@@ -73,14 +81,21 @@ def _bf16_bits(a):
     return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
 
 
-def test_loss_matches_oracle():
+def _loss_inputs(seed):
+    """One tiny32 grid's rulebook and seeded logits and labels (the same arrays on both sides)."""
     cfg, t, layers, occ, rb, lab_bits = _setup()
-    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
-    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
-    stats, dl = npvs.loss(acts[-1], labels, rb, lam=0.99)
+    rng = np.random.default_rng(seed)
+    C = cfg.d ** 3
+    L = (3.0 * rng.normal(size=(rb.cap, C))).astype(np.float32)
+    Y = (rng.random((rb.cap, C)) < 0.3).astype(np.uint8)
+    return cfg, rb, L, Y
+
+
+def test_loss_matches_oracle():
+    cfg, rb, L, Y = _loss_inputs(11)
+    stats, dl = npvs.loss(torch.from_numpy(L).to(DEV), torch.from_numpy(Y).to(DEV), rb, lam=0.99)
     n = rb.host_counts()["n_sites"]
-    l64 = to_np(acts[-1])[:n].astype(np.float64)
-    ref = oracle.loss(l64, to_np(labels)[:n], lam=0.99)
+    ref = oracle.loss(L[:n].astype(np.float64), Y[:n], lam=0.99)
     s = to_np(stats)[0]
     for i, key in enumerate(["loss", "bce", "lrv", "tp", "fn", "fp", "gtp"]):
         assert abs(s[i] - ref[key]) <= 2e-6 * max(1.0, abs(ref[key])), (key, s[i], ref[key])
@@ -113,12 +128,10 @@ def test_loss_batched_mean_over_grids():
 
 @pytest.mark.parametrize("alpha", [0.9, 0.5])
 def test_dice_loss_matches_oracle(alpha):
-    cfg, t, layers, occ, rb, lab_bits = _setup()
-    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_F32)
-    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
-    stats, dl = npvs.loss(acts[-1], labels, rb, lam=0.99, dice_alpha=alpha)
+    cfg, rb, L, Y = _loss_inputs(12)
+    stats, dl = npvs.loss(torch.from_numpy(L).to(DEV), torch.from_numpy(Y).to(DEV), rb, lam=0.99, dice_alpha=alpha)
     n = rb.host_counts()["n_sites"]
-    ref = oracle.loss_dice(to_np(acts[-1])[:n].astype(np.float64), to_np(labels)[:n], lam=0.99, alpha=alpha)
+    ref = oracle.loss_dice(L[:n].astype(np.float64), Y[:n], lam=0.99, alpha=alpha)
     s = to_np(stats)[0]
     for i, key in enumerate(["loss", "dice", "lrv", "tp", "fn", "fp", "gtp"]):
         assert abs(s[i] - ref[key]) <= 2e-6 * max(1.0, abs(ref[key])), (key, s[i], ref[key])
@@ -155,8 +168,7 @@ def test_backward_f32_matches_oracle_gradient():
     _, dl = npvs.loss(acts[-1], labels, rb)
     grads = _gpu_backward(acts, rb, layers, npvs.NPVS_F32, dl)
     out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
-    n = len(out["keys"])
-    lab = to_np(labels)[:n]
+    lab = _oracle_labels(out, cfg.grids[0], cfg.d)
     ref_dl = oracle.loss(out["acts"][-1], lab)["grad"]
     ref, _ = oracle.backward(out, layers, ref_dl)
     for li in range(len(layers)):
@@ -173,9 +185,9 @@ def test_backward_matches_fp64_finite_differences():
     labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
     _, dl = npvs.loss(acts[-1], labels, rb)
     grads = _gpu_backward(acts, rb, layers, npvs.NPVS_F32, dl)
-    n = rb.host_counts()["n_sites"]
-    lab = to_np(labels)[:n]
-    occ_np = to_np(occ).reshape(cfg.grids[0][2], cfg.grids[0][1], -1)
+    occ_np, _ = oracle.froxelize(t, cfg.grids[0])  # the oracle's own occupancy, reused by every evaluation
+    lab = _oracle_labels(oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False, occ=occ_np),
+                         cfg.grids[0], cfg.d)
     rng = np.random.default_rng(0)
     h = 1e-5
     checked = 0
@@ -210,8 +222,7 @@ def test_backward_bf16_close_to_oracle_and_deterministic():
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
     out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
-    n = len(out["keys"])
-    ref_dl = oracle.loss(out["acts"][-1], to_np(labels)[:n])["grad"]
+    ref_dl = oracle.loss(out["acts"][-1], _oracle_labels(out, cfg.grids[0], cfg.d))["grad"]
     ref, _ = oracle.backward(out, layers, ref_dl)
     for li in range(len(layers)):
         rel = np.abs(g1[li][0] - ref[li][0]).max() / np.abs(ref[li][0]).max()
@@ -292,3 +303,41 @@ def test_adam_with_device_step_equals_host_step():
     for x, y in zip(a, b):
         np.testing.assert_array_equal(to_np(x), to_np(y))
     assert int(step[:8].view(torch.int64).item()) == 4
+
+
+def test_city256_training_gradients_at_full_size():
+    """The benchmark's workload at full size (256x256x128 city frame, six 64-channel layers, the
+    launch configuration of its training step: per-layer backward with the weight gradients on
+    side streams) against the oracle's FP64 forward and backward.  FP32: every dW and db within
+    2e-4 of the largest entry.  BF16: activations and dZ are rounded to bfloat16 at every layer
+    and a ReLU whose input lies within that rounding of zero can switch, so the check is the
+    direction and size of each gradient: cosine at least 0.99, norm error at most 10 %."""
+    cfg = synth.config("city256")
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
+    label_mask = synth.label_mask_bits(7, (cfg.grids[0][0] * cfg.grids[0][1] * cfg.grids[0][2] // 8,))
+    out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
+    n = len(out["keys"])
+    assert n == rb.host_counts()["n_sites"] == 9706
+    lab_bits = torch.from_numpy(to_np(occ) & label_mask).to(DEV)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    ref_lab = oracle.site_labels(out["occ"].reshape(-1) & label_mask, cfg.grids[0], cfg.d, out["keys"])
+    ref_dl = oracle.loss(out["acts"][-1], ref_lab)["grad"]
+    ref, _ = oracle.backward(out, layers, ref_dl)
+    for dtype in (npvs.NPVS_F32, npvs.NPVS_BF16):
+        net = Network(layers, cfg.d, dtype)
+        logits, saved = net.forward(npvs.gather_input(occ, rb, dtype), rb)
+        _, dl = npvs.loss(logits, labels, rb)
+        grads = [(to_np(a), to_np(b)) for a, b in net.backward(saved, logits, dl, rb)]
+        for li in range(len(layers)):
+            for a, b, nm in ((grads[li][0], ref[li][0], "dW"), (grads[li][1], ref[li][1], "db")):
+                if dtype == npvs.NPVS_F32:
+                    assert np.abs(a - b).max() <= 2e-4 * np.abs(b).max(), (li, nm)
+                    continue
+                cos = float((a * b).sum() / (np.linalg.norm(a) * np.linalg.norm(b)))
+                nrel = np.linalg.norm(a - b) / np.linalg.norm(b)
+                print(f"city256 bf16 layer {li} {nm}: cosine {cos:.5f}, norm rel err {nrel:.3e}", flush=True)
+                assert cos >= 0.99 and nrel <= 0.1, (li, nm)

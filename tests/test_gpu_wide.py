@@ -145,7 +145,9 @@ def test_network_backward_at_paper_interleave_factors(name):
     labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
     out = oracle.forward(t, cfg.grids[0], cfg.d, layers, want_logits=False)
     n = len(out["keys"])
-    ref_dl = oracle.loss(out["acts"][-1], to_np(labels)[:n])["grad"]
+    o = out["occ"].reshape(-1)
+    ref_lab = oracle.site_labels(o & synth.label_mask_bits(5, (o.size,)), cfg.grids[0], cfg.d, out["keys"])
+    ref_dl = oracle.loss(out["acts"][-1], ref_lab)["grad"]
     ref, _ = oracle.backward(out, layers, ref_dl)
     for dtype in (npvs.NPVS_F32, npvs.NPVS_BF16):
         net = Network(layers, cfg.d, dtype)
