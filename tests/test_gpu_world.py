@@ -24,8 +24,12 @@ def _as_dict(v):
 
 
 def _check(tris, view, dims):
+    """view: (the library's frustum, the oracle's frustum of the same camera)."""
+    view, vd = view
+    lib = _as_dict(view)  # the library's frustum equals the oracle's
+    for k in vd:
+        np.testing.assert_allclose(lib[k], vd[k], rtol=1e-12, atol=1e-12, err_msg=k)
     got = to_np(npvs.froxelize_view(torch.from_numpy(tris).to(DEV), view, dims)).reshape(dims[2], dims[1], -1)
-    vd = _as_dict(view)
     bits = lambda occ: np.unpackbits(occ, axis=-1, bitorder="little")
     exact, n = oracle.froxelize_view(tris, vd, dims)
     inner = bits(oracle.froxelize_view(tris, vd, dims, margin=-1e-9)[0])
@@ -40,8 +44,10 @@ def _check(tris, view, dims):
 
 
 def _paper_view(c, zf=1000.0):
-    # Sec. 4.3 camera: 60 degree field of view, 15 degrees of rotation (90 degree grid), near 0.3
-    return npvs.viewcell_frustum(c, [0.0, 0.0, 1.0], [0.0, 1.0, 0.0], math.pi / 3, 1.0, 0.6, math.pi / 12, 0.3, zf)
+    """Sec. 4.3 camera: 60 degree field of view, 15 degrees of rotation (90 degree grid), near 0.3;
+    the library's frustum and, computed on the oracle side, the oracle's."""
+    args = (c, [0.0, 0.0, 1.0], [0.0, 1.0, 0.0], math.pi / 3, 1.0, 0.6, math.pi / 12, 0.3, zf)
+    return npvs.viewcell_frustum(*args), oracle.viewcell_view(*args)
 
 
 @pytest.mark.parametrize("dims", [(64, 64, 64), (96, 40, 70)])
@@ -60,7 +66,7 @@ def test_city_frame_in_world_space():
 
 
 def test_no_triangles_and_triangles_behind_the_camera():
-    view = _paper_view([0.0, 0.0, 0.0], zf=20.0)
+    view, _ = _paper_view([0.0, 0.0, 0.0], zf=20.0)
     occ = npvs.froxelize_view(torch.zeros((0, 3, 3), dtype=torch.float32, device=DEV), view, (32, 32, 32))
     assert not to_np(occ).any()
     behind = np.array([[[-1, -1, -3.0], [1, -1, -3.0], [0, 1, -2.5]]], np.float32)
