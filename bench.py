@@ -769,9 +769,10 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        lab_np = (occ_np & synth.label_mask_bits(7, (total_bytes,))).reshape(dims[0][2], dims[0][1], -1)
         t0 = time.perf_counter()
         out = oracle.forward(tris_np, dims[0], cfg.d, layers)
+        # the labels: the same seeded subset, of the oracle's own occupancy
+        lab_np = out["occ"] & synth.label_mask_bits(7, (total_bytes,)).reshape(out["occ"].shape)
         site_lab = oracle.site_labels(lab_np, dims[0], cfg.d, out["keys"])
         dl = oracle.loss(out["acts"][-1], site_lab)["grad"]
         oracle.backward(out, layers, dl)
