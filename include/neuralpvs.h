@@ -448,6 +448,22 @@ typedef struct {
 npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step, float lr,
                           float beta1, float beta2, float eps, float weight_decay, void *stream);
 
+/* npvs_adam_dev that also writes each listed layer's updated weights into its two packings, in
+ * the same pass: Wp = npvs_pack_weights(W, ..., flip_transpose = 0) and Wt = the flip_transpose
+ * = 1 packing (forward and data gradient), both of npvs_packed_weight_bytes(cin, cout, dtype)
+ * bytes and packed once before (their padding entries are not rewritten).  Layer l's weight
+ * [27][cin][cout] is p[off, off + 27 cin cout); layers must not overlap; at most
+ * NPVS_MAX_ADAM_PACK layers.  The result equals npvs_adam_dev followed by the two packings. */
+#define NPVS_MAX_ADAM_PACK 32
+typedef struct {
+  int64_t off;       /* first entry of the layer's weight in p */
+  int32_t cin, cout;
+  void *Wp, *Wt;     /* (device) the forward and the flipped-transpose packing */
+} npvs_adam_pack_desc;
+npvs_status npvs_adam_dev_pack(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
+                               float lr, float beta1, float beta2, float eps, float weight_decay, int32_t n_layers,
+                               const npvs_adam_pack_desc *layers, int32_t dtype, void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Whole forward pass V = threshold(g_d^-1(f(g_d(froxelize(tris))))) through a library-owned
  * plan that holds the workspace, the site table, the activations and the packed weights of a

@@ -471,6 +471,21 @@ def adam(p, g, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_d
            float(eps), float(weight_decay), _stream())
 
 
+def adam_dev_pack(p, g, m, v, step: torch.Tensor, layers, dtype: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                  weight_decay=1e-10):
+    """adam_dev that also writes the updated weights into their packings: layers = [(offset in p,
+    cin, cout, Wp, Wt)] with Wp / Wt the forward and flipped-transpose packings (npvs_adam_dev_pack)."""
+    if step.numel() * step.element_size() != 16:
+        raise ValueError("step must hold 16 bytes (npvs_adam_step)")
+    if len(layers) > L.NPVS_MAX_ADAM_PACK:
+        raise ValueError(f"at most {L.NPVS_MAX_ADAM_PACK} layers")
+    descs = (L.AdamPackDesc * max(len(layers), 1))()
+    for i, (off, cin, cout, Wp, Wt) in enumerate(layers):
+        descs[i] = L.AdamPackDesc(int(off), int(cin), int(cout), Wp.data_ptr(), Wt.data_ptr())
+    L.call("npvs_adam_dev_pack", _p(p), _p(g), _p(m), _p(v), p.numel(), _p(step), float(lr), float(beta1),
+           float(beta2), float(eps), float(weight_decay), len(layers), descs, dtype, _stream())
+
+
 def adam_dev(p, g, m, v, step: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-10):
     """Adam with the step counter on the device: `step` is a 16-byte npvs_adam_step (uint8
     tensor, zero to start), advanced by the call (so graph replays keep counting)."""

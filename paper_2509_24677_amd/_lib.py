@@ -22,6 +22,7 @@ NPVS_MAX_GRIDS = 32
 NPVS_CONV_VARIANTS = 14
 NPVS_DEFAULT_CONV_VARIANT = 12
 NPVS_MAX_PACK = 64
+NPVS_MAX_ADAM_PACK = 32
 NPVS_BWD_DB_PARTS = 512
 NPVS_LOSS_BCE = 0
 NPVS_LOSS_DICE = 1
@@ -51,6 +52,11 @@ class View(ctypes.Structure):
     _fields_ = [("eye", ctypes.c_double * 3), ("right", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
                 ("forward", ctypes.c_double * 3), ("tan_half_x", ctypes.c_double), ("tan_half_y", ctypes.c_double),
                 ("z_near", ctypes.c_double), ("z_far", ctypes.c_double)]
+
+
+class AdamPackDesc(ctypes.Structure):
+    _fields_ = [("off", ctypes.c_int64), ("cin", ctypes.c_int32), ("cout", ctypes.c_int32), ("Wp", ctypes.c_void_p),
+                ("Wt", ctypes.c_void_p)]
 
 
 P = ctypes.c_void_p
@@ -104,6 +110,7 @@ SIGNATURES = {
     "npvs_loss_ex": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, P]),
     "npvs_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, f32, P]),
     "npvs_adam_dev": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, P]),
+    "npvs_adam_dev_pack": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, i32, P, i32, P]),
     "npvs_plan_create": (i32, [i32, P, P, i32, i32, P, i32, ctypes.POINTER(P)]),
     "npvs_plan_destroy": (i32, [P]),
     "npvs_plan_set_weights": (i32, [P, i32, P, P, P]),

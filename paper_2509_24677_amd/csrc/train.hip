@@ -165,6 +165,58 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const 
   }
 }
 
+// Adam over the flat parameter buffer with the updated weights written straight into their
+// packed forms (the forward packing and the flipped-transpose packing of the data gradient), so
+// no separate packing pass follows the optimizer step.  Layer l's weight W[27][cin][cout] sits at
+// flat offset off; its entry (k, c, o) is P[k][c][o] of the forward packing and P'[26-k][o][c]
+// of the flipped one (CI x CO = cout x cin).  BF16 packing: fragment entry
+// ((k NB + o / 16) KB + c / 32) 512 + (o % 16 + 16 ((c % 32) / 8)) 8 + c % 8, NB = ceil(CO / 16),
+// KB = ceil(CI / 32), rounded to nearest even; FP32: [k][c][o].  Padding entries keep the zeros
+// of the first packing.
+struct AdamPack {
+  int32_t n;
+  npvs_adam_pack_desc L[NPVS_MAX_ADAM_PACK];
+};
+
+__device__ __forceinline__ int64_t packed_index(int k, int c, int o, int CI, int CO, int dtype) {
+  if (dtype == NPVS_F32) return ((int64_t)k * CI + c) * CO + o;
+  const int KB = (CI + 31) / 32, NB = (CO + 15) / 16;
+  return (((int64_t)k * NB + o / 16) * KB + c / 32) * 512 + ((o & 15) + 16 * ((c & 31) >> 3)) * 8 + (c & 7);
+}
+
+__device__ __forceinline__ void store_packed(void *P, int64_t e, float w, int dtype) {
+  if (dtype == NPVS_F32)
+    static_cast<float *>(P)[e] = w;
+  else
+    static_cast<uint16_t *>(P)[e] = f32_to_bf16(w);
+}
+
+__global__ __launch_bounds__(256) void adam_pack_kernel(float *__restrict__ p, const float *__restrict__ g,
+                                                         float *__restrict__ m, float *__restrict__ v, int64_t n,
+                                                         float lr, float b1, float b2, float eps, float wd,
+                                                         const npvs_adam_step *__restrict__ coef, AdamPack AP,
+                                                         int dtype) {
+  const float c1 = coef->c1, c2 = coef->c2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i] + wd * p[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float w = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = w;
+    for (int l = 0; l < AP.n; ++l) {
+      const npvs_adam_pack_desc &D = AP.L[l];
+      const int64_t e = i - D.off;
+      if (e < 0 || e >= 27LL * D.cin * D.cout) continue;
+      const int o = (int)(e % D.cout), c = (int)((e / D.cout) % D.cin), k = (int)(e / ((int64_t)D.cin * D.cout));
+      store_packed(D.Wp, packed_index(k, c, o, D.cin, D.cout, dtype), w, dtype);
+      store_packed(D.Wt, packed_index(26 - k, o, c, D.cout, D.cin, dtype), w, dtype);
+      break;
+    }
+  }
+}
+
 __global__ void adam_step_kernel(npvs_adam_step *st, float b1, float b2) {
   const int64_t t = st->t + 1;
   st->t = t;
@@ -236,4 +288,35 @@ extern "C" npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *
     adam_kernel<<<stride_grid(n, 256, 2048), 256, 0, s>>>(p, g, m, v, n, lr, beta1, beta2, eps, weight_decay, 0.0f,
                                                           0.0f, step);
   return check_hip(hipGetLastError(), "npvs_adam_dev");
+}
+
+extern "C" npvs_status npvs_adam_dev_pack(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
+                                         float lr, float beta1, float beta2, float eps, float weight_decay,
+                                         int32_t n_layers, const npvs_adam_pack_desc *layers, int32_t dtype,
+                                         void *stream) {
+  if (!p || !g || !m || !v || !step || n < 0 || (n_layers && !layers))
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: bad arguments");
+  if (n_layers < 0 || n_layers > NPVS_MAX_ADAM_PACK)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: 0 to NPVS_MAX_ADAM_PACK layers");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: dtype must be NPVS_F32 or NPVS_BF16");
+  AdamPack AP = {};
+  AP.n = n_layers;
+  for (int l = 0; l < n_layers; ++l) {
+    const npvs_adam_pack_desc &D = layers[l];
+    if (!D.Wp || !D.Wt || D.cin < 1 || D.cout < 1 || D.off < 0 || D.off + 27LL * D.cin * D.cout > n)
+      return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: layer outside the parameter buffer");
+    for (int q = 0; q < l; ++q) {
+      const npvs_adam_pack_desc &E = layers[q];
+      if (D.off < E.off + 27LL * E.cin * E.cout && E.off < D.off + 27LL * D.cin * D.cout)
+        return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: overlapping layers");
+    }
+    AP.L[l] = D;
+  }
+  hipStream_t s = as_stream(stream);
+  adam_step_kernel<<<1, 1, 0, s>>>(step, beta1, beta2);
+  if (n > 0)
+    adam_pack_kernel<<<stride_grid(n, 256, 2048), 256, 0, s>>>(p, g, m, v, n, lr, beta1, beta2, eps, weight_decay,
+                                                               step, AP, dtype);
+  return check_hip(hipGetLastError(), "npvs_adam_dev_pack");
 }

@@ -17,7 +17,7 @@ from __future__ import annotations
 import torch
 
 from . import _lib as L
-from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam_dev, build_rulebook, conv_bwd_begin,
+from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam_dev, adam_dev_pack, build_rulebook, conv_bwd_begin,
                conv_bwd_chain_workspace, conv_bwd_workspace, deinterleave_threshold, froxelize, gather_input, loss,
                pack_weights, pack_weights_batch, sparse_conv_bwd, sparse_conv_bwd_chain, sparse_conv_fwd)
 
@@ -52,6 +52,15 @@ class Network:
     @property
     def n_layers(self):
         return len(self.W)
+
+    def pack_descs(self):
+        """[(offset in the flat buffer, cin, cout, Wp, Wt)] per layer, for the optimizer step that
+        writes the packings itself."""
+        out, off = [], 0
+        for i, W in enumerate(self.W):
+            out.append((off, W.shape[1], W.shape[2], self.Wp[i], self.Wt[i]))
+            off += W.numel()
+        return out
 
     def repack(self):
         """Packs every layer for the forward and the data-gradient convolutions in one launch,
@@ -233,8 +242,9 @@ class Trainer:
         stats, dl = loss(logits, labels, rb, self.lam, dice_alpha=self.dice_alpha)
         net.backward(saved, logits, dl, rb)  # gradients land in net.gflat
         self.step_count += 1
-        adam_dev(net.flat, net.gflat, self.m, self.v, self.adam_step, lr=self.lr, weight_decay=self.wd)
-        net.repack()
+        # Adam, writing the updated weights straight into both packings of every layer
+        adam_dev_pack(net.flat, net.gflat, self.m, self.v, self.adam_step, net.pack_descs(), net.dtype, lr=self.lr,
+                      weight_decay=self.wd)
         return stats, pvs
 
 

@@ -36,9 +36,9 @@ def test_version_and_sizes(lib):
 def test_header_constants_match_binding():
     text = open(L.HEADER).read()
     for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT",
-                 "NPVS_BWD_DB_PARTS", "NPVS_LOSS_BCE", "NPVS_LOSS_DICE"):
+                 "NPVS_BWD_DB_PARTS", "NPVS_LOSS_BCE", "NPVS_LOSS_DICE", "NPVS_MAX_ADAM_PACK"):
         assert f"#define {name} {getattr(L, name)}" in text, name
-    assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16
+    assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16 and ctypes.sizeof(L.AdamPackDesc) == 32
     assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes
 
 
@@ -61,6 +61,25 @@ def test_batched_packing_argument_checks(lib):
     d = (L.PackDesc * 1)(L.PackDesc(None, None, 8, 8, 0, 0))
     assert lib.npvs_pack_weights_batch(1, ctypes.cast(d, ctypes.c_void_p), L.NPVS_BF16, None) == L.NPVS_ERR_INVALID_ARG
     assert b"null pointer" in lib.npvs_last_error()
+
+
+def test_adam_pack_argument_checks(lib):
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(descs, n=1000, nl=None):
+        arr = (L.AdamPackDesc * len(descs))(*descs) if descs else None
+        return lib.npvs_adam_dev_pack(fake, fake, fake, fake, n, fake, 1e-3, 0.9, 0.999, 1e-8, 0.0,
+                                      len(descs) if nl is None else nl, arr, L.NPVS_BF16, None)
+
+    assert call([], nl=L.NPVS_MAX_ADAM_PACK + 1) == L.NPVS_ERR_INVALID_ARG
+    # a layer reaching past the parameter buffer (27 * 8 * 8 = 1728 > 1000)
+    assert call([L.AdamPackDesc(0, 8, 8, 0x2000, 0x3000)]) == L.NPVS_ERR_INVALID_ARG
+    assert b"outside" in lib.npvs_last_error()
+    # overlapping layers
+    d = [L.AdamPackDesc(0, 4, 4, 0x2000, 0x3000), L.AdamPackDesc(100, 4, 4, 0x4000, 0x5000)]
+    assert call(d) == L.NPVS_ERR_INVALID_ARG and b"overlapping" in lib.npvs_last_error()
+    # missing packing buffer
+    assert call([L.AdamPackDesc(0, 4, 4, 0x2000, None)]) == L.NPVS_ERR_INVALID_ARG
 
 
 def test_backward_chain_argument_checks(lib):

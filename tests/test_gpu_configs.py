@@ -166,9 +166,11 @@ def test_trainer_step_applies_adam_to_the_gradient():
         m, v = torch.zeros_like(p), torch.zeros_like(p)
         npvs.adam(p, grads[li][0].contiguous(), m, v, 1)
         assert np.abs(to_np(net.W[li]) - to_np(p)).max() <= 1e-6
-    # the packed weights follow the masters
-    Wp = npvs.pack_weights(net.W[0], npvs.NPVS_BF16)
-    np.testing.assert_array_equal(to_np(net.Wp[0]), to_np(Wp))
+    # both packings of every layer follow the masters (the optimizer step writes them)
+    for li in range(len(layers)):
+        for packed, flip in ((net.Wp[li], False), (net.Wt[li], True)):
+            want = npvs.pack_weights(net.W[li], npvs.NPVS_BF16, flip_transpose=flip)
+            np.testing.assert_array_equal(to_np(packed), to_np(want))
     assert np.isfinite(to_np(stats)).all()
 
 

@@ -341,3 +341,43 @@ def test_city256_training_gradients_at_full_size():
                 nrel = np.linalg.norm(a - b) / np.linalg.norm(b)
                 print(f"city256 bf16 layer {li} {nm}: cosine {cos:.5f}, norm rel err {nrel:.3e}", flush=True)
                 assert cos >= 0.99 and nrel <= 0.1, (li, nm)
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_adam_with_packing_equals_adam_then_packing(dtype):
+    """npvs_adam_dev_pack over two steps equals npvs_adam_dev followed by both packings of each
+    layer, bit for bit (channel counts with padded BF16 fragments included)."""
+    rng = np.random.default_rng(21)
+    shapes = [(24, 40), (64, 8), (16, 136)]
+    sizes = [27 * a * b for a, b in shapes]
+    n = sum(sizes) + 300  # a tail of parameters that are not packed weights (biases)
+    p0 = rng.normal(size=n).astype(np.float32)
+    offs = np.concatenate([[0], np.cumsum(sizes)])[:-1]
+
+    def run(fused):
+        p, m, v = (torch.from_numpy(x).to(DEV) for x in (p0.copy(), np.zeros(n, np.float32), np.zeros(n, np.float32)))
+        step = torch.zeros(16, dtype=torch.uint8, device=DEV)
+        packs = []
+        for (a, b), o in zip(shapes, offs):
+            W = p[o:o + 27 * a * b].view(27, a, b)
+            packs.append((npvs.pack_weights(W, dtype), npvs.pack_weights(W, dtype, flip_transpose=True)))
+        for t in range(2):
+            g = torch.from_numpy(np.random.default_rng(30 + t).normal(size=n).astype(np.float32)).to(DEV)
+            if fused:
+                npvs.adam_dev_pack(p, g, m, v, step, [(o, a, b, wp, wt) for (a, b), o, (wp, wt) in
+                                                      zip(shapes, offs, packs)], dtype)
+            else:
+                npvs.adam_dev(p, g, m, v, step)
+                for (a, b), o, (wp, wt) in zip(shapes, offs, packs):
+                    W = p[o:o + 27 * a * b].view(27, a, b)
+                    wp.copy_(npvs.pack_weights(W, dtype))
+                    wt.copy_(npvs.pack_weights(W, dtype, flip_transpose=True))
+        torch.cuda.synchronize()
+        return to_np(p), [(to_np(wp), to_np(wt)) for wp, wt in packs]
+
+    pa, ka = run(True)
+    pb, kb = run(False)
+    np.testing.assert_array_equal(pa, pb)
+    for (wa, ta), (wb, tb) in zip(ka, kb):
+        np.testing.assert_array_equal(wa, wb)
+        np.testing.assert_array_equal(ta, tb)
