@@ -249,7 +249,9 @@ class Trainer:
 
 
 class SubMConvFn(torch.autograd.Function):
-    """Y = act(b + sum_k gather_k(X) W_k) over a rulebook, differentiable in X, W and b."""
+    """Y = act(b + sum_k gather_k(X) W_k) over a rulebook (built with csr=True), differentiable in
+    X, W and b through the hand-written backward.  Rows of dX past the active sites are left
+    undefined, as are those of Y."""
 
     @staticmethod
     def forward(ctx, X, W, b, rb: Rulebook, dtype: int, relu: bool, out_f32: bool):
