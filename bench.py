@@ -151,6 +151,57 @@ def bench_batch16(args, dev, timed_launches):
             "conv_fwd_bf16_frac_of_peak": flops / (conv_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
 
 
+def bench_train4(args, dev):
+    """The batch-of-four training configuration: one training step (froxelize, rulebook, forward
+    with every second layer input recomputed in the backward, loss, backward, Adam) over four
+    128^3 grids of seeded boxes (3.5-4.1 % occupied), captured as one graph, in BF16 and FP32.
+    Labels are a fixed subset of the occupied froxels (timing does not depend on their values)."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+    from paper_2509_24677_amd.train import Network, Trainer
+
+    cfg = synth.config("train128x4")
+    tri_list = [synth.scene_for(cfg, i) for i in range(len(cfg.grids))]
+    tris = torch.from_numpy(np.concatenate([t.reshape(-1) for t in tri_list]).astype(np.float32)).to(dev)
+    counts = [len(t) for t in tri_list]
+    layers = synth.net_layers(cfg)
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    lab = occ & torch.from_numpy(synth.label_mask_bits(7, (occ.numel(),))).to(dev)
+    rb = npvs.build_rulebook(occ, cfg.grids, cfg.d, csr=True)
+    c = rb.host_counts()
+    r = {"grids": len(cfg.grids), "grid": list(cfg.grids[0]), "n_sites": c["n_sites"], "n_pairs": c["n_pairs"],
+         "checkpoint": "every second layer input recomputed"}
+    for dtype, tag, steps in ((npvs.NPVS_BF16, "bf16", args.steps), (npvs.NPVS_F32, "fp32", 5)):
+        net = Network(layers, cfg.d, dtype)
+        tr = Trainer(net, cfg.grids, counts, checkpoint=True)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                tr.step(tris, lab)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            tr.step(tris, lab)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r[f"{tag}_step_ms"], r[f"{tag}_frames_per_s"] = ms, 1000.0 * len(cfg.grids) / ms
+        del g
+    r["bf16_speedup_vs_fp32"] = r["fp32_step_ms"] / r["bf16_step_ms"]
+    return r
+
+
 def bench_wide(args, dev, timed_launches):
     """The city frame at the paper's interleave factors d = 8 and 16: forward (froxelize -> PVS) as a
     library-captured graph in BF16 and FP32, the training step (forward, loss, backward, Adam) as
@@ -741,6 +792,8 @@ def main():
     # ------------------------------------------------------------------ batching (16 uneven grids)
     batch16 = bench_batch16(args, dev, timed_launches)
     print("# batch16 " + json.dumps(batch16), file=sys.stderr, flush=True)
+    train4 = bench_train4(args, dev)
+    print("# batch of four 128^3 grids, training " + json.dumps(train4), file=sys.stderr, flush=True)
     wide = bench_wide(args, dev, timed_launches)
     print("# interleave factors 8 and 16 " + json.dumps(wide), file=sys.stderr, flush=True)
     cull = bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs_b)
@@ -812,6 +865,7 @@ def main():
         "stages_ms": stage_ms,
         "stages_hbm": stage_gbs,
         "batch16": batch16,
+        "train128x4": train4,
         "interleave_8_16": wide,
         "culling": cull,
         "unet": unet,
