@@ -64,7 +64,7 @@ def conv_traffic(variant):
     elif variant in lds:
         name = f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>"
     else:
-        name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}, false>"
+        name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}, false, 2>"
     for line in text.splitlines():
         if line.startswith("## batch16"):  # the first table is the city256 one
             break

@@ -209,7 +209,8 @@ npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, con
  * 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8); variants 12 and 13 (inputs of at
  * most 64 channels) keep each wave's weights in registers while a workgroup walks several row
  * tiles of 16 or 32 rows.  Channel counts no tuned shape covers use a general kernel (variants
- * 5 and 13 select its 32-row tiles).  All variants give results within float32 rounding of each
+ * 5 and 13 select its 32-row tiles), except 65 to 96 inputs, which take the weight-stationary
+ * kernel with 16-row tiles unless variant 5 is asked for.  All variants give results within float32 rounding of each
  * other; each one is deterministic.  Ignored by the FP32 path. */
 #define NPVS_CONV_VARIANTS 14
 #define NPVS_DEFAULT_CONV_VARIANT 12 /* the tile shape npvs_sparse_conv_fwd and the data gradient use */

@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__
 }
 
 // ------------------------------------------------------------------------------------------
-// BF16 path, weight-stationary, for inputs of at most 64 channels and any number of outputs.
+// BF16 path, weight-stationary, for inputs of at most 96 channels and any number of outputs.
 // Workgroup = 9 waves over the same MB x 16 rows, wave w owning offsets 3w .. 3w + 2;
 // blockIdx.y selects 32 output channels (2 MFMA output blocks).  A wave loads the weight
 // fragments of its 3 offsets x KB chunks x 2 output blocks once (at most 12 fragments) and keeps
@@ -449,7 +449,10 @@ __global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__
 // over all the tiles its workgroup walks.  At the end a fixed butterfly adds the 16 rows of each
 // column and the workgroup writes its row of dbp[NPVS_BWD_DB_PARTS][cout] (rows past the grid are
 // written as zeros), so the bias gradient of the layer below is a fixed-order sum over that table.
-template <int KB, int MB, bool FUSE = false>
+// NBW: output blocks of 16 channels per workgroup (2; 1 for 4 or 5 input chunks, whose weights
+// and rows would not fit the registers otherwise, and which then gather each tile's rows when
+// its iteration starts instead of one tile ahead).
+template <int KB, int MB, bool FUSE = false, int NBW = 2>
 __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
                                                                   const bf16x8_t *__restrict__ Wp,
                                                                   const float *__restrict__ bias, int cout,
@@ -458,7 +461,8 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
                                                                   int relu, int out_f32, void *__restrict__ Y,
                                                                   const uint16_t *__restrict__ M = nullptr,
                                                                   float *__restrict__ dbp = nullptr) {
-  constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBW = 2, NBLK = MB * NBW;
+  constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBLK = MB * NBW;
+  constexpr bool PF = NBW == 2;  // rows of the next tile prefetched
   static_assert(!FUSE || MB == 1, "the fused data gradient keeps one column block per epilogue wave");
   __shared__ f32x4_t red[KSPLIT * NBLK * 64];
   const int32_t n = counts->n_sites;
@@ -513,9 +517,9 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   int ix[KPER][MB];
   bf16x8_t bx[KPER][KB][MB];
   indices(tile, ix);
-  rows(ix, bx);
+  if constexpr (PF) rows(ix, bx);
   int t1 = xcd_tile(blockIdx.x, gridDim.x, ntiles, 1);
-  indices(t1 >= 0 ? t1 : tile, ix);
+  if constexpr (PF) indices(t1 >= 0 ? t1 : tile, ix);
   for (int j = 0; tile >= 0; ++j) {
     const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
     // FUSE: the epilogue waves fetch this tile's mask now, so its latency hides under the products
@@ -525,8 +529,13 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
       if (M && wv < NBLK && r < n && o < cout) mk = *reinterpret_cast<const uint2 *>(M + (int64_t)r * cout + o);
     }
     bf16x8_t bn[KPER][KB][MB];
-    rows(ix, bn);                                        // tile j + 1 (or a repeat)
-    indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
+    if constexpr (PF) {
+      rows(ix, bn);                                        // tile j + 1 (or a repeat)
+      indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
+    } else {
+      rows(ix, bx);                       // tile j
+      indices(t1 >= 0 ? t1 : tile, ix);   // tile j + 1 (or a repeat)
+    }
     f32x4_t acc[MB][NBW];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -572,12 +581,14 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
       }
     }
+    if constexpr (PF) {
 #pragma unroll
-    for (int q = 0; q < KPER; ++q)
+      for (int q = 0; q < KPER; ++q)
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb)
+        for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) bx[q][kb][mb] = bn[q][kb][mb];
+          for (int mb = 0; mb < MB; ++mb) bx[q][kb][mb] = bn[q][kb][mb];
+    }
     tile = t1;
     t1 = t2;
   }
@@ -706,19 +717,19 @@ static void launch_bf16(const void *X, int cin, const void *Wp, const float *bia
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
 }
 
-template <int KB, int MB>
+template <int KB, int MB, int NBW = 2>
 static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float *bias, int cout, const int32_t *nbr,
                              const npvs_counts *counts, int cap, int relu, int out_f32, void *Y, hipStream_t s) {
   // as many workgroups as fit on the chip at once (9-wave workgroups: two per compute unit with
-  // one input chunk, one with two chunks or 32-row tiles), spread over the output groups; each
-  // walks several row tiles
-  const int groups = (cout + 31) / 32;
+  // one input chunk, one with two or more chunks or 32-row tiles), spread over the output groups;
+  // each walks several row tiles
+  const int groups = (cout + 16 * NBW - 1) / (16 * NBW);
   int G = (KB == 1 && MB == 1 ? 512 : 256) / groups;
   G = G < 8 ? 8 : G;
   const int most = stride_grid(cap, 16 * MB, 4096);
   G = G > most ? most : G;
   G = (G + 7) & ~7;
-  conv_fwd_bf16_wsta_kernel<KB, MB><<<dim3(G, groups), 576, 0, s>>>(
+  conv_fwd_bf16_wsta_kernel<KB, MB, false, NBW><<<dim3(G, groups), 576, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
 }
 
@@ -907,6 +918,15 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
       if (wide_rows) launch_bf16_wsta<2, 2>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
       else launch_bf16_wsta<2, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
     }
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
+  }
+  // 65 to 160 input channels (the U-Net decoder: 160 -> 96, 96 -> 96, 96 -> 64): the
+  // weight-stationary kernel, since the general kernel re-reads every offset's weights for each
+  // 16-row tile; 3 input chunks with two output blocks per workgroup (168 VGPRs), 4 or 5 with one
+  if (KB <= 5 && variant != 5) {
+    if (KB == 3) launch_bf16_wsta<3, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    else if (KB == 4) launch_bf16_wsta<4, 1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    else launch_bf16_wsta<5, 1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
     return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
   }
   // wide inputs: split the channel chunks over workgroups when the caller gave a workspace
