@@ -725,10 +725,9 @@ static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float
   // each walks several row tiles
   const int groups = (cout + 16 * NBW - 1) / (16 * NBW);
   int G = (KB == 1 && MB == 1 ? 512 : 256) / groups;
-  G = G < 8 ? 8 : G;
+  G = G < 8 ? 8 : G & ~7;  // a multiple of 8 (one per XCD), rounded down so that all fit at once
   const int most = stride_grid(cap, 16 * MB, 4096);
-  G = G > most ? most : G;
-  G = (G + 7) & ~7;
+  if (G > most) G = (most + 7) & ~7;
   conv_fwd_bf16_wsta_kernel<KB, MB, false, NBW><<<dim3(G, groups), 576, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
 }
