@@ -81,7 +81,7 @@ def _c(a, dtype):
 # ---------------------------------------------------------------- froxelization
 def quantize_tri(tri) -> np.ndarray | None:
     """Fixed-point (1/256 froxel, round half to even) vertices of one triangle, or None when
-    the triangle is ignored (non-finite or |coordinate| >= 1024)."""
+    the triangle is ignored (non-finite or |coordinate| >= 2048)."""
     t = _c(tri, np.float32).reshape(9)
     q = np.zeros((3, 3), np.int64)
     return q if _load().oracle_quantize_tri(_p(t), _p(q)) else None
@@ -282,6 +282,46 @@ def label_raymarch(tris, dims, views, s_r: int = 2) -> np.ndarray:
     lab = np.zeros((nz, ny, nx // 8), np.uint8)
     _load().oracle_label_raymarch(_p(t), t.shape[0], nx, ny, nz, _p(v), v.shape[0], s_r, _p(lab))
     return lab
+
+
+# ---------------------------------------------------------------- evaluation metrics
+def active_froxels(occ, dims, d) -> np.ndarray:
+    """Packed mask [nz][ny][nx/8] of the froxels that lie in active blocks (a block of d^3
+    froxels is active iff one of its froxels is occupied): the froxels that receive a logit and
+    are thresholded (Sec. 3.1, 3.3)."""
+    nx, ny, nz = dims
+    g = unpack(np.asarray(occ, np.uint8).reshape(nz, ny, nx // 8)).astype(bool)
+    blk = g.reshape(nz // d, d, ny // d, d, nx // d, d).any(axis=(1, 3, 5))
+    full = np.repeat(np.repeat(np.repeat(blk, d, axis=0), d, axis=1), d, axis=2)
+    return np.packbits(full.astype(np.uint8), axis=-1, bitorder="little")
+
+
+def metrics(v_ref, v_test, occ, active) -> dict:
+    """Agreement of a tested PVS with a reference PVS (packed bits of the same grid).
+
+    Sec. 5.1 evaluates a PVS by its false negative rate FNR = FN / GTP and false positive rate
+    FPR = FP / GTP, counted over froxels with the reference as the ground truth: FN = #{ref 1,
+    test 0}, FP = #{ref 0, test 1}, GTP = #{ref 1}.  missing_geometry is that FNR (geometry the
+    reference keeps and the tested set drops).  The flip rate is #{ref != test} over three
+    denominators: the occupied froxels (supp G; both sets lie inside G, so only these can
+    differ), the froxels of the active blocks (`active`, the froxels that are thresholded) and
+    all froxels.  Counts are returned beside the rates; a zero denominator gives a rate of 0."""
+    a = unpack(np.asarray(v_ref, np.uint8)).astype(bool)
+    b = unpack(np.asarray(v_test, np.uint8)).astype(bool)
+    g = unpack(np.asarray(occ, np.uint8)).astype(bool)
+    m = unpack(np.asarray(active, np.uint8)).astype(bool)
+    if not (a.shape == b.shape == g.shape == m.shape):
+        raise ValueError("all four grids must have the same shape")
+    flips = int((a != b).sum())
+    fn = int((a & ~b).sum())
+    fp = int((~a & b).sum())
+    gtp = int(a.sum())
+    n_occ, n_act, n_all = int(g.sum()), int(m.sum()), int(g.size)
+    rate = lambda x, y: x / y if y else 0.0
+    return dict(flips=flips, fn=fn, fp=fp, gtp=gtp, occupied=n_occ, active=n_act, froxels=n_all,
+                flip_rate_occupied=rate(flips, n_occ), flip_rate_active=rate(flips, n_act),
+                flip_rate_all=rate(flips, n_all), missing_geometry=rate(fn, gtp), fnr=rate(fn, gtp),
+                fpr=rate(fp, gtp))
 
 
 # ---------------------------------------------------------------- composition

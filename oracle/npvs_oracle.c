@@ -20,7 +20,11 @@
 #include <string.h>
 
 #define FX 256 /* fixed-point scale: 1/256 froxel */
-#define COORD_LIMIT 1024.0
+/* Representation bound of the exact overlap test: |v| < 2048 froxels with 8 fractional bits gives
+ * fixed-point coordinates below 2^19, so every separating-axis projection is a sum of three
+ * products below 2^61 and fits int64.  It bounds how large a triangle can be, not where the grid
+ * is: a triangle that reaches far outside the grid still marks every froxel it meets. */
+#define COORD_LIMIT 2048.0
 
 static int64_t floordiv(int64_t a, int64_t b) {
   int64_t q = a / b;
@@ -37,8 +41,8 @@ static int64_t max3(int64_t a, int64_t b, int64_t c) { int64_t m = a > b ? a : b
  * quantized to 1/256 froxel with round-half-to-even.  All predicates are exact in int64.
  * ------------------------------------------------------------------------------------------ */
 
-/* Quantize one triangle.  Returns 0 when a coordinate is non-finite or |v| >= 1024 froxels
- * (such triangles are ignored by definition). */
+/* Quantize one triangle.  Returns 0 when a coordinate is non-finite or |v| >= 2048 froxels
+ * (such triangles are ignored, and counted by oracle_froxelize). */
 int oracle_quantize_tri(const float *t, int64_t q[3][3]) {
   for (int v = 0; v < 3; ++v)
     for (int a = 0; a < 3; ++a) {

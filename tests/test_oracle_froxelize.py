@@ -179,24 +179,48 @@ def test_order_and_vertex_rotation_invariance():
 def test_invalid_triangles_are_ignored():
     dims = (8, 8, 8)
     good = np.array([[1.5, 1.5, 1.5], [2.5, 1.5, 1.5], [1.5, 2.5, 1.5]], np.float32)
-    bad = [good.copy() for _ in range(3)]
+    bad = [good.copy() for _ in range(4)]
     bad[0][1, 0] = np.nan
     bad[1][2, 2] = np.inf
-    bad[2][0, 1] = 1024.0
-    got, ign = _unpacked(np.stack([good] + bad), dims)
+    bad[2][0, 1] = 2048.0
+    bad[3][1, 2] = -2048.0
+    far = good + np.float32(1500.0)  # inside the exact range, outside the grid: not ignored, marks nothing
+    got, ign = _unpacked(np.stack([good] + bad + [far]), dims)
     want, _ = _unpacked(good, dims)
-    assert ign == 3
+    assert ign == 4
     np.testing.assert_array_equal(got, want)
+
+
+def test_large_triangles_crossing_the_grid_match_exact_clipping():
+    # vertices in [1024, 2048): the triangle reaches far outside the grid and still marks exactly
+    # the froxels it meets (G(x) = 1 iff a triangle meets x, Sec. 3.2, with no limit on where the
+    # triangle lies); checked against rational clipping on whole froxel rows of a 256-wide grid
+    dims = (256, 8, 8)
+    tris = np.array([
+        [[-1500.25, 3.5, 2.0], [1900.75, 4.25, 6.5], [200.0, 1600.5, -1300.0]],
+        [[1024.0, -1024.0, 4.5], [-2047.5, 2.0, 4.5], [100.5, 2047.0, 4.5]],
+        [[-1999.5, 0.5, 7.75], [1999.25, 7.5, 0.25], [64.0, -1500.0, -1800.0]],
+    ], np.float32)
+    rows = [(0, 0), (3, 2), (4, 4), (7, 7), (1, 6), (2, 1), (4, 6)]
+    for t in tris:
+        got, ign = _unpacked(t, dims)
+        assert ign == 0
+        q = oracle.quantize_tri(t)
+        for j, k in rows:
+            for i in range(dims[0]):
+                want = clip_overlap(q, (FX * i, FX * j, FX * k), (FX * i + FX, FX * j + FX, FX * k + FX))
+                assert got[k, j, i] == int(want), (t, i, j, k)
+        assert got.any()
 
 
 def test_worst_case_coordinate_range_is_exact():
     # vertices at the edge of the accepted range exercise the largest int64 products
-    t = np.array([[-1023.99, -1023.5, 1023.99], [1023.99, 3.25, -1023.75], [1.5, 1023.9, 0.5]], np.float32)
+    t = np.array([[-2047.99, -2047.5, 2047.99], [2047.99, 3.25, -2047.75], [1.5, 2047.9, 0.5]], np.float32)
     dims = (16, 16, 16)
     got, ign = _unpacked(t, dims)
     assert ign == 0
     q = oracle.quantize_tri(t)
-    assert np.abs(q).max() <= 2 ** 18
+    assert np.abs(q).max() <= 2 ** 19
     for k in range(0, 16, 3):
         for j in range(16):
             for i in range(0, 16, 2):
