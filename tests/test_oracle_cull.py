@@ -38,7 +38,7 @@ def test_single_visible_froxel():
 
 def test_ignored_triangles_are_never_visible():
     dims = (16, 16, 16)
-    big = _tri((3.0, 4.0, 5.0), (2000.0, 4.0, 5.0), (3.0, 5.0, 5.0))  # |v| >= 1024 froxels: ignored
+    big = _tri((3.0, 4.0, 5.0), (2048.0, 4.0, 5.0), (3.0, 5.0, 5.0))  # |v| >= 2048 froxels: ignored
     nan = _tri((3.0, 4.0, 5.0), (np.nan, 4.0, 5.0), (3.0, 5.0, 5.0))
     full = np.full((16, 16, 2), 0xFF, np.uint8)
     np.testing.assert_array_equal(oracle.visible_triangles(np.concatenate([big, nan]), dims, full), [0, 0])
