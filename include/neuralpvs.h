@@ -57,7 +57,8 @@ typedef int32_t npvs_status;
 
 /* limits */
 #define NPVS_MAX_GRIDS 32        /* grids per batch */
-#define NPVS_MAX_DIM 1024        /* froxels per axis; triangle coordinates must satisfy |v| < 1024 */
+#define NPVS_MAX_DIM 1024        /* froxels per axis */
+#define NPVS_COORD_LIMIT 2048    /* triangles with a coordinate |v| >= 2048 (grid units) are ignored */
 
 typedef struct {
   int32_t nx, ny, nz; /* froxels; nx % 8 == 0 and every extent divisible by d */
@@ -69,7 +70,8 @@ typedef struct {
   int32_t n_sites;        /* active sites stored (min of found and cap_sites) */
   int32_t n_sites_needed; /* active sites found; > cap_sites means the capacity overflowed */
   int32_t n_pairs;        /* rulebook pairs stored (when the CSR form is requested) */
-  int32_t reserved;
+  int32_t n_tris_ignored; /* triangles the plan's froxelization ignored (npvs_froxelize's n_ignored);
+                             npvs_build_rulebook does not write it */
 } npvs_counts;
 
 const char *npvs_version(void);
@@ -82,17 +84,20 @@ npvs_status npvs_batch_sizes(int32_t n_grids, const npvs_dims *dims /*host*/, in
 /* ---------------------------------------------------------------------------------------------
  * Froxelization (Sec. 3.2; Fig. 2(b)): G(x) = 1 iff a triangle meets the closed froxel x.
  * Vertices are in grid units (one froxel = 1), quantized to 1/256 froxel with round half to
- * even, and tested exactly (integer separating-axis test).  Triangles with a non-finite
- * coordinate or |coordinate| >= 1024 are ignored.
- *   tris     (device) float32 [sum T_b][3][3], grid b's triangles after those of grids < b
- *   n_tris   (host)   int64 [n_grids] triangle counts
- *   occ_bits (device) packed grids of the batch, fully overwritten
- *   ws       (device) workspace of npvs_froxelize_workspace_size() bytes
+ * even, and tested exactly (integer separating-axis test).  A triangle may reach outside the grid
+ * (it marks the froxels it meets); one with a non-finite coordinate or |coordinate| >= 2048
+ * (NPVS_COORD_LIMIT, the range in which the fixed-point test is exact in 64-bit integers) is
+ * ignored and counted.
+ *   tris      (device) float32 [sum T_b][3][3], grid b's triangles after those of grids < b
+ *   n_tris    (host)   int64 [n_grids] triangle counts
+ *   occ_bits  (device) packed grids of the batch, fully overwritten
+ *   n_ignored (device, nullable) int32, overwritten with the number of ignored triangles
+ *   ws        (device) workspace of npvs_froxelize_workspace_size() bytes
  * ------------------------------------------------------------------------------------------- */
 npvs_status npvs_froxelize_workspace_size(int32_t n_grids, const npvs_dims *dims, const int64_t *n_tris,
                                           size_t *bytes);
 npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, int32_t n_grids, const npvs_dims *dims,
-                           uint8_t *occ_bits, void *ws, size_t ws_bytes, void *stream);
+                           uint8_t *occ_bits, int32_t *n_ignored, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Active sites and rulebook of the submanifold convolution (Sec. 2.3: the kernel is centred
@@ -394,7 +399,7 @@ npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row
  * against the froxelized PVS and the object is pruned when none of its froxels is visible).
  *   visible[t] = 1 iff some froxel that triangle t overlaps (the exact test of npvs_froxelize:
  *   closed froxels, 1/256 fixed point) has its bit set in pvs_bits, else 0; ignored triangles
- *   (|coordinate| >= 1024 or not finite) are 0.  tris, n_tris, n_grids, dims as for
+ *   (|coordinate| >= 2048 or not finite) are 0.  tris, n_tris, n_grids, dims as for
  *   npvs_froxelize; pvs_bits (device) packed like occ_bits; visible (device) uint8 [total].
  * npvs_visible_objects: visible[i] = OR of vis_tris[obj_off[i] .. obj_off[i + 1] - 1];
  *   obj_off (device) int64 [n_objects + 1], non-decreasing, within vis_tris.

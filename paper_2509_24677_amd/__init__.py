@@ -56,10 +56,13 @@ def batch_sizes(dims, d: int):
 
 
 # --------------------------------------------------------------------------------- froxelize
-def froxelize(tris: torch.Tensor, n_tris, dims, occ: torch.Tensor | None = None) -> torch.Tensor:
+def froxelize(tris: torch.Tensor, n_tris, dims, occ: torch.Tensor | None = None,
+              n_ignored: torch.Tensor | None = None) -> torch.Tensor:
     """Packed occupancy bits of a batch of grids (uint8, grids back to back).
 
-    tris: float32 device tensor [sum T][3][3] in grid units; n_tris: triangles per grid."""
+    tris: float32 device tensor [sum T][3][3] in grid units; n_tris: triangles per grid;
+    n_ignored (optional): int32 device tensor of one element that receives the number of
+    ignored triangles (a non-finite coordinate or |coordinate| >= 2048)."""
     dims = [tuple(g) for g in dims]
     n_tris = [int(t) for t in n_tris]
     tris = tris.contiguous()
@@ -74,8 +77,10 @@ def froxelize(tris: torch.Tensor, n_tris, dims, occ: torch.Tensor | None = None)
         occ = torch.empty(total_bytes, dtype=torch.uint8, device=_dev())
     elif occ.numel() != total_bytes or occ.dtype != torch.uint8:
         raise ValueError("occ must be uint8 with one byte per 8 froxels")
-    L.call("npvs_froxelize", _p(tris) if tris.numel() else None, tarr, len(dims), darr, _p(occ), _p(ws),
-           nbytes.value, _stream())
+    if n_ignored is not None and (n_ignored.dtype != torch.int32 or n_ignored.numel() < 1):
+        raise ValueError("n_ignored must be an int32 tensor of at least one element")
+    L.call("npvs_froxelize", _p(tris) if tris.numel() else None, tarr, len(dims), darr, _p(occ),
+           _p(n_ignored) if n_ignored is not None else None, _p(ws), nbytes.value, _stream())
     return occ
 
 
@@ -547,7 +552,8 @@ class Plan:
     def counts(self) -> dict:
         c = L.Counts()
         L.call("npvs_plan_counts", self._h, ctypes.byref(c), _stream())
-        return dict(n_sites=c.n_sites, n_sites_needed=c.n_sites_needed, n_pairs=c.n_pairs)
+        return dict(n_sites=c.n_sites, n_sites_needed=c.n_sites_needed, n_pairs=c.n_pairs,
+                    n_tris_ignored=c.n_tris_ignored)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -40,7 +40,7 @@ class Dims(ctypes.Structure):
 
 class Counts(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("n_sites_needed", ctypes.c_int32),
-                ("n_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_pairs", ctypes.c_int32), ("n_tris_ignored", ctypes.c_int32)]
 
 
 class PackDesc(ctypes.Structure):
@@ -70,7 +70,7 @@ SIGNATURES = {
     "npvs_last_error": (ctypes.c_char_p, []),
     "npvs_batch_sizes": (i32, [i32, P, i32, PI64, PI64]),
     "npvs_froxelize_workspace_size": (i32, [i32, P, P, PS]),
-    "npvs_froxelize": (i32, [P, P, i32, P, P, P, sz, P]),
+    "npvs_froxelize": (i32, [P, P, i32, P, P, P, P, sz, P]),
     "npvs_rulebook_workspace_size": (i32, [i32, P, i32, i32, PS]),
     "npvs_build_rulebook": (i32, [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, sz, P]),
     "npvs_interleave": (i32, [P, Dims, i32, i32, P, P]),

@@ -227,7 +227,8 @@ extern "C" npvs_status npvs_plan_set_weights(npvs_plan *plan, int32_t layer, con
 static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_out, uint8_t *pvs, float *logits,
                                 hipStream_t s) {
   uint8_t *occ = occ_out ? occ_out : p->d_occ;
-  npvs_status st = npvs_froxelize(tris, p->n_tris.data(), p->n_grids, p->dims.data(), occ, p->d_frox_ws, p->frox_ws, s);
+  npvs_status st = npvs_froxelize(tris, p->n_tris.data(), p->n_grids, p->dims.data(), occ, &p->d_counts->n_tris_ignored,
+                                  p->d_frox_ws, p->frox_ws, s);
   if (st != NPVS_OK) return st;
   st = npvs_build_rulebook(occ, p->n_grids, p->dims.data(), p->d, p->cap, p->d_counts, p->d_keys, p->d_block_row,
                            p->d_grid_rows, p->d_nbr, nullptr, nullptr, p->d_rb_ws, p->rb_ws, s);

@@ -24,8 +24,11 @@ namespace npvs {
 // Constants of one triangle's overlap test.  For an axis a the closed froxel I = (i, j, k) meets
 // the triangle along a iff L <= a . I <= H.  The axes are the triangle normal n and the nine
 // cross products of the edges e_i with the box axes (e x x = (0, e_z, -e_y), e x y = (-e_z, 0, e_x),
-// e x z = (e_y, -e_x, 0)); the box normals are the clipped froxel range.  With |v| < 1024 the
-// edge-axis bounds and projections fit int32.
+// e x z = (e_y, -e_x, 0)); the box normals are the clipped froxel range.  With |v| < 2048 the
+// fixed-point coordinates are below 2^19 and edges below 2^20, so an edge-axis projection of a
+// froxel index (below 1024 per axis) is below 2 * 2^20 * 1023 < 2^31 in magnitude and fits int32.
+// The bounds L, H themselves can exceed that range; they are computed in int64 and clamped to
+// [INT32_MIN, INT32_MAX], which keeps every comparison with an in-range projection unchanged.
 struct TriSetup {
   int64_t n[3];          // normal (fixed-point cross product of two edges)
   int64_t nL, nH;        // normal-axis bounds
@@ -43,9 +46,12 @@ static_assert(kListedParts <= kMaxParts, "part indices");
 constexpr int kTileWords = (kFroxTileX / 32) * kFroxTileY * kFroxTileZ;  // 64
 static_assert(kFroxTileX == 32 && kTileWords == 64, "one 32-froxel word per tile row");
 
-__global__ void frox_zero_kernel(int32_t *p, int n, int32_t *n_parts) {
+__global__ void frox_zero_kernel(int32_t *p, int n, int32_t *n_parts, int32_t *n_ignored) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *n_parts = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *n_parts = 0;
+    if (n_ignored) *n_ignored = 0;
+  }
 }
 
 __device__ __forceinline__ int tri_grid(const Batch &B, int64_t t) {
@@ -71,6 +77,10 @@ __device__ __forceinline__ void axis_bounds(int64_t a0, int64_t a1, int64_t a2, 
   H = (pmax - rm) >> 8;
 }
 
+__device__ __forceinline__ int32_t clamp_i32(int64_t v) {
+  return v < (int64_t)INT32_MIN ? INT32_MIN : v > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)v;
+}
+
 __device__ __forceinline__ void make_setup(const int32_t *q, TriSetup &S) {
   int32_t e[3][3];
 #pragma unroll
@@ -88,22 +98,22 @@ __device__ __forceinline__ void make_setup(const int32_t *q, TriSetup &S) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     axis_bounds(0, e[i][2], -e[i][1], q, L, H);
-    S.L[i][0] = (int32_t)L;
-    S.H[i][0] = (int32_t)H;
+    S.L[i][0] = clamp_i32(L);
+    S.H[i][0] = clamp_i32(H);
     axis_bounds(-e[i][2], 0, e[i][0], q, L, H);
-    S.L[i][1] = (int32_t)L;
-    S.H[i][1] = (int32_t)H;
+    S.L[i][1] = clamp_i32(L);
+    S.H[i][1] = clamp_i32(H);
     axis_bounds(e[i][1], -e[i][0], 0, q, L, H);
-    S.L[i][2] = (int32_t)L;
-    S.H[i][2] = (int32_t)H;
+    S.L[i][2] = clamp_i32(L);
+    S.H[i][2] = clamp_i32(H);
   }
 }
 
 // Fixed-point vertices (rint(256 v), round half to even) and the clipped closed-froxel range of
-// triangle t; true when the triangle is ignored (a coordinate not finite or |v| >= 1024) or its
-// range misses the grid.
+// triangle t; true when the triangle is ignored (a coordinate not finite or |v| >= 2048; then
+// *bad is set) or its range misses the grid.
 __device__ __forceinline__ bool quantize_tri(const float *__restrict__ tris, int64_t t, const GridDesc &g,
-                                             int32_t *q, int32_t *lo, int32_t *hi) {
+                                             int32_t *q, int32_t *lo, int32_t *hi, bool *bad = nullptr) {
   bool ok = true;
   int32_t mn[3], mx[3];
 #pragma unroll
@@ -116,12 +126,13 @@ __device__ __forceinline__ bool quantize_tri(const float *__restrict__ tris, int
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       float x = tris[t * 9 + v * 3 + a];
-      ok = ok && (__builtin_fabsf(x) < (float)NPVS_MAX_DIM);  // finite and |x| < 1024 (NaN fails)
+      ok = ok && (__builtin_fabsf(x) < (float)NPVS_COORD_LIMIT);  // finite and |x| < 2048 (NaN fails)
       int32_t qq = ok ? (int32_t)__builtin_rintf(x * 256.0f) : 0;  // exact scaling, round half to even
       q[v * 3 + a] = qq;
       mn[a] = qq < mn[a] ? qq : mn[a];
       mx[a] = qq > mx[a] ? qq : mx[a];
     }
+  if (bad) *bad = !ok;
   const int32_t dims[3] = {g.nx, g.ny, g.nz};
   bool empty = !ok;
 #pragma unroll
@@ -138,14 +149,15 @@ __device__ __forceinline__ bool quantize_tri(const float *__restrict__ tris, int
 
 __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__ tris, Batch B, int64_t total,
                                                         TriSetup *__restrict__ recs, int32_t *__restrict__ tile_count,
-                                                        int32_t *__restrict__ tile_list) {
+                                                        int32_t *__restrict__ tile_list, int32_t *__restrict__ n_ignored) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int ntl = 0, tx0 = 0, ty0 = 0, tz0 = 0, ntx = 1, nty = 1, toff = 0, tys = 1, txs = 1;
+  bool bad = false;
   if (t < total) {
     const GridDesc &g = B.g[tri_grid(B, t)];
     TriSetup S = {};
     int32_t q[9], lo[3], hi[3];
-    const bool empty = quantize_tri(tris, t, g, q, lo, hi);
+    const bool empty = quantize_tri(tris, t, g, q, lo, hi, &bad);
     if (!empty) make_setup(q, S);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -166,11 +178,14 @@ __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__
       tys = g.tiles_y;
     }
   }
+  // ignored triangles: one counter update per wave that has any
+  const int lane = threadIdx.x & 63;
+  const uint64_t badm = __ballot(bad);
+  if (n_ignored && badm && lane == 0) atomicAdd(n_ignored, (int)__popcll(badm));
   // Append to each covered tile.  Triangles of one object tend to be consecutive and to share
   // tiles, so in each round a run of consecutive lanes that target the same tile shares one
   // counter update (made by the run's first lane); lanes of unrelated triangles update their own
   // counters in parallel.
-  const int lane = threadIdx.x & 63;
   for (int j = 0;; ++j) {
     const bool active = j < ntl;
     if (__ballot(active) == 0ull) break;
@@ -515,7 +530,7 @@ extern "C" npvs_status npvs_froxelize_workspace_size(int32_t n_grids, const npvs
 }
 
 extern "C" npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, int32_t n_grids, const npvs_dims *dims,
-                                      uint8_t *occ_bits, void *ws, size_t ws_bytes, void *stream) {
+                                      uint8_t *occ_bits, int32_t *n_ignored, void *ws, size_t ws_bytes, void *stream) {
   if (!n_tris || !occ_bits || !ws) return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize: null pointer");
   Batch B;
   npvs_status st = make_batch(n_grids, dims, 1, n_tris, &B);
@@ -535,9 +550,9 @@ extern "C" npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, 
   TriSetup *recs = reinterpret_cast<TriSetup *>(w + orr);
   uint32_t *part = reinterpret_cast<uint32_t *>(w + op);
   hipStream_t s = as_stream(stream);
-  frox_zero_kernel<<<stride_grid(B.total_tiles, 256, 1024), 256, 0, s>>>(cnt, B.total_tiles, n_parts);
+  frox_zero_kernel<<<stride_grid(B.total_tiles, 256, 1024), 256, 0, s>>>(cnt, B.total_tiles, n_parts, n_ignored);
   if (total > 0) {
-    frox_bin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(tris, B, total, recs, cnt, lst);
+    frox_bin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(tris, B, total, recs, cnt, lst, n_ignored);
     frox_plan_kernel<<<1, 1024, 0, s>>>(B, cnt, part_list, n_parts);
     frox_part_kernel<<<stride_grid((int64_t)B.total_tiles * kMaxParts, 1, 2048), 256, 0, s>>>(
         B, recs, cnt, lst, part_list, n_parts, part);

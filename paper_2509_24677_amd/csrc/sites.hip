@@ -130,7 +130,6 @@ __global__ __launch_bounds__(256) void sites_write_kernel(Batch B, const uint8_t
     counts->n_sites = stored;
     counts->n_sites_needed = total;
     counts->n_pairs = 0;
-    counts->reserved = 0;
     grid_rows[B.n] = stored;
   }
 }

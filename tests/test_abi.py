@@ -122,7 +122,7 @@ def test_too_many_grids_and_null_pointers(lib):
     dims = L.dims_array([(64, 64, 64)] * 33)
     assert lib.npvs_batch_sizes(33, dims, 4, ctypes.byref(tb), ctypes.byref(tby)) == L.NPVS_ERR_INVALID_ARG
     one = L.dims_array([(64, 64, 64)])
-    st = lib.npvs_froxelize(None, L.i64_array([1]), 1, one, None, None, 0, None)
+    st = lib.npvs_froxelize(None, L.i64_array([1]), 1, one, None, None, None, 0, None)
     assert st == L.NPVS_ERR_INVALID_ARG
     st = lib.npvs_sparse_conv_fwd(None, 64, None, None, 64, None, None, 10, 0, 1, 0, None, None)
     assert st == L.NPVS_ERR_INVALID_ARG
@@ -135,7 +135,7 @@ def test_too_many_grids_and_null_pointers(lib):
 def test_workspace_too_small_is_rejected(lib):
     one = L.dims_array([(64, 64, 64)])
     p = ctypes.c_void_p(256)
-    st = lib.npvs_froxelize(p, L.i64_array([10]), 1, one, p, p, 16, None)
+    st = lib.npvs_froxelize(p, L.i64_array([10]), 1, one, p, None, p, 16, None)
     assert st == L.NPVS_ERR_INVALID_ARG and "workspace" in lib.npvs_last_error().decode()
 
 

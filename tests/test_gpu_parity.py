@@ -92,6 +92,44 @@ def test_froxelize_parts_of_one_tile():
         np.testing.assert_array_equal(to_np(occ), oracle.froxelize(t, dims[0])[0].reshape(-1))
 
 
+def test_froxelize_large_coordinates_and_ignored_count():
+    # vertices in [1024, 2048) reach far outside the 256 x 256 x 128 grid and still mark exactly
+    # the froxels they meet; 2048 and non-finite coordinates are ignored and counted on the device
+    rng = np.random.default_rng(31)
+    dims = [(256, 256, 128)]
+    big = rng.uniform(-2047.9, 2047.9, size=(600, 3, 3))
+    big[:, 0] = rng.uniform(0, 256, size=(600, 3)) * np.array([1.0, 1.0, 0.5])  # one vertex in the grid
+    lattice = rng.integers(-2047, 2048, size=(200, 3, 3)).astype(np.float64)  # integer vertices
+    bad = np.tile(np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [7.0, 8.0, 9.0]]), (7, 1, 1))
+    bad[0, 1, 0] = 2048.0
+    bad[1, 2, 2] = -2048.0
+    bad[2, 0, 1] = np.nan
+    bad[3, 1, 1] = np.inf
+    bad[4, 0, 0] = -np.inf
+    bad[5, 2, 0] = 3.0e38
+    bad[6, 1, 2] = 2048.0001  # rounds to 2048 in float32: ignored
+    edge = np.array([[[2047.9998, -2047.9998, 3.5], [-2047.9998, 2047.9998, 60.25], [128.5, 100.0, 2047.9998]]])
+    t = np.concatenate([big, bad[:3], lattice, edge, bad[3:]]).astype(np.float32)
+    want, ign = oracle.froxelize(t, dims[0])
+    print(f"froxelize large coordinates T={len(t)} ignored={ign}", flush=True)
+    assert ign == 7
+    tris, counts = upload_tris([t])
+    n_ign = torch.full((1,), -5, dtype=torch.int32, device=DEV)
+    occ = npvs.froxelize(tris, counts, dims, n_ignored=n_ign)
+    np.testing.assert_array_equal(to_np(occ), want.reshape(-1))
+    assert int(n_ign.item()) == ign
+
+
+def test_plan_counts_ignored_triangles():
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    t = np.concatenate([t, np.full((3, 3, 3), np.nan, np.float32), np.full((2, 3, 3), 4096.0, np.float32)])
+    tris, counts = upload_tris([t])
+    plan = npvs.Plan(cfg.grids, counts, cfg.d, cfg.channels, npvs.NPVS_F32)
+    plan.forward(tris)
+    assert plan.counts()["n_tris_ignored"] == 5
+
+
 def test_froxelize_empty_and_all_ignored():
     dims = [(64, 16, 16), (32, 32, 32)]
     tri_list = [np.zeros((0, 3, 3), np.float32), np.full((3, 3, 3), np.inf, np.float32)]
