@@ -284,6 +284,119 @@ def label_raymarch(tris, dims, views, s_r: int = 2) -> np.ndarray:
     return lab
 
 
+# ---------------------------------------------------------------- bfloat16 rounding points
+def bf16_round(x) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 value, ties to even, returned as float64.
+
+    bfloat16 keeps float32's 8-bit exponent and 8 significant bits (7 stored).  For a finite x
+    with x = m 2^e, 0.5 <= |m| < 1 (frexp), the representable neighbours are the multiples of
+    the quantum 2^(e - 8) (2^-133 at the subnormal end), and rint rounds half to even; a result
+    of 2^128 or more overflows to infinity.  Non-finite values pass through."""
+    x = np.asarray(x, np.float64)
+    out = x.copy()
+    fin = np.isfinite(x) & (x != 0)
+    _, e = np.frexp(x[fin])
+    q = np.maximum(e - 8, -133)
+    r = np.ldexp(np.rint(np.ldexp(x[fin], -q)), q)
+    r[np.abs(r) >= 2.0 ** 128] = np.inf * np.sign(r[np.abs(r) >= 2.0 ** 128])
+    out[fin] = r
+    return out
+
+
+def subm_conv_f32(X, W, b, rb_off, pairs, relu: bool) -> np.ndarray:
+    """The submanifold convolution evaluated with float32 accumulation (numpy float32 products
+    per offset, added offset by offset): a second admissible evaluation order of the same
+    arithmetic, used to measure how far two orders of the float32 sums drift apart through a
+    BF16 network.  Not a reference value."""
+    X = np.asarray(X, np.float32)
+    W = np.asarray(W, np.float32)
+    Y = np.zeros((X.shape[0], W.shape[2]), np.float32)
+    for k in range(27):
+        p = np.asarray(pairs[rb_off[k]:rb_off[k + 1]])
+        if len(p):
+            Y[p[:, 1]] += X[p[:, 0]] @ W[k]  # output rows are distinct within one offset
+    if b is not None:
+        Y += np.asarray(b, np.float32)
+    return np.maximum(Y, 0.0) if relu else Y
+
+
+def subm_conv_bwd_f32(X, W, rb_off, pairs, dZ, want_dx: bool = True):
+    """The products of ``subm_conv_bwd`` (no ReLU mask; dZ given) evaluated with float32
+    accumulation, offset by offset: (dX, dW).  Used like subm_conv_f32, never as a reference."""
+    X = np.asarray(X, np.float32)
+    W = np.asarray(W, np.float32)
+    dZ = np.asarray(dZ, np.float32)
+    dX = np.zeros_like(X) if want_dx else None
+    dW = np.zeros_like(W)
+    for k in range(27):
+        p = np.asarray(pairs[rb_off[k]:rb_off[k + 1]])
+        if len(p):
+            if want_dx:
+                dX[p[:, 0]] += dZ[p[:, 1]] @ W[k].T  # input rows are distinct within one offset
+            dW[k] = X[p[:, 0]].T @ dZ[p[:, 1]]
+    return dX, dW
+
+
+def forward_bf16(tris, dims, d, layers, occ=None, accum: str = "f64"):
+    """The whole path of ``forward`` at the BF16 path's rounding points (MFMA products of
+    bfloat16 operands with float32 accumulation, float32 bias and ReLU): every weight is rounded
+    to bfloat16 from its float32 master, each hidden layer's result (after bias and ReLU) is
+    rounded to bfloat16 before it feeds the next layer, the last layer's logits are not rounded,
+    and the input (0/1) is exact.  The arithmetic between the rounding points is FP64, so this
+    is the exact value of the BF16 network up to the order of the float32 accumulations.
+    Returns the keys of ``forward`` plus Wb (the rounded weights) and pre (each layer's
+    unrounded result).  accum = "f32" evaluates the sums with float32 accumulation instead
+    (subm_conv_f32): a second evaluation order, for sizing end-to-end tolerances only."""
+    nx, ny, nz = dims
+    if occ is None:
+        occ, _ = froxelize(tris, dims)
+    keys = active_sites(occ, dims, d)
+    rb_off, pairs = rulebook(keys, (nx // d, ny // d, nz // d))
+    X = gather_sites(occ, dims, d, keys)
+    conv = subm_conv if accum == "f64" else subm_conv_f32
+    acts, pre, Wb = [X], [], []
+    for li, (W, b) in enumerate(layers):
+        last = li == len(layers) - 1
+        w = bf16_round(np.asarray(W, np.float32))
+        Wb.append(w)
+        y = conv(acts[-1], w, np.asarray(b, np.float32) if b is not None else None, rb_off, pairs, relu=not last)
+        y = np.asarray(y, np.float64)
+        pre.append(y)
+        acts.append(y if last else bf16_round(y))
+    logits, pvs = deinterleave_threshold(acts[-1], keys, occ, dims, d)
+    return dict(occ=occ, keys=keys, rb_off=rb_off, pairs=pairs, acts=acts, pre=pre, Wb=Wb, logits=logits, pvs=pvs)
+
+
+def backward_bf16(out, layers, dlogits_rows, accum: str = "f64"):
+    """Backward of ``forward_bf16`` at the BF16 path's rounding points: per layer, from the top,
+    dZ = dY [Y > 0] (ReLU'(0) = 0; no mask on the last layer), its bfloat16 rounding dZb is the
+    operand of the products, dX = sum_k dZb W_k^T over the transposed rulebook with the rounded
+    weights, dW_k = sum X^T dZb with the layer's bfloat16 input X, and db = sum dZ (unrounded).
+    dX is the next layer's dY.  FP64 between the rounding points.  Returns [(dW, db)] per layer
+    and the list of each layer's dZb (top layer last).  accum = "f32": float32 accumulation
+    (subm_conv_bwd_f32, with dY carried in float32), for sizing end-to-end tolerances only."""
+    acts, rb_off, pairs, Wb = out["acts"], out["rb_off"], out["pairs"], out["Wb"]
+    grads = [None] * len(layers)
+    dzb = [None] * len(layers)
+    dY = np.asarray(dlogits_rows, np.float64)
+    for li in range(len(layers) - 1, -1, -1):
+        relu = li < len(layers) - 1
+        dZ = dY * (acts[li + 1] > 0) if relu else dY
+        dZb = bf16_round(dZ)
+        dzb[li] = dZb
+        if accum == "f64":
+            dX, dW, _ = subm_conv_bwd(acts[li], Wb[li], rb_off, pairs, None, dZb, relu=False, want_dx=li > 0)
+            db = dZ.sum(axis=0)
+        else:
+            dX, dW = subm_conv_bwd_f32(acts[li], Wb[li], rb_off, pairs, dZb, want_dx=li > 0)
+            dX = None if dX is None else np.asarray(dX, np.float64)
+            dW = np.asarray(dW, np.float64)
+            db = np.asarray(dZ, np.float32).sum(axis=0, dtype=np.float32).astype(np.float64)
+        grads[li] = (dW, db)
+        dY = dX
+    return grads, dzb
+
+
 # ---------------------------------------------------------------- evaluation metrics
 def active_froxels(occ, dims, d) -> np.ndarray:
     """Packed mask [nz][ny][nx/8] of the froxels that lie in active blocks (a block of d^3
