@@ -486,6 +486,141 @@ def bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs):
             "objects_per_s": 2048 / (ms_o * 1e-3)}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_frame(job):
+    """One full frame of the FP64 oracle (forward, loss, backward); returns its wall time."""
+    import numpy as np
+
+    import oracle
+    import synth
+    tris_np, dims, d, layers, total_bytes = job
+    t0 = time.perf_counter()
+    out = oracle.forward(tris_np, dims, d, layers)
+    lab_np = out["occ"] & synth.label_mask_bits(7, (total_bytes,)).reshape(out["occ"].shape)
+    site_lab = oracle.site_labels(lab_np, dims, d, out["keys"])
+    dl = oracle.loss(out["acts"][-1], site_lab)["grad"]
+    oracle.backward(out, layers, dl)
+    return time.perf_counter() - t0, out
+
+
+def _trained_layers(dev, steps=300):
+    """The city network (d = 4, six 64-channel layers, He init) after `steps` BF16 training steps
+    on the four 128^3 grids with their ray-march labels (the oracle's labeller, stored by
+    tests/golden/make_train_labels.py), Adam at the paper's learning rate."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+    from paper_2509_24677_amd.train import Network, Trainer
+
+    cfg = synth.config("train128x4")
+    tri_list = [synth.scene_for(cfg, i) for i in range(len(cfg.grids))]
+    tris = torch.from_numpy(np.concatenate([t.reshape(-1) for t in tri_list]).astype(np.float32)).to(dev)
+    counts = [len(t) for t in tri_list]
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "train128x4_labels.npz"))
+    lab = torch.from_numpy(np.concatenate([gold[f"labels{i}"].reshape(-1) for i in range(len(cfg.grids))])).to(dev)
+    net = Network(synth.net_layers(synth.config("city256")), cfg.d, npvs.NPVS_BF16)
+    tr = Trainer(net, cfg.grids, counts, checkpoint=True)
+    tr_first, _ = tr.step(tris, lab)
+    tr_first = tr_first.clone()
+    stats = tr_first
+    for _ in range(steps - 1):
+        stats, _ = tr.step(tris, lab)
+    torch.cuda.synchronize()
+    layers = [(W.detach().cpu().numpy(), b.detach().cpu().numpy()) for W, b in zip(net.W, net.b)]
+    first = float(tr_first[-1, 0].item())
+    return layers, (first, float(stats[-1, 0].item())), (cfg, tri_list, tris, counts)
+
+
+def cpu_baseline_and_accuracy(args, dev, cfg, tris_np, dims, layers, occ_np, pvs_b, pvs_f, logits_b, logits_f,
+                              n_sites, total_bytes):
+    """The CPU oracle baseline (one frame single-threaded, then one frame per host core in
+    parallel processes; the oracle itself is single-threaded) and the accuracy of the BF16 path:
+    flips, missing geometry and FPR against the FP64 oracle and the FP32 path (oracle.metrics),
+    with the He-initialised weights and after 300 BF16 training steps."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    import paper_2509_24677_amd as npvs
+    from paper_2509_24677_amd.train import Network
+    oracle.build(force=False)
+    acc = {}
+    cpu_s, out = _oracle_frame((tris_np, dims[0], cfg.d, layers, total_bytes))
+    try:
+        n_cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_cores = os.cpu_count() or 1
+    n_cores = max(1, min(n_cores, 16))
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(n_cores) as ex:
+        list(ex.map(_oracle_frame_time, [(tris_np, dims[0], cfg.d, layers, total_bytes)] * n_cores))
+    wall = time.perf_counter() - t0
+    cpu = {"value": n_cores / wall, "unit": "frames/s", "cores": n_cores, "kind": "oracle",
+           "cpu_model": _cpu_model(), "single_thread_value": 1.0 / cpu_s,
+           "sample": f"the 256x256x128 city frame (froxelize, sites, rulebook, interleave, 6 conv layers, "
+                     f"de-interleave + threshold, loss and backward) in the FP64 C oracle: {n_cores} frames in "
+                     f"{n_cores} processes in {wall:.2f} s; one frame single-threaded {cpu_s:.2f} s"}
+    ref = out["acts"][-1]
+    lf = logits_f[:n_sites].cpu().numpy()
+    lb = logits_b[:n_sites].cpu().numpy()
+    acc["max_abs_logit_err_fp32_vs_fp64_oracle"] = float(np.abs(lf - ref).max())
+    acc["max_abs_logit_err_bf16_vs_fp64_oracle"] = float(np.abs(lb - ref).max())
+    pf_bits = pvs_f.cpu().numpy()
+    acc["pvs_bits_fp32_equal_oracle_outside_1e-5_band"] = bool(
+        ((np.unpackbits(out["pvs"].reshape(-1), bitorder="little") == np.unpackbits(pf_bits, bitorder="little")) |
+         (np.abs(np.nan_to_num(out["logits"].reshape(-1), neginf=-1e9)) <= 1e-5)).all())
+    occ = out["occ"].reshape(-1)
+    active = oracle.active_froxels(out["occ"], dims[0], cfg.d).reshape(-1)
+    keep = ("flips", "flip_rate_active", "flip_rate_occupied", "flip_rate_all", "missing_geometry", "fpr")
+    m = oracle.metrics(out["pvs"].reshape(-1), pvs_b.cpu().numpy(), occ, active)
+    acc["bf16_vs_fp64_oracle"] = {k: m[k] for k in keep}
+    m = oracle.metrics(pf_bits, pvs_b.cpu().numpy(), occ, active)
+    acc["bf16_vs_fp32_path"] = {k: m[k] for k in keep}
+    acc["flip_target"] = ("at most 0.1 % of thresholded froxels: flip_rate_active (froxels of active blocks, "
+                          "the ones that receive a logit and are thresholded); flip_rate_occupied beside it")
+    # after training: the same comparisons with the trained weights, on the city frame and on
+    # the four training grids
+    trained, final_loss, (tcfg, tri_list, ttris, tcounts) = _trained_layers(dev)
+    tr_acc = {"training": "300 BF16 steps (Adam, lr 1e-3) on the four 128^3 grids with ray-march labels",
+              "loss_first_step": final_loss[0], "loss_last_step": final_loss[1]}
+    import torch
+    nets = {dt: Network(trained, cfg.d, dt) for dt in (npvs.NPVS_BF16, npvs.NPVS_F32)}
+    for name, (t_np, g) in [("city256", (tris_np, dims[0]))] + [(f"train{i}", (tri_list[i], tcfg.grids[i]))
+                                                                 for i in range(len(tri_list))]:
+        tt = torch.from_numpy(np.asarray(t_np, np.float32)).to(dev)
+        occ_d = npvs.froxelize(tt, [len(t_np)], [g])
+        rb = npvs.build_rulebook(occ_d, [g], cfg.d)
+        pv = {}
+        for dt, net in nets.items():
+            lg, _ = net.forward(npvs.gather_input(occ_d, rb, dt), rb)
+            pv[dt], _ = npvs.deinterleave_threshold(lg, rb, occ_d)
+        o = oracle.forward(t_np, g, cfg.d, trained, want_logits=False)
+        act_m = oracle.active_froxels(o["occ"], g, cfg.d).reshape(-1)
+        ma = oracle.metrics(o["pvs"].reshape(-1), pv[npvs.NPVS_BF16].cpu().numpy(), o["occ"].reshape(-1), act_m)
+        mf = oracle.metrics(pv[npvs.NPVS_F32].cpu().numpy(), pv[npvs.NPVS_BF16].cpu().numpy(), o["occ"].reshape(-1),
+                            act_m)
+        tr_acc[name] = {"bf16_vs_fp64_oracle": {k: ma[k] for k in keep}, "bf16_vs_fp32_path": {k: mf[k] for k in keep}}
+    acc["after_training"] = tr_acc
+    return cpu, acc
+
+
+def _oracle_frame_time(job):
+    return _oracle_frame(job)[0]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -803,43 +938,16 @@ def main():
     world = bench_world(args, dev, timed_launches)
     print("# world space " + json.dumps(world), file=sys.stderr, flush=True)
 
-    # ------------------------------------------------------------------ accuracy
+    # ------------------------------------------------------------------ accuracy + CPU oracle baseline
+    # Both use the oracle (test infrastructure), so both run in this leg only.
     torch.cuda.synchronize()
-    acc = {}
-    pb = np.unpackbits(pvs_b.cpu().numpy(), bitorder="little")
-    pf = np.unpackbits(pvs_f.cpu().numpy(), bitorder="little")
-    g = np.unpackbits(occ_np, bitorder="little")
-    lf = logits_f[:n_sites].cpu().numpy()
-    lb = logits_b[:n_sites].cpu().numpy()
-    acc["flip_rate_occupied"] = float(((pb != pf) & (g == 1)).sum() / g.sum())
-    acc["flip_rate_active_froxels"] = float((pb != pf).sum() / (n_sites * 64))
-    acc["flip_rate_all_froxels"] = float((pb != pf).sum() / g.size)
-    acc["missing_geometry_rate"] = float(((pf == 1) & (pb == 0)).sum() / max(pf.sum(), 1))
-    acc["max_abs_logit_diff_bf16_vs_fp32"] = float(np.abs(lb - lf).max())
-
-    # ------------------------------------------------------------------ CPU oracle baseline
+    acc = {"max_abs_logit_diff_bf16_vs_fp32": float(np.abs(logits_b[:n_sites].cpu().numpy()
+                                                               - logits_f[:n_sites].cpu().numpy()).max())}
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        t0 = time.perf_counter()
-        out = oracle.forward(tris_np, dims[0], cfg.d, layers)
-        # the labels: the same seeded subset, of the oracle's own occupancy
-        lab_np = out["occ"] & synth.label_mask_bits(7, (total_bytes,)).reshape(out["occ"].shape)
-        site_lab = oracle.site_labels(lab_np, dims[0], cfg.d, out["keys"])
-        dl = oracle.loss(out["acts"][-1], site_lab)["grad"]
-        oracle.backward(out, layers, dl)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": 1.0 / cpu_s, "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": "one full 256x256x128 frame: froxelize, sites, rulebook, interleave, 6 conv layers, "
-                         "de-interleave + threshold, loss and backward in the FP64 C oracle (single thread), "
-                         f"{cpu_s:.2f} s"}
-        ref = out["acts"][-1]
-        acc["max_abs_logit_err_fp32_vs_fp64_oracle"] = float(np.abs(lf - ref).max())
-        acc["max_abs_logit_err_bf16_vs_fp64_oracle"] = float(np.abs(lb - ref).max())
-        acc["pvs_bits_fp32_equal_oracle_outside_1e-5_band"] = bool(
-            ((np.unpackbits(out["pvs"].reshape(-1), bitorder="little") == pf) |
-             (np.abs(np.nan_to_num(out["logits"].reshape(-1), neginf=-1e9)) <= 1e-5)).all())
+        cpu, acc_o = cpu_baseline_and_accuracy(args, dev, cfg, tris_np, dims, layers, occ_np, pvs_b, pvs_f,
+                                               logits_b, logits_f, n_sites, total_bytes)
+        acc.update(acc_o)
 
     line = {
         "metric": METRIC,
@@ -871,6 +979,7 @@ def main():
         "unet": unet,
         "world_space": world,
         "accuracy": acc,
+        "library_source_hash": npvs._lib.get().npvs_source_hash().decode(),
     }
     print(json.dumps(line))
 

@@ -75,6 +75,9 @@ typedef struct {
 } npvs_counts;
 
 const char *npvs_version(void);
+/* 16 hex digits identifying the sources the library was built from (SHA-256 over the HIP
+   sources, this header and the compile flags); static string, never freed. */
+const char *npvs_source_hash(void);
 const char *npvs_last_error(void);
 
 /* Total blocks of a batch (sum of Bx*By*Bz) and total packed bytes (sum of nz*ny*nx/8). */

@@ -344,8 +344,8 @@ def forward_bf16(tris, dims, d, layers, occ=None, accum: str = "f64"):
     rounded to bfloat16 before it feeds the next layer, the last layer's logits are not rounded,
     and the input (0/1) is exact.  The arithmetic between the rounding points is FP64, so this
     is the exact value of the BF16 network up to the order of the float32 accumulations.
-    Returns the keys of ``forward`` plus Wb (the rounded weights) and pre (each layer's
-    unrounded result).  accum = "f32" evaluates the sums with float32 accumulation instead
+    Returns the keys of ``forward`` plus Wb (the rounded weights), z (each layer's result before
+    ReLU) and pre (each layer's unrounded result after ReLU).  accum = "f32" evaluates the sums with float32 accumulation instead
     (subm_conv_f32): a second evaluation order, for sizing end-to-end tolerances only."""
     nx, ny, nz = dims
     if occ is None:
@@ -354,33 +354,41 @@ def forward_bf16(tris, dims, d, layers, occ=None, accum: str = "f64"):
     rb_off, pairs = rulebook(keys, (nx // d, ny // d, nz // d))
     X = gather_sites(occ, dims, d, keys)
     conv = subm_conv if accum == "f64" else subm_conv_f32
-    acts, pre, Wb = [X], [], []
+    acts, pre, zs, Wb = [X], [], [], []
     for li, (W, b) in enumerate(layers):
         last = li == len(layers) - 1
         w = bf16_round(np.asarray(W, np.float32))
         Wb.append(w)
-        y = conv(acts[-1], w, np.asarray(b, np.float32) if b is not None else None, rb_off, pairs, relu=not last)
-        y = np.asarray(y, np.float64)
+        z = np.asarray(conv(acts[-1], w, np.asarray(b, np.float32) if b is not None else None, rb_off, pairs,
+                            relu=False), np.float64)
+        y = z if last else np.maximum(z, 0.0)
+        zs.append(z)
         pre.append(y)
         acts.append(y if last else bf16_round(y))
     logits, pvs = deinterleave_threshold(acts[-1], keys, occ, dims, d)
-    return dict(occ=occ, keys=keys, rb_off=rb_off, pairs=pairs, acts=acts, pre=pre, Wb=Wb, logits=logits, pvs=pvs)
+    return dict(occ=occ, keys=keys, rb_off=rb_off, pairs=pairs, acts=acts, pre=pre, z=zs, Wb=Wb, logits=logits,
+                pvs=pvs)
 
 
-def backward_bf16(out, layers, dlogits_rows, accum: str = "f64"):
+def backward_bf16(out, layers, dlogits_rows, accum: str = "f64", dy_bf16: bool = False):
     """Backward of ``forward_bf16`` at the BF16 path's rounding points: per layer, from the top,
     dZ = dY [Y > 0] (ReLU'(0) = 0; no mask on the last layer), its bfloat16 rounding dZb is the
     operand of the products, dX = sum_k dZb W_k^T over the transposed rulebook with the rounded
     weights, dW_k = sum X^T dZb with the layer's bfloat16 input X, and db = sum dZ (unrounded).
     dX is the next layer's dY.  FP64 between the rounding points.  Returns [(dW, db)] per layer
     and the list of each layer's dZb (top layer last).  accum = "f32": float32 accumulation
-    (subm_conv_bwd_f32, with dY carried in float32), for sizing end-to-end tolerances only."""
+    (subm_conv_bwd_f32, with dY carried in float32), for sizing end-to-end tolerances only.
+    dy_bf16: the gradient arriving at each hidden layer is itself rounded to bfloat16 first (a
+    chain of layers through torch autograd hands each layer the gradient in its output's dtype);
+    db then sums the rounded values."""
     acts, rb_off, pairs, Wb = out["acts"], out["rb_off"], out["pairs"], out["Wb"]
     grads = [None] * len(layers)
     dzb = [None] * len(layers)
     dY = np.asarray(dlogits_rows, np.float64)
     for li in range(len(layers) - 1, -1, -1):
         relu = li < len(layers) - 1
+        if relu and dy_bf16:
+            dY = bf16_round(dY)
         dZ = dY * (acts[li + 1] > 0) if relu else dY
         dZb = bf16_round(dZ)
         dzb[li] = dZb
@@ -395,6 +403,176 @@ def backward_bf16(out, layers, dlogits_rows, accum: str = "f64"):
         grads[li] = (dW, db)
         dY = dX
     return grads, dzb
+
+
+# ---------------------------------------------------------------- BF16 error bounds
+# The BF16 path fixes its rounding points (forward_bf16 / backward_bf16); what it leaves free is
+# the order of its float32 sums.  Every product it sums is exact in float32 (a product of two
+# bfloat16 values has at most 16 significant bits), so a sum of n such terms, added in any order
+# with a rounding after each addition, differs from the exact sum by at most
+# gamma_n * sum |term|, gamma_n = n u / (1 - n u) (Higham, Accuracy and Stability of Numerical
+# Algorithms, 2nd ed., Sec. 4.2).  u = 2^-23 covers both round-to-nearest and truncating adders.
+# A blocked sum whose block results are added with compensation (Neumaier) stays within the same
+# bound.  The functions below carry that bound through the network, with the bfloat16 rounding
+# of each hidden value evaluated on the whole interval it can come from (bfloat16 rounding is
+# monotone), so a value whose interval crosses a rounding boundary carries the whole quantum.
+F32_UNIT = 2.0 ** -23
+
+
+def f32_sum_gamma(n: int) -> float:
+    """gamma_n for float32 sums of n exact terms: |computed - exact| <= gamma_n sum |terms|."""
+    nu = n * F32_UNIT
+    if nu >= 1.0:
+        raise ValueError("sum too long for the float32 bound")
+    return nu / (1.0 - nu)
+
+
+def _round_interval_dev(x, lo, hi):
+    """Largest |bf16(t) - x| over t in [lo, hi], with x the rounding of a point of the interval."""
+    return np.maximum(bf16_round(hi) - x, x - bf16_round(lo))
+
+
+def forward_bf16_bound(out, layers) -> dict:
+    """Element-wise bounds on how far any float32-order evaluation of the BF16 network can lie
+    from ``forward_bf16``'s values (same rounded weights, same rounding points).
+
+    Layer l: the computed pre-activation z' = fl(sum x' w + b) with |x' - x| <= E_l satisfies
+    |z' - z| <= D_l = sum E_l |w| + gamma_{27 cin + 1} (sum (|x| + E_l) |w| + |b|).  The next input
+    x' = bf16(relu(z')) lies in [bf16(relu(z - D_l)), bf16(relu(z + D_l))], which gives E_{l+1};
+    the ReLU mask of the layer (x' > 0) is certain where both ends agree.  E_0 = 0 (the 0/1 input
+    is exact).  Returns D (per layer; the last one bounds the logits), E (per layer input) and
+    mask_certain (per hidden layer).  Bounds are widened by 1e-9 of themselves for the float64
+    evaluation of this function."""
+    acts, Wb, zs = out["acts"], out["Wb"], out["z"]
+    rb_off, pairs = out["rb_off"], out["pairs"]
+    E = np.zeros_like(np.asarray(acts[0], np.float64))
+    res = dict(D=[], E=[E], mask_certain=[])
+    for li, (_, b) in enumerate(layers):
+        aW = np.abs(Wb[li])
+        ab = np.abs(np.asarray(b, np.float64)) if b is not None else None
+        prop = subm_conv(E, aW, None, rb_off, pairs, relu=False)
+        mag = subm_conv(np.abs(acts[li]) + E, aW, ab, rb_off, pairs, relu=False)
+        D = (prop + f32_sum_gamma(27 * aW.shape[1] + 1) * mag) * (1.0 + 1e-9)
+        res["D"].append(D)
+        if li == len(layers) - 1:
+            break
+        z = zs[li]
+        lo = bf16_round(np.maximum(z - D, 0.0))
+        hi = bf16_round(np.maximum(z + D, 0.0))
+        E = _round_interval_dev(acts[li + 1], np.maximum(z - D, 0.0), np.maximum(z + D, 0.0))
+        res["E"].append(E)
+        res["mask_certain"].append((lo > 0) == (hi > 0))
+    return res
+
+
+def bf16_layer_bound(X, Wb, b, rb_off, pairs, relu: bool) -> dict:
+    """One BF16 layer on exact operands (X and the rounded weights Wb as float64 values of
+    bfloat16 numbers): the exact pre-activation z, the bound D = gamma_{27 cin + 1} (sum |x| |w| + |b|)
+    on any float32-order evaluation of it, and the interval [lo, hi] that the layer's rounded
+    output bf16(relu(z')) must lie in (lo == hi == bf16(relu(z)) unless z lies within D of a
+    rounding boundary).  Without relu (a last layer) lo / hi bound the float32 output itself."""
+    aW = np.abs(np.asarray(Wb, np.float64))
+    ab = np.abs(np.asarray(b, np.float64)) if b is not None else None
+    z = subm_conv(X, Wb, b, rb_off, pairs, relu=False)
+    D = f32_sum_gamma(27 * aW.shape[1] + 1) * subm_conv(np.abs(X), aW, ab, rb_off, pairs, relu=False)
+    D *= 1.0 + 1e-9
+    if relu:
+        lo, hi = bf16_round(np.maximum(z - D, 0.0)), bf16_round(np.maximum(z + D, 0.0))
+        x = bf16_round(np.maximum(z, 0.0))
+    else:
+        lo, hi, x = z - D, z + D, z
+    return dict(z=z, D=D, lo=lo, hi=hi, out=x)
+
+
+def bf16_layer_bwd_bound(X, Wb, rb_off, pairs, Y, dY, relu: bool, want_dx: bool = True) -> dict:
+    """Backward of one BF16 layer on exact operands: X (the layer's bfloat16 input), Wb (rounded
+    weights), Y (its bfloat16 output, for the ReLU mask) and dY (float32 values).  The path forms
+    dZ = dY [Y > 0] exactly, rounds it to dZb = bf16(dZ) (both sides round the same float32
+    value, so dZb is exact too) and sums exact products in float32.  Returns dX, dW, db with the
+    bounds E_dX = gamma_{27 cout} sum |dZb| |W|, E_dW = gamma_P sum |X| |dZb| (P the largest pair
+    count of an offset) and E_db = gamma_n sum |dZ|, plus dZb."""
+    dY = np.asarray(dY, np.float64)
+    dZ = dY * (np.asarray(Y) > 0) if relu else dY
+    dZb = bf16_round(dZ)
+    dX, dW, _ = subm_conv_bwd(X, Wb, rb_off, pairs, None, dZb, relu=False, want_dx=want_dx)
+    aW = np.abs(np.asarray(Wb, np.float64))
+    n = dZ.shape[0]
+    adx, adW, _ = subm_conv_bwd(np.abs(X), aW, rb_off, pairs, None, np.abs(dZb), relu=False, want_dx=want_dx)
+    P = int(np.diff(rb_off).max()) if len(pairs) else 1
+    w = 1.0 + 1e-9
+    return dict(dX=dX, dW=dW, db=dZ.sum(axis=0), dZb=dZb,
+                E_dX=None if adx is None else f32_sum_gamma(27 * aW.shape[2]) * adx * w,
+                E_dW=f32_sum_gamma(max(P, 1)) * adW * w,
+                E_db=f32_sum_gamma(max(n, 1)) * np.abs(dZ).sum(axis=0) * w)
+
+
+def loss_grad_bound(logits_rows, labels_rows, e_logits, lam: float = 0.99):
+    """Element-wise bound on the loss gradient's deviation when the logits deviate by at most
+    e_logits and the gradient is evaluated in float32 (one grid).
+
+    dL/dl = lam (p - y) / n + (1 - lam) p (1 - p) (1 - 2y) / max(GTP, 1) with p = sigmoid(l) (the
+    loss ``loss``); its derivative in l is at most lam / (4 n) + (1 - lam) / (6 sqrt 3) / max(GTP, 1)
+    in size (p (1 - p) <= 1/4 and |d/dl p (1 - p)| = p (1 - p) |1 - 2p| <= 1 / (6 sqrt 3)).  The float32
+    evaluation (sigmoid through exp, a few operations) is allowed 8 units of 2^-23 of each term's
+    scale and of the result."""
+    l = np.asarray(logits_rows, np.float64)
+    y = np.asarray(labels_rows, np.float64)
+    n = l.size
+    g_den = max(float(y.sum()), 1.0)
+    lip = lam / (4.0 * n) + (1.0 - lam) / (6.0 * np.sqrt(3.0)) / g_den
+    g = loss(l, np.asarray(labels_rows, np.uint8))["grad"]
+    return lip * np.asarray(e_logits, np.float64) + 8 * F32_UNIT * (lam / n + (1.0 - lam) / g_den + np.abs(g))
+
+
+def backward_bf16_bound(out, layers, fwd_bound, dlogits_rows, e_dlogits, dy_bf16: bool = False):
+    """Element-wise bounds on how far any float32-order evaluation of the BF16 backward can lie
+    from ``backward_bf16``'s gradients, given its forward deviation bounds (forward_bf16_bound)
+    and a bound e_dlogits on the deviation of the incoming dL/dlogits.
+
+    Per layer from the top, with E_dY the bound on dY: dZ = dY [x' > 0] deviates by E_dY where
+    the mask is certain and by |dY| + E_dY where it is not; dZb = bf16(dZ) by its interval's
+    rounding; the data gradient by sum E_dZb |W| + gamma_{27 cout} sum (|dZb| + E_dZb) |W| (the
+    next layer's E_dY); dW by sum (|X| + E_X)(|dZb| + E_dZb)(1 + gamma_P) - sum |X| |dZb| with P
+    the largest pair count of an offset; db by sum E_dZ + gamma_n sum (|dZ| + E_dZ).  Returns
+    [(E_dW, E_db)] per layer and the bound on the network input's gradient, widened by 1e-9 of
+    themselves.  dy_bf16 as in backward_bf16: the incoming gradient of each hidden layer is
+    rounded first, its deviation taken over its interval like the other rounding points."""
+    acts, Wb, rb_off, pairs = out["acts"], out["Wb"], out["rb_off"], out["pairs"]
+    n = np.asarray(acts[0]).shape[0]
+    g_p = f32_sum_gamma(int(np.diff(rb_off).max()) if len(pairs) else 1)
+    g_n = f32_sum_gamma(max(n, 1))
+    bounds = [None] * len(layers)
+    dY = np.asarray(dlogits_rows, np.float64)
+    E_dY = np.asarray(e_dlogits, np.float64)
+    for li in range(len(layers) - 1, -1, -1):
+        if li < len(layers) - 1 and dy_bf16:
+            dYr = bf16_round(dY)
+            E_dY = _round_interval_dev(dYr, dY - E_dY, dY + E_dY)
+            dY = dYr
+        if li < len(layers) - 1:
+            m = acts[li + 1] > 0
+            dZ = dY * m
+            E_dZ = np.where(fwd_bound["mask_certain"][li], m * E_dY, np.abs(dY) + E_dY)
+        else:
+            dZ, E_dZ = dY, E_dY
+        dZb = bf16_round(dZ)
+        E_dZb = _round_interval_dev(dZb, dZ - E_dZ, dZ + E_dZ)
+        X, E_X = np.abs(acts[li]), fwd_bound["E"][li]
+        aW = np.abs(Wb[li])
+        dxa, dWa, _ = subm_conv_bwd(X + E_X, aW, rb_off, pairs, None, np.abs(dZb) + E_dZb, relu=False,
+                                    want_dx=li > 0)
+        _, dWb, _ = subm_conv_bwd(X, aW, rb_off, pairs, None, np.abs(dZb), relu=False, want_dx=False)
+        E_dW = np.maximum((1.0 + g_p) * dWa - dWb, 0.0) * (1.0 + 1e-9)
+        E_db = (E_dZ.sum(axis=0) + g_n * (np.abs(dZ) + E_dZ).sum(axis=0)) * (1.0 + 1e-9)
+        bounds[li] = (E_dW, E_db)
+        if li == 0:
+            dxa, _, _ = subm_conv_bwd(X + E_X, aW, rb_off, pairs, None, np.abs(dZb) + E_dZb, relu=False,
+                                      want_dx=True)
+        dxc, _, _ = subm_conv_bwd(X, aW, rb_off, pairs, None, E_dZb, relu=False, want_dx=True)
+        E_dY = (dxc + f32_sum_gamma(27 * aW.shape[2]) * dxa) * (1.0 + 1e-9)
+        if li > 0:
+            dY, _, _ = subm_conv_bwd(acts[li], Wb[li], rb_off, pairs, None, dZb, relu=False, want_dx=True)
+    return bounds, E_dY
 
 
 # ---------------------------------------------------------------- evaluation metrics
@@ -655,6 +833,148 @@ def unet_backward(out, params, dY_rows):
     dS = subm_chain("enc0", dS, rb0)
     dX = subm_chain("stem", dS, rb0)
     return grads, dX
+
+
+# ---------------------------------------------------------------- the U-Net at the BF16 rounding points
+def _strided_down_f32(X0, children, W, b, relu: bool):
+    X0, W = np.asarray(X0, np.float32), np.asarray(W, np.float32)
+    Y = np.zeros((children.shape[1], W.shape[2]), np.float32)
+    for k in range(8):
+        has = children[k] >= 0
+        Y[has] += X0[children[k, has]] @ W[k]
+    Y += np.asarray(b, np.float32)
+    return np.maximum(Y, 0.0) if relu else Y
+
+
+def _inverse_up_f32(X1, parent, kid, W, b, relu: bool):
+    X1, W = np.asarray(X1, np.float32), np.asarray(W, np.float32)
+    Y = np.zeros((len(parent), W.shape[2]), np.float32)
+    for k in range(8):
+        sel = kid == k
+        Y[sel] = X1[parent[sel]] @ W[k]
+    Y += np.asarray(b, np.float32)
+    return np.maximum(Y, 0.0) if relu else Y
+
+
+def unet_forward_bf16(tris, dims, d, params, occ=None, accum: str = "f64"):
+    """``unet_forward`` at the BF16 path's rounding points: every weight rounded to bfloat16 from
+    its float32 master, each layer's result after bias and ReLU (stem, enc0, down, enc1, up,
+    dec0) rounded to bfloat16, the concatenation joining rounded values, the head's logits not
+    rounded.  FP64 between the rounding points; accum = "f32" evaluates every sum with float32
+    accumulation instead (a second evaluation order, for sizing tolerances only).  Returns the
+    keys of ``unet_forward`` plus Wr (the rounded weights by stage)."""
+    nx, ny, nz = dims
+    if occ is None:
+        occ, _ = froxelize(tris, dims)
+    f32 = accum == "f32"
+    b0 = (nx // d, ny // d, nz // d)
+    keys0 = active_sites(occ, dims, d)
+    keys1 = active_sites(occ, dims, 2 * d)
+    rb0 = rulebook(keys0, b0)
+    rb1 = rulebook(keys1, (b0[0] // 2, b0[1] // 2, b0[2] // 2))
+    children, parent, kid = level_maps(keys0, keys1, b0)
+    Wr = {st: [(bf16_round(np.asarray(W, np.float32)), np.asarray(b, np.float32)) for W, b in v]
+          for st, v in params.items()}
+
+    def sub(h, W, b, rb, relu=True):
+        y = np.asarray((subm_conv_f32 if f32 else subm_conv)(h, W, b, *rb, relu=relu), np.float64)
+        return bf16_round(y) if relu else y
+
+    acts = {"X": gather_sites(occ, dims, d, keys0)}
+    inputs = {st: [] for st in params}
+    h = acts["X"]
+    for st in ("stem", "enc0"):
+        for W, b in Wr[st]:
+            inputs[st].append(h)
+            h = sub(h, W, b, rb0)
+    acts["skip"] = h
+    (W, b), = Wr["down"]
+    inputs["down"].append(h)
+    h1 = bf16_round(np.asarray((_strided_down_f32 if f32 else strided_down)(h, children, W, b, True), np.float64))
+    for W, b in Wr["enc1"]:
+        inputs["enc1"].append(h1)
+        h1 = sub(h1, W, b, rb1)
+    acts["coarse"] = h1
+    (W, b), = Wr["up"]
+    inputs["up"].append(h1)
+    u = bf16_round(np.asarray((_inverse_up_f32 if f32 else inverse_up)(h1, parent, kid, W, b, True), np.float64))
+    acts["up"] = u
+    h = np.concatenate([u, acts["skip"]], axis=1)
+    for W, b in Wr["dec0"]:
+        inputs["dec0"].append(h)
+        h = sub(h, W, b, rb0)
+    (W, b), = Wr["head"]
+    inputs["head"].append(h)
+    Y = sub(h, W, b, rb0, relu=False)
+    acts["Y"] = Y
+    acts["inputs"] = inputs
+    logits, pvs = deinterleave_threshold(Y, keys0, occ, dims, d)
+    return dict(occ=occ, keys0=keys0, keys1=keys1, children=children, parent=parent, kid=kid, acts=acts,
+                rb0=rb0, rb1=rb1, logits=logits, pvs=pvs, Wr=Wr)
+
+
+def unet_backward_bf16(out, dY_rows, accum: str = "f64"):
+    """Backward of ``unet_forward_bf16`` at the BF16 path's rounding points: per layer,
+    dZ = dY [Y > 0] (no mask on the head), its bfloat16 rounding dZb is the operand of the
+    products (dX = dZb W^T through the layer's pairs or children, dW = X^T dZb with the layer's
+    bfloat16 input), db = sum dZ unrounded; the concatenation's gradient splits into its up and
+    skip parts, and the skip's part adds the gradient through the strided convolution (one
+    addition of two values).  FP64 between the rounding points, or float32 accumulation with
+    accum = "f32".  Returns {stage: [(dW, db), ...]}."""
+    f32 = accum == "f32"
+    acts, Wr = out["acts"], out["Wr"]
+    inp = acts["inputs"]
+    rb0, rb1 = out["rb0"], out["rb1"]
+    children, parent, kid = out["children"], out["parent"], out["kid"]
+    grads = {st: [None] * len(v) for st, v in Wr.items()}
+    cast = (lambda a: np.asarray(np.asarray(a, np.float32), np.float64)) if f32 else (lambda a: a)
+
+    def layer_bwd(kind, X, W, Y, dY, relu, rb=None):
+        dZ = dY * (Y > 0) if relu else dY
+        dZb = bf16_round(dZ)
+        if kind == "subm":
+            if f32:
+                dX, dW = subm_conv_bwd_f32(X, W, *rb, dZb)
+            else:
+                dX, dW, _ = subm_conv_bwd(X, W, *rb, None, dZb, relu=False)
+        else:
+            X32, W32, dZ32 = (np.asarray(a, np.float32 if f32 else np.float64) for a in (X, W, dZb))
+            dX = np.zeros_like(X32)
+            dW = np.zeros_like(W32)
+            for k in range(8):
+                if kind == "down":
+                    has = children[k] >= 0
+                    rows = children[k, has]
+                    dX[rows] = dZ32[has] @ W32[k].T
+                    dW[k] = X32[rows].T @ dZ32[has]
+                else:
+                    sel = kid == k
+                    np.add.at(dX, parent[sel], dZ32[sel] @ W32[k].T)
+                    dW[k] = X32[parent[sel]].T @ dZ32[sel]
+        db = np.asarray(dZ, np.float32).sum(0, dtype=np.float32) if f32 else dZ.sum(0)
+        return cast(dX), np.asarray(dW, np.float64), np.asarray(db, np.float64)
+
+    def chain(st, dY, rb, last_out, relu_top=True):
+        ins = inp[st]
+        outs = ins[1:] + [last_out]
+        for i in range(len(ins) - 1, -1, -1):
+            dY, dW, db = layer_bwd("subm", ins[i], Wr[st][i][0], outs[i], dY, relu_top or i < len(ins) - 1, rb)
+            grads[st][i] = (dW, db)
+        return dY
+
+    dH = chain("head", cast(dY_rows), rb0, acts["Y"], relu_top=False)
+    dH = chain("dec0", dH, rb0, inp["head"][0])
+    Dc = acts["up"].shape[1]
+    dU, dS = dH[:, :Dc], dH[:, Dc:]
+    dC, dW, db = layer_bwd("up", inp["up"][0], Wr["up"][0][0], acts["up"], dU, True)
+    grads["up"][0] = (dW, db)
+    dC = chain("enc1", dC, rb1, acts["coarse"])
+    dX0, dW, db = layer_bwd("down", inp["down"][0], Wr["down"][0][0], inp["enc1"][0], dC, True)
+    grads["down"][0] = (dW, db)
+    dS = cast(dS + dX0)
+    dS = chain("enc0", dS, rb0, acts["skip"])
+    chain("stem", dS, rb0, inp["enc0"][0])
+    return grads
 
 
 # ---------------------------------------------------------------- world-space front end

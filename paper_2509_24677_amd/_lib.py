@@ -67,6 +67,7 @@ PI64 = ctypes.POINTER(ctypes.c_int64)
 
 SIGNATURES = {
     "npvs_version": (ctypes.c_char_p, []),
+    "npvs_source_hash": (ctypes.c_char_p, []),
     "npvs_last_error": (ctypes.c_char_p, []),
     "npvs_batch_sizes": (i32, [i32, P, i32, PI64, PI64]),
     "npvs_froxelize_workspace_size": (i32, [i32, P, P, PS]),
@@ -132,9 +133,11 @@ def header_functions() -> list[str]:
 
 
 def get() -> ctypes.CDLL:
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built, or if it was built from sources other
+    than the ones in this tree (its compiled-in source hash differs)."""
     global _lib
     if _lib is None:
+        from . import build
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
                                "(python -c 'import __graft_entry__ as g; g.build()')")
@@ -143,6 +146,10 @@ def get() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        built, want = L.npvs_source_hash().decode(), build.source_hash()
+        if built != want:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, the tree's sources hash to "
+                               f"{want}): rebuild it (python -c 'import __graft_entry__ as g; g.build()')")
         _lib = L
     return _lib
 

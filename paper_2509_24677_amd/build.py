@@ -6,6 +6,7 @@ library that exports the C ABI of ``include/neuralpvs.h``.
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -27,14 +28,29 @@ def sources():
     return sorted(glob.glob(os.path.join(SRC, "*.hip")))
 
 
+def source_hash() -> str:
+    """16 hex digits of SHA-256 over every file the library is built from (csrc/*.hip, csrc/*.hpp,
+    include/neuralpvs.h) and the compile flags; compiled into the library (npvs_source_hash) so
+    the loader can refuse a library built from other sources."""
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    files = sources() + sorted(glob.glob(os.path.join(SRC, "*.hpp")))
+    files.append(os.path.join(os.path.dirname(HERE), "include", "neuralpvs.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode() + b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT, exist_ok=True)
     procs = []
     objs = []
+    tag = f'-DNPVS_SOURCE_HASH="{source_hash()}"'
     for src in sources():
         obj = os.path.join(OUT, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, tag, "-c", src, "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     errors = []
     for src, p in procs:

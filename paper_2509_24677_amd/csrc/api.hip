@@ -78,6 +78,11 @@ using namespace npvs;
 
 extern "C" const char *npvs_version(void) { return "neuralpvs-gfx950 0.1.0"; }
 
+#ifndef NPVS_SOURCE_HASH
+#define NPVS_SOURCE_HASH "unknown"
+#endif
+extern "C" const char *npvs_source_hash(void) { return NPVS_SOURCE_HASH; }
+
 extern "C" const char *npvs_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" npvs_status npvs_batch_sizes(int32_t n_grids, const npvs_dims *dims, int32_t d, int64_t *total_blocks,

@@ -70,3 +70,40 @@ def conv_tolerance(X, W, rb_off, pairs, n_terms_scale=2.0):
 def scene(name, i=0):
     cfg = synth.config(name)
     return cfg, synth.scene_for(cfg, i)
+
+
+# End-to-end BF16 tolerance.  Two float32 evaluation orders of the same BF16 network (same
+# rounded weights, same rounding points) differ only where a float32 sum lands on the other side
+# of a bfloat16 rounding boundary or of the ReLU's zero; the deviation that follows is one
+# bfloat16 quantum at a few hidden values, carried on by the later layers.  The oracle measures
+# how large that gets on the same input by evaluating its BF16 network a second time with
+# float32 accumulation (forward_bf16 / backward_bf16 with accum="f32").  The library's order is
+# a third one; its results must lie within DRIFT_FACTOR times the oracle's own drift, per tensor
+# (max-abs).  The arithmetic of each layer is checked separately against rigorous bounds.
+DRIFT_FACTOR = 4.0
+
+
+def bf16_reference(t, dims, d, layers, occ=None, labels_mask=None):
+    """The oracle's BF16 network on one grid in FP64 between the rounding points (emu) and with
+    float32 accumulation (o32); with labels_mask, also the loss gradient and the backward of
+    both (g, g32: [(dW, db)] per layer) from the oracle's own labels."""
+    emu = oracle.forward_bf16(t, dims, d, layers, occ=occ)
+    o32 = oracle.forward_bf16(t, dims, d, layers, occ=emu["occ"], accum="f32")
+    # the float32 bound of the last layer alone: what remains when no rounding decision differs
+    last = oracle.bf16_layer_bound(emu["acts"][-2], emu["Wb"][-1], layers[-1][1], emu["rb_off"], emu["pairs"],
+                                   relu=False)
+    res = dict(emu=emu, o32=o32, logit_floor=float(last["D"].max()) if last["D"].size else 0.0)
+    if labels_mask is not None:
+        occf = emu["occ"].reshape(-1)
+        lab = oracle.site_labels(occf & labels_mask, dims, d, emu["keys"])
+        dl = oracle.loss(emu["acts"][-1], lab)["grad"]
+        dl32 = oracle.loss(o32["acts"][-1], lab)["grad"].astype(np.float32).astype(np.float64)
+        res["g"], _ = oracle.backward_bf16(emu, layers, dl)
+        res["g32"], _ = oracle.backward_bf16(o32, layers, dl32, accum="f32")
+        res["labels"] = lab
+    return res
+
+
+def drift_tol(a_ref, a_alt, floor=0.0):
+    """DRIFT_FACTOR times the max-abs distance of the oracle's two evaluation orders."""
+    return DRIFT_FACTOR * max(float(np.abs(np.asarray(a_alt) - np.asarray(a_ref)).max()), floor)

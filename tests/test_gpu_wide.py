@@ -68,8 +68,17 @@ def test_network_at_paper_interleave_factors(name, dtype):
     got = to_np(logits)
     assert act.any()
     assert (got[~act] == -np.inf).all()
-    err = np.abs(got[act] - ref[act]).max()
-    assert err <= (1e-5 if dtype == npvs.NPVS_F32 else 0.1), err
+    if dtype == npvs.NPVS_F32:
+        err = np.abs(got[act] - ref[act]).max()
+        assert err <= 1e-5, err
+    else:  # against the oracle's BF16 network under the rigorous bound of forward_bf16_bound
+        emu = oracle.forward_bf16(t, cfg.grids[0], cfg.d, layers)
+        fb = oracle.forward_bf16_bound(emu, layers)
+        lg, _ = oracle.deinterleave_threshold(fb["D"][-1], emu["keys"], emu["occ"], cfg.grids[0], cfg.d)
+        bound = lg.reshape(-1)[act]
+        err = np.abs(got[act] - emu["logits"].reshape(-1)[act])
+        print(f"{name} bf16: max err {err.max():.3e}, max err / bound {np.max(err / bound):.3e}", flush=True)
+        assert np.all(err <= bound)
     if dtype == npvs.NPVS_F32:  # the thresholded bits agree wherever the logit is not within the error
         pv = np.unpackbits(to_np(pvs), bitorder="little")
         pw = np.unpackbits(out["pvs"].reshape(-1), bitorder="little")
@@ -133,8 +142,9 @@ def test_conv_bwd_wide_layers_match_oracle(cin, cout, d, dtype):
 @pytest.mark.parametrize("name", ["boxes64_d8", "boxes64_d16"])
 def test_network_backward_at_paper_interleave_factors(name):
     """Gradients of BCE + repulsive visibility loss through the whole network at d = 8 and 16
-    (first and last layers d^3 wide) against the oracle's FP64 backward: FP32 within float32
-    rounding, BF16 within its operand rounding."""
+    (first and last layers d^3 wide): FP32 against the oracle's FP64 backward within float32
+    rounding, BF16 against the oracle's BF16 network within the rigorous bounds of
+    backward_bf16_bound."""
     cfg = synth.config(name)
     t = synth.scene_for(cfg)
     layers = synth.net_layers(cfg, bias_std=0.05)
@@ -149,6 +159,13 @@ def test_network_backward_at_paper_interleave_factors(name):
     ref_lab = oracle.site_labels(o & synth.label_mask_bits(5, (o.size,)), cfg.grids[0], cfg.d, out["keys"])
     ref_dl = oracle.loss(out["acts"][-1], ref_lab)["grad"]
     ref, _ = oracle.backward(out, layers, ref_dl)
+    # BF16: the oracle's BF16 network and the rigorous bounds of its backward
+    emu = oracle.forward_bf16(t, cfg.grids[0], cfg.d, layers, occ=out["occ"])
+    fb = oracle.forward_bf16_bound(emu, layers)
+    bdl = oracle.loss(emu["acts"][-1], ref_lab)["grad"]
+    e_dl = oracle.loss_grad_bound(emu["acts"][-1], ref_lab, fb["D"][-1])
+    bref, _ = oracle.backward_bf16(emu, layers, bdl)
+    bbnd, _ = oracle.backward_bf16_bound(emu, layers, fb, bdl, e_dl)
     for dtype in (npvs.NPVS_F32, npvs.NPVS_BF16):
         net = Network(layers, cfg.d, dtype)
         X0 = npvs.gather_input(occ, rb, dtype)
@@ -157,12 +174,19 @@ def test_network_backward_at_paper_interleave_factors(name):
         grads = net.backward(saved, logits, dl, rb)
         torch.cuda.synchronize()
         for li in range(len(layers)):
-            for a, b, nm in ((to_np(grads[li][0]), ref[li][0], "dW"), (to_np(grads[li][1]), ref[li][1], "db")):
-                scale = np.abs(b).max()
-                rel = np.abs(a - b).max() / scale
-                print(f"{name} dtype {dtype} layer {li} {nm}: max rel err {rel:.3e} (max|g| {scale:.3e})", flush=True)
-                assert scale > 0
-                assert rel <= (1e-4 if dtype == npvs.NPVS_F32 else 0.1)
+            for j, nm in ((0, "dW"), (1, "db")):
+                a = to_np(grads[li][j])
+                if dtype == npvs.NPVS_F32:
+                    b = ref[li][j]
+                    scale = np.abs(b).max()
+                    rel = np.abs(a - b).max() / scale
+                    print(f"{name} fp32 layer {li} {nm}: max rel err {rel:.3e} (max|g| {scale:.3e})", flush=True)
+                    assert scale > 0 and rel <= 1e-4
+                else:
+                    e = np.abs(a - bref[li][j])
+                    print(f"{name} bf16 layer {li} {nm}: max err / bound {np.max(e / np.maximum(bbnd[li][j], 1e-300)):.3e}, "
+                          f"max bound / max|g| {bbnd[li][j].max() / np.abs(bref[li][j]).max():.3e}", flush=True)
+                    assert np.all(e <= bbnd[li][j])
 
 
 @pytest.mark.parametrize("cin,cout", [(512, 64), (64, 4096)])

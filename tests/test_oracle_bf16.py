@@ -136,3 +136,274 @@ def test_float32_order_variants_stay_within_the_float32_bound():
     bw = len(pairs) * u * 2 * np.abs(oracle.subm_conv_bwd(np.abs(x32), np.abs(w32), rb_off, pairs, None, np.abs(dZ),
                                                           relu=False)[1])
     assert np.all(np.abs(dW32 - dW64) <= bw + 1e-300)
+
+
+# ------------------------------------------------------------------ error bounds of the BF16 path
+# Pins of f32_sum_gamma, bf16_layer_bound, bf16_layer_bwd_bound, forward_bf16_bound,
+# backward_bf16_bound and loss_grad_bound: hand values on the one-site network, containment of
+# float32 evaluations in several orders (numpy's sequential and pairwise float32 sums), and
+# planted mistakes that every tight bound must reject.
+import synth
+
+
+def _f32_orders(X, W, b, rb_off, pairs):
+    """Three float32-accumulation evaluations of one layer (no ReLU): offsets in order, offsets
+    reversed, and one pairwise float32 sum over all 27 cin products and the bias per output."""
+    X32, W32 = np.asarray(X, np.float32), np.asarray(W, np.float32)
+    b32 = np.asarray(b, np.float32)
+    fwd = oracle.subm_conv_f32(X32, W32, b32, rb_off, pairs, relu=False)
+    rev = np.zeros_like(fwd)
+    for k in range(26, -1, -1):
+        p = pairs[rb_off[k]:rb_off[k + 1]]
+        if len(p):
+            rev[p[:, 1]] += X32[p[:, 0]] @ W32[k]
+    rev += b32
+    n, cin = X32.shape
+    terms = np.zeros((n, 27 * cin + 1, W32.shape[2]), np.float32)
+    for k in range(27):
+        p = pairs[rb_off[k]:rb_off[k + 1]]
+        terms[p[:, 1], k * cin:(k + 1) * cin, :] = X32[p[:, 0]][:, :, None] * W32[k][None, :, :]
+    terms[:, -1, :] = b32
+    pw = terms.sum(axis=1, dtype=np.float32)
+    return [np.asarray(a, np.float64) for a in (fwd, rev, pw)]
+
+
+def _tiny_case():
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    return cfg, t, layers, oracle.forward_bf16(t, cfg.grids[0], cfg.d, layers)
+
+
+def test_f32_sum_gamma_closed_form_and_containment():
+    u = 2.0 ** -23
+    assert oracle.f32_sum_gamma(1) == u / (1 - u)
+    assert oracle.f32_sum_gamma(1000) == 1000 * u / (1 - 1000 * u)
+    with pytest.raises(ValueError):
+        oracle.f32_sum_gamma(2 ** 23)
+    rng = np.random.default_rng(3)
+    for n in (2, 17, 1000, 20000):
+        t = (rng.standard_normal(n) * np.exp(rng.uniform(-8, 8, n))).astype(np.float32)
+        exact = np.sum(t.astype(np.float64))  # exact float32 terms; float64 error far below the bound
+        g = oracle.f32_sum_gamma(n) * np.abs(t.astype(np.float64)).sum()
+        seq = np.float32(0)
+        for v in t:
+            seq = np.float32(seq + v)
+        for s in (seq, t.sum(dtype=np.float32), t[::-1].sum(dtype=np.float32)):
+            assert abs(float(s) - exact) <= g
+
+
+def test_layer_bound_hand_example():
+    tris, layers = _one_site_net()
+    emu = oracle.forward_bf16(tris, (8, 4, 4), 2, layers)
+    (W1, b1), (W2, b2) = layers
+    r = oracle.bf16_layer_bound(emu["acts"][0], emu["Wb"][0], b1, emu["rb_off"], emu["pairs"], relu=True)
+    g = oracle.f32_sum_gamma(27 * 8 + 1)
+    # z = 1 * 1 + 2^-8 (a tie); sum |x| |w| + |b| = 1 + 2^-8
+    assert r["z"][0, 0] == 1.0 + 2.0 ** -8
+    assert r["D"][0, 0] == pytest.approx(g * (1.0 + 2.0 ** -8), rel=1e-8)
+    assert r["lo"][0, 0] == 1.0 and r["hi"][0, 0] == 1.0 + 2.0 ** -7 and r["out"][0, 0] == 1.0
+    # channels with no weight and no bias: z = 0 exactly, D = 0, the output is certainly 0
+    assert (r["D"][0, 1:] == 0).all() and (r["lo"][0, 1:] == 0).all() and (r["hi"][0, 1:] == 0).all()
+    # the propagated bound: E_1 = the whole quantum 2^-7 at the tie, so the logit carries 3 * 2^-7
+    fb = oracle.forward_bf16_bound(emu, layers)
+    assert fb["E"][1][0, 0] == 2.0 ** -7 and (fb["E"][1][0, 1:] == 0).all()
+    assert fb["mask_certain"][0].all()
+    want = 3 * 2.0 ** -7 + g * ((1.0 + 2.0 ** -7) * 3.0 + 2.0 ** -10)
+    assert fb["D"][1][0, 3] == pytest.approx(want, rel=1e-8)
+
+
+def test_layer_bound_contains_float32_orders_and_rejects_planted_mistakes():
+    cfg, t, layers, emu = _tiny_case()
+    rb_off, pairs = emu["rb_off"], emu["pairs"]
+    n_checked = 0
+    for li, (_, b) in enumerate(layers):
+        relu = li < len(layers) - 1
+        X, Wb = emu["acts"][li], emu["Wb"][li]
+        r = oracle.bf16_layer_bound(X, Wb, b, rb_off, pairs, relu)
+        for z32 in _f32_orders(X, Wb, b, rb_off, pairs):
+            assert np.all(np.abs(z32 - r["z"]) <= r["D"])
+            if relu:
+                o = oracle.bf16_round(np.maximum(z32, 0.0))
+                assert np.all((o >= r["lo"]) & (o <= r["hi"]))
+            n_checked += 1
+        # planted mistakes: a dropped offset, the bias left out, truncation instead of RNE
+        W_drop = Wb.copy()
+        W_drop[4] = 0.0
+        z_drop = oracle.subm_conv(X, W_drop, b, rb_off, pairs, relu=False)
+        assert np.any(np.abs(z_drop - r["z"]) > r["D"])
+        z_nob = oracle.subm_conv(X, Wb, None, rb_off, pairs, relu=False)
+        assert np.any(np.abs(z_nob - r["z"]) > r["D"])
+        if relu:
+            zz = np.maximum(r["z"], 0.0).astype(np.float32)
+            trunc = (zz.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+            assert np.any((trunc < r["lo"]) | (trunc > r["hi"]))
+    assert n_checked == 9
+    # the worst-case gamma_n bound still pins most outputs to one bfloat16 value (82 % here)
+    r = oracle.bf16_layer_bound(emu["acts"][1], emu["Wb"][1], layers[1][1], rb_off, pairs, True)
+    assert (r["lo"] == r["hi"]).mean() > 0.75
+
+
+def test_layer_bwd_bound_contains_float32_orders_and_rejects_planted_mistakes():
+    cfg, t, layers, emu = _tiny_case()
+    rb_off, pairs = emu["rb_off"], emu["pairs"]
+    rng = np.random.default_rng(21)
+    for li in range(len(layers)):
+        relu = li < len(layers) - 1
+        X, Wb, Y = emu["acts"][li], emu["Wb"][li], emu["acts"][li + 1]
+        dY = (rng.standard_normal(Y.shape) * 1e-2).astype(np.float32).astype(np.float64)
+        r = oracle.bf16_layer_bwd_bound(X, Wb, rb_off, pairs, Y, dY, relu, want_dx=True)
+        dZ = dY * (Y > 0) if relu else dY
+        assert np.array_equal(r["dZb"], oracle.bf16_round(dZ))
+        dX32, dW32 = oracle.subm_conv_bwd_f32(X, Wb, rb_off, pairs, r["dZb"])
+        assert np.all(np.abs(dX32 - r["dX"]) <= r["E_dX"])
+        assert np.all(np.abs(dW32 - r["dW"]) <= r["E_dW"])
+        db32 = np.asarray(dZ, np.float32).sum(axis=0, dtype=np.float32)
+        assert np.all(np.abs(db32 - r["db"]) <= r["E_db"])
+        # planted: dZ not rounded to bfloat16 before the products; no ReLU mask; W not transposed
+        _, dW_nr, _ = oracle.subm_conv_bwd(X, Wb, rb_off, pairs, None, dZ, relu=False, want_dx=False)
+        assert np.any(np.abs(dW_nr - r["dW"]) > r["E_dW"])
+        if relu:
+            _, dW_nm, _ = oracle.subm_conv_bwd(X, Wb, rb_off, pairs, None, oracle.bf16_round(dY), relu=False,
+                                               want_dx=False)
+            assert np.any(np.abs(dW_nm - r["dW"]) > r["E_dW"])
+        if Wb.shape[1] == Wb.shape[2]:
+            dX_nt, _, _ = oracle.subm_conv_bwd(X, np.transpose(Wb, (0, 2, 1)), rb_off, pairs, None, r["dZb"],
+                                               relu=False)
+            assert np.any(np.abs(dX_nt - r["dX"]) > r["E_dX"])
+
+
+def test_network_bounds_contain_a_float32_order_evaluation():
+    cfg, t, layers, emu = _tiny_case()
+    fb = oracle.forward_bf16_bound(emu, layers)
+    o32 = oracle.forward_bf16(t, cfg.grids[0], cfg.d, layers, accum="f32")
+    for li in range(1, len(layers)):
+        assert np.all(np.abs(o32["acts"][li] - emu["acts"][li]) <= fb["E"][li])
+    assert np.all(np.abs(o32["acts"][-1] - emu["acts"][-1]) <= fb["D"][-1])
+    occ = emu["occ"].reshape(-1)
+    lab = oracle.site_labels(occ & synth.label_mask_bits(5, (occ.size,)), cfg.grids[0], cfg.d, emu["keys"])
+    dl = oracle.loss(emu["acts"][-1], lab)["grad"]
+    e_dl = oracle.loss_grad_bound(emu["acts"][-1], lab, fb["D"][-1])
+    dl32 = oracle.loss(o32["acts"][-1], lab)["grad"].astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(dl32 - dl) <= e_dl)
+    bb, e_dx0 = oracle.backward_bf16_bound(emu, layers, fb, dl, e_dl)
+    g, _ = oracle.backward_bf16(emu, layers, dl)
+    g32, _ = oracle.backward_bf16(o32, layers, dl32, accum="f32")
+    for li in range(len(layers)):
+        assert np.all(np.abs(g32[li][0] - g[li][0]) <= bb[li][0])
+        assert np.all(np.abs(g32[li][1] - g[li][1]) <= bb[li][1])
+    # with the incoming gradient of each hidden layer rounded to bfloat16 as well
+    gr, _ = oracle.backward_bf16(emu, layers, dl, dy_bf16=True)
+    gr32, _ = oracle.backward_bf16(o32, layers, dl32, accum="f32", dy_bf16=True)
+    bbr, _ = oracle.backward_bf16_bound(emu, layers, fb, dl, e_dl, dy_bf16=True)
+    for li in range(len(layers)):
+        assert np.all(np.abs(gr32[li][0] - gr[li][0]) <= bbr[li][0])
+        assert np.all(np.abs(gr32[li][1] - gr[li][1]) <= bbr[li][1])
+    # the hidden layers' db sums bfloat16 values then; the top layer's is unchanged
+    assert np.array_equal(gr[-1][1], g[-1][1]) and not np.array_equal(gr[0][1], g[0][1])
+    # the input gradient: products of the rounded dZ of layer 0 with its weights
+    _, dzb = oracle.backward_bf16(emu, layers, dl)
+    _, dzb32 = oracle.backward_bf16(o32, layers, dl32, accum="f32")
+    dx0, _ = oracle.subm_conv_bwd_f32(emu["acts"][0], emu["Wb"][0], emu["rb_off"], emu["pairs"], dzb32[0])
+    dx0_ref, _, _ = oracle.subm_conv_bwd(emu["acts"][0], emu["Wb"][0], emu["rb_off"], emu["pairs"], None, dzb[0],
+                                         relu=False)
+    assert np.all(np.abs(dx0 - dx0_ref) <= e_dx0)
+    # the bound of a layer whose inputs are exact equals the one-layer bound
+    r = oracle.bf16_layer_bound(emu["acts"][0], emu["Wb"][0], layers[0][1], emu["rb_off"], emu["pairs"], True)
+    np.testing.assert_allclose(fb["D"][0], r["D"], rtol=1e-12, atol=0)
+
+
+def test_loss_grad_bound_lipschitz_and_float32_evaluation():
+    rng = np.random.default_rng(4)
+    n = 4000
+    l = rng.standard_normal(n) * 4
+    y = (rng.random(n) < 0.2).astype(np.uint8)
+    e = np.full(n, 0.05)
+    bnd = oracle.loss_grad_bound(l, y, e)
+    g = oracle.loss(l, y)["grad"]
+    for s in range(5):
+        d = rng.uniform(-1, 1, n) * e
+        g2 = oracle.loss(l + d, y)["grad"]
+        assert np.all(np.abs(g2 - g) <= bnd)
+    # the largest slope of p (1 - p) is 1 / (6 sqrt 3), at p = 1/2 +- 1/(2 sqrt 3)
+    t = np.linspace(-6, 6, 200001)
+    p = 1 / (1 + np.exp(-t))
+    slope = np.abs(p * (1 - p) * (1 - 2 * p))
+    assert slope.max() == pytest.approx(1 / (6 * np.sqrt(3)), rel=1e-6)
+    # a float32 evaluation of the gradient formula, on the same logits
+    lam, g_den = 0.99, max(float(y.sum()), 1.0)
+    l32 = l.astype(np.float32)
+    p32 = np.float32(1) / (np.float32(1) + np.exp(-l32))
+    yf = y.astype(np.float32)
+    g32 = (np.float32(lam / n) * (p32 - yf) + np.float32((1 - lam) / g_den) * p32 * (np.float32(1) - p32)
+           * (np.float32(1) - np.float32(2) * yf)).astype(np.float64)
+    g_exact = oracle.loss(l32.astype(np.float64), y)["grad"]
+    assert np.all(np.abs(g32 - g_exact) <= oracle.loss_grad_bound(l32.astype(np.float64), y, np.zeros(n)))
+
+
+def _unet_exact_params(rng, d, E=4, Dc=6):
+    # weights in {0, +-1/2, +-1} (sparse), zero biases: every value of the network is a small
+    # multiple of a power of two, exactly representable in bfloat16
+    def conv(k, cin, cout):
+        W = (rng.integers(-2, 3, size=(k, cin, cout)) / 2.0 * (rng.random((k, cin, cout)) < 0.12)).astype(np.float32)
+        return W, np.zeros(cout, np.float32)
+    C = d ** 3
+    return dict(stem=[conv(27, C, E)], enc0=[conv(27, E, E) for _ in range(2)], down=[conv(8, E, E)],
+                enc1=[conv(27, E, E) for _ in range(3)], up=[conv(8, E, Dc)],
+                dec0=[conv(27, Dc + E, Dc), conv(27, Dc, Dc)], head=[conv(27, Dc, C)])
+
+
+def test_unet_bf16_reduces_to_fp64_when_everything_is_representable():
+    rng = np.random.default_rng(31)
+    dims = (16, 16, 16)
+    tris = (rng.uniform(0, 16, size=(40, 1, 3)) + rng.uniform(-1.5, 1.5, size=(40, 3, 3))).astype(np.float32)
+    params = _unet_exact_params(rng, 2)
+    emu = oracle.unet_forward_bf16(tris, dims, 2, params)
+    ref = oracle.unet_forward(tris, dims, 2, params)
+    assert np.abs(ref["acts"]["Y"]).max() > 0 and np.all(oracle.bf16_round(ref["acts"]["skip"]) == ref["acts"]["skip"])
+    for k in ("X", "skip", "coarse", "up", "Y"):
+        np.testing.assert_array_equal(emu["acts"][k], ref["acts"][k])
+
+
+def test_unet_bf16_without_its_rounding_is_the_fp64_unet(monkeypatch):
+    # with bfloat16 rounding replaced by the identity, the BF16 U-Net (forward and backward, both
+    # evaluation orders' wiring) is the FP64 U-Net: the rounding points are the only difference
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    params = synth.unet_params(6, 2, E=16, Dc=24)
+    p64 = {k: [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in v] for k, v in params.items()}
+    monkeypatch.setattr(oracle, "bf16_round", lambda x: np.asarray(x, np.float64))
+    emu = oracle.unet_forward_bf16(t, cfg.grids[0], 2, params)
+    ref = oracle.unet_forward(t, cfg.grids[0], 2, p64)
+    np.testing.assert_allclose(emu["acts"]["Y"], ref["acts"]["Y"], rtol=1e-12, atol=1e-12)
+    dY = np.random.default_rng(2).standard_normal(emu["acts"]["Y"].shape)
+    g = oracle.unet_backward_bf16(emu, dY)
+    r, _ = oracle.unet_backward(ref, p64, dY)
+    for st in r:
+        for (a, b), (c, e) in zip(g[st], r[st]):
+            np.testing.assert_allclose(a, c, rtol=1e-10, atol=1e-12)
+            np.testing.assert_allclose(b, e, rtol=1e-10, atol=1e-12)
+    g32 = oracle.unet_backward_bf16(oracle.unet_forward_bf16(t, cfg.grids[0], 2, params, accum="f32"), dY,
+                                    accum="f32")
+    for st in r:
+        for (a, b), (c, e) in zip(g32[st], r[st]):
+            np.testing.assert_allclose(a, c, rtol=1e-3, atol=1e-5 * np.abs(c).max())
+
+
+def test_unet_bf16_rounds_every_hidden_value():
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    params = synth.unet_params(6, 2, E=16, Dc=24)
+    emu = oracle.unet_forward_bf16(t, cfg.grids[0], 2, params)
+    ref = oracle.unet_forward(t, cfg.grids[0], 2, params)
+    for k in ("skip", "coarse", "up"):
+        a = emu["acts"][k]
+        assert np.array_equal(oracle.bf16_round(a), a)
+        assert not np.array_equal(a, ref["acts"][k])
+        # one rounding per layer: close to the FP64 network, not equal
+        assert np.abs(a - ref["acts"][k]).max() < 0.05 * np.abs(ref["acts"][k]).max()
+    for st, v in emu["Wr"].items():
+        for W, _ in v:
+            assert np.array_equal(oracle.bf16_round(W), W)
+    # logits are not rounded
+    assert not np.array_equal(oracle.bf16_round(emu["acts"]["Y"]), emu["acts"]["Y"])
