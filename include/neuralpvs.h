@@ -126,6 +126,23 @@ npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const 
                                 size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * npvs_build_rulebook without caller workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments and results as npvs_build_rulebook except ws / ws_bytes.  Its workspace is a static
+ * device array of NPVS_RULEBOOK_SCRATCH_BYTES (1 MiB) inside the library, one per GPU, held until
+ * the process ends; the call allocates nothing (no hipMalloc, no library allocation).  A batch
+ * whose workspace (npvs_rulebook_workspace_size) exceeds it is refused with NPVS_ERR_CAPACITY
+ * before anything is enqueued (1 MiB covers 32 grids of 256x256x128 froxels at d = 4; a
+ * 1024x1024x512 grid needs about 1.7 MiB and is refused).  Calls that overlap on one GPU share that array and race: order
+ * them on one stream.  Outputs are the caller's, as for npvs_build_rulebook.
+ * ------------------------------------------------------------------------------------------- */
+#define NPVS_RULEBOOK_SCRATCH_BYTES (1u << 20)
+npvs_status npvs_build_rulebook_noalloc(const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                        int32_t cap_sites, npvs_counts *counts, int32_t *site_keys,
+                                        int32_t *block_row, int32_t *grid_rows, int32_t *nbr, int32_t *rb_off,
+                                        int32_t *rb_pairs, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Interleave g_d and its inverse (Sec. 3.3): pure index permutations of a dense grid,
  *   out[bz][by][bx][c] = in[bz d + oz][by d + oy][bx d + ox],  c = (oz d + oy) d + ox,
  * for any element size (1, 2, 4 or 8 bytes).  in/out (device), not aliased.

@@ -103,15 +103,33 @@ class Rulebook:
         return dict(n_sites=c[0], n_sites_needed=c[1], n_pairs=c[2])
 
 
-def build_rulebook(occ: torch.Tensor, dims, d: int, cap: int | None = None, csr: bool = False) -> Rulebook:
+def build_rulebook(occ: torch.Tensor, dims, d: int, cap: int | None = None, csr: bool = False,
+                   out: Rulebook | None = None, noalloc: bool = False) -> Rulebook:
+    """Active sites, site table, neighbour map and (csr) the per-offset pair lists.  `out`: a
+    Rulebook of the same dims, d, cap and form to write into.  noalloc: the library's
+    workspace-free entry point (npvs_build_rulebook_noalloc), which allocates no device memory."""
     dims = [tuple(g) for g in dims]
     total_blocks, _ = batch_sizes(dims, d)
     cap = total_blocks if cap is None else int(cap)
     darr = L.dims_array(dims)
+    dev = _dev()
+    if out is not None and (out.dims != dims or out.d != d or out.cap != cap or (out.rb_off is not None) != csr):
+        raise ValueError("out: a Rulebook of other dims, d, capacity or form")
+    rb = out if out is not None else _new_rulebook(dims, d, cap, total_blocks, csr, dev)
+    if noalloc:
+        L.call("npvs_build_rulebook_noalloc", _p(occ), len(dims), darr, d, cap, _p(rb.counts), _p(rb.site_keys),
+               _p(rb.block_row), _p(rb.grid_rows), _p(rb.nbr), _p(rb.rb_off), _p(rb.rb_pairs), _stream())
+        return rb
     nbytes = ctypes.c_size_t()
     L.call("npvs_rulebook_workspace_size", len(dims), darr, d, cap, ctypes.byref(nbytes))
-    dev = _dev()
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    L.call("npvs_build_rulebook", _p(occ), len(dims), darr, d, cap, _p(rb.counts), _p(rb.site_keys),
+           _p(rb.block_row), _p(rb.grid_rows), _p(rb.nbr), _p(rb.rb_off), _p(rb.rb_pairs), _p(ws), nbytes.value,
+           _stream())
+    return rb
+
+
+def _new_rulebook(dims, d, cap, total_blocks, csr, dev) -> Rulebook:
     rb = Rulebook(dims, d, cap,
                   torch.empty(4, dtype=torch.int32, device=dev),
                   torch.empty(cap, dtype=torch.int32, device=dev),
@@ -121,9 +139,6 @@ def build_rulebook(occ: torch.Tensor, dims, d: int, cap: int | None = None, csr:
     if csr:
         rb.rb_off = torch.empty(28, dtype=torch.int32, device=dev)
         rb.rb_pairs = torch.empty((27 * cap, 2), dtype=torch.int32, device=dev)
-    L.call("npvs_build_rulebook", _p(occ), len(dims), darr, d, cap, _p(rb.counts), _p(rb.site_keys),
-           _p(rb.block_row), _p(rb.grid_rows), _p(rb.nbr), _p(rb.rb_off), _p(rb.rb_pairs), _p(ws), nbytes.value,
-           _stream())
     return rb
 
 

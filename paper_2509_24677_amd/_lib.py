@@ -74,6 +74,7 @@ SIGNATURES = {
     "npvs_froxelize": (i32, [P, P, i32, P, P, P, P, sz, P]),
     "npvs_rulebook_workspace_size": (i32, [i32, P, i32, i32, PS]),
     "npvs_build_rulebook": (i32, [P, i32, P, i32, i32, P, P, P, P, P, P, P, P, sz, P]),
+    "npvs_build_rulebook_noalloc": (i32, [P, i32, P, i32, i32, P, P, P, P, P, P, P, P]),
     "npvs_interleave": (i32, [P, Dims, i32, i32, P, P]),
     "npvs_deinterleave": (i32, [P, Dims, i32, i32, P, P]),
     "npvs_gather_input": (i32, [P, i32, P, i32, P, P, i32, i32, P, P]),

@@ -8,6 +8,9 @@
 // Rows are numbered by ascending global key through a two-pass compaction (per-workgroup
 // counts, then every workgroup adds the counts of the workgroups before it and scans its own
 // flags), so the numbering is canonical and identical run to run.
+#include <mutex>
+#include <string>
+
 #include "npvs_common.hpp"
 
 namespace npvs {
@@ -277,23 +280,28 @@ extern "C" npvs_status npvs_rulebook_workspace_size(int32_t n_grids, const npvs_
   return NPVS_OK;
 }
 
-extern "C" npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
-                                           int32_t cap_sites, npvs_counts *counts, int32_t *site_keys,
-                                           int32_t *block_row, int32_t *grid_rows, int32_t *nbr, int32_t *rb_off,
-                                           int32_t *rb_pairs, void *ws, size_t ws_bytes, void *stream) {
+// The rulebook build proper; `ws` is caller memory (npvs_build_rulebook) or this file's scratch
+// array (npvs_build_rulebook_noalloc).  Every workspace word is written before it is read.
+static npvs_status build_rulebook_impl(const char *fn, const uint8_t *occ_bits, int32_t n_grids,
+                                       const npvs_dims *dims, int32_t d, int32_t cap_sites, npvs_counts *counts,
+                                       int32_t *site_keys, int32_t *block_row, int32_t *grid_rows, int32_t *nbr,
+                                       int32_t *rb_off, int32_t *rb_pairs, void *ws, size_t ws_bytes,
+                                       void *stream) {
   if (!occ_bits || !counts || !site_keys || !block_row || !grid_rows || !nbr || !ws)
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: null pointer");
+    return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": null pointer");
   if ((rb_off == nullptr) != (rb_pairs == nullptr))
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: give both rb_off and rb_pairs or neither");
+    return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": give both rb_off and rb_pairs or neither");
   Batch B;
   npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
   if (st != NPVS_OK) return st;
-  if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: cap_sites < 1");
-  if ((int64_t)cap_sites * 27 > INT32_MAX) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: cap_sites too large");
+  if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": cap_sites < 1");
+  if ((int64_t)cap_sites * 27 > INT32_MAX) return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": cap_sites too large");
   size_t o_wg, o_cc, o_co, need;
   int n_wg, n_chunks;
   rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &o_co, &need, &n_wg, &n_chunks);
-  if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook: workspace too small");
+  if (ws_bytes < need)
+    return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": workspace too small (" + std::to_string(need) +
+                                          " bytes needed, " + std::to_string(ws_bytes) + " given)");
   char *w = static_cast<char *>(ws);
   int32_t *wg_counts = reinterpret_cast<int32_t *>(w + o_wg);
   int32_t *chunk_counts = reinterpret_cast<int32_t *>(w + o_cc);
@@ -311,5 +319,70 @@ extern "C" npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_gr
     rulebook_scan_kernel<<<1, 256, 0, s>>>(counts, counts, chunk_counts, chunk_off, n_chunks, rb_off);
     rulebook_pairs_kernel<<<g, 256, 0, s>>>(counts, cap_sites, nbr, chunk_off, n_chunks, rb_pairs);
   }
-  return check_hip(hipGetLastError(), "npvs_build_rulebook");
+  return check_hip(hipGetLastError(), fn);
+}
+
+extern "C" npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                           int32_t cap_sites, npvs_counts *counts, int32_t *site_keys,
+                                           int32_t *block_row, int32_t *grid_rows, int32_t *nbr, int32_t *rb_off,
+                                           int32_t *rb_pairs, void *ws, size_t ws_bytes, void *stream) {
+  return build_rulebook_impl("npvs_build_rulebook", occ_bits, n_grids, dims, d, cap_sites, counts, site_keys,
+                             block_row, grid_rows, nbr, rb_off, rb_pairs, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------------------------
+// The same build without caller workspace: the workspace is this file-scope device array, one
+// copy per GPU, held until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address is taken once per device with hipGetSymbolAddress and
+// only that address is ever handed to a kernel.  Calls that overlap on one GPU share the array
+// and race; nothing in it needs to start at zero.
+static __device__ __align__(256) unsigned char scratch[NPVS_RULEBOOK_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices] = {};
+
+npvs_status scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "npvs_build_rulebook_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(NPVS_ERR_UNSUPPORTED, "npvs_build_rulebook_noalloc: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "npvs_build_rulebook_noalloc: hipGetSymbolAddress");
+    if (!p) return fail(NPVS_ERR_HIP, "npvs_build_rulebook_noalloc: hipGetSymbolAddress gave a null address");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return NPVS_OK;
+}
+}  // namespace
+
+extern "C" npvs_status npvs_build_rulebook_noalloc(const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims,
+                                                   int32_t d, int32_t cap_sites, npvs_counts *counts,
+                                                   int32_t *site_keys, int32_t *block_row, int32_t *grid_rows,
+                                                   int32_t *nbr, int32_t *rb_off, int32_t *rb_pairs, void *stream) {
+  // sizes first: an oversized request is refused before anything touches the device
+  Batch B;
+  npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
+  if (st != NPVS_OK) return st;
+  if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook_noalloc: cap_sites < 1");
+  size_t o_wg, o_cc, o_co, need;
+  int n_wg, n_chunks;
+  rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &o_co, &need, &n_wg, &n_chunks);
+  if (need > NPVS_RULEBOOK_SCRATCH_BYTES)
+    return fail(NPVS_ERR_CAPACITY, "npvs_build_rulebook_noalloc: this batch needs " + std::to_string(need) +
+                                       " bytes of workspace, beyond the " +
+                                       std::to_string((size_t)NPVS_RULEBOOK_SCRATCH_BYTES) +
+                                       "-byte scratch; use npvs_build_rulebook with a workspace");
+  void *ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != NPVS_OK) return st;
+  return build_rulebook_impl("npvs_build_rulebook_noalloc", occ_bits, n_grids, dims, d, cap_sites, counts,
+                             site_keys, block_row, grid_rows, nbr, rb_off, rb_pairs, ws,
+                             NPVS_RULEBOOK_SCRATCH_BYTES, stream);
 }

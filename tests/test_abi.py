@@ -171,3 +171,20 @@ def test_viewcell_frustum_matches_oracle_and_rejects_bad_cameras(lib):
     st = lib.npvs_viewcell_frustum(p([0, 0, 0]), p([0, 0, 1]), p([0, 1, 0]), math.pi / 3, 1.0, 0.6, 0.2, 100.0, 50.0,
                                    ctypes.byref(out))
     assert st == L.NPVS_ERR_INVALID_ARG
+
+
+def test_noalloc_rulebook_refuses_a_batch_beyond_its_scratch(lib):
+    # a 1024x1024x512 grid at d = 4 needs 1.7 MiB of rulebook workspace, beyond the 1 MiB static
+    # scratch: refused with NPVS_ERR_CAPACITY before any device call (none is made on this host)
+    dims = L.dims_array([(1024, 1024, 512)])
+    cap = 256 * 256 * 128
+    need = ctypes.c_size_t()
+    L.call("npvs_rulebook_workspace_size", 1, dims, 4, cap, ctypes.byref(need))
+    assert need.value > (1 << 20)
+    assert "#define NPVS_RULEBOOK_SCRATCH_BYTES (1u << 20)" in open(L.HEADER).read()
+    st = lib.npvs_build_rulebook_noalloc(None, 1, dims, 4, cap, None, None, None, None, None, None, None, None)
+    assert st == L.NPVS_ERR_CAPACITY and b"scratch" in lib.npvs_last_error()
+    # 32 city-size grids fit
+    L.call("npvs_rulebook_workspace_size", 32, L.dims_array([(256, 256, 128)] * 32), 4, 32 * 64 * 64 * 32,
+           ctypes.byref(need))
+    assert need.value <= (1 << 20)
