@@ -53,7 +53,7 @@ def conv_traffic(variant):
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    for src in ("conv.hip", "npvs_common.hpp"):
+    for src in ("conv.hip", "conv_common.hpp", "npvs_common.hpp"):
         h = hashlib.sha256(open(os.path.join(ROOT, "paper_2509_24677_amd", "csrc", src), "rb").read()).hexdigest()
         if f"{src} {h}" not in text:
             return None
@@ -63,6 +63,8 @@ def conv_traffic(variant):
         name = f"conv_fwd_bf16_kernel<2, 4, {shapes[variant][0]}, {shapes[variant][1]}>"
     elif variant in lds:
         name = f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>"
+    elif variant == 14:
+        name = "conv_fwd_bf16_wsta_kernel<2, 1, false, 4>"
     else:
         name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}, false, 2>"
     for line in text.splitlines():
@@ -910,7 +912,7 @@ def main():
     achieved = flops / (conv_ms * 1e-3) / 1e12
     shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
               6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>",
-              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>", 12: "_wsta<2,1>", 13: "_wsta<2,2>"}
+              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>", 12: "_wsta<2,1>", 13: "_wsta<2,2>", 14: "_wsta<2,1,4>"}
     alg_bytes = n_sites * 64 * 2 * 2 + 27 * n_sites * 4 + 27 * 64 * 64 * 2  # X in, Y out, neighbour map, weights
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / BF16_PEAK_TFLOPS, "traffic": conv_traffic(net_b.variant[1]),

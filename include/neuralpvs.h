@@ -233,12 +233,14 @@ npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, con
  * offsets and share each offset's weights through LDS, (rows per wave, waves) = 6 (16, 4),
  * 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8); variants 12 and 13 (inputs of at
  * most 64 channels) keep each wave's weights in registers while a workgroup walks several row
- * tiles of 16 or 32 rows.  Channel counts no tuned shape covers use a general kernel (variants
+ * tiles of 16 or 32 rows (32 outputs per workgroup); variant 14 is variant 12 with every output
+ * block (at most 64 outputs) in one workgroup, so a gathered row serves all outputs (more than 64
+ * outputs: variant 12).  Channel counts no tuned shape covers use a general kernel (variants
  * 5 and 13 select its 32-row tiles), except 65 to 96 inputs, which take the weight-stationary
  * kernel with 16-row tiles unless variant 5 is asked for.  All variants give results within float32 rounding of each
  * other; each one is deterministic.  Ignored by the FP32 path. */
-#define NPVS_CONV_VARIANTS 14
-#define NPVS_DEFAULT_CONV_VARIANT 12 /* the tile shape npvs_sparse_conv_fwd and the data gradient use */
+#define NPVS_CONV_VARIANTS 15
+#define NPVS_DEFAULT_CONV_VARIANT 14 /* the tile shape npvs_sparse_conv_fwd and the data gradient use */
 npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                     const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
                                     int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);
@@ -514,7 +516,8 @@ npvs_status npvs_plan_capture(npvs_plan *plan, const float *tris, uint8_t *occ_b
 npvs_status npvs_plan_replay(npvs_plan *plan, void *stream);
 /* Autotuner: runs the pass once on `tris`, then times every BF16 tile shape (`reps` launches
  * each, HIP events on `stream`) for each distinct layer shape on the real rulebook and keeps the
- * fastest for later passes and captures.  Synchronizes `stream`.  variants (host, nullable)
+ * fastest for later passes and captures (the default shape stays unless another is faster by
+ * more than 3 %).  Synchronizes `stream`.  variants (host, nullable)
  * receives the chosen variant of each layer. */
 npvs_status npvs_plan_autotune(npvs_plan *plan, const float *tris, int32_t reps, int32_t *variants, void *stream);
 /* Synchronizes `stream` and copies the plan's npvs_counts to host memory; returns

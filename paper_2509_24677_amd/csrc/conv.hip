@@ -3,25 +3,9 @@
 // Output-stationary gather-GEMM: a tile of output rows loops over the 27 offsets, gathers the
 // neighbour rows of each offset and multiplies them by W_k.  Each offset really is a dense
 // [rows x Cin] x [Cin x Cout] contraction, so the BF16 path runs it on MFMA.
-#include "npvs_common.hpp"
+#include "conv_common.hpp"
 
 namespace npvs {
-
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
-
-// ------------------------------------------------------------------------------------------
-// XCD-aware tile order: workgroup i runs on XCD (i % 8); the tiles of a layer are cut into 8
-// contiguous ranges, one per XCD, so neighbouring rows (which gather overlapping inputs) share
-// that XCD's L2.  Returns the j-th tile of workgroup i, or -1.
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_tile(int i, int G, int ntiles, int j) {
-  const int per = (ntiles + 7) >> 3;  // tiles per XCD
-  const int slot = (i >> 3) + j * (G >> 3);
-  if (slot >= per) return -1;
-  int t = (i & 7) * per + slot;
-  return t < ntiles ? t : -1;
-}
 
 // ------------------------------------------------------------------------------------------
 // Weight packing.  P is the conv weight a kernel reads, [27][CI][CO]:
@@ -187,50 +171,6 @@ __global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restri
 // unconditional (a missing row reads row 0, which exists whenever a tile does, and the value is
 // discarded), so the loads of a stage are the same on every path and the wait before the MFMAs
 // of a stage only covers that stage's loads, not the ones prefetched after it.
-__device__ __forceinline__ bf16x8_t gather8(const uint16_t *__restrict__ X, int cin, int i, int c) {
-  const bool ok = i >= 0 && c < cin;
-  const uint4 v = *reinterpret_cast<const uint4 *>(X + (ok ? (int64_t)i * cin + c : 0));
-  const uint32_t m = ok ? ~0u : 0u;  // a mask, not a select of the loaded value: no branch around the load
-  return __builtin_bit_cast(bf16x8_t, make_uint4(v.x & m, v.y & m, v.z & m, v.w & m));
-}
-
-// Zero as a value the compiler cannot see through, taken once per tile and added to the weight
-// index: the weight loads then stay inside the tile loop instead of being hoisted out of it into
-// registers for all tiles (which would cost the occupancy the gather latency needs), and the
-// pointer keeps its global address space.  The empty asm emits no instruction.
-__device__ __forceinline__ int opaque_zero() {
-  int z = 0;
-  asm volatile("" : "+s"(z));
-  return z;
-}
-
-// Neighbour index of row r for offset k, or -1 past the last site (unconditional load of a row
-// that exists: r is clamped to n - 1).
-__device__ __forceinline__ int nbr_index(const int32_t *__restrict__ nbr, int cap, int k, int r, int n) {
-  const int v = nbr[(int64_t)k * cap + (r < n ? r : n - 1)];
-  return r < n ? v : -1;
-}
-
-template <int NB>
-__device__ __forceinline__ void conv_bf16_epilogue(const f32x4_t &acc, int r, int n, int o, int cout,
-                                                   const float *__restrict__ bias, int relu, int out_f32, void *Y) {
-  if (r >= n || o >= cout) return;
-  float v[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float t = acc[i] + (bias ? bias[o + i] : 0.0f);
-    v[i] = (relu && t < 0.0f) ? 0.0f : t;
-  }
-  if (out_f32) {
-    *reinterpret_cast<float4 *>(static_cast<float *>(Y) + (int64_t)r * cout + o) = make_float4(v[0], v[1], v[2], v[3]);
-  } else {
-    uint2 p;
-    p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-    p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-    *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = p;
-  }
-}
-
 template <int KB, int NB, int MB, int KSPLIT>
 __global__ __launch_bounds__(64 * KSPLIT) void conv_fwd_bf16_kernel(const uint16_t *__restrict__ X, int cin,
                                                                      const bf16x8_t *__restrict__ Wp,
@@ -462,7 +402,7 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
                                                                   const uint16_t *__restrict__ M = nullptr,
                                                                   float *__restrict__ dbp = nullptr) {
   constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBLK = MB * NBW;
-  constexpr bool PF = NBW == 2;  // rows of the next tile prefetched
+  constexpr bool PF = NBW == 2;  // rows of the next tile prefetched (the registers of 4 blocks' weights leave no room)
   static_assert(!FUSE || MB == 1, "the fused data gradient keeps one column block per epilogue wave");
   __shared__ f32x4_t red[KSPLIT * NBLK * 64];
   const int32_t n = counts->n_sites;
@@ -724,7 +664,7 @@ static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float
   // one input chunk, one with two or more chunks or 32-row tiles), spread over the output groups;
   // each walks several row tiles
   const int groups = (cout + 16 * NBW - 1) / (16 * NBW);
-  int G = (KB == 1 && MB == 1 ? 512 : 256) / groups;
+  int G = (KB == 1 && MB == 1 && NBW <= 2 ? 512 : 256) / groups;
   G = G < 8 ? 8 : G & ~7;  // a multiple of 8 (one per XCD), rounded down so that all fit at once
   const int most = stride_grid(cap, 16 * MB, 4096);
   if (G > most) G = (most + 7) & ~7;
@@ -740,18 +680,26 @@ npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int co
                              const npvs_counts *counts, int cap, const uint16_t *M, uint16_t *dZ_below, float *dbp,
                              hipStream_t s) {
   if (cin > 64 || cout % 4) return fail(NPVS_ERR_UNSUPPORTED, "dgrad with fused ReLU': unsupported channel counts");
-  const int groups = (cout + 31) / 32;
-  int G = (cin <= 32 ? 512 : 256) / groups;
+  const bool all = cout <= 64;  // every output block in one workgroup, as the default forward variant
+  const int groups = all ? 1 : (cout + 31) / 32;
+  int G = (cin <= 32 && !all ? 512 : 256) / groups;
   G = G < 8 ? 8 : G;
   const int most = stride_grid(cap, 16, 4096);
   G = G > most ? most : G;
   G = (G + 7) & ~7;
-  if (cin <= 32)
-    conv_fwd_bf16_wsta_kernel<1, 1, true><<<dim3(G, groups), 576, 0, s>>>(
-        dZ, cin, (const bf16x8_t *)Wt, nullptr, cout, nbr, counts, cap, 0, 0, dZ_below, M, dbp);
+  const bf16x8_t *W = (const bf16x8_t *)Wt;
+  if (cin <= 32 && all)
+    conv_fwd_bf16_wsta_kernel<1, 1, true, 4><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts,
+                                                                             cap, 0, 0, dZ_below, M, dbp);
+  else if (all)
+    conv_fwd_bf16_wsta_kernel<2, 1, true, 4><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts,
+                                                                             cap, 0, 0, dZ_below, M, dbp);
+  else if (cin <= 32)
+    conv_fwd_bf16_wsta_kernel<1, 1, true><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts, cap,
+                                                                          0, 0, dZ_below, M, dbp);
   else
-    conv_fwd_bf16_wsta_kernel<2, 1, true><<<dim3(G, groups), 576, 0, s>>>(
-        dZ, cin, (const bf16x8_t *)Wt, nullptr, cout, nbr, counts, cap, 0, 0, dZ_below, M, dbp);
+    conv_fwd_bf16_wsta_kernel<2, 1, true><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts, cap,
+                                                                          0, 0, dZ_below, M, dbp);
   return check_hip(hipGetLastError(), "dgrad with fused ReLU'");
 }
 
@@ -881,6 +829,12 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
   if (cin % 8 || cout % 8)
     return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: BF16 needs cin % 8 == 0 and cout % 8 == 0");
   const int KB = (cin + 31) / 32, NB = (cout + 15) / 16;
+  if (variant == 14 && KB <= 2 && NB <= 4) {  // weight-stationary, all (at most 64) outputs per workgroup
+    if (KB == 1) launch_bf16_wsta<1, 1, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    else launch_bf16_wsta<2, 1, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
+    return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
+  }
+  if (variant == 14) variant = 12;  // more than 64 outputs: 32 per workgroup
   if ((variant == 12 || variant == 13) && KB <= 2) {  // weight-stationary tiles
     if (KB == 1) {
       if (variant == 12) launch_bf16_wsta<1, 1>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);

@@ -28,7 +28,7 @@ def _case(cin, cout, d, seed=3):
     return rb, ref, X, W, b
 
 
-@pytest.mark.parametrize("variant", [0, 5, 12, 13])
+@pytest.mark.parametrize("variant", [0, 5, 12, 13, 14])
 @pytest.mark.parametrize("cin,cout,d", [(128, 64, 4), (96, 24, 4), (160, 96, 4), (136, 40, 4), (64, 200, 4),
                                         (32, 64, 4), (512, 512, 8), (4096, 64, 16), (64, 4096, 16)])
 def test_conv_fwd_bf16_general_shapes(cin, cout, d, variant):
