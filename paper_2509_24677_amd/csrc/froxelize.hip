@@ -4,19 +4,21 @@
 // (round half to even) and overlap is decided by the separating-axis theorem in exact integer
 // arithmetic, so the result does not depend on triangle order or on the schedule.
 //
-// Five launches:
-//   1. zero the per-tile triangle counters and the part counter;
+// Three launches:
+//   1. zero: the per-tile triangle counters (and the ignored-triangle count) and, on the parts
+//      path, the output words;
 //   2. bin: one thread per triangle quantizes it, clips its froxel range, computes the constants
 //      of its separating-axis test once, and appends it to the list of every tile (32 x 8 x 8
-//      froxels) the range meets; lanes of a wave that append to the same tile share one counter
-//      update;
-//   3. plan: one workgroup scans the tiles' counts into a list of parts (256 listed triangles each);
-//   4. part: workgroups take parts from the list, one thread per triangle; each thread tests the
-//      froxels of its triangle's range inside the tile and ORs the hits into the tile's 64-word
-//      mask in LDS; the part's mask is stored once;
-//   5. merge: one thread per 32-froxel word ORs the parts of its tile and writes the word.
-// The output is written once per word, with no global atomics.  A tile whose list overflowed
-// (more than 2048 triangles) is covered by 16 parts that together scan all triangles of its grid.
+//      froxels) the range meets; a workgroup counts its appends per tile in LDS first, so each
+//      (workgroup, tile) pair makes one global counter update, and each chunk of 64 slots of a
+//      tile's list is entered in a chunk list by the workgroup whose appends start it;
+//   3. parts (every grid's x extent a multiple of 32): workgroups take chunks from the list, test
+//      their triangles row by row, OR the hits into 64 words in LDS and each non-zero word into
+//      the output with one atomic; otherwise one workgroup per tile tests all of the tile's
+//      triangles and writes each of its words once.
+// A tile whose list overflowed (more than 2048 triangles) scans all triangles of its grid.
+#include <algorithm>
+
 #include "npvs_common.hpp"
 
 namespace npvs {
@@ -39,19 +41,16 @@ struct TriSetup {
 };
 static_assert(sizeof(TriSetup) % 16 == 0, "setup record is loaded as 16-byte words");
 
-constexpr int kPartTris = 256;                          // triangles of a listed part
-constexpr int kListedParts = kFroxTileCap / kPartTris;  // parts of a tile whose list did not overflow
-constexpr int kMaxParts = 16;                           // parts of a tile that scans its whole grid
-static_assert(kListedParts <= kMaxParts, "part indices");
 constexpr int kTileWords = (kFroxTileX / 32) * kFroxTileY * kFroxTileZ;  // 64
+constexpr int kPartTris = 64;  // triangles of a chunk of the parts path
 static_assert(kFroxTileX == 32 && kTileWords == 64, "one 32-froxel word per tile row");
 
-__global__ void frox_zero_kernel(int32_t *p, int n, int32_t *n_parts, int32_t *n_ignored) {
+// Zeroes the tile counters with the chunk count and, for the parts path, the output words.
+__global__ void frox_zero_kernel(int32_t *p, int n, int32_t *n_ignored, uint32_t *occ_words, int64_t n_words) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *n_parts = 0;
-    if (n_ignored) *n_ignored = 0;
-  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
+    occ_words[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n_ignored) *n_ignored = 0;
 }
 
 __device__ __forceinline__ int tri_grid(const Batch &B, int64_t t) {
@@ -147,9 +146,43 @@ __device__ __forceinline__ bool quantize_tri(const float *__restrict__ tris, int
   return empty;
 }
 
+// LDS table of the tiles one workgroup appends to (open addressing on the tile index).
+constexpr int kBinSlots = 512;
+constexpr int kBinKeep = 8;  // (triangle, tile) appends a thread remembers; more go straight to memory
+
+// Chunk list entries: tile * 64 + c, c < kListedChunks a chunk of 64 listed triangles, c >=
+// kListedChunks the (c - kListedChunks)-th of kListedChunks ranges of an overflowed tile's grid.
+constexpr int kListedChunks = kFroxTileCap / kPartTris;  // 32
+constexpr int kChunkCodes = 2 * kListedChunks;
+
+// The chunk entries that the appends of slots [base, base + k) of a tile start: a chunk c begins
+// at slot 64 c (listed slots only); the range holding slot kFroxTileCap (the first that does not
+// fit) starts the tile's overflow ranges.
+__device__ __forceinline__ int chunks_started(int base, int k) {
+  const int end = min(base + k, kFroxTileCap);
+  const int first = (base + kPartTris - 1) / kPartTris;
+  const int listed = end > base ? max(0, (end - 1) / kPartTris - first + 1) : 0;
+  const bool ovf = base <= kFroxTileCap && base + k > kFroxTileCap;
+  return listed + (ovf ? kListedChunks : 0);
+}
+__device__ __forceinline__ void write_chunks(int tile, int base, int k, int32_t *__restrict__ chunks, int pos) {
+  const int end = min(base + k, kFroxTileCap);
+  for (int c = (base + kPartTris - 1) / kPartTris; c * kPartTris < end; ++c) chunks[pos++] = tile * kChunkCodes + c;
+  if (base <= kFroxTileCap && base + k > kFroxTileCap)
+    for (int c = 0; c < kListedChunks; ++c) chunks[pos++] = tile * kChunkCodes + kListedChunks + c;
+}
+
 __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__ tris, Batch B, int64_t total,
                                                         TriSetup *__restrict__ recs, int32_t *__restrict__ tile_count,
-                                                        int32_t *__restrict__ tile_list, int32_t *__restrict__ n_ignored) {
+                                                        int32_t *__restrict__ tile_list, int32_t *__restrict__ n_ignored,
+                                                        int32_t *__restrict__ n_chunks, int32_t *__restrict__ chunks) {
+  __shared__ int htile[kBinSlots];
+  __shared__ int hcount[kBinSlots];
+  __shared__ int hbase[kBinSlots];
+  for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x) {
+    htile[i] = -1;
+    hcount[i] = 0;
+  }
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int ntl = 0, tx0 = 0, ty0 = 0, tz0 = 0, ntx = 1, nty = 1, toff = 0, tys = 1, txs = 1;
   bool bad = false;
@@ -179,39 +212,98 @@ __global__ __launch_bounds__(256) void frox_bin_kernel(const float *__restrict__
     }
   }
   // ignored triangles: one counter update per wave that has any
-  const int lane = threadIdx.x & 63;
   const uint64_t badm = __ballot(bad);
-  if (n_ignored && badm && lane == 0) atomicAdd(n_ignored, (int)__popcll(badm));
-  // Append to each covered tile.  Triangles of one object tend to be consecutive and to share
-  // tiles, so in each round a run of consecutive lanes that target the same tile shares one
-  // counter update (made by the run's first lane); lanes of unrelated triangles update their own
-  // counters in parallel.
-  for (int j = 0;; ++j) {
-    const bool active = j < ntl;
-    if (__ballot(active) == 0ull) break;
-    int tile = -1;
-    if (active) {
-      const int ix = j % ntx, iy = (j / ntx) % nty, iz = j / (ntx * nty);
-      tile = toff + ((tz0 + iz) * tys + (ty0 + iy)) * txs + (tx0 + ix);
+  if (n_ignored && badm && (threadIdx.x & 63) == 0) atomicAdd(n_ignored, (int)__popcll(badm));
+  __syncthreads();  // the table is initialized
+  // Appends are counted per workgroup first: each (triangle, tile) takes a local slot from the
+  // tile's entry in the LDS table, then one global counter update per (workgroup, tile) reserves
+  // the entry's range.  Consecutive triangles mostly share tiles, so a tile that hundreds of
+  // triangles meet sees a few global updates instead of hundreds.  An append that finds no free
+  // table entry, or a thread's appends past kBinKeep, take a global slot directly.
+  auto tile_of = [&](int j) {
+    const int ix = j % ntx, iy = (j / ntx) % nty, iz = j / (ntx * nty);
+    return toff + ((tz0 + iz) * tys + (ty0 + iy)) * txs + (tx0 + ix);
+  };
+  auto append = [&](int tile, int slot) {
+    if (slot < kFroxTileCap) tile_list[(int64_t)tile * kFroxTileCap + slot] = (int32_t)t;
+  };
+  // an append that reserved its slot alone lists the chunks it starts itself
+  auto direct = [&](int tile) {
+    const int slot = atomicAdd(&tile_count[tile], 1);
+    append(tile, slot);
+    if (chunks) {
+      const int k = chunks_started(slot, 1);
+      if (k) write_chunks(tile, slot, 1, chunks, atomicAdd(n_chunks, k));
     }
-    // runs: maximal groups of consecutive lanes with the same tile (inactive lanes have tile -1,
-    // so they form runs of their own and never make an update)
-    const int prev = __shfl_up(tile, 1, 64);
-    const uint64_t starts = __ballot(lane == 0 || prev != tile);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
-    const int first = 63 - __clzll((long long)(starts & upto));    // start of this lane's run
-    int base = 0;
-    if (active && first == lane) {
-      const uint64_t later = starts & ~upto;
-      const int next = later ? __ffsll((long long)later) - 1 : 64;  // the run is [lane, next)
-      base = atomicAdd(&tile_count[tile], next - lane);
-    }
-    base = __shfl(base, first, 64);
-    if (active) {
-      const int slot = base + (lane - first);
-      if (slot < kFroxTileCap) tile_list[(int64_t)tile * kFroxTileCap + slot] = (int32_t)t;
+  };
+  int kslot[kBinKeep], kent[kBinKeep];
+#pragma unroll
+  for (int j = 0; j < kBinKeep; ++j) {
+    kent[j] = -1;
+    kslot[j] = 0;
+    if (j < ntl) {
+      const int tile = tile_of(j);
+      int h = (int)(((uint32_t)tile * 2654435761u) >> 23) & (kBinSlots - 1);
+      for (int probe = 0; probe < kBinSlots; ++probe, h = (h + 1) & (kBinSlots - 1)) {
+        const int cur = atomicCAS(&htile[h], -1, tile);
+        if (cur == -1 || cur == tile) {
+          kent[j] = h;
+          kslot[j] = atomicAdd(&hcount[h], 1);
+          break;
+        }
+      }
+      if (kent[j] < 0) direct(tile);  // table full
     }
   }
+  for (int j = kBinKeep; j < ntl; ++j) direct(tile_of(j));  // large triangles: the rest directly
+  __syncthreads();
+  // one counter update per table entry, then the chunks the workgroup's ranges start: one update
+  // of the chunk count for the whole workgroup
+  __shared__ int wsum[4];
+  __shared__ int cbase;
+  int nch[kBinSlots / 256] = {};
+#pragma unroll
+  for (int u = 0; u < kBinSlots / 256; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    if (htile[i] >= 0) {
+      hbase[i] = atomicAdd(&tile_count[htile[i]], hcount[i]);
+      if (chunks) nch[u] = chunks_started(hbase[i], hcount[i]);
+    }
+  }
+  if (chunks) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < kBinSlots / 256; ++u) mine += nch[u];
+    int x = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int k = 0; k < 4; ++k) {
+      pre += k < w ? wsum[k] : 0;
+      tot += wsum[k];
+    }
+    if (threadIdx.x == 0) cbase = tot ? atomicAdd(n_chunks, tot) : 0;
+    __syncthreads();
+    int pos = cbase + pre + x - mine;
+#pragma unroll
+    for (int u = 0; u < kBinSlots / 256; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      if (nch[u]) {
+        write_chunks(htile[i], hbase[i], hcount[i], chunks, pos);
+        pos += nch[u];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kBinKeep; ++j)
+    if (kent[j] >= 0) append(htile[kent[j]], hbase[kent[j]] + kslot[j]);
 }
 
 // Froxels x in [xa, xb] of row (y, z) that the triangle meets, as bits x - X0 of a 32-bit word.
@@ -340,15 +432,6 @@ __device__ __forceinline__ const GridDesc &tile_grid(const Batch &B, int tile) {
   return B.g[b];
 }
 
-// Triangles per part and number of parts of a tile.
-__device__ __forceinline__ void tile_parts(const GridDesc &g, int cnt, int &items, int &per, int &nparts,
-                                           bool &listed) {
-  listed = cnt <= kFroxTileCap;
-  items = listed ? cnt : g.tri_n;
-  per = listed ? kPartTris : (g.tri_n + kMaxParts - 1) / kMaxParts;
-  nparts = listed ? (cnt + kPartTris - 1) / kPartTris : kMaxParts;
-}
-
 __device__ __forceinline__ void tile_origin(const GridDesc &g, int tile, int &X0, int &Y0, int &Z0) {
   const int lt = tile - g.tile_off;
   X0 = (lt % g.tiles_x) * kFroxTileX;
@@ -356,97 +439,69 @@ __device__ __forceinline__ void tile_origin(const GridDesc &g, int tile, int &X0
   Z0 = (lt / (g.tiles_x * g.tiles_y)) * kFroxTileZ;
 }
 
-// One workgroup of 1024 threads: the part list, in tile order, from the tiles' counts
-// (exclusive scan of the number of parts of every tile).
-__global__ __launch_bounds__(1024) void frox_plan_kernel(Batch B, const int32_t *__restrict__ tile_count,
-                                                         int32_t *__restrict__ part_list, int32_t *__restrict__ n_parts) {
-  __shared__ int wsum[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int running = 0;
-  for (int base = 0; base < B.total_tiles; base += 1024) {
-    const int tile = base + tid;
-    int np = 0;
-    if (tile < B.total_tiles) {
-      int items, per;
-      bool listed;
-      tile_parts(tile_grid(B, tile), tile_count[tile], items, per, np, listed);
-    }
-    int x = np;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    __syncthreads();
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    int pre = 0, tot = 0;
-    for (int i = 0; i < 16; ++i) {
-      pre += i < w ? wsum[i] : 0;
-      tot += wsum[i];
-    }
-    const int p0 = running + pre + x - np;
-    for (int i = 0; i < np; ++i) part_list[p0 + i] = tile * kMaxParts + i;
-    running += tot;
-  }
-  if (tid == 0) *n_parts = running;
-}
-
-// Grid-stride over the part list; 256 threads.  The part's triangles are taken 256 at a time:
-// their setup records go to LDS, a scan of the number of tile rows (y, z) each one covers gives
-// a flat list of (triangle, row) items, and each thread tests the froxels of one row at a time,
-// so a triangle that covers the whole tile costs 64 short rows spread over the workgroup rather
-// than one long loop on one lane.
+// Grid-stride over the chunk list, 256 threads per chunk: 64 of a tile's listed triangles, or
+// (a tile whose list overflowed) one of kListedChunks ranges of its grid's triangles, 64 at a
+// time; the listed chunks of an overflowed tile have nothing left to do.  A chunk's setup records
+// go to LDS, a scan of the number of tile rows (y, z) each triangle covers gives a flat list of
+// (triangle, row) items, and each thread tests the froxels of one row at a time (a short binary
+// search over 64 row offsets finds an item's triangle).  Hits are OR-ed into the workgroup's
+// 64-word mask in LDS and each non-zero word into the output (zeroed beforehand) with one atomic,
+// so a tile that hundreds of triangles meet is spread over many workgroups.  Requires every
+// grid's x extent to be a multiple of 32 (whole aligned words).
 __global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriSetup *__restrict__ recs,
                                                          const int32_t *__restrict__ tile_count,
                                                          const int32_t *__restrict__ tile_list,
-                                                         const int32_t *__restrict__ part_list,
-                                                         const int32_t *__restrict__ n_parts,
-                                                         uint32_t *__restrict__ partial) {
-  __shared__ TriSetup srec[256];
-  __shared__ int row0[257];  // exclusive scan of the rows of the staged triangles
-  __shared__ int wsum[4];
+                                                         const int32_t *__restrict__ n_chunks,
+                                                         const int32_t *__restrict__ chunks,
+                                                         uint8_t *__restrict__ occ) {
+  __shared__ TriSetup srec[kPartTris];
+  __shared__ int row0[kPartTris + 1];  // exclusive scan of the rows of the staged triangles
   __shared__ uint32_t mask[kTileWords];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int np = *n_parts;
-  for (int pi = blockIdx.x; pi < np; pi += gridDim.x) {
-    const int code = part_list[pi];
-    const int tile = code / kMaxParts, part = code % kMaxParts;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nc = *n_chunks;
+  for (int ci = blockIdx.x; ci < nc; ci += gridDim.x) {
+    const int code = chunks[ci];
+    const int tile = code / kChunkCodes, c = code % kChunkCodes;
+    const int cnt = tile_count[tile];
     const GridDesc &g = tile_grid(B, tile);
-    int items, per, nparts;
-    bool listed;
-    tile_parts(g, tile_count[tile], items, per, nparts, listed);
+    const bool listed = cnt <= kFroxTileCap;
+    if (listed != (c < kListedChunks)) continue;  // uniform: an overflowed tile's listed chunk
+    int i0, i1;
+    if (listed) {
+      i0 = c * kPartTris;
+      i1 = min(cnt, i0 + kPartTris);
+    } else {
+      const int per = (g.tri_n + kListedChunks - 1) / kListedChunks;
+      i0 = (c - kListedChunks) * per;
+      i1 = min(g.tri_n, i0 + per);
+    }
     int X0, Y0, Z0;
     tile_origin(g, tile, X0, Y0, Z0);
     if (tid < kTileWords) mask[tid] = 0;
-    const int i1 = (part + 1) * per < items ? (part + 1) * per : items;
-    for (int c0 = part * per; c0 < i1; c0 += 256) {
-      const int i = c0 + tid;
-      int rows = 0;
-      if (i < i1) {
-        const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + i] : g.tri_off + i;
-        const TriSetup S = recs[t];
-        srec[tid] = S;
-        const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
-        const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
-        const int za = S.lo[2] > Z0 ? S.lo[2] : Z0, zb = S.hi[2] < Z0 + 7 ? S.hi[2] : Z0 + 7;
-        if (xa <= xb && ya <= yb && za <= zb) rows = (yb - ya + 1) * (zb - za + 1);
-      }
-      int x = rows;
+    for (int c0 = i0; c0 < i1; c0 += kPartTris) {
+      const int n = min(kPartTris, i1 - c0);
+      if (tid < 64) {  // wave 0 stages the triangles and scans their rows
+        int rows = 0;
+        if (lane < n) {
+          const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + c0 + lane] : g.tri_off + c0 + lane;
+          const TriSetup S = recs[t];
+          srec[lane] = S;
+          const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+          const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
+          const int za = S.lo[2] > Z0 ? S.lo[2] : Z0, zb = S.hi[2] < Z0 + 7 ? S.hi[2] : Z0 + 7;
+          if (xa <= xb && ya <= yb && za <= zb) rows = (yb - ya + 1) * (zb - za + 1);
+        }
+        int x = rows;
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
+        }
+        row0[lane] = x - rows;
+        if (lane == 63) row0[kPartTris] = x;
       }
-      if (lane == 63) wsum[w] = x;
-      __syncthreads();  // also orders the previous chunk's reads of srec / row0 before these writes
-      int pre = 0;
-      for (int k = 0; k < w; ++k) pre += wsum[k];
-      row0[tid] = pre + x - rows;
-      if (tid == 255) row0[256] = pre + x;
       __syncthreads();
-      const int R = row0[256];
-      const int n = i1 - c0 < 256 ? i1 - c0 : 256;
+      const int R = row0[kPartTris];
       for (int r = tid; r < R; r += 256) {
         int lo = 0, hi = n - 1;  // last staged triangle whose rows start at or before r
         while (lo < hi) {
@@ -463,52 +518,110 @@ __global__ __launch_bounds__(256) void frox_part_kernel(Batch B, const TriSetup 
         const uint32_t m = frox_row(S, xa, xb, y, z, X0);
         if (m) atomicOr(mask + (z - Z0) * 8 + (y - Y0), m);
       }
-      __syncthreads();  // srec and row0 are rewritten by the next chunk
+      __syncthreads();  // srec and row0 are rewritten by the next chunk; the mask is complete
     }
-    __syncthreads();
-    if (tid < kTileWords) partial[((int64_t)tile * kMaxParts + part) * kTileWords + tid] = mask[tid];
-    __syncthreads();  // the mask is cleared for the next part only after it has been stored
+    if (tid < kTileWords) {
+      const uint32_t word = mask[tid];
+      const int y = Y0 + (tid & 7), z = Z0 + (tid >> 3);
+      if (word && y < g.ny && z < g.nz)
+        atomicOr(reinterpret_cast<uint32_t *>(occ + g.occ_off + ((int64_t)z * g.ny + y) * (g.nx / 8) + X0 / 8), word);
+    }
+    __syncthreads();  // the mask is cleared for the next chunk only after it has been read
   }
 }
 
-// 256 threads = 4 tiles x 64 words: OR the parts of the word's tile, write the word once.
-__global__ __launch_bounds__(256) void frox_merge_kernel(Batch B, const int32_t *__restrict__ tile_count,
-                                                          const uint32_t *__restrict__ partial,
-                                                          uint8_t *__restrict__ occ) {
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), w = threadIdx.x & 63;
-  if (tile >= B.total_tiles) return;
+// One workgroup of 256 threads per tile: all of the tile's triangles, 256 at a time.  Their
+// setup records go to LDS, a scan of the number of tile rows (y, z) each one covers gives a flat
+// list of (triangle, row) items, and each thread tests the froxels of one row at a time, so a
+// triangle that covers the whole tile costs 64 short rows spread over the workgroup rather than
+// one long loop on one lane.  Hits are OR-ed into the tile's 64-word mask in LDS, and the tile's
+// words are stored once at the end.  A tile whose list overflowed scans every triangle of its grid.
+__global__ __launch_bounds__(256) void frox_tile_kernel(Batch B, const TriSetup *__restrict__ recs,
+                                                         const int32_t *__restrict__ tile_count,
+                                                         const int32_t *__restrict__ tile_list,
+                                                         uint8_t *__restrict__ occ) {
+  __shared__ TriSetup srec[256];
+  __shared__ int row0[257];  // exclusive scan of the rows of the staged triangles
+  __shared__ int wsum[4];
+  __shared__ uint32_t mask[kTileWords];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tile = blockIdx.x;
   const GridDesc &g = tile_grid(B, tile);
-  int items, per, nparts;
-  bool listed;
-  tile_parts(g, tile_count[tile], items, per, nparts, listed);
-  uint32_t word = 0;
-  for (int p = 0; p < nparts; ++p) word |= partial[((int64_t)tile * kMaxParts + p) * kTileWords + w];
+  const int cnt = tile_count[tile];
+  const bool listed = cnt <= kFroxTileCap;
+  const int items = listed ? cnt : g.tri_n;
   int X0, Y0, Z0;
   tile_origin(g, tile, X0, Y0, Z0);
-  const int x0 = X0, y = Y0 + (w & 7), z = Z0 + (w >> 3);
+  if (tid < kTileWords) mask[tid] = 0;
+  for (int c0 = 0; c0 < items; c0 += 256) {
+    const int i = c0 + tid;
+    int rows = 0;
+    if (i < items) {
+      const int64_t t = listed ? (int64_t)tile_list[(int64_t)tile * kFroxTileCap + i] : g.tri_off + i;
+      const TriSetup S = recs[t];
+      srec[tid] = S;
+      const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+      const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
+      const int za = S.lo[2] > Z0 ? S.lo[2] : Z0, zb = S.hi[2] < Z0 + 7 ? S.hi[2] : Z0 + 7;
+      if (xa <= xb && ya <= yb && za <= zb) rows = (yb - ya + 1) * (zb - za + 1);
+    }
+    int x = rows;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();  // also orders the previous chunk's reads of srec / row0 before these writes
+    int pre = 0;
+    for (int k = 0; k < w; ++k) pre += wsum[k];
+    row0[tid] = pre + x - rows;
+    if (tid == 255) row0[256] = pre + x;
+    __syncthreads();
+    const int R = row0[256];
+    const int n = items - c0 < 256 ? items - c0 : 256;
+    for (int r = tid; r < R; r += 256) {
+      int lo = 0, hi = n - 1;  // last staged triangle whose rows start at or before r
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row0[mid] <= r) lo = mid;
+        else hi = mid - 1;
+      }
+      const TriSetup &S = srec[lo];
+      const int xa = S.lo[0] > X0 ? S.lo[0] : X0, xb = S.hi[0] < X0 + 31 ? S.hi[0] : X0 + 31;
+      const int ya = S.lo[1] > Y0 ? S.lo[1] : Y0, yb = S.hi[1] < Y0 + 7 ? S.hi[1] : Y0 + 7;
+      const int za = S.lo[2] > Z0 ? S.lo[2] : Z0;
+      const int rr = r - row0[lo], ny = yb - ya + 1;
+      const int y = ya + rr % ny, z = za + rr / ny;
+      const uint32_t m = frox_row(S, xa, xb, y, z, X0);
+      if (m) atomicOr(mask + (z - Z0) * 8 + (y - Y0), m);
+    }
+    __syncthreads();  // srec and row0 are rewritten by the next chunk; the mask is complete
+  }
+  if (tid >= kTileWords) return;
+  const uint32_t word = mask[tid];
+  const int y = Y0 + (tid & 7), z = Z0 + (tid >> 3);
   if (y >= g.ny || z >= g.nz) return;
   const int64_t row_bytes = g.nx / 8;
-  uint8_t *dst = occ + g.occ_off + ((int64_t)z * g.ny + y) * row_bytes + x0 / 8;
-  if (x0 + 32 <= g.nx && (row_bytes & 3) == 0 && (g.occ_off & 3) == 0) {
+  uint8_t *dst = occ + g.occ_off + ((int64_t)z * g.ny + y) * row_bytes + X0 / 8;
+  if (X0 + 32 <= g.nx && (row_bytes & 3) == 0 && (g.occ_off & 3) == 0) {
     *reinterpret_cast<uint32_t *>(dst) = word;
   } else {
-    for (int k = 0; k < 4 && x0 + 8 * k < g.nx; ++k) dst[k] = (uint8_t)(word >> (8 * k));
+    for (int k = 0; k < 4 && X0 + 8 * k < g.nx; ++k) dst[k] = (uint8_t)(word >> (8 * k));
   }
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static void frox_ws_layout(const Batch &B, int64_t total_tris, size_t *off_count, size_t *off_list,
-                           size_t *off_recs, size_t *off_part, size_t *bytes) {
+                           size_t *off_recs, size_t *bytes) {
   size_t o = 0;
-  *off_count = o;  // tile counters, then the part count and the part list
-  o += align256(sizeof(int32_t) * ((size_t)B.total_tiles + 1 + (size_t)B.total_tiles * kMaxParts));
+  *off_count = o;  // tile counters, the chunk count, the chunk list
+  o += align256(sizeof(int32_t) * ((size_t)B.total_tiles + 1 + (size_t)B.total_tiles * kChunkCodes));
   *off_list = o;
   o += align256(sizeof(int32_t) * (size_t)B.total_tiles * kFroxTileCap);
   *off_recs = o;
   o += align256(sizeof(TriSetup) * (size_t)(total_tris > 0 ? total_tris : 1));
-  *off_part = o;
-  o += align256(sizeof(uint32_t) * (size_t)B.total_tiles * kMaxParts * kTileWords);
   *bytes = o;
 }
 
@@ -524,8 +637,8 @@ extern "C" npvs_status npvs_froxelize_workspace_size(int32_t n_grids, const npvs
   if (st != NPVS_OK) return st;
   int64_t total = 0;
   for (int b = 0; b < n_grids; ++b) total += n_tris[b];
-  size_t a, c, r, p;
-  frox_ws_layout(B, total, &a, &c, &r, &p, bytes);
+  size_t a, c, r;
+  frox_ws_layout(B, total, &a, &c, &r, bytes);
   return NPVS_OK;
 }
 
@@ -539,25 +652,35 @@ extern "C" npvs_status npvs_froxelize(const float *tris, const int64_t *n_tris, 
   for (int b = 0; b < n_grids; ++b) total += n_tris[b];
   if (total > 0 && !tris) return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize: null triangles");
   if (total > INT32_MAX) return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize: too many triangles");
-  size_t oc, ol, orr, op, need;
-  frox_ws_layout(B, total, &oc, &ol, &orr, &op, &need);
+  size_t oc, ol, orr, need;
+  frox_ws_layout(B, total, &oc, &ol, &orr, &need);
   if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_froxelize: workspace too small");
   char *w = static_cast<char *>(ws);
   int32_t *cnt = reinterpret_cast<int32_t *>(w + oc);
-  int32_t *n_parts = cnt + B.total_tiles;
-  int32_t *part_list = n_parts + 1;
   int32_t *lst = reinterpret_cast<int32_t *>(w + ol);
   TriSetup *recs = reinterpret_cast<TriSetup *>(w + orr);
-  uint32_t *part = reinterpret_cast<uint32_t *>(w + op);
   hipStream_t s = as_stream(stream);
-  frox_zero_kernel<<<stride_grid(B.total_tiles, 256, 1024), 256, 0, s>>>(cnt, B.total_tiles, n_parts, n_ignored);
-  if (total > 0) {
-    frox_bin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(tris, B, total, recs, cnt, lst, n_ignored);
-    frox_plan_kernel<<<1, 1024, 0, s>>>(B, cnt, part_list, n_parts);
-    frox_part_kernel<<<stride_grid((int64_t)B.total_tiles * kMaxParts, 1, 2048), 256, 0, s>>>(
-        B, recs, cnt, lst, part_list, n_parts, part);
+  // the parts path ORs whole aligned 32-froxel words into the output: every grid's x extent a
+  // multiple of 32 (then every grid's bytes start on a 4-byte boundary too) and an aligned output
+  bool parts = total > 0 && (reinterpret_cast<uintptr_t>(occ_bits) & 3) == 0;
+  int64_t total_bytes = 0;
+  for (int b = 0; b < n_grids; ++b) {
+    parts = parts && dims[b].nx % 32 == 0;
+    total_bytes += (int64_t)dims[b].nz * dims[b].ny * (dims[b].nx / 8);
   }
-  frox_merge_kernel<<<(B.total_tiles + 3) / 4, 256, 0, s>>>(B, cnt, part, occ_bits);
+  const int64_t n_words = parts ? total_bytes / 4 : 0;
+  int32_t *n_chunks = cnt + B.total_tiles, *chunks = n_chunks + 1;
+  frox_zero_kernel<<<stride_grid(std::max<int64_t>(B.total_tiles + 1, n_words), 256, 1024), 256, 0, s>>>(
+      cnt, B.total_tiles + 1, n_ignored, reinterpret_cast<uint32_t *>(occ_bits), n_words);
+  if (total > 0)
+    frox_bin_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(tris, B, total, recs, cnt, lst, n_ignored,
+                                                                     parts ? n_chunks : nullptr,
+                                                                     parts ? chunks : nullptr);
+  if (parts)
+    frox_part_kernel<<<stride_grid((int64_t)B.total_tiles * kChunkCodes, 1, 4096), 256, 0, s>>>(B, recs, cnt, lst,
+                                                                                              n_chunks, chunks, occ_bits);
+  else
+    frox_tile_kernel<<<B.total_tiles, 256, 0, s>>>(B, recs, cnt, lst, occ_bits);
   return check_hip(hipGetLastError(), "npvs_froxelize");
 }
 
