@@ -133,7 +133,7 @@ npvs_status npvs_build_rulebook(const uint8_t *occ_bits, int32_t n_grids, const 
  * the process ends; the call allocates nothing (no hipMalloc, no library allocation).  A batch
  * whose workspace (npvs_rulebook_workspace_size) exceeds it is refused with NPVS_ERR_CAPACITY
  * before anything is enqueued (1 MiB covers 32 grids of 256x256x128 froxels at d = 4; a
- * 1024x1024x512 grid needs about 1.7 MiB and is refused).  Calls that overlap on one GPU share that array and race: order
+ * 1024^3 grid at d = 4 needs about 1.7 MiB and is refused).  Calls that overlap on one GPU share that array and race: order
  * them on one stream.  Outputs are the caller's, as for npvs_build_rulebook.
  * ------------------------------------------------------------------------------------------- */
 #define NPVS_RULEBOOK_SCRATCH_BYTES (1u << 20)

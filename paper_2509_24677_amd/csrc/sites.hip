@@ -178,45 +178,31 @@ __global__ __launch_bounds__(256) void rulebook_nbr_kernel(Batch B, const int32_
   }
 }
 
-// One workgroup: exclusive scan of the per-(offset, chunk) counts in offset-major order.
-__global__ __launch_bounds__(256) void rulebook_scan_kernel(const npvs_counts *__restrict__ counts_in,
-                                                             npvs_counts *__restrict__ counts,
-                                                             const int32_t *__restrict__ chunk_counts,
-                                                             int32_t *__restrict__ chunk_off, int32_t n_chunks,
-                                                             int32_t *__restrict__ rb_off) {
-  const int32_t n = counts_in->n_sites;
-  const int used = (n + kRowsPerChunk - 1) / kRowsPerChunk;
-  const int total_items = 27 * used;
-  int running = 0;
-  for (int base = 0; base < total_items; base += 256) {
-    int i = base + threadIdx.x;
-    int k = used ? i / used : 0, ch = used ? i % used : 0;
-    int v = i < total_items ? chunk_counts[k * n_chunks + ch] : 0;
-    int tot;
-    int ex = block_exclusive_scan(v, &tot);
-    if (i < total_items) {
-      chunk_off[k * n_chunks + ch] = running + ex;
-      if (ch == 0) rb_off[k] = running + ex;
-    }
-    running += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (used == 0)
-      for (int k = 0; k < 27; ++k) rb_off[k] = 0;
-    rb_off[27] = running;
-    counts->n_pairs = running;
-  }
-}
-
-__global__ __launch_bounds__(256) void rulebook_pairs_kernel(const npvs_counts *__restrict__ counts, int32_t cap,
+// Pair lists (CSR by offset): the pairs of offset k and chunk ch start after every pair of the
+// (offset, chunk) items before it in offset-major order; each workgroup adds those items' counts
+// itself (27 x 10 at most for a city frame), so no separate scan launch is needed.  The workgroup
+// of each offset's first chunk writes rb_off[k], that of the last item rb_off[27] and the count.
+__global__ __launch_bounds__(256) void rulebook_pairs_kernel(npvs_counts *__restrict__ counts, int32_t cap,
                                                               const int32_t *__restrict__ nbr,
-                                                              const int32_t *__restrict__ chunk_off, int32_t n_chunks,
+                                                              const int32_t *__restrict__ chunk_counts,
+                                                              int32_t n_chunks, int32_t *__restrict__ rb_off,
                                                               int32_t *__restrict__ pairs) {
   const int k = blockIdx.y;
   const int32_t n = counts->n_sites;
-  const int used_chunks = (n + kRowsPerChunk - 1) / kRowsPerChunk;
-  for (int ch = blockIdx.x; ch < used_chunks; ch += gridDim.x) {
+  const int used = (n + kRowsPerChunk - 1) / kRowsPerChunk;
+  if (used == 0) {
+    if (blockIdx.x == 0 && k == 0 && threadIdx.x < 28) {
+      rb_off[threadIdx.x] = 0;
+      if (threadIdx.x == 0) counts->n_pairs = 0;
+    }
+    return;
+  }
+  for (int ch = blockIdx.x; ch < used; ch += gridDim.x) {
+    // pairs before this item: chunks of the offsets before k, then the chunks of k before ch
+    const int before = k * used + ch;
+    int part = 0;
+    for (int i = threadIdx.x; i < before; i += 256) part += chunk_counts[(i / used) * n_chunks + i % used];
+    const int base = block_sum(part);
     // 4 consecutive rows per thread keep the output ascending in row order
     int32_t r0 = ch * kRowsPerChunk + threadIdx.x * 4;
     int32_t v[4];
@@ -226,7 +212,14 @@ __global__ __launch_bounds__(256) void rulebook_pairs_kernel(const npvs_counts *
       c += v[i] >= 0;
     }
     int tot;
-    int pos = chunk_off[k * n_chunks + ch] + block_exclusive_scan(c, &tot);
+    int pos = base + block_exclusive_scan(c, &tot);
+    if (threadIdx.x == 0) {
+      if (ch == 0) rb_off[k] = base;
+      if (k == 26 && ch == used - 1) {
+        rb_off[27] = base + tot;
+        counts->n_pairs = base + tot;
+      }
+    }
     for (int i = 0; i < 4; ++i)
       if (v[i] >= 0) {
         pairs[2 * (int64_t)pos] = v[i];
@@ -247,8 +240,8 @@ static void sites_shape(const Batch &B, int *bpt, int *fast) {
   *bpt = all32 ? 32 / B.d : 4;
 }
 
-static void rb_ws_layout(const Batch &B, int32_t cap, size_t *o_wg, size_t *o_cc, size_t *o_co, size_t *bytes,
-                         int *n_wg, int *n_chunks) {
+static void rb_ws_layout(const Batch &B, int32_t cap, size_t *o_wg, size_t *o_cc, size_t *bytes, int *n_wg,
+                         int *n_chunks) {
   int bpt, fast;
   sites_shape(B, &bpt, &fast);
   *n_wg = (B.total_blocks + 256 * bpt - 1) / (256 * bpt);
@@ -257,8 +250,6 @@ static void rb_ws_layout(const Batch &B, int32_t cap, size_t *o_wg, size_t *o_cc
   *o_wg = o;
   o += align256(sizeof(int32_t) * (size_t)(*n_wg > 0 ? *n_wg : 1));
   *o_cc = o;
-  o += align256(sizeof(int32_t) * 27 * (size_t)(*n_chunks > 0 ? *n_chunks : 1));
-  *o_co = o;
   o += align256(sizeof(int32_t) * 27 * (size_t)(*n_chunks > 0 ? *n_chunks : 1));
   *bytes = o;
 }
@@ -274,9 +265,9 @@ extern "C" npvs_status npvs_rulebook_workspace_size(int32_t n_grids, const npvs_
   npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
   if (st != NPVS_OK) return st;
   if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_rulebook_workspace_size: cap_sites < 1");
-  size_t a, b, c;
+  size_t a, b;
   int nw, nc;
-  rb_ws_layout(B, cap_sites, &a, &b, &c, bytes, &nw, &nc);
+  rb_ws_layout(B, cap_sites, &a, &b, bytes, &nw, &nc);
   return NPVS_OK;
 }
 
@@ -296,16 +287,15 @@ static npvs_status build_rulebook_impl(const char *fn, const uint8_t *occ_bits, 
   if (st != NPVS_OK) return st;
   if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": cap_sites < 1");
   if ((int64_t)cap_sites * 27 > INT32_MAX) return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": cap_sites too large");
-  size_t o_wg, o_cc, o_co, need;
+  size_t o_wg, o_cc, need;
   int n_wg, n_chunks;
-  rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &o_co, &need, &n_wg, &n_chunks);
+  rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &need, &n_wg, &n_chunks);
   if (ws_bytes < need)
     return fail(NPVS_ERR_INVALID_ARG, std::string(fn) + ": workspace too small (" + std::to_string(need) +
                                           " bytes needed, " + std::to_string(ws_bytes) + " given)");
   char *w = static_cast<char *>(ws);
   int32_t *wg_counts = reinterpret_cast<int32_t *>(w + o_wg);
   int32_t *chunk_counts = reinterpret_cast<int32_t *>(w + o_cc);
-  int32_t *chunk_off = reinterpret_cast<int32_t *>(w + o_co);
   hipStream_t s = as_stream(stream);
   int bpt, fast;
   sites_shape(B, &bpt, &fast);
@@ -315,10 +305,7 @@ static npvs_status build_rulebook_impl(const char *fn, const uint8_t *occ_bits, 
   dim3 g(stride_grid(cap_sites, kRowsPerChunk, 512), 27);
   rulebook_nbr_kernel<<<g, 256, 0, s>>>(B, site_keys, block_row, counts, cap_sites, nbr,
                                         rb_off ? chunk_counts : nullptr, n_chunks);
-  if (rb_off) {
-    rulebook_scan_kernel<<<1, 256, 0, s>>>(counts, counts, chunk_counts, chunk_off, n_chunks, rb_off);
-    rulebook_pairs_kernel<<<g, 256, 0, s>>>(counts, cap_sites, nbr, chunk_off, n_chunks, rb_pairs);
-  }
+  if (rb_off) rulebook_pairs_kernel<<<g, 256, 0, s>>>(counts, cap_sites, nbr, chunk_counts, n_chunks, rb_off, rb_pairs);
   return check_hip(hipGetLastError(), fn);
 }
 
@@ -371,9 +358,9 @@ extern "C" npvs_status npvs_build_rulebook_noalloc(const uint8_t *occ_bits, int3
   npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
   if (st != NPVS_OK) return st;
   if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_build_rulebook_noalloc: cap_sites < 1");
-  size_t o_wg, o_cc, o_co, need;
+  size_t o_wg, o_cc, need;
   int n_wg, n_chunks;
-  rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &o_co, &need, &n_wg, &n_chunks);
+  rb_ws_layout(B, cap_sites, &o_wg, &o_cc, &need, &n_wg, &n_chunks);
   if (need > NPVS_RULEBOOK_SCRATCH_BYTES)
     return fail(NPVS_ERR_CAPACITY, "npvs_build_rulebook_noalloc: this batch needs " + std::to_string(need) +
                                        " bytes of workspace, beyond the " +

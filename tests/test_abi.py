@@ -174,10 +174,10 @@ def test_viewcell_frustum_matches_oracle_and_rejects_bad_cameras(lib):
 
 
 def test_noalloc_rulebook_refuses_a_batch_beyond_its_scratch(lib):
-    # a 1024x1024x512 grid at d = 4 needs 1.7 MiB of rulebook workspace, beyond the 1 MiB static
-    # scratch: refused with NPVS_ERR_CAPACITY before any device call (none is made on this host)
-    dims = L.dims_array([(1024, 1024, 512)])
-    cap = 256 * 256 * 128
+    # a 1024^3 grid at d = 4 needs 1.7 MiB of rulebook workspace, beyond the 1 MiB static scratch:
+    # refused with NPVS_ERR_CAPACITY before any device call (none is made on this host)
+    dims = L.dims_array([(1024, 1024, 1024)])
+    cap = 256 * 256 * 256
     need = ctypes.c_size_t()
     L.call("npvs_rulebook_workspace_size", 1, dims, 4, cap, ctypes.byref(need))
     assert need.value > (1 << 20)
