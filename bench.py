@@ -204,6 +204,101 @@ def bench_train4(args, dev):
     return r
 
 
+def bench_stage_table(args, dev):
+    """The city frame at every interleave factor d in {1, 2, 4, 8, 16} (d = 1: no interleave, the
+    ablation of Table 2), BF16, with the stages of the paper's speed figure: froxelize, active
+    sites + neighbour map (rulebook), interleave (sparse g_d), the six convolutions (CNN), and
+    de-interleave + threshold; each stage timed as 20 back-to-back calls in a captured graph, plus
+    the whole pass (library plan graph).  Channels: d^3 -> 64 x 5 -> d^3, He-normal weights."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+    import synth
+
+    def graph_ms(fn, reps=20, loops=10):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(loops):
+            g.replay()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / (reps * loops)
+        del g
+        return ms
+
+    out = {}
+    for name in ("city256_d1", "city256_d2", "city256", "city256_d8", "city256_d16"):
+        cfg = synth.config(name)
+        t = synth.scene_for(cfg)
+        layers = synth.net_layers(cfg)
+        tris = torch.from_numpy(t).to(dev)
+        dims, d = cfg.grids, cfg.d
+        occ = npvs.froxelize(tris, [len(t)], dims)
+        rb = npvs.build_rulebook(occ, dims, d)
+        c = rb.host_counts()
+        C = d ** 3
+        w0 = (C + 7) // 8 * 8  # BF16 rows of fewer than 8 channels are padded
+        X = npvs.gather_input(occ, rb, npvs.NPVS_BF16, width=w0)
+        chans = [w0] + [64] * 5 + [w0]
+        Wp = [npvs.pack_weights(torch.from_numpy(W).to(dev), npvs.NPVS_BF16) for W, _ in layers]
+        bias = [torch.zeros(co, dtype=torch.float32, device=dev) for co in chans[1:]]
+        for i, (_, b) in enumerate(layers):
+            bias[i][:b.shape[0]] = torch.from_numpy(b).to(dev)
+        acts = [X] + [torch.empty((rb.cap, co), dtype=torch.bfloat16 if i < 5 else torch.float32, device=dev)
+                      for i, co in enumerate(chans[1:])]
+
+        def cnn():
+            for i in range(6):
+                npvs.sparse_conv_fwd(acts[i], Wp[i], bias[i], chans[i], chans[i + 1], rb, npvs.NPVS_BF16, relu=i < 5,
+                                     out_f32=i == 5, out=acts[i + 1])
+
+        r = {"d": d, "channels": [C] + [64] * 5 + [C], "n_sites": c["n_sites"]}
+        r["froxelize_ms"] = graph_ms(lambda: npvs.froxelize(tris, [len(t)], dims, occ=occ))
+        rbo = npvs.build_rulebook(occ, dims, d)
+        r["rulebook_ms"] = graph_ms(lambda: npvs.build_rulebook(occ, dims, d, out=rbo))
+        r["interleave_ms"] = graph_ms(lambda: npvs.gather_input(occ, rb, npvs.NPVS_BF16, out=X, width=w0))
+        r["cnn_ms"] = graph_ms(cnn, reps=5 if d == 1 else 20)
+        r["deinterleave_ms"] = graph_ms(lambda: npvs.deinterleave_threshold(acts[6], rb, occ))
+        plan = npvs.Plan(dims, [len(t)], d, [C] + [64] * 5 + [C], npvs.NPVS_BF16)
+        for li, (W, b) in enumerate(layers):
+            plan.set_weights(li, torch.from_numpy(W).to(dev), torch.from_numpy(b).to(dev))
+        r["n_pairs"] = npvs.build_rulebook(occ, dims, d, csr=True).host_counts()["n_pairs"]
+        plan.forward(tris)
+        reps = 5 if d == 1 else 20
+        s = torch.cuda.Stream()  # a capture needs a stream of its own
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.capture(tris)
+            plan.replay()
+            s.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                plan.replay()
+            e1.record(s)
+            e1.synchronize()
+        r["forward_ms"] = e0.elapsed_time(e1) / reps
+        r["forward_frames_per_s"] = 1000.0 / r["forward_ms"]
+        out[f"d{d}"] = r
+        del plan, acts, X, rb, rbo
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_wide(args, dev, timed_launches):
     """The city frame at the paper's interleave factors d = 8 and 16: forward (froxelize -> PVS) as a
     library-captured graph in BF16 and FP32, the training step (forward, loss, backward, Adam) as
@@ -933,6 +1028,8 @@ def main():
     print("# batch of four 128^3 grids, training " + json.dumps(train4), file=sys.stderr, flush=True)
     wide = bench_wide(args, dev, timed_launches)
     print("# interleave factors 8 and 16 " + json.dumps(wide), file=sys.stderr, flush=True)
+    stage_table = bench_stage_table(args, dev)
+    print("# stages by interleave factor " + json.dumps(stage_table), file=sys.stderr, flush=True)
     cull = bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs_b)
     print("# culling " + json.dumps(cull), file=sys.stderr, flush=True)
     unet = bench_unet(args, dev, timed_launches)
@@ -977,6 +1074,7 @@ def main():
         "batch16": batch16,
         "train128x4": train4,
         "interleave_8_16": wide,
+        "stages_by_interleave_factor": stage_table,
         "culling": cull,
         "unet": unet,
         "world_space": world,

@@ -184,11 +184,13 @@ npvs_status npvs_froxelize_view(const float *tris, int64_t n_tris, const npvs_vi
 
 /* Sparse interleave of a packed bit grid onto the active sites:
  *   X[r][c] = bit of froxel (bx d + ox, by d + oy, bz d + oz) of site r, as 0/1 in `dtype`
- *   (NPVS_F32, NPVS_BF16 or NPVS_U8).  X (device) [cap_sites][d^3]; rows >= n_sites untouched.
+ *   (NPVS_F32, NPVS_BF16 or NPVS_U8).  X (device) [cap_sites][row_stride], row_stride = 0 meaning
+ *   d^3; elements d^3 .. row_stride - 1 of a row are written as 0 (the input channels a BF16
+ *   layer with fewer than 8 real ones reads, e.g. d = 1); rows >= n_sites untouched.
  * Used for the network input (bits = G) and for training labels. */
 npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
                               const int32_t *site_keys, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                              void *X, void *stream);
+                              int32_t row_stride, void *X, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Weight packing.  W (device) float32 [27][cin][cout] -> Wp (device) of
@@ -408,12 +410,14 @@ npvs_status npvs_concat_channels_bwd(const float *dY, int32_t ca, int32_t cb, co
  * De-interleave and threshold (Sec. 3.1 V = 1[f(G) >= tau] with tau = 0.5, read as logit >= 0;
  * Sec. 3.3 g_d^-1; Sec. 3.2 the visible set lies inside the occupied set, so V is masked by G):
  *   V(x) = [L(x) >= 0] and G(x),  L(x) = Y[row(block(x))][c(x)], -inf for inactive blocks.
- *   Y (device) float32 [cap][d^3]; pvs_bits (device) packed like occ_bits, fully overwritten;
- *   logits (device, nullable) float32 dense [sum nz*ny*nx], grid after grid, fully overwritten.
+ *   Y (device) float32 [cap][y_stride] (y_stride = 0 meaning d^3; a padded row, as the BF16 last
+ *   layer of d = 1 writes, has its d^3 logits first); pvs_bits (device) packed like occ_bits, fully
+ *   overwritten; logits (device, nullable) float32 dense [sum nz*ny*nx], grid after grid, fully
+ *   overwritten.
  * ------------------------------------------------------------------------------------------- */
-npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row, const uint8_t *occ_bits,
-                                        int32_t n_grids, const npvs_dims *dims, int32_t d, uint8_t *pvs_bits,
-                                        float *logits, void *stream);
+npvs_status npvs_deinterleave_threshold(const float *Y, int32_t y_stride, const int32_t *block_row,
+                                        const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
+                                        uint8_t *pvs_bits, float *logits, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Culling against the PVS (the pipeline discards primitives whose froxels are all invisible,

@@ -143,14 +143,19 @@ def _new_rulebook(dims, d, cap, total_blocks, csr, dev) -> Rulebook:
 
 
 # --------------------------------------------------------------------------------- interleave
-def gather_input(bits: torch.Tensor, rb: Rulebook, dtype: int = NPVS_F32, out: torch.Tensor | None = None):
-    """Sparse g_d: [cap][d^3] 0/1 values of `bits` on the active sites (rows >= n_sites are left
-    as allocated)."""
+def gather_input(bits: torch.Tensor, rb: Rulebook, dtype: int = NPVS_F32, out: torch.Tensor | None = None,
+                 width: int | None = None):
+    """Sparse g_d: [cap][width] 0/1 values of `bits` on the active sites, width d^3 by default;
+    channels d^3 .. width - 1 are zero (a BF16 input of fewer than 8 channels is given width 8).
+    Rows >= n_sites are left as allocated."""
     C = rb.d ** 3
+    width = C if width is None else int(width)
     if out is None:
-        out = torch.empty((rb.cap, C), dtype=_TORCH_DT[dtype], device=_dev())
+        out = torch.empty((rb.cap, width), dtype=_TORCH_DT[dtype], device=_dev())
+    elif out.shape[-1] != width:
+        raise ValueError("out must have `width` elements per row")
     L.call("npvs_gather_input", _p(bits), len(rb.dims), L.dims_array(rb.dims), rb.d, _p(rb.site_keys),
-           _p(rb.counts), rb.cap, dtype, _p(out), _stream())
+           _p(rb.counts), rb.cap, dtype, width, _p(out), _stream())
     return out
 
 
@@ -409,14 +414,17 @@ def concat_channels(A: torch.Tensor, B: torch.Tensor, rb: Rulebook) -> torch.Ten
 
 # --------------------------------------------------------------------------------- output
 def deinterleave_threshold(Y: torch.Tensor, rb: Rulebook, occ: torch.Tensor, want_logits: bool = False):
-    """(pvs bits uint8 like occ, dense float32 logits or None)."""
+    """(pvs bits uint8 like occ, dense float32 logits or None).  Y float32 [cap][w], w >= d^3: the
+    d^3 logits first (a padded last layer's extra channels are ignored)."""
+    if Y.dtype != torch.float32 or Y.dim() != 2 or Y.shape[1] < rb.d ** 3 or not Y.is_contiguous():
+        raise ValueError("Y must be contiguous float32 [cap][w] with w >= d^3")
     pvs = torch.empty_like(occ)
     logits = None
     if want_logits:
         n = sum(nx * ny * nz for nx, ny, nz in rb.dims)
         logits = torch.empty(n, dtype=torch.float32, device=occ.device)
-    L.call("npvs_deinterleave_threshold", _p(Y), _p(rb.block_row), _p(occ), len(rb.dims), L.dims_array(rb.dims),
-           rb.d, _p(pvs), _p(logits), _stream())
+    L.call("npvs_deinterleave_threshold", _p(Y), Y.shape[1], _p(rb.block_row), _p(occ), len(rb.dims),
+           L.dims_array(rb.dims), rb.d, _p(pvs), _p(logits), _stream())
     return pvs, logits
 
 

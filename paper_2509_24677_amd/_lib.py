@@ -77,7 +77,7 @@ SIGNATURES = {
     "npvs_build_rulebook_noalloc": (i32, [P, i32, P, i32, i32, P, P, P, P, P, P, P, P]),
     "npvs_interleave": (i32, [P, Dims, i32, i32, P, P]),
     "npvs_deinterleave": (i32, [P, Dims, i32, i32, P, P]),
-    "npvs_gather_input": (i32, [P, i32, P, i32, P, P, i32, i32, P, P]),
+    "npvs_gather_input": (i32, [P, i32, P, i32, P, P, i32, i32, i32, P, P]),
     "npvs_packed_weight_bytes": (sz, [i32, i32, i32]),
     "npvs_pack_weights": (i32, [P, i32, i32, i32, i32, P, P]),
     "npvs_pack_weights_batch": (i32, [i32, P, i32, P]),
@@ -106,7 +106,7 @@ SIGNATURES = {
     "npvs_froxelize_view": (i32, [P, i64, P, Dims, P, P, sz, P]),
     "npvs_visible_triangles": (i32, [P, PI64, i32, P, P, P, P]),
     "npvs_visible_objects": (i32, [P, P, i64, P, P]),
-    "npvs_deinterleave_threshold": (i32, [P, P, P, i32, P, i32, P, P, P]),
+    "npvs_deinterleave_threshold": (i32, [P, i32, P, P, i32, P, i32, P, P, P]),
     "npvs_loss_workspace_size": (i32, [i32, PS]),
     "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, P, P, P, sz, P]),
     "npvs_loss_ex": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, P]),

@@ -106,6 +106,10 @@ struct npvs_plan {
   std::vector<npvs_dims> dims;
   std::vector<int64_t> n_tris;
   std::vector<int32_t> ch;
+  // channels as the kernels see them: BF16 pads every count to a multiple of 8 (the packed
+  // weights are zero past the real channels, the padded input channels are written as 0, and the
+  // padded outputs are never read), so e.g. the 1-channel input and output of d = 1 run on MFMA
+  std::vector<int32_t> ce;
   int64_t total_bytes = 0, total_dense = 0;
   size_t frox_ws = 0, rb_ws = 0;
   std::vector<void *> allocs;
@@ -166,6 +170,9 @@ extern "C" npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, 
   p->dims.assign(dims, dims + n_grids);
   p->n_tris.assign(n_tris, n_tris + n_grids);
   p->ch.assign(channels, channels + n_layers + 1);
+  p->ce = p->ch;
+  if (dtype == NPVS_BF16)
+    for (auto &c : p->ce) c = (c + 7) & ~7;
   for (int b = 0; b < n_grids; ++b) {
     p->total_bytes += (int64_t)dims[b].nz * dims[b].ny * (dims[b].nx / 8);
     p->total_dense += (int64_t)dims[b].nz * dims[b].ny * dims[b].nx;
@@ -190,15 +197,17 @@ extern "C" npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, 
   TRY(plan_alloc(p, (void **)&p->d_block_row, sizeof(int32_t) * cap));
   TRY(plan_alloc(p, (void **)&p->d_grid_rows, sizeof(int32_t) * (n_grids + 1)));
   TRY(plan_alloc(p, (void **)&p->d_nbr, sizeof(int32_t) * 27 * cap));
-  TRY(plan_alloc(p, &p->d_X0, es * cap * C));
+  int maxce = 0;
+  for (int l = 1; l < n_layers; ++l) maxce = p->ce[l] > maxce ? p->ce[l] : maxce;
+  TRY(plan_alloc(p, &p->d_X0, es * cap * p->ce[0]));
   if (n_layers > 1) {
-    TRY(plan_alloc(p, &p->d_act[0], es * cap * maxc));
-    TRY(plan_alloc(p, &p->d_act[1], es * cap * maxc));
+    TRY(plan_alloc(p, &p->d_act[0], es * cap * maxce));
+    TRY(plan_alloc(p, &p->d_act[1], es * cap * maxce));
   }
-  TRY(plan_alloc(p, (void **)&p->d_logits, sizeof(float) * cap * C));
+  TRY(plan_alloc(p, (void **)&p->d_logits, sizeof(float) * cap * p->ce[n_layers]));
   TRY(plan_alloc(p, (void **)&p->d_pvs_scratch, (size_t)p->total_bytes));
   for (int l = 0; l < n_layers; ++l) {
-    const size_t b = conv_fwd_ws_bytes(channels[l], channels[l + 1], cap, dtype);
+    const size_t b = conv_fwd_ws_bytes(p->ce[l], p->ce[l + 1], cap, dtype);
     p->conv_ws = b > p->conv_ws ? b : p->conv_ws;
   }
   if (p->conv_ws) TRY(plan_alloc(p, &p->d_conv_ws, p->conv_ws));
@@ -207,8 +216,8 @@ extern "C" npvs_status npvs_plan_create(int32_t n_grids, const npvs_dims *dims, 
   p->d_bias.assign(n_layers, nullptr);
   for (int l = 0; l < n_layers; ++l) {
     TRY(plan_alloc(p, &p->d_Wp[l], npvs_packed_weight_bytes(channels[l], channels[l + 1], dtype)));
-    TRY(plan_alloc(p, (void **)&p->d_bias[l], sizeof(float) * channels[l + 1]));
-    TRY(check_hip(hipMemset(p->d_bias[l], 0, sizeof(float) * channels[l + 1]), "npvs_plan_create"));
+    TRY(plan_alloc(p, (void **)&p->d_bias[l], sizeof(float) * p->ce[l + 1]));
+    TRY(check_hip(hipMemset(p->d_bias[l], 0, sizeof(float) * p->ce[l + 1]), "npvs_plan_create"));
   }
 #undef TRY
   *out = p;
@@ -238,18 +247,20 @@ static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_ou
   st = npvs_build_rulebook(occ, p->n_grids, p->dims.data(), p->d, p->cap, p->d_counts, p->d_keys, p->d_block_row,
                            p->d_grid_rows, p->d_nbr, nullptr, nullptr, p->d_rb_ws, p->rb_ws, s);
   if (st != NPVS_OK) return st;
-  st = npvs_gather_input(occ, p->n_grids, p->dims.data(), p->d, p->d_keys, p->d_counts, p->cap, p->dtype, p->d_X0, s);
+  st = npvs_gather_input(occ, p->n_grids, p->dims.data(), p->d, p->d_keys, p->d_counts, p->cap, p->dtype, p->ce[0],
+                         p->d_X0, s);
   if (st != NPVS_OK) return st;
   const void *in = p->d_X0;
   for (int l = 0; l < p->n_layers; ++l) {
     const bool last = l == p->n_layers - 1;
     void *out = last ? (void *)p->d_logits : p->d_act[l & 1];
-    st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
+    st = conv_fwd_dispatch(in, p->ce[l], p->d_Wp[l], p->d_bias[l], p->ce[l + 1], p->d_nbr, p->d_counts, p->cap,
                            p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, p->variant[l], p->d_conv_ws, p->conv_ws);
     if (st != NPVS_OK) return st;
     in = out;
   }
-  return npvs_deinterleave_threshold(p->d_logits, p->d_block_row, occ, p->n_grids, p->dims.data(), p->d, pvs, logits,
+  return npvs_deinterleave_threshold(p->d_logits, p->ce[p->n_layers], p->d_block_row, occ, p->n_grids, p->dims.data(),
+                                     p->d, pvs, logits,
                                      s);
 }
 
@@ -325,7 +336,7 @@ extern "C" npvs_status npvs_plan_autotune(npvs_plan *plan, const float *tris, in
       const bool last = l == p->n_layers - 1;
       int same = -1;  // an earlier layer of the same shape
       for (int m = 0; m < l; ++m)
-        if (p->ch[m] == p->ch[l] && p->ch[m + 1] == p->ch[l + 1] && (m == p->n_layers - 1) == last) same = m;
+        if (p->ce[m] == p->ce[l] && p->ce[m + 1] == p->ce[l + 1] && (m == p->n_layers - 1) == last) same = m;
       if (same >= 0) {
         p->variant[l] = p->variant[same];
         continue;
@@ -337,12 +348,12 @@ extern "C" npvs_status npvs_plan_autotune(npvs_plan *plan, const float *tris, in
       for (int v = 0; v < NPVS_CONV_VARIANTS && st == NPVS_OK; ++v) {
         // every shape rewrites layer l's output from the same input (values equal up to the order
         // of the float32 sums), which the next layer then reads as its timing input
-        st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
+        st = conv_fwd_dispatch(in, p->ce[l], p->d_Wp[l], p->d_bias[l], p->ce[l + 1], p->d_nbr, p->d_counts, p->cap,
                                p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v, p->d_conv_ws, p->conv_ws);
         if (st != NPVS_OK) break;
         st = check_hip(hipEventRecord(e0, s), "npvs_plan_autotune");
         for (int r = 0; r < reps && st == NPVS_OK; ++r)
-          st = conv_fwd_dispatch(in, p->ch[l], p->d_Wp[l], p->d_bias[l], p->ch[l + 1], p->d_nbr, p->d_counts, p->cap,
+          st = conv_fwd_dispatch(in, p->ce[l], p->d_Wp[l], p->d_bias[l], p->ce[l + 1], p->d_nbr, p->d_counts, p->cap,
                                  p->dtype, last ? 0 : 1, last ? 1 : 0, out, s, v, p->d_conv_ws, p->conv_ws);
         if (st != NPVS_OK) break;
         st = check_hip(hipEventRecord(e1, s), "npvs_plan_autotune");

@@ -38,10 +38,13 @@ __device__ __forceinline__ uint16_t one_zero<uint16_t>(int bit) { return bit ? (
 template <>
 __device__ __forceinline__ uint8_t one_zero<uint8_t>(int bit) { return (uint8_t)bit; }
 
+// Row r of X is [stride] elements: the d^3 values, then zeros up to the stride (the padding a
+// BF16 layer of fewer than 8 input channels reads as channels of zero).
 template <typename T>
 __global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t *__restrict__ bits,
                                                            const int32_t *__restrict__ site_keys,
-                                                           const npvs_counts *__restrict__ counts, T *__restrict__ X) {
+                                                           const npvs_counts *__restrict__ counts, T *__restrict__ X,
+                                                           int stride) {
   const int d = B.d;
   const int32_t n = counts->n_sites;
   const int64_t runs = (int64_t)n * d * d;
@@ -53,12 +56,14 @@ __global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t
     int32_t l = key - g.key_off;
     int bx = l % g.Bx, by = (l / g.Bx) % g.By, bz = l / (g.Bx * g.By);
     const uint8_t *row = bits + g.occ_off + ((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * (g.nx >> 3);
-    T *dst = X + (int64_t)r * d * d * d + (oz * d + oy) * d;
+    T *dst = X + (int64_t)r * stride + (oz * d + oy) * d;
     const int x0 = bx * d;
     for (int ox = 0; ox < d; ++ox) {
       int x = x0 + ox;
       dst[ox] = one_zero<T>((row[x >> 3] >> (x & 7)) & 1);
     }
+    if (oy == d - 1 && oz == d - 1)  // the row's last run also clears its padding
+      for (int c = d * d * d; c < stride; ++c) X[(int64_t)r * stride + c] = one_zero<T>(0);
   }
 }
 
@@ -66,12 +71,12 @@ __global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t
 // byte's froxels lie in 8/d consecutive blocks (d <= 8) or in one block (d >= 8); each block's
 // row is looked up once and its logits of this (y, z) line are contiguous in Y.
 __global__ __launch_bounds__(256) void deinterleave_threshold_kernel(Batch B, int64_t total_bytes,
-                                                                      const float *__restrict__ Y,
+                                                                      const float *__restrict__ Y, int C,
                                                                       const int32_t *__restrict__ block_row,
                                                                       const uint8_t *__restrict__ occ,
                                                                       uint8_t *__restrict__ pvs,
                                                                       float *__restrict__ logits) {
-  const int d = B.d, C = d * d * d;
+  const int d = B.d;  // C: elements per row of Y (d^3, or more for a padded row)
   const float ninf = -__builtin_huge_valf();
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_bytes;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -87,7 +92,7 @@ __global__ __launch_bounds__(256) void deinterleave_threshold_kernel(Batch B, in
     const int key_yz = g.key_off + ((z / d) * g.By + (y / d)) * g.Bx;
     const int cyz = ((z % d) * d + (y % d)) * d;
     float lv[8];
-    if (d == 4) {
+    if (d == 4 && (C & 3) == 0) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int32_t row = block_row[key_yz + xb * 2 + j];
@@ -156,26 +161,30 @@ extern "C" npvs_status npvs_deinterleave(const void *in, npvs_dims g, int32_t d,
 
 extern "C" npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
                                         const int32_t *site_keys, const npvs_counts *counts, int32_t cap_sites,
-                                        int32_t dtype, void *X, void *stream) {
+                                        int32_t dtype, int32_t row_stride, void *X, void *stream) {
   if (!bits || !site_keys || !counts || !X) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: null pointer");
   Batch B;
   npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
   if (st != NPVS_OK) return st;
   if (cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: cap_sites < 1");
+  const int C = d * d * d, stride = row_stride ? row_stride : C;
+  if (stride < C) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: row_stride below d^3");
   int grid = stride_grid((int64_t)cap_sites * d * d, 256, 4096);
   hipStream_t s = as_stream(stream);
   switch (dtype) {
-    case NPVS_F32: gather_bits_kernel<float><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (float *)X); break;
-    case NPVS_BF16: gather_bits_kernel<uint16_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint16_t *)X); break;
-    case NPVS_U8: gather_bits_kernel<uint8_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint8_t *)X); break;
+    case NPVS_F32: gather_bits_kernel<float><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (float *)X, stride); break;
+    case NPVS_BF16:
+      gather_bits_kernel<uint16_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint16_t *)X, stride);
+      break;
+    case NPVS_U8: gather_bits_kernel<uint8_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint8_t *)X, stride); break;
     default: return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: dtype must be NPVS_F32, NPVS_BF16 or NPVS_U8");
   }
   return check_hip(hipGetLastError(), "npvs_gather_input");
 }
 
-extern "C" npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t *block_row, const uint8_t *occ_bits,
-                                                   int32_t n_grids, const npvs_dims *dims, int32_t d, uint8_t *pvs_bits,
-                                                   float *logits, void *stream) {
+extern "C" npvs_status npvs_deinterleave_threshold(const float *Y, int32_t y_stride, const int32_t *block_row,
+                                                   const uint8_t *occ_bits, int32_t n_grids, const npvs_dims *dims,
+                                                   int32_t d, uint8_t *pvs_bits, float *logits, void *stream) {
   if (!Y || !block_row || !occ_bits || !pvs_bits)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_deinterleave_threshold: null pointer");
   Batch B;
@@ -183,8 +192,10 @@ extern "C" npvs_status npvs_deinterleave_threshold(const float *Y, const int32_t
   if (st != NPVS_OK) return st;
   int64_t total = 0;
   for (int b = 0; b < n_grids; ++b) total += (int64_t)dims[b].nz * dims[b].ny * (dims[b].nx / 8);
+  const int C = d * d * d, stride = y_stride ? y_stride : C;
+  if (stride < C) return fail(NPVS_ERR_INVALID_ARG, "npvs_deinterleave_threshold: y_stride below d^3");
   int grid = stride_grid(total, 256, 8192);
-  deinterleave_threshold_kernel<<<grid, 256, 0, as_stream(stream)>>>(B, total, Y, block_row, occ_bits, pvs_bits,
-                                                                      logits);
+  deinterleave_threshold_kernel<<<grid, 256, 0, as_stream(stream)>>>(B, total, Y, stride, block_row, occ_bits,
+                                                                      pvs_bits, logits);
   return check_hip(hipGetLastError(), "npvs_deinterleave_threshold");
 }

@@ -233,6 +233,11 @@ CONFIGS["city256_d8"] = Config("city256_d8", [(256, 256, 128)], 8, [512] + [64] 
                                [dict()])
 CONFIGS["city256_d16"] = Config("city256_d16", [(256, 256, 128)], 16, [4096] + [64] * 5 + [4096], "city", [1],
                                 116, [dict()])
+# no interleave (d = 1, the ablation of Table 2): one input and one output channel per site
+CONFIGS["tiny32_d1"] = Config("tiny32_d1", [(32, 32, 32)], 1, [1, 16, 16, 1], "boxes", [0], 201,
+                              [dict(n_boxes=20, side_lo=2, side_hi=8)])
+CONFIGS["city256_d1"] = Config("city256_d1", [(256, 256, 128)], 1, [1] + [64] * 5 + [1], "city", [1], 102, [dict()])
+CONFIGS["city256_d2"] = Config("city256_d2", [(256, 256, 128)], 2, [8] + [64] * 5 + [8], "city", [1], 103, [dict()])
 CONFIGS["boxes64_d8"] = Config("boxes64_d8", [(64, 64, 64)], 8, [512, 32, 512], "boxes", [5], 208,
                                [dict(n_boxes=12, side_lo=4, side_hi=16)])
 CONFIGS["boxes64_d16"] = Config("boxes64_d16", [(64, 64, 64)], 16, [4096, 32, 4096], "boxes", [6], 216,

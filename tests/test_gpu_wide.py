@@ -204,3 +204,39 @@ def test_conv_bwd_wide_layers_on_an_empty_grid_are_zero(cin, cout):
     Wt = npvs.pack_weights(W, npvs.NPVS_BF16, flip_transpose=True)
     _, dW, db = npvs.sparse_conv_bwd(X, Wt, cin, cout, Y, dY, rb, npvs.NPVS_BF16, relu=True, want_dx=False)
     assert not to_np(dW).any() and not to_np(db).any()
+
+
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_network_without_interleave_d1(dtype):
+    """No interleave (d = 1, Table 2's ablation): one input and one output channel per site.  The
+    BF16 path pads them to 8 (zero input channels, zero weights, unread outputs).  FP32 within
+    1e-5 of the FP64 oracle; BF16 against the oracle's BF16 network under the rigorous bound of
+    forward_bf16_bound; the PVS bits agree outside the error band."""
+    cfg = synth.config("tiny32_d1")
+    t = synth.scene_for(cfg)
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    tris, counts = upload_tris([t])
+    plan = npvs.Plan(cfg.grids, counts, cfg.d, cfg.channels, dtype)
+    for li, (W, b) in enumerate(layers):
+        plan.set_weights(li, torch.from_numpy(W).to(DEV), torch.from_numpy(b).to(DEV))
+    pvs, logits = plan.forward(tris, want_logits=True)
+    got = to_np(logits)
+    if dtype == npvs.NPVS_F32:
+        out = oracle.forward(t, cfg.grids[0], cfg.d, layers)
+        ref, bound = out["logits"].reshape(-1), 1e-5
+    else:
+        out = oracle.forward_bf16(t, cfg.grids[0], cfg.d, layers)
+        fb = oracle.forward_bf16_bound(out, layers)
+        lg, _ = oracle.deinterleave_threshold(fb["D"][-1], out["keys"], out["occ"], cfg.grids[0], cfg.d)
+        ref, bound = out["logits"].reshape(-1), lg.reshape(-1)
+    act = np.isfinite(ref)
+    assert act.sum() > 1000  # the occupied froxels are the sites
+    assert (got[~act] == -np.inf).all()
+    err = np.abs(got[act] - ref[act])
+    b = bound if np.isscalar(bound) else bound[act]
+    print(f"d = 1 dtype {dtype}: {int(act.sum())} sites, max err {err.max():.3e}", flush=True)
+    assert np.all(err <= b)
+    pv = np.unpackbits(to_np(pvs), bitorder="little")
+    pw = np.unpackbits(out["pvs"].reshape(-1), bitorder="little")
+    safe = np.abs(np.nan_to_num(ref, neginf=-1e9)) > (b if np.isscalar(b) else np.where(act, np.nan_to_num(bound), 0))
+    np.testing.assert_array_equal(pv[safe], pw[safe])
