@@ -299,6 +299,62 @@ def bench_stage_table(args, dev):
     return out
 
 
+def bench_dense_interleave(dev):
+    """Dense g_d and its inverse on the logits grid of the 256x256x128 frame (33.5 MB of float32):
+    mean time per launch from graph replays and the HBM rate of its algorithmic bytes (every
+    element read once and written once)."""
+    import numpy as np
+    import torch
+
+    import paper_2509_24677_amd as npvs
+
+    def graph_ms(fn, reps=20, loops=10):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(loops):
+            g.replay()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / (reps * loops)
+
+    dims = (256, 256, 128)
+    gen = torch.Generator(device=dev).manual_seed(11)
+    res = {}
+    for name, dt, ds in (("f32", torch.float32, (1, 2, 4, 8, 16, 32)), ("bf16", torch.bfloat16, (4,)),
+                         ("u8", torch.uint8, (4,))):
+        if dt == torch.uint8:
+            x = torch.randint(0, 256, (dims[2], dims[1], dims[0]), device=dev, dtype=torch.uint8, generator=gen)
+        else:
+            x = torch.randn((dims[2], dims[1], dims[0]), device=dev, generator=gen).to(dt)
+        nbytes = 2 * x.numel() * x.element_size()
+        for d in ds:
+            y = npvs.interleave(x, d)
+            back = npvs.deinterleave(y, dims, d)
+            exact = bool(torch.equal(back.reshape(-1), x.reshape(-1)))
+            out_y, out_x = torch.empty_like(y), torch.empty_like(back)
+            ms_i = graph_ms(lambda: npvs.interleave(x, d, out=out_y))
+            ms_d = graph_ms(lambda: npvs.deinterleave(y, dims, d, out=out_x))
+            res[f"{name}_d{d}"] = {"bytes": nbytes, "interleave_ms": ms_i, "deinterleave_ms": ms_d,
+                                   "interleave_GB_per_s": nbytes / ms_i / 1e6,
+                                   "deinterleave_GB_per_s": nbytes / ms_d / 1e6,
+                                   "frac_of_hbm_peak": nbytes / min(ms_i, ms_d) / 1e6 / HBM_PEAK_GBS,
+                                   "round_trip_exact": exact}
+    return res
+
+
 def bench_wide(args, dev, timed_launches):
     """The city frame at the paper's interleave factors d = 8 and 16: forward (froxelize -> PVS) as a
     library-captured graph in BF16 and FP32, the training step (forward, loss, backward, Adam) as
@@ -932,6 +988,46 @@ def main():
                                                    variants["bf16_infer"]["ms_per_frame"])
     print("# variants " + json.dumps(variants), file=sys.stderr, flush=True)
 
+    # ------------------------------------------------------------------ device memory per frame
+    # Transient: the largest amount of torch-allocated memory one eager frame holds on top of what
+    # was allocated before it (activations, rulebook, workspaces; freed when the frame ends).
+    # Persistent: what a network with its Adam state and its autotuned shapes keeps between
+    # frames.  The library plan allocates through HIP directly, so its footprint is the drop in
+    # free device memory over its creation and capture.
+    def transient_mb(fn):
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        fn()
+        torch.cuda.synchronize()
+        return (torch.cuda.max_memory_allocated() - base) / 2 ** 20
+
+    base = torch.cuda.memory_allocated()
+    net_m, tr_m = make(npvs.NPVS_BF16)
+    tr_m.step(tris, labels)
+    torch.cuda.synchronize()
+    persistent = (torch.cuda.memory_allocated() - base) / 2 ** 20
+    memory = {"bf16_fwd_bwd_transient_MiB": transient_mb(train_fn(tr_m)),
+              "bf16_fwd_bwd_persistent_MiB": persistent,
+              "bf16_fwd_bwd_checkpointed_transient_MiB": transient_mb(train_fn(tr_c)),
+              "bf16_fwd_transient_MiB": transient_mb(fwd_fn(net_bf)),
+              "fp32_fwd_bwd_transient_MiB": transient_mb(train_fn(tr_f))}
+    del net_m, tr_m
+    torch.cuda.synchronize()
+    pvs_m = torch.empty(total_bytes, dtype=torch.uint8, device=dev)
+    wts_m = [(torch.from_numpy(W).to(dev), torch.from_numpy(b).to(dev)) for W, b in layers]
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    plan_m = npvs.Plan(dims, n_tris, cfg.d, cfg.channels, npvs.NPVS_BF16)
+    for li, (W, b) in enumerate(wts_m):
+        plan_m.set_weights(li, W, b)
+    with torch.cuda.stream(ps):
+        plan_m.capture(tris, pvs=pvs_m)
+        ps.synchronize()
+    memory["bf16_fwd_plan_MiB"] = (free0 - torch.cuda.mem_get_info()[0]) / 2 ** 20
+    del plan_m
+    print("# device memory " + json.dumps(memory), file=sys.stderr, flush=True)
+
     # ------------------------------------------------------------------ per-launch kernel timing
     # A GPU-side spin first lets the host enqueue the instrumented launches ahead of the GPU, so
     # each event pair brackets exactly one kernel on the stream it runs on.
@@ -1028,6 +1124,8 @@ def main():
     print("# batch of four 128^3 grids, training " + json.dumps(train4), file=sys.stderr, flush=True)
     wide = bench_wide(args, dev, timed_launches)
     print("# interleave factors 8 and 16 " + json.dumps(wide), file=sys.stderr, flush=True)
+    dense = bench_dense_interleave(dev)
+    print("# dense interleave " + json.dumps(dense), file=sys.stderr, flush=True)
     stage_table = bench_stage_table(args, dev)
     print("# stages by interleave factor " + json.dumps(stage_table), file=sys.stderr, flush=True)
     cull = bench_cull(args, dev, timed_launches, tris, n_tris, dims, pvs_b)
@@ -1075,6 +1173,8 @@ def main():
         "train128x4": train4,
         "interleave_8_16": wide,
         "stages_by_interleave_factor": stage_table,
+        "dense_interleave_logits_grid": dense,
+        "device_memory": memory,
         "culling": cull,
         "unet": unet,
         "world_space": world,

@@ -159,19 +159,28 @@ def gather_input(bits: torch.Tensor, rb: Rulebook, dtype: int = NPVS_F32, out: t
     return out
 
 
-def interleave(x: torch.Tensor, d: int) -> torch.Tensor:
-    """Dense g_d of a [nz][ny][nx] tensor -> [nz/d][ny/d][nx/d][d^3]."""
+def _dense_out(out, shape, x):
+    if out is None:
+        return torch.empty(shape, dtype=x.dtype, device=x.device)
+    if out.dtype != x.dtype or out.device != x.device or not out.is_contiguous() or out.numel() != x.numel():
+        raise ValueError("out must be a contiguous tensor of x's dtype, device and size")
+    return out
+
+
+def interleave(x: torch.Tensor, d: int, out: torch.Tensor = None) -> torch.Tensor:
+    """Dense g_d of a [nz][ny][nx] tensor -> [nz/d][ny/d][nx/d][d^3] (written into `out` if given)."""
     x = x.contiguous()
     nz, ny, nx = x.shape
-    out = torch.empty((nz // d, ny // d, nx // d, d ** 3), dtype=x.dtype, device=x.device)
+    out = _dense_out(out, (nz // d, ny // d, nx // d, d ** 3), x)
     L.call("npvs_interleave", _p(x), L.Dims(nx, ny, nz), d, x.element_size(), _p(out), _stream())
     return out
 
 
-def deinterleave(x: torch.Tensor, dims, d: int) -> torch.Tensor:
+def deinterleave(x: torch.Tensor, dims, d: int, out: torch.Tensor = None) -> torch.Tensor:
+    """Inverse of interleave: [nz/d][ny/d][nx/d][d^3] -> [nz][ny][nx] for dims (nx, ny, nz)."""
     x = x.contiguous()
     nx, ny, nz = dims
-    out = torch.empty((nz, ny, nx), dtype=x.dtype, device=x.device)
+    out = _dense_out(out, (nz, ny, nx), x)
     L.call("npvs_deinterleave", _p(x), L.Dims(nx, ny, nz), d, x.element_size(), _p(out), _stream())
     return out
 

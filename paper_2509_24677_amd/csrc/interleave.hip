@@ -6,25 +6,135 @@
 
 namespace npvs {
 
-// Dense g_d: one thread per (block, oz, oy) row of d contiguous x-elements.  The d elements
-// are contiguous on both sides (input row segment, output channel run).
-template <typename T>
+// Dense g_d through LDS (d >= 2; g_1 is the identity and a plain copy).  For one (bz, by) the
+// output [Bx][d^3] is one contiguous run and the input is d^2 contiguous row segments
+// (z = bz d + oz, y = by d + oy, row r = oz d + oy).  A workgroup takes Kx consecutive blocks of
+// one (bz, by) and R of their rows: it reads the R row segments of Kx d elements (coalesced
+// along x, V elements per lane) into an LDS tile [R][P] (row pitch P = Kx d + V keeps the
+// strided reads of the other side off a single bank), then writes the Kx R d outputs in output
+// order, V per lane, element (bx, r, ox) from tile[r][bx d + ox].  The inverse reads and writes
+// the other way round.  Kx and R are powers of two, so every index is a shift or a mask; the
+// last chunk of a row of blocks leaves its columns beyond the grid idle.  One tile holds 16 KiB:
+// R = d^2 and Kx = min(16 KiB / d^3 elements, Bx rounded up to a power of two) while a block
+// fits, else Kx = 1 and R = 16 KiB / d elements.
+constexpr int kDenseTileBytes = 16384;
+constexpr int kDenseSmemBytes = 24576;  // tile + row padding (at most R V elements)
+
+struct DenseShape {
+  int ld, lkx, lr;    // log2 of d, Kx, R
+  int chunks, rchunks, pitch;
+};
+
+template <int B> struct VecOf;
+template <> struct VecOf<16> { using type = uint4; };
+template <> struct VecOf<8> { using type = uint2; };
+template <> struct VecOf<4> { using type = uint32_t; };
+template <> struct VecOf<2> { using type = uint16_t; };
+template <> struct VecOf<1> { using type = uint8_t; };
+
+template <typename T, int V>
 __global__ __launch_bounds__(256) void dense_interleave_kernel(const T *__restrict__ in, T *__restrict__ out, int nx,
-                                                                int ny, int nz, int d, int inverse) {
-  const int Bx = nx / d, By = ny / d, Bz = nz / d;
-  const int64_t runs = (int64_t)Bx * By * Bz * d * d;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < runs; t += (int64_t)gridDim.x * blockDim.x) {
-    // t enumerates (block key, oz, oy) with the block key outermost: output-contiguous
-    int oy = t % d, oz = (t / d) % d;
-    int64_t key = t / ((int64_t)d * d);
-    int bx = key % Bx, by = (key / Bx) % By, bz = key / ((int64_t)Bx * By);
-    int64_t src = ((int64_t)(bz * d + oz) * ny + (by * d + oy)) * nx + (int64_t)bx * d;
-    int64_t dst = key * (int64_t)d * d * d + (int64_t)(oz * d + oy) * d;
-    if (!inverse)
-      for (int ox = 0; ox < d; ++ox) out[dst + ox] = in[src + ox];
-    else
-      for (int ox = 0; ox < d; ++ox) out[src + ox] = in[dst + ox];
+                                                                int ny, int nz, DenseShape t, int inverse) {
+  using Vec = typename VecOf<V * sizeof(T)>::type;
+  union Pack {
+    Vec v;
+    T e[V];
+  };
+  __shared__ __align__(16) unsigned char smem[kDenseSmemBytes];
+  T *tile = reinterpret_cast<T *>(smem);
+  const int ld = t.ld, d = 1 << ld, P = t.pitch;
+  const int Bx = nx >> ld, By = ny >> ld, Bz = nz >> ld;
+  const int lcols = t.lkx + ld, lrd = t.lr + ld;  // log2 of Kx d (tile columns) and R d (outputs per block)
+  const int64_t items = (int64_t)Bz * By * t.chunks * t.rchunks;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int rc = it % t.rchunks;
+    const int64_t rest = it / t.rchunks;
+    const int ch = rest % t.chunks;
+    const int64_t byz = rest / t.chunks;
+    const int by = byz % By, bz = byz / By;
+    const int bx0 = ch << t.lkx, kx = min(1 << t.lkx, Bx - bx0), W = kx << ld, r0 = rc << t.lr;
+    // source row r of the tile: z = bz d + (r0 + r) / d, y = by d + (r0 + r) % d, x from bx0 d
+    const int64_t src0 = ((int64_t)(bz << ld) * ny + (by << ld)) * nx + ((int64_t)bx0 << ld);
+    const int64_t dst0 = (((int64_t)(bz * By + by) * Bx + bx0) << (3 * ld)) + ((int64_t)r0 << ld);
+    const int nrow = (1 << (t.lr + lcols)) / V, nout = (1 << (t.lkx + lrd)) / V;
+    if (!inverse) {
+      for (int q = threadIdx.x; q < nrow; q += 256) {
+        const int e = q * V, r = e >> lcols, x = e & ((1 << lcols) - 1);
+        if (x >= W) continue;
+        const int rr = r0 + r;
+        *reinterpret_cast<Vec *>(tile + r * P + x) =
+            *reinterpret_cast<const Vec *>(in + src0 + ((int64_t)(rr >> ld) * ny + (rr & (d - 1))) * nx + x);
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < nout; q += 256) {
+        const int o = q * V, bxl = o >> lrd, rem = o & ((1 << lrd) - 1);
+        if (bxl >= kx) continue;
+        Pack u;
+#pragma unroll
+        for (int j = 0; j < V; ++j) u.e[j] = tile[((rem + j) >> ld) * P + (bxl << ld) + ((rem + j) & (d - 1))];
+        *reinterpret_cast<Vec *>(out + dst0 + ((int64_t)bxl << (3 * ld)) + rem) = u.v;
+      }
+    } else {
+      for (int q = threadIdx.x; q < nout; q += 256) {
+        const int o = q * V, bxl = o >> lrd, rem = o & ((1 << lrd) - 1);
+        if (bxl >= kx) continue;
+        Pack u;
+        u.v = *reinterpret_cast<const Vec *>(in + dst0 + ((int64_t)bxl << (3 * ld)) + rem);
+#pragma unroll
+        for (int j = 0; j < V; ++j) tile[((rem + j) >> ld) * P + (bxl << ld) + ((rem + j) & (d - 1))] = u.e[j];
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < nrow; q += 256) {
+        const int e = q * V, r = e >> lcols, x = e & ((1 << lcols) - 1);
+        if (x >= W) continue;
+        const int rr = r0 + r;
+        *reinterpret_cast<Vec *>(out + src0 + ((int64_t)(rr >> ld) * ny + (rr & (d - 1))) * nx + x) =
+            *reinterpret_cast<const Vec *>(tile + r * P + x);
+      }
+    }
+    __syncthreads();  // the tile is refilled by the next item
   }
+}
+
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// Tile shape for Bx blocks along x at interleave factor d >= 2, elements of esize bytes moved V
+// at a time.
+static DenseShape dense_shape(int Bx, int d, int esize, int V) {
+  DenseShape t;
+  const int tile = kDenseTileBytes / esize, d2 = d * d, d3 = d2 * d;
+  int kx = 1, r = d2;
+  if (d3 <= tile) {
+    while (kx < Bx && kx * 2 * d3 <= tile) kx *= 2;
+  } else {
+    r = tile / d;
+  }
+  t.ld = ilog2(d);
+  t.lkx = ilog2(kx);
+  t.lr = ilog2(r);
+  t.chunks = (Bx + kx - 1) / kx;
+  t.rchunks = d2 / r;
+  t.pitch = kx * d + V;
+  return t;
+}
+
+template <typename T>
+static void launch_dense(const void *in, void *out, const npvs_dims &g, int d, int inverse, hipStream_t s) {
+  // 16-byte lanes (8 for single bytes, whose rows are only known to be multiples of 8 long) when
+  // both buffers allow it
+  constexpr int VV = sizeof(T) == 1 ? 8 : 16 / (int)sizeof(T);
+  const bool vec = ((uintptr_t)in % (VV * sizeof(T))) == 0 && ((uintptr_t)out % (VV * sizeof(T))) == 0;
+  const DenseShape t = dense_shape(g.nx / d, d, sizeof(T), vec ? VV : 1);
+  const int64_t items = (int64_t)(g.ny / d) * (g.nz / d) * t.chunks * t.rchunks;
+  const int grid = stride_grid(items, 1, 16384);
+  if (vec)
+    dense_interleave_kernel<T, VV><<<grid, 256, 0, s>>>((const T *)in, (T *)out, g.nx, g.ny, g.nz, t, inverse);
+  else
+    dense_interleave_kernel<T, 1><<<grid, 256, 0, s>>>((const T *)in, (T *)out, g.nx, g.ny, g.nz, t, inverse);
 }
 
 // Sparse interleave of packed bits onto active sites: one thread per (site, oz, oy) run of d
@@ -136,15 +246,16 @@ static npvs_status dense_perm(const void *in, npvs_dims g, int32_t d, int32_t es
   Batch B;
   npvs_status st = make_batch(1, &g, d, nullptr, &B);
   if (st != NPVS_OK) return st;
-  int64_t runs = (int64_t)(g.nx / d) * (g.ny / d) * (g.nz / d) * d * d;
-  int grid = stride_grid(runs, 256, 8192);
   hipStream_t s = as_stream(stream);
+  if (esize != 1 && esize != 2 && esize != 4 && esize != 8)
+    return fail(NPVS_ERR_INVALID_ARG, std::string(name) + ": elem_bytes must be 1, 2, 4 or 8");
+  if (d == 1)  // g_1 is the identity
+    return check_hip(hipMemcpyAsync(out, in, (size_t)g.nx * g.ny * g.nz * esize, hipMemcpyDeviceToDevice, s), name);
   switch (esize) {
-    case 1: dense_interleave_kernel<uint8_t><<<grid, 256, 0, s>>>((const uint8_t *)in, (uint8_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
-    case 2: dense_interleave_kernel<uint16_t><<<grid, 256, 0, s>>>((const uint16_t *)in, (uint16_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
-    case 4: dense_interleave_kernel<uint32_t><<<grid, 256, 0, s>>>((const uint32_t *)in, (uint32_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
-    case 8: dense_interleave_kernel<uint64_t><<<grid, 256, 0, s>>>((const uint64_t *)in, (uint64_t *)out, g.nx, g.ny, g.nz, d, inverse); break;
-    default: return fail(NPVS_ERR_INVALID_ARG, std::string(name) + ": elem_bytes must be 1, 2, 4 or 8");
+    case 1: launch_dense<uint8_t>(in, out, g, d, inverse, s); break;
+    case 2: launch_dense<uint16_t>(in, out, g, d, inverse, s); break;
+    case 4: launch_dense<uint32_t>(in, out, g, d, inverse, s); break;
+    default: launch_dense<uint64_t>(in, out, g, d, inverse, s); break;
   }
   return check_hip(hipGetLastError(), name);
 }

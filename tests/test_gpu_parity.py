@@ -187,10 +187,13 @@ def test_empty_grid_has_no_sites():
 
 
 # ------------------------------------------------------------------------------- interleave
-@pytest.mark.parametrize("d", [1, 2, 4, 8])
+# (d, dims): the LDS tile holds 4096 elements, Kx = 4096 / d^3 blocks along x; (280, 8, 4) at
+# d = 4 ends in a partial tile of 6 blocks, d = 16 fills one tile per block and d = 32 splits
+# each block over 8 tiles of 128 rows.
+@pytest.mark.parametrize("d,dims", [(1, (64, 32, 16)), (2, (64, 32, 16)), (4, (64, 32, 16)), (4, (280, 8, 4)),
+                                    (8, (64, 32, 16)), (16, (96, 32, 16)), (32, (96, 64, 32))])
 @pytest.mark.parametrize("dtype", [torch.uint8, torch.float16, torch.float32, torch.float64])
-def test_dense_interleave_bit_exact(d, dtype):
-    dims = (64, 32, 16)
+def test_dense_interleave_bit_exact(d, dims, dtype):
     g = torch.Generator().manual_seed(d)
     a = (torch.rand((dims[2], dims[1], dims[0]), generator=g) * 200).to(dtype)
     out = npvs.interleave(a.to(DEV), d)
