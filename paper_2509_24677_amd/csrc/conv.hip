@@ -389,9 +389,11 @@ __global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__
 // over all the tiles its workgroup walks.  At the end a fixed butterfly adds the 16 rows of each
 // column and the workgroup writes its row of dbp[NPVS_BWD_DB_PARTS][cout] (rows past the grid are
 // written as zeros), so the bias gradient of the layer below is a fixed-order sum over that table.
-// NBW: output blocks of 16 channels per workgroup (2; 1 for 4 or 5 input chunks, whose weights
-// and rows would not fit the registers otherwise, and which then gather each tile's rows when
-// its iteration starts instead of one tile ahead).
+// NBW: output blocks of 16 channels per workgroup (2, 4, or 1 for 4 or 5 input chunks).  With
+// two blocks the rows of the next tile are gathered into a second buffer while the current
+// tile's products run; with one or four (whose weights leave no registers for a second buffer)
+// they are gathered into the same buffer as soon as the products have issued, ahead of the
+// reduction and the epilogue.
 template <int KB, int MB, bool FUSE = false, int NBW = 2>
 __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
                                                                   const bf16x8_t *__restrict__ Wp,
@@ -439,27 +441,55 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
     if constexpr (FUSE) write_db_parts();
     return;
   }
-  // indices of a tile (clamped: a missing tile re-reads the last valid one)
+  // Loads retire in order, so a value used right after its load makes every load issued before
+  // it wait too.  The neighbour indices are therefore loaded raw (rows past the last site read
+  // the last site's entry) and judged only when their rows are gathered, and a gathered row is
+  // loaded raw (a missing neighbour loads row 0) with its mask kept beside it, applied only where
+  // the products read the row; the bias of the epilogue is loaded once, before the tiles.
+  // (A missing tile re-reads the indices of the last valid one.)
   auto indices = [&](int t, int (&ix)[KPER][MB]) {
 #pragma unroll
     for (int q = 0; q < KPER; ++q)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) ix[q][mb] = nbr_index(nbr, cap, kbeg + q, t * ROWS + mb * 16 + (lane & 15), n);
+      for (int mb = 0; mb < MB; ++mb) {
+        const int r = t * ROWS + mb * 16 + (lane & 15);
+        ix[q][mb] = nbr[(int64_t)(kbeg + q) * cap + (r < n ? r : n - 1)];
+      }
   };
-  auto rows = [&](const int (&ix)[KPER][MB], bf16x8_t (&b)[KPER][KB][MB]) {
+  // rows of tile t, whose raw indices ix holds
+  auto rows = [&](const int (&ix)[KPER][MB], int t, uint4 (&b)[KPER][KB][MB], uint32_t (&m)[KPER][MB]) {
 #pragma unroll
     for (int q = 0; q < KPER; ++q)
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb)
+      for (int mb = 0; mb < MB; ++mb) {
+        const bool ok = t * ROWS + mb * 16 + (lane & 15) < n && ix[q][mb] >= 0;
+        m[q][mb] = ok ? ~0u : 0u;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) b[q][kb][mb] = gather8(X, cin, ix[q][mb], kb * 32 + csub);
+        for (int kb = 0; kb < KB; ++kb) {
+          const int c = kb * 32 + csub;
+          b[q][kb][mb] = *reinterpret_cast<const uint4 *>(X + (ok && c < cin ? (int64_t)ix[q][mb] * cin + c : 0));
+        }
+      }
   };
+  auto masked = [&](const uint4 &v, uint32_t m, int kb) {
+    const uint32_t mm = kb * 32 + csub < cin ? m : 0u;
+    return __builtin_bit_cast(bf16x8_t, make_uint4(v.x & mm, v.y & mm, v.z & mm, v.w & mm));
+  };
+  // the epilogue block of this wave (at most one: NBLK <= KSPLIT) and its bias
+  float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if constexpr (!FUSE) {
+    const int o = (nb0 + wv % NBW) * 16 + 4 * (lane >> 4);
+    if (bias && wv < NBLK && o < cout)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bv[i] = bias[o + i];
+  }
   int ix[KPER][MB];
-  bf16x8_t bx[KPER][KB][MB];
+  uint4 bx[KPER][KB][MB];
+  uint32_t bm[KPER][MB];
   indices(tile, ix);
-  if constexpr (PF) rows(ix, bx);
+  rows(ix, tile, bx, bm);
   int t1 = xcd_tile(blockIdx.x, gridDim.x, ntiles, 1);
-  if constexpr (PF) indices(t1 >= 0 ? t1 : tile, ix);
+  indices(t1 >= 0 ? t1 : tile, ix);
   for (int j = 0; tile >= 0; ++j) {
     const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
     // FUSE: the epilogue waves fetch this tile's mask now, so its latency hides under the products
@@ -468,13 +498,11 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
       const int r = tile * ROWS + (lane & 15), o = (nb0 + wv) * 16 + 4 * (lane >> 4);
       if (M && wv < NBLK && r < n && o < cout) mk = *reinterpret_cast<const uint2 *>(M + (int64_t)r * cout + o);
     }
-    bf16x8_t bn[KPER][KB][MB];
+    uint4 bn[KPER][KB][MB];
+    uint32_t bnm[KPER][MB];
     if constexpr (PF) {
-      rows(ix, bn);                                        // tile j + 1 (or a repeat)
+      rows(ix, t1 >= 0 ? t1 : tile, bn, bnm);              // tile j + 1 (or a repeat)
       indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
-    } else {
-      rows(ix, bx);                       // tile j
-      indices(t1 >= 0 ? t1 : tile, ix);   // tile j + 1 (or a repeat)
     }
     f32x4_t acc[MB][NBW];
 #pragma unroll
@@ -489,16 +517,27 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         for (int nb = 0; nb < NBW; ++nb)
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], bx[q][kb][mb], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], masked(bx[q][kb][mb], bm[q][mb], kb),
+                                                                  acc[mb][nb], 0, 0, 0);
+    // Without a second row buffer, the next tile's rows go into this tile's registers as soon as
+    // the products have taken them (the fused data gradient, which holds more registers, waits
+    // until the sums are out in LDS), their latency hidden by the reduction and the epilogue.
+    auto next_rows = [&]() {
+      rows(ix, t1 >= 0 ? t1 : tile, bx, bm);               // tile j + 1 (or a repeat)
+      indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
+    };
+    if constexpr (!PF && !FUSE) next_rows();
     __syncthreads();  // the previous tile's readers are done with red
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) red[(wv * NBLK + mb * NBW + nb) * 64 + lane] = acc[mb][nb];
+    if constexpr (!PF && FUSE) next_rows();
     __syncthreads();
     const int row0 = tile * ROWS;
     for (int blk = wv; blk < NBLK; blk += KSPLIT) {
       f32x4_t sum = red[blk * 64 + lane];
+#pragma unroll 4  // with the next tile's rows in flight, a full unroll would spill
       for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
       const int mb = blk / NBW, nb = blk % NBW;
       const int r = row0 + mb * 16 + (lane & 15), o = (nb0 + nb) * 16 + 4 * (lane >> 4);
@@ -518,7 +557,7 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
           *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = h;
         }
       } else {
-        conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
+        conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
       }
     }
     if constexpr (PF) {
@@ -528,6 +567,10 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) bx[q][kb][mb] = bn[q][kb][mb];
+#pragma unroll
+      for (int q = 0; q < KPER; ++q)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) bm[q][mb] = bnm[q][mb];
     }
     tile = t1;
     t1 = t2;

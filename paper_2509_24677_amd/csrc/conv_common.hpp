@@ -45,6 +45,26 @@ __device__ __forceinline__ int nbr_index(const int32_t *__restrict__ nbr, int ca
   return r < n ? v : -1;
 }
 
+// Bias (4 values, already loaded) + optional ReLU, stored as float32 or bfloat16.
+__device__ __forceinline__ void conv_bf16_epilogue_bias(const f32x4_t &acc, int r, int n, int o, int cout,
+                                                        const float (&bv)[4], int relu, int out_f32, void *Y) {
+  if (r >= n || o >= cout) return;
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float t = acc[i] + bv[i];
+    v[i] = (relu && t < 0.0f) ? 0.0f : t;
+  }
+  if (out_f32) {
+    *reinterpret_cast<float4 *>(static_cast<float *>(Y) + (int64_t)r * cout + o) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    uint2 p;
+    p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+    p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+    *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = p;
+  }
+}
+
 template <int NB>
 __device__ __forceinline__ void conv_bf16_epilogue(const f32x4_t &acc, int r, int n, int o, int cout,
                                                    const float *__restrict__ bias, int relu, int out_f32, void *Y) {
