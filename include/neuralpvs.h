@@ -485,7 +485,8 @@ npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *v, int64_t 
  * = 1 packing (forward and data gradient), both of npvs_packed_weight_bytes(cin, cout, dtype)
  * bytes and packed once before (their padding entries are not rewritten).  Layer l's weight
  * [27][cin][cout] is p[off, off + 27 cin cout); layers must not overlap; at most
- * NPVS_MAX_ADAM_PACK layers.  The result equals npvs_adam_dev followed by the two packings. */
+ * NPVS_MAX_ADAM_PACK layers, each of fewer than 2^31 weights (NPVS_ERR_UNSUPPORTED otherwise).
+ * The result equals npvs_adam_dev followed by the two packings. */
 #define NPVS_MAX_ADAM_PACK 32
 typedef struct {
   int64_t off;       /* first entry of the layer's weight in p */

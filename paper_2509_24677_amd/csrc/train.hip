@@ -29,6 +29,7 @@ struct Comp {
 
 constexpr int kLossSlices = 256;
 constexpr int kLossQ = 5;  // BCE sum, TP, FN, FP, GTP
+constexpr int kLossBatch = 8;  // elements per thread loaded together
 
 __device__ __forceinline__ float sigmoidf_(float l) { return 1.0f / (1.0f + expf(-l)); }
 
@@ -46,16 +47,30 @@ __global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restri
   Comp q[kLossQ];
 #pragma unroll
   for (int i = 0; i < kLossQ; ++i) q[i] = Comp{0.0f, 0.0f};
-  for (int64_t e = a0 + tid; e < a1; e += 256) {
-    const float l = logits[e];
-    const float y = labels[e] ? 1.0f : 0.0f;
-    const float p = sigmoidf_(l);
-    const float sp = fmaxf(l, 0.0f) + log1pf(expf(-__builtin_fabsf(l)));
-    q[0].add(sp - y * l);
-    q[1].add(y * p);
-    q[2].add(y * (1.0f - p));
-    q[3].add((1.0f - y) * p);
-    q[4].add(y);
+  // kLossBatch elements per thread are loaded before any is used (a value used right after its
+  // load would make each element wait for memory in turn); they are added in the same order.
+  for (int64_t eb = a0 + tid; eb < a1; eb += 256 * kLossBatch) {
+    float lv[kLossBatch];
+    uint8_t yv[kLossBatch];
+#pragma unroll
+    for (int u = 0; u < kLossBatch; ++u) {
+      const int64_t e = eb + 256 * u;
+      lv[u] = e < a1 ? logits[e] : 0.0f;
+      yv[u] = e < a1 ? labels[e] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLossBatch; ++u) {
+      if (eb + 256 * u >= a1) break;
+      const float l = lv[u];
+      const float y = yv[u] ? 1.0f : 0.0f;
+      const float p = sigmoidf_(l);
+      const float sp = fmaxf(l, 0.0f) + log1pf(expf(-__builtin_fabsf(l)));
+      q[0].add(sp - y * l);
+      q[1].add(y * p);
+      q[2].add(y * (1.0f - p));
+      q[3].add((1.0f - y) * p);
+      q[4].add(y);
+    }
   }
 #pragma unroll
   for (int i = 0; i < kLossQ; ++i) red[i][tid] = q[i];
@@ -207,9 +222,13 @@ __global__ __launch_bounds__(256) void adam_pack_kernel(float *__restrict__ p, c
     p[i] = w;
     for (int l = 0; l < AP.n; ++l) {
       const npvs_adam_pack_desc &D = AP.L[l];
-      const int64_t e = i - D.off;
-      if (e < 0 || e >= 27LL * D.cin * D.cout) continue;
-      const int o = (int)(e % D.cout), c = (int)((e / D.cout) % D.cin), k = (int)(e / ((int64_t)D.cin * D.cout));
+      const int64_t e64 = i - D.off;
+      if (e64 < 0 || e64 >= 27LL * D.cin * D.cout) continue;
+      // 32-bit index arithmetic (27 cin cout < 2^31, checked by the host): a 64-bit division
+      // is a long instruction sequence on the GPU
+      const uint32_t e = (uint32_t)e64, co = (uint32_t)D.cout, ci = (uint32_t)D.cin;
+      const uint32_t eo = e / co;
+      const int o = (int)(e - eo * co), c = (int)(eo % ci), k = (int)(eo / ci);
       store_packed(D.Wp, packed_index(k, c, o, D.cin, D.cout, dtype), w, dtype);
       store_packed(D.Wt, packed_index(26 - k, o, c, D.cout, D.cin, dtype), w, dtype);
       break;
@@ -306,6 +325,8 @@ extern "C" npvs_status npvs_adam_dev_pack(float *p, const float *g, float *m, fl
     const npvs_adam_pack_desc &D = layers[l];
     if (!D.Wp || !D.Wt || D.cin < 1 || D.cout < 1 || D.off < 0 || D.off + 27LL * D.cin * D.cout > n)
       return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: layer outside the parameter buffer");
+    if (27LL * D.cin * D.cout > 0x7fffffffLL)
+      return fail(NPVS_ERR_UNSUPPORTED, "npvs_adam_dev_pack: a layer of 2^31 or more weights");
     for (int q = 0; q < l; ++q) {
       const npvs_adam_pack_desc &E = layers[q];
       if (D.off < E.off + 27LL * E.cin * E.cout && E.off < D.off + 27LL * D.cin * D.cout)
