@@ -225,39 +225,32 @@ npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int3
  *   X (device) [cap_sites][cin]; Wp packed weights; bias (device, nullable) float32 [cout];
  *   nbr, counts from npvs_build_rulebook; Y (device) [cap_sites][cout], rows >= n_sites untouched.
  * BF16 requires cin % 8 == 0 and cout % 8 == 0 (NPVS_ERR_UNSUPPORTED otherwise).
+ * variant: the BF16 tile shape in [0, NPVS_CONV_VARIANTS), or -1 for NPVS_DEFAULT_CONV_VARIANT.
+ *   Variants 0-5 split a tile's 27 offsets over several waves, (rows per wave, waves) = 0 (16, 9),
+ *   1 (32, 1), 2 (16, 3), 3 (32, 3), 4 (16, 1), 5 (32, 9); variants 6-11 give each wave its own
+ *   rows and all offsets and share each offset's weights through LDS, (rows per wave, waves) =
+ *   6 (16, 4), 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8); variants 12 and 13 (inputs
+ *   of at most 64 channels) keep each wave's weights in registers while a workgroup walks several
+ *   row tiles of 16 or 32 rows (32 outputs per workgroup); variant 14 is variant 12 with every
+ *   output block (at most 64 outputs) in one workgroup, so a gathered row serves all outputs (more
+ *   than 64 outputs: variant 12).  Channel counts no tuned shape covers use a general kernel
+ *   (variants 5 and 13 select its 32-row tiles), except 65 to 160 inputs, which take the
+ *   weight-stationary kernel with 16-row tiles unless variant 5 is asked for.  All variants give
+ *   results within float32 rounding of each other; each one is deterministic.  Ignored by the
+ *   FP32 path.
+ * ws (device, nullable): scratch of npvs_conv_fwd_workspace_size() bytes.  BF16 layers with 1024
+ *   or more input channels (the first layer of interleave factor 16, cin = 4096) then split their
+ *   input channels over several workgroups and add the partial sums in a fixed order (within
+ *   float32 rounding of the unsplit kernel, deterministic); without it (or when the size is 0)
+ *   the unsplit kernel runs.  A non-null ws of fewer bytes than needed is an argument error.
  * ------------------------------------------------------------------------------------------- */
+#define NPVS_CONV_VARIANTS 15
+#define NPVS_DEFAULT_CONV_VARIANT 14 /* the tile shape of variant -1 and of the data gradient */
+npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
 npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                  const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                                 int32_t relu, int32_t out_f32, void *Y, void *stream);
-/* Same, with an explicit BF16 tile shape `variant` in [0, NPVS_CONV_VARIANTS).  Variants 0-5
- * split a tile's 27 offsets over several waves, (rows per wave, waves) = 0 (16, 9), 1 (32, 1),
- * 2 (16, 3), 3 (32, 3), 4 (16, 1), 5 (32, 9); variants 6-9 give each wave its own rows and all
- * offsets and share each offset's weights through LDS, (rows per wave, waves) = 6 (16, 4),
- * 7 (16, 2), 8 (32, 2), 9 (16, 8), 10 (32, 4), 11 (32, 8); variants 12 and 13 (inputs of at
- * most 64 channels) keep each wave's weights in registers while a workgroup walks several row
- * tiles of 16 or 32 rows (32 outputs per workgroup); variant 14 is variant 12 with every output
- * block (at most 64 outputs) in one workgroup, so a gathered row serves all outputs (more than 64
- * outputs: variant 12).  Channel counts no tuned shape covers use a general kernel (variants
- * 5 and 13 select its 32-row tiles), except 65 to 96 inputs, which take the weight-stationary
- * kernel with 16-row tiles unless variant 5 is asked for.  All variants give results within float32 rounding of each
- * other; each one is deterministic.  Ignored by the FP32 path. */
-#define NPVS_CONV_VARIANTS 15
-#define NPVS_DEFAULT_CONV_VARIANT 14 /* the tile shape npvs_sparse_conv_fwd and the data gradient use */
-npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
-                                    const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                                    int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *stream);
-
-/* Same, with a workspace: BF16 layers with 1024 or more input channels (the first layer of
- * interleave factor 16, Cin = 4096) then split their input channels over several workgroups and
- * add the partial sums in a fixed order (results within float32 rounding of the unsplit kernel,
- * deterministic).  npvs_conv_fwd_workspace_size() gives the bytes (0: no workspace needed, ws
- * may be NULL); a smaller non-zero ws_bytes is an argument error.  ws (device) is scratch,
- * overwritten by the call. */
-npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
-npvs_status npvs_sparse_conv_fwd_ws(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
-                                    const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                                    int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *ws,
-                                    size_t ws_bytes, void *stream);
+                                 int32_t relu, int32_t out_f32, int32_t variant, void *Y, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Backward of one submanifold layer (chain rule on the forward definition):
@@ -274,65 +267,20 @@ npvs_status npvs_sparse_conv_fwd_ws(const void *X, int32_t cin, const void *Wp, 
  *   of 64 x 64 channels, and the data gradient of a BF16 layer with 1024+ outputs splits its input
  *   channels over several workgroups (the workspace size covers it).
  * ------------------------------------------------------------------------------------------- */
+/* Streams: dZ and the bias partials are formed on `stream`, and the data gradient dX runs there.
+ * wgrad_stream (nullable: `stream`) waits for dZ and computes the weight-gradient slices, so they
+ * overlap the data-gradient chain of the layers below; reduce_stream (nullable: wgrad_stream)
+ * waits for those and adds the slices and the bias partials into dW and db, so that the next
+ * layer's weight gradient does not wait for this layer's reductions.  Until the caller makes
+ * `stream` wait for the side streams, dW, db, X and ws are in use by them (do not read dW / db
+ * or reuse ws or X before that).  All streams may be under capture (the waits are graph
+ * dependencies). */
 npvs_status npvs_conv_bwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
 npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
                                  const float *dY, const int32_t *nbr, const int32_t *rb_off, const int32_t *rb_pairs,
                                  const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
-                                 float *dW, float *db, void *ws, size_t ws_bytes, void *stream);
-
-/* The same backward with the weight and bias gradients on a second stream, so that they overlap
- * the data-gradient chain of the layers below.  dZ and the bias partials are formed on `stream`,
- * then `wgrad_stream` waits for them and computes dW and db while dX is computed on `stream`.
- * Until the caller makes `stream` wait for `wgrad_stream`, dW, db, X and ws are in use by
- * `wgrad_stream` (do not read dW / db or reuse ws or X before that).  wgrad_stream == stream is
- * npvs_sparse_conv_bwd.  Both streams may be under capture (the wait is a graph dependency). */
-npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
-                                       const float *dY, const int32_t *nbr, const int32_t *rb_off,
-                                       const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
-                                       int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
-                                       size_t ws_bytes, void *stream, void *wgrad_stream);
-
-/* The same with the final reductions (dW over the weight-gradient slices, db over the row blocks)
- * on a third stream: reduce_stream waits for the weight gradient of wgrad_stream, so the next
- * layer's weight gradient does not wait for this layer's reductions (they are small and run
- * beside it).  Until the caller makes `stream` wait for reduce_stream (and wgrad_stream), dW,
- * db, X and ws are in use; reduce_stream may equal wgrad_stream (npvs_sparse_conv_bwd_split). */
-npvs_status npvs_sparse_conv_bwd_split2(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
-                                        const float *dY, const int32_t *nbr, const int32_t *rb_off,
-                                        const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
-                                        int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
-                                        size_t ws_bytes, void *stream, void *wgrad_stream, void *reduce_stream);
-
-/* The backward of a stack of BF16 layers as a chain, one call per layer from the top, with each
- * layer's ReLU' fused into the data gradient of the layer above it (the same chain rule as above;
- * the gradients are in a different float32 summation order for db only: dZ and dW are
- * bit-identical to npvs_sparse_conv_bwd).  A layer's dZ travels as bfloat16 [cap][cout] (the
- * MFMA operand; rows >= n_sites undefined) with a bias partial table dbp, float32
- * [NPVS_BWD_DB_PARTS][cout], whose column sums in a fixed order give db.
- *
- * npvs_conv_bwd_begin: dZ = bf16(dY * [Y > 0]) (relu) or bf16(dY), and its dbp, for the top
- *   layer.  dY (device) float32 [cap][cout], Y (device, used when relu) bfloat16 [cap][cout];
- *   cout <= 64, cout % 4 == 0, dY and Y 16-byte aligned.
- * npvs_sparse_conv_bwd_chain: given this layer's dZ / dbp (as begin or the chain call of the
- *   layer above wrote them), computes dW [27][cin][cout] and db [cout] (float32, overwritten) on
- *   wgrad_stream (after a wait for `stream`), and, when dZ_below is non-null, on `stream`
- *   dZ_below[r][c] = bf16(dX[r][c] * [X[r][c] > 0]) (relu_below; else without the mask) for
- *   r < n_sites with its dbp_below (float32 [NPVS_BWD_DB_PARTS][cin]): the dZ / dbp of the layer
- *   below, whose output X is.  X (device) bfloat16 layer input [cap][cin]; Wt as for
- *   npvs_sparse_conv_bwd; cin, cout <= 64 and multiples of 8; ws (device) of
- *   npvs_conv_bwd_chain_workspace_size() bytes, scratch.  Until the caller makes `stream` wait
- *   for wgrad_stream, dZ, dbp, X, dW, db and ws are in use by wgrad_stream (one ws serves
- *   calls whose wgrad_stream is the same stream); dZ_below / dbp_below must not alias them.
- *   wgrad_stream may equal stream; both may be under capture. */
-#define NPVS_BWD_DB_PARTS 512
-npvs_status npvs_conv_bwd_begin(const float *dY, const void *Y, int32_t cout, const npvs_counts *counts,
-                                int32_t cap_sites, int32_t relu, void *dZ, float *dbp, void *stream);
-npvs_status npvs_conv_bwd_chain_workspace_size(int32_t cin, int32_t cout, size_t *bytes);
-npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *dZ,
-                                       const float *dbp, const int32_t *nbr, const int32_t *rb_off,
-                                       const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
-                                       int32_t relu_below, void *dZ_below, float *dbp_below, float *dW, float *db,
-                                       void *ws, size_t ws_bytes, void *stream, void *wgrad_stream);
+                                 float *dW, float *db, void *ws, size_t ws_bytes, void *stream, void *wgrad_stream,
+                                 void *reduce_stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Two-level sparse U-Net pieces (Sec. 3.3 adopts an encoder/decoder backbone; the supplement's

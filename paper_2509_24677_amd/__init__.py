@@ -21,7 +21,7 @@ from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  #
 
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
-    "sparse_conv_fwd", "sparse_conv_bwd", "conv_bwd_begin", "sparse_conv_bwd_chain", "Levels", "build_levels",
+    "sparse_conv_fwd", "sparse_conv_bwd", "Levels", "build_levels",
     "pack_weights_k", "strided_conv_fwd", "concat_channels", "viewcell_frustum", "froxelize_view", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
     "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
 ]
@@ -224,17 +224,10 @@ def sparse_conv_fwd(X: torch.Tensor, Wp: torch.Tensor, bias: torch.Tensor | None
         out = torch.empty((rb.cap, cout), dtype=odt, device=X.device)
     nbytes = ctypes.c_size_t()
     L.call("npvs_conv_fwd_workspace_size", cin, cout, rb.cap, dtype, ctypes.byref(nbytes))
-    if nbytes.value:  # wide inputs: channel-split partial sums
-        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
-        L.call("npvs_sparse_conv_fwd_ws", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap,
-               dtype, int(relu), int(out_f32), int(variant if variant is not None else L.NPVS_DEFAULT_CONV_VARIANT), _p(out),
-               _p(ws), nbytes.value, _stream())
-    elif variant is None:
-        L.call("npvs_sparse_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap, dtype,
-               int(relu), int(out_f32), _p(out), _stream())
-    else:
-        L.call("npvs_sparse_conv_fwd_ex", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap,
-               dtype, int(relu), int(out_f32), int(variant), _p(out), _stream())
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device) if nbytes.value else None
+    L.call("npvs_sparse_conv_fwd", _p(X), cin, _p(Wp), _p(bias), cout, _p(rb.nbr), _p(rb.counts), rb.cap, dtype,
+           int(relu), int(out_f32), int(variant) if variant is not None else -1, _p(out), _p(ws), nbytes.value,
+           _stream())
     return out
 
 
@@ -249,9 +242,9 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
                     wgrad_stream: torch.cuda.Stream | None = None, reduce_stream: torch.cuda.Stream | None = None):
     """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout]).
     dW / db may be given (contiguous float32 device tensors) to receive the gradients in place.
-    With `wgrad_stream`, dW and db are computed on that stream (npvs_sparse_conv_bwd_split), and
-    with `reduce_stream` too their final reductions on that one (npvs_sparse_conv_bwd_split2):
-    the caller keeps X and ws alive and joins the streams before reading dW / db."""
+    With `wgrad_stream`, dW and db are computed on that stream, and with `reduce_stream` too their
+    final reductions on that one: the caller keeps X and ws alive and joins the streams before
+    reading dW / db."""
     if rb.rb_off is None:
         raise ValueError("the backward needs a rulebook built with csr=True")
     dev = X.device
@@ -267,63 +260,11 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
         db = torch.empty(cout, dtype=torch.float32, device=dev)
     if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
         raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
-    args = (_p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off), _p(rb.rb_pairs),
-            _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), ws.numel(), _stream())
-    if wgrad_stream is None:
-        L.call("npvs_sparse_conv_bwd", *args)
-    elif reduce_stream is None:
-        L.call("npvs_sparse_conv_bwd_split", *args, ctypes.c_void_p(wgrad_stream.cuda_stream))
-    else:
-        L.call("npvs_sparse_conv_bwd_split2", *args, ctypes.c_void_p(wgrad_stream.cuda_stream),
-               ctypes.c_void_p(reduce_stream.cuda_stream))
+    side = [ctypes.c_void_p(t.cuda_stream) if t is not None else None for t in (wgrad_stream, reduce_stream)]
+    L.call("npvs_sparse_conv_bwd", _p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off),
+           _p(rb.rb_pairs), _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), ws.numel(),
+           _stream(), side[0], side[1])
     return dX, dW, db
-
-
-def conv_bwd_begin(dY: torch.Tensor, rb: Rulebook, Y: torch.Tensor | None = None, relu: bool = False):
-    """Top of a BF16 backward chain: (dZ bfloat16 [cap][C], dbp float32 [NPVS_BWD_DB_PARTS][C]) from
-    dY float32 [cap][C] (masked by Y > 0 when relu)."""
-    C = dY.shape[1]
-    dY = dY.contiguous()
-    dZ = torch.empty((rb.cap, C), dtype=torch.bfloat16, device=dY.device)
-    dbp = torch.empty((L.NPVS_BWD_DB_PARTS, C), dtype=torch.float32, device=dY.device)
-    L.call("npvs_conv_bwd_begin", _p(dY), _p(Y) if relu else None, C, _p(rb.counts), rb.cap, int(relu), _p(dZ),
-           _p(dbp), _stream())
-    return dZ, dbp
-
-
-def conv_bwd_chain_workspace(cin: int, cout: int, device) -> torch.Tensor:
-    nbytes = ctypes.c_size_t()
-    L.call("npvs_conv_bwd_chain_workspace_size", cin, cout, ctypes.byref(nbytes))
-    return torch.empty(nbytes.value, dtype=torch.uint8, device=device)
-
-
-def sparse_conv_bwd_chain(X, Wt, cin: int, cout: int, dZ, dbp, rb: Rulebook, relu_below: bool = True,
-                          want_below: bool = True, dW: torch.Tensor | None = None, db: torch.Tensor | None = None,
-                          ws: torch.Tensor | None = None, wgrad_stream: torch.cuda.Stream | None = None):
-    """One layer of the BF16 backward chain (npvs_sparse_conv_bwd_chain).  Returns (dZ_below, dbp_below,
-    dW, db); dZ_below / dbp_below are None without want_below.  With `wgrad_stream`, dW and db are
-    computed there: the caller keeps X, dZ, dbp and ws alive and joins it before reading them."""
-    if rb.rb_off is None:
-        raise ValueError("the backward needs a rulebook built with csr=True")
-    dev = X.device
-    if ws is None:
-        ws = conv_bwd_chain_workspace(cin, cout, dev)
-        if wgrad_stream is not None:  # freed here, still read by the side stream
-            ws.record_stream(wgrad_stream)
-    dZb = torch.empty((rb.cap, cin), dtype=torch.bfloat16, device=dev) if want_below else None
-    dbpb = torch.empty((L.NPVS_BWD_DB_PARTS, cin), dtype=torch.float32, device=dev) if want_below else None
-    if dW is None:
-        dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
-    if db is None:
-        db = torch.empty(cout, dtype=torch.float32, device=dev)
-    if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
-        raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
-    s = _stream()
-    s2 = ctypes.c_void_p(wgrad_stream.cuda_stream) if wgrad_stream is not None else s
-    L.call("npvs_sparse_conv_bwd_chain", _p(X), cin, _p(Wt), cout, _p(dZ), _p(dbp), _p(rb.nbr), _p(rb.rb_off),
-           _p(rb.rb_pairs), _p(rb.counts), rb.cap, int(relu_below), _p(dZb), _p(dbpb), _p(dW), _p(db), _p(ws),
-           ws.numel(), s, s2)
-    return dZb, dbpb, dW, db
 
 
 # --------------------------------------------------------------------------------- U-Net levels

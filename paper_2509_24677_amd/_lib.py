@@ -23,7 +23,6 @@ NPVS_CONV_VARIANTS = 15
 NPVS_DEFAULT_CONV_VARIANT = 14
 NPVS_MAX_PACK = 64
 NPVS_MAX_ADAM_PACK = 32
-NPVS_BWD_DB_PARTS = 512
 NPVS_LOSS_BCE = 0
 NPVS_LOSS_DICE = 1
 
@@ -81,17 +80,10 @@ SIGNATURES = {
     "npvs_packed_weight_bytes": (sz, [i32, i32, i32]),
     "npvs_pack_weights": (i32, [P, i32, i32, i32, i32, P, P]),
     "npvs_pack_weights_batch": (i32, [i32, P, i32, P]),
-    "npvs_sparse_conv_fwd": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, P, P]),
-    "npvs_sparse_conv_fwd_ex": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P]),
+    "npvs_sparse_conv_fwd": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P, sz, P]),
     "npvs_conv_fwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
-    "npvs_sparse_conv_fwd_ws": (i32, [P, i32, P, P, i32, P, P, i32, i32, i32, i32, i32, P, P, sz, P]),
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
-    "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P]),
-    "npvs_sparse_conv_bwd_split": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P]),
-    "npvs_sparse_conv_bwd_split2": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P, P]),
-    "npvs_conv_bwd_begin": (i32, [P, P, i32, P, i32, i32, P, P, P]),
-    "npvs_conv_bwd_chain_workspace_size": (i32, [i32, i32, PS]),
-    "npvs_sparse_conv_bwd_chain": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, P, P, P, P, P, sz, P, P]),
+    "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P, P]),
     "npvs_level_maps": (i32, [i32, P, i32, P, P, P, i32, P, P, P, i32, P, P, P]),
     "npvs_packed_weight_bytes_k": (sz, [i32, i32, i32, i32]),
     "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, P, P]),

@@ -547,80 +547,10 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
                                            const float *dY, const int32_t *nbr, const int32_t *rb_off,
                                            const int32_t *rb_pairs, const npvs_counts *counts, int32_t cap_sites,
                                            int32_t dtype, int32_t relu, float *dX, float *dW, float *db, void *ws,
-                                           size_t ws_bytes, void *stream) {
+                                           size_t ws_bytes, void *stream, void *wgrad_stream, void *reduce_stream) {
+  const hipStream_t s = as_stream(stream);
+  const hipStream_t s2 = wgrad_stream ? as_stream(wgrad_stream) : s;
+  const hipStream_t s3 = reduce_stream ? as_stream(reduce_stream) : s2;
   return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
-                  ws_bytes, as_stream(stream), as_stream(stream), as_stream(stream));
-}
-
-extern "C" npvs_status npvs_sparse_conv_bwd_split(const void *X, int32_t cin, const void *Wt, int32_t cout,
-                                                 const void *Y, const float *dY, const int32_t *nbr,
-                                                 const int32_t *rb_off, const int32_t *rb_pairs,
-                                                 const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                                                 int32_t relu, float *dX, float *dW, float *db, void *ws,
-                                                 size_t ws_bytes, void *stream, void *wgrad_stream) {
-  return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
-                  ws_bytes, as_stream(stream), as_stream(wgrad_stream), as_stream(wgrad_stream));
-}
-
-extern "C" npvs_status npvs_sparse_conv_bwd_split2(const void *X, int32_t cin, const void *Wt, int32_t cout,
-                                                  const void *Y, const float *dY, const int32_t *nbr,
-                                                  const int32_t *rb_off, const int32_t *rb_pairs,
-                                                  const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                                                  int32_t relu, float *dX, float *dW, float *db, void *ws,
-                                                  size_t ws_bytes, void *stream, void *wgrad_stream,
-                                                  void *reduce_stream) {
-  return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
-                  ws_bytes, as_stream(stream), as_stream(wgrad_stream), as_stream(reduce_stream));
-}
-
-extern "C" npvs_status npvs_conv_bwd_begin(const float *dY, const void *Y, int32_t cout, const npvs_counts *counts,
-                                          int32_t cap_sites, int32_t relu, void *dZ, float *dbp, void *stream) {
-  if (!dY || !counts || !dZ || !dbp || (relu && !Y)) return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_begin: null pointer");
-  if (cout < 1 || cout > 64 || cout % 4 || cap_sites < 1)
-    return fail(NPVS_ERR_UNSUPPORTED, "npvs_conv_bwd_begin: needs 4 <= cout <= 64, cout % 4 == 0");
-  if ((reinterpret_cast<uintptr_t>(dY) & 15) || (relu && (reinterpret_cast<uintptr_t>(Y) & 15)))
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_begin: dY and Y must be 16-byte aligned");
-  relu_grad_kernel<uint16_t><<<NPVS_BWD_DB_PARTS, 256, 0, as_stream(stream)>>>(
-      (const uint16_t *)Y, dY, counts, cout, relu, 1, nullptr, static_cast<uint16_t *>(dZ), dbp);
-  return check_hip(hipGetLastError(), "npvs_conv_bwd_begin");
-}
-
-// Chain workspace: the float32 slice partials of dW.
-static size_t chain_ws_bytes(int32_t cin, int32_t cout) { return sizeof(float) * 27 * kWgSlices * (size_t)cin * cout; }
-
-extern "C" npvs_status npvs_conv_bwd_chain_workspace_size(int32_t cin, int32_t cout, size_t *bytes) {
-  if (!bytes || cin < 1 || cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_conv_bwd_chain_workspace_size: bad arguments");
-  *bytes = chain_ws_bytes(cin, cout);
-  return NPVS_OK;
-}
-
-extern "C" npvs_status npvs_sparse_conv_bwd_chain(const void *X, int32_t cin, const void *Wt, int32_t cout,
-                                                 const void *dZ, const float *dbp, const int32_t *nbr,
-                                                 const int32_t *rb_off, const int32_t *rb_pairs,
-                                                 const npvs_counts *counts, int32_t cap_sites, int32_t relu_below,
-                                                 void *dZ_below, float *dbp_below, float *dW, float *db, void *ws,
-                                                 size_t ws_bytes, void *stream, void *wgrad_stream) {
-  if (!X || !dZ || !dbp || !nbr || !rb_off || !rb_pairs || !counts || !dW || !db || !ws ||
-      (dZ_below && (!Wt || !dbp_below)))
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd_chain: null pointer");
-  if (cap_sites < 1 || cin < 8 || cout < 8 || cin > 64 || cout > 64 || cin % 8 || cout % 8)
-    return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_bwd_chain: needs cin, cout in [8, 64], multiples of 8");
-  if (ws_bytes < chain_ws_bytes(cin, cout))
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd_chain: workspace too small");
-  const hipStream_t s = as_stream(stream), s2 = as_stream(wgrad_stream);
-  // the side stream joins before the data gradient is enqueued: it waits for dZ only
-  npvs_status st = join_after(s, s2);
-  if (st != NPVS_OK) return st;
-  if (dZ_below) {
-    st = dgrad_relu_fused((const uint16_t *)dZ, cout, Wt, cin, nbr, counts, cap_sites,
-                          relu_below ? (const uint16_t *)X : nullptr, static_cast<uint16_t *>(dZ_below), dbp_below, s);
-    if (st != NPVS_OK) return st;
-  }
-  float *wpart = static_cast<float *>(ws);
-  wgrad_bf16_kernel<<<dim3(kWgSlices, 27), 256, 0, s2>>>((const uint16_t *)X, cin, (const uint16_t *)dZ, cout,
-                                                         rb_off, rb_pairs, wpart);
-  const int nbw = stride_grid(27LL * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s2>>>(wpart, dbp, NPVS_BWD_DB_PARTS, cin, cout, nbw, 27,
-                                                            kWgSlices, dW, db);
-  return check_hip(hipGetLastError(), "npvs_sparse_conv_bwd_chain");
+                  ws_bytes, s, s2, s3);
 }

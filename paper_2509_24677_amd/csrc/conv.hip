@@ -377,35 +377,25 @@ __global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__
 // ------------------------------------------------------------------------------------------
 // BF16 path, weight-stationary, for inputs of at most 96 channels and any number of outputs.
 // Workgroup = 9 waves over the same MB x 16 rows, wave w owning offsets 3w .. 3w + 2;
-// blockIdx.y selects 32 output channels (2 MFMA output blocks).  A wave loads the weight
-// fragments of its 3 offsets x KB chunks x 2 output blocks once (at most 12 fragments) and keeps
-// them in registers while the workgroup walks its row tiles; the next tile's rows and the
-// neighbour indices of the tile after it are loaded during the current tile's products.  The 9
-// partial sums are added in LDS in wave order.
+// blockIdx.y selects 16 NBW output channels (NBW MFMA output blocks).  A wave loads the weight
+// fragments of its 3 offsets x KB chunks x NBW output blocks once and keeps them in registers
+// while the workgroup walks its row tiles; the neighbour indices of the tile after next are
+// loaded during the current tile.  The 9 partial sums are added in LDS in wave order.
 // ------------------------------------------------------------------------------------------
-// With FUSE (the data gradient of a layer, feeding the backward of the layer below): the result
-// is masked by M > 0 (ReLU' of the layer below, whose output M is; no mask when M is null),
-// rounded to bf16 into Y, and each epilogue wave keeps per-lane running sums of its masked values
-// over all the tiles its workgroup walks.  At the end a fixed butterfly adds the 16 rows of each
-// column and the workgroup writes its row of dbp[NPVS_BWD_DB_PARTS][cout] (rows past the grid are
-// written as zeros), so the bias gradient of the layer below is a fixed-order sum over that table.
 // NBW: output blocks of 16 channels per workgroup (2, 4, or 1 for 4 or 5 input chunks).  With
 // two blocks the rows of the next tile are gathered into a second buffer while the current
 // tile's products run; with one or four (whose weights leave no registers for a second buffer)
 // they are gathered into the same buffer as soon as the products have issued, ahead of the
 // reduction and the epilogue.
-template <int KB, int MB, bool FUSE = false, int NBW = 2>
+template <int KB, int MB, int NBW = 2>
 __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
                                                                   const bf16x8_t *__restrict__ Wp,
                                                                   const float *__restrict__ bias, int cout,
                                                                   const int32_t *__restrict__ nbr,
                                                                   const npvs_counts *__restrict__ counts, int cap,
-                                                                  int relu, int out_f32, void *__restrict__ Y,
-                                                                  const uint16_t *__restrict__ M = nullptr,
-                                                                  float *__restrict__ dbp = nullptr) {
+                                                                  int relu, int out_f32, void *__restrict__ Y) {
   constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBLK = MB * NBW;
   constexpr bool PF = NBW == 2;  // rows of the next tile prefetched (the registers of 4 blocks' weights leave no room)
-  static_assert(!FUSE || MB == 1, "the fused data gradient keeps one column block per epilogue wave");
   __shared__ f32x4_t red[KSPLIT * NBLK * 64];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
@@ -423,24 +413,8 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         const int g = nb0 + nb < NBT ? nb0 + nb : NBT - 1;  // blocks past cout: any valid fragment
         aw[q][kb][nb] = Wp[(((int64_t)(kbeg + q) * NBT + g) * KB + kb) * 64 + lane];
       }
-  float da[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // FUSE: this lane's running column sums
-  auto write_db_parts = [&]() {
-    if (wv >= NBLK) return;
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) da[i] += __shfl_xor(da[i], off, 64);
-    const int o = (nb0 + wv) * 16 + 4 * (lane >> 4);
-    if ((lane & 15) == 0 && o < cout)
-      for (int row = blockIdx.x; row < NPVS_BWD_DB_PARTS; row += gridDim.x)
-        *reinterpret_cast<f32x4_t *>(dbp + (int64_t)row * cout + o) =
-            row == (int)blockIdx.x ? f32x4_t{da[0], da[1], da[2], da[3]} : f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-  };
   int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
-  if (tile < 0) {  // whole workgroup: tile depends on blockIdx only
-    if constexpr (FUSE) write_db_parts();
-    return;
-  }
+  if (tile < 0) return;  // whole workgroup: tile depends on blockIdx only
   // Loads retire in order, so a value used right after its load makes every load issued before
   // it wait too.  The neighbour indices are therefore loaded raw (rows past the last site read
   // the last site's entry) and judged only when their rows are gathered, and a gathered row is
@@ -477,7 +451,7 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   };
   // the epilogue block of this wave (at most one: NBLK <= KSPLIT) and its bias
   float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  if constexpr (!FUSE) {
+  {
     const int o = (nb0 + wv % NBW) * 16 + 4 * (lane >> 4);
     if (bias && wv < NBLK && o < cout)
 #pragma unroll
@@ -492,12 +466,6 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   indices(t1 >= 0 ? t1 : tile, ix);
   for (int j = 0; tile >= 0; ++j) {
     const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
-    // FUSE: the epilogue waves fetch this tile's mask now, so its latency hides under the products
-    uint2 mk = {0u, 0u};
-    if constexpr (FUSE) {
-      const int r = tile * ROWS + (lane & 15), o = (nb0 + wv) * 16 + 4 * (lane >> 4);
-      if (M && wv < NBLK && r < n && o < cout) mk = *reinterpret_cast<const uint2 *>(M + (int64_t)r * cout + o);
-    }
     uint4 bn[KPER][KB][MB];
     uint32_t bnm[KPER][MB];
     if constexpr (PF) {
@@ -519,20 +487,17 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
           for (int mb = 0; mb < MB; ++mb)
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], masked(bx[q][kb][mb], bm[q][mb], kb),
                                                                   acc[mb][nb], 0, 0, 0);
-    // Without a second row buffer, the next tile's rows go into this tile's registers as soon as
-    // the products have taken them (the fused data gradient, which holds more registers, waits
-    // until the sums are out in LDS), their latency hidden by the reduction and the epilogue.
-    auto next_rows = [&]() {
+    if constexpr (!PF) {
+      // without a second row buffer, the next tile's rows go into this tile's registers as soon
+      // as the products have taken them, their latency hidden by the reduction and the epilogue
       rows(ix, t1 >= 0 ? t1 : tile, bx, bm);               // tile j + 1 (or a repeat)
       indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
-    };
-    if constexpr (!PF && !FUSE) next_rows();
+    }
     __syncthreads();  // the previous tile's readers are done with red
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) red[(wv * NBLK + mb * NBW + nb) * 64 + lane] = acc[mb][nb];
-    if constexpr (!PF && FUSE) next_rows();
     __syncthreads();
     const int row0 = tile * ROWS;
     for (int blk = wv; blk < NBLK; blk += KSPLIT) {
@@ -541,24 +506,7 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
       for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
       const int mb = blk / NBW, nb = blk % NBW;
       const int r = row0 + mb * 16 + (lane & 15), o = (nb0 + nb) * 16 + 4 * (lane >> 4);
-      if constexpr (FUSE) {
-        if (r < n && o < cout) {
-          float g[4] = {sum[0], sum[1], sum[2], sum[3]};
-          if (M) {
-            const uint16_t mv[4] = {(uint16_t)mk.x, (uint16_t)(mk.x >> 16), (uint16_t)mk.y, (uint16_t)(mk.y >> 16)};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) g[i] = bf16_to_f32(mv[i]) > 0.0f ? g[i] : 0.0f;
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) da[i] += g[i];
-          uint2 h;
-          h.x = (uint32_t)f32_to_bf16(g[0]) | ((uint32_t)f32_to_bf16(g[1]) << 16);
-          h.y = (uint32_t)f32_to_bf16(g[2]) | ((uint32_t)f32_to_bf16(g[3]) << 16);
-          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = h;
-        }
-      } else {
-        conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
-      }
+      conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
     }
     if constexpr (PF) {
 #pragma unroll
@@ -575,7 +523,6 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
     tile = t1;
     t1 = t2;
   }
-  if constexpr (FUSE) write_db_parts();
 }
 
 template <int KB, int NB, int MB, int RG>
@@ -711,39 +658,8 @@ static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float
   G = G < 8 ? 8 : G & ~7;  // a multiple of 8 (one per XCD), rounded down so that all fit at once
   const int most = stride_grid(cap, 16 * MB, 4096);
   if (G > most) G = (most + 7) & ~7;
-  conv_fwd_bf16_wsta_kernel<KB, MB, false, NBW><<<dim3(G, groups), 576, 0, s>>>(
+  conv_fwd_bf16_wsta_kernel<KB, MB, NBW><<<dim3(G, groups), 576, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
-}
-
-// The data gradient of a BF16 layer with the ReLU' mask of the layer below fused in (see the
-// weight-stationary kernel): dZ_below[r][o] = bf16(conv(dZ, Wt)[r][o] if M[r][o] > 0 else 0) for
-// r < n_sites, and the bias partial table dbp.  Requires cin (of the data gradient) <= 64 and
-// cout % 4 == 0.
-npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int cout, const int32_t *nbr,
-                             const npvs_counts *counts, int cap, const uint16_t *M, uint16_t *dZ_below, float *dbp,
-                             hipStream_t s) {
-  if (cin > 64 || cout % 4) return fail(NPVS_ERR_UNSUPPORTED, "dgrad with fused ReLU': unsupported channel counts");
-  const bool all = cout <= 64;  // every output block in one workgroup, as the default forward variant
-  const int groups = all ? 1 : (cout + 31) / 32;
-  int G = (cin <= 32 && !all ? 512 : 256) / groups;
-  G = G < 8 ? 8 : G;
-  const int most = stride_grid(cap, 16, 4096);
-  G = G > most ? most : G;
-  G = (G + 7) & ~7;
-  const bf16x8_t *W = (const bf16x8_t *)Wt;
-  if (cin <= 32 && all)
-    conv_fwd_bf16_wsta_kernel<1, 1, true, 4><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts,
-                                                                             cap, 0, 0, dZ_below, M, dbp);
-  else if (all)
-    conv_fwd_bf16_wsta_kernel<2, 1, true, 4><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts,
-                                                                             cap, 0, 0, dZ_below, M, dbp);
-  else if (cin <= 32)
-    conv_fwd_bf16_wsta_kernel<1, 1, true><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts, cap,
-                                                                          0, 0, dZ_below, M, dbp);
-  else
-    conv_fwd_bf16_wsta_kernel<2, 1, true><<<dim3(G, groups), 576, 0, s>>>(dZ, cin, W, nullptr, cout, nbr, counts, cap,
-                                                                          0, 0, dZ_below, M, dbp);
-  return check_hip(hipGetLastError(), "dgrad with fused ReLU'");
 }
 
 template <int MB>
@@ -944,43 +860,20 @@ extern "C" npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, i
   return NPVS_OK;
 }
 
-extern "C" npvs_status npvs_sparse_conv_fwd_ws(const void *X, int32_t cin, const void *Wp, const float *bias,
-                                              int32_t cout, const int32_t *nbr, const npvs_counts *counts,
-                                              int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32,
-                                              int32_t variant, void *Y, void *ws, size_t ws_bytes, void *stream) {
+extern "C" npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
+                                           int32_t cout, const int32_t *nbr, const npvs_counts *counts,
+                                           int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32,
+                                           int32_t variant, void *Y, void *ws, size_t ws_bytes, void *stream) {
   if (!X || !Wp || !nbr || !counts || !Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: null pointer");
   if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: bad sizes");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: dtype must be NPVS_F32 or NPVS_BF16");
   if (X == Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: X and Y must not alias");
+  if (variant == -1) variant = kDefaultConvVariant;
   if (variant < 0 || variant >= NPVS_CONV_VARIANTS)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: variant out of range");
   const size_t need = conv_fwd_ws_bytes(cin, cout, cap_sites, dtype);
-  if (need && (!ws || ws_bytes < need))
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd_ws: workspace missing or too small");
+  if (ws && ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: workspace too small");
   return conv_fwd_dispatch(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32, Y,
-                           as_stream(stream), variant, ws, ws_bytes);
-}
-
-extern "C" npvs_status npvs_sparse_conv_fwd_ex(const void *X, int32_t cin, const void *Wp, const float *bias,
-                                              int32_t cout, const int32_t *nbr, const npvs_counts *counts,
-                                              int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32,
-                                              int32_t variant, void *Y, void *stream) {
-  if (!X || !Wp || !nbr || !counts || !Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: null pointer");
-  if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: bad sizes");
-  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: dtype must be NPVS_F32 or NPVS_BF16");
-  if (X == Y) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: X and Y must not alias");
-  if (variant < 0 || variant >= NPVS_CONV_VARIANTS)
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_fwd: variant out of range");
-  return conv_fwd_dispatch(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32, Y,
-                           as_stream(stream), variant, nullptr, 0);
-}
-
-extern "C" npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
-                                           int32_t cout, const int32_t *nbr, const npvs_counts *counts,
-                                           int32_t cap_sites, int32_t dtype, int32_t relu, int32_t out_f32, void *Y,
-                                           void *stream) {
-  return npvs_sparse_conv_fwd_ex(X, cin, Wp, bias, cout, nbr, counts, cap_sites, dtype, relu, out_f32,
-                                 kDefaultConvVariant, Y, stream);
+                           as_stream(stream), variant, ws, ws ? ws_bytes : 0);
 }

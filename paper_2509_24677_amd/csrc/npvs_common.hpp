@@ -88,10 +88,6 @@ constexpr int kDefaultConvVariant = NPVS_DEFAULT_CONV_VARIANT;
 npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                               const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
                               int32_t out_f32, void *Y, hipStream_t s, int variant, void *ws, size_t ws_bytes);
-// Data gradient of a BF16 layer with the ReLU' of the layer below fused in (conv.hip).
-npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int cout, const int32_t *nbr,
-                             const npvs_counts *counts, int cap, const uint16_t *M, uint16_t *dZ_below, float *dbp,
-                             hipStream_t s);
 size_t conv_fwd_ws_bytes(int32_t cin, int32_t cout, int32_t cap, int32_t dtype);
 
 // Backward building blocks shared by the submanifold and the strided layers (backward.hip), all

@@ -17,9 +17,9 @@ from __future__ import annotations
 import torch
 
 from . import _lib as L
-from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam_dev, adam_dev_pack, build_rulebook, conv_bwd_begin,
-               conv_bwd_chain_workspace, conv_bwd_workspace, deinterleave_threshold, froxelize, gather_input, loss,
-               pack_weights, pack_weights_batch, sparse_conv_bwd, sparse_conv_bwd_chain, sparse_conv_fwd)
+from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam_dev, adam_dev_pack, build_rulebook, conv_bwd_workspace,
+               deinterleave_threshold, froxelize, gather_input, loss, pack_weights, pack_weights_batch, sparse_conv_bwd,
+               sparse_conv_fwd)
 
 
 class Network:
@@ -127,34 +127,18 @@ class Network:
             X = self.layer(i, X, rb)
         return X, saved
 
-    def chainable(self) -> bool:
-        """BF16 stacks whose layers all have 8..64 channels (multiples of 8) take the chained
-        backward, where each ReLU' is fused into the data gradient of the layer above."""
-        return self.dtype == NPVS_BF16 and all(8 <= c <= 64 and c % 8 == 0 for c in self.channels)
-
-    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True,
-                 fused: bool | None = None):
+    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True):
         """Hand-written backward through the stack; recomputes the layer inputs that were not
         saved.  With `overlap`, each layer's weight gradient runs on a side stream while the data
         gradient continues down the stack (their final reductions on a third stream, beside the
         next weight gradient); the side streams are joined before returning.  The
-        gradients land in the flat gradient buffer; returns [(dW, db)] per layer (views of it).
-        With `fused` (and a chainable stack) the layers are chained through bfloat16 dZ with the
-        ReLU' fused into the data gradients; otherwise each layer forms its own dZ in a small
-        kernel.  By default the chain is taken on one stream only: the data- and weight-gradient
-        kernels cannot share a compute unit (registers), so with a side stream the small dZ
-        kernels of the per-layer form are what runs beside the weight gradients, and that form
-        is the faster one there."""
-        if fused is None:
-            fused = not overlap
+        gradients land in the flat gradient buffer; returns [(dW, db)] per layer (views of it)."""
         main = torch.cuda.current_stream()
         side = side2 = None
         if overlap:
             if getattr(self, "_side", None) is None:
                 self._side, self._side2 = torch.cuda.Stream(), torch.cuda.Stream()
             side, side2 = self._side, self._side2
-        if fused and self.chainable():
-            return self._backward_chain(saved, dlogits, rb, main, side)
         grads = [None] * self.n_layers
         outputs = {self.n_layers - 1: logits}
         in_use = []  # tensors the side stream reads: alive until it is joined
@@ -179,37 +163,6 @@ class Network:
         if side is not None:
             main.wait_stream(side)
             main.wait_stream(side2)
-        del in_use
-        return grads
-
-    def _chain_ws(self, device):
-        """One workspace for every layer of the chain: their weight gradients run one after
-        another on one stream."""
-        ws = getattr(self, "_ws_chain", None)
-        if ws is None:
-            biggest = max(zip(self.channels[:-1], self.channels[1:]), key=lambda c: c[0] * c[1])
-            ws = self._ws_chain = conv_bwd_chain_workspace(biggest[0], biggest[1], device)
-        return ws
-
-    def _backward_chain(self, saved, dlogits, rb, main, side):
-        grads = [None] * self.n_layers
-        top = self.n_layers - 1
-        dZ, dbp = conv_bwd_begin(dlogits, rb)  # the last layer has no ReLU
-        in_use = []  # tensors the side stream reads: alive until it is joined
-        for i in range(top, -1, -1):
-            X = saved.get(i)
-            if X is None:  # recompute this layer's input from the previous saved one
-                X = self.layer(i - 1, saved[i - 1], rb)
-            cin, cout = self.channels[i], self.channels[i + 1]
-            ws = self._chain_ws(X.device)
-            dZb, dbpb, dW, db = sparse_conv_bwd_chain(X, self.Wt[i], cin, cout, dZ, dbp, rb, relu_below=True,
-                                                      want_below=i > 0, dW=self.gW[i], db=self.gb[i], ws=ws,
-                                                      wgrad_stream=side)
-            in_use += [X, dZ, dbp, ws]
-            grads[i] = (dW, db)
-            dZ, dbp = dZb, dbpb
-        if side is not None:
-            main.wait_stream(side)
         del in_use
         return grads
 

@@ -36,7 +36,7 @@ def test_version_and_sizes(lib):
 def test_header_constants_match_binding():
     text = open(L.HEADER).read()
     for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT",
-                 "NPVS_BWD_DB_PARTS", "NPVS_LOSS_BCE", "NPVS_LOSS_DICE", "NPVS_MAX_ADAM_PACK"):
+                 "NPVS_LOSS_BCE", "NPVS_LOSS_DICE", "NPVS_MAX_ADAM_PACK"):
         assert f"#define {name} {getattr(L, name)}" in text, name
     assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16 and ctypes.sizeof(L.AdamPackDesc) == 32
     assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes
@@ -49,10 +49,27 @@ def test_conv_workspace_sizes_and_checks(lib):
     for cin, cout, dt in ((64, 64, L.NPVS_BF16), (512, 64, L.NPVS_BF16), (4096, 64, L.NPVS_F32)):
         L.call("npvs_conv_fwd_workspace_size", cin, cout, 1000, dt, ctypes.byref(n))
         assert n.value == 0
-    fake = ctypes.c_void_p(16)  # never dereferenced: the argument check answers first
-    st = lib.npvs_sparse_conv_fwd_ws(fake, 4096, fake, None, 64, fake, fake, 1000, L.NPVS_BF16, 1, 0, 0,
-                                     ctypes.c_void_p(32), None, 0, None)
-    assert st == L.NPVS_ERR_INVALID_ARG and b"workspace" in lib.npvs_last_error()
+    fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
+
+    def fwd(variant=-1, ws=None, ws_bytes=0, cin=4096):
+        return lib.npvs_sparse_conv_fwd(fake, cin, fake, None, 64, fake, fake, 1000, L.NPVS_BF16, 1, 0, variant,
+                                        ctypes.c_void_p(32), ws, ws_bytes, None)
+
+    # a workspace given, but smaller than the split needs
+    assert fwd(ws=fake, ws_bytes=16) == L.NPVS_ERR_INVALID_ARG and b"workspace" in lib.npvs_last_error()
+    for v in (-2, L.NPVS_CONV_VARIANTS):
+        assert fwd(variant=v) == L.NPVS_ERR_INVALID_ARG and b"variant" in lib.npvs_last_error()
+    assert lib.npvs_sparse_conv_fwd(fake, 64, fake, None, 64, fake, fake, 1000, L.NPVS_BF16, 1, 0, -1, fake, None, 0,
+                                    None) == L.NPVS_ERR_INVALID_ARG  # X aliases Y
+    L.call("npvs_conv_bwd_workspace_size", 64, 64, 1000, L.NPVS_BF16, ctypes.byref(n))
+    bwd = [fake, 64, fake, 64, fake, fake, fake, fake, fake, fake, 1000, L.NPVS_BF16, 1, fake, fake, fake, fake,
+           n.value, None, None, None]
+    bad = list(bwd)
+    bad[17] = n.value - 1
+    assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_INVALID_ARG and b"workspace" in lib.npvs_last_error()
+    bad = list(bwd)
+    bad[1] = 60  # BF16 needs multiples of 8
+    assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_UNSUPPORTED
 
 
 def test_batched_packing_argument_checks(lib):
@@ -82,28 +99,6 @@ def test_adam_pack_argument_checks(lib):
     assert call([L.AdamPackDesc(0, 4, 4, 0x2000, None)]) == L.NPVS_ERR_INVALID_ARG
 
 
-def test_backward_chain_argument_checks(lib):
-    n = ctypes.c_size_t()
-    L.call("npvs_conv_bwd_chain_workspace_size", 32, 64, ctypes.byref(n))
-    assert n.value == 27 * 16 * 32 * 64 * 4  # float32 weight-gradient slices of every offset
-    fake = ctypes.c_void_p(256)  # never dereferenced: the argument checks answer first
-    args = [fake, 32, fake, 64, fake, fake, fake, fake, fake, fake, 1000, 1, fake, fake, fake, fake, fake, n.value,
-            None, None]
-    bad = list(args)
-    bad[1] = 96  # cin > 64
-    assert lib.npvs_sparse_conv_bwd_chain(*bad) == L.NPVS_ERR_UNSUPPORTED
-    bad = list(args)
-    bad[17] = n.value - 1
-    assert lib.npvs_sparse_conv_bwd_chain(*bad) == L.NPVS_ERR_INVALID_ARG and b"workspace" in lib.npvs_last_error()
-    bad = list(args)
-    bad[13] = None  # dZ_below given without dbp_below
-    assert lib.npvs_sparse_conv_bwd_chain(*bad) == L.NPVS_ERR_INVALID_ARG
-    assert lib.npvs_conv_bwd_begin(fake, None, 64, fake, 1000, 1, fake, fake, None) == L.NPVS_ERR_INVALID_ARG
-    assert lib.npvs_conv_bwd_begin(fake, fake, 66, fake, 1000, 0, fake, fake, None) == L.NPVS_ERR_UNSUPPORTED
-    assert lib.npvs_conv_bwd_begin(ctypes.c_void_p(260), None, 64, fake, 1000, 0, fake, fake, None) == \
-        L.NPVS_ERR_INVALID_ARG
-
-
 @pytest.mark.parametrize("dims,d,msg", [
     ([(250, 256, 128)], 4, "multiple of 8"),
     ([(256, 256, 126)], 4, "multiples of d"),
@@ -124,7 +119,7 @@ def test_too_many_grids_and_null_pointers(lib):
     one = L.dims_array([(64, 64, 64)])
     st = lib.npvs_froxelize(None, L.i64_array([1]), 1, one, None, None, None, 0, None)
     assert st == L.NPVS_ERR_INVALID_ARG
-    st = lib.npvs_sparse_conv_fwd(None, 64, None, None, 64, None, None, 10, 0, 1, 0, None, None)
+    st = lib.npvs_sparse_conv_fwd(None, 64, None, None, 64, None, None, 10, 0, 1, 0, -1, None, None, 0, None)
     assert st == L.NPVS_ERR_INVALID_ARG
     st = lib.npvs_build_rulebook(ctypes.c_void_p(16), 1, one, 4, 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
                                  ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
@@ -141,7 +136,8 @@ def test_workspace_too_small_is_rejected(lib):
 
 def test_unsupported_bf16_shape_reported(lib):
     p = ctypes.c_void_p(256)
-    st = lib.npvs_sparse_conv_fwd(p, 12, p, None, 64, p, p, 10, L.NPVS_BF16, 1, 0, ctypes.c_void_p(512), None)
+    st = lib.npvs_sparse_conv_fwd(p, 12, p, None, 64, p, p, 10, L.NPVS_BF16, 1, 0, -1, ctypes.c_void_p(512), None, 0,
+                                  None)
     assert st == L.NPVS_ERR_UNSUPPORTED
 
 

@@ -56,31 +56,6 @@ def _gpu_backward(acts, rb, layers, dtype, dlogits, dx_out=None):
     return grads
 
 
-def _chain_backward(acts, rb, layers, dlogits, side=None):
-    """The BF16 backward as a chain (ReLU' fused into each data gradient): per layer (dW, db,
-    dZ of the layer below as bfloat16 bit patterns or None)."""
-    out, keep = [None] * len(layers), []
-    dZ, dbp = npvs.conv_bwd_begin(dlogits, rb)
-    for li in range(len(layers) - 1, -1, -1):
-        W, _ = layers[li]
-        Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_BF16, flip_transpose=True)
-        dZb, dbpb, dW, db = npvs.sparse_conv_bwd_chain(acts[li], Wt, W.shape[1], W.shape[2], dZ, dbp, rb,
-                                                       want_below=li > 0, wgrad_stream=side)
-        keep += [Wt, dZ, dbp]
-        out[li] = (dW, db, dZb)
-        dZ, dbp = dZb, dbpb
-    if side is not None:
-        torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    return [(to_np(a), to_np(b), None if z is None else to_np(z.view(torch.int16)).view(np.uint16)) for a, b, z in out]
-
-
-def _bf16_bits(a):
-    """float32 -> bfloat16 bit patterns, round to nearest even (finite values)."""
-    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
-    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
-
-
 def _loss_inputs(seed):
     """One tiny32 grid's rulebook and seeded logits and labels (the same arrays on both sides)."""
     cfg, t, layers, occ, rb, lab_bits = _setup()
@@ -243,42 +218,31 @@ def test_backward_bf16_within_rigorous_bounds_and_deterministic():
             assert np.all(e <= bnd[li][j]), (li, nm)
 
 
-def test_backward_chain_equals_per_layer_backward():
-    """The chained BF16 backward (ReLU' fused into the data gradient of the layer above) forms the
-    same bfloat16 dZ and the same dW bit for bit as the per-layer backward; db is the same float32
-    sum in another order (checked against the FP64 sum of the same float32 terms)."""
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_backward_side_streams_change_nothing(dtype):
+    """npvs_sparse_conv_bwd with the weight gradient on a second stream and its reductions on a
+    third gives the single-stream dX, dW and db bit for bit."""
     cfg, t, layers, occ, rb, lab_bits = _setup()
-    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_BF16)
+    acts = _gpu_forward(occ, rb, layers, dtype)
     labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
     _, dl = npvs.loss(acts[-1], labels, rb)
-    dx = {}
-    ref = _gpu_backward(acts, rb, layers, npvs.NPVS_BF16, dl, dx_out=dx)
-    got = _chain_backward(acts, rb, layers, dl)
-    side = torch.cuda.Stream()
-    got2 = _chain_backward(acts, rb, layers, dl, side=side)
+    side, side2 = torch.cuda.Stream(), torch.cuda.Stream()
+    W, _ = layers[-1]
+    Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), dtype, flip_transpose=True)
+    args = (acts[-2], Wt, W.shape[1], W.shape[2], acts[-1], dl, rb, dtype, False)
     n = rb.host_counts()["n_sites"]
-    assert n > 100
-    top = len(layers) - 1
-    for li in range(top, -1, -1):
-        np.testing.assert_array_equal(got[li][0], ref[li][0])
-        # dZ of layer li as float32 terms: dlogits at the top, else dX of the layer above, masked
-        dz = to_np(dl)[:n] if li == top else np.where(to_np(acts[li + 1].float())[:n] > 0, dx[li + 1][:n], 0.0)
-        exact = dz.astype(np.float64).sum(0)
-        bound = 1e-5 * np.abs(dz).astype(np.float64).sum(0) + 1e-30
-        assert (np.abs(got[li][1] - exact) <= bound).all(), li
-        assert (np.abs(ref[li][1] - exact) <= bound).all(), li
-        if li > 0:
-            mask = to_np(acts[li].float())[:n] > 0
-            # ReLU'(z) selects the gradient or +0 (a product with the mask would give -0)
-            np.testing.assert_array_equal(got[li][2][:n], _bf16_bits(np.where(mask, dx[li][:n], np.float32(0))))
-        # the side stream changes nothing
-        np.testing.assert_array_equal(got2[li][0], got[li][0])
-        np.testing.assert_array_equal(got2[li][1], got[li][1])
-        if li > 0:
-            np.testing.assert_array_equal(got2[li][2][:n], got[li][2][:n])
+    ref = npvs.sparse_conv_bwd(*args)
+    for ws, rs in ((side, None), (side, side2)):
+        got = npvs.sparse_conv_bwd(*args, wgrad_stream=ws, reduce_stream=rs)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.current_stream().wait_stream(side2)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(ref[0])[:n], to_np(got[0])[:n])  # rows past n_sites: undefined
+        for a, b in zip(ref[1:], got[1:]):
+            np.testing.assert_array_equal(to_np(a), to_np(b))
 
 
-def test_backward_chain_on_an_empty_grid_is_zero():
+def test_backward_on_an_empty_grid_is_zero():
     cfg = synth.config("tiny32")
     layers = synth.net_layers(cfg, bias_std=0.05)
     tris, counts = upload_tris([np.zeros((0, 3, 3), np.float32)])
@@ -287,7 +251,7 @@ def test_backward_chain_on_an_empty_grid_is_zero():
     assert rb.host_counts()["n_sites"] == 0
     acts = _gpu_forward(occ, rb, layers, npvs.NPVS_BF16)
     dl = torch.zeros((rb.cap, cfg.channels[-1]), dtype=torch.float32, device=DEV)
-    for dW, db, _ in _chain_backward(acts, rb, layers, dl):
+    for dW, db in _gpu_backward(acts, rb, layers, npvs.NPVS_BF16, dl):
         assert not dW.any() and not db.any()
 
 
