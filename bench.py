@@ -64,9 +64,9 @@ def conv_traffic(variant):
     elif variant in lds:
         name = f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>"
     elif variant == 14:
-        name = "conv_fwd_bf16_wsta_kernel<2, 1, false, 4>"
+        name = "conv_fwd_bf16_wsta_kernel<2, 1, 4>"
     else:
-        name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}, false, 2>"
+        name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}, 2>"
     for line in text.splitlines():
         if line.startswith("## batch16"):  # the first table is the city256 one
             break
@@ -918,7 +918,7 @@ def main():
         rb16 = npvs.build_rulebook(occ16, c16.grids, c16.d)
         h16 = net_b.layer(0, npvs.gather_input(occ16, rb16, npvs.NPVS_BF16), rb16)
         o16 = torch.empty_like(h16)
-        for v in (9, 12, 3, 0):
+        for v in (14, 9, 12, 3, 0):
             for _ in range(5):
                 npvs.sparse_conv_fwd(h16, net_b.Wp[1], net_b.b[1], 64, 64, rb16, npvs.NPVS_BF16, True, out=o16,
                                      variant=v)

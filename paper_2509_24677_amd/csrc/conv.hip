@@ -430,14 +430,15 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         ix[q][mb] = nbr[(int64_t)(kbeg + q) * cap + (r < n ? r : n - 1)];
       }
   };
-  // rows of tile t, whose raw indices ix holds
-  auto rows = [&](const int (&ix)[KPER][MB], int t, uint4 (&b)[KPER][KB][MB], uint32_t (&m)[KPER][MB]) {
+  // rows of tile t, whose raw indices ix holds; bit q MB + mb of m marks a row that exists
+  auto rows = [&](const int (&ix)[KPER][MB], int t, uint4 (&b)[KPER][KB][MB], uint32_t &m) {
+    m = 0u;
 #pragma unroll
     for (int q = 0; q < KPER; ++q)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const bool ok = t * ROWS + mb * 16 + (lane & 15) < n && ix[q][mb] >= 0;
-        m[q][mb] = ok ? ~0u : 0u;
+        m |= (ok ? 1u : 0u) << (q * MB + mb);
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           const int c = kb * 32 + csub;
@@ -445,13 +446,26 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         }
       }
   };
-  auto masked = [&](const uint4 &v, uint32_t m, int kb) {
-    const uint32_t mm = kb * 32 + csub < cin ? m : 0u;
-    return __builtin_bit_cast(bf16x8_t, make_uint4(v.x & mm, v.y & mm, v.z & mm, v.w & mm));
+  auto masked = [&](const uint4 &v, uint32_t m, int bit, int kb) {
+    const uint32_t mm = ((m >> bit) & 1u) && kb * 32 + csub < cin ? ~0u : 0u;
+    return make_uint4(v.x & mm, v.y & mm, v.z & mm, v.w & mm);
   };
-  // the epilogue block of this wave (at most one: NBLK <= KSPLIT) and its bias
+  // with a second buffer, rows are masked when they become the current tile's (a whole tile after
+  // their loads were issued), so the current buffer needs no mask word
+  auto mask_all = [&](const uint4 (&src)[KPER][KB][MB], uint32_t m, uint4 (&dst)[KPER][KB][MB]) {
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) dst[q][kb][mb] = masked(src[q][kb][mb], m, q * MB + mb, kb);
+  };
+  // the epilogue block of this wave (at most one: NBLK <= KSPLIT) and its bias, loaded once
+  // (except with two 16-row blocks and a second row buffer, whose registers leave no room: there
+  // the epilogue loads it, after this tile's loads and before the next tile's are needed)
+  constexpr bool BIAS_ONCE = !(PF && MB == 2);
   float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  {
+  if constexpr (BIAS_ONCE) {
     const int o = (nb0 + wv % NBW) * 16 + 4 * (lane >> 4);
     if (bias && wv < NBLK && o < cout)
 #pragma unroll
@@ -459,15 +473,16 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   }
   int ix[KPER][MB];
   uint4 bx[KPER][KB][MB];
-  uint32_t bm[KPER][MB];
+  uint32_t bm;
   indices(tile, ix);
   rows(ix, tile, bx, bm);
+  if constexpr (PF) mask_all(bx, bm, bx);
   int t1 = xcd_tile(blockIdx.x, gridDim.x, ntiles, 1);
   indices(t1 >= 0 ? t1 : tile, ix);
   for (int j = 0; tile >= 0; ++j) {
     const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
     uint4 bn[KPER][KB][MB];
-    uint32_t bnm[KPER][MB];
+    uint32_t bnm;
     if constexpr (PF) {
       rows(ix, t1 >= 0 ? t1 : tile, bn, bnm);              // tile j + 1 (or a repeat)
       indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
@@ -484,9 +499,11 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb)
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], masked(bx[q][kb][mb], bm[q][mb], kb),
+          for (int mb = 0; mb < MB; ++mb) {
+            const uint4 row = PF ? bx[q][kb][mb] : masked(bx[q][kb][mb], bm, q * MB + mb, kb);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], __builtin_bit_cast(bf16x8_t, row),
                                                                   acc[mb][nb], 0, 0, 0);
+          }
     if constexpr (!PF) {
       // without a second row buffer, the next tile's rows go into this tile's registers as soon
       // as the products have taken them, their latency hidden by the reduction and the epilogue
@@ -506,19 +523,11 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
       for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
       const int mb = blk / NBW, nb = blk % NBW;
       const int r = row0 + mb * 16 + (lane & 15), o = (nb0 + nb) * 16 + 4 * (lane >> 4);
-      conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
+      if constexpr (BIAS_ONCE) conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
+      else conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
     }
     if constexpr (PF) {
-#pragma unroll
-      for (int q = 0; q < KPER; ++q)
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) bx[q][kb][mb] = bn[q][kb][mb];
-#pragma unroll
-      for (int q = 0; q < KPER; ++q)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) bm[q][mb] = bnm[q][mb];
+      mask_all(bn, bnm, bx);
     }
     tile = t1;
     t1 = t2;
