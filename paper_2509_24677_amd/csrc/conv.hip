@@ -77,10 +77,14 @@ __global__ void pack_batch_kernel(PackBatch PB, int dtype) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Plain FP32 path (vector FMA).  Workgroup of 256 = 4 waves; a tile of 32 output rows; lane =
-// output channel of a 64-channel group; each wave owns 8 rows.  For each offset the tile's 32
-// neighbour rows are staged through LDS 64 input channels at a time; every lane reads them as
-// broadcasts and its weight column with a coalesced load.
+// Plain FP32 path (vector FMA).  Workgroup of 256 = 4 waves; a tile of 32 output rows; blockIdx.y
+// selects 64 output channels; lane = output channel, each wave owns 8 rows.  A tile is a
+// sequence of steps (offset k, 64-channel input chunk c0): the step's 32 gathered rows and its
+// 64 x 64 weight block go through LDS, every lane reading the rows as broadcasts and its weight
+// column without conflicts.  The loads of step s + 1 are issued into registers before the
+// products of step s, and the neighbour indices of offset k + 2 when offset k begins, so a step
+// waits for memory only when its products are shorter than a load.  The products run in the
+// order (offset, channel) for every output, so the result does not depend on the launch shape.
 // ------------------------------------------------------------------------------------------
 constexpr int kF32Rows = 32;
 
@@ -90,63 +94,85 @@ __global__ __launch_bounds__(256) void conv_fwd_f32_kernel(const float *__restri
                                                             const int32_t *__restrict__ nbr,
                                                             const npvs_counts *__restrict__ counts, int cap, int relu,
                                                             float *__restrict__ Y) {
-  __shared__ float Xs[kF32Rows][64];
-  __shared__ int idx_s[kF32Rows];
+  __shared__ __align__(16) float Xs[kF32Rows][64];
+  __shared__ __align__(16) float Ws[64][64];
+  __shared__ int idx_s[2][kF32Rows];  // neighbour indices of offsets k (slot k % 2)
   const int32_t n = counts->n_sites;
   const int ntiles = (n + kF32Rows - 1) / kF32Rows;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
+  const int cg = 64 * blockIdx.y, o = cg + lane;
+  const int CB = (cin + 63) / 64, S = 27 * CB;  // steps per tile
   for (int j = 0;; ++j) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, j);
     if (tile < 0) break;
     const int row0 = tile * kF32Rows;
-    for (int cg = 0; cg < cout; cg += 64) {
-      const int o = cg + lane;
-      float acc[8];
+    auto idx_load = [&](int k) {
+      return tid < kF32Rows && row0 + tid < n ? nbr[(int64_t)k * cap + row0 + tid] : -1;
+    };
+    float xr[8], wr[16];
+    auto load_step = [&](int s) {  // step s's rows (through the indices in LDS) and weights
+      const int k = s / CB, c0 = (s - k * CB) * 64;
+      const int *ids = idx_s[k & 1];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
-      for (int k = 0; k < 27; ++k) {
-        __syncthreads();
-        if (tid < kF32Rows) idx_s[tid] = row0 + tid < n ? nbr[(int64_t)k * cap + row0 + tid] : -1;
-        __syncthreads();
-        if (!__syncthreads_or(idx_s[tid & (kF32Rows - 1)] >= 0)) continue;
-        for (int c0 = 0; c0 < cin; c0 += 64) {
-          for (int e = tid; e < kF32Rows * 64; e += 256) {
-            int r = e >> 6, c = e & 63;
-            int src = idx_s[r];
-            Xs[r][c] = (src >= 0 && c0 + c < cin) ? X[(int64_t)src * cin + c0 + c] : 0.0f;
-          }
-          __syncthreads();
-          const int cn = cin - c0 < 64 ? cin - c0 : 64;
-          if (o < cout) {
-            const float *wp = P + ((int64_t)k * cin + c0) * cout + o;
-            for (int c = 0; c < cn; c += 4) {
-              float w0 = wp[(int64_t)c * cout];
-              float w1 = c + 1 < cn ? wp[(int64_t)(c + 1) * cout] : 0.0f;
-              float w2 = c + 2 < cn ? wp[(int64_t)(c + 2) * cout] : 0.0f;
-              float w3 = c + 3 < cn ? wp[(int64_t)(c + 3) * cout] : 0.0f;
-#pragma unroll
-              for (int i = 0; i < 8; ++i) {
-                const float4 xv = *reinterpret_cast<const float4 *>(&Xs[wv * 8 + i][c]);
-                acc[i] = fmaf(xv.x, w0, acc[i]);
-                acc[i] = fmaf(xv.y, w1, acc[i]);
-                acc[i] = fmaf(xv.z, w2, acc[i]);
-                acc[i] = fmaf(xv.w, w3, acc[i]);
-              }
-            }
-          }
-          __syncthreads();
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u, r = e >> 6, c = c0 + (e & 63), src = ids[r];
+        xr[u] = src >= 0 && c < cin ? X[(int64_t)src * cin + c] : 0.0f;
       }
-      if (o < cout) {
-        const float bo = bias ? bias[o] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, c = c0 + (e >> 6), oo = cg + (e & 63);
+        wr[u] = c < cin && oo < cout ? P[((int64_t)k * cin + c) * cout + oo] : 0.0f;
+      }
+    };
+    auto store_step = [&]() {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Xs[(tid + 256 * u) >> 6][tid & 63] = xr[u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) Ws[(tid + 256 * u) >> 6][tid & 63] = wr[u];
+    };
+    if (tid < kF32Rows) {
+      idx_s[0][tid] = idx_load(0);
+      idx_s[1][tid] = idx_load(1);
+    }
+    __syncthreads();
+    load_step(0);
+    store_step();
+    __syncthreads();
+    float acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+    int ni = -1;  // indices of offset k + 2, loaded when offset k begins
+    for (int s = 0; s < S; ++s) {
+      const int k = s / CB, cb = s - k * CB, c0 = cb * 64;
+      if (cb == 0 && k + 2 < 27) ni = idx_load(k + 2);
+      if (s + 1 < S) load_step(s + 1);
+      const int cn = ((cin - c0 < 64 ? cin - c0 : 64) + 3) & ~3;  // entries past cin are zero
+      for (int c = 0; c < cn; c += 4) {
+        const float w0 = Ws[c][lane], w1 = Ws[c + 1][lane], w2 = Ws[c + 2][lane], w3 = Ws[c + 3][lane];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          int r = row0 + wv * 8 + i;
-          if (r < n) {
-            float v = acc[i] + bo;
-            Y[(int64_t)r * cout + o] = (relu && v < 0.0f) ? 0.0f : v;
-          }
+          const float4 xv = *reinterpret_cast<const float4 *>(&Xs[wv * 8 + i][c]);
+          acc[i] = fmaf(xv.x, w0, acc[i]);
+          acc[i] = fmaf(xv.y, w1, acc[i]);
+          acc[i] = fmaf(xv.z, w2, acc[i]);
+          acc[i] = fmaf(xv.w, w3, acc[i]);
+        }
+      }
+      __syncthreads();  // the products of step s are done with Xs and Ws
+      if (s + 1 < S) store_step();
+      // offset k's indices were last read by the loads of its last step, issued during step s
+      if (cb == CB - 1 && k + 2 < 27 && tid < kF32Rows) idx_s[k & 1][tid] = ni;
+      __syncthreads();
+    }
+    if (o < cout) {
+      const float bo = bias ? bias[o] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = row0 + wv * 8 + i;
+        if (r < n) {
+          const float v = acc[i] + bo;
+          Y[(int64_t)r * cout + o] = (relu && v < 0.0f) ? 0.0f : v;
         }
       }
     }
@@ -788,10 +814,13 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
                               const int32_t *nbr, const npvs_counts *counts, int32_t cap, int32_t dtype, int32_t relu,
                               int32_t out_f32, void *Y, hipStream_t s, int variant, void *ws, size_t ws_bytes) {
   if (dtype == NPVS_F32) {
+    const int groups = (cout + 63) / 64;
     int G = stride_grid(cap, kF32Rows, 2048);
-    G = (G + 7) & ~7;
-    conv_fwd_f32_kernel<<<G, 256, 0, s>>>((const float *)X, cin, (const float *)Wp, bias, cout, nbr, counts, cap, relu,
-                                          (float *)Y);
+    const int most = 8192 / groups;  // workgroups over all output groups, at most about 8192
+    if (G > most) G = most;
+    G = G < 8 ? 8 : (G + 7) & ~7;
+    conv_fwd_f32_kernel<<<dim3(G, groups), 256, 0, s>>>((const float *)X, cin, (const float *)Wp, bias, cout, nbr,
+                                                         counts, cap, relu, (float *)Y);
     return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
   }
   if (cin % 8 || cout % 8)
