@@ -127,52 +127,117 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
                                                              const int32_t *__restrict__ rb_off,
                                                              const int32_t *__restrict__ pairs,
                                                              float *__restrict__ part) {
-  __shared__ float Xs[kWgPairs][65];
+  __shared__ __align__(16) float Xs[kWgPairs][64];
   __shared__ float Gs[kWgPairs][64];
-  __shared__ int in_s[kWgPairs], out_s[kWgPairs];
+  __shared__ int in_s[2][kWgPairs], out_s[2][kWgPairs];  // pair indices of steps t (slot t % 2)
   const int k = blockIdx.y, s = blockIdx.x, S = gridDim.x, tid = threadIdx.x;
   const int o0 = 64 * blockIdx.z, ow = cout - o0 < 64 ? cout - o0 : 64;
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
   const int64_t p0 = pk0 + pk * s / S, p1 = pk0 + pk * (s + 1) / S;
+  const int nsteps = (int)((p1 - p0 + kWgPairs - 1) / kWgPairs);
   const int cw = (256 * kWgEPT) / ow < 64 ? (256 * kWgEPT) / ow : 64;  // channels of X per pass
+  // the dW entries of this thread: with a full 64 x 64 window, channels 16 (tid / 64) + j of
+  // output tid % 64 (the channels read as four broadcast float4 per pair); otherwise (c, o) of
+  // e = tid + 256 j
+  const bool block = ow == 64 && cin % 64 == 0;
+  const int bc0 = 16 * (tid >> 6), bo = tid & 63;
   for (int cbase = 0; cbase < cin; cbase += cw) {
     const int cn = cin - cbase < cw ? cin - cbase : cw;
     const int e_pass = cn * ow;
     Comp acc[kWgEPT];
 #pragma unroll
     for (int j = 0; j < kWgEPT; ++j) acc[j] = Comp{0.0f, 0.0f};
-    for (int64_t pb = p0; pb < p1; pb += kWgPairs) {
-      const int m = p1 - pb < kWgPairs ? (int)(p1 - pb) : kWgPairs;
-      __syncthreads();
-      if (tid < kWgPairs) {
-        in_s[tid] = tid < m ? pairs[2 * (pb + tid)] : -1;
-        out_s[tid] = tid < m ? pairs[2 * (pb + tid) + 1] : -1;
-      }
-      __syncthreads();
-      for (int e = tid; e < kWgPairs * 64; e += 256) {
-        int p = e >> 6, c = e & 63;
-        Xs[p][c] = (p < m && c < cn && in_s[p] >= 0) ? load_as_f32(X, (int64_t)in_s[p] * cin + cbase + c) : 0.0f;
-        Gs[p][c] = (p < m && c < ow && out_s[p] >= 0) ? dZ[(int64_t)out_s[p] * cout + o0 + c] : 0.0f;
-      }
-      __syncthreads();
+    // Step t stages pairs [p0 + 32 t, ..) in LDS.  The pair indices of step t + 2 are loaded
+    // into registers during step t and the rows of step t + 1 too, so a step waits for memory
+    // only where its products are shorter than a load.  Products and additions keep the order
+    // (step, pair).
+    auto pair_idx = [&](int t, int &vi, int &vo) {
+      const int64_t pb = p0 + (int64_t)t * kWgPairs;
+      const bool ok = tid < kWgPairs && t < nsteps && pb + tid < p1;
+      vi = ok ? pairs[2 * (pb + tid)] : -1;
+      vo = ok ? pairs[2 * (pb + tid) + 1] : -1;
+    };
+    float xr[8], gr[8];
+    auto load_rows = [&](int t) {  // through the indices of step t in LDS
+      const int *is = in_s[t & 1], *os = out_s[t & 1];
 #pragma unroll
-      for (int j = 0; j < kWgEPT; ++j) {
-        const int e = tid + 256 * j;
-        if (e < e_pass) {
-          const int c = e / ow, o = e % ow;
-          float t = 0.0f;
-          for (int p = 0; p < m; ++p) t = fmaf(Xs[p][c], Gs[p][o], t);
-          acc[j].add(t);
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u, p = e >> 6, c = e & 63, ii = is[p], io = os[p];
+        xr[u] = (c < cn && ii >= 0) ? load_as_f32(X, (int64_t)ii * cin + cbase + c) : 0.0f;
+        gr[u] = (c < ow && io >= 0) ? dZ[(int64_t)io * cout + o0 + c] : 0.0f;
+      }
+    };
+    auto store_rows = [&]() {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u;
+        Xs[e >> 6][e & 63] = xr[u];
+        Gs[e >> 6][e & 63] = gr[u];
+      }
+    };
+    __syncthreads();  // the previous pass is done with the LDS
+    if (tid < kWgPairs) {
+      int vi, vo;
+      pair_idx(0, vi, vo);
+      in_s[0][tid] = vi;
+      out_s[0][tid] = vo;
+      pair_idx(1, vi, vo);
+      in_s[1][tid] = vi;
+      out_s[1][tid] = vo;
+    }
+    __syncthreads();
+    if (nsteps > 0) {
+      load_rows(0);
+      store_rows();
+    }
+    __syncthreads();
+    for (int t = 0; t < nsteps; ++t) {
+      const int m = p1 - (p0 + (int64_t)t * kWgPairs) < kWgPairs ? (int)(p1 - (p0 + (int64_t)t * kWgPairs)) : kWgPairs;
+      int ni = -1, no = -1;
+      pair_idx(t + 2, ni, no);
+      if (t + 1 < nsteps) load_rows(t + 1);
+      if (block) {  // cn = 64: every entry is in range
+        float v[kWgEPT];
+#pragma unroll
+        for (int j = 0; j < kWgEPT; ++j) v[j] = 0.0f;
+        for (int p = 0; p < m; ++p) {
+          const float g = Gs[p][bo];
+#pragma unroll
+          for (int q = 0; q < kWgEPT / 4; ++q) {
+            const float4 x = *reinterpret_cast<const float4 *>(&Xs[p][bc0 + 4 * q]);
+            v[4 * q] = fmaf(x.x, g, v[4 * q]);
+            v[4 * q + 1] = fmaf(x.y, g, v[4 * q + 1]);
+            v[4 * q + 2] = fmaf(x.z, g, v[4 * q + 2]);
+            v[4 * q + 3] = fmaf(x.w, g, v[4 * q + 3]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kWgEPT; ++j) acc[j].add(v[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kWgEPT; ++j) {
+          const int e = tid + 256 * j;
+          if (e < e_pass) {
+            const int c = e / ow, o = e - c * ow;
+            float v = 0.0f;
+            for (int p = 0; p < m; ++p) v = fmaf(Xs[p][c], Gs[p][o], v);
+            acc[j].add(v);
+          }
         }
       }
+      __syncthreads();  // the products of step t are done with Xs, Gs and the indices of slot t % 2
+      if (t + 1 < nsteps) store_rows();
+      if (tid < kWgPairs) {
+        in_s[t & 1][tid] = ni;
+        out_s[t & 1][tid] = no;
+      }
+      __syncthreads();
     }
 #pragma unroll
     for (int j = 0; j < kWgEPT; ++j) {
       const int e = tid + 256 * j;
-      if (e < e_pass) {
-        const int c = e / ow, o = e % ow;
-        part[((int64_t)(k * S + s) * cin + cbase + c) * cout + o0 + o] = acc[j].value();
-      }
+      const int c = block ? bc0 + j : e / ow, o = block ? bo : e - (e / ow) * ow;
+      if (block || e < e_pass) part[((int64_t)(k * S + s) * cin + cbase + c) * cout + o0 + o] = acc[j].value();
     }
   }
 }
