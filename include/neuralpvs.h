@@ -294,7 +294,9 @@ npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int
  *   level-1 site_keys / block_row / counts are those written by npvs_build_rulebook at d and 2d
  *   for the same grids (extents multiples of 2d, d <= 16).
  * npvs_packed_weight_bytes_k / npvs_pack_weights_k: float32 [K][cin][cout] weights of K offsets
- *   packed like npvs_pack_weights (no flip); the strided layers use K = 8.
+ *   packed like npvs_pack_weights (no flip) with transpose = 0; with transpose = 1 the packing of
+ *   the per-offset transposes W_k^T ([K][cout][cin], npvs_packed_weight_bytes_k(K, cout, cin,
+ *   dtype) bytes), the weight of the data gradient.  The strided layers use K = 8.
  * npvs_strided_conv_fwd: up = 0, the convolution with kernel 2 and stride 2 (level 0 -> 1):
  *     Y[c] = act(b + sum_k X[children[k][c]] W_k), map = children, counts_out / cap_out of level 1;
  *   up = 1, its transposed convolution on the same blocks (level 1 -> 0):
@@ -312,8 +314,8 @@ npvs_status npvs_level_maps(int32_t n_grids, const npvs_dims *dims, int32_t d, c
                             const npvs_counts *counts1, const int32_t *site_keys1, const int32_t *block_row1,
                             int32_t cap1, int32_t *children, int32_t *parent, void *stream);
 size_t npvs_packed_weight_bytes_k(int32_t K, int32_t cin, int32_t cout, int32_t dtype);
-npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t dtype, void *Wp,
-                                void *stream);
+npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t transpose,
+                                int32_t dtype, void *Wp, void *stream);
 npvs_status npvs_strided_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                   const int32_t *map, int32_t up, const npvs_counts *counts_out, int32_t cap_out,
                                   int32_t dtype, int32_t relu, int32_t out_f32, void *Y, void *stream);
@@ -323,9 +325,6 @@ npvs_status npvs_concat_channels(const void *A, int32_t ca, const void *B, int32
 /* ---------------------------------------------------------------------------------------------
  * Backward of the U-Net's strided layers and skip concatenation (chain rule on the forward
  * definitions above; the paper trains its encoder/decoder backbone, Sec. 3.3, 4.2):
- * npvs_pack_weights_k_ex: npvs_pack_weights_k, or with transpose = 1 the packing of the
- *   per-offset transposes W_k^T ([K][cout][cin], npvs_packed_weight_bytes_k(K, cout, cin, dtype)
- *   bytes): the weight of the data gradient.
  * npvs_strided_conv_bwd: dZ = dY [Y > 0] when relu (ReLU'(0) = 0), else dY; for the strided
  *   convolution (up = 0: X level 0, Y level 1) dX0[child k of c] = dZ[c] W_k^T and
  *   dW_k = sum_c X0[child k of c]^T dZ[c]; for its inverse (up = 1: X level 1, Y level 0)
@@ -333,7 +332,7 @@ npvs_status npvs_concat_channels(const void *A, int32_t ca, const void *B, int32
  *   rows f with child index k of X1[parent f]^T dZ[f]; db = sum of dZ over the output rows.
  *   X (device) [cap_in][cin] and Y [cap_out][cout] in `dtype`; dY float32 [cap_out][cout];
  *   children / parent from npvs_level_maps; counts_in / counts_out the input and output level's
- *   counts; Wt = npvs_pack_weights_k_ex(W, 8, cin, cout, transpose = 1) (nullable when dX is);
+ *   counts; Wt = npvs_pack_weights_k(W, 8, cin, cout, transpose = 1, ...) (nullable when dX is);
  *   dX (nullable) float32 [cap_in][cin], dW float32 [8][cin][cout], db float32 [cout], all
  *   overwritten (rows of dX past the input count untouched).  ws (device) scratch of
  *   npvs_strided_bwd_workspace_size() bytes.  Deterministic (fixed reduction orders).  BF16:
@@ -342,8 +341,6 @@ npvs_status npvs_concat_channels(const void *A, int32_t ca, const void *B, int32
  *   (+ add_b[r] when add_b is given: the gradient the second part receives from elsewhere);
  *   float32, dA or dB nullable (not both), ca and cb multiples of 4, 16-byte aligned buffers.
  * ------------------------------------------------------------------------------------------- */
-npvs_status npvs_pack_weights_k_ex(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t transpose,
-                                   int32_t dtype, void *Wp, void *stream);
 npvs_status npvs_strided_bwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_in, int32_t cap_out, int32_t up,
                                             int32_t dtype, size_t *bytes);
 npvs_status npvs_strided_conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t cout, const void *Y,
@@ -386,64 +383,53 @@ npvs_status npvs_visible_objects(const uint8_t *vis_tris, const int64_t *obj_off
 /* ---------------------------------------------------------------------------------------------
  * Training loss per grid over the froxels of its active blocks (Sec. 3.3: repulsive visibility
  * loss L_rv = L_attr + L_rep with L_attr read as FN/GTP, L_rep = FP/GTP, combined with weight
- * lambda; BCE stands in for the Dice term):
- *   p = sigmoid(l); BCE = mean(softplus(l) - y l); TP = sum y p; FN = sum y (1-p);
- *   FP = sum (1-y) p; GTP = sum y; L = lambda BCE + (1-lambda)(FN + FP)/max(GTP, 1).
+ * lambda with a term T):
+ *   p = sigmoid(l); TP = sum y p; FN = sum y (1-p); FP = sum (1-y) p; GTP = sum y;
+ *   L = lambda T + (1-lambda)(FN + FP)/max(GTP, 1), with
+ *   term = NPVS_LOSS_BCE:  T = BCE = mean(softplus(l) - y l) (alpha unused), or
+ *   term = NPVS_LOSS_DICE: T = L_dice = 1 - 2 TP / (2 TP + alpha FN + (1-alpha) FP), the paper's
+ *     weighted Dice term (alpha weighs the missed ground-truth froxels, as the text of Sec. 3.3
+ *     says; the printed formulas name that term FP).
  * The batch loss is the mean over grids.
  *   logits (device) float32 [cap][C]; labels (device) uint8 [cap][C] 0/1; grid_rows from the
- *   rulebook; stats (device) float32 [n_grids + 1][8] = {L, BCE, L_rv, TP, FN, FP, GTP, m} per
+ *   rulebook; stats (device) float32 [n_grids + 1][8] = {L, T, L_rv, TP, FN, FP, GTP, m} per
  *   grid, row n_grids = batch mean; dlogits (device, nullable) float32 [cap][C] = dL_batch/dl,
  *   rows >= n_sites untouched.
  *   ws: npvs_loss_workspace_size() bytes.
  * ------------------------------------------------------------------------------------------- */
-npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes);
-npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
-                      int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, float *stats,
-                      float *dlogits, void *ws, size_t ws_bytes, void *stream);
-
-/* The same with the paper's weighted Dice term in place of BCE (term = NPVS_LOSS_DICE):
- *   L = lambda L_dice + (1-lambda) L_rv,  L_dice = 1 - 2 TP / (2 TP + alpha FN + (1-alpha) FP)
- * (alpha weighs the missed ground-truth froxels, as the text of Sec. 3.3 says; the printed
- * formulas name that term FP); stats column 1 then holds L_dice.  term = NPVS_LOSS_BCE is
- * npvs_loss (alpha unused). */
 #define NPVS_LOSS_BCE 0
 #define NPVS_LOSS_DICE 1
-npvs_status npvs_loss_ex(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
-                         int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, int32_t term,
-                         float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream);
+npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes);
+npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                      int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, int32_t term,
+                      float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream);
 
-/* Adam (Kingma & Ba) step t >= 1 on float32 masters, with weight decay added to the gradient
- * (read from the decay rate the paper lists with the learning rate); p, g, m, v (device) float32 [n]. */
-npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr, float beta1,
-                      float beta2, float eps, float weight_decay, void *stream);
-
-/* The same update with the step counter on the device, so that a captured training step replays
- * with the right bias correction: `step` (device) is advanced on the stream first (t += 1,
- * c1 = 1 - beta1^t, c2 = 1 - beta2^t, each rounded from double to float), then the update uses
- * its c1, c2.  Start from t = 0. */
+/* Adam (Kingma & Ba) on float32 masters, with weight decay added to the gradient (read from the
+ * decay rate the paper lists with the learning rate); p, g, m, v (device) float32 [n].  The step
+ * counter lives on the device, so that a captured training step replays with the right bias
+ * correction: `step` (device) is advanced on the stream first (t += 1, c1 = 1 - beta1^t,
+ * c2 = 1 - beta2^t, each rounded from double to float), then the update uses its c1, c2 (start
+ * from t = 0; a caller that counts on the host writes t - 1 before the call).
+ * Each listed layer's updated weights are also written into its two packings in the same pass:
+ * Wp = npvs_pack_weights(W, ..., flip_transpose = 0) and Wt = the flip_transpose = 1 packing
+ * (forward and data gradient), both of npvs_packed_weight_bytes(cin, cout, dtype) bytes and
+ * packed once before (their padding entries are not rewritten).  Layer l's weight [27][cin][cout]
+ * is p[off, off + 27 cin cout); layers must not overlap; at most NPVS_MAX_ADAM_PACK layers (none
+ * is fine), each of fewer than 2^31 weights (NPVS_ERR_UNSUPPORTED otherwise).  The result
+ * equals the plain update followed by the two packings. */
 typedef struct {
   int64_t t;
   float c1, c2;
 } npvs_adam_step;
-npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step, float lr,
-                          float beta1, float beta2, float eps, float weight_decay, void *stream);
-
-/* npvs_adam_dev that also writes each listed layer's updated weights into its two packings, in
- * the same pass: Wp = npvs_pack_weights(W, ..., flip_transpose = 0) and Wt = the flip_transpose
- * = 1 packing (forward and data gradient), both of npvs_packed_weight_bytes(cin, cout, dtype)
- * bytes and packed once before (their padding entries are not rewritten).  Layer l's weight
- * [27][cin][cout] is p[off, off + 27 cin cout); layers must not overlap; at most
- * NPVS_MAX_ADAM_PACK layers, each of fewer than 2^31 weights (NPVS_ERR_UNSUPPORTED otherwise).
- * The result equals npvs_adam_dev followed by the two packings. */
 #define NPVS_MAX_ADAM_PACK 32
 typedef struct {
   int64_t off;       /* first entry of the layer's weight in p */
   int32_t cin, cout;
   void *Wp, *Wt;     /* (device) the forward and the flipped-transpose packing */
 } npvs_adam_pack_desc;
-npvs_status npvs_adam_dev_pack(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
-                               float lr, float beta1, float beta2, float eps, float weight_decay, int32_t n_layers,
-                               const npvs_adam_pack_desc *layers, int32_t dtype, void *stream);
+npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step, float lr,
+                      float beta1, float beta2, float eps, float weight_decay, int32_t n_layers,
+                      const npvs_adam_pack_desc *layers, int32_t dtype, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Whole forward pass V = threshold(g_d^-1(f(g_d(froxelize(tris))))) through a library-owned

@@ -300,7 +300,7 @@ def pack_weights_k(W: torch.Tensor, dtype: int, transpose: bool = False) -> torc
     K, cin, cout = W.shape
     nbytes = L.get().npvs_packed_weight_bytes_k(K, cout if transpose else cin, cin if transpose else cout, dtype)
     Wp = torch.empty(nbytes, dtype=torch.uint8, device=W.device)
-    L.call("npvs_pack_weights_k_ex", _p(W), K, cin, cout, int(transpose), dtype, _p(Wp), _stream())
+    L.call("npvs_pack_weights_k", _p(W), K, cin, cout, int(transpose), dtype, _p(Wp), _stream())
     return Wp
 
 
@@ -439,20 +439,24 @@ def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 
     stats = torch.empty((G + 1, 8), dtype=torch.float32, device=dev)
     dl = torch.empty_like(logits) if want_grad else None  # rows past the active sites are never read
     term = L.NPVS_LOSS_BCE if dice_alpha is None else L.NPVS_LOSS_DICE
-    L.call("npvs_loss_ex", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam), term,
+    L.call("npvs_loss", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam), term,
            float(dice_alpha or 0.0), _p(stats), _p(dl), _p(ws), nbytes.value, _stream())
     return stats, dl
 
 
-def adam(p, g, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-10):
-    L.call("npvs_adam", _p(p), _p(g), _p(m), _p(v), p.numel(), int(t), float(lr), float(beta1), float(beta2),
-           float(eps), float(weight_decay), _stream())
-
-
-def adam_dev_pack(p, g, m, v, step: torch.Tensor, layers, dtype: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-                  weight_decay=1e-10):
-    """adam_dev that also writes the updated weights into their packings: layers = [(offset in p,
-    cin, cout, Wp, Wt)] with Wp / Wt the forward and flipped-transpose packings (npvs_adam_dev_pack)."""
+def adam(p, g, m, v, step, layers=(), dtype: int = NPVS_F32, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+         weight_decay=1e-10):
+    """npvs_adam.  `step`: a 16-byte npvs_adam_step on the device (uint8 tensor, zero to start),
+    advanced by the call so that graph replays keep counting; or the step number t >= 1 counted on
+    the host (a temporary counter holding t - 1 is made for the call).  layers = [(offset in p,
+    cin, cout, Wp, Wt)]: weights whose forward and flipped-transpose packings (in `dtype`) are
+    rewritten in the same pass."""
+    if isinstance(step, int):
+        if step < 1:
+            raise ValueError("the step number starts at 1")
+        host = torch.zeros(2, dtype=torch.int64)
+        host[0] = step - 1
+        step = host.view(torch.uint8).to(p.device)
     if step.numel() * step.element_size() != 16:
         raise ValueError("step must hold 16 bytes (npvs_adam_step)")
     if len(layers) > L.NPVS_MAX_ADAM_PACK:
@@ -460,17 +464,8 @@ def adam_dev_pack(p, g, m, v, step: torch.Tensor, layers, dtype: int, lr=1e-3, b
     descs = (L.AdamPackDesc * max(len(layers), 1))()
     for i, (off, cin, cout, Wp, Wt) in enumerate(layers):
         descs[i] = L.AdamPackDesc(int(off), int(cin), int(cout), Wp.data_ptr(), Wt.data_ptr())
-    L.call("npvs_adam_dev_pack", _p(p), _p(g), _p(m), _p(v), p.numel(), _p(step), float(lr), float(beta1),
-           float(beta2), float(eps), float(weight_decay), len(layers), descs, dtype, _stream())
-
-
-def adam_dev(p, g, m, v, step: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-10):
-    """Adam with the step counter on the device: `step` is a 16-byte npvs_adam_step (uint8
-    tensor, zero to start), advanced by the call (so graph replays keep counting)."""
-    if step.numel() * step.element_size() != 16:
-        raise ValueError("step must hold 16 bytes (npvs_adam_step)")
-    L.call("npvs_adam_dev", _p(p), _p(g), _p(m), _p(v), p.numel(), _p(step), float(lr), float(beta1), float(beta2),
-           float(eps), float(weight_decay), _stream())
+    L.call("npvs_adam", _p(p), _p(g), _p(m), _p(v), p.numel(), _p(step), float(lr), float(beta1), float(beta2),
+           float(eps), float(weight_decay), len(layers), descs, dtype, _stream())
 
 
 # --------------------------------------------------------------------------------- plan

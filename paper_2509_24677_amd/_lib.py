@@ -86,10 +86,9 @@ SIGNATURES = {
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P, P]),
     "npvs_level_maps": (i32, [i32, P, i32, P, P, P, i32, P, P, P, i32, P, P, P]),
     "npvs_packed_weight_bytes_k": (sz, [i32, i32, i32, i32]),
-    "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, P, P]),
+    "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, i32, P, P]),
     "npvs_strided_conv_fwd": (i32, [P, i32, P, P, i32, P, i32, P, i32, i32, i32, i32, P, P]),
     "npvs_concat_channels": (i32, [P, i32, P, i32, i32, P, i32, P, P]),
-    "npvs_pack_weights_k_ex": (i32, [P, i32, i32, i32, i32, i32, P, P]),
     "npvs_strided_bwd_workspace_size": (i32, [i32, i32, i32, i32, i32, i32, PS]),
     "npvs_strided_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, i32, P, i32, P, i32, i32, i32, P, P, P, P, sz, P]),
     "npvs_concat_channels_bwd": (i32, [P, i32, i32, P, P, i32, P, P, P]),
@@ -100,11 +99,8 @@ SIGNATURES = {
     "npvs_visible_objects": (i32, [P, P, i64, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, i32, P, P, i32, P, i32, P, P, P]),
     "npvs_loss_workspace_size": (i32, [i32, PS]),
-    "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, P, P, P, sz, P]),
-    "npvs_loss_ex": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, P]),
-    "npvs_adam": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, f32, P]),
-    "npvs_adam_dev": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, P]),
-    "npvs_adam_dev_pack": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, i32, P, i32, P]),
+    "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, P]),
+    "npvs_adam": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, i32, P, i32, P]),
     "npvs_plan_create": (i32, [i32, P, P, i32, i32, P, i32, ctypes.POINTER(P)]),
     "npvs_plan_destroy": (i32, [P]),
     "npvs_plan_set_weights": (i32, [P, i32, P, P, P]),

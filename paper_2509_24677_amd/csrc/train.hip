@@ -161,25 +161,6 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict_
   }
 }
 
-// c1, c2 come from `coef` (the device step state) when it is given.
-__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ g,
-                                                    float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
-                                                    float b1, float b2, float eps, float wd, float c1, float c2,
-                                                    const npvs_adam_step *__restrict__ coef) {
-  if (coef) {
-    c1 = coef->c1;
-    c2 = coef->c2;
-  }
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[i] + wd * p[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  }
-}
-
 // Adam over the flat parameter buffer with the updated weights written straight into their
 // packed forms (the forward packing and the flipped-transpose packing of the data gradient), so
 // no separate packing pass follows the optimizer step.  Layer l's weight W[27][cin][cout] sits at
@@ -254,10 +235,10 @@ extern "C" npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes) 
   return NPVS_OK;
 }
 
-extern "C" npvs_status npvs_loss_ex(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
-                                   int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
-                                   int32_t term, float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes,
-                                   void *stream) {
+extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
+                                int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
+                                int32_t term, float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes,
+                                void *stream) {
   if (!logits || !labels || !grid_rows || !counts || !stats || !ws)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: null pointer");
   if (C < 1 || n_grids < 1 || n_grids > NPVS_MAX_GRIDS || cap_sites < 1)
@@ -280,57 +261,27 @@ extern "C" npvs_status npvs_loss_ex(const float *logits, const uint8_t *labels, 
   return check_hip(hipGetLastError(), "npvs_loss");
 }
 
-extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
-                                int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
-                                float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream) {
-  return npvs_loss_ex(logits, labels, C, grid_rows, n_grids, counts, cap_sites, lambda, NPVS_LOSS_BCE, 0.0f, stats,
-                      dlogits, ws, ws_bytes, stream);
-}
-
-extern "C" npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t t, float lr,
-                                float beta1, float beta2, float eps, float weight_decay, void *stream) {
-  if (!p || !g || !m || !v || n < 0 || t < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: bad arguments");
-  if (n == 0) return NPVS_OK;
-  const float c1 = 1.0f - (float)std::pow((double)beta1, (double)t);
-  const float c2 = 1.0f - (float)std::pow((double)beta2, (double)t);
-  adam_kernel<<<stride_grid(n, 256, 2048), 256, 0, as_stream(stream)>>>(p, g, m, v, n, lr, beta1, beta2, eps,
-                                                                         weight_decay, c1, c2, nullptr);
-  return check_hip(hipGetLastError(), "npvs_adam");
-}
-
-extern "C" npvs_status npvs_adam_dev(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
-                                    float lr, float beta1, float beta2, float eps, float weight_decay, void *stream) {
-  if (!p || !g || !m || !v || !step || n < 0) return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev: bad arguments");
-  hipStream_t s = as_stream(stream);
-  adam_step_kernel<<<1, 1, 0, s>>>(step, beta1, beta2);
-  if (n > 0)
-    adam_kernel<<<stride_grid(n, 256, 2048), 256, 0, s>>>(p, g, m, v, n, lr, beta1, beta2, eps, weight_decay, 0.0f,
-                                                          0.0f, step);
-  return check_hip(hipGetLastError(), "npvs_adam_dev");
-}
-
-extern "C" npvs_status npvs_adam_dev_pack(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
-                                         float lr, float beta1, float beta2, float eps, float weight_decay,
-                                         int32_t n_layers, const npvs_adam_pack_desc *layers, int32_t dtype,
-                                         void *stream) {
+extern "C" npvs_status npvs_adam(float *p, const float *g, float *m, float *v, int64_t n, npvs_adam_step *step,
+                                float lr, float beta1, float beta2, float eps, float weight_decay, int32_t n_layers,
+                                const npvs_adam_pack_desc *layers, int32_t dtype, void *stream) {
   if (!p || !g || !m || !v || !step || n < 0 || (n_layers && !layers))
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: bad arguments");
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: bad arguments");
   if (n_layers < 0 || n_layers > NPVS_MAX_ADAM_PACK)
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: 0 to NPVS_MAX_ADAM_PACK layers");
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: 0 to NPVS_MAX_ADAM_PACK layers");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
-    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: dtype must be NPVS_F32 or NPVS_BF16");
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: dtype must be NPVS_F32 or NPVS_BF16");
   AdamPack AP = {};
   AP.n = n_layers;
   for (int l = 0; l < n_layers; ++l) {
     const npvs_adam_pack_desc &D = layers[l];
     if (!D.Wp || !D.Wt || D.cin < 1 || D.cout < 1 || D.off < 0 || D.off + 27LL * D.cin * D.cout > n)
-      return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: layer outside the parameter buffer");
+      return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: layer outside the parameter buffer");
     if (27LL * D.cin * D.cout > 0x7fffffffLL)
-      return fail(NPVS_ERR_UNSUPPORTED, "npvs_adam_dev_pack: a layer of 2^31 or more weights");
+      return fail(NPVS_ERR_UNSUPPORTED, "npvs_adam: a layer of 2^31 or more weights");
     for (int q = 0; q < l; ++q) {
       const npvs_adam_pack_desc &E = layers[q];
       if (D.off < E.off + 27LL * E.cin * E.cout && E.off < D.off + 27LL * D.cin * D.cout)
-        return fail(NPVS_ERR_INVALID_ARG, "npvs_adam_dev_pack: overlapping layers");
+        return fail(NPVS_ERR_INVALID_ARG, "npvs_adam: overlapping layers");
     }
     AP.L[l] = D;
   }
@@ -339,5 +290,5 @@ extern "C" npvs_status npvs_adam_dev_pack(float *p, const float *g, float *m, fl
   if (n > 0)
     adam_pack_kernel<<<stride_grid(n, 256, 2048), 256, 0, s>>>(p, g, m, v, n, lr, beta1, beta2, eps, weight_decay,
                                                                step, AP, dtype);
-  return check_hip(hipGetLastError(), "npvs_adam_dev_pack");
+  return check_hip(hipGetLastError(), "npvs_adam");
 }

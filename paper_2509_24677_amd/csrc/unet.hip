@@ -339,8 +339,8 @@ extern "C" size_t npvs_packed_weight_bytes_k(int32_t K, int32_t cin, int32_t cou
   return 0;
 }
 
-extern "C" npvs_status npvs_pack_weights_k_ex(const float *W, int32_t K, int32_t cin, int32_t cout,
-                                             int32_t transpose, int32_t dtype, void *Wp, void *stream) {
+extern "C" npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t transpose,
+                                          int32_t dtype, void *Wp, void *stream) {
   if (!W || !Wp) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_k: null pointer");
   if (K < 1 || cin < 1 || cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_pack_weights_k: bad sizes");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
@@ -352,10 +352,6 @@ extern "C" npvs_status npvs_pack_weights_k_ex(const float *W, int32_t K, int32_t
   return check_hip(hipGetLastError(), "npvs_pack_weights_k");
 }
 
-extern "C" npvs_status npvs_pack_weights_k(const float *W, int32_t K, int32_t cin, int32_t cout, int32_t dtype,
-                                          void *Wp, void *stream) {
-  return npvs_pack_weights_k_ex(W, K, cin, cout, 0, dtype, Wp, stream);
-}
 
 extern "C" npvs_status npvs_strided_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias,
                                             int32_t cout, const int32_t *map, int32_t up,

@@ -17,7 +17,7 @@ from __future__ import annotations
 import torch
 
 from . import _lib as L
-from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam_dev, adam_dev_pack, build_rulebook, conv_bwd_workspace,
+from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam, build_rulebook, conv_bwd_workspace,
                deinterleave_threshold, froxelize, gather_input, loss, pack_weights, pack_weights_batch, sparse_conv_bwd,
                sparse_conv_fwd)
 
@@ -196,7 +196,7 @@ class Trainer:
         net.backward(saved, logits, dl, rb)  # gradients land in net.gflat
         self.step_count += 1
         # Adam, writing the updated weights straight into both packings of every layer
-        adam_dev_pack(net.flat, net.gflat, self.m, self.v, self.adam_step, net.pack_descs(), net.dtype, lr=self.lr,
+        adam(net.flat, net.gflat, self.m, self.v, self.adam_step, net.pack_descs(), net.dtype, lr=self.lr,
                       weight_decay=self.wd)
         return stats, pvs
 

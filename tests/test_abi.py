@@ -85,8 +85,8 @@ def test_adam_pack_argument_checks(lib):
 
     def call(descs, n=1000, nl=None):
         arr = (L.AdamPackDesc * len(descs))(*descs) if descs else None
-        return lib.npvs_adam_dev_pack(fake, fake, fake, fake, n, fake, 1e-3, 0.9, 0.999, 1e-8, 0.0,
-                                      len(descs) if nl is None else nl, arr, L.NPVS_BF16, None)
+        return lib.npvs_adam(fake, fake, fake, fake, n, fake, 1e-3, 0.9, 0.999, 1e-8, 0.0,
+                             len(descs) if nl is None else nl, arr, L.NPVS_BF16, None)
 
     assert call([], nl=L.NPVS_MAX_ADAM_PACK + 1) == L.NPVS_ERR_INVALID_ARG
     # a layer reaching past the parameter buffer (27 * 8 * 8 = 1728 > 1000)

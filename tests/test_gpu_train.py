@@ -276,7 +276,7 @@ def test_adam_with_device_step_equals_host_step():
     step = torch.zeros(16, dtype=torch.uint8, device=DEV)
     for t, g in enumerate(gs, start=1):
         npvs.adam(a[0], g, a[1], a[2], t)
-        npvs.adam_dev(b[0], g, b[1], b[2], step)
+        npvs.adam(b[0], g, b[1], b[2], step)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(to_np(x), to_np(y))
     assert int(step[:8].view(torch.int64).item()) == 4
@@ -326,8 +326,8 @@ def test_city256_training_gradients_at_full_size():
 
 @pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
 def test_adam_with_packing_equals_adam_then_packing(dtype):
-    """npvs_adam_dev_pack over two steps equals npvs_adam_dev followed by both packings of each
-    layer, bit for bit (channel counts with padded BF16 fragments included)."""
+    """npvs_adam with packings over two steps equals npvs_adam without them followed by both
+    packings of each layer, bit for bit (channel counts with padded BF16 fragments included)."""
     rng = np.random.default_rng(21)
     shapes = [(24, 40), (64, 8), (16, 136)]
     sizes = [27 * a * b for a, b in shapes]
@@ -345,10 +345,10 @@ def test_adam_with_packing_equals_adam_then_packing(dtype):
         for t in range(2):
             g = torch.from_numpy(np.random.default_rng(30 + t).normal(size=n).astype(np.float32)).to(DEV)
             if fused:
-                npvs.adam_dev_pack(p, g, m, v, step, [(o, a, b, wp, wt) for (a, b), o, (wp, wt) in
-                                                      zip(shapes, offs, packs)], dtype)
+                npvs.adam(p, g, m, v, step, [(o, a, b, wp, wt) for (a, b), o, (wp, wt) in zip(shapes, offs, packs)],
+                          dtype)
             else:
-                npvs.adam_dev(p, g, m, v, step)
+                npvs.adam(p, g, m, v, step)
                 for (a, b), o, (wp, wt) in zip(shapes, offs, packs):
                     W = p[o:o + 27 * a * b].view(27, a, b)
                     wp.copy_(npvs.pack_weights(W, dtype))
