@@ -144,7 +144,19 @@ def bench_batch16(args, dev, timed_launches):
     n_pairs = rb.host_counts()["n_pairs"]
     flops = 2.0 * n_pairs * 64 * 64
     n = len(cfg.grids)
-    return {"grids": n, "n_sites": c["n_sites"], "n_pairs": n_pairs, "tile_variants": tuned,
+    # balance: the conv's 16-row tiles are cut from the concatenated sites of all grids and dealt
+    # to the XCDs in contiguous ranges, then over each XCD's workgroups (the default shape runs
+    # 256 workgroups); tiles per workgroup, whatever the grids' sizes
+    grid_rows = rb.grid_rows.cpu().numpy().astype(np.int64)
+    ntiles = (int(grid_rows[-1]) + 15) // 16
+    G = 256
+    per = (ntiles + 7) // 8
+    per_wg = [sum(1 for j in range(per) if (i // 8) + j * (G // 8) < per and (i % 8) * per + (i // 8) + j * (G // 8)
+                  < ntiles) for i in range(G)]
+    balance = {"sites_per_grid": np.diff(grid_rows).tolist(), "tiles": ntiles,
+               "tiles_per_workgroup_min": min(per_wg), "tiles_per_workgroup_max": max(per_wg),
+               "tiles_spanning_two_grids": int(sum(1 for r in grid_rows[1:-1] if r % 16))}
+    return {"grids": n, "n_sites": c["n_sites"], "n_pairs": n_pairs, "tile_variants": tuned, "balance": balance,
             "batched_ms": ms_batched, "batched_frames_per_s": 1000.0 * n / ms_batched,
             "separate_ms": ms_separate, "separate_frames_per_s": 1000.0 * n / ms_separate,
             "speedup": ms_separate / ms_batched,
