@@ -1103,6 +1103,15 @@ def main():
     stage_gbs = {k: {"bytes": b, "GB_per_s": b / (stage_ms[k] * 1e-3) / 1e9,
                      "frac_of_hbm_peak": b / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
                  for k, b in stage_bytes.items()}
+    # froxelize's integer work: one separating-axis test per froxel of each triangle's clipped
+    # range (vertices in 1/256-froxel fixed point, rounded to nearest even; closed froxels, so a
+    # coordinate on a froxel face also meets the froxel below)
+    q = np.rint(tris_np.astype(np.float64).reshape(-1, 3, 3) * 256.0).astype(np.int64)
+    ext = np.array([dims[0][0], dims[0][1], dims[0][2]])
+    lo = np.maximum((q.min(axis=1) - 1) >> 8, 0)
+    hi = np.minimum(q.max(axis=1) >> 8, ext - 1)
+    sat_tests = int(np.prod(np.maximum(hi - lo + 1, 0), axis=1).sum())
+    stage_gbs["froxelize"].update(sat_tests=sat_tests, sat_tests_per_s=sat_tests / (stage_ms["froxelize"] * 1e-3))
     print("# stages (median ms per call) " + json.dumps(stage_ms), file=sys.stderr, flush=True)
 
     # dominant kernel: the BF16 MFMA gather-GEMM (6 forward and 5 data-gradient launches per
