@@ -1089,6 +1089,19 @@ def main():
     dY = torch.randn((rb.cap, 64), device=dev)
     stage["conv_bwd_bf16"] = timed_launches(
         lambda: npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True), 20)
+    # the training step's form: each layer's dZ and data gradient, then the weight gradients of
+    # all six layers in one launch (here six copies of the hidden layer's operands)
+    ws_b = npvs.conv_bwd_workspace(64, 64, rb, npvs.NPVS_BF16)
+    stage["conv_bwd_bf16_without_wgrad"] = timed_launches(
+        lambda: npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True, ws=ws_b,
+                                     want_dw=False), 20)
+    wg_ws = [npvs.conv_bwd_workspace(64, 64, rb, npvs.NPVS_BF16) for _ in range(6)]
+    for w in wg_ws:
+        npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True, ws=w, want_dw=False)
+    wg_out = [(torch.empty((27, 64, 64), device=dev), torch.empty(64, device=dev)) for _ in range(6)]
+    wg_layers = [(hid_b, 64, 64, w, gW, gb) for w, (gW, gb) in zip(wg_ws, wg_out)]
+    stage["wgrad_bf16_six_layers_batched"] = timed_launches(
+        lambda: npvs.sparse_conv_wgrad(wg_layers, rb, npvs.NPVS_BF16), 20)
     stage["deinterleave_threshold"] = timed_launches(lambda: npvs.deinterleave_threshold(logits_b, rb, occ), 20)
     stage_ms = {k: float(np.median(v)) for k, v in stage.items()}
     # algorithmic bytes of the memory-bound stages and the HBM rate they reach (peak 8 TB/s)

@@ -59,6 +59,7 @@ typedef int32_t npvs_status;
 #define NPVS_MAX_GRIDS 32        /* grids per batch */
 #define NPVS_MAX_DIM 1024        /* froxels per axis */
 #define NPVS_COORD_LIMIT 2048    /* triangles with a coordinate |v| >= 2048 (grid units) are ignored */
+#define NPVS_MAX_WGRAD_LAYERS 16 /* layers of one npvs_sparse_conv_wgrad call */
 
 typedef struct {
   int32_t nx, ny, nz; /* froxels; nx % 8 == 0 and every extent divisible by d */
@@ -267,7 +268,9 @@ npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, con
  *   of 64 x 64 channels, and the data gradient of a BF16 layer with 1024+ outputs splits its input
  *   channels over several workgroups (the workspace size covers it).
  * ------------------------------------------------------------------------------------------- */
-/* Streams: dZ and the bias partials are formed on `stream`, and the data gradient dX runs there.
+/* dW and db both null: the weight gradient is not computed here; dZ and the bias partials stay in
+ * ws for a later npvs_sparse_conv_wgrad (one non-null and one null is an argument error).
+ * Streams: dZ and the bias partials are formed on `stream`, and the data gradient dX runs there.
  * wgrad_stream (nullable: `stream`) waits for dZ and computes the weight-gradient slices, so they
  * overlap the data-gradient chain of the layers below; reduce_stream (nullable: wgrad_stream)
  * waits for those and adds the slices and the bias partials into dW and db, so that the next
@@ -281,6 +284,36 @@ npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int
                                  const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
                                  float *dW, float *db, void *ws, size_t ws_bytes, void *stream, void *wgrad_stream,
                                  void *reduce_stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Weight and bias gradients of several layers of one rulebook (the dW / db of the backward
+ * above), in one weight-gradient launch and one reduction launch for all of them:
+ *   layers (host) array of n_layers (1 .. NPVS_MAX_WGRAD_LAYERS) descriptors, read during the
+ *   call: X (device) the layer input [cap][cin] in `dtype`; ws (device) the workspace that an
+ *   npvs_sparse_conv_bwd call of that layer with dW = db = NULL left its dZ and bias partials in
+ *   (same cin, cout, cap_sites, dtype; its slice partials are overwritten here); dW / db (device)
+ *   float32 [27][cin][cout] / [cout], overwritten.
+ *   rb_off / rb_pairs: the CSR rulebook of those backward calls.  slices: pair-list slices per
+ *   offset (0: the library's choice; at most the single-layer count, which is used when larger).
+ *   Results equal npvs_sparse_conv_bwd's dW / db computed with the same slice count (the
+ *   single-layer call uses 16 slices for layers of at most 64 x 64 channels).  The FP32 path
+ *   takes one weight-gradient launch per layer, each with that layer's single-layer slice count
+ *   (or `slices` when smaller), and one reduction launch.
+ * Why: a layer's weight gradient is a short latency-bound kernel; issued one layer at a time it
+ * forms a serial chain behind the data gradients of the layers below, whereas all layers at once
+ * fill the chip and pay the launch and memory round trips once (Sec. 3.3 trains the stack end to
+ * end; the gradients themselves are those of the layer backward above).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+  const void *X;
+  int32_t cin, cout;
+  void *ws;
+  size_t ws_bytes;
+  float *dW, *db;
+} npvs_wgrad_layer;
+npvs_status npvs_sparse_conv_wgrad(int32_t n_layers, const npvs_wgrad_layer *layers, const int32_t *rb_off,
+                                   const int32_t *rb_pairs, int32_t cap_sites, int32_t dtype, int32_t slices,
+                                   void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Two-level sparse U-Net pieces (Sec. 3.3 adopts an encoder/decoder backbone; the supplement's

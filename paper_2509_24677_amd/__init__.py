@@ -21,7 +21,7 @@ from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  #
 
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
-    "sparse_conv_fwd", "sparse_conv_bwd", "Levels", "build_levels",
+    "sparse_conv_fwd", "sparse_conv_bwd", "sparse_conv_wgrad", "Levels", "build_levels",
     "pack_weights_k", "strided_conv_fwd", "concat_channels", "viewcell_frustum", "froxelize_view", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
     "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
 ]
@@ -239,32 +239,60 @@ def conv_bwd_workspace(cin: int, cout: int, rb: Rulebook, dtype: int) -> torch.T
 
 def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int, relu: bool, want_dx: bool = True,
                     dW: torch.Tensor | None = None, db: torch.Tensor | None = None, ws: torch.Tensor | None = None,
-                    wgrad_stream: torch.cuda.Stream | None = None, reduce_stream: torch.cuda.Stream | None = None):
+                    wgrad_stream: torch.cuda.Stream | None = None, reduce_stream: torch.cuda.Stream | None = None,
+                    want_dw: bool = True):
     """Returns (dX float32 [cap][cin] or None, dW float32 [27][cin][cout], db float32 [cout]).
     dW / db may be given (contiguous float32 device tensors) to receive the gradients in place.
     With `wgrad_stream`, dW and db are computed on that stream, and with `reduce_stream` too their
     final reductions on that one: the caller keeps X and ws alive and joins the streams before
-    reading dW / db."""
+    reading dW / db.  With want_dw=False, dW and db are not computed (returned as None): dZ and
+    the bias partials stay in `ws` (which must be given) for `sparse_conv_wgrad`."""
     if rb.rb_off is None:
         raise ValueError("the backward needs a rulebook built with csr=True")
     dev = X.device
     if ws is None:
+        if not want_dw:
+            raise ValueError("want_dw=False needs the workspace that sparse_conv_wgrad will read")
         ws = conv_bwd_workspace(cin, cout, rb, dtype)
         for side in (wgrad_stream, reduce_stream):  # freed here, still read by the side streams
             if side is not None:
                 ws.record_stream(side)
     dX = torch.empty((rb.cap, cin), dtype=torch.float32, device=dev) if want_dx else None
-    if dW is None:
-        dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
-    if db is None:
-        db = torch.empty(cout, dtype=torch.float32, device=dev)
-    if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
-        raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
+    if not want_dw:
+        dW = db = None
+    else:
+        if dW is None:
+            dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
+        if db is None:
+            db = torch.empty(cout, dtype=torch.float32, device=dev)
+        _check_grad_out(dW, db, cin, cout)
     side = [ctypes.c_void_p(t.cuda_stream) if t is not None else None for t in (wgrad_stream, reduce_stream)]
     L.call("npvs_sparse_conv_bwd", _p(X), cin, _p(Wt), cout, _p(Y), _p(dY.contiguous()), _p(rb.nbr), _p(rb.rb_off),
            _p(rb.rb_pairs), _p(rb.counts), rb.cap, dtype, int(relu), _p(dX), _p(dW), _p(db), _p(ws), ws.numel(),
            _stream(), side[0], side[1])
     return dX, dW, db
+
+
+def _check_grad_out(dW, db, cin: int, cout: int):
+    if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
+        raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
+
+
+def sparse_conv_wgrad(layers, rb: Rulebook, dtype: int, slices: int = 0):
+    """Weight and bias gradients of several layers of rulebook `rb` in one launch: `layers` is a
+    list of (X, cin, cout, ws, dW, db), ws being the workspace of that layer's
+    sparse_conv_bwd(..., want_dw=False) call; dW / db (contiguous float32 [27][cin][cout] /
+    [cout]) are overwritten.  slices: pair-list slices per offset (0: the library's choice)."""
+    if rb.rb_off is None:
+        raise ValueError("the weight gradient needs a rulebook built with csr=True")
+    if not 1 <= len(layers) <= L.NPVS_MAX_WGRAD_LAYERS:
+        raise ValueError(f"1 to {L.NPVS_MAX_WGRAD_LAYERS} layers")
+    arr = (L.WgradLayer * len(layers))()
+    for i, (X, cin, cout, ws, dW, db) in enumerate(layers):
+        _check_grad_out(dW, db, cin, cout)
+        arr[i] = L.WgradLayer(X.data_ptr(), cin, cout, ws.data_ptr(), ws.numel(), dW.data_ptr(), db.data_ptr())
+    L.call("npvs_sparse_conv_wgrad", len(layers), ctypes.cast(arr, ctypes.c_void_p), _p(rb.rb_off), _p(rb.rb_pairs),
+           rb.cap, dtype, slices, _stream())
 
 
 # --------------------------------------------------------------------------------- U-Net levels

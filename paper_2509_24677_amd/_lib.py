@@ -23,6 +23,7 @@ NPVS_CONV_VARIANTS = 15
 NPVS_DEFAULT_CONV_VARIANT = 14
 NPVS_MAX_PACK = 64
 NPVS_MAX_ADAM_PACK = 32
+NPVS_MAX_WGRAD_LAYERS = 16
 NPVS_LOSS_BCE = 0
 NPVS_LOSS_DICE = 1
 
@@ -51,6 +52,11 @@ class View(ctypes.Structure):
     _fields_ = [("eye", ctypes.c_double * 3), ("right", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
                 ("forward", ctypes.c_double * 3), ("tan_half_x", ctypes.c_double), ("tan_half_y", ctypes.c_double),
                 ("z_near", ctypes.c_double), ("z_far", ctypes.c_double)]
+
+
+class WgradLayer(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("cin", ctypes.c_int32), ("cout", ctypes.c_int32), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("dW", ctypes.c_void_p), ("db", ctypes.c_void_p)]
 
 
 class AdamPackDesc(ctypes.Structure):
@@ -84,6 +90,7 @@ SIGNATURES = {
     "npvs_conv_fwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P, P]),
+    "npvs_sparse_conv_wgrad": (i32, [i32, P, P, P, i32, i32, i32, P]),
     "npvs_level_maps": (i32, [i32, P, i32, P, P, P, i32, P, P, P, i32, P, P, P]),
     "npvs_packed_weight_bytes_k": (sz, [i32, i32, i32, i32]),
     "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, i32, P, P]),

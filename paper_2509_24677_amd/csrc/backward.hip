@@ -105,7 +105,9 @@ __global__ __launch_bounds__(256) void relu_grad_kernel(const T *__restrict__ Y,
   }
 }
 
+constexpr int kMaxWgradLayers = NPVS_MAX_WGRAD_LAYERS;  // layers of one batched weight-gradient launch
 constexpr int kWgSlices = 16;  // slices of each offset's pair list (at most; fewer for wide layers)
+constexpr int kWgBatchBlocks = 512;  // workgroups resident at once (72 KB of LDS each: two per compute unit)
 constexpr size_t kWgPartBudget = size_t(8) << 20;  // bytes of float32 slice partials aimed at
 
 // Slices per offset: 16 while the float32 partials of every slice stay within the budget (every
@@ -321,19 +323,34 @@ __device__ __forceinline__ void wg_store(uint16_t *XT, uint16_t *GT, const WgTas
   }
 }
 
-__global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restrict__ X, int cin,
-                                                          const uint16_t *__restrict__ dZ16,
-                                                          int cout, const int32_t *__restrict__ rb_off,
-                                                          const int32_t *__restrict__ pairs,
-                                                          float *__restrict__ part) {
+// The layers of one weight-gradient launch (one rulebook): layer i owns the windows
+// blockIdx.z in [z0, next layer's z0).
+struct WgLayer {
+  const uint16_t *X, *dZ;
+  float *part;
+  int cin, cout, z0;
+};
+struct WgBatch {
+  int n;
+  WgLayer L[kMaxWgradLayers];
+};
+
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const int32_t *__restrict__ rb_off,
+                                                          const int32_t *__restrict__ pairs) {
   // two staging buffers: chunk ch is read from buffer ch & 1 while chunk ch + 1 is written to the
   // other one, so one barrier per chunk orders both
   __shared__ __attribute__((aligned(16))) uint16_t XT[2][64 * kWgPitch];
   __shared__ __attribute__((aligned(16))) uint16_t GT[2][64 * kWgPitch];
+  int li = 0;
+  for (int i = 1; i < B.n; ++i) li = (int)blockIdx.z >= B.L[i].z0 ? i : li;
+  const uint16_t *__restrict__ X = B.L[li].X;
+  const uint16_t *__restrict__ dZ16 = B.L[li].dZ;
+  float *__restrict__ part = B.L[li].part;
+  const int cin = B.L[li].cin, cout = B.L[li].cout, z = (int)blockIdx.z - B.L[li].z0;
   const int k = blockIdx.y, s = blockIdx.x, S = gridDim.x, tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
   const int otiles = (cout + 63) / 64;
-  const int c0 = 64 * (blockIdx.z / otiles), o0 = 64 * (blockIdx.z % otiles);
+  const int c0 = 64 * (z / otiles), o0 = 64 * (z % otiles);
   const int cw = cin - c0 < 64 ? cin - c0 : 64, ow = cout - o0 < 64 ? cout - o0 : 64;  // window size
   const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
   const int64_t p0 = pk0 + pk * s / S, p1 = pk0 + pk * (s + 1) / S;
@@ -440,16 +457,34 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const uint16_t *__restr
   }
 }
 
-// Blocks [0, nbw) reduce dW (K offsets) over the slices (grid-stride, one entry per thread); each block
-// after them reduces db over the nparts partial rows for 4 channels, one wave per channel: lane l
-// adds partials l, l + 64, ..., then a fixed butterfly adds the 64 lane totals; lane 0 writes.
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ wpart,
-                                                           const float *__restrict__ dbpart, int nparts, int cin,
-                                                           int cout, int nbw, int K, int S, float *__restrict__ dW,
-                                                           float *__restrict__ db) {
-  if ((int)blockIdx.x < nbw) {
+// The final reductions of the layers of one launch: layer i owns the blocks [b0, next layer's b0):
+// nbw blocks for dW, then one per 4 bias channels.
+struct RdLayer {
+  const float *wpart, *dbpart;
+  float *dW, *db;
+  int cin, cout, nbw, b0, S;  // S: slices per offset of this layer's partials
+};
+struct RdBatch {
+  int n;
+  RdLayer L[kMaxWgradLayers];
+};
+
+// Per layer: blocks [0, nbw) reduce dW (K offsets) over the slices (grid-stride, one entry per
+// thread); each block after them reduces db over the nparts partial rows for 4 channels, one wave
+// per channel: lane l adds partials l, l + 64, ..., then a fixed butterfly adds the 64 lane totals;
+// lane 0 writes.
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const RdBatch B, int nparts, int K) {
+  int li = 0;
+  for (int i = 1; i < B.n; ++i) li = (int)blockIdx.x >= B.L[i].b0 ? i : li;
+  const float *__restrict__ wpart = B.L[li].wpart;
+  const float *__restrict__ dbpart = B.L[li].dbpart;
+  float *__restrict__ dW = B.L[li].dW;
+  float *__restrict__ db = B.L[li].db;
+  const int cin = B.L[li].cin, cout = B.L[li].cout, nbw = B.L[li].nbw, S = B.L[li].S;
+  const int bx = (int)blockIdx.x - B.L[li].b0;
+  if (bx < nbw) {
     const int64_t E = (int64_t)cin * cout;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K * E; e += (int64_t)nbw * blockDim.x) {
+    for (int64_t e = (int64_t)bx * blockDim.x + threadIdx.x; e < K * E; e += (int64_t)nbw * blockDim.x) {
       Comp a{0.0f, 0.0f};
       const int64_t k = e / E, ce = e % E;
       if (S == kWgSlices) {  // the usual count, unrolled so that the loads are issued together
@@ -462,7 +497,7 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
     }
     return;
   }
-  const int o = ((int)blockIdx.x - nbw) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int o = (bx - nbw) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (o >= cout) return;  // whole waves leave together
   Comp a{0.0f, 0.0f};
   for (int s = lane; s < nparts; s += 64) a.add(dbpart[s * cout + o]);
@@ -490,16 +525,26 @@ npvs_status bwd_wgrad(int32_t dtype, const void *X, int32_t cin, const void *dZ,
   if (dtype == NPVS_F32)
     wgrad_partial_kernel<float><<<dim3(S, K, (cout + 63) / 64), 256, 0, s>>>(
         (const float *)X, cin, (const float *)dZ, cout, rb_off, pairs, wpart);
-  else
-    wgrad_bf16_kernel<<<dim3(S, K, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s>>>(
-        (const uint16_t *)X, cin, (const uint16_t *)dZ, cout, rb_off, pairs, wpart);
+  else {
+    WgBatch B{};
+    B.n = 1;
+    B.L[0] = WgLayer{(const uint16_t *)X, (const uint16_t *)dZ, wpart, cin, cout, 0};
+    wgrad_bf16_kernel<<<dim3(S, K, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s>>>(B, rb_off, pairs);
+  }
   return check_hip(hipGetLastError(), "backward: weight gradient");
+}
+
+static int reduce_blocks(int32_t K, int32_t cin, int32_t cout) {
+  return stride_grid((int64_t)K * cin * cout, 256, 2048);
 }
 
 npvs_status bwd_reduce(const float *wpart, const float *dbpart, int nparts, int32_t K, int S, int32_t cin,
                        int32_t cout, float *dW, float *db, hipStream_t s) {
-  const int nbw = stride_grid((int64_t)K * cin * cout, 256, 2048);
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s>>>(wpart, dbpart, nparts, cin, cout, nbw, K, S, dW, db);
+  const int nbw = reduce_blocks(K, cin, cout);
+  RdBatch B{};
+  B.n = 1;
+  B.L[0] = RdLayer{wpart, dbpart, dW, db, cin, cout, nbw, 0, S};
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s>>>(B, nparts, K);
   return check_hip(hipGetLastError(), "backward: reductions");
 }
 
@@ -573,8 +618,9 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
                             const npvs_counts *counts, int32_t cap_sites, int32_t dtype, int32_t relu, float *dX,
                             float *dW, float *db, void *ws, size_t ws_bytes, hipStream_t s, hipStream_t s2,
                             hipStream_t s3) {
-  if (!X || !dY || !nbr || !rb_off || !rb_pairs || !counts || !dW || !db || !ws || (relu && !Y) || (dX && !Wt))
+  if (!X || !dY || !nbr || !rb_off || !rb_pairs || !counts || !ws || (relu && !Y) || (dX && !Wt))
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: null pointer");
+  if (!dW != !db) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: dW and db must both be given or both null");
   if (cin < 1 || cout < 1 || cap_sites < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: bad sizes");
   if (dtype != NPVS_F32 && dtype != NPVS_BF16)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_bwd: dtype must be NPVS_F32 or NPVS_BF16");
@@ -591,7 +637,7 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
   float *dbpart = reinterpret_cast<float *>(w + odb);
   npvs_status st = bwd_form_dz(dtype, Y, dY, counts, cout, relu, dZ32, dZ16, dbpart, s);
   if (st != NPVS_OK) return st;
-  st = join_after(s, s2);
+  if (dW) st = join_after(s, s2);
   if (st != NPVS_OK) return st;
   if (dX) {
     st = conv_fwd_dispatch(dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, Wt, nullptr, cin, nbr,
@@ -599,6 +645,7 @@ static npvs_status conv_bwd(const void *X, int32_t cin, const void *Wt, int32_t 
                            dx_bytes);
     if (st != NPVS_OK) return st;
   }
+  if (!dW) return NPVS_OK;  // dZ and the bias partials stay in ws for npvs_sparse_conv_wgrad
   const int S = wg_slices(cin, cout);
   st = bwd_wgrad(dtype, X, cin, dtype == NPVS_F32 ? (const void *)dZ32 : (const void *)dZ16, cout, 27, rb_off,
                  rb_pairs, S, wpart, s2);
@@ -618,4 +665,67 @@ extern "C" npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const vo
   const hipStream_t s3 = reduce_stream ? as_stream(reduce_stream) : s2;
   return conv_bwd(X, cin, Wt, cout, Y, dY, nbr, rb_off, rb_pairs, counts, cap_sites, dtype, relu, dX, dW, db, ws,
                   ws_bytes, s, s2, s3);
+}
+
+extern "C" npvs_status npvs_sparse_conv_wgrad(int32_t n_layers, const npvs_wgrad_layer *layers,
+                                             const int32_t *rb_off, const int32_t *rb_pairs, int32_t cap_sites,
+                                             int32_t dtype, int32_t slices, void *stream) {
+  if (!layers || !rb_off || !rb_pairs) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_wgrad: null pointer");
+  if (n_layers < 1 || n_layers > NPVS_MAX_WGRAD_LAYERS || cap_sites < 1 || slices < 0)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_wgrad: bad sizes");
+  if (dtype != NPVS_F32 && dtype != NPVS_BF16)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_wgrad: dtype must be NPVS_F32 or NPVS_BF16");
+  int S = kWgSlices, windows = 0;
+  for (int i = 0; i < n_layers; ++i) {
+    const npvs_wgrad_layer &l = layers[i];
+    if (!l.X || !l.ws || !l.dW || !l.db) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_wgrad: null pointer");
+    if (l.cin < 1 || l.cout < 1) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_wgrad: bad sizes");
+    if (dtype == NPVS_BF16 && (l.cin % 8 || l.cout % 8))
+      return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_wgrad: BF16 needs cin % 8 == 0 and cout % 8 == 0");
+    size_t a, b, c, d, e, f, need;
+    bwd_ws_layout(l.cin, l.cout, cap_sites, dtype, &a, &b, &c, &d, &e, &f, &need);
+    if (l.ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_wgrad: workspace too small");
+    const int sl = wg_slices(l.cin, l.cout);
+    S = sl < S ? sl : S;
+    windows += ((l.cin + 63) / 64) * ((l.cout + 63) / 64);
+  }
+  if (slices > 0) S = slices < S ? slices : S;
+  else {  // at most kWgBatchBlocks workgroups in all, so that they run in one round
+    const int want = kWgBatchBlocks / (27 * windows);
+    S = want < S ? (want < 1 ? 1 : want) : S;
+  }
+  const hipStream_t s = as_stream(stream);
+  WgBatch W{};
+  RdBatch R{};
+  W.n = R.n = n_layers;
+  int z0 = 0, b0 = 0;
+  for (int i = 0; i < n_layers; ++i) {
+    const npvs_wgrad_layer &l = layers[i];
+    size_t o32, o16, owp, odb, odx, dxb, need;
+    bwd_ws_layout(l.cin, l.cout, cap_sites, dtype, &o32, &o16, &owp, &odb, &odx, &dxb, &need);
+    char *w = static_cast<char *>(l.ws);
+    float *wpart = reinterpret_cast<float *>(w + owp);
+    const float *dbpart = reinterpret_cast<const float *>(w + odb);
+    // FP32: one launch per layer (the FP32 kernel's grid is per layer), each with the layer's own
+    // slice count (or `slices` when smaller)
+    int Sl = S;
+    if (dtype == NPVS_F32) {
+      Sl = wg_slices(l.cin, l.cout);
+      Sl = slices > 0 && slices < Sl ? slices : Sl;
+      const npvs_status st = bwd_wgrad(dtype, l.X, l.cin, w + o32, l.cout, 27, rb_off, rb_pairs, Sl, wpart, s);
+      if (st != NPVS_OK) return st;
+    }
+    W.L[i] = WgLayer{(const uint16_t *)l.X, reinterpret_cast<const uint16_t *>(w + o16), wpart, l.cin, l.cout, z0};
+    z0 += ((l.cin + 63) / 64) * ((l.cout + 63) / 64);
+    const int nbw = reduce_blocks(27, l.cin, l.cout);
+    R.L[i] = RdLayer{wpart, dbpart, l.dW, l.db, l.cin, l.cout, nbw, b0, Sl};
+    b0 += nbw + (l.cout + 3) / 4;
+  }
+  if (dtype == NPVS_BF16) {
+    wgrad_bf16_kernel<<<dim3(S, 27, z0), 256, 0, s>>>(W, rb_off, rb_pairs);
+    const npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_wgrad: weight gradient");
+    if (st != NPVS_OK) return st;
+  }
+  grad_reduce_kernel<<<b0, 256, 0, s>>>(R, kDbBlocks, 27);
+  return check_hip(hipGetLastError(), "npvs_sparse_conv_wgrad: reductions");
 }

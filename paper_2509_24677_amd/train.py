@@ -19,7 +19,7 @@ import torch
 from . import _lib as L
 from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam, build_rulebook, conv_bwd_workspace,
                deinterleave_threshold, froxelize, gather_input, loss, pack_weights, pack_weights_batch, sparse_conv_bwd,
-               sparse_conv_fwd)
+               sparse_conv_fwd, sparse_conv_wgrad)
 
 
 class Network:
@@ -127,12 +127,22 @@ class Network:
             X = self.layer(i, X, rb)
         return X, saved
 
-    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True):
+    def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True,
+                 batch_wgrad: bool | None = None, wgrad_slices: int = 0):
         """Hand-written backward through the stack; recomputes the layer inputs that were not
-        saved.  With `overlap`, each layer's weight gradient runs on a side stream while the data
-        gradient continues down the stack (their final reductions on a third stream, beside the
-        next weight gradient); the side streams are joined before returning.  The
-        gradients land in the flat gradient buffer; returns [(dW, db)] per layer (views of it)."""
+        saved.  With `batch_wgrad` (default: for BF16, whose weight gradients are short
+        latency-bound launches), the data gradients run down the stack first, all on the current
+        stream, and the weight gradients of every layer follow in one launch (and one reduction
+        launch; `wgrad_slices` pair-list slices per offset, 0 for the library's choice).
+        Otherwise (the FP32 default) each layer's weight gradient follows its data gradient:
+        with `overlap` on a side stream while the data gradient continues down the stack (their
+        final reductions on a third stream, beside the next weight gradient; the side streams
+        are joined before returning).  The gradients land in the flat gradient buffer; returns
+        [(dW, db)] per layer (views of it)."""
+        if batch_wgrad is None:
+            batch_wgrad = self.dtype == NPVS_BF16
+        if batch_wgrad:
+            return self._backward_batched(saved, logits, dlogits, rb, wgrad_slices)
         main = torch.cuda.current_stream()
         side = side2 = None
         if overlap:
@@ -166,19 +176,44 @@ class Network:
         del in_use
         return grads
 
+    def _backward_batched(self, saved, logits, dlogits, rb, slices):
+        outputs = {self.n_layers - 1: logits}
+        pending = []  # (X, cin, cout, ws, dW, db) of each layer, for the batched weight gradient
+        dY = dlogits
+        for i in range(self.n_layers - 1, -1, -1):
+            X = saved.get(i)
+            if X is None:
+                X = self.layer(i - 1, saved[i - 1], rb)
+            Y = outputs.get(i)
+            if Y is None:
+                Y = self.layer(i, X, rb)
+            cin, cout = self.channels[i], self.channels[i + 1]
+            ws = conv_bwd_workspace(cin, cout, rb, self.dtype)
+            dX, _, _ = sparse_conv_bwd(X, self.Wt[i], cin, cout, Y, dY, rb, self.dtype, relu=i < self.n_layers - 1,
+                                       want_dx=i > 0, ws=ws, want_dw=False)
+            pending.append((X, cin, cout, ws, self.gW[i], self.gb[i]))
+            if i > 0:
+                outputs[i - 1] = X
+            dY = dX
+        sparse_conv_wgrad(pending, rb, self.dtype, slices)
+        return [(self.gW[i], self.gb[i]) for i in range(self.n_layers)]
+
 
 class Trainer:
     """One training step per call; all state lives on the device."""
 
     def __init__(self, net: Network, dims, n_tris, lam: float = 0.99, lr: float = 1e-3, weight_decay: float = 1e-10,
-                 checkpoint: bool = True, dice_alpha: float | None = None):
-        """dice_alpha: train on the paper's weighted Dice term (with that alpha) instead of BCE."""
+                 checkpoint: bool = True, dice_alpha: float | None = None, batch_wgrad: bool | None = None):
+        """dice_alpha: train on the paper's weighted Dice term (with that alpha) instead of BCE;
+        batch_wgrad: the backward's weight gradients in one launch after the data gradients, or
+        per layer on side streams (None: as Network.backward chooses for the precision)."""
         self.net = net
         self.dice_alpha = dice_alpha
         self.dims = [tuple(g) for g in dims]
         self.n_tris = list(n_tris)
         self.lam, self.lr, self.wd = lam, lr, weight_decay
         self.checkpoint = checkpoint
+        self.batch_wgrad = batch_wgrad
         self.m = torch.zeros_like(net.flat)
         self.v = torch.zeros_like(net.flat)
         self.adam_step = torch.zeros(16, dtype=torch.uint8, device=net.flat.device)  # npvs_adam_step, t = 0
@@ -193,7 +228,7 @@ class Trainer:
         pvs, _ = deinterleave_threshold(logits, rb, occ)
         labels = gather_input(label_bits, rb, NPVS_U8)
         stats, dl = loss(logits, labels, rb, self.lam, dice_alpha=self.dice_alpha)
-        net.backward(saved, logits, dl, rb)  # gradients land in net.gflat
+        net.backward(saved, logits, dl, rb, batch_wgrad=self.batch_wgrad)  # gradients land in net.gflat
         self.step_count += 1
         # Adam, writing the updated weights straight into both packings of every layer
         adam(net.flat, net.gflat, self.m, self.v, self.adam_step, net.pack_descs(), net.dtype, lr=self.lr,

@@ -36,9 +36,10 @@ def test_version_and_sizes(lib):
 def test_header_constants_match_binding():
     text = open(L.HEADER).read()
     for name in ("NPVS_MAX_GRIDS", "NPVS_MAX_PACK", "NPVS_CONV_VARIANTS", "NPVS_DEFAULT_CONV_VARIANT",
-                 "NPVS_LOSS_BCE", "NPVS_LOSS_DICE", "NPVS_MAX_ADAM_PACK"):
+                 "NPVS_LOSS_BCE", "NPVS_LOSS_DICE", "NPVS_MAX_ADAM_PACK", "NPVS_MAX_WGRAD_LAYERS"):
         assert f"#define {name} {getattr(L, name)}" in text, name
     assert ctypes.sizeof(L.PackDesc) == 32 and ctypes.sizeof(L.Counts) == 16 and ctypes.sizeof(L.AdamPackDesc) == 32
+    assert ctypes.sizeof(L.WgradLayer) == 48
     assert "int64_t t;\n  float c1, c2;\n} npvs_adam_step;" in text  # 16 bytes, as the binding assumes
 
 
@@ -70,6 +71,30 @@ def test_conv_workspace_sizes_and_checks(lib):
     bad = list(bwd)
     bad[1] = 60  # BF16 needs multiples of 8
     assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_UNSUPPORTED
+    bad = list(bwd)
+    bad[15] = None  # dW given, db null
+    assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_INVALID_ARG and b"both" in lib.npvs_last_error()
+
+
+def test_batched_weight_gradient_argument_checks(lib):
+    fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
+    n = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_workspace_size", 64, 64, 1000, L.NPVS_BF16, ctypes.byref(n))
+
+    def call(descs, nl=None, dtype=L.NPVS_BF16, slices=0, rb=fake):
+        arr = (L.WgradLayer * len(descs))(*descs) if descs else None
+        return lib.npvs_sparse_conv_wgrad(len(descs) if nl is None else nl, arr, rb, fake, 1000, dtype, slices, None)
+
+    good = L.WgradLayer(16, 64, 64, 16, n.value, 16, 16)
+    assert call([], nl=0) == L.NPVS_ERR_INVALID_ARG
+    assert call([good] * (L.NPVS_MAX_WGRAD_LAYERS + 1)) == L.NPVS_ERR_INVALID_ARG
+    assert call([good], rb=None) == L.NPVS_ERR_INVALID_ARG and b"null" in lib.npvs_last_error()
+    assert call([good], dtype=L.NPVS_U8) == L.NPVS_ERR_INVALID_ARG and b"dtype" in lib.npvs_last_error()
+    assert call([good], slices=-1) == L.NPVS_ERR_INVALID_ARG
+    assert call([good, L.WgradLayer(16, 64, 64, 16, n.value, 16, None)]) == L.NPVS_ERR_INVALID_ARG
+    assert call([L.WgradLayer(16, 64, 64, 16, n.value - 1, 16, 16)]) == L.NPVS_ERR_INVALID_ARG
+    assert b"workspace" in lib.npvs_last_error()
+    assert call([L.WgradLayer(16, 60, 64, 16, n.value, 16, 16)]) == L.NPVS_ERR_UNSUPPORTED
 
 
 def test_batched_packing_argument_checks(lib):

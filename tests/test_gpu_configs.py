@@ -32,14 +32,14 @@ def _train_setup():
     return cfg, tri_list, labels
 
 
-def _grads(net, tris, counts, dims, lab_bits, checkpoint, overlap=True):
+def _grads(net, tris, counts, dims, lab_bits, checkpoint, **backward_kw):
     occ = npvs.froxelize(tris, counts, dims)
     rb = npvs.build_rulebook(occ, dims, net.d, csr=True)
     X0 = npvs.gather_input(occ, rb, net.dtype)
     logits, saved = net.forward(X0, rb, checkpoint=checkpoint)
     labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
     stats, dl = npvs.loss(logits, labels, rb)
-    grads = net.backward(saved, logits, dl, rb, overlap=overlap)
+    grads = net.backward(saved, logits, dl, rb, **backward_kw)
     # the gradients are views of the network's flat gradient buffer: keep copies
     return stats, [(a.clone(), b.clone()) for a, b in grads], rb
 
@@ -93,16 +93,23 @@ def test_weight_gradient_on_side_stream_gives_identical_gradients(dtype):
     tris, counts = upload_tris(tri_list)
     lab_bits = torch.from_numpy(np.concatenate([l.reshape(-1) for l in labels])).to(DEV)
     net = Network(layers, cfg.d, dtype)
-    _, g1, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, overlap=True)
-    _, g2, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, overlap=False)
-    for (a, b), (c, d) in zip(g1, g2):
+    _, g1, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, batch_wgrad=False, overlap=True)
+    _, g2, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, batch_wgrad=False, overlap=False)
+    # every layer's weight gradient in one launch after the data gradients, at the single-layer
+    # slice count
+    _, g3, _ = _grads(net, tris, counts, cfg.grids, lab_bits, checkpoint=True, batch_wgrad=True, wgrad_slices=16)
+    for (a, b), (c, d), (e, f) in zip(g1, g2, g3):
         np.testing.assert_array_equal(to_np(a), to_np(c))
         np.testing.assert_array_equal(to_np(b), to_np(d))
+        np.testing.assert_array_equal(to_np(a), to_np(e))
+        np.testing.assert_array_equal(to_np(b), to_np(f))
 
 
-def test_captured_training_step_replays_equal_eager_steps():
-    """A training step captured in a graph (two streams, device-side Adam counter) and replayed
-    three times ends in the same weights and moments as three eager steps."""
+@pytest.mark.parametrize("batch_wgrad", [True, False])
+def test_captured_training_step_replays_equal_eager_steps(batch_wgrad):
+    """A training step captured in a graph (device-side Adam counter) and replayed three times
+    ends in the same weights and moments as three eager steps, with the weight gradients batched
+    after the data gradients (the default) and with them on side streams."""
     cfg, tri_list, labels = _train_setup()
     layers = synth.net_layers(cfg, bias_std=0.05)
     tris, counts = upload_tris(tri_list)
@@ -110,7 +117,7 @@ def test_captured_training_step_replays_equal_eager_steps():
     trainers = []
     for _ in range(2):
         net = Network(layers, cfg.d, npvs.NPVS_BF16)
-        trainers.append(Trainer(net, cfg.grids, counts))
+        trainers.append(Trainer(net, cfg.grids, counts, batch_wgrad=batch_wgrad))
     eager, graphed = trainers
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())

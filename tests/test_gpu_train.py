@@ -242,6 +242,58 @@ def test_backward_side_streams_change_nothing(dtype):
             np.testing.assert_array_equal(to_np(a), to_np(b))
 
 
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_batched_weight_gradient_matches_per_layer(dtype):
+    """Every layer's backward with the weight gradient deferred (dW = db = NULL), then one
+    npvs_sparse_conv_wgrad over all layers: with the single-layer slice count (16) dX, dW and db
+    equal the per-layer backward bit for bit; with other slice counts only the grouping of the
+    float32 sums changes, so dW stays within 2^-15 sum_p |x_p| |dz_p| of it (each side's error is
+    at most a 128-term float32 chunk sum, gamma_128 < 2^-16, of that magnitude) and db is
+    unchanged."""
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    acts = _gpu_forward(occ, rb, layers, dtype)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    _, dl = npvs.loss(acts[-1], labels, rb)
+    n = rb.host_counts()["n_sites"]
+    ref, pending, mags = {}, [], {}
+    off = to_np(rb.rb_off).astype(np.int64)
+    pairs = to_np(rb.rb_pairs).reshape(-1, 2)
+    dY = dl
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        cin, cout = W.shape[1], W.shape[2]
+        Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), dtype, flip_transpose=True)
+        args = (acts[li], Wt, cin, cout, acts[li + 1], dY, rb, dtype)
+        kw = dict(relu=li < len(layers) - 1, want_dx=li > 0)
+        dX, dW, db = npvs.sparse_conv_bwd(*args, **kw)
+        ws = npvs.conv_bwd_workspace(cin, cout, rb, dtype)
+        dX2, dW2, db2 = npvs.sparse_conv_bwd(*args, **kw, ws=ws, want_dw=False)
+        assert dW2 is None and db2 is None
+        if dX is not None:
+            np.testing.assert_array_equal(to_np(dX)[:n], to_np(dX2)[:n])
+        ref[li] = (to_np(dW), to_np(db))
+        pending.append((acts[li], cin, cout, ws, torch.empty_like(dW), torch.empty_like(db)))
+        # sum over each offset's pairs of |X[i]| |dZ[r]| (|dZ| <= |dY|, bf16 rounding of dZ inside 1 %)
+        ax = np.abs(to_np(acts[li][:n]).astype(np.float64))  # rows past n_sites: undefined
+        ag = 1.01 * np.abs(to_np(dY[:n]).astype(np.float64))
+        mags[li] = np.stack([ax[pairs[off[k]:off[k + 1], 0]].T @ ag[pairs[off[k]:off[k + 1], 1]] for k in range(27)])
+        dY = dX
+    order = list(range(len(layers) - 1, -1, -1))
+    for slices in (16, 0, 1, 3):
+        for _, _, _, _, gW, gb in pending:
+            gW.fill_(float("nan"))
+            gb.fill_(float("nan"))
+        npvs.sparse_conv_wgrad(pending, rb, dtype, slices=slices)
+        torch.cuda.synchronize()
+        for li, (_, _, _, _, gW, gb) in zip(order, pending):
+            if slices == 16:
+                np.testing.assert_array_equal(to_np(gW), ref[li][0])
+            else:
+                err = np.abs(to_np(gW).astype(np.float64) - ref[li][0])
+                assert np.all(err <= 2.0 ** -15 * mags[li] + 1e-30), (slices, li, float(err.max()))
+            np.testing.assert_array_equal(to_np(gb), ref[li][1])
+
+
 def test_backward_on_an_empty_grid_is_zero():
     cfg = synth.config("tiny32")
     layers = synth.net_layers(cfg, bias_std=0.05)
