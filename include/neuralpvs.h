@@ -293,12 +293,16 @@ npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int
  *   npvs_sparse_conv_bwd call of that layer with dW = db = NULL left its dZ and bias partials in
  *   (same cin, cout, cap_sites, dtype; its slice partials are overwritten here); dW / db (device)
  *   float32 [27][cin][cout] / [cout], overwritten.
- *   rb_off / rb_pairs: the CSR rulebook of those backward calls.  slices: pair-list slices per
- *   offset (0: the library's choice; at most the single-layer count, which is used when larger).
- *   Results equal npvs_sparse_conv_bwd's dW / db computed with the same slice count (the
- *   single-layer call uses 16 slices for layers of at most 64 x 64 channels).  The FP32 path
- *   takes one weight-gradient launch per layer, each with that layer's single-layer slice count
- *   (or `slices` when smaller), and one reduction launch.
+ *   rb_off / rb_pairs: the CSR rulebook of those backward calls.
+ *   slices > 0: each offset's pair list is cut into that many slices (at most the single-layer
+ *   count, which is used when larger), and the results equal npvs_sparse_conv_bwd's dW / db
+ *   computed with the same slice count bit for bit (the single-layer call uses 16 slices for
+ *   layers of at most 64 x 64 channels).  slices = 0 (BF16): the whole pair list of the 27
+ *   offsets is cut into equal ranges, one per workgroup (as many as run at once), so that an
+ *   offset with more pairs (the centre one pairs every site with itself) does not make its
+ *   workgroups the last to finish; the sums are the same up to float32 regrouping.  The FP32
+ *   path takes one weight-gradient launch per layer, each with that layer's single-layer slice
+ *   count (or `slices` when smaller), and one reduction launch.
  * Why: a layer's weight gradient is a short latency-bound kernel; issued one layer at a time it
  * forms a serial chain behind the data gradients of the layers below, whereas all layers at once
  * fill the chip and pay the launch and memory round trips once (Sec. 3.3 trains the stack end to

@@ -260,6 +260,7 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
 // current chunk's products run, then stored into the other LDS buffer.  Each chunk's product
 // starts from zero and is added into a compensated total.
 constexpr int kWgChunk = 128;
+constexpr int kMaxWgOffsets = 27;  // offsets of one pair list (27 for 3^3 layers, 8 for strided ones)
 constexpr int kWgPitch = kWgChunk + 16;  // bf16 elements per LDS row (padding spreads banks)
 constexpr int kWgQuads = kWgChunk / 4;
 
@@ -335,25 +336,75 @@ struct WgBatch {
   WgLayer L[kMaxWgradLayers];
 };
 
+// A chunk: pairs [pb, pb + m) of offset k; `last` when it ends the workgroup's part of offset k
+// (the partial sum of that offset is then written out).
+struct WgChunk {
+  int pb, m, k;
+  bool last;
+};
+
+// Sliced form (G = 0): grid (S, K, windows); workgroup (s, k) takes slice s of offset k's pairs
+// and writes partial slot k S + s.  Balanced form (G > 0): grid (G, 1, windows); with P pairs in
+// the whole list of the K offsets and L = ceil(P / G), workgroup g takes pairs [g L, (g + 1) L)
+// (clipped to P), so every workgroup has the same number of pairs whatever their spread over
+// the offsets, and writes the partial of each offset k its range meets to slot g + k.  The pair
+// list is ordered by offset, so a later workgroup only meets the same or later offsets: no two
+// (g, k) written share a slot, and the slots number at most G + K - 1.  The workgroups that
+// meet offset k (pairs [a, b)) are g = a / L .. (b - 1) / L, which is how the reduction finds
+// them.
 __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const int32_t *__restrict__ rb_off,
-                                                          const int32_t *__restrict__ pairs) {
+                                                          const int32_t *__restrict__ pairs, int G, int K) {
   // two staging buffers: chunk ch is read from buffer ch & 1 while chunk ch + 1 is written to the
   // other one, so one barrier per chunk orders both
   __shared__ __attribute__((aligned(16))) uint16_t XT[2][64 * kWgPitch];
   __shared__ __attribute__((aligned(16))) uint16_t GT[2][64 * kWgPitch];
+  __shared__ int offs[kMaxWgOffsets + 1];
   int li = 0;
   for (int i = 1; i < B.n; ++i) li = (int)blockIdx.z >= B.L[i].z0 ? i : li;
   const uint16_t *__restrict__ X = B.L[li].X;
   const uint16_t *__restrict__ dZ16 = B.L[li].dZ;
   float *__restrict__ part = B.L[li].part;
   const int cin = B.L[li].cin, cout = B.L[li].cout, z = (int)blockIdx.z - B.L[li].z0;
-  const int k = blockIdx.y, s = blockIdx.x, S = gridDim.x, tid = threadIdx.x, lane = tid & 63;
+  const int s = blockIdx.x, S = gridDim.x, tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform (scalar)
   const int otiles = (cout + 63) / 64;
   const int c0 = 64 * (z / otiles), o0 = 64 * (z % otiles);
   const int cw = cin - c0 < 64 ? cin - c0 : 64, ow = cout - o0 < 64 ? cout - o0 : 64;  // window size
-  const int64_t pk0 = rb_off[k], pk = (int64_t)rb_off[k + 1] - pk0;
-  const int64_t p0 = pk0 + pk * s / S, p1 = pk0 + pk * (s + 1) / S;
+  if (tid <= K) offs[tid] = rb_off[tid];
+  __syncthreads();
+  // this workgroup's pairs [pA, pB) and the offset of its first pair
+  int pA, pB, k0;
+  if (G > 0) {
+    const int64_t P = offs[K] - offs[0], L = (P + G - 1) / G;
+    const int64_t a = (int64_t)s * L, b = a + L;
+    pA = offs[0] + (int)(a < P ? a : P);
+    pB = offs[0] + (int)(b < P ? b : P);
+    k0 = 0;
+    while (k0 + 1 < K && offs[k0 + 1] <= pA) ++k0;
+  } else {
+    k0 = blockIdx.y;
+    const int64_t pk = offs[k0 + 1] - offs[k0];
+    pA = offs[k0] + (int)(pk * s / S);
+    pB = offs[k0] + (int)(pk * (s + 1) / S);
+  }
+  // chunks in order: at most kWgChunk pairs, never across an offset boundary
+  auto next_chunk = [&](int &p, int &k) {
+    const int end = pB < offs[k + 1] ? pB : offs[k + 1];
+    const int m = end - p < kWgChunk ? end - p : kWgChunk;
+    const WgChunk c{p, m, k, p + m == end};
+    p += m;
+    if (c.last)
+      while (k + 1 < K && offs[k + 1] <= p) ++k;  // past the end of offset k (and empty offsets)
+    return c;
+  };
+  int nch = 0;
+  {
+    int p = pA, k = k0;
+    while (p < pB) {
+      next_chunk(p, k);
+      ++nch;
+    }
+  }
   const int CB = (cw + 15) / 16, OB = (ow + 15) / 16, nblk = CB * OB;
   const int cin8 = (cw + 7) / 8, cout8 = (ow + 7) / 8;
   // rows are read from the window's first channel on; the row pitch stays cin / cout
@@ -385,24 +436,46 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int i = 0; i < 4; ++i) tot[j][i] = Comp{0.0f, 0.0f};
-  const int nch = (int)((p1 - p0 + kWgChunk - 1) / kWgChunk);
-  auto chunk_m = [&](int ch) {
-    const int64_t left = p1 - (p0 + (int64_t)ch * kWgChunk);
-    return left < kWgChunk ? (int)left : kWgChunk;
+  // the partial of offset k goes to slot k S + s (sliced) or s + k (balanced, s = g)
+  auto write_partial = [&](int k, const Comp(&t)[4][4], bool zero) {
+    const int64_t slot = G > 0 ? (int64_t)s + k : (int64_t)k * S + s;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int blk = wv + 4 * j;
+      if (blk < nblk) {
+        const int mb = blk / OB, nb = blk % OB;
+        const int o = nb * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = mb * 16 + 4 * (lane >> 4) + i;
+          if (c < cw && o < ow) part[(slot * cin + c0 + c) * cout + o0 + o] = zero ? 0.0f : t[j][i].value();
+        }
+      }
+    }
   };
+  // an empty slice of the sliced form still writes its (zero) slot, which the reduction reads;
+  // the balanced form's reduction reads only the slots of ranges that meet an offset
+  if (nch == 0) {
+    if (G == 0) write_partial(k0, tot, true);
+    return;
+  }
+  // chunk descriptors: q0 = chunk ch, q1 = ch + 1, q2 = ch + 2; the prefetches past the last
+  // chunk re-read the last chunk (no branch around a load)
+  int gp = pA, gk = k0;
+  WgChunk q0 = next_chunk(gp, gk);
+  WgChunk q1 = nch > 1 ? next_chunk(gp, gk) : q0;
+  WgChunk q2 = nch > 2 ? next_chunk(gp, gk) : q1;
   int rn[2][4];
-  if (nch > 0) {  // an empty slice loads nothing (p0 may be the end of the pair list)
+  {
     uint4 v[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      wg_indices(pairs, p0, chunk_m(0), task[u], rn[u]);
+      wg_indices(pairs, q0.pb, q0.m, task[u], rn[u]);
       wg_gather(Xw, cin, Gw, cout, task[u], rn[u], v[u]);
     }
-    // the prefetches past the last chunk re-read the last chunk (no branch around a load)
-    const int c1 = nch > 1 ? 1 : 0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      wg_indices(pairs, p0 + (int64_t)c1 * kWgChunk, chunk_m(c1), task[u], rn[u]);
+      wg_indices(pairs, q1.pb, q1.m, task[u], rn[u]);
       wg_store(XT[0], GT[0], task[u], v[u]);
     }
   }
@@ -412,9 +485,8 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
     uint4 v[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u) wg_gather(Xw, cin, Gw, cout, task[u], rn[u], v[u]);  // chunk ch + 1
-    const int c2 = ch + 2 < nch ? ch + 2 : nch - 1;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) wg_indices(pairs, p0 + (int64_t)c2 * kWgChunk, chunk_m(c2), task[u], rn[u]);
+    for (int u = 0; u < 2; ++u) wg_indices(pairs, q2.pb, q2.m, task[u], rn[u]);
     f32x4_t acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
@@ -437,23 +509,20 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int i = 0; i < 4; ++i) tot[j][i].add(acc[j][i]);
+    if (q0.last) {  // the end of this workgroup's part of offset q0.k
+      write_partial(q0.k, tot, false);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tot[j][i] = Comp{0.0f, 0.0f};
+    }
+    q0 = q1;
+    q1 = q2;
+    if (ch + 3 < nch) q2 = next_chunk(gp, gk);
     // the other buffer was last read in chunk ch - 1, before the barrier that ended it
 #pragma unroll
     for (int u = 0; u < 2; ++u) wg_store(XT[cur ^ 1], GT[cur ^ 1], task[u], v[u]);
     __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int blk = wv + 4 * j;
-    if (blk < nblk) {
-      const int mb = blk / OB, nb = blk % OB;
-      const int o = nb * 16 + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = mb * 16 + 4 * (lane >> 4) + i;
-        if (c < cw && o < ow) part[((int64_t)(k * S + s) * cin + c0 + c) * cout + o0 + o] = tot[j][i].value();
-      }
-    }
   }
 }
 
@@ -462,7 +531,7 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
 struct RdLayer {
   const float *wpart, *dbpart;
   float *dW, *db;
-  int cin, cout, nbw, b0, S;  // S: slices per offset of this layer's partials
+  int cin, cout, nbw, b0, S;  // S: slices per offset of this layer's partials (sliced form)
 };
 struct RdBatch {
   int n;
@@ -472,8 +541,10 @@ struct RdBatch {
 // Per layer: blocks [0, nbw) reduce dW (K offsets) over the slices (grid-stride, one entry per
 // thread); each block after them reduces db over the nparts partial rows for 4 channels, one wave
 // per channel: lane l adds partials l, l + 64, ..., then a fixed butterfly adds the 64 lane totals;
-// lane 0 writes.
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const RdBatch B, int nparts, int K) {
+// lane 0 writes.  G > 0: the partials are those of the balanced weight-gradient form with G
+// workgroups per window over the pair list rb_off (see wgrad_bf16_kernel), added in the order of g.
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const RdBatch B, int nparts, int K, int G,
+                                                           const int32_t *__restrict__ rb_off) {
   int li = 0;
   for (int i = 1; i < B.n; ++i) li = (int)blockIdx.x >= B.L[i].b0 ? i : li;
   const float *__restrict__ wpart = B.L[li].wpart;
@@ -482,6 +553,24 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const RdBatch B, int n
   float *__restrict__ db = B.L[li].db;
   const int cin = B.L[li].cin, cout = B.L[li].cout, nbw = B.L[li].nbw, S = B.L[li].S;
   const int bx = (int)blockIdx.x - B.L[li].b0;
+  if (bx < nbw && G > 0) {
+    const int64_t E = (int64_t)cin * cout;
+    const int off0 = rb_off[0];
+    const int64_t P = rb_off[K] - off0;
+    const uint32_t L = (uint32_t)((P + G - 1) / G);
+    for (int64_t e = (int64_t)bx * blockDim.x + threadIdx.x; e < K * E; e += (int64_t)nbw * blockDim.x) {
+      const int k = (int)(e / E);
+      const int64_t ce = e - k * E;
+      const int a = rb_off[k] - off0, b = rb_off[k + 1] - off0;
+      Comp t{0.0f, 0.0f};
+      if (a < b) {
+        const int g1 = (int)((uint32_t)(b - 1) / L);
+        for (int g = (int)((uint32_t)a / L); g <= g1; ++g) t.add(wpart[(int64_t)(g + k) * E + ce]);
+      }
+      dW[e] = t.value();
+    }
+    return;
+  }
   if (bx < nbw) {
     const int64_t E = (int64_t)cin * cout;
     for (int64_t e = (int64_t)bx * blockDim.x + threadIdx.x; e < K * E; e += (int64_t)nbw * blockDim.x) {
@@ -529,7 +618,7 @@ npvs_status bwd_wgrad(int32_t dtype, const void *X, int32_t cin, const void *dZ,
     WgBatch B{};
     B.n = 1;
     B.L[0] = WgLayer{(const uint16_t *)X, (const uint16_t *)dZ, wpart, cin, cout, 0};
-    wgrad_bf16_kernel<<<dim3(S, K, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s>>>(B, rb_off, pairs);
+    wgrad_bf16_kernel<<<dim3(S, K, ((cin + 63) / 64) * ((cout + 63) / 64)), 256, 0, s>>>(B, rb_off, pairs, 0, K);
   }
   return check_hip(hipGetLastError(), "backward: weight gradient");
 }
@@ -544,7 +633,7 @@ npvs_status bwd_reduce(const float *wpart, const float *dbpart, int nparts, int3
   RdBatch B{};
   B.n = 1;
   B.L[0] = RdLayer{wpart, dbpart, dW, db, cin, cout, nbw, 0, S};
-  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s>>>(B, nparts, K);
+  grad_reduce_kernel<<<nbw + (cout + 3) / 4, 256, 0, s>>>(B, nparts, K, 0, nullptr);
   return check_hip(hipGetLastError(), "backward: reductions");
 }
 
@@ -689,10 +778,16 @@ extern "C" npvs_status npvs_sparse_conv_wgrad(int32_t n_layers, const npvs_wgrad
     S = sl < S ? sl : S;
     windows += ((l.cin + 63) / 64) * ((l.cout + 63) / 64);
   }
-  if (slices > 0) S = slices < S ? slices : S;
-  else {  // at most kWgBatchBlocks workgroups in all, so that they run in one round
-    const int want = kWgBatchBlocks / (27 * windows);
-    S = want < S ? (want < 1 ? 1 : want) : S;
+  // BF16 with slices = 0: the balanced form, at most kWgBatchBlocks workgroups in all so that they
+  // run in one round, and at most as many per window as the partial slots allow (G + 26 slots of
+  // the 27 S the workspace holds); otherwise the sliced form with `slices` slices per offset
+  int G = 0;
+  if (slices > 0) {
+    S = slices < S ? slices : S;
+  } else if (dtype == NPVS_BF16) {
+    const int want = kWgBatchBlocks / windows, cap = 27 * S - 26;
+    G = want < cap ? want : cap;
+    G = G < 1 ? 1 : G;
   }
   const hipStream_t s = as_stream(stream);
   WgBatch W{};
@@ -722,10 +817,11 @@ extern "C" npvs_status npvs_sparse_conv_wgrad(int32_t n_layers, const npvs_wgrad
     b0 += nbw + (l.cout + 3) / 4;
   }
   if (dtype == NPVS_BF16) {
-    wgrad_bf16_kernel<<<dim3(S, 27, z0), 256, 0, s>>>(W, rb_off, rb_pairs);
+    const dim3 grid = G > 0 ? dim3(G, 1, z0) : dim3(S, 27, z0);
+    wgrad_bf16_kernel<<<grid, 256, 0, s>>>(W, rb_off, rb_pairs, G, 27);
     const npvs_status st = check_hip(hipGetLastError(), "npvs_sparse_conv_wgrad: weight gradient");
     if (st != NPVS_OK) return st;
   }
-  grad_reduce_kernel<<<b0, 256, 0, s>>>(R, kDbBlocks, 27);
+  grad_reduce_kernel<<<b0, 256, 0, s>>>(R, kDbBlocks, 27, G, rb_off);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_wgrad: reductions");
 }

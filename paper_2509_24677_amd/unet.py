@@ -24,7 +24,8 @@ import torch
 
 from . import (NPVS_BF16, NPVS_F32, Levels, build_levels, concat_channels, concat_channels_bwd, conv_bwd_workspace,
                deinterleave_threshold, froxelize, gather_input, pack_weights, pack_weights_k, sparse_conv_bwd,
-               sparse_conv_fwd, strided_conv_bwd, strided_conv_fwd)
+               sparse_conv_fwd, sparse_conv_wgrad, strided_conv_bwd, strided_conv_fwd)
+from ._lib import NPVS_MAX_WGRAD_LAYERS
 
 STAGES = ("stem", "enc0", "down", "enc1", "up", "dec0", "head")
 
@@ -100,18 +101,23 @@ class UNet:
         return self.Wt[(st, i)]
 
     def backward(self, saved: dict, logits: torch.Tensor, dlogits: torch.Tensor, lv: Levels,
-                 overlap: bool = True) -> dict:
+                 overlap: bool = True, batch_wgrad: bool = False, wgrad_slices: int = 0) -> dict:
         """Gradients {stage: [(dW, db), ...]} (float32) of the loss whose gradient with respect to
         the logits rows is `dlogits` (float32 [rb0.cap][d^3]), through the activations kept by
         forward(saved=...).  The levels must carry CSR rulebooks (build_levels(csr=True)).  With
-        `overlap`, the weight gradients of the 3^3 layers run on a side stream (their final
-        reductions on a third) while the data gradients continue; both are joined before
-        returning."""
+        `batch_wgrad`, the weight gradients of the 3^3 layers are deferred and computed after the
+        data gradients, those of each level's layers in one launch (up to 16 per launch;
+        `wgrad_slices` pair-list slices per offset, 0 for the library's choice).  It is not the
+        default: the decoder's wider layers give a level about 15 channel windows, so the
+        one-round launch has a single slice per offset and window, and the per-layer form is
+        faster.  Otherwise, with `overlap`, they run on a side stream (their final reductions on
+        a third) while the data gradients continue; both are joined before returning."""
         dt = self.dtype
         rb0, rb1 = lv.rb0, lv.rb1
+        pending = {id(rb0): [], id(rb1): []}  # deferred weight gradients per rulebook
         main = torch.cuda.current_stream()
         side = side2 = None
-        if overlap:
+        if overlap and not batch_wgrad:
             if getattr(self, "_side", None) is None:
                 self._side, self._side2 = torch.cuda.Stream(), torch.cuda.Stream()
             side, side2 = self._side, self._side2
@@ -127,8 +133,13 @@ class UNet:
                 ws = conv_bwd_workspace(cin, cout, rb, dt)
                 dX, dW, db = sparse_conv_bwd(saved[st][i], self._wt(st, i), cin, cout, outs[st][i], dY, rb, dt,
                                              relu=not last_is_head, want_dx=want_dx or i > 0, ws=ws,
-                                             wgrad_stream=side, reduce_stream=side2)
+                                             wgrad_stream=side, reduce_stream=side2, want_dw=not batch_wgrad)
                 in_use.extend((ws, saved[st][i]))
+                if batch_wgrad:
+                    dev = dY.device
+                    dW = torch.empty((27, cin, cout), dtype=torch.float32, device=dev)
+                    db = torch.empty(cout, dtype=torch.float32, device=dev)
+                    pending[id(rb)].append((saved[st][i], cin, cout, ws, dW, db))
                 grads[st][i] = (dW, db)
                 dY = dX
             return dY
@@ -147,6 +158,10 @@ class UNet:
         _, dS = concat_channels_bwd(dH, Dc, E, rb0, add_b=dX0, want_a=False)
         dS = subm_chain("enc0", dS, rb0)
         subm_chain("stem", dS, rb0, want_dx=False)
+        for rb in (rb0, rb1):
+            todo = pending[id(rb)]
+            for j in range(0, len(todo), NPVS_MAX_WGRAD_LAYERS):
+                sparse_conv_wgrad(todo[j:j + NPVS_MAX_WGRAD_LAYERS], rb, dt, wgrad_slices)
         if side is not None:
             main.wait_stream(side)
             main.wait_stream(side2)

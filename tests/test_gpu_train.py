@@ -295,6 +295,8 @@ def test_batched_weight_gradient_matches_per_layer(dtype):
 
 
 def test_backward_on_an_empty_grid_is_zero():
+    """No active sites: every gradient is zero, per layer and with the weight gradients batched
+    (both forms; the outputs start as NaN, so each entry must be written)."""
     cfg = synth.config("tiny32")
     layers = synth.net_layers(cfg, bias_std=0.05)
     tris, counts = upload_tris([np.zeros((0, 3, 3), np.float32)])
@@ -305,6 +307,18 @@ def test_backward_on_an_empty_grid_is_zero():
     dl = torch.zeros((rb.cap, cfg.channels[-1]), dtype=torch.float32, device=DEV)
     for dW, db in _gpu_backward(acts, rb, layers, npvs.NPVS_BF16, dl):
         assert not dW.any() and not db.any()
+    W, _ = layers[1]
+    cin, cout = W.shape[1], W.shape[2]
+    Wt = npvs.pack_weights(torch.from_numpy(W).to(DEV), npvs.NPVS_BF16, flip_transpose=True)
+    ws = npvs.conv_bwd_workspace(cin, cout, rb, npvs.NPVS_BF16)
+    npvs.sparse_conv_bwd(acts[1], Wt, cin, cout, acts[2], dl[:, :cout].contiguous(), rb, npvs.NPVS_BF16, relu=True,
+                         ws=ws, want_dw=False)
+    for slices in (0, 3):
+        gW = torch.full((27, cin, cout), float("nan"), device=DEV)
+        gb = torch.full((cout,), float("nan"), device=DEV)
+        npvs.sparse_conv_wgrad([(acts[1], cin, cout, ws, gW, gb)], rb, npvs.NPVS_BF16, slices=slices)
+        torch.cuda.synchronize()
+        assert not gW.isnan().any() and not gW.any() and not gb.any()
 
 
 def test_adam_matches_oracle():
@@ -336,8 +350,9 @@ def test_adam_with_device_step_equals_host_step():
 
 def test_city256_training_gradients_at_full_size():
     """The benchmark's workload at full size (256x256x128 city frame, six 64-channel layers, the
-    launch configuration of its training step: per-layer backward with the weight gradients on
-    side streams).  FP32 against the oracle's FP64 forward and backward: every dW and db within
+    launch configuration of its training step: BF16 with the weight gradients of all layers in
+    one balanced launch after the data gradients, FP32 per layer on side streams; BF16 per layer
+    as well).  FP32 against the oracle's FP64 forward and backward: every dW and db within
     2e-4 of the largest entry.  BF16 against the oracle's BF16 network (forward_bf16 /
     backward_bf16, the same rounding points, labels from the oracle's occupancy): every dW and db
     within DRIFT_FACTOR times the oracle's own drift between two evaluation orders."""
@@ -357,11 +372,11 @@ def test_city256_training_gradients_at_full_size():
     ref_dl = oracle.loss(out["acts"][-1], ref_lab)["grad"]
     ref, _ = oracle.backward(out, layers, ref_dl)
     rbf = bf16_reference(t, cfg.grids[0], cfg.d, layers, occ=out["occ"], labels_mask=label_mask)
-    for dtype in (npvs.NPVS_F32, npvs.NPVS_BF16):
+    for dtype, batch in ((npvs.NPVS_F32, None), (npvs.NPVS_BF16, None), (npvs.NPVS_BF16, False)):
         net = Network(layers, cfg.d, dtype)
         logits, saved = net.forward(npvs.gather_input(occ, rb, dtype), rb)
         _, dl = npvs.loss(logits, labels, rb)
-        grads = [(to_np(a), to_np(b)) for a, b in net.backward(saved, logits, dl, rb)]
+        grads = [(to_np(a), to_np(b)) for a, b in net.backward(saved, logits, dl, rb, batch_wgrad=batch)]
         for li in range(len(layers)):
             for j, nm in ((0, "dW"), (1, "db")):
                 a = grads[li][j]
@@ -371,7 +386,7 @@ def test_city256_training_gradients_at_full_size():
                 b, b32 = rbf["g"][li][j], rbf["g32"][li][j]
                 tol = drift_tol(b, b32)
                 err = np.abs(a - b).max()
-                print(f"city256 bf16 layer {li} {nm}: max err {err:.3e}, tolerance {tol:.3e} "
+                print(f"city256 bf16 (batched {batch is None}) layer {li} {nm}: max err {err:.3e}, tolerance {tol:.3e} "
                       f"({tol / np.abs(b).max():.2e} of the largest entry)", flush=True)
                 assert tol > 0 and err <= tol, (li, nm)
 

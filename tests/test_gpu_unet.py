@@ -256,6 +256,31 @@ def test_unet_backward_matches_oracle(dtype):
                     assert tol > 0 and err <= tol, (st, i, nm)
 
 
+@pytest.mark.parametrize("dtype", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_unet_batched_weight_gradients_equal_per_layer(dtype):
+    """The 3^3 layers' weight gradients deferred and batched per level (at the single-layer slice
+    count) give the per-layer side-stream backward's gradients bit for bit."""
+    cfg = synth.config("tiny32")
+    t = synth.scene_for(cfg)
+    params = synth.unet_params(6, 2, E=16, Dc=24)
+    tris, counts = upload_tris([t])
+    occ = npvs.froxelize(tris, counts, cfg.grids)
+    lv = npvs.build_levels(occ, cfg.grids, 2, csr=True)
+    lab_bits = torch.from_numpy(to_np(occ) & synth.label_mask_bits(5, (to_np(occ).size,))).to(DEV)
+    labels = npvs.gather_input(lab_bits, lv.rb0, npvs.NPVS_U8)
+    net = UNet(params, 2, dtype)
+    saved = {}
+    logits = net.forward(npvs.gather_input(occ, lv.rb0, dtype), lv, saved=saved)
+    _, dl = npvs.loss(logits, labels, lv.rb0)
+    per_layer = net.backward(saved, logits, dl, lv, overlap=True)
+    batched = net.backward(saved, logits, dl, lv, batch_wgrad=True, wgrad_slices=16)
+    torch.cuda.synchronize()
+    for st in per_layer:
+        for (a, b), (c, e) in zip(per_layer[st], batched[st]):
+            np.testing.assert_array_equal(to_np(a), to_np(c))
+            np.testing.assert_array_equal(to_np(b), to_np(e))
+
+
 def test_unet_backward_on_an_empty_grid_is_zero():
     """No triangles: no active sites on either level; every gradient is zero (the strided layers'
     pair lists are empty, every slice partial is zero)."""
