@@ -13,6 +13,7 @@ namespace npvs {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 
 
 struct Comp {  // Neumaier-compensated float sum
@@ -405,7 +406,8 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
       ++nch;
     }
   }
-  const int CB = (cw + 15) / 16, OB = (ow + 15) / 16, nblk = CB * OB;
+  // 32 x 32 blocks of the window: wave wv computes block (wv / OB, wv % OB) when wv < nblk
+  const int CB = (cw + 31) / 32, OB = (ow + 31) / 32, nblk = CB * OB;
   const int cin8 = (cw + 7) / 8, cout8 = (ow + 7) / 8;
   // rows are read from the window's first channel on; the row pitch stays cin / cout
   const uint16_t *Xw = X + c0, *Gw = dZ16 + o0;
@@ -423,33 +425,28 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
   }
   // channel rows past cin / cout (up to the 16-row MFMA block) stay zero; the others are written
   // by every chunk
-  for (int e = cw * kWgPitch / 2 + tid; e < CB * 16 * kWgPitch / 2; e += 256) {
+  for (int e = cw * kWgPitch / 2 + tid; e < CB * 32 * kWgPitch / 2; e += 256) {
     reinterpret_cast<uint32_t *>(XT[0])[e] = 0;
     reinterpret_cast<uint32_t *>(XT[1])[e] = 0;
   }
-  for (int e = ow * kWgPitch / 2 + tid; e < OB * 16 * kWgPitch / 2; e += 256) {
+  for (int e = ow * kWgPitch / 2 + tid; e < OB * 32 * kWgPitch / 2; e += 256) {
     reinterpret_cast<uint32_t *>(GT[0])[e] = 0;
     reinterpret_cast<uint32_t *>(GT[1])[e] = 0;
   }
-  Comp tot[4][4];
+  Comp tot[16];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) tot[j][i] = Comp{0.0f, 0.0f};
-  // the partial of offset k goes to slot k S + s (sliced) or s + k (balanced, s = g)
-  auto write_partial = [&](int k, const Comp(&t)[4][4], bool zero) {
+  for (int r = 0; r < 16; ++r) tot[r] = Comp{0.0f, 0.0f};
+  // the partial of offset k goes to slot k S + s (sliced) or s + k (balanced, s = g); entry r of
+  // lane l is dW[mb 32 + 8 (r / 4) + 4 (l / 32) + r % 4][nb 32 + l % 32]
+  auto write_partial = [&](int k, const Comp(&t)[16], bool zero) {
     const int64_t slot = G > 0 ? (int64_t)s + k : (int64_t)k * S + s;
+    if (wv < nblk) {
+      const int mb = wv / OB, nb = wv % OB;
+      const int o = nb * 32 + (lane & 31);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int blk = wv + 4 * j;
-      if (blk < nblk) {
-        const int mb = blk / OB, nb = blk % OB;
-        const int o = nb * 16 + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int c = mb * 16 + 4 * (lane >> 4) + i;
-          if (c < cw && o < ow) part[(slot * cin + c0 + c) * cout + o0 + o] = zero ? 0.0f : t[j][i].value();
-        }
+      for (int r = 0; r < 16; ++r) {
+        const int c = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (c < cw && o < ow) part[(slot * cin + c0 + c) * cout + o0 + o] = zero ? 0.0f : t[r].value();
       }
     }
   };
@@ -487,34 +484,26 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(const WgBatch B, const 
     for (int u = 0; u < 2; ++u) wg_gather(Xw, cin, Gw, cout, task[u], rn[u], v[u]);  // chunk ch + 1
 #pragma unroll
     for (int u = 0; u < 2; ++u) wg_indices(pairs, q2.pb, q2.m, task[u], rn[u]);
-    f32x4_t acc[4];
+    f32x16_t acc = {};
+    {
+      // a wave past nblk computes on in-range rows and is discarded at the store, so the
+      // products need no branch
+      const int mb = wv / OB < 1 ? wv / OB : 1, nb = wv % OB;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int kk = 0; kk < kWgChunk; kk += 32) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        // blocks past nblk compute on in-range rows and are discarded at the store, so the
-        // products need no branch (a branch would make the compiler copy the accumulators)
-        const int blk = wv + 4 * j;
-        const int mb = blk / OB < 3 ? blk / OB : 3, nb = blk % OB;
+      for (int kk = 0; kk < kWgChunk; kk += 16) {
         const bf16x8_t a =
-            *reinterpret_cast<const bf16x8_t *>(XT[cur] + wg_lds_pos(mb * 16 + (lane & 15), kk + 8 * (lane >> 4)));
+            *reinterpret_cast<const bf16x8_t *>(XT[cur] + wg_lds_pos(mb * 32 + (lane & 31), kk + 8 * (lane >> 5)));
         const bf16x8_t b =
-            *reinterpret_cast<const bf16x8_t *>(GT[cur] + wg_lds_pos(nb * 16 + (lane & 15), kk + 8 * (lane >> 4)));
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            *reinterpret_cast<const bf16x8_t *>(GT[cur] + wg_lds_pos(nb * 32 + (lane & 31), kk + 8 * (lane >> 5)));
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) tot[j][i].add(acc[j][i]);
+    for (int r = 0; r < 16; ++r) tot[r].add(acc[r]);
     if (q0.last) {  // the end of this workgroup's part of offset q0.k
       write_partial(q0.k, tot, false);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) tot[j][i] = Comp{0.0f, 0.0f};
+      for (int r = 0; r < 16; ++r) tot[r] = Comp{0.0f, 0.0f};
     }
     q0 = q1;
     q1 = q2;
