@@ -542,22 +542,28 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const RdBatch B, int n
   float *__restrict__ db = B.L[li].db;
   const int cin = B.L[li].cin, cout = B.L[li].cout, nbw = B.L[li].nbw, S = B.L[li].S;
   const int bx = (int)blockIdx.x - B.L[li].b0;
-  if (bx < nbw && G > 0) {
+  if (bx < nbw && G > 0) {  // nbw = K blocks_per_offset: block bx reduces 256 entries of one offset
     const int64_t E = (int64_t)cin * cout;
+    const int per_k = (int)((E + 255) / 256), k = bx / per_k;
+    const int64_t ce = (int64_t)(bx - k * per_k) * 256 + threadIdx.x;
     const int off0 = rb_off[0];
     const int64_t P = rb_off[K] - off0;
-    const uint32_t L = (uint32_t)((P + G - 1) / G);
-    for (int64_t e = (int64_t)bx * blockDim.x + threadIdx.x; e < K * E; e += (int64_t)nbw * blockDim.x) {
-      const int k = (int)(e / E);
-      const int64_t ce = e - k * E;
-      const int a = rb_off[k] - off0, b = rb_off[k + 1] - off0;
-      Comp t{0.0f, 0.0f};
-      if (a < b) {
-        const int g1 = (int)((uint32_t)(b - 1) / L);
-        for (int g = (int)((uint32_t)a / L); g <= g1; ++g) t.add(wpart[(int64_t)(g + k) * E + ce]);
+    const int a = rb_off[k] - off0, b = rb_off[k + 1] - off0;
+    Comp t{0.0f, 0.0f};
+    if (a < b && ce < E) {
+      const uint32_t L = (uint32_t)((P + G - 1) / G);
+      const int g0 = (int)((uint32_t)a / L), g1 = (int)((uint32_t)(b - 1) / L);
+      const float *src = wpart + (int64_t)k * E + ce;  // slot g + k of this entry: src[g E]
+      for (int g = g0; g <= g1; g += 4) {  // four slots loaded before any is added, in order of g
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = g + i <= g1 ? src[(int64_t)(g + i) * E] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (g + i <= g1) t.add(v[i]);
       }
-      dW[e] = t.value();
     }
+    if (ce < E) dW[(int64_t)k * E + ce] = t.value();
     return;
   }
   if (bx < nbw) {
@@ -801,7 +807,7 @@ extern "C" npvs_status npvs_sparse_conv_wgrad(int32_t n_layers, const npvs_wgrad
     }
     W.L[i] = WgLayer{(const uint16_t *)l.X, reinterpret_cast<const uint16_t *>(w + o16), wpart, l.cin, l.cout, z0};
     z0 += ((l.cin + 63) / 64) * ((l.cout + 63) / 64);
-    const int nbw = reduce_blocks(27, l.cin, l.cout);
+    const int nbw = G > 0 ? 27 * (int)(((int64_t)l.cin * l.cout + 255) / 256) : reduce_blocks(27, l.cin, l.cout);
     R.L[i] = RdLayer{wpart, dbpart, l.dW, l.db, l.cin, l.cout, nbw, b0, Sl};
     b0 += nbw + (l.cout + 3) / 4;
   }
