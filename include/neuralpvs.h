@@ -286,6 +286,28 @@ npvs_status npvs_sparse_conv_bwd(const void *X, int32_t cin, const void *Wt, int
                                  void *reduce_stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * The data gradient of a BF16 layer fused with the ReLU' of the layer below it (the chain rule
+ * through two consecutive layers of the stack): from this layer's dZ [cap][cout], held by its
+ * backward workspace ws (npvs_sparse_conv_bwd with dW = db = NULL, or an earlier call of this
+ * function with ws as ws_below), computes dX = sum_k sum_{(i,r) in R_k} dZ[r] W_k^T and writes
+ * the layer below's dZ_below = bf16(dX * [M > 0]) and its bias partials into ws_below, the
+ * workspace of the layer below (cin_below -> cin channels), exactly as npvs_sparse_conv_bwd of
+ * that layer with dY = dX and relu = 1 would form them (the same bfloat16 values; the bias
+ * partials in another grouping), so its data gradient can follow with this function again and
+ * its weight gradient with npvs_sparse_conv_wgrad.
+ *   Wt = npvs_pack_weights(W, ..., flip_transpose = 1) of this layer (cin -> cout); M (device,
+ *   nullable: no mask) the layer below's output = this layer's input X, bfloat16 [cap][cin].
+ *   cin, cout <= 64 and multiples of 8; cin_below a multiple of 8 (NPVS_ERR_UNSUPPORTED
+ *   otherwise).  ws and ws_below must differ.
+ * Why: it removes the elementwise dZ pass (a launch-bound kernel) between the data gradients of
+ * a stack of narrow layers.
+ * ------------------------------------------------------------------------------------------- */
+npvs_status npvs_sparse_conv_dgrad_relu(const void *Wt, int32_t cin, int32_t cout, const void *M, int32_t cin_below,
+                                        const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites,
+                                        const void *ws, size_t ws_bytes, void *ws_below, size_t ws_below_bytes,
+                                        void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Weight and bias gradients of several layers of one rulebook (the dW / db of the backward
  * above), in one weight-gradient launch and one reduction launch for all of them:
  *   layers (host) array of n_layers (1 .. NPVS_MAX_WGRAD_LAYERS) descriptors, read during the

@@ -21,7 +21,7 @@ from ._lib import NPVS_BF16, NPVS_CONV_VARIANTS, NPVS_F32, NPVS_U8, NpvsError  #
 
 __all__ = [
     "froxelize", "build_rulebook", "gather_input", "interleave", "deinterleave", "pack_weights",
-    "sparse_conv_fwd", "sparse_conv_bwd", "sparse_conv_wgrad", "Levels", "build_levels",
+    "sparse_conv_fwd", "sparse_conv_bwd", "sparse_conv_wgrad", "sparse_conv_dgrad_relu", "Levels", "build_levels",
     "pack_weights_k", "strided_conv_fwd", "concat_channels", "viewcell_frustum", "froxelize_view", "deinterleave_threshold", "loss", "adam", "Plan", "Rulebook",
     "NpvsError", "NPVS_F32", "NPVS_BF16", "NPVS_U8", "version",
 ]
@@ -276,6 +276,17 @@ def sparse_conv_bwd(X, Wt, cin: int, cout: int, Y, dY, rb: Rulebook, dtype: int,
 def _check_grad_out(dW, db, cin: int, cout: int):
     if dW.numel() != 27 * cin * cout or db.numel() != cout or not (dW.is_contiguous() and db.is_contiguous()):
         raise ValueError("dW / db must be contiguous float32 [27][cin][cout] / [cout]")
+
+
+def sparse_conv_dgrad_relu(Wt, cin: int, cout: int, M, cin_below: int, rb: Rulebook, ws: torch.Tensor,
+                           ws_below: torch.Tensor):
+    """BF16 data gradient of a layer (cin -> cout) from the dZ its backward workspace `ws` holds,
+    fused with the ReLU' of the layer below (M: that layer's output, this layer's input; None: no
+    mask): writes the layer below's dZ and bias partials into `ws_below` (that layer's backward
+    workspace, cin_below -> cin channels), ready for another sparse_conv_dgrad_relu and for
+    sparse_conv_wgrad."""
+    L.call("npvs_sparse_conv_dgrad_relu", _p(Wt), cin, cout, _p(M), cin_below, _p(rb.nbr), _p(rb.counts), rb.cap,
+           _p(ws), ws.numel(), _p(ws_below), ws_below.numel(), _stream())
 
 
 def sparse_conv_wgrad(layers, rb: Rulebook, dtype: int, slices: int = 0):

@@ -91,6 +91,7 @@ SIGNATURES = {
     "npvs_conv_bwd_workspace_size": (i32, [i32, i32, i32, i32, PS]),
     "npvs_sparse_conv_bwd": (i32, [P, i32, P, i32, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, sz, P, P, P]),
     "npvs_sparse_conv_wgrad": (i32, [i32, P, P, P, i32, i32, i32, P]),
+    "npvs_sparse_conv_dgrad_relu": (i32, [P, i32, i32, P, i32, P, P, i32, P, sz, P, sz, P]),
     "npvs_level_maps": (i32, [i32, P, i32, P, P, P, i32, P, P, P, i32, P, P, P]),
     "npvs_packed_weight_bytes_k": (sz, [i32, i32, i32, i32]),
     "npvs_pack_weights_k": (i32, [P, i32, i32, i32, i32, i32, P, P]),

@@ -820,3 +820,29 @@ extern "C" npvs_status npvs_sparse_conv_wgrad(int32_t n_layers, const npvs_wgrad
   grad_reduce_kernel<<<b0, 256, 0, s>>>(R, kDbBlocks, 27, G, rb_off);
   return check_hip(hipGetLastError(), "npvs_sparse_conv_wgrad: reductions");
 }
+
+extern "C" npvs_status npvs_sparse_conv_dgrad_relu(const void *Wt, int32_t cin, int32_t cout, const void *M,
+                                                  int32_t cin_below, const int32_t *nbr, const npvs_counts *counts,
+                                                  int32_t cap_sites, const void *ws, size_t ws_bytes,
+                                                  void *ws_below, size_t ws_below_bytes, void *stream) {
+  if (!Wt || !nbr || !counts || !ws || !ws_below)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_dgrad_relu: null pointer");
+  if (cin < 1 || cout < 1 || cin_below < 1 || cap_sites < 1)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_dgrad_relu: bad sizes");
+  if (ws == ws_below) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_dgrad_relu: ws and ws_below must differ");
+  if (cin > 64 || cout > 64 || cin % 8 || cout % 8 || cin_below % 8)
+    return fail(NPVS_ERR_UNSUPPORTED,
+                "npvs_sparse_conv_dgrad_relu: needs cin, cout <= 64 and cin, cout, cin_below multiples of 8");
+  size_t a, o16, c, d, e, f, need;
+  bwd_ws_layout(cin, cout, cap_sites, NPVS_BF16, &a, &o16, &c, &d, &e, &f, &need);
+  if (ws_bytes < need) return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_dgrad_relu: workspace too small");
+  size_t b16, bdb;
+  bwd_ws_layout(cin_below, cin, cap_sites, NPVS_BF16, &a, &b16, &c, &bdb, &e, &f, &need);
+  if (ws_below_bytes < need)
+    return fail(NPVS_ERR_INVALID_ARG, "npvs_sparse_conv_dgrad_relu: workspace of the layer below too small");
+  const uint16_t *dZ = reinterpret_cast<const uint16_t *>(static_cast<const char *>(ws) + o16);
+  char *wb = static_cast<char *>(ws_below);
+  return dgrad_relu_fused(dZ, cout, Wt, cin, nbr, counts, cap_sites, static_cast<const uint16_t *>(M),
+                          reinterpret_cast<uint16_t *>(wb + b16), reinterpret_cast<float *>(wb + bdb),
+                          as_stream(stream));
+}

@@ -413,15 +413,22 @@ __global__ __launch_bounds__(256) void conv_splitk_finish_kernel(const float *__
 // tile's products run; with one or four (whose weights leave no registers for a second buffer)
 // they are gathered into the same buffer as soon as the products have issued, ahead of the
 // reduction and the epilogue.
-template <int KB, int MB, int NBW = 2>
-__global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
-                                                                  const bf16x8_t *__restrict__ Wp,
-                                                                  const float *__restrict__ bias, int cout,
-                                                                  const int32_t *__restrict__ nbr,
-                                                                  const npvs_counts *__restrict__ counts, int cap,
-                                                                  int relu, int out_f32, void *__restrict__ Y) {
+// With FUSE (the data gradient of a layer, feeding the backward of the layer below): the result
+// is masked by M > 0 (the ReLU' of the layer below, whose output M is; no mask when M is null),
+// rounded to bf16 into Y, and each epilogue wave keeps per-lane running sums of its masked values
+// over the tiles its workgroup walks; at the end a fixed butterfly adds the 16 rows of each
+// column and workgroup b writes row b of the bias partial table dbp[kBwdDbBlocks][cout] (rows
+// past the grid are written as zeros), so the layer below's bias gradient is a fixed-order sum
+// over that table.  Needs one column group (cout <= 16 NBW) and MB = 1.
+template <int KB, int MB, int NBW, bool FUSE>
+__device__ __forceinline__ void wsta_body(const uint16_t *__restrict__ X, int cin, const bf16x8_t *__restrict__ Wp,
+                                          const float *__restrict__ bias, int cout, const int32_t *__restrict__ nbr,
+                                          const npvs_counts *__restrict__ counts, int cap, int relu, int out_f32,
+                                          void *__restrict__ Y, const uint16_t *__restrict__ M,
+                                          float *__restrict__ dbp) {
   constexpr int KSPLIT = 9, KPER = 3, ROWS = 16 * MB, NBLK = MB * NBW;
   constexpr bool PF = NBW == 2;  // rows of the next tile prefetched (the registers of 4 blocks' weights leave no room)
+  static_assert(!FUSE || MB == 1, "the fused data gradient keeps one column block per epilogue wave");
   __shared__ f32x4_t red[KSPLIT * NBLK * 64];
   const int32_t n = counts->n_sites;
   const int ntiles = (n + ROWS - 1) / ROWS;
@@ -439,8 +446,24 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
         const int g = nb0 + nb < NBT ? nb0 + nb : NBT - 1;  // blocks past cout: any valid fragment
         aw[q][kb][nb] = Wp[(((int64_t)(kbeg + q) * NBT + g) * KB + kb) * 64 + lane];
       }
+  float da[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // FUSE: this lane's running column sums
+  auto write_db_parts = [&]() {
+    if (wv >= NBLK) return;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) da[i] += __shfl_xor(da[i], off, 64);
+    const int o = (nb0 + wv) * 16 + 4 * (lane >> 4);
+    if ((lane & 15) == 0 && o < cout)
+      for (int row = blockIdx.x; row < kBwdDbBlocks; row += gridDim.x)
+        *reinterpret_cast<f32x4_t *>(dbp + (int64_t)row * cout + o) =
+            row == (int)blockIdx.x ? f32x4_t{da[0], da[1], da[2], da[3]} : f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  };
   int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
-  if (tile < 0) return;  // whole workgroup: tile depends on blockIdx only
+  if (tile < 0) {  // whole workgroup: tile depends on blockIdx only
+    if constexpr (FUSE) write_db_parts();
+    return;
+  }
   // Loads retire in order, so a value used right after its load makes every load issued before
   // it wait too.  The neighbour indices are therefore loaded raw (rows past the last site read
   // the last site's entry) and judged only when their rows are gathered, and a gathered row is
@@ -491,7 +514,7 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   // the epilogue loads it, after this tile's loads and before the next tile's are needed)
   constexpr bool BIAS_ONCE = !(PF && MB == 2);
   float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  if constexpr (BIAS_ONCE) {
+  if constexpr (BIAS_ONCE && !FUSE) {
     const int o = (nb0 + wv % NBW) * 16 + 4 * (lane >> 4);
     if (bias && wv < NBLK && o < cout)
 #pragma unroll
@@ -507,6 +530,13 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   indices(t1 >= 0 ? t1 : tile, ix);
   for (int j = 0; tile >= 0; ++j) {
     const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
+    // FUSE: the epilogue waves fetch this tile's mask before the next tile's rows are issued, so
+    // waiting for it does not wait for them
+    uint2 mk = {0u, 0u};
+    if constexpr (FUSE) {
+      const int r = tile * ROWS + (lane & 15), o = (nb0 + wv) * 16 + 4 * (lane >> 4);
+      if (M && wv < NBLK && r < n && o < cout) mk = *reinterpret_cast<const uint2 *>(M + (int64_t)r * cout + o);
+    }
     uint4 bn[KPER][KB][MB];
     uint32_t bnm;
     if constexpr (PF) {
@@ -549,8 +579,26 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
       for (int w = 1; w < KSPLIT; ++w) sum += red[(w * NBLK + blk) * 64 + lane];
       const int mb = blk / NBW, nb = blk % NBW;
       const int r = row0 + mb * 16 + (lane & 15), o = (nb0 + nb) * 16 + 4 * (lane >> 4);
-      if constexpr (BIAS_ONCE) conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
-      else conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
+      if constexpr (FUSE) {
+        if (r < n && o < cout) {
+          float g[4] = {sum[0], sum[1], sum[2], sum[3]};
+          if (M) {
+            const uint16_t mv[4] = {(uint16_t)mk.x, (uint16_t)(mk.x >> 16), (uint16_t)mk.y, (uint16_t)(mk.y >> 16)};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g[i] = bf16_to_f32(mv[i]) > 0.0f ? g[i] : 0.0f;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) da[i] += g[i];
+          uint2 h;
+          h.x = (uint32_t)f32_to_bf16(g[0]) | ((uint32_t)f32_to_bf16(g[1]) << 16);
+          h.y = (uint32_t)f32_to_bf16(g[2]) | ((uint32_t)f32_to_bf16(g[3]) << 16);
+          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(Y) + (int64_t)r * cout + o) = h;
+        }
+      } else if constexpr (BIAS_ONCE) {
+        conv_bf16_epilogue_bias(sum, r, n, o, cout, bv, relu, out_f32, Y);
+      } else {
+        conv_bf16_epilogue<4>(sum, r, n, o, cout, bias, relu, out_f32, Y);
+      }
     }
     if constexpr (PF) {
       mask_all(bn, bnm, bx);
@@ -558,6 +606,30 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
     tile = t1;
     t1 = t2;
   }
+  if constexpr (FUSE) write_db_parts();
+}
+
+template <int KB, int MB, int NBW = 2>
+__global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t *__restrict__ X, int cin,
+                                                                  const bf16x8_t *__restrict__ Wp,
+                                                                  const float *__restrict__ bias, int cout,
+                                                                  const int32_t *__restrict__ nbr,
+                                                                  const npvs_counts *__restrict__ counts, int cap,
+                                                                  int relu, int out_f32, void *__restrict__ Y) {
+  wsta_body<KB, MB, NBW, false>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, nullptr, nullptr);
+}
+
+// The data gradient of a BF16 layer with the ReLU' of the layer below fused in: dZ_below =
+// bf16(conv(dZ, W') masked by M > 0) and the bias partial table dbp (see wsta_body).
+template <int KB>
+__global__ __launch_bounds__(576) void dgrad_relu_bf16_wsta_kernel(const uint16_t *__restrict__ dZ, int cin,
+                                                                    const bf16x8_t *__restrict__ Wt, int cout,
+                                                                    const int32_t *__restrict__ nbr,
+                                                                    const npvs_counts *__restrict__ counts, int cap,
+                                                                    uint16_t *__restrict__ dZ_below,
+                                                                    const uint16_t *__restrict__ M,
+                                                                    float *__restrict__ dbp) {
+  wsta_body<KB, 1, 4, true>(dZ, cin, Wt, nullptr, cout, nbr, counts, cap, 0, 0, dZ_below, M, dbp);
 }
 
 template <int KB, int NB, int MB, int RG>
@@ -695,6 +767,25 @@ static void launch_bf16_wsta(const void *X, int cin, const void *Wp, const float
   if (G > most) G = (most + 7) & ~7;
   conv_fwd_bf16_wsta_kernel<KB, MB, NBW><<<dim3(G, groups), 576, 0, s>>>(
       (const uint16_t *)X, cin, (const bf16x8_t *)Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y);
+}
+
+npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int cout, const int32_t *nbr,
+                             const npvs_counts *counts, int cap, const uint16_t *M, uint16_t *dZ_below, float *dbp,
+                             hipStream_t s) {
+  if (cin > 64 || cin % 8 || cout > 64 || cout % 4)
+    return fail(NPVS_ERR_UNSUPPORTED, "data gradient with fused ReLU': unsupported channel counts");
+  // the grid of the default forward shape (one column group); at most kBwdDbBlocks workgroups,
+  // one bias partial row each
+  int G = 256;
+  const int most = stride_grid(cap, 16, 4096);
+  if (G > most) G = (most + 7) & ~7;
+  G = G > kBwdDbBlocks ? kBwdDbBlocks : G;
+  const bf16x8_t *W = (const bf16x8_t *)Wt;
+  if (cin <= 32)
+    dgrad_relu_bf16_wsta_kernel<1><<<dim3(G, 1), 576, 0, s>>>(dZ, cin, W, cout, nbr, counts, cap, dZ_below, M, dbp);
+  else
+    dgrad_relu_bf16_wsta_kernel<2><<<dim3(G, 1), 576, 0, s>>>(dZ, cin, W, cout, nbr, counts, cap, dZ_below, M, dbp);
+  return check_hip(hipGetLastError(), "data gradient with fused ReLU'");
 }
 
 template <int MB>

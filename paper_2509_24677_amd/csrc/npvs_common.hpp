@@ -105,5 +105,12 @@ npvs_status bwd_wgrad(int32_t dtype, const void *X, int32_t cin, const void *dZ,
                       const int32_t *rb_off, const int32_t *pairs, int S, float *wpart, hipStream_t s);
 npvs_status bwd_reduce(const float *wpart, const float *dbpart, int nparts, int32_t K, int S, int32_t cin,
                        int32_t cout, float *dW, float *db, hipStream_t s);
+// The data gradient of a BF16 layer (dZ [cap][cin] of this layer -> [cap][cout] of the layer
+// below, weights packed as for the data gradient) with the layer below's ReLU' fused in
+// (conv.hip): dZ_below = bf16(result masked by M > 0; M null: no mask) and that layer's bias
+// partials dbp[kBwdDbBlocks][cout].  cin <= 64 (multiple of 8), cout <= 64 (multiple of 4).
+npvs_status dgrad_relu_fused(const uint16_t *dZ, int cin, const void *Wt, int cout, const int32_t *nbr,
+                             const npvs_counts *counts, int cap, const uint16_t *M, uint16_t *dZ_below, float *dbp,
+                             hipStream_t s);
 
 }  // namespace npvs

@@ -19,7 +19,7 @@ import torch
 from . import _lib as L
 from . import (NPVS_BF16, NPVS_F32, NPVS_U8, Rulebook, adam, build_rulebook, conv_bwd_workspace,
                deinterleave_threshold, froxelize, gather_input, loss, pack_weights, pack_weights_batch, sparse_conv_bwd,
-               sparse_conv_fwd, sparse_conv_wgrad)
+               sparse_conv_dgrad_relu, sparse_conv_fwd, sparse_conv_wgrad)
 
 
 class Network:
@@ -128,13 +128,15 @@ class Network:
         return X, saved
 
     def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True,
-                 batch_wgrad: bool | None = None, wgrad_slices: int = 0):
+                 batch_wgrad: bool | None = None, wgrad_slices: int = 0, chain: bool | None = None):
         """Hand-written backward through the stack; recomputes the layer inputs that were not
         saved.  With `batch_wgrad` (default: for BF16, whose weight gradients are short
         latency-bound launches), the data gradients run down the stack first, all on the current
         stream, and the weight gradients of every layer follow in one launch (and one reduction
-        launch; `wgrad_slices` pair-list slices per offset, 0 for the library's choice).
-        Otherwise (the FP32 default) each layer's weight gradient follows its data gradient:
+        launch; `wgrad_slices` pair-list slices per offset, 0 for the library's choice); there,
+        with `chain` (default: wherever the layers allow it, see _chainable) each data gradient
+        also forms the dZ of the layer below in its epilogue (npvs_sparse_conv_dgrad_relu), so no
+        separate ReLU' pass runs between them.  Otherwise (the FP32 default) each layer's weight gradient follows its data gradient:
         with `overlap` on a side stream while the data gradient continues down the stack (their
         final reductions on a third stream, beside the next weight gradient; the side streams
         are joined before returning).  The gradients land in the flat gradient buffer; returns
@@ -142,7 +144,11 @@ class Network:
         if batch_wgrad is None:
             batch_wgrad = self.dtype == NPVS_BF16
         if batch_wgrad:
-            return self._backward_batched(saved, logits, dlogits, rb, wgrad_slices)
+            if chain is None:
+                chain = self._chainable()
+            elif chain and not self._chainable():
+                raise ValueError("the chained backward needs BF16 layers of at most 64 channels above the first")
+            return self._backward_batched(saved, logits, dlogits, rb, wgrad_slices, chain)
         main = torch.cuda.current_stream()
         side = side2 = None
         if overlap:
@@ -176,7 +182,16 @@ class Network:
         del in_use
         return grads
 
-    def _backward_batched(self, saved, logits, dlogits, rb, slices):
+    def _chainable(self) -> bool:
+        """The fused data gradient applies: BF16, every layer above the first at most 64 channels
+        in and out, every channel count a multiple of 8."""
+        ch = self.channels
+        return (self.dtype == NPVS_BF16 and all(c % 8 == 0 for c in ch)
+                and all(max(ch[i], ch[i + 1]) <= 64 for i in range(1, self.n_layers)))
+
+    def _backward_batched(self, saved, logits, dlogits, rb, slices, chain):
+        if chain:
+            return self._backward_chained(saved, logits, dlogits, rb, slices)
         outputs = {self.n_layers - 1: logits}
         pending = []  # (X, cin, cout, ws, dW, db) of each layer, for the batched weight gradient
         dY = dlogits
@@ -195,6 +210,28 @@ class Network:
             if i > 0:
                 outputs[i - 1] = X
             dY = dX
+        sparse_conv_wgrad(pending, rb, self.dtype, slices)
+        return [(self.gW[i], self.gb[i]) for i in range(self.n_layers)]
+
+    def _backward_chained(self, saved, logits, dlogits, rb, slices):
+        """The top layer's dZ from dlogits, then each layer's data gradient fused with the ReLU' of
+        the layer below (its input is that layer's output, the mask), writing the layer below's
+        dZ and bias partials straight into its workspace; then every weight gradient at once."""
+        top, ch = self.n_layers - 1, self.channels
+        inputs = {}
+
+        def layer_input(i):
+            if i not in inputs:
+                inputs[i] = saved[i] if i in saved else self.layer(i - 1, saved[i - 1], rb)
+            return inputs[i]
+
+        ws = [conv_bwd_workspace(ch[i], ch[i + 1], rb, self.dtype) for i in range(self.n_layers)]
+        sparse_conv_bwd(layer_input(top), self.Wt[top], ch[top], ch[top + 1], logits, dlogits, rb, self.dtype,
+                        relu=False, want_dx=False, ws=ws[top], want_dw=False)
+        for i in range(top, 0, -1):
+            sparse_conv_dgrad_relu(self.Wt[i], ch[i], ch[i + 1], layer_input(i), ch[i - 1], rb, ws[i], ws[i - 1])
+        layer_input(0)
+        pending = [(inputs[i], ch[i], ch[i + 1], ws[i], self.gW[i], self.gb[i]) for i in range(top, -1, -1)]
         sparse_conv_wgrad(pending, rb, self.dtype, slices)
         return [(self.gW[i], self.gb[i]) for i in range(self.n_layers)]
 

@@ -76,6 +76,26 @@ def test_conv_workspace_sizes_and_checks(lib):
     assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_INVALID_ARG and b"both" in lib.npvs_last_error()
 
 
+def test_fused_data_gradient_argument_checks(lib):
+    fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
+    n = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_workspace_size", 64, 64, 1000, L.NPVS_BF16, ctypes.byref(n))
+
+    def call(cin=64, cout=64, cin_below=64, ws=fake, ws_bytes=None, ws_below=ctypes.c_void_p(32), wsb_bytes=None,
+             Wt=fake):
+        return lib.npvs_sparse_conv_dgrad_relu(Wt, cin, cout, fake, cin_below, fake, fake, 1000, ws,
+                                               n.value if ws_bytes is None else ws_bytes, ws_below,
+                                               n.value if wsb_bytes is None else wsb_bytes, None)
+
+    assert call(Wt=None) == L.NPVS_ERR_INVALID_ARG and b"null" in lib.npvs_last_error()
+    assert call(ws_below=fake) == L.NPVS_ERR_INVALID_ARG and b"differ" in lib.npvs_last_error()
+    assert call(cin=96) == L.NPVS_ERR_UNSUPPORTED
+    assert call(cout=60) == L.NPVS_ERR_UNSUPPORTED
+    assert call(cin_below=12) == L.NPVS_ERR_UNSUPPORTED
+    assert call(ws_bytes=n.value - 1) == L.NPVS_ERR_INVALID_ARG and b"workspace too small" in lib.npvs_last_error()
+    assert call(wsb_bytes=16) == L.NPVS_ERR_INVALID_ARG and b"layer below" in lib.npvs_last_error()
+
+
 def test_batched_weight_gradient_argument_checks(lib):
     fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
     n = ctypes.c_size_t()

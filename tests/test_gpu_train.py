@@ -294,6 +294,42 @@ def test_batched_weight_gradient_matches_per_layer(dtype):
             np.testing.assert_array_equal(to_np(gb), ref[li][1])
 
 
+@pytest.mark.parametrize("checkpoint", [False, True])
+def test_chained_backward_matches_unchained(checkpoint):
+    """The BF16 network backward with each data gradient fused with the ReLU' of the layer below
+    (npvs_sparse_conv_dgrad_relu) against the same backward with separate ReLU' passes and
+    against the per-layer backward, all at 16 slices: dW bit for bit (the fused epilogue forms
+    the same bfloat16 dZ), the top layer's db bit for bit (formed the same way), and the other
+    layers' db within 2^-14 sum_r |dX[r]| (float32 sums of the same values in another grouping:
+    running sums over a workgroup's tiles and a 16-row butterfly instead of per-block sums)."""
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    net = Network(layers, cfg.d, npvs.NPVS_BF16)
+    assert net._chainable()
+    logits, saved = net.forward(npvs.gather_input(occ, rb, npvs.NPVS_BF16), rb, checkpoint=checkpoint)
+    _, dl = npvs.loss(logits, labels, rb)
+    grads = {}
+    for name, kw in (("chain", dict(batch_wgrad=True, chain=True)), ("plain", dict(batch_wgrad=True, chain=False)),
+                     ("layer", dict(batch_wgrad=False))):
+        grads[name] = [(to_np(a), to_np(b)) for a, b in net.backward(saved, logits, dl, rb, wgrad_slices=16, **kw)]
+    # |dX| of each layer from the per-layer reference path
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_BF16)
+    dx = {}
+    _gpu_backward(acts, rb, layers, npvs.NPVS_BF16, dl, dx_out=dx)
+    n = rb.host_counts()["n_sites"]
+    top = len(layers) - 1
+    for li in range(len(layers)):
+        np.testing.assert_array_equal(grads["chain"][li][0], grads["plain"][li][0])
+        np.testing.assert_array_equal(grads["plain"][li][0], grads["layer"][li][0])
+        np.testing.assert_array_equal(grads["plain"][li][1], grads["layer"][li][1])
+        if li == top:
+            np.testing.assert_array_equal(grads["chain"][li][1], grads["plain"][li][1])
+        else:
+            mag = np.abs(dx[li + 1][:n].astype(np.float64)).sum(axis=0)
+            err = np.abs(grads["chain"][li][1].astype(np.float64) - grads["plain"][li][1])
+            assert np.all(err <= 2.0 ** -14 * mag + 1e-30), (li, float(err.max()))
+
+
 def test_backward_on_an_empty_grid_is_zero():
     """No active sites: every gradient is zero, per layer and with the weight gradients batched
     (both forms; the outputs start as NaN, so each entry must be written)."""
