@@ -1095,6 +1095,11 @@ def main():
     stage["conv_bwd_bf16_without_wgrad"] = timed_launches(
         lambda: npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True, ws=ws_b,
                                      want_dw=False), 20)
+    # the chained form's data gradient: dZ of the hidden layer -> the layer below's dZ and bias
+    # partials, its ReLU' fused in
+    ws_b2 = npvs.conv_bwd_workspace(64, 64, rb, npvs.NPVS_BF16)
+    stage["dgrad_relu_bf16"] = timed_launches(
+        lambda: npvs.sparse_conv_dgrad_relu(net_b.Wt[1], 64, 64, hid_b, 64, rb, ws_b, ws_b2), 20)
     wg_ws = [npvs.conv_bwd_workspace(64, 64, rb, npvs.NPVS_BF16) for _ in range(6)]
     for w in wg_ws:
         npvs.sparse_conv_bwd(hid_b, net_b.Wt[1], 64, 64, out_b, dY, rb, npvs.NPVS_BF16, True, ws=w, want_dw=False)
