@@ -454,6 +454,13 @@ npvs_status npvs_visible_objects(const uint8_t *vis_tris, const int64_t *obj_off
  *   rulebook; stats (device) float32 [n_grids + 1][8] = {L, T, L_rv, TP, FN, FP, GTP, m} per
  *   grid, row n_grids = batch mean; dlogits (device, nullable) float32 [cap][C] = dL_batch/dl,
  *   rows >= n_sites untouched.
+ *   dz_ws (device, nullable): the BF16 backward workspace of the network's last layer (dz_cin ->
+ *   C channels, npvs_conv_bwd_workspace_size bytes, dz_ws_bytes): the gradient is also written
+ *   there as that layer's dZ (bfloat16; the last layer has no ReLU) and bias partials, exactly
+ *   the values npvs_sparse_conv_bwd of that layer with dY = dlogits and dW = db = NULL forms, so
+ *   that call can be skipped (its data gradient follows with npvs_sparse_conv_dgrad_relu, its
+ *   weight gradient with npvs_sparse_conv_wgrad).  Needs C and dz_cin multiples of 8 and
+ *   16-byte aligned logits / dlogits rows (NPVS_ERR_UNSUPPORTED otherwise).
  *   ws: npvs_loss_workspace_size() bytes.
  * ------------------------------------------------------------------------------------------- */
 #define NPVS_LOSS_BCE 0
@@ -461,7 +468,8 @@ npvs_status npvs_visible_objects(const uint8_t *vis_tris, const int64_t *obj_off
 npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes);
 npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
                       int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda, int32_t term,
-                      float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes, void *stream);
+                      float alpha, float *stats, float *dlogits, void *dz_ws, size_t dz_ws_bytes, int32_t dz_cin,
+                      void *ws, size_t ws_bytes, void *stream);
 
 /* Adam (Kingma & Ba) on float32 masters, with weight decay added to the gradient (read from the
  * decay rate the paper lists with the learning rate); p, g, m, v (device) float32 [n].  The step

@@ -465,10 +465,12 @@ def visible_objects(vis_tris: torch.Tensor, obj_off: torch.Tensor) -> torch.Tens
 
 # --------------------------------------------------------------------------------- training
 def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 0.99, want_grad: bool = True,
-         dice_alpha: float | None = None):
+         dice_alpha: float | None = None, dz_ws: torch.Tensor | None = None, dz_cin: int = 0):
     """Per-grid BCE (or, with dice_alpha, the weighted Dice term) + repulsive visibility loss.
     Returns (stats float32 [n_grids + 1][8] with columns L, BCE or Dice, L_rv, TP, FN, FP, GTP, m
-    and the batch mean in the last row, dL/dlogits)."""
+    and the batch mean in the last row, dL/dlogits or None).  dz_ws: the BF16 backward workspace
+    of the last layer (dz_cin -> C channels), which also receives the gradient as that layer's dZ
+    and bias partials (see sparse_conv_bwd(want_dw=False))."""
     G = len(rb.dims)
     C = logits.shape[1]
     nbytes = ctypes.c_size_t()
@@ -479,7 +481,8 @@ def loss(logits: torch.Tensor, labels: torch.Tensor, rb: Rulebook, lam: float = 
     dl = torch.empty_like(logits) if want_grad else None  # rows past the active sites are never read
     term = L.NPVS_LOSS_BCE if dice_alpha is None else L.NPVS_LOSS_DICE
     L.call("npvs_loss", _p(logits), _p(labels), C, _p(rb.grid_rows), G, _p(rb.counts), rb.cap, float(lam), term,
-           float(dice_alpha or 0.0), _p(stats), _p(dl), _p(ws), nbytes.value, _stream())
+           float(dice_alpha or 0.0), _p(stats), _p(dl), _p(dz_ws), 0 if dz_ws is None else dz_ws.numel(), dz_cin,
+           _p(ws), nbytes.value, _stream())
     return stats, dl
 
 

@@ -107,7 +107,7 @@ SIGNATURES = {
     "npvs_visible_objects": (i32, [P, P, i64, P, P]),
     "npvs_deinterleave_threshold": (i32, [P, i32, P, P, i32, P, i32, P, P, P]),
     "npvs_loss_workspace_size": (i32, [i32, PS]),
-    "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, P]),
+    "npvs_loss": (i32, [P, P, i32, P, i32, P, i32, f32, i32, f32, P, P, P, sz, i32, P, sz, P]),
     "npvs_adam": (i32, [P, P, P, P, i64, P, f32, f32, f32, f32, f32, i32, P, i32, P]),
     "npvs_plan_create": (i32, [i32, P, P, i32, i32, P, i32, ctypes.POINTER(P)]),
     "npvs_plan_destroy": (i32, [P]),

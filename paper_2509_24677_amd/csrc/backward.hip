@@ -7,7 +7,7 @@
 //   db = sum_r dZ[r], from per-row-block partial sums written while dZ is formed.
 // Every float32 reduction adds short plain partial sums into a Neumaier-compensated total, and
 // all reduction orders are fixed, so gradients are bit-identical run to run.
-#include "npvs_common.hpp"
+#include "bwd_layout.hpp"
 
 namespace npvs {
 
@@ -652,6 +652,11 @@ static void bwd_ws_layout(int32_t cin, int32_t cout, int32_t cap, int32_t dtype,
   *dx_bytes = conv_fwd_ws_bytes(cout, cin, cap, dtype);
   o += align256(*dx_bytes);
   *bytes = o;
+}
+
+void bwd_ws_dz_parts(int32_t cin, int32_t cout, int32_t cap, size_t *o_dz16, size_t *o_dbpart, size_t *bytes) {
+  size_t a, c, e, f;
+  bwd_ws_layout(cin, cout, cap, NPVS_BF16, &a, o_dz16, &c, o_dbpart, &e, &f, bytes);
 }
 
 }  // namespace npvs

@@ -10,7 +10,7 @@
 // elementwise gradient dL/dl = c0_b (p - y) + p (1 - p) (y ? cy_b : cn_b).
 #include <cmath>
 
-#include "npvs_common.hpp"
+#include "bwd_layout.hpp"
 
 namespace npvs {
 
@@ -144,6 +144,15 @@ __global__ __launch_bounds__(kLossSlices) void loss_final_kernel(const float *__
   }
 }
 
+// dL/dl of one element of grid b (both gradient kernels evaluate it with this one function, with
+// no multiply-add contraction, so that both round every operation the same way)
+__device__ __forceinline__ float loss_grad_value(float l, uint8_t lab, const float *__restrict__ coef, int b) {
+#pragma clang fp contract(off)
+  const float y = lab ? 1.0f : 0.0f;
+  const float p = sigmoidf_(l);
+  return coef[3 * b] * (p - y) + p * (1.0f - p) * (lab ? coef[3 * b + 1] : coef[3 * b + 2]);
+}
+
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict__ logits,
                                                          const uint8_t *__restrict__ labels, int C,
                                                          const int32_t *__restrict__ grid_rows, int n_grids,
@@ -154,10 +163,55 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict_
     const int32_t r = (int32_t)(e / C);
     int b = 0;
     while (b + 1 < n_grids && r >= grid_rows[b + 1]) ++b;
-    const float l = logits[e];
-    const float y = labels[e] ? 1.0f : 0.0f;
-    const float p = sigmoidf_(l);
-    dl[e] = coef[3 * b] * (p - y) + p * (1.0f - p) * (labels[e] ? coef[3 * b + 1] : coef[3 * b + 2]);
+    dl[e] = loss_grad_value(logits[e], labels[e], coef, b);
+  }
+}
+
+// The gradient formed as the top layer's dZ (no ReLU on the logits): bf16 dZ16 [cap][C], the bias
+// partial table dbpart[kBwdDbBlocks][C] and, when dl is given, the float32 gradient too.  The
+// blocks, the row ranges, the four columns per thread and the fixed-order sums are those of the
+// backward's own dZ pass (backward.hip) on that gradient, so both form the same values.  grid
+// (kBwdDbBlocks, ceil(C / 64)), 256 threads; C % 4 == 0 and 16-byte aligned rows.
+__global__ __launch_bounds__(256) void loss_dz_kernel(const float *__restrict__ logits,
+                                                       const uint8_t *__restrict__ labels, int C,
+                                                       const int32_t *__restrict__ grid_rows, int n_grids,
+                                                       const npvs_counts *__restrict__ counts,
+                                                       const float *__restrict__ coef, float *__restrict__ dl,
+                                                       uint16_t *__restrict__ dZ16, float *__restrict__ dbpart) {
+  __shared__ float red[256 * 4];
+  const int64_t n = counts->n_sites;
+  const int64_t r0 = n * blockIdx.x / gridDim.x, r1 = n * (blockIdx.x + 1) / gridDim.x;
+  const int c0 = 64 * blockIdx.y, Cw = C - c0 < 64 ? C - c0 : 64;
+  const int TPR = Cw / 4, RG = 256 / TPR;
+  const int cg = threadIdx.x % TPR, rg = threadIdx.x / TPR;
+  Comp a[4] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+  if (rg < RG) {
+    for (int64_t r = r0 + rg; r < r1; r += RG) {
+      int b = 0;
+      while (b + 1 < n_grids && r >= grid_rows[b + 1]) ++b;
+      const int64_t e = r * C + c0 + 4 * cg;
+      const float4 lv = *reinterpret_cast<const float4 *>(logits + e);
+      const uint32_t yv = *reinterpret_cast<const uint32_t *>(labels + e);
+      float g[4] = {loss_grad_value(lv.x, (uint8_t)yv, coef, b), loss_grad_value(lv.y, (uint8_t)(yv >> 8), coef, b),
+                    loss_grad_value(lv.z, (uint8_t)(yv >> 16), coef, b),
+                    loss_grad_value(lv.w, (uint8_t)(yv >> 24), coef, b)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i].add(g[i]);
+      if (dl) *reinterpret_cast<float4 *>(dl + e) = make_float4(g[0], g[1], g[2], g[3]);
+      uint2 h;
+      h.x = (uint32_t)f32_to_bf16(g[0]) | ((uint32_t)f32_to_bf16(g[1]) << 16);
+      h.y = (uint32_t)f32_to_bf16(g[2]) | ((uint32_t)f32_to_bf16(g[3]) << 16);
+      *reinterpret_cast<uint2 *>(dZ16 + e) = h;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[threadIdx.x * 4 + i] = a[i].s + a[i].c;
+  __syncthreads();
+  if (threadIdx.x < Cw) {
+    const int c = threadIdx.x, g0 = c / 4, comp = c % 4;
+    Comp t{0.0f, 0.0f};
+    for (int g = 0; g < RG; ++g) t.add(red[(g * TPR + g0) * 4 + comp]);
+    dbpart[(int64_t)blockIdx.x * C + c0 + c] = t.s + t.c;
   }
 }
 
@@ -237,8 +291,8 @@ extern "C" npvs_status npvs_loss_workspace_size(int32_t n_grids, size_t *bytes) 
 
 extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int32_t C, const int32_t *grid_rows,
                                 int32_t n_grids, const npvs_counts *counts, int32_t cap_sites, float lambda,
-                                int32_t term, float alpha, float *stats, float *dlogits, void *ws, size_t ws_bytes,
-                                void *stream) {
+                                int32_t term, float alpha, float *stats, float *dlogits, void *dz_ws,
+                                size_t dz_ws_bytes, int32_t dz_cin, void *ws, size_t ws_bytes, void *stream) {
   if (!logits || !labels || !grid_rows || !counts || !stats || !ws)
     return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: null pointer");
   if (C < 1 || n_grids < 1 || n_grids > NPVS_MAX_GRIDS || cap_sites < 1)
@@ -251,13 +305,30 @@ extern "C" npvs_status npvs_loss(const float *logits, const uint8_t *labels, int
     return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: term must be NPVS_LOSS_BCE or NPVS_LOSS_DICE");
   float *coef = part + (size_t)n_grids * kLossSlices * kLossQ;
   uint32_t *ticket = reinterpret_cast<uint32_t *>(coef + 3 * (size_t)n_grids);
+  size_t o_dz = 0, o_db = 0;
+  if (dz_ws) {
+    size_t need_dz;
+    if (C % 8 || dz_cin < 1 || dz_cin % 8)
+      return fail(NPVS_ERR_UNSUPPORTED, "npvs_loss: dZ into a backward workspace needs C and dz_cin multiples of 8");
+    if ((reinterpret_cast<uintptr_t>(logits) & 15) || (reinterpret_cast<uintptr_t>(labels) & 3) ||
+        (dlogits && (reinterpret_cast<uintptr_t>(dlogits) & 15)))
+      return fail(NPVS_ERR_UNSUPPORTED, "npvs_loss: dZ into a backward workspace needs aligned rows");
+    bwd_ws_dz_parts(dz_cin, C, cap_sites, &o_dz, &o_db, &need_dz);
+    if (dz_ws_bytes < need_dz) return fail(NPVS_ERR_INVALID_ARG, "npvs_loss: dZ workspace too small");
+  }
   hipStream_t s = as_stream(stream);
   loss_partial_kernel<<<dim3(kLossSlices, n_grids), 256, 0, s>>>(logits, labels, C, grid_rows, part, ticket);
   loss_final_kernel<<<n_grids, kLossSlices, 0, s>>>(part, grid_rows, n_grids, C, lambda, term, alpha, stats, coef,
                                                     ticket);
-  if (dlogits)
+  if (dz_ws) {
+    char *w = static_cast<char *>(dz_ws);
+    loss_dz_kernel<<<dim3(kBwdDbBlocks, (C + 63) / 64), 256, 0, s>>>(
+        logits, labels, C, grid_rows, n_grids, counts, coef, dlogits, reinterpret_cast<uint16_t *>(w + o_dz),
+        reinterpret_cast<float *>(w + o_db));
+  } else if (dlogits) {
     loss_grad_kernel<<<stride_grid((int64_t)cap_sites * C, 256, 4096), 256, 0, s>>>(logits, labels, C, grid_rows,
                                                                                    n_grids, counts, coef, dlogits);
+  }
   return check_hip(hipGetLastError(), "npvs_loss");
 }
 

@@ -128,7 +128,8 @@ class Network:
         return X, saved
 
     def backward(self, saved, logits: torch.Tensor, dlogits: torch.Tensor, rb: Rulebook, overlap: bool = True,
-                 batch_wgrad: bool | None = None, wgrad_slices: int = 0, chain: bool | None = None):
+                 batch_wgrad: bool | None = None, wgrad_slices: int = 0, chain: bool | None = None,
+                 top_ws: torch.Tensor | None = None):
         """Hand-written backward through the stack; recomputes the layer inputs that were not
         saved.  With `batch_wgrad` (default: for BF16, whose weight gradients are short
         latency-bound launches), the data gradients run down the stack first, all on the current
@@ -136,19 +137,18 @@ class Network:
         launch; `wgrad_slices` pair-list slices per offset, 0 for the library's choice); there,
         with `chain` (default: wherever the layers allow it, see _chainable) each data gradient
         also forms the dZ of the layer below in its epilogue (npvs_sparse_conv_dgrad_relu), so no
-        separate ReLU' pass runs between them.  Otherwise (the FP32 default) each layer's weight gradient follows its data gradient:
+        separate ReLU' pass runs between them (`top_ws`: the last layer's backward workspace, into
+        which the loss already wrote that layer's dZ, see loss(dz_ws=...); dlogits is then unused).
+        Otherwise (the FP32 default) each layer's weight gradient follows its data gradient:
         with `overlap` on a side stream while the data gradient continues down the stack (their
         final reductions on a third stream, beside the next weight gradient; the side streams
         are joined before returning).  The gradients land in the flat gradient buffer; returns
         [(dW, db)] per layer (views of it)."""
-        if batch_wgrad is None:
-            batch_wgrad = self.dtype == NPVS_BF16
+        batch_wgrad, chain = self.backward_form(batch_wgrad, chain)
+        if top_ws is not None and not chain:
+            raise ValueError("top_ws is for the chained backward")
         if batch_wgrad:
-            if chain is None:
-                chain = self._chainable()
-            elif chain and not self._chainable():
-                raise ValueError("the chained backward needs BF16 layers of at most 64 channels above the first")
-            return self._backward_batched(saved, logits, dlogits, rb, wgrad_slices, chain)
+            return self._backward_batched(saved, logits, dlogits, rb, wgrad_slices, chain, top_ws)
         main = torch.cuda.current_stream()
         side = side2 = None
         if overlap:
@@ -182,6 +182,18 @@ class Network:
         del in_use
         return grads
 
+    def backward_form(self, batch_wgrad: bool | None = None, chain: bool | None = None):
+        """(batch_wgrad, chain) as backward() resolves them."""
+        if batch_wgrad is None:
+            batch_wgrad = self.dtype == NPVS_BF16
+        if not batch_wgrad:
+            return False, False
+        if chain is None:
+            chain = self._chainable()
+        elif chain and not self._chainable():
+            raise ValueError("the chained backward needs BF16 layers of at most 64 channels above the first")
+        return True, chain
+
     def _chainable(self) -> bool:
         """The fused data gradient applies: BF16, every layer above the first at most 64 channels
         in and out, every channel count a multiple of 8."""
@@ -189,9 +201,9 @@ class Network:
         return (self.dtype == NPVS_BF16 and all(c % 8 == 0 for c in ch)
                 and all(max(ch[i], ch[i + 1]) <= 64 for i in range(1, self.n_layers)))
 
-    def _backward_batched(self, saved, logits, dlogits, rb, slices, chain):
+    def _backward_batched(self, saved, logits, dlogits, rb, slices, chain, top_ws=None):
         if chain:
-            return self._backward_chained(saved, logits, dlogits, rb, slices)
+            return self._backward_chained(saved, logits, dlogits, rb, slices, top_ws)
         outputs = {self.n_layers - 1: logits}
         pending = []  # (X, cin, cout, ws, dW, db) of each layer, for the batched weight gradient
         dY = dlogits
@@ -213,7 +225,7 @@ class Network:
         sparse_conv_wgrad(pending, rb, self.dtype, slices)
         return [(self.gW[i], self.gb[i]) for i in range(self.n_layers)]
 
-    def _backward_chained(self, saved, logits, dlogits, rb, slices):
+    def _backward_chained(self, saved, logits, dlogits, rb, slices, top_ws=None):
         """The top layer's dZ from dlogits, then each layer's data gradient fused with the ReLU' of
         the layer below (its input is that layer's output, the mask), writing the layer below's
         dZ and bias partials straight into its workspace; then every weight gradient at once."""
@@ -225,9 +237,11 @@ class Network:
                 inputs[i] = saved[i] if i in saved else self.layer(i - 1, saved[i - 1], rb)
             return inputs[i]
 
-        ws = [conv_bwd_workspace(ch[i], ch[i + 1], rb, self.dtype) for i in range(self.n_layers)]
-        sparse_conv_bwd(layer_input(top), self.Wt[top], ch[top], ch[top + 1], logits, dlogits, rb, self.dtype,
-                        relu=False, want_dx=False, ws=ws[top], want_dw=False)
+        ws = [conv_bwd_workspace(ch[i], ch[i + 1], rb, self.dtype) if i < top or top_ws is None else top_ws
+              for i in range(self.n_layers)]
+        if top_ws is None:
+            sparse_conv_bwd(layer_input(top), self.Wt[top], ch[top], ch[top + 1], logits, dlogits, rb, self.dtype,
+                            relu=False, want_dx=False, ws=ws[top], want_dw=False)
         for i in range(top, 0, -1):
             sparse_conv_dgrad_relu(self.Wt[i], ch[i], ch[i + 1], layer_input(i), ch[i - 1], rb, ws[i], ws[i - 1])
         layer_input(0)
@@ -264,8 +278,16 @@ class Trainer:
         logits, saved = net.forward(X0, rb, checkpoint=self.checkpoint)
         pvs, _ = deinterleave_threshold(logits, rb, occ)
         labels = gather_input(label_bits, rb, NPVS_U8)
-        stats, dl = loss(logits, labels, rb, self.lam, dice_alpha=self.dice_alpha)
-        net.backward(saved, logits, dl, rb, batch_wgrad=self.batch_wgrad)  # gradients land in net.gflat
+        _, chain = net.backward_form(self.batch_wgrad)
+        if chain:  # the loss forms the last layer's dZ in that layer's backward workspace
+            top = net.n_layers - 1
+            top_ws = conv_bwd_workspace(net.channels[top], net.channels[top + 1], rb, net.dtype)
+            stats, dl = loss(logits, labels, rb, self.lam, want_grad=False, dice_alpha=self.dice_alpha,
+                             dz_ws=top_ws, dz_cin=net.channels[top])
+            net.backward(saved, logits, dl, rb, batch_wgrad=self.batch_wgrad, top_ws=top_ws)
+        else:
+            stats, dl = loss(logits, labels, rb, self.lam, dice_alpha=self.dice_alpha)
+            net.backward(saved, logits, dl, rb, batch_wgrad=self.batch_wgrad)  # gradients land in net.gflat
         self.step_count += 1
         # Adam, writing the updated weights straight into both packings of every layer
         adam(net.flat, net.gflat, self.m, self.v, self.adam_step, net.pack_descs(), net.dtype, lr=self.lr,

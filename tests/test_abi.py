@@ -76,6 +76,23 @@ def test_conv_workspace_sizes_and_checks(lib):
     assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_INVALID_ARG and b"both" in lib.npvs_last_error()
 
 
+def test_loss_argument_checks(lib):
+    fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
+    nl = ctypes.c_size_t()
+    L.call("npvs_loss_workspace_size", 1, ctypes.byref(nl))
+    n = ctypes.c_size_t()
+    L.call("npvs_conv_bwd_workspace_size", 64, 64, 1000, L.NPVS_BF16, ctypes.byref(n))
+
+    def call(C=64, dz_ws=ctypes.c_void_p(4096), dz_bytes=None, dz_cin=64, term=L.NPVS_LOSS_BCE):
+        return lib.npvs_loss(ctypes.c_void_p(1024), fake, C, fake, 1, fake, 1000, 0.99, term, 0.0, fake, None, dz_ws,
+                             n.value if dz_bytes is None else dz_bytes, dz_cin, fake, nl.value, None)
+
+    assert call(term=7) == L.NPVS_ERR_INVALID_ARG and b"term" in lib.npvs_last_error()
+    assert call(C=60) == L.NPVS_ERR_UNSUPPORTED and b"multiples of 8" in lib.npvs_last_error()
+    assert call(dz_cin=12) == L.NPVS_ERR_UNSUPPORTED
+    assert call(dz_bytes=n.value - 1) == L.NPVS_ERR_INVALID_ARG and b"dZ workspace" in lib.npvs_last_error()
+
+
 def test_fused_data_gradient_argument_checks(lib):
     fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
     n = ctypes.c_size_t()

@@ -330,6 +330,42 @@ def test_chained_backward_matches_unchained(checkpoint):
             assert np.all(err <= 2.0 ** -14 * mag + 1e-30), (li, float(err.max()))
 
 
+@pytest.mark.parametrize("grids", ["one", "three"])
+def test_loss_forms_the_last_layers_dz(grids):
+    """npvs_loss with the last layer's backward workspace (dz_ws): the chained BF16 backward that
+    starts from the dZ the loss wrote equals, bit for bit, the one that forms that dZ itself from
+    dL/dlogits (every dW and db), and the loss statistics and dL/dlogits are unchanged.  Three
+    grids of different sizes exercise the row-to-grid lookup of the gradient coefficients."""
+    cfg = synth.config("tiny32")
+    layers = synth.net_layers(cfg, bias_std=0.05)
+    if grids == "one":
+        dims = cfg.grids
+        tri_list = [synth.scene_for(cfg)]
+    else:
+        dims = [(32, 32, 32), (64, 32, 32), (32, 32, 64)]
+        tri_list = [synth.box_scene(70 + i, g, 20, 2, 8) for i, g in enumerate(dims)]
+    tris, counts = upload_tris(tri_list)
+    occ = npvs.froxelize(tris, counts, dims)
+    rb = npvs.build_rulebook(occ, dims, cfg.d, csr=True)
+    lab_bits = torch.from_numpy(to_np(occ) & synth.label_mask_bits(5, (to_np(occ).size,))).to(DEV)
+    labels = npvs.gather_input(lab_bits, rb, npvs.NPVS_U8)
+    net = Network(layers, cfg.d, npvs.NPVS_BF16)
+    assert net.backward_form() == (True, True)
+    logits, saved = net.forward(npvs.gather_input(occ, rb, npvs.NPVS_BF16), rb)
+    stats, dl = npvs.loss(logits, labels, rb)
+    ref = [(to_np(a), to_np(b)) for a, b in net.backward(saved, logits, dl, rb)]
+    top = len(layers) - 1
+    top_ws = npvs.conv_bwd_workspace(net.channels[top], net.channels[top + 1], rb, npvs.NPVS_BF16)
+    stats2, dl2 = npvs.loss(logits, labels, rb, dz_ws=top_ws, dz_cin=net.channels[top])
+    got = [(to_np(a), to_np(b)) for a, b in net.backward(saved, logits, None, rb, top_ws=top_ws)]
+    n = rb.host_counts()["n_sites"]
+    np.testing.assert_array_equal(to_np(stats2), to_np(stats))
+    np.testing.assert_array_equal(to_np(dl2)[:n], to_np(dl)[:n])
+    for (a, b), (c, d) in zip(ref, got):
+        np.testing.assert_array_equal(a, c)
+        np.testing.assert_array_equal(b, d)
+
+
 def test_backward_on_an_empty_grid_is_zero():
     """No active sites: every gradient is zero, per layer and with the weight gradients batched
     (both forms; the outputs start as NaN, so each entry must be written)."""
