@@ -27,7 +27,7 @@ struct Comp {
   }
 };
 
-constexpr int kLossSlices = 256;
+constexpr int kLossSlices = 512;
 constexpr int kLossQ = 5;  // BCE sum, TP, FN, FP, GTP
 constexpr int kLossBatch = 8;  // elements per thread loaded together
 
