@@ -188,10 +188,12 @@ npvs_status npvs_froxelize_view(const float *tris, int64_t n_tris, const npvs_vi
  *   (NPVS_F32, NPVS_BF16 or NPVS_U8).  X (device) [cap_sites][row_stride], row_stride = 0 meaning
  *   d^3; elements d^3 .. row_stride - 1 of a row are written as 0 (the input channels a BF16
  *   layer with fewer than 8 real ones reads, e.g. d = 1); rows >= n_sites untouched.
- * Used for the network input (bits = G) and for training labels. */
+ * Used for the network input (bits = G) and for training labels.  bits2 / X2 (device, both or
+ * neither): a second bit grid of the same grids, gathered in the same pass into uint8 rows
+ * X2 [cap_sites][d^3] (a training step's labels beside its input: one launch instead of two). */
 npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
                               const int32_t *site_keys, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,
-                              int32_t row_stride, void *X, void *stream);
+                              int32_t row_stride, void *X, const uint8_t *bits2, uint8_t *X2, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Weight packing.  W (device) float32 [27][cin][cout] -> Wp (device) of

@@ -144,19 +144,21 @@ def _new_rulebook(dims, d, cap, total_blocks, csr, dev) -> Rulebook:
 
 # --------------------------------------------------------------------------------- interleave
 def gather_input(bits: torch.Tensor, rb: Rulebook, dtype: int = NPVS_F32, out: torch.Tensor | None = None,
-                 width: int | None = None):
+                 width: int | None = None, bits2: torch.Tensor | None = None):
     """Sparse g_d: [cap][width] 0/1 values of `bits` on the active sites, width d^3 by default;
     channels d^3 .. width - 1 are zero (a BF16 input of fewer than 8 channels is given width 8).
-    Rows >= n_sites are left as allocated."""
+    Rows >= n_sites are left as allocated.  With `bits2` (a second bit grid of the same grids),
+    returns (out, out2): out2 uint8 [cap][d^3] its values, gathered in the same launch."""
     C = rb.d ** 3
     width = C if width is None else int(width)
     if out is None:
         out = torch.empty((rb.cap, width), dtype=_TORCH_DT[dtype], device=_dev())
     elif out.shape[-1] != width:
         raise ValueError("out must have `width` elements per row")
+    out2 = None if bits2 is None else torch.empty((rb.cap, C), dtype=torch.uint8, device=_dev())
     L.call("npvs_gather_input", _p(bits), len(rb.dims), L.dims_array(rb.dims), rb.d, _p(rb.site_keys),
-           _p(rb.counts), rb.cap, dtype, width, _p(out), _stream())
-    return out
+           _p(rb.counts), rb.cap, dtype, width, _p(out), _p(bits2), _p(out2), _stream())
+    return out if bits2 is None else (out, out2)
 
 
 def _dense_out(out, shape, x):

@@ -82,7 +82,7 @@ SIGNATURES = {
     "npvs_build_rulebook_noalloc": (i32, [P, i32, P, i32, i32, P, P, P, P, P, P, P, P]),
     "npvs_interleave": (i32, [P, Dims, i32, i32, P, P]),
     "npvs_deinterleave": (i32, [P, Dims, i32, i32, P, P]),
-    "npvs_gather_input": (i32, [P, i32, P, i32, P, P, i32, i32, i32, P, P]),
+    "npvs_gather_input": (i32, [P, i32, P, i32, P, P, i32, i32, i32, P, P, P, P]),
     "npvs_packed_weight_bytes": (sz, [i32, i32, i32]),
     "npvs_pack_weights": (i32, [P, i32, i32, i32, i32, P, P]),
     "npvs_pack_weights_batch": (i32, [i32, P, i32, P]),

@@ -248,7 +248,7 @@ static npvs_status plan_forward(npvs_plan *p, const float *tris, uint8_t *occ_ou
                            p->d_grid_rows, p->d_nbr, nullptr, nullptr, p->d_rb_ws, p->rb_ws, s);
   if (st != NPVS_OK) return st;
   st = npvs_gather_input(occ, p->n_grids, p->dims.data(), p->d, p->d_keys, p->d_counts, p->cap, p->dtype, p->ce[0],
-                         p->d_X0, s);
+                         p->d_X0, nullptr, nullptr, s);
   if (st != NPVS_OK) return st;
   const void *in = p->d_X0;
   for (int l = 0; l < p->n_layers; ++l) {

@@ -150,11 +150,14 @@ __device__ __forceinline__ uint8_t one_zero<uint8_t>(int bit) { return (uint8_t)
 
 // Row r of X is [stride] elements: the d^3 values, then zeros up to the stride (the padding a
 // BF16 layer of fewer than 8 input channels reads as channels of zero).
+// With X2, a second bit grid of the same shape, bits2, is gathered in the same pass into the
+// uint8 rows X2 [cap][d^3] (the labels of a training step, beside its input).
 template <typename T>
 __global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t *__restrict__ bits,
                                                            const int32_t *__restrict__ site_keys,
                                                            const npvs_counts *__restrict__ counts, T *__restrict__ X,
-                                                           int stride) {
+                                                           int stride, const uint8_t *__restrict__ bits2,
+                                                           uint8_t *__restrict__ X2) {
   const int d = B.d;
   const int32_t n = counts->n_sites;
   const int64_t runs = (int64_t)n * d * d;
@@ -165,12 +168,21 @@ __global__ __launch_bounds__(256) void gather_bits_kernel(Batch B, const uint8_t
     const GridDesc &g = B.g[grid_of_key(B, key)];
     int32_t l = key - g.key_off;
     int bx = l % g.Bx, by = (l / g.Bx) % g.By, bz = l / (g.Bx * g.By);
-    const uint8_t *row = bits + g.occ_off + ((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * (g.nx >> 3);
+    const int64_t row_off = g.occ_off + ((int64_t)(bz * d + oz) * g.ny + (by * d + oy)) * (g.nx >> 3);
+    const uint8_t *row = bits + row_off;
     T *dst = X + (int64_t)r * stride + (oz * d + oy) * d;
     const int x0 = bx * d;
     for (int ox = 0; ox < d; ++ox) {
       int x = x0 + ox;
       dst[ox] = one_zero<T>((row[x >> 3] >> (x & 7)) & 1);
+    }
+    if (X2) {
+      const uint8_t *row2 = bits2 + row_off;
+      uint8_t *dst2 = X2 + (int64_t)r * d * d * d + (oz * d + oy) * d;
+      for (int ox = 0; ox < d; ++ox) {
+        int x = x0 + ox;
+        dst2[ox] = (row2[x >> 3] >> (x & 7)) & 1;
+      }
     }
     if (oy == d - 1 && oz == d - 1)  // the row's last run also clears its padding
       for (int c = d * d * d; c < stride; ++c) X[(int64_t)r * stride + c] = one_zero<T>(0);
@@ -272,8 +284,10 @@ extern "C" npvs_status npvs_deinterleave(const void *in, npvs_dims g, int32_t d,
 
 extern "C" npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, const npvs_dims *dims, int32_t d,
                                         const int32_t *site_keys, const npvs_counts *counts, int32_t cap_sites,
-                                        int32_t dtype, int32_t row_stride, void *X, void *stream) {
+                                        int32_t dtype, int32_t row_stride, void *X, const uint8_t *bits2,
+                                        uint8_t *X2, void *stream) {
   if (!bits || !site_keys || !counts || !X) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: null pointer");
+  if (!bits2 != !X2) return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: bits2 and X2 must both be given or both null");
   Batch B;
   npvs_status st = make_batch(n_grids, dims, d, nullptr, &B);
   if (st != NPVS_OK) return st;
@@ -283,11 +297,15 @@ extern "C" npvs_status npvs_gather_input(const uint8_t *bits, int32_t n_grids, c
   int grid = stride_grid((int64_t)cap_sites * d * d, 256, 4096);
   hipStream_t s = as_stream(stream);
   switch (dtype) {
-    case NPVS_F32: gather_bits_kernel<float><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (float *)X, stride); break;
-    case NPVS_BF16:
-      gather_bits_kernel<uint16_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint16_t *)X, stride);
+    case NPVS_F32:
+      gather_bits_kernel<float><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (float *)X, stride, bits2, X2);
       break;
-    case NPVS_U8: gather_bits_kernel<uint8_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint8_t *)X, stride); break;
+    case NPVS_BF16:
+      gather_bits_kernel<uint16_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint16_t *)X, stride, bits2, X2);
+      break;
+    case NPVS_U8:
+      gather_bits_kernel<uint8_t><<<grid, 256, 0, s>>>(B, bits, site_keys, counts, (uint8_t *)X, stride, bits2, X2);
+      break;
     default: return fail(NPVS_ERR_INVALID_ARG, "npvs_gather_input: dtype must be NPVS_F32, NPVS_BF16 or NPVS_U8");
   }
   return check_hip(hipGetLastError(), "npvs_gather_input");

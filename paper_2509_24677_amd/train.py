@@ -274,10 +274,9 @@ class Trainer:
         net = self.net
         occ = froxelize(tris, self.n_tris, self.dims)
         rb = build_rulebook(occ, self.dims, net.d, csr=True)
-        X0 = gather_input(occ, rb, net.dtype)
+        X0, labels = gather_input(occ, rb, net.dtype, width=net.channels[0], bits2=label_bits)  # one launch
         logits, saved = net.forward(X0, rb, checkpoint=self.checkpoint)
         pvs, _ = deinterleave_threshold(logits, rb, occ)
-        labels = gather_input(label_bits, rb, NPVS_U8)
         _, chain = net.backward_form(self.batch_wgrad)
         if chain:  # the loss forms the last layer's dZ in that layer's backward workspace
             top = net.n_layers - 1

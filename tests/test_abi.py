@@ -76,6 +76,15 @@ def test_conv_workspace_sizes_and_checks(lib):
     assert lib.npvs_sparse_conv_bwd(*bad) == L.NPVS_ERR_INVALID_ARG and b"both" in lib.npvs_last_error()
 
 
+def test_gather_argument_checks(lib):
+    fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
+    dims = L.dims_array([(32, 32, 32)])
+    assert lib.npvs_gather_input(fake, 1, dims, 4, fake, fake, 100, L.NPVS_BF16, 0, fake, fake, None,
+                                 None) == L.NPVS_ERR_INVALID_ARG and b"both" in lib.npvs_last_error()
+    assert lib.npvs_gather_input(fake, 1, dims, 4, fake, fake, 100, L.NPVS_BF16, 32, fake, None, None,
+                                 None) == L.NPVS_ERR_INVALID_ARG and b"row_stride" in lib.npvs_last_error()
+
+
 def test_loss_argument_checks(lib):
     fake = ctypes.c_void_p(16)  # never dereferenced: the argument checks answer first
     nl = ctypes.c_size_t()

@@ -226,6 +226,31 @@ def test_sparse_gather_bit_exact(dt):
     np.testing.assert_array_equal(to_np(X)[:ref["n"]], ref["X"])
 
 
+@pytest.mark.parametrize("dt", [npvs.NPVS_F32, npvs.NPVS_BF16])
+def test_sparse_gather_of_two_grids_in_one_pass(dt):
+    """npvs_gather_input with a second bit grid (a training step's labels): the first output equals
+    the oracle's interleave of the occupancy, the second the oracle's site labels of the second
+    grid (u8), bit for bit, over two grids of different sizes."""
+    dims = [(64, 64, 64), (32, 32, 32)]
+    tri_list = [synth.box_scene(40 + i, g, 20, 2, 10) for i, g in enumerate(dims)]
+    occ, rb = _frox_and_rb(tri_list, dims, 4, csr=False)
+    mask = synth.label_mask_bits(9, (to_np(occ).size,))
+    lab_bits = torch.from_numpy(to_np(occ) & mask).to(DEV)
+    X, Y = npvs.gather_input(occ, rb, dt, bits2=lab_bits)
+    ref = oracle_batch(tri_list, dims, 4)
+    n = ref["n"]
+    np.testing.assert_array_equal(to_np(X)[:n], ref["X"])
+    # the oracle's labels: its own occupancy masked by the same bits, interleaved onto its sites
+    lab_ref, o = [], 0
+    for i, g in enumerate(dims):
+        nb = g[0] * g[1] * g[2] // 8
+        occ_i, _ = oracle.froxelize(tri_list[i], g)
+        keys = oracle.active_sites(occ_i, g, 4)
+        lab_ref.append(oracle.site_labels(occ_i.reshape(-1) & mask[o:o + nb], g, 4, keys))
+        o += nb
+    np.testing.assert_array_equal(to_np(Y)[:n], np.concatenate(lab_ref))
+
+
 # ------------------------------------------------------------------------------- convolution
 def _conv_case(cin, cout, d=2, seed=0, dims=((32, 32, 32), (64, 32, 32))):
     dims = [tuple(g) for g in dims]
