@@ -266,13 +266,14 @@ constexpr int kWgPitch = kWgChunk + 16;  // bf16 elements per LDS row (padding s
 constexpr int kWgQuads = kWgChunk / 4;
 
 // LDS position of pair p of staged row `row` (a channel): the 16-byte blocks of 8 pairs are
-// permuted within the row by XOR with (row / 8) % 8.  A staging store writes 4 pairs of rows
-// 8 cc + j for 8 channel groups cc at once; the row pitch (72 dwords) puts those 8 rows on the
-// same bank group, and the swizzle moves them onto 8 different ones, while the 16 rows x 4 blocks
-// of an MFMA operand read still cover every bank group equally.  A block stays 16 bytes and
-// aligned, so an operand is one 16-byte read.
+// permuted within the row by XOR with (row / 8) % 8 and with bit 2 of the row.  The row pitch
+// (72 dwords) puts row r on 16-byte bank group (2 r + block) % 8.  A staging store writes 4 pairs
+// of rows 8 cc + j for 8 channel groups cc at once: without the swizzle all 8 on one bank group,
+// with it (row / 8 differs) on 8 different ones.  An MFMA operand read has 8 lanes read rows
+// 8 g .. 8 g + 7 at one block: 2 r alone puts rows i and i + 4 on the same group, and bit 2
+// separates them.  A block stays 16 bytes and aligned, so an operand is one 16-byte read.
 __device__ __forceinline__ int wg_lds_pos(int row, int p) {
-  return row * kWgPitch + ((((p >> 3) ^ (row >> 3)) & 15) << 3) + (p & 7);
+  return row * kWgPitch + ((((p >> 3) ^ (row >> 3) ^ ((row >> 2) & 1)) & 15) << 3) + (p & 7);
 }
 
 struct WgTask {

@@ -202,15 +202,20 @@ __global__ __launch_bounds__(256) void deinterleave_threshold_kernel(Batch B, in
   const float ninf = -__builtin_huge_valf();
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_bytes;
        t += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t gbits = occ[t];
+    if (!logits && !gbits) {  // no occupied froxel in this byte: no PVS bit either
+      pvs[t] = 0;
+      continue;
+    }
     int b = 0;
     while (b + 1 < B.n && t >= B.g[b + 1].occ_off) ++b;
     const GridDesc &g = B.g[b];
-    const int64_t l = t - g.occ_off;
-    const int rb = g.nx >> 3;
-    const int xb = l % rb;
-    const int y = (l / rb) % g.ny;
-    const int z = l / ((int64_t)rb * g.ny);
-    const uint8_t gbits = occ[t];
+    // 32-bit index arithmetic: a grid holds at most 1024^3 / 8 bytes
+    const uint32_t l = (uint32_t)(t - g.occ_off), rb = (uint32_t)g.nx >> 3, ny = (uint32_t)g.ny;
+    const uint32_t ly = l / rb;
+    const int xb = (int)(l - ly * rb);
+    const int y = (int)(ly % ny);
+    const int z = (int)(ly / ny);
     const int key_yz = g.key_off + ((z / d) * g.By + (y / d)) * g.Bx;
     const int cyz = ((z % d) * d + (y % d)) * d;
     float lv[8];
