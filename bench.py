@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default tile shape for every layer (for profiler runs, whose "
+                         "per-launch overhead skews the autotuner's timings)")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + timed steps only (for rocprofv3)")
     ap.add_argument("--counters", action="store_true",
                     help="for rocprofv3 --pmc: a plain 256 MiB copy (counter calibration), then --steps eager "
@@ -834,7 +837,8 @@ def main():
         net = Network(layers, cfg.d, dtype)
         if dtype == npvs.NPVS_BF16:  # autotuned tile shapes, chosen once on the real rulebook
             if "v" not in tuned:
-                tuned["v"] = net.autotune(X0_b, rb0)
+                tuned["v"] = ([npvs._lib.NPVS_DEFAULT_CONV_VARIANT] * net.n_layers if args.no_autotune
+                              else net.autotune(X0_b, rb0))
             net.variant = list(tuned["v"])
         tr = Trainer(net, dims, n_tris, checkpoint=checkpoint)
         return net, tr
