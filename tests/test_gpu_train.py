@@ -330,6 +330,35 @@ def test_chained_backward_matches_unchained(checkpoint):
             assert np.all(err <= 2.0 ** -14 * mag + 1e-30), (li, float(err.max()))
 
 
+def test_fused_data_gradient_without_mask():
+    """npvs_sparse_conv_dgrad_relu with M = NULL (no ReLU' below): the dZ and bias partials it leaves
+    in the lower layer's workspace give that layer's weight gradient bit for bit as the per-layer
+    backward of that layer with relu = 0 on the same data gradient (dX of the upper layer, in
+    float32), and its bias gradient within 2^-14 sum_r |dX[r]| (another grouping of the sums)."""
+    cfg, t, layers, occ, rb, lab_bits = _setup()
+    acts = _gpu_forward(occ, rb, layers, npvs.NPVS_BF16)
+    dY = torch.randn((rb.cap, cfg.channels[2]), device=DEV)
+    n = rb.host_counts()["n_sites"]
+    (W1, _), (W0, _) = layers[1], layers[0]
+    c0, c1, c2 = W0.shape[1], W1.shape[1], W1.shape[2]
+    Wt1 = npvs.pack_weights(torch.from_numpy(W1).to(DEV), npvs.NPVS_BF16, flip_transpose=True)
+    # upper layer (1): its dZ in ws1, then its data gradient two ways
+    ws1 = npvs.conv_bwd_workspace(c1, c2, rb, npvs.NPVS_BF16)
+    dX, _, _ = npvs.sparse_conv_bwd(acts[1], Wt1, c1, c2, acts[2], dY, rb, npvs.NPVS_BF16, relu=True, ws=ws1,
+                                    want_dw=False)
+    ws0 = npvs.conv_bwd_workspace(c0, c1, rb, npvs.NPVS_BF16)
+    npvs.sparse_conv_dgrad_relu(Wt1, c1, c2, None, c0, rb, ws1, ws0)
+    gW, gb = torch.empty((27, c0, c1), device=DEV), torch.empty(c1, device=DEV)
+    npvs.sparse_conv_wgrad([(acts[0], c0, c1, ws0, gW, gb)], rb, npvs.NPVS_BF16, slices=16)
+    Wt0 = npvs.pack_weights(torch.from_numpy(W0).to(DEV), npvs.NPVS_BF16, flip_transpose=True)
+    _, rW, rdb = npvs.sparse_conv_bwd(acts[0], Wt0, c0, c1, acts[1], dX, rb, npvs.NPVS_BF16, relu=False,
+                                      want_dx=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(gW), to_np(rW))
+    mag = np.abs(to_np(dX)[:n].astype(np.float64)).sum(axis=0)
+    assert np.all(np.abs(to_np(gb).astype(np.float64) - to_np(rdb)) <= 2.0 ** -14 * mag + 1e-30)
+
+
 @pytest.mark.parametrize("grids", ["one", "three"])
 def test_loss_forms_the_last_layers_dz(grids):
     """npvs_loss with the last layer's backward workspace (dz_ws): the chained BF16 backward that
