@@ -145,8 +145,8 @@ class Network:
         are joined before returning).  The gradients land in the flat gradient buffer; returns
         [(dW, db)] per layer (views of it)."""
         batch_wgrad, chain = self.backward_form(batch_wgrad, chain)
-        if top_ws is not None and not chain:
-            raise ValueError("top_ws is for the chained backward")
+        if top_ws is not None and not self.loss_forms_top_dz(batch_wgrad):
+            raise ValueError("top_ws is for the chained backward with a fusable last layer")
         if batch_wgrad:
             return self._backward_batched(saved, logits, dlogits, rb, wgrad_slices, chain, top_ws)
         main = torch.cuda.current_stream()
@@ -194,12 +194,26 @@ class Network:
             raise ValueError("the chained backward needs BF16 layers of at most 64 channels above the first")
         return True, chain
 
-    def _chainable(self) -> bool:
-        """The fused data gradient applies: BF16, every layer above the first at most 64 channels
-        in and out, every channel count a multiple of 8."""
+    def _fusable(self, i: int) -> bool:
+        """Layer i's data gradient can form the dZ of layer i - 1 in its epilogue
+        (npvs_sparse_conv_dgrad_relu): BF16, at most 64 channels in and out, and the layer below
+        can take that dZ in place (it is fusable itself, or it is the first layer, which needs no
+        data gradient): the fused layers are a run from layer 1 upward."""
         ch = self.channels
-        return (self.dtype == NPVS_BF16 and all(c % 8 == 0 for c in ch)
-                and all(max(ch[i], ch[i + 1]) <= 64 for i in range(1, self.n_layers)))
+        if self.dtype != NPVS_BF16 or i < 1 or ch[0] % 8:
+            return False
+        return all(max(ch[j], ch[j + 1]) <= 64 and ch[j + 1] % 8 == 0 for j in range(1, i + 1))
+
+    def _chainable(self) -> bool:
+        """Some layer's data gradient can be fused (see _fusable)."""
+        return any(self._fusable(i) for i in range(1, self.n_layers))
+
+    def loss_forms_top_dz(self, batch_wgrad: bool | None = None) -> bool:
+        """The loss may write the last layer's dZ into its workspace (backward(top_ws=...)): the
+        chained form runs and the last layer's data gradient is fused."""
+        _, chain = self.backward_form(batch_wgrad)
+        top = self.n_layers - 1
+        return chain and (top == 0 or self._fusable(top)) and self.channels[top + 1] % 8 == 0
 
     def _backward_batched(self, saved, logits, dlogits, rb, slices, chain, top_ws=None):
         if chain:
@@ -226,9 +240,11 @@ class Network:
         return [(self.gW[i], self.gb[i]) for i in range(self.n_layers)]
 
     def _backward_chained(self, saved, logits, dlogits, rb, slices, top_ws=None):
-        """The top layer's dZ from dlogits, then each layer's data gradient fused with the ReLU' of
-        the layer below (its input is that layer's output, the mask), writing the layer below's
-        dZ and bias partials straight into its workspace; then every weight gradient at once."""
+        """Down the stack, each layer whose data gradient is fusable (_fusable) runs it with the
+        ReLU' of the layer below fused in, writing that layer's dZ and bias partials straight
+        into its workspace; any other layer forms its dZ from the float32 gradient of the layer
+        above and, when the layer below needs one, its float32 data gradient as usual.  Then
+        every weight gradient at once."""
         top, ch = self.n_layers - 1, self.channels
         inputs = {}
 
@@ -239,11 +255,21 @@ class Network:
 
         ws = [conv_bwd_workspace(ch[i], ch[i + 1], rb, self.dtype) if i < top or top_ws is None else top_ws
               for i in range(self.n_layers)]
-        if top_ws is None:
-            sparse_conv_bwd(layer_input(top), self.Wt[top], ch[top], ch[top + 1], logits, dlogits, rb, self.dtype,
-                            relu=False, want_dx=False, ws=ws[top], want_dw=False)
-        for i in range(top, 0, -1):
-            sparse_conv_dgrad_relu(self.Wt[i], ch[i], ch[i + 1], layer_input(i), ch[i - 1], rb, ws[i], ws[i - 1])
+        dY = dlogits  # float32 gradient of layer i's output, when its dZ is not in ws[i] yet
+        have_dz = top_ws is not None
+        for i in range(top, -1, -1):
+            fuse = i > 0 and self._fusable(i)
+            if not have_dz:
+                Y = logits if i == top else layer_input(i + 1)
+                dX, _, _ = sparse_conv_bwd(layer_input(i), self.Wt[i], ch[i], ch[i + 1], Y, dY, rb, self.dtype,
+                                           relu=i < top, want_dx=i > 0 and not fuse, ws=ws[i], want_dw=False)
+            if fuse:
+                sparse_conv_dgrad_relu(self.Wt[i], ch[i], ch[i + 1], layer_input(i), ch[i - 1], rb, ws[i], ws[i - 1])
+                have_dz = True
+            else:
+                if have_dz and i > 0:
+                    raise RuntimeError("a layer whose dZ is formed in place needs a fusable data gradient")
+                have_dz, dY = False, (dX if i > 0 else None)
         layer_input(0)
         pending = [(inputs[i], ch[i], ch[i + 1], ws[i], self.gW[i], self.gb[i]) for i in range(top, -1, -1)]
         sparse_conv_wgrad(pending, rb, self.dtype, slices)
@@ -277,8 +303,7 @@ class Trainer:
         X0, labels = gather_input(occ, rb, net.dtype, width=net.channels[0], bits2=label_bits)  # one launch
         logits, saved = net.forward(X0, rb, checkpoint=self.checkpoint)
         pvs, _ = deinterleave_threshold(logits, rb, occ)
-        _, chain = net.backward_form(self.batch_wgrad)
-        if chain:  # the loss forms the last layer's dZ in that layer's backward workspace
+        if net.loss_forms_top_dz(self.batch_wgrad):  # the loss forms the last layer's dZ in its workspace
             top = net.n_layers - 1
             top_ws = conv_bwd_workspace(net.channels[top], net.channels[top + 1], rb, net.dtype)
             stats, dl = loss(logits, labels, rb, self.lam, want_grad=False, dice_alpha=self.dice_alpha,
