@@ -245,16 +245,17 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(const T *__restrict_
   }
 }
 
-// BF16 path on MFMA.  grid (S slices, K offsets, windows), 256 threads = 4 waves; a workgroup computes
-// the window of at most 64 x 64 entries (input channels c0 .., outputs o0 ..) that blockIdx.z
-// selects (one window when cin, cout <= 64).
+// BF16 path on MFMA.  256 threads = 4 waves; a workgroup computes the window of at most 64 x 64
+// entries (input channels c0 .., outputs o0 ..) that its window index selects (one window when
+// cin, cout <= 64), over the pairs of its slice (sliced form, grid (S, K, windows)) or of its
+// range of the whole pair list (balanced form, see wgrad_bf16_kernel).
 // dW_k[c][o] = sum_p X[in_p][c] dZ[out_p][o] is a [cin x P] x [P x cout] product with the pair
 // index as the contraction.  128 pairs at a time are staged into LDS transposed (channel-major,
-// XT[c][p], GT[o][p]) so that both MFMA operands of v_mfma_f32_16x16x32_bf16 are one 16-byte
-// LDS read per lane:
-//   A (16 x 32): lane l gives XT[mb*16 + l%16][kk + 8(l/16) + j]
-//   B (32 x 16): lane l gives GT[nb*16 + l%16][kk + 8(l/16) + j]
-//   D: lane l holds dW[mb*16 + 4(l/16) + i][nb*16 + l%16]
+// XT[c][p], GT[o][p]) so that both MFMA operands of v_mfma_f32_32x32x16_bf16 are one 16-byte
+// LDS read per lane; wave w computes the 32 x 32 block (mb, nb) = (w / OB, w % OB):
+//   A (32 x 16): lane l gives XT[mb*32 + l%32][kk + 8(l/32) + j]
+//   B (16 x 32): lane l gives GT[nb*32 + l%32][kk + 8(l/32) + j]
+//   D: entry r of lane l is dW[mb*32 + 8(r/4) + 4(l/32) + r%4][nb*32 + l%32]
 // A staging task is 4 consecutive pairs x 8 channels of X or dZ (at most 2 per thread; the 8
 // tasks of one pair quad sit in adjacent lanes).  The pair
 // indices are fetched two chunks ahead and the rows of the next chunk are loaded while the
