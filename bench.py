@@ -68,6 +68,8 @@ def conv_traffic(variant):
         name = f"conv_fwd_bf16_lds_kernel<2, 4, {lds[variant][0]}, {lds[variant][1]}>"
     elif variant == 14:
         name = "conv_fwd_bf16_wsta_kernel<2, 1, 4>"
+    elif variant == 15:
+        name = "conv_fwd_bf16_wsred_kernel<2>"
     else:
         name = f"conv_fwd_bf16_wsta_kernel<2, {variant - 11}, 2>"
     for line in text.splitlines():
@@ -934,7 +936,7 @@ def main():
         rb16 = npvs.build_rulebook(occ16, c16.grids, c16.d)
         h16 = net_b.layer(0, npvs.gather_input(occ16, rb16, npvs.NPVS_BF16), rb16)
         o16 = torch.empty_like(h16)
-        for v in (14, 9, 12, 3, 0):
+        for v in (14, 15, 9, 12, 3, 0):
             for _ in range(5):
                 npvs.sparse_conv_fwd(h16, net_b.Wp[1], net_b.b[1], 64, 64, rb16, npvs.NPVS_BF16, True, out=o16,
                                      variant=v)
@@ -1146,7 +1148,8 @@ def main():
     achieved = flops / (conv_ms * 1e-3) / 1e12
     shapes = {0: "<2,4,1,9>", 1: "<2,4,2,1>", 2: "<2,4,1,3>", 3: "<2,4,2,3>", 4: "<2,4,1,1>", 5: "<2,4,2,9>",
               6: "_lds<2,4,1,4>", 7: "_lds<2,4,1,2>", 8: "_lds<2,4,2,2>", 9: "_lds<2,4,1,8>",
-              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>", 12: "_wsta<2,1>", 13: "_wsta<2,2>", 14: "_wsta<2,1,4>"}
+              10: "_lds<2,4,2,4>", 11: "_lds<2,4,2,8>", 12: "_wsta<2,1>", 13: "_wsta<2,2>", 14: "_wsta<2,1,4>",
+              15: "_wsred<2>"}
     alg_bytes = n_sites * 64 * 2 * 2 + 27 * n_sites * 4 + 27 * 64 * 64 * 2  # X in, Y out, neighbour map, weights
     roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / BF16_PEAK_TFLOPS, "traffic": conv_traffic(net_b.variant[1]),

@@ -236,7 +236,9 @@ npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int3
  *   of at most 64 channels) keep each wave's weights in registers while a workgroup walks several
  *   row tiles of 16 or 32 rows (32 outputs per workgroup); variant 14 is variant 12 with every
  *   output block (at most 64 outputs) in one workgroup, so a gathered row serves all outputs (more
- *   than 64 outputs: variant 12).  Channel counts no tuned shape covers use a general kernel
+ *   than 64 outputs: variant 12); variant 15 is variant 14 with three more waves that only sum
+ *   the other waves' partial products and store the tile, while those go on to the next tile
+ *   (at most 64 inputs and outputs; other shapes take variant 14).  Channel counts no tuned shape covers use a general kernel
  *   (variants 5 and 13 select its 32-row tiles), except 65 to 160 inputs, which take the
  *   weight-stationary kernel with 16-row tiles unless variant 5 is asked for.  All variants give
  *   results within float32 rounding of each other; each one is deterministic.  Ignored by the
@@ -247,7 +249,7 @@ npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int3
  *   float32 rounding of the unsplit kernel, deterministic); without it (or when the size is 0)
  *   the unsplit kernel runs.  A non-null ws of fewer bytes than needed is an argument error.
  * ------------------------------------------------------------------------------------------- */
-#define NPVS_CONV_VARIANTS 15
+#define NPVS_CONV_VARIANTS 16
 #define NPVS_DEFAULT_CONV_VARIANT 14 /* the tile shape of variant -1 and of the data gradient */
 npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
 npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,

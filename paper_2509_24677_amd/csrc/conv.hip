@@ -619,6 +619,144 @@ __global__ __launch_bounds__(576) void conv_fwd_bf16_wsta_kernel(const uint16_t 
   wsta_body<KB, MB, NBW, false>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, nullptr, nullptr);
 }
 
+// The weight-stationary layer (at most 64 outputs, 16-row tiles) with its cross-wave reduction
+// taken off the product waves.  Nine product waves hold the weights of three offsets each and,
+// per tile, write their partial products to one of two LDS tables; three reducer waves sum a
+// table (partials 0 .. 8 in order, as the single-role kernel does) and apply the epilogue while
+// the product waves go on to the next tile.  One barrier per tile: a table is rewritten two
+// tiles later, after a barrier that every reducer reaches only once it has read the table.  The
+// twelve waves fill three per SIMD at up to 168 registers, as many as the nine-wave kernel's
+// register budget allows on the busiest SIMD.
+template <int KB>
+__global__ __launch_bounds__(768) void conv_fwd_bf16_wsred_kernel(const uint16_t *__restrict__ X, int cin,
+                                                                  const bf16x8_t *__restrict__ Wp,
+                                                                  const float *__restrict__ bias, int cout,
+                                                                  const int32_t *__restrict__ nbr,
+                                                                  const npvs_counts *__restrict__ counts, int cap,
+                                                                  int relu, int out_f32, void *__restrict__ Y) {
+  constexpr int KSPLIT = 9, KPER = 3, ROWS = 16, NBLK = 4, NRED = 3;
+  __shared__ f32x4_t red[2][KSPLIT * NBLK * 64];
+  const int32_t n = counts->n_sites;
+  const int ntiles = (n + ROWS - 1) / ROWS;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index, uniform (scalar)
+  const bool prod = wv < KSPLIT;                                     // a product wave (else a reducer)
+  const int kbeg = (prod ? wv : 0) * KPER, csub = 8 * (lane >> 4);
+  const int NBT = (cout + 15) / 16;
+  int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
+  if (tile < 0) return;  // whole workgroup: tile depends on blockIdx only
+  bf16x8_t aw[KPER][KB][NBLK];
+  if (prod)
+#pragma unroll
+    for (int q = 0; q < KPER; ++q)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < NBLK; ++nb) {
+          const int g = nb < NBT ? nb : NBT - 1;  // blocks past cout: any valid fragment
+          aw[q][kb][nb] = Wp[(((int64_t)(kbeg + q) * NBT + g) * KB + kb) * 64 + lane];
+        }
+  // as in the single-role kernel: indices and rows loaded raw, rows masked where the products
+  // read them (loads retire in order, so nothing loaded is used right after its load)
+  auto indices = [&](int t, int (&ix)[KPER]) {
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) {
+      const int r = t * ROWS + (lane & 15);
+      ix[q] = nbr[(int64_t)(kbeg + q) * cap + (r < n ? r : n - 1)];
+    }
+  };
+  auto rows = [&](const int (&ix)[KPER], int t, uint4 (&b)[KPER][KB], uint32_t &m) {
+    m = 0u;
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) {
+      const bool ok = t * ROWS + (lane & 15) < n && ix[q] >= 0;
+      m |= (ok ? 1u : 0u) << q;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int c = kb * 32 + csub;
+        b[q][kb] = *reinterpret_cast<const uint4 *>(X + (ok && c < cin ? (int64_t)ix[q] * cin + c : 0));
+      }
+    }
+  };
+  // a reducer's blocks: wv - 9 and wv - 6 (the second only for wave 9); their bias, loaded once
+  float bv[2][4] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+  if (!prod && bias)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int blk = wv - KSPLIT + NRED * h, o = blk * 16 + 4 * (lane >> 4);
+      if (blk < NBLK && o < cout)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[h][i] = bias[o + i];
+    }
+  // The two roles walk the same tiles in their own loops, one barrier per tile each (the role is
+  // uniform over a wave, so every wave of the workgroup meets every barrier); in the reducers'
+  // loop no product registers are live, so a reducer loads all nine partials of its blocks at once.
+  int t1 = xcd_tile(blockIdx.x, gridDim.x, ntiles, 1);
+  if (prod) {
+    int ix[KPER];
+    uint4 bx[KPER][KB];
+    uint32_t bm = 0u;
+    indices(tile, ix);
+    rows(ix, tile, bx, bm);
+    indices(t1 >= 0 ? t1 : tile, ix);
+    for (int j = 0; tile >= 0; ++j) {
+      const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
+      f32x4_t *tab = red[j & 1];
+      f32x4_t acc[NBLK];
+#pragma unroll
+      for (int nb = 0; nb < NBLK; ++nb) acc[nb] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < KPER; ++q)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          const uint32_t mm = ((bm >> q) & 1u) && kb * 32 + csub < cin ? ~0u : 0u;
+          const uint4 v = bx[q][kb];
+          const uint4 row = make_uint4(v.x & mm, v.y & mm, v.z & mm, v.w & mm);
+#pragma unroll
+          for (int nb = 0; nb < NBLK; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[q][kb][nb], __builtin_bit_cast(bf16x8_t, row),
+                                                              acc[nb], 0, 0, 0);
+        }
+      // the next tile's rows go into this tile's registers as soon as the products have taken
+      // them; their latency is covered by the table writes, the barrier and the wait there for
+      // the waves of the busiest SIMD
+      rows(ix, t1 >= 0 ? t1 : tile, bx, bm);               // tile j + 1 (or a repeat)
+      indices(t2 >= 0 ? t2 : (t1 >= 0 ? t1 : tile), ix);  // tile j + 2 (or a repeat)
+#pragma unroll
+      for (int nb = 0; nb < NBLK; ++nb) tab[(wv * NBLK + nb) * 64 + lane] = acc[nb];
+      __syncthreads();  // table j % 2 is complete
+      tile = t1;
+      t1 = t2;
+    }
+  } else {
+    const int blk0 = wv - KSPLIT, blk1 = blk0 + NRED;  // blk1 < NBLK for wave 9 only
+    for (int j = 0; tile >= 0; ++j) {
+      const int t2 = xcd_tile(blockIdx.x, gridDim.x, ntiles, j + 2);
+      const f32x4_t *tab = red[j & 1];
+      __syncthreads();  // table j % 2 is complete; this wave is done with table (j - 1) % 2
+      f32x4_t p0[KSPLIT], p1[KSPLIT];
+#pragma unroll
+      for (int w = 0; w < KSPLIT; ++w) {
+        p0[w] = tab[(w * NBLK + blk0) * 64 + lane];
+        if (blk1 < NBLK) p1[w] = tab[(w * NBLK + blk1) * 64 + lane];
+      }
+      const int r = tile * ROWS + (lane & 15);
+      f32x4_t sum = p0[0];
+#pragma unroll
+      for (int w = 1; w < KSPLIT; ++w) sum += p0[w];
+      conv_bf16_epilogue_bias(sum, r, n, blk0 * 16 + 4 * (lane >> 4), cout, bv[0], relu, out_f32, Y);
+      if (blk1 < NBLK) {
+        sum = p1[0];
+#pragma unroll
+        for (int w = 1; w < KSPLIT; ++w) sum += p1[w];
+        conv_bf16_epilogue_bias(sum, r, n, blk1 * 16 + 4 * (lane >> 4), cout, bv[1], relu, out_f32, Y);
+      }
+      tile = t1;
+      t1 = t2;
+    }
+  }
+}
+
 // The data gradient of a BF16 layer with the ReLU' of the layer below fused in: dZ_below =
 // bf16(conv(dZ, W') masked by M > 0) and the bias partial table dbp (see wsta_body).
 template <int KB>
@@ -917,6 +1055,21 @@ npvs_status conv_fwd_dispatch(const void *X, int32_t cin, const void *Wp, const 
   if (cin % 8 || cout % 8)
     return fail(NPVS_ERR_UNSUPPORTED, "npvs_sparse_conv_fwd: BF16 needs cin % 8 == 0 and cout % 8 == 0");
   const int KB = (cin + 31) / 32, NB = (cout + 15) / 16;
+  if (variant == 15) {  // variant 14 with dedicated reducer waves: at most 64 inputs and outputs
+    if (KB <= 2 && NB <= 4) {
+      int G = 256;
+      const int most = stride_grid(cap, 16, 4096);
+      if (G > most) G = (most + 7) & ~7;
+      if (KB == 1)
+        conv_fwd_bf16_wsred_kernel<1><<<dim3(G, 1), 768, 0, s>>>((const uint16_t *)X, cin, (const bf16x8_t *)Wp,
+                                                                 bias, cout, nbr, counts, cap, relu, out_f32, Y);
+      else
+        conv_fwd_bf16_wsred_kernel<2><<<dim3(G, 1), 768, 0, s>>>((const uint16_t *)X, cin, (const bf16x8_t *)Wp,
+                                                                 bias, cout, nbr, counts, cap, relu, out_f32, Y);
+      return check_hip(hipGetLastError(), "npvs_sparse_conv_fwd");
+    }
+    variant = 14;
+  }
   if (variant == 14 && KB <= 2 && NB <= 4) {  // weight-stationary, all (at most 64) outputs per workgroup
     if (KB == 1) launch_bf16_wsta<1, 1, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
     else launch_bf16_wsta<2, 1, 4>(X, cin, Wp, bias, cout, nbr, counts, cap, relu, out_f32, Y, s);
