@@ -250,7 +250,7 @@ npvs_status npvs_pack_weights_batch(int32_t n, const npvs_pack_desc *descs, int3
  *   the unsplit kernel runs.  A non-null ws of fewer bytes than needed is an argument error.
  * ------------------------------------------------------------------------------------------- */
 #define NPVS_CONV_VARIANTS 16
-#define NPVS_DEFAULT_CONV_VARIANT 14 /* the tile shape of variant -1 and of the data gradient */
+#define NPVS_DEFAULT_CONV_VARIANT 15 /* the tile shape of variant -1 (the data gradient: variant 14's) */
 npvs_status npvs_conv_fwd_workspace_size(int32_t cin, int32_t cout, int32_t cap_sites, int32_t dtype, size_t *bytes);
 npvs_status npvs_sparse_conv_fwd(const void *X, int32_t cin, const void *Wp, const float *bias, int32_t cout,
                                  const int32_t *nbr, const npvs_counts *counts, int32_t cap_sites, int32_t dtype,

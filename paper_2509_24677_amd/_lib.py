@@ -20,7 +20,7 @@ NPVS_ERR_UNSUPPORTED = -4
 NPVS_F32, NPVS_BF16, NPVS_U8 = 0, 1, 2
 NPVS_MAX_GRIDS = 32
 NPVS_CONV_VARIANTS = 16
-NPVS_DEFAULT_CONV_VARIANT = 14
+NPVS_DEFAULT_CONV_VARIANT = 15
 NPVS_MAX_PACK = 64
 NPVS_MAX_ADAM_PACK = 32
 NPVS_MAX_WGRAD_LAYERS = 16
